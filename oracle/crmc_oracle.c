@@ -1,0 +1,912 @@
+/*
+ * Plain FP64 CPU oracle for charge-regulation Monte Carlo (CR-MC).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library may link, load or
+ * call this file; it exists so that tests, the smoke check and the CPU baseline
+ * of the benchmark can compare the GPU path against a slow, obviously correct
+ * implementation.  It shares no code with the GPU path.
+ *
+ * What it implements (Curk, Yuan, Luijten, "Accelerated simulation method for
+ * charge regulation effects"):
+ *   - the three grouped reactions A <-> A- + X+, B <-> B+ + X-, 0 <-> X+ + X-
+ *     (Sec. II B, eqs. acid_new, base_new, salt_new);
+ *   - the six moves (forward and reverse of each reaction), proposed with equal
+ *     probability, participants chosen uniformly, auto-reject when no eligible
+ *     participant exists (Sec. II C);
+ *   - the Metropolis acceptance probabilities of Sec. II C (eqs. acidacc,
+ *     MCmetro, the acid/base reverse and forward forms, MCsaltf, MCmetro2),
+ *     written in the log10 parametrisation pH, pOH, pK, pI_X (Sec. II C);
+ *   - energy changes computed from the changed particles only, keeping the old
+ *     energy between moves (Sec. II D).
+ *
+ * Two schedules:
+ *   paper mode  - one global move at a time, insertion uniform in the whole box
+ *                 (the literal algorithm of Sec. II C);
+ *   cell mode   - the same moves restricted to one cell of a randomly shifted
+ *                 cubic grid; cells of one parity class ("colour") are mutually
+ *                 non-interacting (cell width >= cutoff) and are processed one
+ *                 after another; the grid shift is redrawn every sweep so that
+ *                 cells overlap across sweeps.  The acceptance is the paper's
+ *                 formula with V replaced by the cell volume and every count
+ *                 replaced by the cell's count (detailed balance, eq. accrat,
+ *                 with a proposal density uniform in the cell).  This is the
+ *                 schedule the GPU path runs, word for word.
+ *
+ * Energy model (screened Coulomb + excluded volume, positions fixed):
+ *   E = sum_{i<j, r<rc} lB q_i q_j exp(-kappa r)/r
+ *     + sum_{pairs with at least one free ion, r<2^(1/6)} 4 eps (r^-12 - r^-6) + eps
+ *     + sum_{ion, core} expanded WCA with Delta = R - 1/2     (Table II, eq. LJe)
+ * Site-site excluded volume and bonds are constant (sites never move) and are
+ * left out.  The Coulomb cutoff is decided exactly on the integer squared
+ * distance of the fixed-point coordinates.  A free-ion pair closer than 0.5
+ * (or an ion closer than Delta + 0.5 to a core centre) has infinite energy.
+ *
+ * Everything is FP64.  Random numbers are Philox4x32-10 (Salmon, Moraes, Dror,
+ * Shaw, SC'11), written here from its published definition.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_ACID 1
+#define ORC_BASE 2
+#define ORC_XPOS 3
+#define ORC_XNEG 4
+#define ORC_NEUTRAL 5
+
+#define TAG_TRIAL 1u
+#define TAG_SHIFT 2u
+#define TAG_PAPER 3u
+#define TAG_PAIR 4u
+
+static const double LN10 = 2.302585092994045684017991454684364208;
+static const double TWO32 = 4294967296.0;
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10                                                              */
+/* ------------------------------------------------------------------------- */
+void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Data                                                                       */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t x[3];
+    int32_t kind;
+    int32_t charged; /* sites: 0/1; free ions: always 1 */
+    int32_t sid;     /* site index in input order; -1 for free ions */
+} orc_particle;
+
+typedef struct {
+    int64_t sweep, cell, trial; /* cell = -1 in paper mode; trial = global index there */
+    int32_t move;               /* 0..5; auto-rejected trials keep their move id */
+    int32_t status;             /* 0 rejected, 1 accepted, 2 auto-rejected (no participant) */
+    double dU;                  /* beta * Delta E (NaN when auto-rejected) */
+    double lnp;                 /* log acceptance ratio (NaN when auto-rejected) */
+    double u;                   /* uniform in [0,1) used for the decision */
+} orc_trial;
+
+typedef struct {
+    int n, cap;
+    orc_particle* p;
+} orc_list;
+
+typedef struct {
+    /* parameters */
+    double L, lB, kappa, rc, eps, rho0NA;
+    int ion_coupling;
+    uint64_t R2; /* exact integer Coulomb cutoff on squared lattice distance */
+    uint32_t key[2];
+    /* conditions */
+    double lnKA, lnKB, lnKion;
+    /* cell schedule */
+    int n;           /* cells per dimension */
+    int trials;      /* trials per active cell per phase */
+    int fixed_grid;  /* 1 = never shift the grid (test-only negative control) */
+    int pairing;     /* 1 = trials act on reflection-paired cells, 0 = single cells */
+    /* state, in global order */
+    int np, npcap;
+    orc_particle* P;
+    int nc;
+    uint32_t* core_x; /* nc*3 */
+    double* core_delta;
+    uint64_t sweep;
+    int64_t paper_trial;
+    double E; /* running energy: brute force at build, then += accepted dU */
+    int64_t attempts[6], accepts[6];
+    /* cell lists during a sweep */
+    orc_list* cells;
+    int ncells;
+    orc_particle* flat; /* scratch: all particles in one array */
+    int flat_cap;
+    /* logging */
+    orc_trial* log;
+    int64_t log_cap, log_n;
+    /* checking: when set, every trial's local dU is compared with a brute-force
+       energy difference and the largest deviation is kept */
+    int check_dU;
+    double max_dU_err;
+} orc_sys;
+
+/* ------------------------------------------------------------------------- */
+/* Small helpers                                                              */
+/* ------------------------------------------------------------------------- */
+static int charge_of(int kind, int charged)
+{
+    if (kind == ORC_ACID) return charged ? -1 : 0;
+    if (kind == ORC_BASE) return charged ? 1 : 0;
+    if (kind == ORC_XPOS) return 1;
+    if (kind == ORC_XNEG) return -1;
+    return 0;
+}
+static int is_ion(int kind) { return kind == ORC_XPOS || kind == ORC_XNEG; }
+
+/* floor(w * m / 2^32): uniform integer in [0, m) from one 32-bit word */
+static uint32_t pick32(uint32_t w, uint32_t m) { return (uint32_t)(((uint64_t)w * m) >> 32); }
+
+/* floor((hi*2^32 + lo) * m / 2^64): uniform integer in [0, m) from two words */
+static uint32_t pick64(uint32_t hi, uint32_t lo, uint32_t m)
+{
+    uint64_t low = ((uint64_t)lo * m) >> 32;
+    uint64_t top = (uint64_t)hi * m + low;
+    return (uint32_t)(top >> 32);
+}
+
+/* uniform double in [0,1) with 53 random bits */
+static double unit53(uint32_t a, uint32_t b)
+{
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+uint64_t orc_cutoff_R2(double rc, double L)
+{
+    double t = (rc / L) * TWO32;
+    return (uint64_t)ceil(t * t);
+}
+
+/* x in [any real] -> fixed point on the periodic lattice of 2^32 points per box edge */
+void orc_to_fixed(int64_t n3, const double* xyz, double L, uint32_t* out)
+{
+    for (int64_t i = 0; i < n3; ++i) {
+        double f = xyz[i] / L;
+        f -= floor(f);
+        double v = floor(f * TWO32);
+        if (v >= TWO32) v = 0.0;
+        out[i] = (uint32_t)v;
+    }
+}
+
+/* cell boundaries b_k = ceil(k 2^32 / n); cell of relative coordinate y */
+static uint64_t cell_lo(int k, int n) { return (((uint64_t)k << 32) + (uint64_t)n - 1) / (uint64_t)n; }
+static int cell_of(uint32_t y, int n) { return (int)(((uint64_t)y * (uint64_t)n) >> 32); }
+
+/* ------------------------------------------------------------------------- */
+/* Energies                                                                   */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    uint32_t x[3];
+    int q;       /* charge in this state */
+    int ion;     /* 1 if a free ion */
+    int present; /* 0 if absent in this state */
+} orc_state_pt;
+
+static void lattice_delta(const uint32_t* a, const uint32_t* b, int32_t d[3])
+{
+    for (int k = 0; k < 3; ++k) d[k] = (int32_t)(b[k] - a[k]);
+}
+
+static double wca(double r2, double eps)
+{
+    if (r2 < 0.25) return INFINITY;
+    double ir2 = 1.0 / r2;
+    double ir6 = ir2 * ir2 * ir2;
+    return 4.0 * eps * (ir6 * ir6 - ir6) + eps;
+}
+
+/* energy of one pair; either member may be absent */
+static double pair_energy(const orc_sys* S, const orc_state_pt* a, const orc_state_pt* b)
+{
+    if (!a->present || !b->present) return 0.0;
+    if (!S->ion_coupling && (a->ion || b->ion)) return 0.0;
+    int32_t d[3];
+    lattice_delta(a->x, b->x, d);
+    uint64_t r2i = (uint64_t)((int64_t)d[0] * d[0]) + (uint64_t)((int64_t)d[1] * d[1]) +
+                   (uint64_t)((int64_t)d[2] * d[2]);
+    double s = S->L / TWO32;
+    double r2 = (double)r2i * s * s;
+    double e = 0.0;
+    if (S->eps > 0.0 && (a->ion || b->ion) && r2 < 1.2599210498948731647672106) /* 2^(1/3) */
+        e += wca(r2, S->eps);
+    if (r2i < S->R2 && a->q != 0 && b->q != 0) {
+        double r = sqrt(r2);
+        e += S->lB * (double)(a->q * b->q) * exp(-S->kappa * r) / r;
+    }
+    return e;
+}
+
+/* energy of a free ion with all nanoparticle cores (expanded WCA, Table II) */
+static double core_energy(const orc_sys* S, const orc_state_pt* a)
+{
+    if (!a->present || !a->ion || !S->ion_coupling || S->eps <= 0.0) return 0.0;
+    double e = 0.0;
+    double s = S->L / TWO32;
+    for (int c = 0; c < S->nc; ++c) {
+        int32_t d[3];
+        lattice_delta(a->x, &S->core_x[3 * c], d);
+        double dx = d[0] * s, dy = d[1] * s, dz = d[2] * s;
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        double sh = r - S->core_delta[c];
+        if (sh < 1.122462048309373) /* 2^(1/6) */
+            e += wca(sh * sh, S->eps);
+    }
+    return e;
+}
+
+static orc_state_pt as_state(const orc_particle* p)
+{
+    orc_state_pt s;
+    memcpy(s.x, p->x, sizeof s.x);
+    s.q = charge_of(p->kind, p->charged);
+    s.ion = is_ion(p->kind);
+    s.present = 1;
+    return s;
+}
+
+static int total_count(const orc_sys* S, int in_cells)
+{
+    if (!in_cells) return S->np;
+    int t = 0;
+    for (int c = 0; c < S->ncells; ++c) t += S->cells[c].n;
+    return t;
+}
+
+/* brute-force total energy: every pair once, plus ion-core terms */
+static double energy_of_array(const orc_sys* S, const orc_particle* P, int np)
+{
+    double E = 0.0;
+    for (int i = 0; i < np; ++i) {
+        orc_state_pt a = as_state(&P[i]);
+        E += core_energy(S, &a);
+        for (int j = i + 1; j < np; ++j) {
+            orc_state_pt b = as_state(&P[j]);
+            E += pair_energy(S, &a, &b);
+        }
+    }
+    return E;
+}
+
+double orc_energy(const orc_sys* S) { return energy_of_array(S, S->P, S->np); }
+
+/* ------------------------------------------------------------------------- */
+/* Creation and set-up                                                        */
+/* ------------------------------------------------------------------------- */
+orc_sys* orc_create(double L, int n_cells, double lB, double kappa, double rc, double eps,
+                    double rho0NA, int ion_coupling, uint64_t seed, uint32_t replica)
+{
+    orc_sys* S = (orc_sys*)calloc(1, sizeof(orc_sys));
+    S->L = L; S->n = n_cells; S->lB = lB; S->kappa = kappa; S->rc = rc; S->eps = eps;
+    S->rho0NA = rho0NA; S->ion_coupling = ion_coupling;
+    S->R2 = orc_cutoff_R2(rc, L);
+    S->key[0] = (uint32_t)seed;
+    S->key[1] = (uint32_t)(seed >> 32) ^ replica;
+    S->trials = 1;
+    S->ncells = n_cells * n_cells * n_cells;
+    S->cells = (orc_list*)calloc((size_t)S->ncells, sizeof(orc_list));
+    return S;
+}
+
+void orc_destroy(orc_sys* S)
+{
+    if (!S) return;
+    for (int c = 0; c < S->ncells; ++c) free(S->cells[c].p);
+    free(S->cells); free(S->flat); free(S->P); free(S->core_x); free(S->core_delta);
+    free(S);
+}
+
+void orc_set_conditions(orc_sys* S, double pH, double pKa, double pKb, double pIXp, double pIXm,
+                        double pKw)
+{
+    double pOH = pKw - pH;
+    S->lnKA = (pH - pKa - pIXp) * LN10;
+    S->lnKB = (pOH - pKb - pIXm) * LN10;
+    S->lnKion = -(pIXp + pIXm) * LN10;
+}
+
+void orc_set_kappa(orc_sys* S, double kappa) { S->kappa = kappa; }
+
+void orc_set_schedule(orc_sys* S, int trials_per_cell, int fixed_grid, int pairing)
+{
+    S->trials = trials_per_cell;
+    S->fixed_grid = fixed_grid;
+    S->pairing = pairing;
+}
+
+void orc_set_log(orc_sys* S, orc_trial* log, int64_t cap)
+{
+    S->log = log; S->log_cap = cap; S->log_n = 0;
+}
+int64_t orc_log_count(const orc_sys* S) { return S->log_n; }
+
+void orc_set_check(orc_sys* S, int on) { S->check_dU = on; S->max_dU_err = 0.0; }
+double orc_max_dU_err(const orc_sys* S) { return S->max_dU_err; }
+
+static void ensure_cap(orc_sys* S, int need)
+{
+    if (need <= S->npcap) return;
+    int c = S->npcap ? S->npcap : 64;
+    while (c < need) c *= 2;
+    S->P = (orc_particle*)realloc(S->P, (size_t)c * sizeof(orc_particle));
+    S->npcap = c;
+}
+
+static void list_push(orc_list* l, const orc_particle* p)
+{
+    if (l->n == l->cap) {
+        l->cap = l->cap ? 2 * l->cap : 16;
+        l->p = (orc_particle*)realloc(l->p, (size_t)l->cap * sizeof(orc_particle));
+    }
+    l->p[l->n++] = *p;
+}
+
+/* stable binning of the global array into the cells of grid shift o */
+static void bin_into_cells(orc_sys* S, const uint32_t o[3])
+{
+    int n = S->n;
+    for (int c = 0; c < S->ncells; ++c) S->cells[c].n = 0;
+    for (int i = 0; i < S->np; ++i) {
+        const orc_particle* p = &S->P[i];
+        int cx = cell_of(p->x[0] - o[0], n), cy = cell_of(p->x[1] - o[1], n), cz = cell_of(p->x[2] - o[2], n);
+        list_push(&S->cells[cx + n * (cy + n * cz)], p);
+    }
+}
+
+/* concatenate the cell lists back into the global array (cell index order) */
+static void gather_from_cells(orc_sys* S)
+{
+    int np = total_count(S, 1);
+    ensure_cap(S, np);
+    int k = 0;
+    for (int c = 0; c < S->ncells; ++c)
+        for (int j = 0; j < S->cells[c].n; ++j) S->P[k++] = S->cells[c].p[j];
+    S->np = k;
+}
+
+/* Particles in input order; the build then puts them into the cells of the
+   unshifted grid (stable) and takes that as the initial global order. */
+int orc_set_particles(orc_sys* S, int np, const uint32_t* xyz, const int32_t* kind,
+                      const int32_t* charged, const int32_t* sid)
+{
+    ensure_cap(S, np > 0 ? np : 1);
+    S->np = np;
+    for (int i = 0; i < np; ++i) {
+        orc_particle* p = &S->P[i];
+        p->x[0] = xyz[3 * i]; p->x[1] = xyz[3 * i + 1]; p->x[2] = xyz[3 * i + 2];
+        p->kind = kind[i];
+        p->charged = is_ion(kind[i]) ? 1 : (charged ? charged[i] : 0);
+        p->sid = sid ? sid[i] : (is_ion(kind[i]) ? -1 : i);
+    }
+    uint32_t o[3] = {0, 0, 0};
+    bin_into_cells(S, o);
+    gather_from_cells(S);
+    S->E = orc_energy(S);
+    S->sweep = 0;
+    S->paper_trial = 0;
+    memset(S->attempts, 0, sizeof S->attempts);
+    memset(S->accepts, 0, sizeof S->accepts);
+    return 0;
+}
+
+int orc_set_cores(orc_sys* S, int nc, const uint32_t* xyz, const double* radius)
+{
+    free(S->core_x); free(S->core_delta);
+    S->nc = nc;
+    S->core_x = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (size_t)(nc > 0 ? nc : 1));
+    S->core_delta = (double*)malloc(sizeof(double) * (size_t)(nc > 0 ? nc : 1));
+    for (int c = 0; c < nc; ++c) {
+        memcpy(&S->core_x[3 * c], &xyz[3 * c], 3 * sizeof(uint32_t));
+        S->core_delta[c] = radius[c] - 0.5; /* Delta = R - r with ion radius r = sigma/2 */
+    }
+    S->E = orc_energy(S);
+    return 0;
+}
+
+int orc_num_particles(const orc_sys* S) { return S->np; }
+
+int orc_get_particles(const orc_sys* S, int cap, uint32_t* xyz, int32_t* kind, int32_t* charged,
+                      int32_t* sid)
+{
+    int n = S->np < cap ? S->np : cap;
+    for (int i = 0; i < n; ++i) {
+        const orc_particle* p = &S->P[i];
+        xyz[3 * i] = p->x[0]; xyz[3 * i + 1] = p->x[1]; xyz[3 * i + 2] = p->x[2];
+        kind[i] = p->kind; charged[i] = p->charged; sid[i] = p->sid;
+    }
+    return S->np;
+}
+
+/* counts: [nA, nA-, nB, nB+, nX+, nX-] */
+void orc_counts(const orc_sys* S, int64_t out[6])
+{
+    memset(out, 0, 6 * sizeof(int64_t));
+    for (int i = 0; i < S->np; ++i) {
+        const orc_particle* p = &S->P[i];
+        if (p->kind == ORC_ACID) { out[0]++; out[1] += p->charged; }
+        else if (p->kind == ORC_BASE) { out[2]++; out[3] += p->charged; }
+        else if (p->kind == ORC_XPOS) out[4]++;
+        else if (p->kind == ORC_XNEG) out[5]++;
+    }
+}
+
+double orc_running_energy(const orc_sys* S) { return S->E; }
+uint64_t orc_sweep_index(const orc_sys* S) { return S->sweep; }
+void orc_move_stats(const orc_sys* S, int64_t att[6], int64_t acc[6])
+{
+    memcpy(att, S->attempts, sizeof S->attempts);
+    memcpy(acc, S->accepts, sizeof S->accepts);
+}
+
+/* ------------------------------------------------------------------------- */
+/* One trial, shared by both schedules                                        */
+/* ------------------------------------------------------------------------- */
+/* A "changed" particle: an existing one (index into the particle set being
+   moved on, old state from there) or a new one (old state absent). */
+typedef struct {
+    int idx;           /* index into the working set; -1 for an inserted ion */
+    orc_state_pt old_s, new_s;
+} orc_change;
+
+/* dU = E(new) - E(old), restricted to the terms that involve changed particles:
+   changed-vs-unchanged pairs, the pair between the changed particles, and
+   ion-core terms. 'set' holds every particle of the system (np of them). */
+static double local_dU(const orc_sys* S, const orc_particle* set, int np, const orc_change* ch, int nch)
+{
+    double dU = 0.0;
+    for (int a = 0; a < nch; ++a) {
+        dU += core_energy(S, &ch[a].new_s) - core_energy(S, &ch[a].old_s);
+        for (int j = 0; j < np; ++j) {
+            int skip = 0;
+            for (int b = 0; b < nch; ++b)
+                if (ch[b].idx == j) skip = 1;
+            if (skip) continue;
+            orc_state_pt pj = as_state(&set[j]);
+            double en = pair_energy(S, &ch[a].new_s, &pj);
+            double eo = pair_energy(S, &ch[a].old_s, &pj);
+            dU += en - eo;
+        }
+    }
+    if (nch == 2)
+        dU += pair_energy(S, &ch[0].new_s, &ch[1].new_s) - pair_energy(S, &ch[0].old_s, &ch[1].old_s);
+    return dU;
+}
+
+/* A trial acts on a "domain": one cell, two mutually non-interacting cells of
+   the same colour (cell mode), or the whole box (paper mode).  Its particles
+   are the concatenation of the domain's lists; picks are uniform over the
+   domain's eligible particles in that order. */
+typedef struct {
+    int ncell;                  /* number of cells (1 or 2); 1 in paper mode */
+    orc_list* list[2];
+    int cell[2];                /* linear cell index (cell mode) */
+    uint32_t ins_base[2][3];    /* insertion region per cell: lattice origin */
+    uint32_t ins_width[2][3];   /* lattice width; 0 = whole box (paper mode) */
+    double lnZ[2];              /* ln(rho0 NA / q) where q is the insertion density
+                                   of a point in that cell: 1/(ncell V_cell) */
+    int nreact;
+    int react[3];
+    int paper;
+} orc_dom;
+
+/* domain-order index -> (cell j, local index) */
+static void dom_locate(const orc_dom* D, int g, int* j, int* i)
+{
+    if (D->ncell == 2 && g >= D->list[0]->n) { *j = 1; *i = g - D->list[0]->n; }
+    else { *j = 0; *i = g; }
+}
+
+static int dom_size(const orc_dom* D)
+{
+    int n = 0;
+    for (int j = 0; j < D->ncell; ++j) n += D->list[j]->n;
+    return n;
+}
+
+static orc_particle* dom_at(const orc_dom* D, int g)
+{
+    int j, i;
+    dom_locate(D, g, &j, &i);
+    return &D->list[j]->p[i];
+}
+
+/* domain-order index of the k-th particle satisfying the predicate */
+static int kth(const orc_dom* D, int kind, int charged, int k)
+{
+    int n = dom_size(D);
+    for (int g = 0; g < n; ++g) {
+        const orc_particle* p = dom_at(D, g);
+        if (p->kind == kind && (is_ion(kind) || p->charged == charged)) {
+            if (k == 0) return g;
+            --k;
+        }
+    }
+    return -1;
+}
+
+static int count_of(const orc_dom* D, int kind, int charged)
+{
+    int c = 0, n = dom_size(D);
+    for (int g = 0; g < n; ++g) {
+        const orc_particle* p = dom_at(D, g);
+        if (p->kind == kind && (is_ion(kind) || p->charged == charged)) ++c;
+    }
+    return c;
+}
+
+/* insertion point: choose a cell of the domain uniformly (word wc), then a
+   lattice point uniformly inside it (two words per coordinate, ws[0..5]);
+   paper mode: one word per coordinate over the whole box */
+static int insertion_point(const orc_dom* D, uint32_t wc, const uint32_t* ws, uint32_t out[3])
+{
+    int j = D->ncell == 1 ? 0 : (int)pick32(wc, (uint32_t)D->ncell);
+    for (int d = 0; d < 3; ++d) {
+        if (D->ins_width[j][d] == 0)
+            out[d] = ws[2 * d];
+        else
+            out[d] = D->ins_base[j][d] + pick64(ws[2 * d], ws[2 * d + 1], D->ins_width[j][d]);
+    }
+    return j;
+}
+
+/* Every particle of the system in one array, for the energy sums; base[j]
+   is the offset of domain cell j inside it. */
+static orc_particle* flatten(orc_sys* S, const orc_dom* D, int* nall, int base[2])
+{
+    if (D->paper) {
+        *nall = D->list[0]->n; base[0] = 0;
+        return D->list[0]->p;
+    }
+    int n = total_count(S, 1);
+    if (n > S->flat_cap) {
+        S->flat_cap = n + 64;
+        S->flat = (orc_particle*)realloc(S->flat, (size_t)S->flat_cap * sizeof(orc_particle));
+    }
+    int k = 0;
+    for (int c = 0; c < S->ncells; ++c) {
+        for (int j = 0; j < D->ncell; ++j)
+            if (c == D->cell[j]) base[j] = k;
+        for (int i = 0; i < S->cells[c].n; ++i) S->flat[k++] = S->cells[c].p[i];
+    }
+    *nall = k;
+    return S->flat;
+}
+
+static void swap_remove(orc_list* l, int i)
+{
+    l->p[i] = l->p[l->n - 1];
+    l->n--;
+}
+
+static void do_trial(orc_sys* S, orc_dom* D, const uint32_t* w, int64_t cell, int64_t trial)
+{
+    uint32_t k = pick32(w[0], (uint32_t)(2 * D->nreact));
+    int reaction = D->react[k >> 1];
+    int dir = (int)(k & 1u);
+    int move = 2 * reaction + dir;
+
+    int m0a = count_of(D, ORC_ACID, 0), mca = count_of(D, ORC_ACID, 1);
+    int m0b = count_of(D, ORC_BASE, 0), mcb = count_of(D, ORC_BASE, 1);
+    int npos = count_of(D, ORC_XPOS, 1), nneg = count_of(D, ORC_XNEG, 1);
+
+    int auto_reject = 0;
+    int site = -1, del_pos = -1, del_neg = -1, ins_pos = 0, ins_neg = 0;
+    double lnp_counts = 0.0; /* every term of ln p except the volume terms and -dU */
+    switch (move) {
+    case 0: /* acid forward: A -> A-, X+ in */
+        if (m0a == 0) { auto_reject = 1; break; }
+        site = kth(D, ORC_ACID, 0, (int)pick32(w[1], (uint32_t)m0a));
+        ins_pos = 1;
+        lnp_counts = log((double)m0a) - log((double)(mca + 1)) - log((double)(npos + 1)) + S->lnKA;
+        break;
+    case 1: /* acid reverse: A- -> A, X+ out */
+        if (mca == 0 || npos == 0) { auto_reject = 1; break; }
+        site = kth(D, ORC_ACID, 1, (int)pick32(w[1], (uint32_t)mca));
+        del_pos = kth(D, ORC_XPOS, 1, (int)pick32(w[2], (uint32_t)npos));
+        lnp_counts = log((double)mca) + log((double)npos) - log((double)(m0a + 1)) - S->lnKA;
+        break;
+    case 2: /* base forward: B -> B+, X- in */
+        if (m0b == 0) { auto_reject = 1; break; }
+        site = kth(D, ORC_BASE, 0, (int)pick32(w[1], (uint32_t)m0b));
+        ins_neg = 1;
+        lnp_counts = log((double)m0b) - log((double)(mcb + 1)) - log((double)(nneg + 1)) + S->lnKB;
+        break;
+    case 3: /* base reverse: B+ -> B, X- out */
+        if (mcb == 0 || nneg == 0) { auto_reject = 1; break; }
+        site = kth(D, ORC_BASE, 1, (int)pick32(w[1], (uint32_t)mcb));
+        del_neg = kth(D, ORC_XNEG, 1, (int)pick32(w[3], (uint32_t)nneg));
+        lnp_counts = log((double)mcb) + log((double)nneg) - log((double)(m0b + 1)) - S->lnKB;
+        break;
+    case 4: /* salt pair in */
+        ins_pos = ins_neg = 1;
+        lnp_counts = -log((double)(npos + 1)) - log((double)(nneg + 1)) + S->lnKion;
+        break;
+    case 5: /* salt pair out */
+        if (npos == 0 || nneg == 0) { auto_reject = 1; break; }
+        del_pos = kth(D, ORC_XPOS, 1, (int)pick32(w[2], (uint32_t)npos));
+        del_neg = kth(D, ORC_XNEG, 1, (int)pick32(w[3], (uint32_t)nneg));
+        lnp_counts = log((double)npos) + log((double)nneg) - S->lnKion;
+        break;
+    }
+    S->attempts[move]++;
+    double u = unit53(w[16], w[17]);
+    if (auto_reject) {
+        if (S->log && S->log_n < S->log_cap) {
+            orc_trial* t = &S->log[S->log_n++];
+            t->sweep = (int64_t)S->sweep; t->cell = cell; t->trial = trial; t->move = move;
+            t->status = 2; t->dU = NAN; t->lnp = NAN; t->u = u;
+        }
+        return;
+    }
+
+    /* positions of inserted ions, and the volume terms: each inserted ion
+       contributes +ln(rho0 NA / q), each deleted one -ln(rho0 NA / q), with q
+       the density at which the reverse move would propose its position */
+    uint32_t xp[3], xn[3];
+    int jp = -1, jn = -1;
+    double lnvol = 0.0;
+    if (ins_pos) { jp = insertion_point(D, w[18], &w[4], xp); lnvol += D->lnZ[jp]; }
+    if (ins_neg) { jn = insertion_point(D, w[19], &w[10], xn); lnvol += D->lnZ[jn]; }
+    int sj = -1, si = -1, pj = -1, pi = -1, nj = -1, ni = -1;
+    if (site >= 0) dom_locate(D, site, &sj, &si);
+    if (del_pos >= 0) { dom_locate(D, del_pos, &pj, &pi); lnvol -= D->lnZ[pj]; }
+    if (del_neg >= 0) { dom_locate(D, del_neg, &nj, &ni); lnvol -= D->lnZ[nj]; }
+
+    int base[2] = {0, 0}, nall = 0;
+    orc_particle* all = flatten(S, D, &nall, base);
+
+    orc_change ch[2];
+    int nch = 0;
+    if (site >= 0) {
+        orc_change* c = &ch[nch++];
+        const orc_particle* p = &D->list[sj]->p[si];
+        c->idx = base[sj] + si;
+        c->old_s = as_state(p);
+        c->new_s = c->old_s;
+        c->new_s.q = charge_of(p->kind, !p->charged);
+    }
+    if (del_pos >= 0) {
+        orc_change* c = &ch[nch++];
+        c->idx = base[pj] + pi;
+        c->old_s = as_state(&D->list[pj]->p[pi]);
+        c->new_s = c->old_s; c->new_s.present = 0;
+    }
+    if (del_neg >= 0) {
+        orc_change* c = &ch[nch++];
+        c->idx = base[nj] + ni;
+        c->old_s = as_state(&D->list[nj]->p[ni]);
+        c->new_s = c->old_s; c->new_s.present = 0;
+    }
+    if (ins_pos) {
+        orc_change* c = &ch[nch++];
+        c->idx = -1;
+        memcpy(c->new_s.x, xp, sizeof xp);
+        c->new_s.q = 1; c->new_s.ion = 1; c->new_s.present = 1;
+        c->old_s = c->new_s; c->old_s.present = 0;
+    }
+    if (ins_neg) {
+        orc_change* c = &ch[nch++];
+        c->idx = -1;
+        memcpy(c->new_s.x, xn, sizeof xn);
+        c->new_s.q = -1; c->new_s.ion = 1; c->new_s.present = 1;
+        c->old_s = c->new_s; c->old_s.present = 0;
+    }
+
+    double dU = local_dU(S, all, nall, ch, nch);
+    double lnp = lnp_counts + lnvol - dU;
+    int accept = u < exp(lnp < 0.0 ? lnp : 0.0);
+
+    if (S->check_dU && isfinite(dU)) {
+        /* brute force: total energy of the new state minus that of the old */
+        double e_old = energy_of_array(S, all, nall);
+        orc_particle* tmp = (orc_particle*)malloc((size_t)(nall + 2) * sizeof(orc_particle));
+        int m = 0;
+        for (int j = 0; j < nall; ++j) {
+            int gone = 0;
+            for (int b = 0; b < nch; ++b)
+                if (ch[b].idx == j && !ch[b].new_s.present) gone = 1;
+            if (gone) continue;
+            tmp[m] = all[j];
+            if (site >= 0 && j == base[sj] + si) tmp[m].charged = !tmp[m].charged;
+            ++m;
+        }
+        if (ins_pos) { memcpy(tmp[m].x, xp, sizeof xp); tmp[m].kind = ORC_XPOS; tmp[m].charged = 1; tmp[m].sid = -1; ++m; }
+        if (ins_neg) { memcpy(tmp[m].x, xn, sizeof xn); tmp[m].kind = ORC_XNEG; tmp[m].charged = 1; tmp[m].sid = -1; ++m; }
+        double e_new = energy_of_array(S, tmp, m);
+        free(tmp);
+        double err = fabs((e_new - e_old) - dU) / (fabs(dU) > 1.0 ? fabs(dU) : 1.0);
+        if (err > S->max_dU_err) S->max_dU_err = err;
+    }
+
+    if (S->log && S->log_n < S->log_cap) {
+        orc_trial* t = &S->log[S->log_n++];
+        t->sweep = (int64_t)S->sweep; t->cell = cell; t->trial = trial; t->move = move;
+        t->status = accept; t->dU = dU; t->lnp = lnp; t->u = u;
+    }
+    if (!accept) return;
+
+    /* commit: flip in place; deletions, each by moving the last element of its
+       cell into the hole (when both deleted ions sit in one cell, the one at
+       the higher index goes first); insertions appended to their cells, X+
+       before X- */
+    S->accepts[move]++;
+    S->E += dU;
+    if (site >= 0) D->list[sj]->p[si].charged = !D->list[sj]->p[si].charged;
+    if (del_pos >= 0 && del_neg >= 0 && pj == nj && ni > pi) {
+        swap_remove(D->list[nj], ni);
+        swap_remove(D->list[pj], pi);
+    } else {
+        if (del_pos >= 0) swap_remove(D->list[pj], pi);
+        if (del_neg >= 0) swap_remove(D->list[nj], ni);
+    }
+    orc_particle q;
+    q.charged = 1; q.sid = -1;
+    if (ins_pos) { memcpy(q.x, xp, sizeof xp); q.kind = ORC_XPOS; list_push(D->list[jp], &q); }
+    if (ins_neg) { memcpy(q.x, xn, sizeof xn); q.kind = ORC_XNEG; list_push(D->list[jn], &q); }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cell schedule                                                              */
+/* ------------------------------------------------------------------------- */
+void orc_shift(const orc_sys* S, uint64_t sweep, uint32_t o[3])
+{
+    if (S->fixed_grid) { o[0] = o[1] = o[2] = 0; return; }
+    uint32_t ctr[4] = {(uint32_t)sweep, 0u, 0u, TAG_SHIFT}, w[4];
+    orc_philox(ctr, S->key, w);
+    o[0] = w[0]; o[1] = w[1]; o[2] = w[2];
+}
+
+/* Partner of active cell a (of M active cells of one colour) in a phase: the
+   reflection a -> (c - a) mod M about a point c drawn from the phase's own
+   counter.  It pairs far-apart cells, is an involution, and has no fixed
+   point when M is even (one when M is odd). */
+uint32_t orc_partner(const orc_sys* S, uint64_t sweep, int colour, uint32_t a, uint32_t M)
+{
+    uint32_t ctr[4] = {(uint32_t)sweep, (uint32_t)colour, 0u, TAG_PAIR}, w[4];
+    orc_philox(ctr, S->key, w);
+    uint32_t r = pick32(w[0], M);
+    uint64_t c = ((uint64_t)M - 1u + 2ull * M - 2ull * r) % M; /* (M - 1 - 2r) mod M */
+    return (uint32_t)((c + M - a) % M);
+}
+
+static void trial_words(const orc_sys* S, uint32_t tag, uint32_t c0, uint32_t c1, uint32_t c2base, uint32_t w[20])
+{
+    for (uint32_t b = 0; b < 5; ++b) {
+        uint32_t ctr[4] = {c0, c1, c2base + b, tag};
+        orc_philox(ctr, S->key, &w[4 * b]);
+    }
+}
+
+static void set_cell_region(const orc_sys* S, orc_dom* D, int j, int c, const uint32_t o[3], double lnZ0)
+{
+    int n = S->n;
+    int cc[3] = {c % n, (c / n) % n, c / (n * n)};
+    double lnV = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        uint64_t lo = cell_lo(cc[d], n), hi = cell_lo(cc[d] + 1, n);
+        D->ins_base[j][d] = o[d] + (uint32_t)lo;
+        D->ins_width[j][d] = (uint32_t)(hi - lo);
+        lnV += log((double)(hi - lo));
+    }
+    D->lnZ[j] = lnZ0 + lnV;
+    D->list[j] = &S->cells[c];
+    D->cell[j] = c;
+}
+
+static void one_sweep(orc_sys* S, int32_t* series)
+{
+    int n = S->n, h = n / 2;
+    uint32_t M = (uint32_t)(h * h * h);
+    uint32_t o[3];
+    orc_shift(S, S->sweep, o);
+    bin_into_cells(S, o);
+    double lnZ0 = log(S->rho0NA) + 3.0 * log(S->L / TWO32);
+    for (int colour = 0; colour < 8; ++colour) {
+        int px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
+        for (uint32_t a = 0; a < M; ++a) {
+            uint32_t b = S->pairing ? orc_partner(S, S->sweep, colour, a, M) : a;
+            if (b < a) continue; /* the domain is handled from its lower member */
+            uint32_t mem[2] = {a, b};
+            orc_dom D;
+            memset(&D, 0, sizeof D);
+            D.ncell = (b == a) ? 1 : 2;
+            double lnk = log((double)D.ncell);
+            for (int j = 0; j < D.ncell; ++j) {
+                uint32_t m = mem[j];
+                int i = (int)(m % (uint32_t)h), jj = (int)((m / (uint32_t)h) % (uint32_t)h), kk = (int)(m / (uint32_t)(h * h));
+                int c = (2 * i + px) + n * ((2 * jj + py) + n * (2 * kk + pz));
+                set_cell_region(S, &D, j, c, o, lnZ0 + lnk);
+            }
+            /* static move set: the domain's site content does not depend on the state */
+            int has_acid = 0, has_base = 0;
+            for (int j = 0; j < D.ncell; ++j)
+                for (int q = 0; q < D.list[j]->n; ++q) {
+                    if (D.list[j]->p[q].kind == ORC_ACID) has_acid = 1;
+                    if (D.list[j]->p[q].kind == ORC_BASE) has_base = 1;
+                }
+            D.nreact = 0;
+            if (has_acid) D.react[D.nreact++] = 0;
+            if (has_base) D.react[D.nreact++] = 1;
+            D.react[D.nreact++] = 2;
+            int ntr = S->trials * D.ncell;
+            for (int t = 0; t < ntr; ++t) {
+                uint32_t w[20];
+                trial_words(S, TAG_TRIAL, (uint32_t)S->sweep, (uint32_t)D.cell[0], (uint32_t)t * 8u, w);
+                do_trial(S, &D, w, D.cell[0], t);
+            }
+        }
+    }
+    gather_from_cells(S);
+    if (series) {
+        int64_t cnt[6];
+        orc_counts(S, cnt);
+        series[0] = (int32_t)cnt[1]; series[1] = (int32_t)cnt[3];
+        series[2] = (int32_t)cnt[4]; series[3] = (int32_t)cnt[5];
+    }
+    S->sweep++;
+}
+
+/* series: nsweeps x [nA-, nB+, nX+, nX-] after each sweep (may be NULL) */
+int orc_sweeps(orc_sys* S, int64_t nsweeps, int32_t* series)
+{
+    for (int64_t s = 0; s < nsweeps; ++s) one_sweep(S, series ? &series[4 * s] : NULL);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Paper schedule: global moves                                               */
+/* ------------------------------------------------------------------------- */
+/* series: one row [nA-, nB+, nX+, nX-] every sample_every trials */
+int orc_paper_trials(orc_sys* S, int64_t ntrials, int64_t sample_every, int32_t* series)
+{
+    orc_dom D;
+    memset(&D, 0, sizeof D);
+    D.paper = 1;
+    D.ncell = 1;
+    D.nreact = 3;
+    D.react[0] = 0; D.react[1] = 1; D.react[2] = 2;
+    D.lnZ[0] = log(S->rho0NA * S->L * S->L * S->L);
+    orc_list whole;
+    int64_t cnt[6];
+    int64_t row = 0;
+    for (int64_t t = 0; t < ntrials; ++t) {
+        uint32_t w[20];
+        int64_t g = S->paper_trial++;
+        trial_words(S, TAG_PAPER, (uint32_t)g, (uint32_t)(g >> 32), 0u, w);
+        whole.n = S->np; whole.cap = S->npcap; whole.p = S->P;
+        D.list[0] = &whole;
+        do_trial(S, &D, w, -1, g);
+        S->np = whole.n; S->npcap = whole.cap; S->P = whole.p;
+        if (series && sample_every > 0 && (t + 1) % sample_every == 0) {
+            orc_counts(S, cnt);
+            series[4 * row + 0] = (int32_t)cnt[1]; series[4 * row + 1] = (int32_t)cnt[3];
+            series[4 * row + 2] = (int32_t)cnt[4]; series[4 * row + 3] = (int32_t)cnt[5];
+            ++row;
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,313 @@
+"""Pins of the oracle's Monte Carlo (no GPU).
+
+The oracle is checked against things other than itself: rocRAND's Philox,
+brute-force total energies, exact ideal-ion distributions, the exact 2^N
+enumeration, a one-site quadrature, and the paper's global-move schedule
+against the cell schedule.  A fixed (never shifted) cell grid is the planted
+mistake that must fail.
+"""
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_forms as cf
+from paper_2109_07527_amd.stats import mean_se
+from workloads import config1, random_sites, ring
+
+RHO = 0.0269424
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+# ---------------------------------------------------------------- RNG ----
+def test_philox_matches_rocrand():
+    """The oracle's Philox4x32-10 against rocRAND's generator compiled for the host."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    d = tempfile.mkdtemp()
+    exe = os.path.join(d, "rr")
+    subprocess.check_call([hipcc, "-O1", "-o", exe, os.path.join(HERE, "rocrand_philox_ref.cpp")],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    rng = np.random.default_rng(99)
+    rows = []
+    for i in range(300):
+        c = rng.integers(0, 2 ** 32, 4, dtype=np.uint64)
+        c[1] %= 2 ** 30  # rocRAND's skip-ahead offset is 4*(c1:c0) modulo 2^64
+        k = rng.integers(0, 2 ** 32, 2, dtype=np.uint64)
+        if i == 0:
+            c[:] = 0
+            k[:] = 0
+        rows.append((c, k))
+    inp = "\n".join(" ".join("%x" % v for v in list(c) + list(k)) for c, k in rows) + "\n"
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split("\n")
+    for (c, k), line in zip(rows, out):
+        ref = [int(t, 16) for t in line.split()]
+        assert list(oracle.philox(c, k)) == ref
+
+
+# ------------------------------------------------------- fixed point ----
+def test_fixed_point_and_cutoff():
+    L = 40.0
+    X = oracle.to_fixed(np.array([[0.0, L / 2, L - 1e-12], [L, -L / 2, 3 * L / 4]]), L)
+    assert list(X[0]) == [0, 2 ** 31, 0] or list(X[0])[:2] == [0, 2 ** 31]
+    assert list(X[1]) == [0, 2 ** 31, 3 * 2 ** 30]
+    R2 = oracle.cutoff_R2(6.0, 40.0)
+    t = 6.0 / 40.0 * 2 ** 32
+    assert (R2 - 1) < t * t <= R2
+
+
+# --------------------------------------------------- energy pinning ----
+def _mixed_system(seed=3, with_core=True, ion_coupling=1, L=24.0):
+    s = random_sites(12, 10, L, seed, min_dist=1.0)
+    o = oracle.Oracle(L, 4, 2.0, 0.5, 6.0, eps=1.0, ion_coupling=ion_coupling, seed=seed)
+    o.set_conditions(6.0, 5.0, 5.0, 0.5, 0.7)
+    o.set_particles(s["xyz"], s["kind"])
+    if with_core:
+        o.set_cores(np.array([[L / 2, L / 2, L / 2]]), np.array([3.0]))
+    return o
+
+
+@pytest.mark.parametrize("with_core", [False, True])
+def test_local_dU_equals_bruteforce_difference(with_core):
+    """T-7 inside the oracle: every trial's dU equals E_total(new) - E_total(old)."""
+    o = _mixed_system(with_core=with_core)
+    o.set_check(True)
+    o.set_schedule(2)
+    o.sweeps(6)
+    o.paper_trials(3000)
+    assert o.max_dU_err() < 1e-10
+    a, b = o.move_stats()
+    assert b.sum() > 50  # moves were accepted, so the check saw real changes
+
+
+def test_running_energy_and_invariants():
+    """T-11: retained energy equals the brute-force energy; electroneutrality;
+    no free ion overlaps anything or a core."""
+    o = _mixed_system()
+    o.set_schedule(2)
+    s = o.sweeps(40)
+    o.paper_trials(4000)
+    assert o.running_energy() == pytest.approx(o.energy(), rel=1e-9, abs=1e-9)
+    c = o.counts()
+    assert c["nXp"] + c["nBp"] == c["nXm"] + c["nAm"]
+    assert np.all(s[:, 2] + s[:, 1] == s[:, 3] + s[:, 0])
+    X, kind, charged, sid = o.particles()
+    L = 24.0
+    pos = X.astype(np.float64) * (L / 2 ** 32)
+    ions = np.where((kind == 3) | (kind == 4))[0]
+    assert len(ions) > 5
+    for i in ions:
+        d = pos - pos[i]
+        d -= L * np.round(d / L)
+        r = np.sqrt((d * d).sum(1))
+        r[i] = 9.0
+        assert r.min() >= 0.5
+        dc = pos[i] - L / 2
+        dc -= L * np.round(dc / L)
+        assert np.sqrt(dc @ dc) >= 2.5 + 0.5  # Delta = R - 1/2, hard core at Delta + 1/2
+    # sites keep their identity and order of ids is a permutation
+    sites = np.sort(sid[sid >= 0])
+    assert np.array_equal(sites, np.arange(22))
+
+
+def test_deterministic_and_seed_dependent():
+    a, b, c = _mixed_system(seed=3), _mixed_system(seed=3), _mixed_system(seed=3)
+    for o in (a, b, c):
+        o.set_schedule(2)
+    a.sweeps(10)
+    b.sweeps(10)
+    pa, pb = a.particles(), b.particles()
+    for u, v in zip(pa, pb):
+        assert np.array_equal(u, v)
+    c2 = oracle.Oracle(24.0, 4, 2.0, 0.5, 6.0, eps=1.0, seed=4)
+    s = random_sites(12, 10, 24.0, 3, min_dist=1.0)
+    c2.set_conditions(6.0, 5.0, 5.0, 0.5, 0.7)
+    c2.set_particles(s["xyz"], s["kind"])
+    c2.set_cores(np.array([[12.0, 12.0, 12.0]]), np.array([3.0]))
+    c2.set_schedule(2)
+    c2.sweeps(10)
+    assert not all(np.array_equal(u, v) for u, v in zip(pa, c2.particles()))
+
+
+# ------------------------------------------------ statistical pins -----
+def _ideal_40(seed=7, n_cells=6):
+    rng = np.random.default_rng(1)
+    L = 40.0
+    xyz = rng.uniform(0, L, (40, 3))
+    pIX = cf.pIX_from_salt(2.0, 4.5)
+    o = oracle.Oracle(L, n_cells, 0.0, 0.5, 6.0, eps=0.0, seed=seed)
+    o.set_conditions(4.5, 4.5, 0.0, pIX, pIX)
+    o.set_particles(xyz, np.full(40, 1))
+    return o, cf.ideal_alpha(40, 4.5, 4.5, pIX, pIX, L ** 3, RHO)
+
+
+def _within(series, exact, k=3.0, burn=0.1):
+    x = series[int(len(series) * burn):]
+    m, se, tau = mean_se(x)
+    assert abs(m - exact) < k * se + 1e-12, (m, exact, se, tau)
+    return m, se
+
+
+def test_paper_schedule_ideal_limit():
+    """T-1: the paper's global moves sample the exact ideal distribution."""
+    o, ex = _ideal_40()
+    s = o.paper_trials(1_000_000, 50)
+    _within(s[:, 0] / 40.0, ex)
+    h = np.bincount(s[len(s) // 10:, 0], minlength=41) / (len(s) - len(s) // 10)
+    P = cf.ideal_distribution(40, 0, 4.5, 4.5, 0.0, cf.pIX_from_salt(2.0, 4.5),
+                              cf.pIX_from_salt(2.0, 4.5), 64000.0, RHO)[:, 0]
+    assert np.abs(h - P).max() < 0.01
+
+
+def test_cell_schedule_ideal_limit():
+    """T-1 for the shifted-cell schedule (local insertion, cell-local counts)."""
+    o, ex = _ideal_40()
+    o.set_schedule(4)
+    s = o.sweeps(6000)
+    _within(s[:, 0] / 40.0, ex)
+
+
+def test_fixed_grid_negative_control():
+    """T-12: without the per-sweep random shift, cell-local coupled moves keep
+    every cell neutral on its own and the result is wrong; the pin must see it."""
+    o, ex = _ideal_40()
+    o.set_schedule(4, fixed_grid=True)
+    s = o.sweeps(6000)
+    x = s[600:, 0] / 40.0
+    m, se, _ = mean_se(x)
+    assert abs(m - ex) > 6 * se
+
+
+def test_cell_schedule_acids_and_bases_ideal():
+    """T-1 with both reactions and pIX+ != pIX-: marginal means of the exact
+    two-species distribution."""
+    s = random_sites(20, 20, 40.0, 11)
+    pH, pKa, pKb, pIXp, pIXm = 6.0, 6.3, 7.4, 1.8, 2.1
+    P = cf.ideal_distribution(20, 20, pH, pKa, pKb, pIXp, pIXm, 64000.0, RHO)
+    eA = (np.arange(21)[:, None] * P).sum()
+    eB = (np.arange(21)[None, :] * P).sum()
+    for mode in ("paper", "cell"):
+        o = oracle.Oracle(40.0, 6, 0.0, 0.5, 6.0, eps=0.0, seed=21)
+        o.set_conditions(pH, pKa, pKb, pIXp, pIXm)
+        o.set_particles(s["xyz"], s["kind"])
+        if mode == "paper":
+            ser = o.paper_trials(1_000_000, 50)
+        else:
+            o.set_schedule(4)
+            ser = o.sweeps(5000)
+        _within(ser[:, 0], eA)
+        _within(ser[:, 1], eB)
+
+
+def test_salt_only_box():
+    """T-4: no ionizable groups, ideal ions."""
+    pIX = cf.pIX_from_salt(2.0, 7.0)
+    ex = cf.salt_only_mean(64000.0, RHO, pIX, pIX)
+    for mode in ("paper", "cell"):
+        o = oracle.Oracle(40.0, 6, 0.0, 0.5, 6.0, eps=0.0, seed=5)
+        o.set_conditions(7.0, 4.5, 5.0, pIX, pIX)
+        o.set_particles(np.zeros((0, 3)), np.zeros(0, dtype=np.int32))
+        if mode == "paper":
+            ser = o.paper_trials(400_000, 50)
+        else:
+            o.set_schedule(2)
+            ser = o.sweeps(3000)
+        _within(ser[:, 2], ex)
+
+
+def _hist_within(x, P, k=4.0):
+    """every bin of the empirical histogram within k standard errors, the
+    errors inflated by the integrated autocorrelation time of that bin"""
+    from paper_2109_07527_amd.stats import tau_int
+    n = len(x)
+    for v in range(len(P)):
+        ind = (x == v).astype(float)
+        p = ind.mean()
+        tau = tau_int(ind) if 0 < p < 1 else 0.5
+        se = np.sqrt(max(P[v] * (1 - P[v]), 1e-12) * 2 * tau / n)
+        assert abs(p - P[v]) < k * se + 2.0 / n, (v, p, P[v], se)
+
+
+def test_ring_enumeration():
+    """T-5: 12 acid sites on a ring with site-site screened Coulomb and ideal
+    ions; both schedules against the exact 2^12 enumeration."""
+    L = 24.0
+    s = ring(12, L=L)
+    X = oracle.to_fixed(s["xyz"], L)
+    pIX = cf.pIX_from_salt(1.0, 4.5)
+    P, ex, _ = cf.enumerate_sites(X, [1] * 12, L, 2.0, 0.5, 6.0, 4.5, 4.5, 0.0, pIX, pIX, RHO)
+    for mode in ("paper", "cell"):
+        o = oracle.Oracle(L, 4, 2.0, 0.5, 6.0, eps=1.0, ion_coupling=0, seed=13)
+        o.set_conditions(4.5, 4.5, 0.0, pIX, pIX)
+        o.set_particles(s["xyz"], s["kind"])
+        if mode == "paper":
+            ser = o.paper_trials(1_000_000, 50)
+        else:
+            o.set_schedule(16)
+            ser = o.sweeps(4000)
+        _within(ser[:, 0] / 12.0, ex)
+        _hist_within(ser[len(ser) // 10:, 0], P)
+
+
+def test_one_site_interacting_counterion():
+    """T-6: one acid site, interacting ions (Coulomb + excluded volume), dilute
+    salt; P(ionized) against the quadrature."""
+    pIX = cf.pIX_from_salt(6.0, 7.5)
+    ex = cf.one_site_ion_probability(24.0, 8.0, 0.5, 6.0, 7.5, 4.5, pIX, RHO)
+    ideal = cf.one_site_ion_probability(24.0, 0.0, 0.5, 6.0, 7.5, 4.5, pIX, RHO, eps=0.0)
+    o = oracle.Oracle(24.0, 4, 8.0, 0.5, 6.0, eps=1.0, seed=17)
+    o.set_conditions(7.5, 4.5, 5.0, pIX, pIX)
+    o.set_particles(np.array([[12.0, 12.0, 12.0]]), np.array([1]))
+    ser = o.paper_trials(1_200_000, 20)
+    m, se = _within(ser[:, 0].astype(float), ex)
+    assert abs(m - ideal) > 3 * se  # the interaction is visible at this precision
+
+
+@pytest.mark.parametrize("trials", [1, 3])
+def test_schedules_agree_with_interacting_ions(trials):
+    """T-8: the 40-site chain with full interactions; paper schedule and cell
+    schedule give the same <alpha> (no closed form exists here)."""
+    c = config1()
+    res = []
+    for mode in ("paper", "cell"):
+        o = oracle.Oracle(c["L"], 6, c["lB"], c["kappa"], c["rc"], eps=1.0, seed=31 + trials)
+        o.set_conditions(c["pH"], c["pKa"], c["pKb"], c["pIX"], c["pIX"])
+        o.set_particles(c["xyz"], c["kind"])
+        if mode == "paper":
+            ser = o.paper_trials(600_000, 50)
+        else:
+            o.set_schedule(trials)
+            ser = o.sweeps(6000 // trials)
+        x = ser[len(ser) // 10:, 0] / 40.0
+        res.append(mean_se(x)[:2])
+    (m1, s1), (m2, s2) = res
+    assert abs(m1 - m2) < 3.0 * np.hypot(s1, s2), res
+    # and it differs from the ideal value: interactions matter here
+    pIX = c["pIX"]
+    ideal = cf.ideal_alpha(40, 4.5, 4.5, pIX, pIX, 64000.0, RHO)
+    assert m1 < ideal - 0.05
+
+
+def test_partner_is_an_involution():
+    o = oracle.Oracle(40.0, 6, 0.0, 0.5, 6.0)
+    for M in (1, 8, 27, 343):
+        for sweep in range(5):
+            for colour in range(8):
+                p = [o.partner(sweep, colour, a, M) for a in range(M)]
+                assert all(p[p[a]] == a for a in range(M))
+                fixed = sum(p[a] == a for a in range(M))
+                assert fixed == (M % 2)
+
+
+def test_fixed_grid_negative_control_single_cells():
+    """T-12 with single-cell domains, the survey's original form of the scheme."""
+    o, ex = _ideal_40()
+    o.set_schedule(4, fixed_grid=True, pairing=False)
+    s = o.sweeps(6000)
+    m, se, _ = mean_se(s[600:, 0] / 40.0)
+    assert abs(m - ex) > 6 * se
