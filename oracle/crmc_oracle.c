@@ -253,6 +253,9 @@ static double core_energy(const orc_sys* S, const orc_state_pt* a)
         double dx = d[0] * s, dy = d[1] * s, dz = d[2] * s;
         double r = sqrt(dx * dx + dy * dy + dz * dz);
         double sh = r - S->core_delta[c];
+        /* the expanded potential is defined outside the core only (r > Delta);
+           closer than Delta + 1/2 (inside included) is an overlap */
+        if (sh < 0.5) return INFINITY;
         if (sh < 1.122462048309373) /* 2^(1/6) */
             e += wca(sh * sh, S->eps);
     }

@@ -311,3 +311,26 @@ def test_fixed_grid_negative_control_single_cells():
     s = o.sweeps(6000)
     m, se, _ = mean_se(s[600:, 0] / 40.0)
     assert abs(m - ex) > 6 * se
+
+
+@pytest.mark.parametrize("r_off", [0.0, 1.0, 2.9, 3.49])
+def test_ion_inside_or_touching_a_core_has_infinite_energy(r_off):
+    """Expanded excluded volume (Table II): for a core of radius R the
+    potential is defined for r > Delta = R - 1/2 and an ion closer than
+    Delta + 1/2 = R overlaps, wherever inside the core it sits."""
+    L = 24.0
+    o = oracle.Oracle(L, 4, 0.0, 0.5, 6.0, eps=1.0)
+    o.set_conditions(7.0, 4.5, 5.0, 1.0, 1.0)
+    o.set_particles(np.array([[12.0 + r_off, 12.0, 12.0]]), np.array([3]))
+    o.set_cores(np.array([[12.0, 12.0, 12.0]]), np.array([3.5]))
+    assert np.isinf(o.energy())
+
+
+def test_ion_just_outside_a_core_has_the_expanded_wca_energy():
+    L = 24.0
+    o = oracle.Oracle(L, 4, 0.0, 0.5, 6.0, eps=1.0)
+    o.set_conditions(7.0, 4.5, 5.0, 1.0, 1.0)
+    o.set_particles(np.array([[12.0 + 3.0 + 0.75, 12.0, 12.0]]), np.array([3]))
+    o.set_cores(np.array([[12.0, 12.0, 12.0]]), np.array([3.5]))
+    s = 0.75  # r - Delta, up to the fixed-point rounding of the position
+    assert o.energy() == pytest.approx(4 * (s ** -12 - s ** -6) + 1, rel=1e-6)
