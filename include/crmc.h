@@ -1,0 +1,219 @@
+/*
+ * crmc.h - C ABI of the MI355X charge-regulation Monte Carlo (CR-MC) library.
+ *
+ * The method is the one of Curk, Yuan and Luijten, "Accelerated simulation
+ * method for charge regulation effects": acid and base groups ionize by the
+ * grouped reactions A <-> A- + X+, B <-> B+ + X-, and salt pairs enter and
+ * leave by 0 <-> X+ + X- (Sec. II B).  Each trial is one of the six moves
+ * (forward/reverse of each reaction, equal probability), picks its
+ * participants uniformly, computes the energy change from the changed
+ * particles only and accepts with the Metropolis probabilities of Sec. II C,
+ * written with pH, pOH = pKw - pH, pK and the combined-ion chemical potentials
+ * pI_X+ / pI_X- in log10 units (eq. pIXgen gives pI_X from a salt pI_S).
+ *
+ * Parallel schedule.  Each sweep draws a random shift of a cubic cell grid
+ * (cell width >= cutoff, an even number >= 4 of cells per edge) and re-bins all
+ * particles into the shifted cells.  The cells are split into 8 parity classes
+ * (colours); cells of one colour never interact, so all of them are updated at
+ * once.  In the phase of a colour the active cells are paired by a random
+ * reflection of their index; a trial acts on such a pair ("domain"): it picks
+ * participants among the domain's particles and inserts ions uniformly in one
+ * of its two cells, with the paper's acceptance probability in which the volume
+ * is the insertion volume of the domain and every count is the domain's count.
+ * With pairing off a domain is a single cell.
+ *
+ * Energy model (units: length sigma, energy kT):
+ *   screened Coulomb lB q_i q_j exp(-kappa r)/r for r < rc (truncated),
+ *   excluded volume 4 eps (r^-12 - r^-6) + eps for r < 2^(1/6) between a free
+ *   ion and any other particle (Table I, eq. LJ with C = 1/4),
+ *   expanded excluded volume between a free ion and a nanoparticle core of
+ *   radius R with Delta = R - 1/2 (Table II, eq. LJe).
+ * A free ion closer than 1/2 to a particle (or than Delta + 1/2 to a core
+ * centre) is an overlap and is never accepted.  Positions are 32-bit fixed
+ * point per box edge; the Coulomb cutoff is decided exactly on the integer
+ * squared distance.
+ *
+ * Conventions.
+ *   - Every host array passed in is owned by the caller and copied before the
+ *     call returns; the library never frees caller memory.
+ *   - Device memory is allocated by the library (crmc_create / build) and freed
+ *     by crmc_destroy.
+ *   - Calls that launch work are asynchronous and ordered on the stream given
+ *     in crmc_params (NULL = the default stream).  crmc_observe,
+ *     crmc_get_series, crmc_get_particles, crmc_energy, crmc_read_log and
+ *     crmc_destroy synchronize.
+ *   - Errors: a negative status; crmc_last_error() describes the last one.
+ *     Device-side conditions (a cell running out of capacity) are reported as
+ *     CRMC_E_CAPACITY by the next synchronizing call; the state is then not
+ *     trustworthy.  No C++ exception crosses the ABI.  A handle is not
+ *     thread-safe.
+ */
+#ifndef CRMC_H
+#define CRMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CRMC_ABI_VERSION 1
+
+typedef struct crmc_s* crmc_t;
+
+enum crmc_status {
+    CRMC_OK = 0,
+    CRMC_E_ARG = -1,      /* invalid argument */
+    CRMC_E_NOMEM = -2,    /* device or host allocation failed */
+    CRMC_E_DEVICE = -3,   /* HIP runtime error */
+    CRMC_E_CAPACITY = -4, /* a cell exceeded its record capacity */
+    CRMC_E_STATE = -5     /* call out of order (e.g. sweep before build) */
+};
+
+/* particle kinds (sites keep their kind; their ionization is a separate flag) */
+enum crmc_kind {
+    CRMC_ACID = 1,    /* A (neutral) / A- (charged, q = -1) */
+    CRMC_BASE = 2,    /* B (neutral) / B+ (charged, q = +1) */
+    CRMC_XPOS = 3,    /* free monovalent cation X+ */
+    CRMC_XNEG = 4,    /* free monovalent anion X- */
+    CRMC_NEUTRAL = 5  /* non-ionizable bead (excluded volume for ions only) */
+};
+
+/* move ids used by statistics and trial logs */
+enum crmc_move {
+    CRMC_ACID_FWD = 0, CRMC_ACID_BACK = 1, CRMC_BASE_FWD = 2,
+    CRMC_BASE_BACK = 3, CRMC_SALT_IN = 4, CRMC_SALT_OUT = 5
+};
+
+typedef struct {
+    int32_t n_replicas;      /* independent systems advanced together (>= 1) */
+    int32_t precision;       /* 32: pair terms in FP32 (FP64 sums); 64: all FP64 */
+    int32_t trials_per_cell; /* trials per active cell per phase (>= 1) */
+    int32_t pairing;         /* 1: domains are reflection-paired cells; 0: single cells */
+    int32_t ion_coupling;    /* 1: ions interact; 0: ideal ions (test systems) */
+    int32_t lds_records;     /* neighbour records staged on chip per domain (0 = default) */
+    int32_t fixed_grid;      /* 1: never shift the grid (only for tests: not ergodic) */
+    int32_t reserved;
+    double lB;               /* Bjerrum length (sigma) */
+    double rc;               /* Coulomb cutoff (sigma) */
+    double eps_wca;          /* excluded-volume strength (kT); 0 disables it */
+    double rho0NA;           /* reference density rho0 NA in sigma^-3 (rho0 = 1 M) */
+    double pKw;              /* water: pOH = pKw - pH */
+    double kappa;            /* default inverse screening length (sigma^-1) */
+    double pKb;              /* default base pK used by crmc_sweep */
+    uint64_t seed;           /* Philox key: (seed low word, seed high word ^ replica) */
+    void* stream;            /* hipStream_t on which every call is ordered */
+} crmc_params;
+
+/* Per-replica reservoir conditions for crmc_sweep_ex. */
+typedef struct {
+    double pH, pKa, pKb;     /* pOH = pKw - pH */
+    double pIX_pos, pIX_neg; /* combined-ion chemical potentials (log10 units) */
+    double kappa;            /* inverse screening length of this replica */
+} crmc_cond;
+
+typedef struct {
+    int64_t sweeps;           /* sweeps done since build */
+    int64_t n_acid, n_acid_charged, n_base, n_base_charged, n_xpos, n_xneg;
+    double energy;            /* retained energy: start energy + accepted changes (kT) */
+    int64_t attempts[6];      /* trials per move id, auto-rejected ones included */
+    int64_t accepts[6];
+    uint32_t error_flags;     /* bit 0: cell capacity exceeded in binning;
+                                 bit 1: capacity exceeded by an insertion;
+                                 bit 2: (info) a domain's neighbours did not fit on
+                                 chip and were read from memory */
+    int32_t n_cells;          /* cells per box edge */
+    int32_t cell_capacity;
+    int32_t reserved;
+} crmc_obs;
+
+/* Trial log record (56 bytes), written when logging is enabled. */
+typedef struct {
+    int64_t sweep, cell;        /* cell: first cell of the domain (linear index) */
+    int32_t trial, replica;
+    int32_t move, status;       /* status: 0 rejected, 1 accepted, 2 no participant */
+    double dU, lnp, u;          /* dU in kT; lnp = log acceptance ratio; u uniform */
+} crmc_trial_rec;
+
+/* Create a handle.  No device work; returns CRMC_E_ARG for invalid params. */
+int crmc_create(const crmc_params* params, crmc_t* out);
+
+/*
+ * Define replica `replica`: box edge L (periodic cube), n particles with
+ * positions xyz (n*3 doubles, any real values; wrapped into the box), kind
+ * (crmc_kind), optional charged flags (NULL = all sites neutral; ions are
+ * always charged), optional group id per particle (NULL = 0) and n_cores
+ * nanoparticle cores (core_xyz n_cores*3, radius core_R).  n_cells = 0 picks
+ * the largest even count per edge whose cells are at least rc wide;
+ * cell_capacity = 0 sizes the per-cell record capacity from the site density.
+ * The initial order of particles is their stable binning into the unshifted
+ * grid.  Returns CRMC_E_ARG when L < 4 rc, when n_cells is odd, below 4 or
+ * gives cells narrower than rc, or when a cell already holds more than
+ * cell_capacity particles.
+ */
+int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32_t cell_capacity,
+                     int32_t n, const double* xyz, const int32_t* kind, const int32_t* charged,
+                     const int32_t* group, int32_t n_cores, const double* core_xyz,
+                     const double* core_R);
+
+/*
+ * Run n_sweeps sweeps on every replica with the same conditions: pH, acid
+ * pKa, combined-ion chemical potential mu_ion = pI_X+ = pI_X- (the input of
+ * App. B; use crmc_pIX_from_salt for a salt pI_S), base pK and kappa from
+ * crmc_params.  Asynchronous.
+ */
+int crmc_sweep(crmc_t h, double pH, double pKa, double mu_ion, int64_t n_sweeps);
+
+/* Same with per-replica conditions (array of n_replicas). */
+int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps);
+
+/* Counts, energy and move statistics of a replica (synchronizes). */
+int crmc_observe(crmc_t h, int32_t replica, crmc_obs* out);
+
+/*
+ * Per-sweep series [nA-, nB+, nX+, nX-] of a replica for sweeps
+ * first .. first+count-1 (counted from build), written to out (count*4).
+ * Sweeps beyond the retained window return CRMC_E_ARG.
+ */
+int crmc_get_series(crmc_t h, int32_t replica, int64_t first, int64_t count, int32_t* out);
+
+/*
+ * Current particles of a replica in the library's order (cell order, then
+ * order inside the cell): fixed-point positions xyz (cap*3), kind, charged,
+ * site id (input index of the site; -1 for free ions).  *n_out = number of
+ * particles; arrays are filled up to cap.
+ */
+int crmc_get_particles(crmc_t h, int32_t replica, int32_t cap, uint32_t* xyz, int32_t* kind,
+                       int32_t* charged, int32_t* site_id, int32_t* n_out);
+
+/* Total energy of the current state recomputed from scratch (kT). */
+int crmc_energy(crmc_t h, int32_t replica, double* out);
+
+/* Per-site count of sweeps at whose start the site was charged (n_sites values). */
+int crmc_get_occupancy(crmc_t h, int32_t replica, int64_t cap, uint64_t* out, int64_t* n_out);
+
+/* Histogram over sweeps of the number of ionized sites of each group g:
+   out[off[g] + k], k = 0..n_sites(g); offsets written to off (n_groups+1). */
+int crmc_get_group_hist(crmc_t h, int32_t replica, int64_t cap, int64_t* out, int32_t off_cap,
+                        int32_t* off, int32_t* n_groups);
+
+/* Trial logging (testing): keep up to `capacity` records on the device. */
+int crmc_enable_log(crmc_t h, int64_t capacity);
+int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out);
+
+/* Philox4x32-10 on the device: n counter blocks (ctr n*4 words) with key
+   (k0, k1) into out (n*4 words).  For checking the generator. */
+int crmc_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out);
+
+/* Combined-ion chemical potential from a symmetric salt (eq. pIXgen). */
+double crmc_pIX_from_salt(double pIS, double pH, double pKw);
+
+const char* crmc_last_error(crmc_t h);
+void crmc_destroy(crmc_t h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRMC_H */

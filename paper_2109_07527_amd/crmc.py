@@ -1,0 +1,334 @@
+"""ctypes binding of libcrmc.so (include/crmc.h): argument marshalling only.
+
+The functions carry the C names; ``System`` is a small convenience wrapper over
+them.  Every step of the Monte Carlo runs in the HIP library: if the library
+is missing or cannot be loaded this module raises, it never falls back.
+PyTorch (optional here) only supplies the HIP stream the calls are ordered on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrmc.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "crmc.h")
+
+CRMC_OK, CRMC_E_ARG, CRMC_E_NOMEM, CRMC_E_DEVICE, CRMC_E_CAPACITY, CRMC_E_STATE = 0, -1, -2, -3, -4, -5
+ACID, BASE, XPOS, XNEG, NEUTRAL = 1, 2, 3, 4, 5
+MOVES = ("acid_fwd", "acid_back", "base_fwd", "base_back", "salt_in", "salt_out")
+
+
+class CrmcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("crmc error %d: %s" % (code, msg))
+        self.code = code
+
+
+class crmc_params(C.Structure):
+    _fields_ = [("n_replicas", C.c_int32), ("precision", C.c_int32), ("trials_per_cell", C.c_int32),
+                ("pairing", C.c_int32), ("ion_coupling", C.c_int32), ("lds_records", C.c_int32),
+                ("fixed_grid", C.c_int32), ("reserved", C.c_int32),
+                ("lB", C.c_double), ("rc", C.c_double), ("eps_wca", C.c_double), ("rho0NA", C.c_double),
+                ("pKw", C.c_double), ("kappa", C.c_double), ("pKb", C.c_double),
+                ("seed", C.c_uint64), ("stream", C.c_void_p)]
+
+
+class crmc_cond(C.Structure):
+    _fields_ = [("pH", C.c_double), ("pKa", C.c_double), ("pKb", C.c_double),
+                ("pIX_pos", C.c_double), ("pIX_neg", C.c_double), ("kappa", C.c_double)]
+
+
+class crmc_obs(C.Structure):
+    _fields_ = [("sweeps", C.c_int64), ("n_acid", C.c_int64), ("n_acid_charged", C.c_int64),
+                ("n_base", C.c_int64), ("n_base_charged", C.c_int64), ("n_xpos", C.c_int64),
+                ("n_xneg", C.c_int64), ("energy", C.c_double), ("attempts", C.c_int64 * 6),
+                ("accepts", C.c_int64 * 6), ("error_flags", C.c_uint32), ("n_cells", C.c_int32),
+                ("cell_capacity", C.c_int32), ("reserved", C.c_int32)]
+
+
+class crmc_trial_rec(C.Structure):
+    _fields_ = [("sweep", C.c_int64), ("cell", C.c_int64), ("trial", C.c_int32), ("replica", C.c_int32),
+                ("move", C.c_int32), ("status", C.c_int32),
+                ("dU", C.c_double), ("lnp", C.c_double), ("u", C.c_double)]
+
+
+TRIAL_DTYPE = np.dtype([("sweep", "i8"), ("cell", "i8"), ("trial", "i4"), ("replica", "i4"), ("move", "i4"),
+                        ("status", "i4"), ("dU", "f8"), ("lnp", "f8"), ("u", "f8")])
+
+_lib = None
+
+
+def load():
+    """Load libcrmc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libcrmc.so is not built (run __graft_entry__.build() or "
+                           "python -m paper_2109_07527_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    P, vp, d, i32, i64, u32, u64 = C.POINTER, C.c_void_p, C.c_double, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
+    sig = {
+        "crmc_create": (C.c_int, [P(crmc_params), P(vp)]),
+        "crmc_build_cells": (C.c_int, [vp, i32, d, i32, i32, i32, P(d), P(i32), P(i32), P(i32), i32, P(d), P(d)]),
+        "crmc_sweep": (C.c_int, [vp, d, d, d, i64]),
+        "crmc_sweep_ex": (C.c_int, [vp, P(crmc_cond), i64]),
+        "crmc_observe": (C.c_int, [vp, i32, P(crmc_obs)]),
+        "crmc_get_series": (C.c_int, [vp, i32, i64, i64, P(i32)]),
+        "crmc_get_particles": (C.c_int, [vp, i32, i32, P(u32), P(i32), P(i32), P(i32), P(i32)]),
+        "crmc_energy": (C.c_int, [vp, i32, P(d)]),
+        "crmc_get_occupancy": (C.c_int, [vp, i32, i64, P(u64), P(i64)]),
+        "crmc_get_group_hist": (C.c_int, [vp, i32, i64, P(i64), i32, P(i32), P(i32)]),
+        "crmc_enable_log": (C.c_int, [vp, i64]),
+        "crmc_read_log": (C.c_int, [vp, i64, P(crmc_trial_rec), P(i64)]),
+        "crmc_philox": (C.c_int, [i64, P(u32), u32, u32, P(u32)]),
+        "crmc_pIX_from_salt": (d, [d, d, d]),
+        "crmc_last_error": (C.c_char_p, [vp]),
+        "crmc_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def header_symbols():
+    """Function names declared in include/crmc.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    decl = r"^\s*(?:int|void|double|const\s+char\s*\*)\s*(crmc_\w+)\s*\("
+    return sorted(set(re.findall(decl, text, flags=re.M)))
+
+
+def _p(a, ct):
+    return None if a is None else a.ctypes.data_as(C.POINTER(ct))
+
+
+def _check(h, rc):
+    if rc != CRMC_OK:
+        msg = load().crmc_last_error(h)
+        raise CrmcError(rc, msg.decode() if msg else "")
+    return rc
+
+
+# --------------------------------------------------------------------------
+# the C functions, same names
+# --------------------------------------------------------------------------
+def crmc_create(params: crmc_params):
+    h = C.c_void_p()
+    rc = load().crmc_create(C.byref(params), C.byref(h))
+    if rc != CRMC_OK:
+        raise CrmcError(rc, "crmc_create rejected the parameters")
+    return h
+
+
+def crmc_build_cells(h, replica, L, xyz, kind, charged=None, group=None, core_xyz=None, core_R=None,
+                     n_cells=0, cell_capacity=0):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    kind = np.ascontiguousarray(kind, dtype=np.int32)
+    n = kind.size
+    ch = None if charged is None else np.ascontiguousarray(charged, dtype=np.int32)
+    gr = None if group is None else np.ascontiguousarray(group, dtype=np.int32)
+    if core_xyz is None or len(core_R) == 0:
+        cx, cr, nc = None, None, 0
+    else:
+        cx = np.ascontiguousarray(core_xyz, dtype=np.float64).reshape(-1, 3)
+        cr = np.ascontiguousarray(core_R, dtype=np.float64)
+        nc = cr.size
+    return _check(h, load().crmc_build_cells(h, int(replica), float(L), int(n_cells), int(cell_capacity), n,
+                                             _p(xyz, C.c_double), _p(kind, C.c_int32), _p(ch, C.c_int32),
+                                             _p(gr, C.c_int32), nc, _p(cx, C.c_double), _p(cr, C.c_double)))
+
+
+def crmc_sweep(h, pH, pKa, mu_ion, n_sweeps):
+    return _check(h, load().crmc_sweep(h, float(pH), float(pKa), float(mu_ion), int(n_sweeps)))
+
+
+def crmc_sweep_ex(h, conds, n_sweeps):
+    arr = (crmc_cond * len(conds))()
+    for i, c in enumerate(conds):
+        arr[i] = crmc_cond(*[float(c[k]) for k in ("pH", "pKa", "pKb", "pIX_pos", "pIX_neg", "kappa")])
+    return _check(h, load().crmc_sweep_ex(h, arr, int(n_sweeps)))
+
+
+def crmc_observe(h, replica):
+    o = crmc_obs()
+    rc = load().crmc_observe(h, int(replica), C.byref(o))
+    out = {k: getattr(o, k) for k, _ in crmc_obs._fields_ if k not in ("attempts", "accepts", "reserved")}
+    out["attempts"] = list(o.attempts)
+    out["accepts"] = list(o.accepts)
+    out["status"] = rc
+    return out
+
+
+def crmc_get_series(h, replica, first, count):
+    out = np.zeros((int(count), 4), dtype=np.int32)
+    _check(h, load().crmc_get_series(h, int(replica), int(first), int(count), _p(out, C.c_int32)))
+    return out
+
+
+def crmc_get_particles(h, replica, cap=None):
+    n = C.c_int32(0)
+    if cap is None:
+        _check(h, load().crmc_get_particles(h, int(replica), 0, None, None, None, None, C.byref(n)))
+        cap = n.value
+    X = np.zeros((max(cap, 1), 3), dtype=np.uint32)
+    k = np.zeros(max(cap, 1), dtype=np.int32)
+    c = np.zeros(max(cap, 1), dtype=np.int32)
+    s = np.zeros(max(cap, 1), dtype=np.int32)
+    _check(h, load().crmc_get_particles(h, int(replica), int(cap), _p(X, C.c_uint32), _p(k, C.c_int32),
+                                        _p(c, C.c_int32), _p(s, C.c_int32), C.byref(n)))
+    m = min(n.value, cap)
+    return X[:m], k[:m], c[:m], s[:m]
+
+
+def crmc_energy(h, replica):
+    e = C.c_double(0.0)
+    _check(h, load().crmc_energy(h, int(replica), C.byref(e)))
+    return e.value
+
+
+def crmc_get_occupancy(h, replica):
+    n = C.c_int64(0)
+    _check(h, load().crmc_get_occupancy(h, int(replica), 0, None, C.byref(n)))
+    out = np.zeros(max(n.value, 1), dtype=np.uint64)
+    _check(h, load().crmc_get_occupancy(h, int(replica), n.value, _p(out, C.c_uint64), C.byref(n)))
+    return out[:n.value]
+
+
+def crmc_get_group_hist(h, replica):
+    ng = C.c_int32(0)
+    _check(h, load().crmc_get_group_hist(h, int(replica), 0, None, 0, None, C.byref(ng)))
+    off = np.zeros(ng.value + 1, dtype=np.int32)
+    _check(h, load().crmc_get_group_hist(h, int(replica), 0, None, ng.value + 1, _p(off, C.c_int32), C.byref(ng)))
+    out = np.zeros(max(int(off[-1]), 1), dtype=np.int64)
+    _check(h, load().crmc_get_group_hist(h, int(replica), int(off[-1]), _p(out, C.c_int64), ng.value + 1,
+                                         _p(off, C.c_int32), C.byref(ng)))
+    return [out[off[g]:off[g + 1]] for g in range(ng.value)]
+
+
+def crmc_enable_log(h, capacity):
+    return _check(h, load().crmc_enable_log(h, int(capacity)))
+
+
+def crmc_read_log(h, cap):
+    n = C.c_int64(0)
+    buf = np.zeros(max(int(cap), 1), dtype=TRIAL_DTYPE)
+    _check(h, load().crmc_read_log(h, int(cap), buf.ctypes.data_as(C.POINTER(crmc_trial_rec)), C.byref(n)))
+    return buf[:min(n.value, int(cap))], n.value
+
+
+def crmc_philox(ctr, k0, k1):
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    out = np.zeros_like(ctr)
+    rc = load().crmc_philox(ctr.shape[0], _p(ctr, C.c_uint32), int(k0), int(k1), _p(out, C.c_uint32))
+    if rc != CRMC_OK:
+        raise CrmcError(rc, "crmc_philox failed")
+    return out
+
+
+def crmc_pIX_from_salt(pIS, pH, pKw=14.0):
+    return load().crmc_pIX_from_salt(float(pIS), float(pH), float(pKw))
+
+
+def crmc_destroy(h):
+    load().crmc_destroy(h)
+
+
+def current_stream():
+    """The current torch HIP stream handle (None when torch has no GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+# --------------------------------------------------------------------------
+# convenience wrapper
+# --------------------------------------------------------------------------
+class System:
+    """A batch of CR-MC replicas on the GPU (one handle of the C library)."""
+
+    def __init__(self, n_replicas=1, lB=2.0, rc=6.0, eps=1.0, rho0NA=0.0269424, pKw=14.0, kappa=0.5,
+                 pKb=5.0, seed=1234, precision=32, trials_per_cell=1, pairing=True, ion_coupling=True,
+                 lds_records=0, fixed_grid=False, stream="torch"):
+        p = crmc_params()
+        p.n_replicas = int(n_replicas)
+        p.precision = int(precision)
+        p.trials_per_cell = int(trials_per_cell)
+        p.pairing = int(bool(pairing))
+        p.ion_coupling = int(bool(ion_coupling))
+        p.lds_records = int(lds_records)
+        p.fixed_grid = int(bool(fixed_grid))
+        p.lB, p.rc, p.eps_wca, p.rho0NA, p.pKw, p.kappa, p.pKb = lB, rc, eps, rho0NA, pKw, kappa, pKb
+        p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        s = current_stream() if stream == "torch" else stream
+        p.stream = s.value if isinstance(s, C.c_void_p) else s
+        self.params = p
+        self.n_replicas = int(n_replicas)
+        self.pKw, self.kappa, self.pKb = pKw, kappa, pKb
+        self.h = crmc_create(p)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            crmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_cells(self, replica, system=None, **kw):
+        if system is not None:
+            kw.setdefault("L", system["L"])
+            kw.setdefault("xyz", system["xyz"])
+            kw.setdefault("kind", system["kind"])
+            kw.setdefault("group", system.get("group"))
+            if len(system.get("core_R", [])):
+                kw.setdefault("core_xyz", system["core_xyz"])
+                kw.setdefault("core_R", system["core_R"])
+        return crmc_build_cells(self.h, replica, **kw)
+
+    def sweep(self, pH, pKa, mu_ion, n_sweeps):
+        return crmc_sweep(self.h, pH, pKa, mu_ion, n_sweeps)
+
+    def sweep_ex(self, conds, n_sweeps):
+        return crmc_sweep_ex(self.h, conds, n_sweeps)
+
+    def observe(self, replica=0):
+        return crmc_observe(self.h, replica)
+
+    def series(self, replica, first, count):
+        return crmc_get_series(self.h, replica, first, count)
+
+    def particles(self, replica=0):
+        return crmc_get_particles(self.h, replica)
+
+    def energy(self, replica=0):
+        return crmc_energy(self.h, replica)
+
+    def occupancy(self, replica=0):
+        return crmc_get_occupancy(self.h, replica)
+
+    def group_hist(self, replica=0):
+        return crmc_get_group_hist(self.h, replica)
+
+    def enable_log(self, capacity):
+        return crmc_enable_log(self.h, capacity)
+
+    def read_log(self, cap=None):
+        if cap is None:
+            _, n = crmc_read_log(self.h, 0)
+            cap = n
+        return crmc_read_log(self.h, cap)[0]

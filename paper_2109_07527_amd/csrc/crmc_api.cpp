@@ -1,0 +1,671 @@
+// Host side of the CR-MC library: the C ABI declared in include/crmc.h.
+//
+// Holds per-replica geometry, converts positions to the fixed-point lattice,
+// performs the initial stable binning into the unshifted grid, allocates the
+// device buffers, turns reservoir conditions into the log acceptance
+// constants of Sec. II C (FP64) and enqueues the sweep kernels.
+#include "crmc.h"
+#include "crmc_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace crmc;
+
+namespace {
+
+constexpr double TWO32 = 4294967296.0;
+constexpr double LN10 = 2.302585092994045684017991454684364208;
+constexpr int DEFAULT_POOL = 3072;          // LDS pool per domain (records, 48 KB)
+constexpr int64_t DEFAULT_SERIES = 16384;   // retained sweeps of the series
+
+struct HostReplica {
+    bool built = false;
+    double L = 0.0;
+    uint32_t n = 0, cap = 0, ncells = 0, ncores = 0, nsites = 0, ngroups = 0;
+    int64_t nA = 0, nB = 0;
+    double E0 = 0.0;          // energy at the last restart of the running sum
+    double e0_kappa = 0.0;    // screening length E0 was computed with (NaN: not yet)
+    std::vector<int32_t> hist_off;
+    crmc_cond cond{};
+    Replica d{}; // device pointers and constants (host copy of the descriptor)
+};
+
+} // namespace
+
+struct crmc_s {
+    crmc_params p{};
+    std::vector<HostReplica> reps;
+    Replica* d_reps = nullptr;
+    uint64_t* d_sweep = nullptr;
+    uint32_t* d_err = nullptr;
+    TrialRec* d_log = nullptr;
+    unsigned long long* d_log_n = nullptr;
+    int64_t log_cap = 0;
+    int64_t sweeps = 0;
+    int pool = DEFAULT_POOL;
+    bool lds_attr_set = false;
+    hipStream_t stream = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int fail(crmc_t h, int code, const std::string& msg)
+{
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIP_TRY(h, expr)                                                                    \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((h), e_ == hipErrorOutOfMemory ? CRMC_E_NOMEM : CRMC_E_DEVICE,      \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+uint64_t cutoff_R2(double rc, double L)
+{
+    const double t = (rc / L) * TWO32;
+    return (uint64_t)std::ceil(t * t);
+}
+
+uint32_t to_fixed(double x, double L)
+{
+    double f = x / L;
+    f -= std::floor(f);
+    double v = std::floor(f * TWO32);
+    if (v >= TWO32) v = 0.0;
+    return (uint32_t)v;
+}
+
+uint64_t cell_lo_h(uint32_t k, uint32_t n) { return (((uint64_t)k << 32) + n - 1u) / n; }
+uint32_t cell_of_h(uint32_t y, uint32_t n) { return (uint32_t)(((uint64_t)y * n) >> 32); }
+
+// cells two apart never interact: a full cell lies between them
+bool grid_ok(uint32_t n, uint64_t R2)
+{
+    if (n < 4 || (n & 1u)) return false;
+    const uint64_t wmin = (uint64_t)(TWO32 / n); // floor(2^32 / n)
+    const uint64_t sep = wmin + 1u;
+    return sep * sep >= R2;
+}
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count)
+{
+    return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+void free_replica(HostReplica& r)
+{
+    Replica& d = r.d;
+    void* ptrs[] = {d.rec[0], d.rec[1], d.cnt[0], d.cnt[1], d.e_acc, d.occupancy, d.site_group,
+                    d.group_ionized, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
+                    d.moves, d.series};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    d = Replica{};
+    r.built = false;
+}
+
+void set_conditions(crmc_t h, HostReplica& r, const crmc_cond& c)
+{
+    r.cond = c;
+    const double pOH = h->p.pKw - c.pH;
+    r.d.lnKA = (c.pH - c.pKa - c.pIX_pos) * LN10;
+    r.d.lnKB = (pOH - c.pKb - c.pIX_neg) * LN10;
+    r.d.lnKion = -(c.pIX_pos + c.pIX_neg) * LN10;
+    r.d.kappa = c.kappa;
+}
+
+SweepArgs base_args(crmc_t h)
+{
+    SweepArgs a{};
+    a.reps = h->d_reps;
+    a.nrep = (uint32_t)h->reps.size();
+    uint32_t cells = 0, doms = 0;
+    for (auto& r : h->reps) {
+        cells += r.ncells;
+        const uint32_t M = r.d.h * r.d.h * r.d.h;
+        doms += h->p.pairing ? (M + 1u) / 2u : M;
+    }
+    a.ncell_total = cells;
+    a.ndom_total = doms;
+    a.sweep = h->d_sweep;
+    a.err = h->d_err;
+    a.log = h->d_log;
+    a.log_n = h->d_log_n;
+    a.log_cap = (uint64_t)h->log_cap;
+    a.lB = h->p.lB;
+    a.eps = h->p.eps_wca;
+    a.ion_coupling = h->p.ion_coupling;
+    a.trials = h->p.trials_per_cell;
+    a.pairing = h->p.pairing;
+    a.fixed_grid = h->p.fixed_grid;
+    a.budget = h->pool;
+    a.precision = h->p.precision;
+    return a;
+}
+
+int upload_descriptors(crmc_t h)
+{
+    std::vector<Replica> v(h->reps.size());
+    uint32_t cells = 0, doms = 0;
+    for (size_t i = 0; i < h->reps.size(); ++i) {
+        HostReplica& r = h->reps[i];
+        r.d.cell_begin = cells;
+        r.d.dom_begin = doms;
+        cells += r.ncells;
+        const uint32_t M = r.d.h * r.d.h * r.d.h;
+        doms += h->p.pairing ? (M + 1u) / 2u : M;
+        v[i] = r.d;
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(h->d_reps, v.data(), v.size() * sizeof(Replica), hipMemcpyHostToDevice));
+    return CRMC_OK;
+}
+
+int check_device_errors(crmc_t h)
+{
+    uint32_t e = 0;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(&e, h->d_err, sizeof e, hipMemcpyDeviceToHost));
+    if (e & (ERR_BIN_CAPACITY | ERR_INSERT_CAPACITY))
+        return fail(h, CRMC_E_CAPACITY, "a cell exceeded its record capacity (flags " + std::to_string(e) +
+                                            "); rebuild with a larger cell_capacity");
+    return CRMC_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+double crmc_pIX_from_salt(double pIS, double pH, double pKw)
+{
+    const double pOH = pKw - pH;
+    return -std::log10(std::pow(10.0, -pIS) + std::pow(10.0, -std::min(pH, pOH)));
+}
+
+const char* crmc_last_error(crmc_t h) { return h ? h->err.c_str() : "null handle"; }
+
+int crmc_create(const crmc_params* p, crmc_t* out)
+{
+    if (!p || !out) return CRMC_E_ARG;
+    *out = nullptr;
+    if (p->n_replicas < 1 || p->n_replicas > (1 << 20)) return CRMC_E_ARG;
+    if (p->precision != 32 && p->precision != 64) return CRMC_E_ARG;
+    if (p->trials_per_cell < 1 || p->trials_per_cell > (1 << 20)) return CRMC_E_ARG;
+    if (!(p->rc > 0.0) || !(p->lB >= 0.0) || !(p->eps_wca >= 0.0) || !(p->rho0NA > 0.0)) return CRMC_E_ARG;
+    if (p->lds_records < 0) return CRMC_E_ARG;
+    crmc_t h = new (std::nothrow) crmc_s;
+    if (!h) return CRMC_E_NOMEM;
+    h->p = *p;
+    h->reps.resize((size_t)p->n_replicas);
+    h->stream = (hipStream_t)p->stream;
+    h->pool = p->lds_records > 0 ? p->lds_records : DEFAULT_POOL;
+    crmc_cond c{};
+    c.pH = 7.0; c.pKa = 4.5; c.pKb = p->pKb; c.pIX_pos = c.pIX_neg = 1.0; c.kappa = p->kappa;
+    for (auto& r : h->reps) r.cond = c;
+    if (hipMalloc((void**)&h->d_sweep, sizeof(uint64_t)) != hipSuccess ||
+        hipMalloc((void**)&h->d_err, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void**)&h->d_reps, sizeof(Replica) * h->reps.size()) != hipSuccess) {
+        crmc_destroy(h);
+        return CRMC_E_DEVICE;
+    }
+    (void)hipMemset(h->d_sweep, 0, sizeof(uint64_t));
+    (void)hipMemset(h->d_err, 0, sizeof(uint32_t));
+    *out = h;
+    return CRMC_OK;
+}
+
+int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32_t cell_capacity, int32_t n,
+                     const double* xyz, const int32_t* kind, const int32_t* charged, const int32_t* group,
+                     int32_t n_cores, const double* core_xyz, const double* core_R)
+{
+    if (!h) return CRMC_E_ARG;
+    if (replica < 0 || replica >= (int32_t)h->reps.size()) return fail(h, CRMC_E_ARG, "replica out of range");
+    if (h->sweeps != 0) return fail(h, CRMC_E_STATE, "replicas must be built before the first sweep");
+    if (!(L > 0.0) || n < 0 || (n > 0 && (!xyz || !kind)) || n_cores < 0 || (n_cores > 0 && (!core_xyz || !core_R)))
+        return fail(h, CRMC_E_ARG, "invalid geometry arguments");
+    if (n >= (int32_t)NO_SITE) return fail(h, CRMC_E_ARG, "too many particles in one replica");
+    if (L < 4.0 * h->p.rc) return fail(h, CRMC_E_ARG, "box edge must be at least 4 rc");
+    const uint64_t R2 = cutoff_R2(h->p.rc, L);
+    uint32_t nc;
+    if (n_cells == 0) {
+        nc = (uint32_t)std::floor(L / h->p.rc);
+        if (nc & 1u) --nc;
+        while (nc >= 4 && !grid_ok(nc, R2)) nc -= 2;
+        if (nc < 4) return fail(h, CRMC_E_ARG, "no valid cell grid");
+    } else {
+        if (n_cells < 4 || (n_cells & 1) || !grid_ok((uint32_t)n_cells, R2))
+            return fail(h, CRMC_E_ARG, "n_cells must be even, >= 4 and give cells at least rc wide");
+        nc = (uint32_t)n_cells;
+    }
+    if ((uint64_t)nc * nc * nc > (1ull << 31)) return fail(h, CRMC_E_ARG, "too many cells");
+    for (int32_t i = 0; i < n; ++i) {
+        const int k = kind[i];
+        if (k < CRMC_ACID || k > CRMC_NEUTRAL) return fail(h, CRMC_E_ARG, "invalid particle kind");
+        if (charged && (charged[i] != 0 && charged[i] != 1)) return fail(h, CRMC_E_ARG, "charged must be 0/1");
+    }
+    for (int32_t i = 0; i < n_cores; ++i)
+        if (!(core_R[i] >= 0.5)) return fail(h, CRMC_E_ARG, "core radius must be >= 1/2");
+
+    HostReplica& r = h->reps[(size_t)replica];
+    if (r.built) free_replica(r);
+    const uint32_t ncells = nc * nc * nc;
+
+    // records in input order, then the stable binning into the unshifted grid
+    std::vector<uint4> in((size_t)n);
+    std::vector<std::vector<uint32_t>> lists(ncells);
+    std::vector<uint32_t> site_cnt(ncells, 0);
+    int64_t tot[4] = {0, 0, 0, 0};
+    r.nA = r.nB = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const uint32_t x = to_fixed(xyz[3 * i], L), y = to_fixed(xyz[3 * i + 1], L), z = to_fixed(xyz[3 * i + 2], L);
+        const uint32_t k = (uint32_t)kind[i];
+        const bool ion = k == KIND_XPOS || k == KIND_XNEG;
+        const uint32_t ch = ion ? 1u : (charged ? (uint32_t)charged[i] : 0u);
+        in[(size_t)i] = make_uint4(x, y, z, make_meta(k, ch, ion ? NO_SITE : (uint32_t)i));
+        const uint32_t c = cell_of_h(x, nc) + nc * (cell_of_h(y, nc) + nc * cell_of_h(z, nc));
+        lists[c].push_back((uint32_t)i);
+        if (!ion) site_cnt[c]++;
+        if (k == KIND_ACID) { r.nA++; tot[0] += ch; }
+        if (k == KIND_BASE) { r.nB++; tot[1] += ch; }
+        if (k == KIND_XPOS) tot[2]++;
+        if (k == KIND_XNEG) tot[3]++;
+    }
+    uint32_t maxc = 0, maxblock = 0;
+    for (uint32_t c = 0; c < ncells; ++c) maxc = std::max<uint32_t>(maxc, (uint32_t)lists[c].size());
+    for (uint32_t z = 0; z < nc; ++z)
+        for (uint32_t y = 0; y < nc; ++y)
+            for (uint32_t x = 0; x < nc; ++x) {
+                uint32_t s = 0;
+                for (int o = 0; o < 8; ++o)
+                    s += site_cnt[((x + (o & 1)) % nc) + nc * (((y + ((o >> 1) & 1)) % nc) + nc * ((z + (o >> 2)) % nc))];
+                maxblock = std::max(maxblock, s);
+            }
+    uint32_t cap;
+    if (cell_capacity == 0) {
+        cap = std::max<uint32_t>(64u, 2u * maxblock + 96u);
+        cap = std::max<uint32_t>(cap, maxc + 32u);
+        cap = (cap + 31u) & ~31u;
+    } else {
+        if (cell_capacity < 1 || (uint32_t)cell_capacity < maxc)
+            return fail(h, CRMC_E_ARG, "cell_capacity below the particles already in one cell");
+        cap = (uint32_t)cell_capacity;
+    }
+
+    // groups: dense indices in ascending order of the caller's ids
+    std::map<int32_t, int32_t> gid;
+    for (int32_t i = 0; i < n; ++i) {
+        const uint32_t k = (uint32_t)kind[i];
+        if (k == KIND_XPOS || k == KIND_XNEG) continue;
+        gid.emplace(group ? group[i] : 0, 0);
+    }
+    int32_t gi = 0;
+    for (auto& kv : gid) kv.second = gi++;
+    const uint32_t ngroups = (uint32_t)gid.size();
+    std::vector<int32_t> site_group((size_t)std::max(n, 1), 0);
+    std::vector<int32_t> gsize(ngroups, 0), gion(ngroups, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        const uint32_t k = (uint32_t)kind[i];
+        if (k == KIND_XPOS || k == KIND_XNEG) continue;
+        const int32_t g = gid[group ? group[i] : 0];
+        site_group[(size_t)i] = g;
+        gsize[(size_t)g]++;
+        if (charged && charged[i]) gion[(size_t)g]++;
+    }
+    r.hist_off.assign(ngroups + 1, 0);
+    for (uint32_t g = 0; g < ngroups; ++g) r.hist_off[g + 1] = r.hist_off[g] + gsize[g] + 1;
+
+    std::vector<uint4> cells((size_t)ncells * cap);
+    std::vector<uint32_t> counts(ncells);
+    for (uint32_t c = 0; c < ncells; ++c) {
+        counts[c] = (uint32_t)lists[c].size();
+        for (size_t j = 0; j < lists[c].size(); ++j) cells[(size_t)c * cap + j] = in[lists[c][j]];
+    }
+    std::vector<uint4> cores((size_t)std::max(n_cores, 1));
+    std::vector<double> deltas((size_t)std::max(n_cores, 1));
+    for (int32_t i = 0; i < n_cores; ++i) {
+        cores[(size_t)i] = make_uint4(to_fixed(core_xyz[3 * i], L), to_fixed(core_xyz[3 * i + 1], L),
+                                      to_fixed(core_xyz[3 * i + 2], L), 0u);
+        deltas[(size_t)i] = core_R[i] - 0.5;
+    }
+
+    Replica& d = r.d;
+    d = Replica{};
+    const size_t nrec = (size_t)ncells * cap;
+    const int64_t series_cap = DEFAULT_SERIES;
+    HIP_TRY(h, dalloc(&d.rec[0], nrec));
+    HIP_TRY(h, dalloc(&d.rec[1], nrec));
+    HIP_TRY(h, dalloc(&d.cnt[0], ncells));
+    HIP_TRY(h, dalloc(&d.cnt[1], ncells));
+    HIP_TRY(h, dalloc(&d.e_acc, ncells));
+    HIP_TRY(h, dalloc(&d.occupancy, (size_t)std::max(n, 1)));
+    HIP_TRY(h, dalloc(&d.site_group, (size_t)std::max(n, 1)));
+    HIP_TRY(h, dalloc(&d.group_ionized, std::max<uint32_t>(ngroups, 1)));
+    HIP_TRY(h, dalloc(&d.group_hist, (size_t)std::max(r.hist_off[ngroups], 1)));
+    HIP_TRY(h, dalloc(&d.group_hist_off, ngroups + 1));
+    HIP_TRY(h, dalloc(&d.core_x, cores.size()));
+    HIP_TRY(h, dalloc(&d.core_delta, deltas.size()));
+    HIP_TRY(h, dalloc(&d.totals, 4));
+    HIP_TRY(h, dalloc(&d.moves, 12));
+    HIP_TRY(h, dalloc(&d.series, (size_t)series_cap * 4));
+    HIP_TRY(h, hipMemcpy(d.rec[0], cells.data(), nrec * sizeof(uint4), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d.cnt[0], counts.data(), ncells * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d.cnt[1], 0, ncells * sizeof(uint32_t)));
+    HIP_TRY(h, hipMemset(d.e_acc, 0, ncells * sizeof(double)));
+    HIP_TRY(h, hipMemset(d.occupancy, 0, (size_t)std::max(n, 1) * sizeof(uint64_t)));
+    HIP_TRY(h, hipMemcpy(d.site_group, site_group.data(), site_group.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (ngroups) HIP_TRY(h, hipMemcpy(d.group_ionized, gion.data(), ngroups * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d.group_hist, 0, (size_t)std::max(r.hist_off[ngroups], 1) * sizeof(int64_t)));
+    HIP_TRY(h, hipMemcpy(d.group_hist_off, r.hist_off.data(), (ngroups + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d.core_x, cores.data(), cores.size() * sizeof(uint4), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d.core_delta, deltas.data(), deltas.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d.totals, tot, sizeof tot, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d.moves, 0, 12 * sizeof(uint64_t)));
+    HIP_TRY(h, hipMemset(d.series, 0, (size_t)series_cap * 4 * sizeof(int32_t)));
+    d.series_cap = series_cap;
+    d.n = nc;
+    d.h = nc / 2u;
+    d.ncells = ncells;
+    d.cap = cap;
+    d.ncores = (uint32_t)n_cores;
+    d.nsites = (uint32_t)n;
+    d.ngroups = ngroups;
+    d.key0 = (uint32_t)h->p.seed;
+    d.key1 = (uint32_t)(h->p.seed >> 32) ^ (uint32_t)replica;
+    d.L = L;
+    d.scale = L / TWO32;
+    d.lnZ0 = std::log(h->p.rho0NA) + 3.0 * std::log(L / TWO32);
+    d.R2 = R2;
+    r.L = L;
+    r.n = nc;
+    r.cap = cap;
+    r.ncells = ncells;
+    r.ncores = (uint32_t)n_cores;
+    r.nsites = (uint32_t)n;
+    r.ngroups = ngroups;
+    set_conditions(h, r, r.cond);
+    r.built = true;
+
+    // the retained energy starts from scratch at the first sweep, once the
+    // replica's screening length is known
+    r.e0_kappa = std::nan("");
+    return CRMC_OK;
+}
+
+static int state_energy(crmc_t h, HostReplica& r, double* out)
+{
+    Replica* d_one = nullptr;
+    double* d_e = nullptr;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMalloc((void**)&d_one, sizeof(Replica)));
+    HIP_TRY(h, dalloc(&d_e, r.ncells));
+    HIP_TRY(h, hipMemcpy(d_one, &r.d, sizeof(Replica), hipMemcpyHostToDevice));
+    HIP_TRY(h, launch_energy(d_one, r.d, h->p.lB, h->p.eps_wca, h->p.ion_coupling, (int)(h->sweeps & 1), d_e,
+                             h->stream));
+    std::vector<double> pe(r.ncells);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(pe.data(), d_e, r.ncells * sizeof(double), hipMemcpyDeviceToHost));
+    (void)hipFree(d_one);
+    (void)hipFree(d_e);
+    double E = 0.0;
+    for (double v : pe) E += v;
+    *out = E;
+    return CRMC_OK;
+}
+
+int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
+{
+    if (!h || !per_replica || n_sweeps < 0) return fail(h, CRMC_E_ARG, "invalid sweep arguments");
+    uint32_t maxcap = 0;
+    for (auto& r : h->reps) {
+        if (!r.built) return fail(h, CRMC_E_STATE, "every replica must be built before sweeping");
+        maxcap = std::max(maxcap, r.cap);
+    }
+    if ((uint64_t)h->sweeps + (uint64_t)n_sweeps >= (1ull << 32))
+        return fail(h, CRMC_E_ARG, "sweep counter would exceed 2^32");
+    for (size_t i = 0; i < h->reps.size(); ++i) {
+        const crmc_cond& c = per_replica[i];
+        if (!std::isfinite(c.pH) || !std::isfinite(c.pKa) || !std::isfinite(c.pKb) || !std::isfinite(c.pIX_pos) ||
+            !std::isfinite(c.pIX_neg) || !(c.kappa >= 0.0))
+            return fail(h, CRMC_E_ARG, "invalid conditions");
+        set_conditions(h, h->reps[i], c);
+    }
+    // The energy function depends on kappa: where it changed (or before the
+    // first sweep) the retained energy restarts from a from-scratch sum.
+    for (auto& r : h->reps) {
+        if (r.e0_kappa == r.d.kappa) continue;
+        double E = 0.0;
+        int rc = state_energy(h, r, &E);
+        if (rc) return rc;
+        HIP_TRY(h, hipMemset(r.d.e_acc, 0, r.ncells * sizeof(double)));
+        r.E0 = E;
+        r.e0_kappa = r.d.kappa;
+    }
+    // the LDS pool must hold both cells of a domain
+    if (h->pool < (int)(2 * maxcap + 64)) h->pool = (int)(2 * maxcap + 64);
+    const size_t lds = phase_lds_bytes(maxcap, h->pool);
+    int dev = 0, maxlds = 0;
+    HIP_TRY(h, hipGetDevice(&dev));
+    HIP_TRY(h, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    if (lds + 1024 > (size_t)maxlds)
+        return fail(h, CRMC_E_ARG, "cell capacity too large for on-chip staging (" + std::to_string(lds) +
+                                        " bytes of LDS needed)");
+    if (!h->lds_attr_set) {
+        HIP_TRY(h, set_phase_lds_limit(lds));
+        h->lds_attr_set = true;
+    }
+    int rc = upload_descriptors(h);
+    if (rc) return rc;
+    SweepArgs a = base_args(h);
+    for (int64_t i = 0; i < n_sweeps; ++i) {
+        HIP_TRY(h, launch_bin(a, h->stream));
+        for (int col = 0; col < 8; ++col) {
+            a.colour = col;
+            HIP_TRY(h, launch_phase(a, lds, h->stream));
+        }
+        HIP_TRY(h, launch_sweep_end(a, 0, h->stream));
+        h->sweeps++;
+    }
+    return CRMC_OK;
+}
+
+int crmc_sweep(crmc_t h, double pH, double pKa, double mu_ion, int64_t n_sweeps)
+{
+    if (!h) return CRMC_E_ARG;
+    std::vector<crmc_cond> c(h->reps.size());
+    for (auto& x : c) {
+        x.pH = pH; x.pKa = pKa; x.pKb = h->p.pKb; x.pIX_pos = mu_ion; x.pIX_neg = mu_ion; x.kappa = h->p.kappa;
+    }
+    return crmc_sweep_ex(h, c.data(), n_sweeps);
+}
+
+int crmc_observe(crmc_t h, int32_t replica, crmc_obs* out)
+{
+    if (!h || !out || replica < 0 || replica >= (int32_t)h->reps.size()) return fail(h, CRMC_E_ARG, "bad arguments");
+    HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    std::memset(out, 0, sizeof *out);
+    int64_t tot[4];
+    uint64_t mv[12];
+    std::vector<double> e(r.ncells);
+    uint32_t err = 0;
+    HIP_TRY(h, hipMemcpy(tot, r.d.totals, sizeof tot, hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(mv, r.d.moves, sizeof mv, hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(e.data(), r.d.e_acc, r.ncells * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(&err, h->d_err, sizeof err, hipMemcpyDeviceToHost));
+    double E = r.E0;
+    for (double v : e) E += v;
+    out->sweeps = h->sweeps;
+    out->n_acid = r.nA;
+    out->n_acid_charged = tot[0];
+    out->n_base = r.nB;
+    out->n_base_charged = tot[1];
+    out->n_xpos = tot[2];
+    out->n_xneg = tot[3];
+    out->energy = E;
+    for (int i = 0; i < 6; ++i) {
+        out->attempts[i] = (int64_t)mv[i];
+        out->accepts[i] = (int64_t)mv[6 + i];
+    }
+    out->error_flags = err;
+    out->n_cells = (int32_t)r.n;
+    out->cell_capacity = (int32_t)r.cap;
+    if (err & (ERR_BIN_CAPACITY | ERR_INSERT_CAPACITY))
+        return fail(h, CRMC_E_CAPACITY, "a cell exceeded its record capacity; rebuild with a larger cell_capacity");
+    return CRMC_OK;
+}
+
+int crmc_get_series(crmc_t h, int32_t replica, int64_t first, int64_t count, int32_t* out)
+{
+    if (!h || replica < 0 || replica >= (int32_t)h->reps.size() || count < 0 || (count && !out))
+        return fail(h, CRMC_E_ARG, "bad arguments");
+    HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    const int64_t capn = r.d.series_cap;
+    if (first < 0 || first + count > h->sweeps || first < h->sweeps - capn)
+        return fail(h, CRMC_E_ARG, "requested sweeps outside the retained window");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    std::vector<int32_t> all((size_t)capn * 4);
+    HIP_TRY(h, hipMemcpy(all.data(), r.d.series, all.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t row = (first + i) % capn;
+        std::memcpy(out + 4 * i, &all[(size_t)row * 4], 4 * sizeof(int32_t));
+    }
+    return CRMC_OK;
+}
+
+int crmc_get_particles(crmc_t h, int32_t replica, int32_t cap, uint32_t* xyz, int32_t* kind, int32_t* charged,
+                       int32_t* site_id, int32_t* n_out)
+{
+    if (!h || replica < 0 || replica >= (int32_t)h->reps.size() || cap < 0 || !n_out)
+        return fail(h, CRMC_E_ARG, "bad arguments");
+    HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const int buf = (int)(h->sweeps & 1);
+    std::vector<uint32_t> cnt(r.ncells);
+    std::vector<uint4> rec((size_t)r.ncells * r.cap);
+    HIP_TRY(h, hipMemcpy(cnt.data(), r.d.cnt[buf], r.ncells * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIP_TRY(h, hipMemcpy(rec.data(), r.d.rec[buf], rec.size() * sizeof(uint4), hipMemcpyDeviceToHost));
+    int32_t k = 0;
+    for (uint32_t c = 0; c < r.ncells; ++c)
+        for (uint32_t j = 0; j < cnt[c]; ++j, ++k) {
+            if (k >= cap) continue;
+            const uint4 v = rec[(size_t)c * r.cap + j];
+            if (xyz) { xyz[3 * k] = v.x; xyz[3 * k + 1] = v.y; xyz[3 * k + 2] = v.z; }
+            const uint32_t sid = v.w >> 8;
+            if (kind) kind[k] = (int32_t)(v.w & 7u);
+            if (charged) charged[k] = (int32_t)((v.w >> 3) & 1u);
+            if (site_id) site_id[k] = sid == NO_SITE ? -1 : (int32_t)sid;
+        }
+    *n_out = k;
+    return check_device_errors(h);
+}
+
+int crmc_energy(crmc_t h, int32_t replica, double* out)
+{
+    if (!h || !out || replica < 0 || replica >= (int32_t)h->reps.size()) return fail(h, CRMC_E_ARG, "bad arguments");
+    HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    return state_energy(h, r, out);
+}
+
+int crmc_get_occupancy(crmc_t h, int32_t replica, int64_t cap, uint64_t* out, int64_t* n_out)
+{
+    if (!h || !n_out || replica < 0 || replica >= (int32_t)h->reps.size() || cap < 0)
+        return fail(h, CRMC_E_ARG, "bad arguments");
+    HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    *n_out = r.nsites;
+    const int64_t m = std::min<int64_t>(cap, r.nsites);
+    if (m > 0) HIP_TRY(h, hipMemcpy(out, r.d.occupancy, (size_t)m * sizeof(uint64_t), hipMemcpyDeviceToHost));
+    return CRMC_OK;
+}
+
+int crmc_get_group_hist(crmc_t h, int32_t replica, int64_t cap, int64_t* out, int32_t off_cap, int32_t* off,
+                        int32_t* n_groups)
+{
+    if (!h || !n_groups || replica < 0 || replica >= (int32_t)h->reps.size() || cap < 0 || off_cap < 0)
+        return fail(h, CRMC_E_ARG, "bad arguments");
+    HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    *n_groups = (int32_t)r.ngroups;
+    for (int32_t i = 0; i < std::min<int32_t>(off_cap, (int32_t)r.ngroups + 1); ++i) off[i] = r.hist_off[(size_t)i];
+    const int64_t m = std::min<int64_t>(cap, r.hist_off[r.ngroups]);
+    if (m > 0) HIP_TRY(h, hipMemcpy(out, r.d.group_hist, (size_t)m * sizeof(int64_t), hipMemcpyDeviceToHost));
+    return CRMC_OK;
+}
+
+int crmc_enable_log(crmc_t h, int64_t capacity)
+{
+    if (!h || capacity < 0) return fail(h, CRMC_E_ARG, "bad arguments");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (h->d_log) { (void)hipFree(h->d_log); h->d_log = nullptr; }
+    if (!h->d_log_n) HIP_TRY(h, hipMalloc((void**)&h->d_log_n, sizeof(unsigned long long)));
+    HIP_TRY(h, hipMemset(h->d_log_n, 0, sizeof(unsigned long long)));
+    h->log_cap = capacity;
+    if (capacity > 0) HIP_TRY(h, hipMalloc((void**)&h->d_log, (size_t)capacity * sizeof(TrialRec)));
+    return CRMC_OK;
+}
+
+int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out)
+{
+    static_assert(sizeof(crmc_trial_rec) == sizeof(TrialRec), "trial record layout");
+    if (!h || !n_out || cap < 0) return fail(h, CRMC_E_ARG, "bad arguments");
+    *n_out = 0;
+    if (!h->d_log) return CRMC_OK;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    unsigned long long n = 0;
+    HIP_TRY(h, hipMemcpy(&n, h->d_log_n, sizeof n, hipMemcpyDeviceToHost));
+    const int64_t m = std::min<int64_t>({(int64_t)n, h->log_cap, cap});
+    if (m > 0) HIP_TRY(h, hipMemcpy(out, h->d_log, (size_t)m * sizeof(TrialRec), hipMemcpyDeviceToHost));
+    *n_out = (int64_t)n;
+    return CRMC_OK;
+}
+
+int crmc_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out)
+{
+    if (n < 0 || (n > 0 && (!ctr || !out))) return CRMC_E_ARG;
+    if (n == 0) return CRMC_OK;
+    uint32_t *dc = nullptr, *dout = nullptr;
+    if (hipMalloc((void**)&dc, (size_t)n * 16) != hipSuccess) return CRMC_E_NOMEM;
+    if (hipMalloc((void**)&dout, (size_t)n * 16) != hipSuccess) { (void)hipFree(dc); return CRMC_E_NOMEM; }
+    int rc = CRMC_OK;
+    if (hipMemcpy(dc, ctr, (size_t)n * 16, hipMemcpyHostToDevice) != hipSuccess ||
+        launch_philox(n, dc, k0, k1, dout, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = CRMC_E_DEVICE;
+    (void)hipFree(dc);
+    (void)hipFree(dout);
+    return rc;
+}
+
+void crmc_destroy(crmc_t h)
+{
+    if (!h) return;
+    if (h->stream || true) (void)hipStreamSynchronize(h->stream);
+    for (auto& r : h->reps)
+        if (r.built) free_replica(r);
+    if (h->d_reps) (void)hipFree(h->d_reps);
+    if (h->d_sweep) (void)hipFree(h->d_sweep);
+    if (h->d_err) (void)hipFree(h->d_err);
+    if (h->d_log) (void)hipFree(h->d_log);
+    if (h->d_log_n) (void)hipFree(h->d_log_n);
+    delete h;
+}
+
+} // extern "C"

@@ -1,0 +1,89 @@
+// Internal definitions shared by the host library and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crmc {
+
+constexpr uint32_t KIND_ACID = 1, KIND_BASE = 2, KIND_XPOS = 3, KIND_XNEG = 4, KIND_NEUTRAL = 5;
+constexpr uint32_t TAG_TRIAL = 1, TAG_SHIFT = 2, TAG_PAIR = 4;
+constexpr uint32_t NO_SITE = 0xFFFFFFu;
+
+constexpr uint32_t ERR_BIN_CAPACITY = 1u;
+constexpr uint32_t ERR_INSERT_CAPACITY = 2u;
+constexpr uint32_t INFO_UNSTAGED = 4u;
+
+constexpr int PHASE_THREADS = 256; // four wavefronts per domain
+constexpr int BIN_THREADS = 64;    // one wavefront per cell
+
+// Record: three fixed-point coordinates and a meta word
+//   bits 0-2 kind, bit 3 charged flag, bits 8-31 site id (NO_SITE for ions)
+__host__ __device__ inline uint32_t make_meta(uint32_t kind, uint32_t charged, uint32_t sid)
+{
+    return kind | (charged << 3) | (sid << 8);
+}
+
+// One replica as the kernels see it.
+struct Replica {
+    uint4* rec[2];           // ping-pong record buffers, ncells*cap records each
+    uint32_t* cnt[2];        // records per cell
+    double* e_acc;           // per cell: accumulated energy change of accepted trials
+    uint64_t* occupancy;     // per site: sweeps at whose start it was charged
+    int32_t* site_group;     // per site: group index
+    int32_t* group_ionized;  // per group: ionized sites now
+    int64_t* group_hist;     // per group histogram of ionized-site counts
+    int32_t* group_hist_off; // ngroups+1 offsets into group_hist
+    uint4* core_x;           // core centres (x, y, z, unused)
+    double* core_delta;      // Delta = R - 1/2
+    int64_t* totals;         // nA-, nB+, nX+, nX-
+    uint64_t* moves;         // attempts[6], accepts[6]
+    int32_t* series;         // series_cap rows of 4
+    int64_t series_cap;
+    uint32_t n, h, ncells, cap;
+    uint32_t ncores, nsites, ngroups;
+    uint32_t key0, key1;
+    uint32_t cell_begin;     // prefix of cells over replicas (binning grid)
+    uint32_t dom_begin;      // prefix of domains per phase over replicas
+    uint32_t pad0;
+    double L, scale, lnZ0;   // scale = L / 2^32; lnZ0 = ln(rho0 NA) + 3 ln(scale)
+    uint64_t R2;             // Coulomb cutoff on the integer squared distance
+    double lnKA, lnKB, lnKion, kappa;
+};
+
+struct TrialRec {
+    int64_t sweep, cell;
+    int32_t trial, replica;
+    int32_t move, status;
+    double dU, lnp, u;
+};
+
+struct SweepArgs {
+    Replica* reps;
+    uint32_t nrep;
+    uint32_t ncell_total;
+    uint32_t ndom_total;
+    int32_t colour;
+    uint64_t* sweep;   // device sweep counter (all replicas advance together)
+    uint32_t* err;     // device error flags
+    TrialRec* log;
+    unsigned long long* log_n;
+    uint64_t log_cap;
+    double lB, eps;
+    int32_t ion_coupling, trials, pairing, fixed_grid;
+    int32_t budget;    // neighbour records staged on chip per domain
+    int32_t precision; // 32 or 64
+};
+
+// launchers (device translation unit)
+hipError_t launch_bin(const SweepArgs& a, hipStream_t s);
+hipError_t launch_phase(const SweepArgs& a, size_t lds_bytes, hipStream_t s);
+hipError_t launch_sweep_end(const SweepArgs& a, int64_t series_first, hipStream_t s);
+hipError_t launch_energy(const Replica* rep_dev, const Replica& rep_host, double lB, double eps,
+                         int ion_coupling, int buf, double* out_per_cell, hipStream_t s);
+hipError_t launch_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
+                         hipStream_t s);
+size_t phase_lds_bytes(uint32_t max_cap, int budget);
+hipError_t set_phase_lds_limit(size_t bytes);
+
+} // namespace crmc

@@ -1,0 +1,52 @@
+"""The C ABI without a GPU: the library loads, exports what the header
+declares, and its pure host functions and argument checks behave."""
+import ctypes as C
+import os
+
+import pytest
+
+from paper_2109_07527_amd import crmc
+
+pytestmark = pytest.mark.skipif(not os.path.exists(crmc.LIB_PATH), reason="libcrmc.so not built")
+
+
+def test_every_declared_symbol_is_exported():
+    L = crmc.load()
+    names = crmc.header_symbols()
+    assert "crmc_create" in names and "crmc_sweep" in names and "crmc_observe" in names
+    assert "crmc_build_cells" in names
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_pIX_from_salt_matches_closed_form():
+    from oracle import closed_forms as cf
+    for pIS, pH in [(1.0, 7.0), (2.0, 4.5), (6.0, 7.5), (3.0, 11.0), (-1.0, 2.0)]:
+        assert crmc.crmc_pIX_from_salt(pIS, pH) == pytest.approx(cf.pIX_from_salt(pIS, pH), abs=1e-13)
+
+
+def _params(**kw):
+    p = crmc.crmc_params()
+    p.n_replicas, p.precision, p.trials_per_cell, p.pairing, p.ion_coupling = 1, 32, 1, 1, 1
+    p.lB, p.rc, p.eps_wca, p.rho0NA, p.pKw, p.kappa, p.pKb = 2.0, 6.0, 1.0, 0.0269424, 14.0, 0.5, 5.0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("bad", [dict(precision=16), dict(trials_per_cell=0), dict(rc=0.0),
+                                 dict(n_replicas=0), dict(rho0NA=-1.0), dict(lds_records=-5),
+                                 dict(lB=-1.0)])
+def test_create_rejects_invalid_parameters(bad):
+    L = crmc.load()
+    h = C.c_void_p()
+    rc = L.crmc_create(C.byref(_params(**bad)), C.byref(h))
+    assert rc == crmc.CRMC_E_ARG
+    assert not h.value
+
+
+def test_null_arguments():
+    L = crmc.load()
+    assert L.crmc_create(None, None) == crmc.CRMC_E_ARG
+    assert L.crmc_sweep(None, 7.0, 4.5, 1.0, 1) == crmc.CRMC_E_ARG
+    L.crmc_destroy(None)

@@ -1,0 +1,264 @@
+"""GPU path against the oracle (needs an MI355X).
+
+FP64 runs must reproduce the oracle's cell schedule bit for bit: same final
+particles in the same order, same per-sweep series, same move statistics.
+FP32 runs must give the same decisions except within 1e-4 of the acceptance
+threshold, and every energy change within 1e-5 * max(|dU|, 1 kT).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import closed_forms as cf
+from workloads import config1, config2, nanoparticle_pair, random_sites, ring
+
+pytestmark = pytest.mark.gpu
+
+RHO = 0.0269424
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_07527_amd import crmc
+    return crmc
+
+
+def _cond(pH, pKa, pKb, pIXp, pIXm, kappa):
+    return dict(pH=pH, pKa=pKa, pKb=pKb, pIX_pos=pIXp, pIX_neg=pIXm, kappa=kappa)
+
+
+def _mixed(seed=3, L=24.0, with_core=True, charged=False):
+    s = random_sites(12, 10, L, seed, min_dist=1.0)
+    if with_core:
+        s["core_xyz"] = np.array([[L / 2, L / 2, L / 2]])
+        s["core_R"] = np.array([3.0])
+    if charged:
+        s["charged"] = (np.arange(22) % 3 == 0).astype(np.int32)
+    return s
+
+
+CASES = {
+    # name: (system factory, model, condition)
+    "mixed": (lambda: _mixed(), dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=1),
+              _cond(6.0, 5.0, 5.0, 0.5, 0.7, 0.5)),
+    "mixed_charged_start": (lambda: _mixed(charged=True), dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=1),
+                            _cond(5.0, 5.5, 6.0, 1.2, 0.9, 0.7)),
+    "chain40": (lambda: config1(), dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=1),
+                _cond(4.5, 4.5, 5.0, cf.pIX_from_salt(2.0, 4.5), cf.pIX_from_salt(2.0, 4.5), 0.5)),
+    "ring_ideal_ions": (lambda: ring(12, L=24.0), dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=0),
+                        _cond(4.5, 4.5, 5.0, 1.0, 1.0, 0.5)),
+    "np_pair_small": (lambda: nanoparticle_pair(seed=4, L=40.0, R=4.0, sites=120, separation=11.0),
+                      dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=1), _cond(7.0, 5.0, 5.0, 0.8, 0.8, 0.5)),
+    "salt_only": (lambda: dict(L=24.0, xyz=np.zeros((0, 3)), kind=np.zeros(0, np.int32),
+                               group=np.zeros(0, np.int32), core_xyz=np.zeros((0, 3)), core_R=np.zeros(0)),
+                  dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=1), _cond(7.0, 4.5, 5.0, 0.3, 0.3, 0.5)),
+}
+
+
+def _oracle_for(s, model, cond, n_cells, trials, pairing, seed, replica=0, fixed_grid=False):
+    o = oracle.Oracle(s["L"], n_cells, model["lB"], cond["kappa"], model["rc"], eps=model["eps"],
+                      ion_coupling=model["ion_coupling"], seed=seed, replica=replica)
+    o.set_conditions(cond["pH"], cond["pKa"], cond["pKb"], cond["pIX_pos"], cond["pIX_neg"])
+    o.set_particles(s["xyz"], s["kind"], charged=s.get("charged"))
+    if len(s.get("core_R", [])):
+        o.set_cores(s["core_xyz"], s["core_R"])
+    o.set_schedule(trials, fixed_grid=fixed_grid, pairing=pairing)
+    return o
+
+
+def _gpu_system(crmc, s, model, n_rep, precision, trials, pairing, seed, lds_records=0, fixed_grid=False):
+    S = crmc.System(n_replicas=n_rep, lB=model["lB"], rc=model["rc"], eps=model["eps"],
+                    ion_coupling=model["ion_coupling"], precision=precision, trials_per_cell=trials,
+                    pairing=pairing, seed=seed, lds_records=lds_records, fixed_grid=fixed_grid)
+    for r in range(n_rep):
+        kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"], charged=s.get("charged"), group=s.get("group"))
+        if len(s.get("core_R", [])):
+            kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
+        S.build_cells(r, **kw)
+    return S
+
+
+def _same_state(gpu_particles, orc_particles):
+    for a, b, name in zip(gpu_particles, orc_particles, ("xyz", "kind", "charged", "site_id")):
+        a = np.asarray(a)
+        b = np.asarray(b)
+        assert a.shape == b.shape, (name, a.shape, b.shape)
+        assert np.array_equal(a.astype(np.int64), b.astype(np.int64)), name
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("trials,pairing", [(1, True), (2, True), (1, False)])
+def test_fp64_bit_exact(case, trials, pairing):
+    crmc = _gpu()
+    make, model, cond = CASES[case]
+    s = make()
+    nsw = 12
+    S = _gpu_system(crmc, s, model, 1, 64, trials, pairing, seed=77)
+    S.sweep_ex([cond], nsw)
+    obs = S.observe(0)
+    assert obs["status"] == 0 and obs["error_flags"] & 3 == 0
+    o = _oracle_for(s, model, cond, obs["n_cells"], trials, pairing, seed=77)
+    ser = o.sweeps(nsw)
+    _same_state(S.particles(0), o.particles())
+    assert np.array_equal(S.series(0, 0, nsw), ser)
+    att, acc = o.move_stats()
+    assert list(att) == obs["attempts"] and list(acc) == obs["accepts"]
+    assert obs["energy"] == pytest.approx(o.running_energy(), rel=1e-9, abs=1e-9)
+    assert S.energy(0) == pytest.approx(o.energy(), rel=1e-9, abs=1e-9)
+    assert sum(obs["accepts"]) > 0
+
+
+def _compare_logs(glog, olog, ftol=1e-5):
+    """Walk the oracle's trials in processing order; the GPU must agree until
+    the first decision within 1e-4 of threshold, which may differ."""
+    key = {(int(r["sweep"]), int(r["cell"]), int(r["trial"])): r for r in glog}
+    assert len(key) == len(glog)
+    n_checked = 0
+    for r in olog:
+        g = key[(int(r["sweep"]), int(r["cell"]), int(r["trial"]))]
+        assert g["move"] == r["move"]
+        if r["status"] == 2:
+            assert g["status"] == 2
+            continue
+        ro, rg = r["dU"], g["dU"]
+        if np.isfinite(ro) and ro < 1e3:
+            assert abs(rg - ro) <= ftol * max(abs(ro), 1.0), (r, g)
+        else:
+            assert not np.isfinite(rg) or rg > 1e3
+        if g["status"] != r["status"]:
+            p = math.exp(min(0.0, r["lnp"]))
+            assert abs(r["u"] - p) < 1e-4, (r, g)
+            return n_checked, True
+        n_checked += 1
+    return n_checked, False
+
+
+@pytest.mark.parametrize("case", ["mixed", "chain40", "np_pair_small"])
+def test_fp32_decisions_and_dU(case):
+    crmc = _gpu()
+    make, model, cond = CASES[case]
+    s = make()
+    nsw = 10
+    S = _gpu_system(crmc, s, model, 1, 32, 2, True, seed=5)
+    S.enable_log(2_000_000)
+    S.sweep_ex([cond], nsw)
+    obs = S.observe(0)
+    o = _oracle_for(s, model, cond, obs["n_cells"], 2, True, seed=5)
+    o.enable_log(2_000_000)
+    o.sweeps(nsw)
+    n, diverged = _compare_logs(S.read_log(), o.log())
+    assert n > 1000
+    if not diverged:
+        _same_state(S.particles(0), o.particles())
+
+
+def test_unstaged_neighbours_bit_exact():
+    """A tiny on-chip pool forces every domain to read its neighbours from
+    memory; results must not change."""
+    crmc = _gpu()
+    _, model, _ = CASES["mixed"]
+    s = _mixed()
+    cond = _cond(6.0, 5.0, 5.0, -0.8, -0.8, 0.5)  # dense salt: neighbourhoods outgrow the pool
+    S = crmc.System(n_replicas=1, lB=2.0, rc=6.0, eps=1.0, precision=64, trials_per_cell=2, seed=9,
+                    lds_records=1)
+    S.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"],
+                  cell_capacity=256)
+    S.sweep_ex([cond], 8)
+    obs = S.observe(0)
+    assert obs["error_flags"] & 4  # the slow path was taken
+    o = _oracle_for(s, model, cond, obs["n_cells"], 2, True, seed=9)
+    o.sweeps(8)
+    _same_state(S.particles(0), o.particles())
+
+
+def test_replica_batch_with_different_conditions():
+    """Several replicas of different size and conditions in one launch; each
+    matches its own oracle."""
+    crmc = _gpu()
+    systems = [_mixed(seed=3), _mixed(seed=4, L=32.0), config1(), _mixed(seed=5, with_core=False)]
+    conds = [_cond(6.0, 5.0, 5.0, 0.5, 0.7, 0.5), _cond(4.0, 4.5, 6.0, 1.0, 1.0, 0.3),
+             _cond(4.5, 4.5, 5.0, 2.0, 2.0, 0.9), _cond(8.0, 5.0, 4.0, 0.2, 0.4, 0.6)]
+    model = dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=1)
+    S = crmc.System(n_replicas=4, lB=2.0, rc=6.0, eps=1.0, precision=64, trials_per_cell=1, seed=123)
+    for r, s in enumerate(systems):
+        kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"])
+        if len(s.get("core_R", [])):
+            kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
+        S.build_cells(r, **kw)
+    S.sweep_ex(conds, 10)
+    for r, s in enumerate(systems):
+        obs = S.observe(r)
+        o = _oracle_for(s, model, conds[r], obs["n_cells"], 1, True, seed=123, replica=r)
+        ser = o.sweeps(10)
+        _same_state(S.particles(r), o.particles())
+        assert np.array_equal(S.series(r, 0, 10), ser)
+
+
+def test_philox_words_match_oracle():
+    crmc = _gpu()
+    rng = np.random.default_rng(5)
+    ctr = rng.integers(0, 2 ** 32, (1000, 4), dtype=np.uint64).astype(np.uint32)
+    k0, k1 = 0x12345678, 0x9ABCDEF0
+    g = crmc.crmc_philox(ctr, k0, k1)
+    for i in range(0, 1000, 37):
+        assert list(g[i]) == list(oracle.philox(ctr[i], [k0, k1]))
+
+
+def test_capacity_overflow_is_reported():
+    """Far more salt than a tiny per-cell capacity allows: the library must
+    refuse the extra insertions and report the condition, not corrupt memory."""
+    crmc = _gpu()
+    s = CASES["salt_only"][0]()
+    S = crmc.System(n_replicas=1, lB=2.0, rc=6.0, eps=1.0, precision=32, trials_per_cell=4, seed=1)
+    S.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], cell_capacity=4)
+    S.sweep(7.0, 4.5, -1.5, 5)
+    obs = S.observe(0)
+    assert obs["status"] == crmc.CRMC_E_CAPACITY
+    assert obs["error_flags"] & 2
+
+
+def test_running_energy_tracks_recomputed_energy_fp32():
+    crmc = _gpu()
+    make, model, cond = CASES["np_pair_small"]
+    s = make()
+    S = _gpu_system(crmc, s, model, 1, 32, 2, True, seed=21)
+    S.sweep_ex([cond], 30)
+    obs = S.observe(0)
+    e = S.energy(0)
+    assert obs["energy"] == pytest.approx(e, rel=1e-5, abs=1e-3)
+    o = _oracle_for(s, model, cond, obs["n_cells"], 2, True, seed=21)
+    # the oracle's brute-force energy of the GPU's state (computed on the CPU)
+    X, kind, charged, sid = S.particles(0)
+    chk = oracle.Oracle(s["L"], obs["n_cells"], model["lB"], cond["kappa"], model["rc"], eps=1.0)
+    chk.set_particles(X, kind, charged=charged, sid=sid, fixed=True)
+    chk.set_cores(s["core_xyz"], s["core_R"])
+    assert e == pytest.approx(chk.energy(), rel=1e-9, abs=1e-9)
+    del o
+
+
+def test_config2_full_size_sampled_replicas():
+    """The benchmark workload (two nanoparticles, 4000 sites, L = 120, nine
+    pH replicas, FP32) for a few sweeps; replicas 0 and 4 against the oracle."""
+    crmc = _gpu()
+    c = config2()
+    model = dict(lB=c["lB"], rc=c["rc"], eps=1.0, ion_coupling=1)
+    conds = [_cond(pH, c["pKa"], c["pKb"], c["pIX"], c["pIX"], c["kappa"]) for pH in c["pH_list"]]
+    S = crmc.System(n_replicas=9, lB=c["lB"], rc=c["rc"], eps=1.0, precision=32, trials_per_cell=1, seed=2024)
+    for r in range(9):
+        S.build_cells(r, c)
+    S.enable_log(4_000_000)
+    nsw = 2
+    S.sweep_ex(conds, nsw)
+    glog = S.read_log()
+    for r in (0, 4):
+        obs = S.observe(r)
+        assert obs["status"] == 0
+        o = _oracle_for(c, model, conds[r], obs["n_cells"], 1, True, seed=2024, replica=r)
+        o.enable_log(2_000_000)
+        o.sweeps(nsw)
+        n, _ = _compare_logs(glog[glog["replica"] == r], o.log())
+        assert n > 1000
