@@ -1,0 +1,201 @@
+#!/usr/bin/env python
+"""Benchmark of the CR-MC hot path on one MI355X.
+
+Workload (default): two oppositely charged nanoparticles (radius 10, 2000
+acid sites with pKa 5 on one, 2000 base sites with pKb 5 on the other,
+centres 25 apart) in a periodic box L = 120 with about 2x10^4 free ions
+(pI_X = 0.668), lB = 2, kappa = 0.5, rc = 8, scanned over pH 3..11 as nine
+replicas advanced together; FP32 pair terms, FP64 sums and acceptance.
+
+A step is one sweep of every replica: re-binning into the shifted cell grid
+plus the eight colour phases (every cell gets `trials` trials) plus the
+end-of-sweep bookkeeping.  The timed region holds exactly --steps sweeps
+after --warmup untimed ones, bracketed by device synchronisation.
+
+Printed (one JSON line): trial moves/s (value), effectively independent
+samples/s from the integrated autocorrelation time of the number of ionized
+sites per replica, the roofline of the phase kernel measured with HIP events
+around its launches, and the oracle's own rate on a bounded sample on the
+host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CR-MC trial moves/s and indep. samples/s at matched <alpha>; % HBM roofline"
+HBM_PEAK_GBS = 8000.0
+PHASE_SOURCES = ["paper_2109_07527_amd/csrc/crmc_kernels.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_traffic_config2.json")
+
+
+def phase_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in PHASE_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stencil_bytes_per_sweep(n_records: float, n_cells: int) -> float:
+    """Algorithmic bytes the phase kernels move per sweep with the 27-cell
+    neighbourhood method: every record is read once as a member of its own
+    cell, 26 times as a neighbour and written back once (16 B each); every
+    cell count is read 27 times and written once (4 B)."""
+    return n_records * 16.0 * 28.0 + n_cells * 4.0 * 28.0
+
+
+def cpu_baseline(system, cond, trials, site_trials, seconds):
+    """The oracle as it stands (plain FP64 C, one core) on the same system at
+    one pH, started from the same neutral state; rate over the sweeps of the
+    last half of the sample."""
+    import oracle
+    o = oracle.Oracle(system["L"], system["n_cells"], system["lB"], cond["kappa"], system["rc"],
+                      eps=1.0, seed=2024, replica=4)
+    o.set_conditions(cond["pH"], cond["pKa"], cond["pKb"], cond["pIX_pos"], cond["pIX_neg"])
+    o.set_particles(system["xyz"], system["kind"])
+    o.set_cores(system["core_xyz"], system["core_R"])
+    o.set_schedule(trials, pairing=True, site_trials=site_trials)
+    t_start = time.perf_counter()
+    marks = []
+    while True:
+        a0 = int(sum(o.move_stats()[0]))
+        t0 = time.perf_counter()
+        o.sweeps(1, series=False)
+        t1 = time.perf_counter()
+        marks.append((t1 - t0, int(sum(o.move_stats()[0])) - a0))
+        if t1 - t_start > seconds:
+            break
+    tail = marks[len(marks) // 2:]
+    dt = sum(m[0] for m in tail)
+    n = sum(m[1] for m in tail)
+    c = o.counts()
+    return {"value": n / dt, "unit": "trial moves/s", "cores": 1, "kind": "oracle",
+            "sample": "one replica (pH %.0f) of the same system from the neutral start, %d sweeps in %.0f s; "
+                      "rate over the last %d sweeps (%d free ions at the end)"
+                      % (cond["pH"], len(marks), time.perf_counter() - t_start, len(tail), c["nXp"] + c["nXm"])}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--trials", type=int, default=2, help="trials per cell per sweep")
+    ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
+    ap.add_argument("--site-trials", type=int, default=0, help="extra trials per 16 sites of a domain")
+    ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per domain in records (0 = default)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the CR-MC replicas of this workload fit one MI355X "
+              "and no multi-GPU path is built (requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world),
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2109_07527_amd import crmc
+    from paper_2109_07527_amd.stats import tau_int
+    from workloads import config2
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    c = config2()
+    conds = [dict(pH=pH, pKa=c["pKa"], pKb=c["pKb"], pIX_pos=c["pIX"], pIX_neg=c["pIX"], kappa=c["kappa"])
+             for pH in c["pH_list"]]
+    R = len(conds)
+    S = crmc.System(n_replicas=R, lB=c["lB"], rc=c["rc"], eps=1.0, precision=args.precision,
+                    trials_per_cell=args.trials, pairing=True, seed=2024, site_trials=args.site_trials,
+                    lds_records=args.lds_records)
+    for r in range(R):
+        S.build_cells(r, c)
+    S.sweep_ex(conds, args.warmup)
+    torch.cuda.synchronize()
+    before = [S.observe(r) for r in range(R)]
+    crmc.crmc_set_timing(S.h, True)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.sweep_ex(conds, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    ms, launches = crmc.crmc_get_timing(S.h)
+    after = [S.observe(r) for r in range(R)]
+    for o in after:
+        if o["status"] != 0:
+            raise SystemExit("device error: %s" % o)
+    elapsed = t1 - t0
+    trials = sum(sum(a["attempts"]) - sum(b["attempts"]) for a, b in zip(after, before))
+    rate = trials / elapsed
+
+    # independent samples: per replica, tau_int (in sweeps) of the ionized-site count
+    taus, alphaA, alphaB, samples = [], [], [], 0.0
+    sweeps_per_s = args.steps / elapsed
+    for r in range(R):
+        ser = S.series(r, args.warmup, args.steps).astype(np.float64)
+        q = ser[:, 0] + ser[:, 1]
+        t = tau_int(q)
+        taus.append(round(t, 2))
+        samples += sweeps_per_s / (2.0 * t)
+        alphaA.append(round(float(ser[:, 0].mean()) / after[r]["n_acid"], 5))
+        alphaB.append(round(float(ser[:, 1].mean()) / after[r]["n_base"], 5))
+
+    # roofline of the phase kernel
+    n_rec = [0.5 * (a["n_acid"] + a["n_base"] + a["n_xpos"] + a["n_xneg"]
+                    + b["n_acid"] + b["n_base"] + b["n_xpos"] + b["n_xneg"]) for a, b in zip(after, before)]
+    cells = [a["n_cells"] ** 3 for a in after]
+    bytes_sweep = sum(stencil_bytes_per_sweep(n, k) for n, k in zip(n_rec, cells))
+    bytes_launch = bytes_sweep / 8.0
+    phase_avg_ms = ms[1] / max(launches[1], 1)
+    achieved = bytes_launch / (phase_avg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == phase_source_hash():
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_phase", "bytes_per_launch": round(bytes_launch),
+                "avg_launch_ms": round(phase_avg_ms, 5)}
+
+    line = {
+        "metric": METRIC, "value": round(rate, 1), "unit": "trial moves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
+        "config": {"workload": "nanoparticle pair: 2000 acid + 2000 base sites, R=10, separation 25, "
+                               "L=120, ~2e4 ions (pI_X=0.668), lB=2, kappa=0.5, rc=8; 9 replicas pH 3..11",
+                   "replicas": R, "trials_per_cell": args.trials, "site_trials_per_16": args.site_trials,
+                   "schedule": "shifted cells, paired domains",
+                   "cells_per_edge": after[0]["n_cells"], "cell_capacity": after[0]["cell_capacity"]},
+        "independent_samples_per_s": round(samples, 1),
+        "tau_int_sweeps": taus, "alpha_acid": alphaA, "alpha_base": alphaB,
+        "kernel_ms": {"bin": round(ms[0] / max(launches[0], 1), 5), "phase": round(phase_avg_ms, 5),
+                      "sweep_end": round(ms[2] / max(launches[2], 1), 5)},
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        sysd = dict(c)
+        sysd["n_cells"] = after[0]["n_cells"]
+        line["cpu_baseline"] = cpu_baseline(sysd, conds[4], args.trials, args.site_trials, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

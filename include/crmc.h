@@ -94,7 +94,7 @@ typedef struct {
     int32_t ion_coupling;    /* 1: ions interact; 0: ideal ions (test systems) */
     int32_t lds_records;     /* neighbour records staged on chip per domain (0 = default) */
     int32_t fixed_grid;      /* 1: never shift the grid (only for tests: not ergodic) */
-    int32_t reserved;
+    int32_t site_trials;     /* extra trials per 16 ionizable sites of a domain (rounded up) */
     double lB;               /* Bjerrum length (sigma) */
     double rc;               /* Coulomb cutoff (sigma) */
     double eps_wca;          /* excluded-volume strength (kT); 0 disables it */
@@ -125,7 +125,7 @@ typedef struct {
                                  chip and were read from memory */
     int32_t n_cells;          /* cells per box edge */
     int32_t cell_capacity;
-    int32_t reserved;
+    int32_t max_cell_count;   /* most records any cell has held after re-binning */
 } crmc_obs;
 
 /* Trial log record (56 bytes), written when logging is enabled. */
@@ -201,6 +201,16 @@ int crmc_get_group_hist(crmc_t h, int32_t replica, int64_t cap, int64_t* out, in
 /* Trial logging (testing): keep up to `capacity` records on the device. */
 int crmc_enable_log(crmc_t h, int64_t capacity);
 int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out);
+
+/*
+ * Kernel timing.  While on, every kernel that crmc_sweep / crmc_sweep_ex
+ * enqueues is bracketed by HIP events on the library's stream.
+ * crmc_get_timing (synchronizes) returns the accumulated device milliseconds
+ * and launch counts per kernel kind: [0] re-binning, [1] trial phases,
+ * [2] end-of-sweep bookkeeping; crmc_set_timing(h, 1) also resets them.
+ */
+int crmc_set_timing(crmc_t h, int32_t on);
+int crmc_get_timing(crmc_t h, double ms[3], int64_t launches[3]);
 
 /* Philox4x32-10 on the device: n counter blocks (ctr n*4 words) with key
    (k0, k1) into out (n*4 words).  For checking the generator. */

@@ -56,7 +56,7 @@ def lib():
         L.orc_destroy.argtypes = [vp]
         L.orc_set_conditions.argtypes = [vp, d, d, d, d, d, d]
         L.orc_set_kappa.argtypes = [vp, d]
-        L.orc_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int]
+        L.orc_set_schedule.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_int]
         L.orc_partner.restype = u32
         L.orc_partner.argtypes = [vp, u64, C.c_int, u32, u32]
         L.orc_set_log.argtypes = [vp, vp, i64]
@@ -143,11 +143,13 @@ class Oracle:
         if kappa is not None:
             self._L.orc_set_kappa(self.h, float(kappa))
 
-    def set_schedule(self, trials_per_cell=1, fixed_grid=False, pairing=True):
-        """Cell schedule: trials per active cell per phase; fixed_grid turns the
-        per-sweep random shift off (a planted mistake for the negative control);
-        pairing lets a trial act on two reflection-paired cells of the phase."""
-        self._L.orc_set_schedule(self.h, int(trials_per_cell), int(bool(fixed_grid)), int(bool(pairing)))
+    def set_schedule(self, trials_per_cell=1, fixed_grid=False, pairing=True, site_trials=0):
+        """Cell schedule: trials per active cell per phase, plus site_trials/16
+        extra trials per ionizable site of a domain (rounded up); fixed_grid
+        turns the per-sweep random shift off (a planted mistake for the negative
+        control); pairing lets a trial act on two reflection-paired cells."""
+        self._L.orc_set_schedule(self.h, int(trials_per_cell), int(bool(fixed_grid)), int(bool(pairing)),
+                                 int(site_trials))
 
     def partner(self, sweep, colour, a, M):
         return int(self._L.orc_partner(self.h, int(sweep), int(colour), int(a), int(M)))

@@ -121,6 +121,7 @@ typedef struct {
     int trials;      /* trials per active cell per phase */
     int fixed_grid;  /* 1 = never shift the grid (test-only negative control) */
     int pairing;     /* 1 = trials act on reflection-paired cells, 0 = single cells */
+    int site_trials; /* extra trials per 16 ionizable sites of a domain */
     /* state, in global order */
     int np, npcap;
     orc_particle* P;
@@ -334,11 +335,12 @@ void orc_set_conditions(orc_sys* S, double pH, double pKa, double pKb, double pI
 
 void orc_set_kappa(orc_sys* S, double kappa) { S->kappa = kappa; }
 
-void orc_set_schedule(orc_sys* S, int trials_per_cell, int fixed_grid, int pairing)
+void orc_set_schedule(orc_sys* S, int trials_per_cell, int fixed_grid, int pairing, int site_trials)
 {
     S->trials = trials_per_cell;
     S->fixed_grid = fixed_grid;
     S->pairing = pairing;
+    S->site_trials = site_trials;
 }
 
 void orc_set_log(orc_sys* S, orc_trial* log, int64_t cap)
@@ -844,18 +846,19 @@ static void one_sweep(orc_sys* S, int32_t* series)
                 int c = (2 * i + px) + n * ((2 * jj + py) + n * (2 * kk + pz));
                 set_cell_region(S, &D, j, c, o, lnZ0 + lnk);
             }
-            /* static move set: the domain's site content does not depend on the state */
-            int has_acid = 0, has_base = 0;
+            /* static move set and trial count: the domain's site content does
+               not depend on the state */
+            int has_acid = 0, has_base = 0, nsites = 0;
             for (int j = 0; j < D.ncell; ++j)
                 for (int q = 0; q < D.list[j]->n; ++q) {
-                    if (D.list[j]->p[q].kind == ORC_ACID) has_acid = 1;
-                    if (D.list[j]->p[q].kind == ORC_BASE) has_base = 1;
+                    if (D.list[j]->p[q].kind == ORC_ACID) { has_acid = 1; ++nsites; }
+                    if (D.list[j]->p[q].kind == ORC_BASE) { has_base = 1; ++nsites; }
                 }
             D.nreact = 0;
             if (has_acid) D.react[D.nreact++] = 0;
             if (has_base) D.react[D.nreact++] = 1;
             D.react[D.nreact++] = 2;
-            int ntr = S->trials * D.ncell;
+            int ntr = S->trials * D.ncell + (nsites * S->site_trials + 15) / 16;
             for (int t = 0; t < ntr; ++t) {
                 uint32_t w[20];
                 trial_words(S, TAG_TRIAL, (uint32_t)S->sweep, (uint32_t)D.cell[0], (uint32_t)t * 8u, w);

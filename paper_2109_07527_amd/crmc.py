@@ -31,7 +31,7 @@ class CrmcError(RuntimeError):
 class crmc_params(C.Structure):
     _fields_ = [("n_replicas", C.c_int32), ("precision", C.c_int32), ("trials_per_cell", C.c_int32),
                 ("pairing", C.c_int32), ("ion_coupling", C.c_int32), ("lds_records", C.c_int32),
-                ("fixed_grid", C.c_int32), ("reserved", C.c_int32),
+                ("fixed_grid", C.c_int32), ("site_trials", C.c_int32),
                 ("lB", C.c_double), ("rc", C.c_double), ("eps_wca", C.c_double), ("rho0NA", C.c_double),
                 ("pKw", C.c_double), ("kappa", C.c_double), ("pKb", C.c_double),
                 ("seed", C.c_uint64), ("stream", C.c_void_p)]
@@ -47,7 +47,7 @@ class crmc_obs(C.Structure):
                 ("n_base", C.c_int64), ("n_base_charged", C.c_int64), ("n_xpos", C.c_int64),
                 ("n_xneg", C.c_int64), ("energy", C.c_double), ("attempts", C.c_int64 * 6),
                 ("accepts", C.c_int64 * 6), ("error_flags", C.c_uint32), ("n_cells", C.c_int32),
-                ("cell_capacity", C.c_int32), ("reserved", C.c_int32)]
+                ("cell_capacity", C.c_int32), ("max_cell_count", C.c_int32)]
 
 
 class crmc_trial_rec(C.Structure):
@@ -86,6 +86,8 @@ def load():
         "crmc_enable_log": (C.c_int, [vp, i64]),
         "crmc_read_log": (C.c_int, [vp, i64, P(crmc_trial_rec), P(i64)]),
         "crmc_philox": (C.c_int, [i64, P(u32), u32, u32, P(u32)]),
+        "crmc_set_timing": (C.c_int, [vp, i32]),
+        "crmc_get_timing": (C.c_int, [vp, P(d), P(i64)]),
         "crmc_pIX_from_salt": (d, [d, d, d]),
         "crmc_last_error": (C.c_char_p, [vp]),
         "crmc_destroy": (None, [vp]),
@@ -160,7 +162,7 @@ def crmc_sweep_ex(h, conds, n_sweeps):
 def crmc_observe(h, replica):
     o = crmc_obs()
     rc = load().crmc_observe(h, int(replica), C.byref(o))
-    out = {k: getattr(o, k) for k, _ in crmc_obs._fields_ if k not in ("attempts", "accepts", "reserved")}
+    out = {k: getattr(o, k) for k, _ in crmc_obs._fields_ if k not in ("attempts", "accepts")}
     out["attempts"] = list(o.attempts)
     out["accepts"] = list(o.accepts)
     out["status"] = rc
@@ -233,6 +235,18 @@ def crmc_philox(ctr, k0, k1):
     return out
 
 
+def crmc_set_timing(h, on):
+    return _check(h, load().crmc_set_timing(h, int(bool(on))))
+
+
+def crmc_get_timing(h):
+    """(milliseconds, launches) per kernel kind: re-binning, trial phases, end of sweep."""
+    ms = np.zeros(3, dtype=np.float64)
+    n = np.zeros(3, dtype=np.int64)
+    _check(h, load().crmc_get_timing(h, _p(ms, C.c_double), _p(n, C.c_int64)))
+    return ms, n
+
+
 def crmc_pIX_from_salt(pIS, pH, pKw=14.0):
     return load().crmc_pIX_from_salt(float(pIS), float(pH), float(pKw))
 
@@ -260,7 +274,7 @@ class System:
 
     def __init__(self, n_replicas=1, lB=2.0, rc=6.0, eps=1.0, rho0NA=0.0269424, pKw=14.0, kappa=0.5,
                  pKb=5.0, seed=1234, precision=32, trials_per_cell=1, pairing=True, ion_coupling=True,
-                 lds_records=0, fixed_grid=False, stream="torch"):
+                 lds_records=0, fixed_grid=False, site_trials=0, stream="torch"):
         p = crmc_params()
         p.n_replicas = int(n_replicas)
         p.precision = int(precision)
@@ -269,6 +283,7 @@ class System:
         p.ion_coupling = int(bool(ion_coupling))
         p.lds_records = int(lds_records)
         p.fixed_grid = int(bool(fixed_grid))
+        p.site_trials = int(site_trials)
         p.lB, p.rc, p.eps_wca, p.rho0NA, p.pKw, p.kappa, p.pKb = lB, rc, eps, rho0NA, pKw, kappa, pKb
         p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         s = current_stream() if stream == "torch" else stream

@@ -43,6 +43,11 @@ struct crmc_s {
     crmc_params p{};
     std::vector<HostReplica> reps;
     Replica* d_reps = nullptr;
+    uint32_t* d_cell2rep = nullptr;
+    uint32_t* d_dom2rep = nullptr;
+    double* d_lntab = nullptr;
+    int32_t lntab_n = 0;
+    uint32_t ncell_total = 0, ndom_total = 0;
     uint64_t* d_sweep = nullptr;
     uint32_t* d_err = nullptr;
     TrialRec* d_log = nullptr;
@@ -53,6 +58,13 @@ struct crmc_s {
     bool lds_attr_set = false;
     hipStream_t stream = nullptr;
     std::string err;
+    // kernel timing
+    bool timing = false;
+    struct Pending { int kind; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> free_events;
+    double t_ms[3] = {0, 0, 0};
+    int64_t t_n[3] = {0, 0, 0};
 };
 
 namespace {
@@ -109,7 +121,7 @@ void free_replica(HostReplica& r)
     Replica& d = r.d;
     void* ptrs[] = {d.rec[0], d.rec[1], d.cnt[0], d.cnt[1], d.e_acc, d.occupancy, d.site_group,
                     d.group_ionized, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
-                    d.moves, d.series};
+                    d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = Replica{};
@@ -130,15 +142,14 @@ SweepArgs base_args(crmc_t h)
 {
     SweepArgs a{};
     a.reps = h->d_reps;
+    a.cell2rep = h->d_cell2rep;
+    a.dom2rep = h->d_dom2rep;
+    a.lntab = h->d_lntab;
+    a.lntab_n = h->lntab_n;
+    a.ln2 = std::log(2.0);
     a.nrep = (uint32_t)h->reps.size();
-    uint32_t cells = 0, doms = 0;
-    for (auto& r : h->reps) {
-        cells += r.ncells;
-        const uint32_t M = r.d.h * r.d.h * r.d.h;
-        doms += h->p.pairing ? (M + 1u) / 2u : M;
-    }
-    a.ncell_total = cells;
-    a.ndom_total = doms;
+    a.ncell_total = h->ncell_total;
+    a.ndom_total = h->ndom_total;
     a.sweep = h->d_sweep;
     a.err = h->d_err;
     a.log = h->d_log;
@@ -150,6 +161,7 @@ SweepArgs base_args(crmc_t h)
     a.trials = h->p.trials_per_cell;
     a.pairing = h->p.pairing;
     a.fixed_grid = h->p.fixed_grid;
+    a.site_trials = h->p.site_trials;
     a.budget = h->pool;
     a.precision = h->p.precision;
     return a;
@@ -170,6 +182,83 @@ int upload_descriptors(crmc_t h)
     }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     HIP_TRY(h, hipMemcpy(h->d_reps, v.data(), v.size() * sizeof(Replica), hipMemcpyHostToDevice));
+    if (cells != h->ncell_total || doms != h->ndom_total || !h->d_cell2rep) {
+        // flattened cell and domain indices -> replica (the geometry is fixed after build)
+        std::vector<uint32_t> c2r(cells), d2r(doms);
+        uint32_t maxcap = 0;
+        for (size_t i = 0; i < h->reps.size(); ++i) {
+            const HostReplica& r = h->reps[i];
+            const uint32_t M = r.d.h * r.d.h * r.d.h;
+            const uint32_t nd = h->p.pairing ? (M + 1u) / 2u : M;
+            std::fill(c2r.begin() + r.d.cell_begin, c2r.begin() + r.d.cell_begin + r.ncells, (uint32_t)i);
+            std::fill(d2r.begin() + r.d.dom_begin, d2r.begin() + r.d.dom_begin + nd, (uint32_t)i);
+            maxcap = std::max(maxcap, r.cap);
+        }
+        if (h->d_cell2rep) (void)hipFree(h->d_cell2rep);
+        if (h->d_dom2rep) (void)hipFree(h->d_dom2rep);
+        if (h->d_lntab) (void)hipFree(h->d_lntab);
+        h->d_cell2rep = h->d_dom2rep = nullptr;
+        h->d_lntab = nullptr;
+        // ln k for every count a domain can reach (two cells of capacity maxcap, plus one)
+        h->lntab_n = (int32_t)(2u * maxcap + 2u);
+        std::vector<double> lt((size_t)h->lntab_n, 0.0);
+        for (int32_t k = 1; k < h->lntab_n; ++k) lt[(size_t)k] = std::log((double)k);
+        HIP_TRY(h, dalloc(&h->d_cell2rep, c2r.size()));
+        HIP_TRY(h, dalloc(&h->d_dom2rep, d2r.size()));
+        HIP_TRY(h, dalloc(&h->d_lntab, lt.size()));
+        HIP_TRY(h, hipMemcpy(h->d_cell2rep, c2r.data(), c2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(h->d_dom2rep, d2r.data(), d2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(h->d_lntab, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice));
+        h->ncell_total = cells;
+        h->ndom_total = doms;
+    }
+    return CRMC_OK;
+}
+
+hipError_t event_get(crmc_t h, hipEvent_t* e)
+{
+    if (!h->free_events.empty()) {
+        *e = h->free_events.back();
+        h->free_events.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(e);
+}
+
+// accumulate (and recycle) all but the newest `keep` timed launches
+int drain_timing(crmc_t h, size_t keep)
+{
+    const size_t n = h->pending.size() > keep ? h->pending.size() - keep : 0;
+    for (size_t i = 0; i < n; ++i) {
+        auto& p = h->pending[i];
+        HIP_TRY(h, hipEventSynchronize(p.b));
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, p.a, p.b));
+        h->t_ms[p.kind] += ms;
+        h->t_n[p.kind] += 1;
+        h->free_events.push_back(p.a);
+        h->free_events.push_back(p.b);
+    }
+    h->pending.erase(h->pending.begin(), h->pending.begin() + (ptrdiff_t)n);
+    return CRMC_OK;
+}
+
+// enqueue one kernel, bracketed by events when timing is on
+template <typename F>
+int timed(crmc_t h, int kind, F&& launch)
+{
+    if (!h->timing) {
+        HIP_TRY(h, launch());
+        return CRMC_OK;
+    }
+    hipEvent_t a, b;
+    HIP_TRY(h, event_get(h, &a));
+    HIP_TRY(h, event_get(h, &b));
+    HIP_TRY(h, hipEventRecord(a, h->stream));
+    HIP_TRY(h, launch());
+    HIP_TRY(h, hipEventRecord(b, h->stream));
+    h->pending.push_back({kind, a, b});
+    if (h->pending.size() > 4096) return drain_timing(h, 2048);
     return CRMC_OK;
 }
 
@@ -203,8 +292,9 @@ int crmc_create(const crmc_params* p, crmc_t* out)
     if (p->n_replicas < 1 || p->n_replicas > (1 << 20)) return CRMC_E_ARG;
     if (p->precision != 32 && p->precision != 64) return CRMC_E_ARG;
     if (p->trials_per_cell < 1 || p->trials_per_cell > (1 << 20)) return CRMC_E_ARG;
-    if (!(p->rc > 0.0) || !(p->lB >= 0.0) || !(p->eps_wca >= 0.0) || !(p->rho0NA > 0.0)) return CRMC_E_ARG;
-    if (p->lds_records < 0) return CRMC_E_ARG;
+    // the Coulomb cutoff must exceed the excluded-volume range 2^(1/6)
+    if (!(p->rc > 1.2) || !(p->lB >= 0.0) || !(p->eps_wca >= 0.0) || !(p->rho0NA > 0.0)) return CRMC_E_ARG;
+    if (p->lds_records < 0 || p->site_trials < 0 || p->site_trials > 4096) return CRMC_E_ARG;
     crmc_t h = new (std::nothrow) crmc_s;
     if (!h) return CRMC_E_NOMEM;
     h->p = *p;
@@ -282,19 +372,40 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
         if (k == KIND_XPOS) tot[2]++;
         if (k == KIND_XNEG) tot[3]++;
     }
-    uint32_t maxc = 0, maxblock = 0;
+    uint32_t maxc = 0;
     for (uint32_t c = 0; c < ncells; ++c) maxc = std::max<uint32_t>(maxc, (uint32_t)lists[c].size());
-    for (uint32_t z = 0; z < nc; ++z)
-        for (uint32_t y = 0; y < nc; ++y)
-            for (uint32_t x = 0; x < nc; ++x) {
-                uint32_t s = 0;
-                for (int o = 0; o < 8; ++o)
-                    s += site_cnt[((x + (o & 1)) % nc) + nc * (((y + ((o >> 1) & 1)) % nc) + nc * ((z + (o >> 2)) % nc))];
-                maxblock = std::max(maxblock, s);
+    // Most sites any shifted cell can hold: on a grid four times finer, a
+    // cell-wide interval touches at most five fine cells per dimension, so the
+    // largest 5x5x5 block sum of fine-cell site counts bounds every shift.
+    uint32_t site_bound = 0;
+    {
+        const uint32_t F = 4u * nc;
+        std::vector<uint32_t> f((size_t)F * F * F, 0), g(f.size(), 0);
+        for (int32_t i = 0; i < n; ++i) {
+            const uint32_t k = (uint32_t)kind[i];
+            if (k == KIND_XPOS || k == KIND_XNEG) continue;
+            const uint4 v = in[(size_t)i];
+            f[cell_of_h(v.x, F) + F * (cell_of_h(v.y, F) + (size_t)F * cell_of_h(v.z, F))]++;
+        }
+        for (int dim = 0; dim < 3; ++dim) {
+            const size_t stride = dim == 0 ? 1 : (dim == 1 ? F : (size_t)F * F);
+            for (size_t idx = 0; idx < f.size(); ++idx) {
+                const size_t coord = (idx / stride) % F;
+                uint32_t sum = 0;
+                for (uint32_t o = 0; o < 5; ++o) {
+                    const size_t cj = (coord + o) % F;
+                    sum += f[idx + (cj - coord) * stride];
+                }
+                g[idx] = sum;
             }
+            f.swap(g);
+        }
+        for (uint32_t v : f) site_bound = std::max(site_bound, v);
+    }
     uint32_t cap;
     if (cell_capacity == 0) {
-        cap = std::max<uint32_t>(64u, 2u * maxblock + 96u);
+        // sites, as many counter-ions again, and room for salt
+        cap = std::max<uint32_t>(64u, 2u * site_bound + 64u);
         cap = std::max<uint32_t>(cap, maxc + 32u);
         cap = (cap + 31u) & ~31u;
     } else {
@@ -373,6 +484,21 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     HIP_TRY(h, hipMemcpy(d.totals, tot, sizeof tot, hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d.moves, 0, 12 * sizeof(uint64_t)));
     HIP_TRY(h, hipMemset(d.series, 0, (size_t)series_cap * 4 * sizeof(int32_t)));
+    {
+        // cell boundaries b_k = ceil(k 2^32 / n) (b_n wraps to 0) and ln of the widths
+        std::vector<uint32_t> b(nc + 1);
+        std::vector<double> lw(nc);
+        for (uint32_t k = 0; k <= nc; ++k) b[k] = (uint32_t)cell_lo_h(k, nc);
+        for (uint32_t k = 0; k < nc; ++k) lw[k] = std::log((double)(cell_lo_h(k + 1, nc) - cell_lo_h(k, nc)));
+        HIP_TRY(h, dalloc(&d.bnd, nc + 1));
+        HIP_TRY(h, dalloc(&d.lnW, nc));
+        HIP_TRY(h, dalloc(&d.hiwater, 1));
+        HIP_TRY(h, dalloc(&d.tab, 1));
+        HIP_TRY(h, hipMemcpy(d.bnd, b.data(), b.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.lnW, lw.data(), lw.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.hiwater, &maxc, sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemset(d.tab, 0, sizeof(SweepTab)));
+    }
     d.series_cap = series_cap;
     d.n = nc;
     d.h = nc / 2u;
@@ -454,7 +580,7 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
     }
     // the LDS pool must hold both cells of a domain
     if (h->pool < (int)(2 * maxcap + 64)) h->pool = (int)(2 * maxcap + 64);
-    const size_t lds = phase_lds_bytes(maxcap, h->pool);
+    const size_t lds = (size_t)h->pool * sizeof(uint4);
     int dev = 0, maxlds = 0;
     HIP_TRY(h, hipGetDevice(&dev));
     HIP_TRY(h, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -468,13 +594,17 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
     int rc = upload_descriptors(h);
     if (rc) return rc;
     SweepArgs a = base_args(h);
+    hipStream_t st = h->stream;
     for (int64_t i = 0; i < n_sweeps; ++i) {
-        HIP_TRY(h, launch_bin(a, h->stream));
+        rc = timed(h, 0, [&] { return launch_bin(a, st); });
+        if (rc) return rc;
         for (int col = 0; col < 8; ++col) {
             a.colour = col;
-            HIP_TRY(h, launch_phase(a, lds, h->stream));
+            rc = timed(h, 1, [&] { return launch_phase(a, lds, st); });
+            if (rc) return rc;
         }
-        HIP_TRY(h, launch_sweep_end(a, 0, h->stream));
+        rc = timed(h, 2, [&] { return launch_sweep_end(a, st); });
+        if (rc) return rc;
         h->sweeps++;
     }
     return CRMC_OK;
@@ -505,6 +635,8 @@ int crmc_observe(crmc_t h, int32_t replica, crmc_obs* out)
     HIP_TRY(h, hipMemcpy(mv, r.d.moves, sizeof mv, hipMemcpyDeviceToHost));
     HIP_TRY(h, hipMemcpy(e.data(), r.d.e_acc, r.ncells * sizeof(double), hipMemcpyDeviceToHost));
     HIP_TRY(h, hipMemcpy(&err, h->d_err, sizeof err, hipMemcpyDeviceToHost));
+    uint32_t hiw = 0;
+    HIP_TRY(h, hipMemcpy(&hiw, r.d.hiwater, sizeof hiw, hipMemcpyDeviceToHost));
     double E = r.E0;
     for (double v : e) E += v;
     out->sweeps = h->sweeps;
@@ -522,6 +654,7 @@ int crmc_observe(crmc_t h, int32_t replica, crmc_obs* out)
     out->error_flags = err;
     out->n_cells = (int32_t)r.n;
     out->cell_capacity = (int32_t)r.cap;
+    out->max_cell_count = (int32_t)hiw;
     if (err & (ERR_BIN_CAPACITY | ERR_INSERT_CAPACITY))
         return fail(h, CRMC_E_CAPACITY, "a cell exceeded its record capacity; rebuild with a larger cell_capacity");
     return CRMC_OK;
@@ -654,10 +787,31 @@ int crmc_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32
     return rc;
 }
 
+int crmc_set_timing(crmc_t h, int32_t on)
+{
+    if (!h) return CRMC_E_ARG;
+    int rc = drain_timing(h, 0);
+    if (rc) return rc;
+    h->timing = on != 0;
+    for (int i = 0; i < 3; ++i) { h->t_ms[i] = 0.0; h->t_n[i] = 0; }
+    return CRMC_OK;
+}
+
+int crmc_get_timing(crmc_t h, double ms[3], int64_t launches[3])
+{
+    if (!h || !ms || !launches) return fail(h, CRMC_E_ARG, "bad arguments");
+    int rc = drain_timing(h, 0);
+    if (rc) return rc;
+    for (int i = 0; i < 3; ++i) { ms[i] = h->t_ms[i]; launches[i] = h->t_n[i]; }
+    return CRMC_OK;
+}
+
 void crmc_destroy(crmc_t h)
 {
     if (!h) return;
-    if (h->stream || true) (void)hipStreamSynchronize(h->stream);
+    (void)hipStreamSynchronize(h->stream);
+    for (auto& p : h->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+    for (auto e : h->free_events) (void)hipEventDestroy(e);
     for (auto& r : h->reps)
         if (r.built) free_replica(r);
     if (h->d_reps) (void)hipFree(h->d_reps);
@@ -665,6 +819,9 @@ void crmc_destroy(crmc_t h)
     if (h->d_err) (void)hipFree(h->d_err);
     if (h->d_log) (void)hipFree(h->d_log);
     if (h->d_log_n) (void)hipFree(h->d_log_n);
+    if (h->d_cell2rep) (void)hipFree(h->d_cell2rep);
+    if (h->d_dom2rep) (void)hipFree(h->d_dom2rep);
+    if (h->d_lntab) (void)hipFree(h->d_lntab);
     delete h;
 }
 

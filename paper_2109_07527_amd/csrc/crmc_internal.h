@@ -15,7 +15,7 @@ constexpr uint32_t ERR_INSERT_CAPACITY = 2u;
 constexpr uint32_t INFO_UNSTAGED = 4u;
 
 constexpr int PHASE_THREADS = 256; // four wavefronts per domain
-constexpr int BIN_THREADS = 64;    // one wavefront per cell
+constexpr int BIN_THREADS = 256;   // four wavefronts, one new cell each
 
 // Record: three fixed-point coordinates and a meta word
 //   bits 0-2 kind, bit 3 charged flag, bits 8-31 site id (NO_SITE for ions)
@@ -23,6 +23,12 @@ __host__ __device__ inline uint32_t make_meta(uint32_t kind, uint32_t charged, u
 {
     return kind | (charged << 3) | (sid << 8);
 }
+
+// per replica, rewritten by the re-binning kernel every sweep
+struct SweepTab {
+    uint32_t o[4];     // grid shift of the current sweep
+    uint32_t pairc[8]; // reflection centre of the active-cell pairing, per colour
+};
 
 // One replica as the kernels see it.
 struct Replica {
@@ -39,6 +45,10 @@ struct Replica {
     int64_t* totals;         // nA-, nB+, nX+, nX-
     uint64_t* moves;         // attempts[6], accepts[6]
     int32_t* series;         // series_cap rows of 4
+    uint32_t* bnd;           // n+1 cell boundaries b_k = ceil(k 2^32 / n), b_n stored as 0
+    double* lnW;             // n: ln of the cell widths in lattice units
+    uint32_t* hiwater;       // largest cell count seen by the re-binning
+    SweepTab* tab;
     int64_t series_cap;
     uint32_t n, h, ncells, cap;
     uint32_t ncores, nsites, ngroups;
@@ -60,6 +70,10 @@ struct TrialRec {
 
 struct SweepArgs {
     Replica* reps;
+    const uint32_t* cell2rep; // global cell index -> replica
+    const uint32_t* dom2rep;  // global domain index (of one phase) -> replica
+    const double* lntab;      // ln k for k < lntab_n (k = 0 unused)
+    int32_t lntab_n;
     uint32_t nrep;
     uint32_t ncell_total;
     uint32_t ndom_total;
@@ -69,21 +83,20 @@ struct SweepArgs {
     TrialRec* log;
     unsigned long long* log_n;
     uint64_t log_cap;
-    double lB, eps;
-    int32_t ion_coupling, trials, pairing, fixed_grid;
-    int32_t budget;    // neighbour records staged on chip per domain
+    double lB, eps, ln2;
+    int32_t ion_coupling, trials, pairing, fixed_grid, site_trials;
+    int32_t budget;    // LDS pool per domain, in records
     int32_t precision; // 32 or 64
 };
 
 // launchers (device translation unit)
 hipError_t launch_bin(const SweepArgs& a, hipStream_t s);
 hipError_t launch_phase(const SweepArgs& a, size_t lds_bytes, hipStream_t s);
-hipError_t launch_sweep_end(const SweepArgs& a, int64_t series_first, hipStream_t s);
+hipError_t launch_sweep_end(const SweepArgs& a, hipStream_t s);
 hipError_t launch_energy(const Replica* rep_dev, const Replica& rep_host, double lB, double eps,
                          int ion_coupling, int buf, double* out_per_cell, hipStream_t s);
 hipError_t launch_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                          hipStream_t s);
-size_t phase_lds_bytes(uint32_t max_cap, int budget);
 hipError_t set_phase_lds_limit(size_t bytes);
 
 } // namespace crmc

@@ -2,9 +2,9 @@
 //
 //   k_bin        per sweep: draw the grid shift, re-bin every record into the
 //                shifted cells (stable: old cell order, then order in the old
-//                cell), sample per-site occupancy.  One wavefront per new cell,
-//                gathering from the (at most 27, usually 8) old cells that
-//                overlap it, so no atomics and no scan are needed.
+//                cell), sample per-site occupancy, publish the sweep's shift and
+//                pairing table.  One wavefront per new cell gathers from the old
+//                cells that overlap it (at most 27, usually 8): no atomics, no scan.
 //   k_phase<R>   per colour: one 256-thread workgroup per domain (one cell, or
 //                two reflection-paired cells of the colour).  Stages the
 //                domain's cells and their 26-cell neighbourhoods in LDS, then
@@ -40,7 +40,7 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 }
 
 // ------------------------------------------------------------------------
-// integer helpers shared by all kernels
+// integer helpers
 // ------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t pick32(uint32_t w, uint32_t m) { return __umulhi(w, m); }
 
@@ -55,18 +55,13 @@ __device__ __forceinline__ double unit53(uint32_t a, uint32_t b)
     return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) * (1.0 / 9007199254740992.0);
 }
 
-// cell boundary b_k = ceil(k 2^32 / n) (b_n = 2^32)
-__device__ __forceinline__ uint64_t cell_lo(uint32_t k, uint32_t n)
-{
-    return (((uint64_t)k << 32) + (uint64_t)n - 1u) / (uint64_t)n;
-}
 __device__ __forceinline__ uint32_t cell_of(uint32_t y, uint32_t n) { return __umulhi(y, n); }
 
-__device__ __forceinline__ void grid_shift(const Replica& R, uint64_t sweep, int fixed, uint32_t o[3])
+__device__ __forceinline__ void grid_shift(uint32_t k0, uint32_t k1, uint64_t sweep, int fixed, uint32_t o[3])
 {
     if (fixed) { o[0] = o[1] = o[2] = 0u; return; }
     uint32_t w[4];
-    philox4x32_10((uint32_t)sweep, 0u, 0u, TAG_SHIFT, R.key0, R.key1, w);
+    philox4x32_10((uint32_t)sweep, 0u, 0u, TAG_SHIFT, k0, k1, w);
     o[0] = w[0]; o[1] = w[1]; o[2] = w[2];
 }
 
@@ -87,19 +82,6 @@ __device__ __forceinline__ int rec_q(uint32_t meta)
     return 0;
 }
 
-// replica owning a flattened index, by binary search on a prefix field
-template <int FIELD>
-__device__ __forceinline__ uint32_t find_replica(const Replica* reps, uint32_t nrep, uint32_t x)
-{
-    uint32_t lo = 0, hi = nrep; // invariant: prefix(lo) <= x < prefix(hi)
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        const uint32_t p = FIELD == 0 ? reps[mid].cell_begin : reps[mid].dom_begin;
-        if (p <= x) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
     const uint32_t lane = threadIdx.x & 63u;
@@ -111,8 +93,10 @@ __device__ __forceinline__ uint64_t lanemask_lt()
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
 {
-    const uint32_t gcell = blockIdx.x;
-    const uint32_t r = find_replica<0>(a.reps, a.nrep, gcell);
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t gcell = blockIdx.x * (BIN_THREADS / 64) + wave;
+    if (gcell >= a.ncell_total) return;
+    const uint32_t r = a.cell2rep[gcell];
     const Replica& R = a.reps[r];
     const uint32_t n = R.n, cap = R.cap;
     const uint32_t k = gcell - R.cell_begin;
@@ -121,32 +105,50 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     const uint4* __restrict__ src = R.rec[cur];
     const uint32_t* __restrict__ scnt = R.cnt[cur];
     uint4* __restrict__ dst = R.rec[nxt];
+    const uint32_t* __restrict__ bnd = R.bnd;
+    const uint32_t hw = *R.hiwater;
 
     uint32_t on[3], oo[3];
-    grid_shift(R, s, a.fixed_grid, on);
+    grid_shift(R.key0, R.key1, s, a.fixed_grid, on);
     if (s == 0) { oo[0] = oo[1] = oo[2] = 0u; }
-    else grid_shift(R, s - 1, a.fixed_grid, oo);
+    else grid_shift(R.key0, R.key1, s - 1, a.fixed_grid, oo);
+
+    if (k == 0 && lane < 12) {
+        // the sweep's table: shift, and the pairing centre of every colour
+        const uint32_t M = R.h * R.h * R.h;
+        uint32_t v = 0;
+        if (lane < 4) v = lane < 3 ? on[lane] : 0u;
+        else {
+            uint32_t w[4];
+            philox4x32_10((uint32_t)s, lane - 4u, 0u, TAG_PAIR, R.key0, R.key1, w);
+            const uint32_t rr = pick32(w[0], M);
+            v = (uint32_t)(((uint64_t)M - 1u + 2ull * M - 2ull * rr) % M);
+        }
+        if (lane < 4) R.tab->o[lane] = v; else R.tab->pairc[lane - 4] = v;
+    }
 
     const uint32_t kc[3] = {k % n, (k / n) % n, k / (n * n)};
     uint32_t cand[3][3];
     int ncand[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const uint32_t lo_abs = on[d] + (uint32_t)cell_lo(kc[d], n);
-        const uint32_t hi_abs = on[d] + (uint32_t)(cell_lo(kc[d] + 1, n) - 1u);
+        const uint32_t lo_abs = on[d] + bnd[kc[d]];
+        const uint32_t hi_abs = on[d] + bnd[kc[d] + 1] - 1u;
         const uint32_t j0 = cell_of(lo_abs - oo[d], n), j1 = cell_of(hi_abs - oo[d], n);
         const int m = (int)((j1 + n - j0) % n) + 1;
-        uint32_t v[3];
-        for (int i = 0; i < m; ++i) v[i] = (j0 + (uint32_t)i) % n;
-        // ascending (wrap-around puts small indices last)
-        for (int i = 0; i < m; ++i)
-            for (int j = i + 1; j < m; ++j)
-                if (v[j] < v[i]) { uint32_t t = v[i]; v[i] = v[j]; v[j] = t; }
-        for (int i = 0; i < m; ++i) cand[d][i] = v[i];
+        uint32_t v0 = j0, v1 = (j0 + 1u) % n, v2 = (j0 + 2u) % n;
+        // ascending order (a wrap-around puts small indices last)
+        if (m == 2 && v1 < v0) { uint32_t t = v0; v0 = v1; v1 = t; }
+        if (m == 3) {
+            if (v1 < v0) { uint32_t t = v0; v0 = v1; v1 = t; }
+            if (v2 < v1) { uint32_t t = v1; v1 = v2; v2 = t; }
+            if (v1 < v0) { uint32_t t = v0; v0 = v1; v1 = t; }
+        }
+        cand[d][0] = v0; cand[d][1] = v1; cand[d][2] = v2;
         ncand[d] = m;
     }
 
     const uint64_t lt = lanemask_lt();
-    const uint32_t lane = threadIdx.x;
     uint32_t base = 0;
     for (int iz = 0; iz < ncand[2]; ++iz)
         for (int iy = 0; iy < ncand[1]; ++iy)
@@ -167,7 +169,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
                         const uint32_t pos = base + (uint32_t)__popcll(mask & lt);
                         if (pos < cap) dst[(size_t)k * cap + pos] = rec;
                         const uint32_t sid = rec.w >> 8;
-                        if (sid != NO_SITE && rec_charged(rec.w)) R.occupancy[sid] += 1u;
+                        // each site lands in exactly one new cell: a non-returning add
+                        if (sid != NO_SITE && rec_charged(rec.w))
+                            atomicAdd((unsigned long long*)&R.occupancy[sid], 1ull);
                     }
                     base += (uint32_t)__popcll(mask);
                 }
@@ -175,6 +179,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     if (lane == 0) {
         R.cnt[nxt][k] = base < cap ? base : cap;
         if (base > cap) atomicOr(a.err, ERR_BIN_CAPACITY);
+        if (base > hw) atomicMax(R.hiwater, base); // rarely taken once the mark has settled
     }
 }
 
@@ -198,10 +203,10 @@ template <> struct Math<double> {
 // a particle whose state the trial changes
 struct Chg {
     uint32_t x, y, z;
-    int dq;     // charge change seen by every other particle
-    int dw;     // +1 inserted free ion, -1 deleted free ion, 0 otherwise
-    int member; // domain cell it lives in
-    int own;    // index in that cell's list, -1 if inserted
+    int dq;      // charge change seen by every other particle
+    int dw;      // +1 inserted free ion, -1 deleted free ion, 0 otherwise
+    int member;  // domain cell it lives in
+    int own;     // index in that cell's list, -1 if inserted
     int q_old, q_new, ion, pres_old, pres_new;
 };
 
@@ -209,28 +214,43 @@ struct PairParams {
     float scale_f;
     double scale_d;
     uint64_t R2;
+    double rc2_lo, rc2_hi; // rc^2 (1 -+ 1e-5): outside this band the float distance decides
     double lB, kappa, eps;
     int ion_coupling;
 };
 
 template <typename Real>
+__device__ __forceinline__ Real scale_of(const PairParams& P)
+{
+    return sizeof(Real) == 4 ? (Real)P.scale_f : (Real)P.scale_d;
+}
+
+template <typename Real>
 __device__ __forceinline__ double pair_term(const uint4& rec, const Chg& c, const PairParams& P, int& ov)
 {
+    // distance first: most records of a 27-cell neighbourhood lie beyond rc
+    const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
+    const Real sc = scale_of<Real>(P);
+    const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
+    const Real r2 = fx * fx + fy * fy + fz * fz;
+    if (r2 > (Real)P.rc2_hi) return 0.0;
     const int ionj = rec_is_ion(rec.w);
     if (!P.ion_coupling && ionj) return 0.0;
     const int qj = rec_q(rec.w);
     const bool coul = c.dq != 0 && qj != 0;
     const bool ev = c.dw != 0;
     if (!coul && !ev) return 0.0;
-    const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
-    const Real sc = sizeof(Real) == 4 ? (Real)P.scale_f : (Real)P.scale_d;
-    const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
-    const Real r2 = fx * fx + fy * fy + fz * fz;
     double e = 0.0;
     if (coul) {
-        const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
-        const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
-        if (r2i < P.R2) {
+        // inside/outside the cutoff as decided on the exact integer squared
+        // distance; the float distance settles it outside a +-1e-5 band
+        bool in = r2 < (Real)P.rc2_lo;
+        if (!in) {
+            const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
+            const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+            in = r2i < P.R2;
+        }
+        if (in) {
             const Real rinv = Math<Real>::rsqrt(r2);
             const Real r = r2 * rinv;
             const Real phi = Math<Real>::ex(-(Real)P.kappa * r) * rinv;
@@ -254,7 +274,7 @@ template <typename Real>
 __device__ __forceinline__ double wca_core(const Chg& c, const uint4& cx, double delta, const PairParams& P, int& ov)
 {
     const int32_t dx = (int32_t)(cx.x - c.x), dy = (int32_t)(cx.y - c.y), dz = (int32_t)(cx.z - c.z);
-    const Real sc = sizeof(Real) == 4 ? (Real)P.scale_f : (Real)P.scale_d;
+    const Real sc = scale_of<Real>(P);
     const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
     const Real r = Math<Real>::sqrt_(fx * fx + fy * fy + fz * fz);
     const Real sh = r - (Real)delta;
@@ -266,6 +286,38 @@ __device__ __forceinline__ double wca_core(const Chg& c, const uint4& cx, double
     const Real ir2 = Math<Real>::rcp(sh * sh);
     const Real ir6 = ir2 * ir2 * ir2;
     return (double)c.dw * (double)((Real)4.0 * (Real)P.eps * (ir6 * ir6 - ir6) + (Real)P.eps);
+}
+
+// the pair formed or broken between the two changed particles
+template <typename Real>
+__device__ __forceinline__ double changed_pair(const Chg& A, const Chg& B, const PairParams& P, bool ev_on, int& ov)
+{
+    if (!P.ion_coupling && (A.ion || B.ion)) return 0.0;
+    const int32_t dx = (int32_t)(B.x - A.x), dy = (int32_t)(B.y - A.y), dz = (int32_t)(B.z - A.z);
+    const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
+    const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+    const Real sc = scale_of<Real>(P);
+    const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
+    const Real r2 = fx * fx + fy * fy + fz * fz;
+    double e = 0.0;
+    const int dqq = A.q_new * B.q_new - A.q_old * B.q_old;
+    if (dqq != 0 && r2i < P.R2) {
+        const Real rinv = Math<Real>::rsqrt(r2);
+        e += P.lB * (double)dqq * (double)(Math<Real>::ex(-(Real)P.kappa * r2 * rinv) * rinv);
+    }
+    const int any_ion = A.ion || B.ion;
+    const int pn = ev_on && any_ion && A.pres_new && B.pres_new;
+    const int po = ev_on && any_ion && A.pres_old && B.pres_old;
+    if ((pn || po) && r2 < (Real)1.2599210498948731647672106) {
+        if (r2 < (Real)0.25) {
+            if (pn) ov = 1;
+        } else {
+            const Real ir2 = Math<Real>::rcp(r2);
+            const Real ir6 = ir2 * ir2 * ir2;
+            e += (double)(pn - po) * (double)((Real)4.0 * (Real)P.eps * (ir6 * ir6 - ir6) + (Real)P.eps);
+        }
+    }
+    return e;
 }
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -287,16 +339,25 @@ struct PhaseShared {
     int32_t dtot[4];
 };
 
-// record g of the neighbour list of the domain (concatenated over both members)
+// position g of the concatenated neighbour segments -> segment
+__device__ __forceinline__ int segment_of(const PhaseShared& S, int g)
+{
+    int lo = 0, hi = 52; // pre[lo] <= g < pre[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (S.pre[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ uint4 neighbour_global(const PhaseShared& S, const uint4* recb, uint32_t cap, int g)
 {
-    int q = 0;
-    while (S.pre[q + 1] <= g) ++q;
+    const int q = segment_of(S, g);
     return recb[(size_t)S.seg_cell[q] * cap + (uint32_t)(g - S.pre[q])];
 }
 
-// k-th record of the domain (member 0's list, then member 1's) matching the
-// predicate; every wavefront computes the same answer independently
+// domain-order index of the k-th record of the domain matching the predicate
+// (member 0's list, then member 1's); each wavefront computes it alone
 template <typename Pred>
 __device__ __forceinline__ int domain_kth(const uint4* own0, int n0, const uint4* own1, int n1, Pred pred, int k)
 {
@@ -319,23 +380,6 @@ __device__ __forceinline__ int domain_kth(const uint4* own0, int n0, const uint4
     return -1;
 }
 
-__device__ __forceinline__ int domain_count(const uint4* own0, int n0, const uint4* own1, int n1, int kind, int charged)
-{
-    const int lane = threadIdx.x & 63;
-    const int total = n0 + n1;
-    int c = 0;
-    for (int b = 0; b < total; b += 64) {
-        const int g = b + lane;
-        bool p = false;
-        if (g < total) {
-            const uint32_t m = g < n0 ? own0[g].w : own1[g - n0].w;
-            p = rec_kind(m) == kind && (kind == (int)KIND_XPOS || kind == (int)KIND_XNEG || rec_charged(m) == charged);
-        }
-        c += __popcll(__ballot(p));
-    }
-    return c;
-}
-
 template <typename Real>
 __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
 {
@@ -344,7 +388,7 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t gd = blockIdx.x;
-    const uint32_t r = find_replica<1>(a.reps, a.nrep, gd);
+    const uint32_t r = a.dom2rep[gd];
     const Replica& R = a.reps[r];
     const uint32_t n = R.n, h = R.h, cap = R.cap;
     const uint64_t s = *a.sweep;
@@ -359,10 +403,7 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
     const uint32_t d = gd - R.dom_begin;
     uint32_t ma, mb;
     if (a.pairing) {
-        uint32_t w[4];
-        philox4x32_10((uint32_t)s, (uint32_t)colour, 0u, TAG_PAIR, R.key0, R.key1, w);
-        const uint32_t rr = pick32(w[0], M);
-        const uint32_t c = (uint32_t)(((uint64_t)M - 1u + 2ull * M - 2ull * rr) % M);
+        const uint32_t c = R.tab->pairc[colour];
         const uint32_t half = c >> 1;
         if (d <= half) { ma = d; mb = c - d; }
         else { ma = c + 1u + (d - half - 1u); mb = M + c - ma; }
@@ -370,180 +411,198 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
         ma = mb = d;
     }
     const int ncell = (ma == mb) ? 1 : 2;
-    uint32_t cellv[2], cc[2][3];
-    {
-        const uint32_t mm[2] = {ma, mb};
-        for (int j = 0; j < 2; ++j) {
-            const uint32_t m = mm[j];
-            cc[j][0] = 2u * (m % h) + px;
-            cc[j][1] = 2u * ((m / h) % h) + py;
-            cc[j][2] = 2u * (m / (h * h)) + pz;
-            cellv[j] = cc[j][0] + n * (cc[j][1] + n * cc[j][2]);
-        }
-    }
+    uint32_t cc0[3], cc1[3];
+    cc0[0] = 2u * (ma % h) + px; cc0[1] = 2u * ((ma / h) % h) + py; cc0[2] = 2u * (ma / (h * h)) + pz;
+    cc1[0] = 2u * (mb % h) + px; cc1[1] = 2u * ((mb / h) % h) + py; cc1[2] = 2u * (mb / (h * h)) + pz;
+    const uint32_t cell0 = cc0[0] + n * (cc0[1] + n * cc0[2]);
+    const uint32_t cell1 = cc1[0] + n * (cc1[1] + n * cc1[2]);
 
     // LDS pool of a.budget records: each member's list, with room for the
-    // growth its trials can cause (two ions per trial), then the neighbours
-    const int ntr = a.trials * ncell;
-    int n_own[2];
-    n_own[0] = (int)cntb[cellv[0]];
-    n_own[1] = ncell == 2 ? (int)cntb[cellv[1]] : 0;
-    const int room0 = min((int)cap, n_own[0] + 2 * ntr);
-    const int room1 = ncell == 2 ? min((int)cap, n_own[1] + 2 * ntr) : 0;
+    // growth its trials can cause (two ions per trial, with the site count
+    // bounded by the record count), then the neighbours
+    int n0 = (int)cntb[cell0];
+    int n1 = ncell == 2 ? (int)cntb[cell1] : 0;
+    const int ntr_max = a.trials * ncell + ((n0 + n1) * a.site_trials + 15) / 16;
+    const int room0 = min((int)cap, n0 + 2 * ntr_max);
+    const int room1 = ncell == 2 ? min((int)cap, n1 + 2 * ntr_max) : 0;
     uint4* own0 = smem;
     uint4* own1 = smem + room0;
     uint4* nb = smem + room0 + room1;
 
-    // ---- neighbour segments and staging ------------------------------------
-    if (tid < 52) {
-        const int j = tid / 26, q = tid % 26;
-        const int o = q < 13 ? q : q + 1;
-        const int dxo = o % 3 - 1, dyo = (o / 3) % 3 - 1, dzo = o / 9 - 1;
-        uint32_t nc = 0, cnt = 0;
-        if (j < ncell) {
-            const uint32_t x = (cc[j][0] + n + (uint32_t)dxo) % n, y = (cc[j][1] + n + (uint32_t)dyo) % n,
-                           z = (cc[j][2] + n + (uint32_t)dzo) % n;
-            nc = x + n * (y + n * z);
-            cnt = cntb[nc];
+    // ---- neighbour segments: counts, then a wavefront prefix scan -----------
+    if (wave == 0) {
+        int cnt = 0;
+        uint32_t nc = 0;
+        if (lane < 52) {
+            const int j = lane / 26, q = lane % 26;
+            const int o = q < 13 ? q : q + 1;
+            const uint32_t* cc = j ? cc1 : cc0;
+            if (j < ncell) {
+                const uint32_t x = (cc[0] + n + (uint32_t)(o % 3) - 1u) % n;
+                const uint32_t y = (cc[1] + n + (uint32_t)((o / 3) % 3) - 1u) % n;
+                const uint32_t z = (cc[2] + n + (uint32_t)(o / 9) - 1u) % n;
+                nc = x + n * (y + n * z);
+                cnt = (int)cntb[nc];
+            }
+            S.seg_cell[lane] = nc;
         }
-        S.seg_cell[tid] = nc;
-        S.pre[tid + 1] = (int32_t)cnt;
+        int incl = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int v = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += v;
+        }
+        if (lane < 52) S.pre[lane + 1] = incl;
+        if (lane == 0) S.pre[0] = 0;
     }
     if (tid < 6) { S.att[tid] = 0; S.acc[tid] = 0; }
     if (tid < 4) S.dtot[tid] = 0;
-    __syncthreads();
-    if (tid == 0) {
-        S.pre[0] = 0;
-        for (int q = 0; q < 52; ++q) S.pre[q + 1] += S.pre[q];
-    }
-    for (int i = tid; i < n_own[0]; i += PHASE_THREADS) own0[i] = recb[(size_t)cellv[0] * cap + i];
-    for (int i = tid; i < n_own[1]; i += PHASE_THREADS) own1[i] = recb[(size_t)cellv[1] * cap + i];
+    for (int i = tid; i < n0; i += PHASE_THREADS) own0[i] = recb[(size_t)cell0 * cap + i];
+    for (int i = tid; i < n1; i += PHASE_THREADS) own1[i] = recb[(size_t)cell1 * cap + i];
     __syncthreads();
     const int nb_total = S.pre[52];
     const bool staged = room0 + room1 + nb_total <= a.budget;
     if (staged) {
         for (int g = tid; g < nb_total; g += PHASE_THREADS) {
-            int lo = 0, hi = 52; // pre[lo] <= g < pre[hi]
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (S.pre[mid] <= g) lo = mid; else hi = mid;
-            }
-            nb[g] = recb[(size_t)S.seg_cell[lo] * cap + (uint32_t)(g - S.pre[lo])];
+            const int q = segment_of(S, g);
+            nb[g] = recb[(size_t)S.seg_cell[q] * cap + (uint32_t)(g - S.pre[q])];
         }
     } else if (tid == 0) {
         atomicOr(a.err, INFO_UNSTAGED);
     }
+    const int nbb0 = 0, nbc0 = S.pre[26];
+    const int nbb1 = S.pre[26], nbc1 = S.pre[52] - S.pre[26];
     __syncthreads();
-    const int nb_begin[2] = {S.pre[0], S.pre[26]};
-    const int nb_count[2] = {S.pre[26] - S.pre[0], S.pre[52] - S.pre[26]};
 
-    // ---- static move set and counts of the domain ---------------------------
-    int m0a = domain_count(own0, n_own[0], own1, n_own[1], KIND_ACID, 0);
-    int mca = domain_count(own0, n_own[0], own1, n_own[1], KIND_ACID, 1);
-    int m0b = domain_count(own0, n_own[0], own1, n_own[1], KIND_BASE, 0);
-    int mcb = domain_count(own0, n_own[0], own1, n_own[1], KIND_BASE, 1);
-    int npos = domain_count(own0, n_own[0], own1, n_own[1], KIND_XPOS, 1);
-    int nneg = domain_count(own0, n_own[0], own1, n_own[1], KIND_XNEG, 1);
-    int react[3], nreact = 0;
-    if (m0a + mca > 0) react[nreact++] = 0;
-    if (m0b + mcb > 0) react[nreact++] = 1;
-    react[nreact++] = 2;
-
-    // insertion regions and volume terms of the members
-    uint32_t on[3];
-    grid_shift(R, s, a.fixed_grid, on);
-    uint32_t ins_base[2][3], ins_w[2][3];
-    double lnZ[2];
-    for (int j = 0; j < ncell; ++j) {
-        double lnV = 0.0;
-        for (int dd = 0; dd < 3; ++dd) {
-            const uint64_t lo = cell_lo(cc[j][dd], n), hi = cell_lo(cc[j][dd] + 1u, n);
-            ins_base[j][dd] = on[dd] + (uint32_t)lo;
-            ins_w[j][dd] = (uint32_t)(hi - lo);
-            lnV += log((double)(hi - lo));
+    // ---- counts of the domain, one pass -------------------------------------
+    int m0a = 0, mca = 0, m0b = 0, mcb = 0, npos = 0, nneg = 0;
+    {
+        const int total = n0 + n1;
+        for (int b = 0; b < total; b += 64) {
+            const int g = b + lane;
+            uint32_t m = 0;
+            if (g < total) m = g < n0 ? own0[g].w : own1[g - n0].w;
+            const int kd = g < total ? rec_kind(m) : 0, ch = rec_charged(m);
+            m0a += __popcll(__ballot(kd == (int)KIND_ACID && !ch));
+            mca += __popcll(__ballot(kd == (int)KIND_ACID && ch));
+            m0b += __popcll(__ballot(kd == (int)KIND_BASE && !ch));
+            mcb += __popcll(__ballot(kd == (int)KIND_BASE && ch));
+            npos += __popcll(__ballot(kd == (int)KIND_XPOS));
+            nneg += __popcll(__ballot(kd == (int)KIND_XNEG));
         }
-        lnZ[j] = (R.lnZ0 + log((double)ncell)) + lnV;
     }
+    // trials of this domain: the state-independent schedule
+    const int ntr = a.trials * ncell + ((m0a + mca + m0b + mcb) * a.site_trials + 15) / 16;
+    int react0 = 2, react1 = 2;
+    int nreact = 1;
+    {
+        const bool ha = m0a + mca > 0, hb = m0b + mcb > 0;
+        if (ha && hb) { react0 = 0; react1 = 1; nreact = 3; }
+        else if (ha) { react0 = 0; nreact = 2; }
+        else if (hb) { react0 = 1; nreact = 2; }
+    }
+
+    // insertion regions and volume terms of the members (tables built on the host)
+    const uint32_t o0 = R.tab->o[0], o1 = R.tab->o[1], o2 = R.tab->o[2];
+    const uint32_t* bnd = R.bnd;
+    const double lnk = ncell == 2 ? a.ln2 : 0.0;
+    uint32_t ib0[3], iw0[3], ib1[3], iw1[3];
+    {
+        const uint32_t oo[3] = {o0, o1, o2};
+#pragma unroll
+        for (int dd = 0; dd < 3; ++dd) {
+            const uint32_t l0 = bnd[cc0[dd]], h0 = bnd[cc0[dd] + 1];
+            const uint32_t l1 = bnd[cc1[dd]], h1 = bnd[cc1[dd] + 1];
+            ib0[dd] = oo[dd] + l0; iw0[dd] = h0 - l0;
+            ib1[dd] = oo[dd] + l1; iw1[dd] = h1 - l1;
+        }
+    }
+    const double lnZm0 = (R.lnZ0 + lnk) + ((R.lnW[cc0[0]] + R.lnW[cc0[1]]) + R.lnW[cc0[2]]);
+    const double lnZm1 = (R.lnZ0 + lnk) + ((R.lnW[cc1[0]] + R.lnW[cc1[1]]) + R.lnW[cc1[2]]);
+    const double* __restrict__ LN = a.lntab;
 
     PairParams P;
     P.scale_f = (float)R.scale;
     P.scale_d = R.scale;
     P.R2 = R.R2;
+    P.rc2_lo = (double)R.R2 * R.scale * R.scale * (1.0 - 1e-5);
+    P.rc2_hi = (double)R.R2 * R.scale * R.scale * (1.0 + 1e-5);
     P.lB = a.lB;
     P.kappa = R.kappa;
     P.eps = a.eps;
     P.ion_coupling = a.ion_coupling;
     const bool ev_on = a.eps > 0.0 && a.ion_coupling;
+    const double lnKA = R.lnKA, lnKB = R.lnKB, lnKion = R.lnKion;
+    const uint32_t ncores = R.ncores;
 
     double dE = 0.0;
     for (int t = 0; t < ntr; ++t) {
         // 20 Philox words: lane b of every wavefront computes block b
         uint32_t wl[4];
-        philox4x32_10((uint32_t)s, cellv[0], (uint32_t)t * 8u + (uint32_t)(lane < 5 ? lane : 0), TAG_TRIAL,
+        philox4x32_10((uint32_t)s, cell0, (uint32_t)t * 8u + (uint32_t)(lane < 5 ? lane : 0), TAG_TRIAL,
                       R.key0, R.key1, wl);
         uint32_t W[20];
 #pragma unroll
         for (int i = 0; i < 20; ++i) W[i] = (uint32_t)__builtin_amdgcn_readlane((int)wl[i & 3], i >> 2);
 
         const uint32_t kk = pick32(W[0], (uint32_t)(2 * nreact));
-        const int move = 2 * react[kk >> 1] + (int)(kk & 1u);
-        int auto_reject = 0, site = -1, del_pos = -1, del_neg = -1, ins_pos = 0, ins_neg = 0;
+        const int rsel = (int)(kk >> 1);
+        const int reaction = rsel == 0 ? react0 : (rsel == 1 ? react1 : 2);
+        const int move = 2 * reaction + (int)(kk & 1u);
+        const double u = unit53(W[16], W[17]);
+
+        // participants: A is the site (moves 0-3) or the cation (4, 5); B is the ion
+        int a_idx = -1, b_idx = -1; // domain-order indices of existing participants
+        bool auto_reject = false;
         double lnp_counts = 0.0;
-        const uint4* o0 = own0;
-        const uint4* o1 = own1;
-        const int n0 = n_own[0], n1 = n_own[1];
         switch (move) {
         case 0:
-            if (m0a == 0) { auto_reject = 1; break; }
-            site = domain_kth(o0, n0, o1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && !rec_charged(m); },
-                              (int)pick32(W[1], (uint32_t)m0a));
-            ins_pos = 1;
-            lnp_counts = log((double)m0a) - log((double)(mca + 1)) - log((double)(npos + 1)) + R.lnKA;
+            if (m0a == 0) { auto_reject = true; break; }
+            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && !rec_charged(m); },
+                               (int)pick32(W[1], (uint32_t)m0a));
+            lnp_counts = LN[m0a] - LN[mca + 1] - LN[npos + 1] + lnKA;
             break;
         case 1:
-            if (mca == 0 || npos == 0) { auto_reject = 1; break; }
-            site = domain_kth(o0, n0, o1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && rec_charged(m); },
-                              (int)pick32(W[1], (uint32_t)mca));
-            del_pos = domain_kth(o0, n0, o1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
-                                 (int)pick32(W[2], (uint32_t)npos));
-            lnp_counts = log((double)mca) + log((double)npos) - log((double)(m0a + 1)) - R.lnKA;
+            if (mca == 0 || npos == 0) { auto_reject = true; break; }
+            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && rec_charged(m); },
+                               (int)pick32(W[1], (uint32_t)mca));
+            b_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
+                               (int)pick32(W[2], (uint32_t)npos));
+            lnp_counts = LN[mca] + LN[npos] - LN[m0a + 1] - lnKA;
             break;
         case 2:
-            if (m0b == 0) { auto_reject = 1; break; }
-            site = domain_kth(o0, n0, o1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && !rec_charged(m); },
-                              (int)pick32(W[1], (uint32_t)m0b));
-            ins_neg = 1;
-            lnp_counts = log((double)m0b) - log((double)(mcb + 1)) - log((double)(nneg + 1)) + R.lnKB;
+            if (m0b == 0) { auto_reject = true; break; }
+            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && !rec_charged(m); },
+                               (int)pick32(W[1], (uint32_t)m0b));
+            lnp_counts = LN[m0b] - LN[mcb + 1] - LN[nneg + 1] + lnKB;
             break;
         case 3:
-            if (mcb == 0 || nneg == 0) { auto_reject = 1; break; }
-            site = domain_kth(o0, n0, o1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && rec_charged(m); },
-                              (int)pick32(W[1], (uint32_t)mcb));
-            del_neg = domain_kth(o0, n0, o1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
-                                 (int)pick32(W[3], (uint32_t)nneg));
-            lnp_counts = log((double)mcb) + log((double)nneg) - log((double)(m0b + 1)) - R.lnKB;
+            if (mcb == 0 || nneg == 0) { auto_reject = true; break; }
+            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && rec_charged(m); },
+                               (int)pick32(W[1], (uint32_t)mcb));
+            b_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
+                               (int)pick32(W[3], (uint32_t)nneg));
+            lnp_counts = LN[mcb] + LN[nneg] - LN[m0b + 1] - lnKB;
             break;
         case 4:
-            ins_pos = ins_neg = 1;
-            lnp_counts = -log((double)(npos + 1)) - log((double)(nneg + 1)) + R.lnKion;
+            lnp_counts = -LN[npos + 1] - LN[nneg + 1] + lnKion;
             break;
         default:
-            if (npos == 0 || nneg == 0) { auto_reject = 1; break; }
-            del_pos = domain_kth(o0, n0, o1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
-                                 (int)pick32(W[2], (uint32_t)npos));
-            del_neg = domain_kth(o0, n0, o1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
-                                 (int)pick32(W[3], (uint32_t)nneg));
-            lnp_counts = log((double)npos) + log((double)nneg) - R.lnKion;
+            if (npos == 0 || nneg == 0) { auto_reject = true; break; }
+            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
+                               (int)pick32(W[2], (uint32_t)npos));
+            b_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
+                               (int)pick32(W[3], (uint32_t)nneg));
+            lnp_counts = LN[npos] + LN[nneg] - lnKion;
             break;
         }
-        const double u = unit53(W[16], W[17]);
         if (tid == 0) S.att[move] += 1u;
         if (auto_reject) {
             if (tid == 0 && a.log) {
                 const unsigned long long li = atomicAdd(a.log_n, 1ull);
                 if (li < a.log_cap) {
                     TrialRec& L = a.log[li];
-                    L.sweep = (int64_t)s; L.cell = cellv[0]; L.trial = t; L.replica = (int32_t)r;
+                    L.sweep = (int64_t)s; L.cell = cell0; L.trial = t; L.replica = (int32_t)r;
                     L.move = move; L.status = 2;
                     L.dU = __longlong_as_double(0x7FF8000000000000ll); L.lnp = L.dU; L.u = u;
                 }
@@ -551,191 +610,192 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
             continue;
         }
 
-        // ---- changed particles --------------------------------------------
-        Chg ch[2];
-        int nch = 0;
+        // ---- the two changed particles -------------------------------------
+        Chg A, B;
         double lnvol = 0.0;
-        int ins_into[2] = {0, 0}, del_from[2] = {0, 0};
-        if (site >= 0) {
-            Chg& c = ch[nch++];
-            c.member = site < n0 ? 0 : 1;
-            c.own = site < n0 ? site : site - n0;
-            const uint4 rc = (c.member ? o1 : o0)[c.own];
-            c.x = rc.x; c.y = rc.y; c.z = rc.z;
-            const int kind = rec_kind(rc.w), chg = rec_charged(rc.w);
-            c.q_old = kind == (int)KIND_ACID ? -chg : chg;
-            c.q_new = kind == (int)KIND_ACID ? -(1 - chg) : (1 - chg);
-            c.dq = c.q_new - c.q_old;
-            c.dw = 0; c.ion = 0; c.pres_old = 1; c.pres_new = 1;
+        if (move <= 3) {
+            // A: the site flips
+            A.member = a_idx < n0 ? 0 : 1;
+            A.own = a_idx < n0 ? a_idx : a_idx - n0;
+            const uint4 rc = (A.member ? own1 : own0)[A.own];
+            A.x = rc.x; A.y = rc.y; A.z = rc.z;
+            const int chg = rec_charged(rc.w);
+            const int sgn = rec_kind(rc.w) == (int)KIND_ACID ? -1 : 1;
+            A.q_old = sgn * chg; A.q_new = sgn * (1 - chg);
+            A.dq = A.q_new - A.q_old; A.dw = 0; A.ion = 0; A.pres_old = 1; A.pres_new = 1;
         }
-        if (del_pos >= 0 || del_neg >= 0) {
-            const int dels[2] = {del_pos, del_neg};
-            for (int i = 0; i < 2; ++i) {
-                if (dels[i] < 0) continue;
-                Chg& c = ch[nch++];
-                c.member = dels[i] < n0 ? 0 : 1;
-                c.own = dels[i] < n0 ? dels[i] : dels[i] - n0;
-                const uint4 rc = (c.member ? o1 : o0)[c.own];
-                c.x = rc.x; c.y = rc.y; c.z = rc.z;
-                c.q_old = i == 0 ? 1 : -1; c.q_new = 0;
-                c.ion = 1; c.pres_old = 1; c.pres_new = 0;
-                c.dq = a.ion_coupling ? -c.q_old : 0;
-                c.dw = ev_on ? -1 : 0;
-                lnvol -= lnZ[c.member];
-                del_from[c.member]++;
-            }
-        }
-        if (ins_pos || ins_neg) {
-            const int ins[2] = {ins_pos, ins_neg};
-            for (int i = 0; i < 2; ++i) {
-                if (!ins[i]) continue;
-                Chg& c = ch[nch++];
-                const uint32_t wc = i == 0 ? W[18] : W[19];
-                const uint32_t* ws = i == 0 ? &W[4] : &W[10];
+        const bool insertion = move == 0 || move == 2 || move == 4;
+        // B (and A for salt moves): ions in or out
+        {
+            const int qB = (move <= 1) ? 1 : -1; // cation for acid moves, anion otherwise
+            B.ion = 1;
+            B.q_old = insertion ? 0 : qB;
+            B.q_new = insertion ? qB : 0;
+            B.pres_old = insertion ? 0 : 1;
+            B.pres_new = insertion ? 1 : 0;
+            B.dq = a.ion_coupling ? B.q_new - B.q_old : 0;
+            B.dw = ev_on ? (insertion ? 1 : -1) : 0;
+            if (insertion) {
+                const uint32_t wc = qB > 0 ? W[18] : W[19];
+                const int wo = qB > 0 ? 4 : 10;
                 const int j = ncell == 1 ? 0 : (int)pick32(wc, (uint32_t)ncell);
-                c.member = j;
-                c.own = -1;
-                c.x = ins_base[j][0] + pick64(ws[0], ws[1], ins_w[j][0]);
-                c.y = ins_base[j][1] + pick64(ws[2], ws[3], ins_w[j][1]);
-                c.z = ins_base[j][2] + pick64(ws[4], ws[5], ins_w[j][2]);
-                c.q_old = 0; c.q_new = i == 0 ? 1 : -1;
-                c.ion = 1; c.pres_old = 0; c.pres_new = 1;
-                c.dq = a.ion_coupling ? c.q_new : 0;
-                c.dw = ev_on ? 1 : 0;
-                lnvol += lnZ[j];
-                ins_into[j]++;
+                B.member = j;
+                B.own = -1;
+                const uint32_t* ibj = j ? ib1 : ib0;
+                const uint32_t* iwj = j ? iw1 : iw0;
+                B.x = ibj[0] + pick64(W[wo + 0], W[wo + 1], iwj[0]);
+                B.y = ibj[1] + pick64(W[wo + 2], W[wo + 3], iwj[1]);
+                B.z = ibj[2] + pick64(W[wo + 4], W[wo + 5], iwj[2]);
+                lnvol += j ? lnZm1 : lnZm0;
+            } else {
+                B.member = b_idx < n0 ? 0 : 1;
+                B.own = b_idx < n0 ? b_idx : b_idx - n0;
+                const uint4 rc = (B.member ? own1 : own0)[B.own];
+                B.x = rc.x; B.y = rc.y; B.z = rc.z;
+                lnvol -= B.member ? lnZm1 : lnZm0;
             }
         }
-        bool cap_fail = false;
-        for (int j = 0; j < ncell; ++j)
-            if (n_own[j] - del_from[j] + ins_into[j] > (int)cap) cap_fail = true;
+        if (move >= 4) {
+            A.ion = 1;
+            A.q_old = insertion ? 0 : 1;
+            A.q_new = insertion ? 1 : 0;
+            A.pres_old = insertion ? 0 : 1;
+            A.pres_new = insertion ? 1 : 0;
+            A.dq = a.ion_coupling ? A.q_new - A.q_old : 0;
+            A.dw = ev_on ? (insertion ? 1 : -1) : 0;
+            if (insertion) {
+                const int j = ncell == 1 ? 0 : (int)pick32(W[18], (uint32_t)ncell);
+                A.member = j;
+                A.own = -1;
+                const uint32_t* ibj = j ? ib1 : ib0;
+                const uint32_t* iwj = j ? iw1 : iw0;
+                A.x = ibj[0] + pick64(W[4], W[5], iwj[0]);
+                A.y = ibj[1] + pick64(W[6], W[7], iwj[1]);
+                A.z = ibj[2] + pick64(W[8], W[9], iwj[2]);
+                lnvol += j ? lnZm1 : lnZm0;
+            } else {
+                A.member = a_idx < n0 ? 0 : 1;
+                A.own = a_idx < n0 ? a_idx : a_idx - n0;
+                const uint4 rc = (A.member ? own1 : own0)[A.own];
+                A.x = rc.x; A.y = rc.y; A.z = rc.z;
+                lnvol -= A.member ? lnZm1 : lnZm0;
+            }
+        }
+        // per-member growth check against the cell capacity
+        const int gA = A.pres_new - A.pres_old, gB = B.pres_new - B.pres_old;
+        const int grow0 = (A.member == 0 ? gA : 0) + (B.member == 0 ? gB : 0);
+        const int grow1 = (A.member == 1 ? gA : 0) + (B.member == 1 ? gB : 0);
+        const bool cap_fail = n0 + grow0 > (int)cap || n1 + grow1 > (int)cap;
 
         // ---- energy change: every wavefront sums a share of the records ------
         double acc = 0.0;
         int ov = 0;
         for (int j = 0; j < ncell; ++j) {
-            int idx[2], m = 0;
-            for (int i = 0; i < nch; ++i)
-                if (ch[i].member == j) idx[m++] = i;
-            if (m == 0) continue;
-            const uint4* own = j ? o1 : o0;
-            const int no = n_own[j];
-            const int skip0 = ch[idx[0]].own, skip1 = m > 1 ? ch[idx[1]].own : -1;
-            const int total = no + nb_count[j];
+            const bool inA = A.member == j, inB = B.member == j;
+            if (!inA && !inB) continue;
+            const uint4* own = j ? own1 : own0;
+            const int no = j ? n1 : n0;
+            const int skipA = inA ? A.own : -1, skipB = inB ? B.own : -1;
+            const int nbb = j ? nbb1 : nbb0, nbc = j ? nbc1 : nbc0;
+            const int total = no + nbc;
             for (int g = tid; g < total; g += PHASE_THREADS) {
                 uint4 rc;
                 if (g < no) {
-                    if (g == skip0 || g == skip1) continue;
+                    if (g == skipA || g == skipB) continue;
                     rc = own[g];
                 } else {
-                    const int q = nb_begin[j] + (g - no);
+                    const int q = nbb + (g - no);
                     rc = staged ? nb[q] : neighbour_global(S, recb, cap, q);
                 }
-                acc += pair_term<Real>(rc, ch[idx[0]], P, ov);
-                if (m > 1) acc += pair_term<Real>(rc, ch[idx[1]], P, ov);
+                if (inA) acc += pair_term<Real>(rc, A, P, ov);
+                if (inB) acc += pair_term<Real>(rc, B, P, ov);
             }
         }
-        if (ev_on && R.ncores) {
-            for (int k = tid; k < (int)R.ncores; k += PHASE_THREADS) {
+        if (ev_on && ncores) {
+            for (int k = tid; k < (int)ncores; k += PHASE_THREADS) {
                 const uint4 cx = R.core_x[k];
                 const double dl = R.core_delta[k];
-                for (int i = 0; i < nch; ++i)
-                    if (ch[i].dw != 0) acc += wca_core<Real>(ch[i], cx, dl, P, ov);
+                if (A.dw != 0) acc += wca_core<Real>(A, cx, dl, P, ov);
+                if (B.dw != 0) acc += wca_core<Real>(B, cx, dl, P, ov);
             }
         }
-        if (tid == 0 && nch == 2 && (a.ion_coupling || (!ch[0].ion && !ch[1].ion))) {
-            // the pair formed or broken between the two changed particles
-            const int32_t dx = (int32_t)(ch[1].x - ch[0].x), dy = (int32_t)(ch[1].y - ch[0].y),
-                          dz = (int32_t)(ch[1].z - ch[0].z);
-            const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
-            const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
-            const Real sc = sizeof(Real) == 4 ? (Real)P.scale_f : (Real)P.scale_d;
-            const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
-            const Real r2 = fx * fx + fy * fy + fz * fz;
-            const int dqq = ch[0].q_new * ch[1].q_new - ch[0].q_old * ch[1].q_old;
-            if (dqq != 0 && r2i < P.R2) {
-                const Real rinv = Math<Real>::rsqrt(r2);
-                acc += P.lB * (double)dqq * (double)(Math<Real>::ex(-(Real)P.kappa * r2 * rinv) * rinv);
-            }
-            const int any_ion = ch[0].ion || ch[1].ion;
-            const int pn = ev_on && any_ion && ch[0].pres_new && ch[1].pres_new;
-            const int po = ev_on && any_ion && ch[0].pres_old && ch[1].pres_old;
-            if ((pn || po) && r2 < (Real)1.2599210498948731647672106) {
-                if (r2 < (Real)0.25) {
-                    if (pn) ov = 1;
-                } else {
-                    const Real ir2 = Math<Real>::rcp(r2);
-                    const Real ir6 = ir2 * ir2 * ir2;
-                    acc += (double)(pn - po) * (double)((Real)4.0 * (Real)P.eps * (ir6 * ir6 - ir6) + (Real)P.eps);
-                }
-            }
-        }
+        if (tid == 0) acc += changed_pair<Real>(A, B, P, ev_on, ov);
         const double wsum = wave_sum(acc);
         const int wov = __ballot(ov) != 0ull;
         const int par = t & 1;
         if (lane == 0) { S.red[par][wave] = wsum; S.ovf[par][wave] = wov; }
         __syncthreads();
         double dU = ((S.red[par][0] + S.red[par][1]) + S.red[par][2]) + S.red[par][3];
-        if (S.ovf[par][0] | S.ovf[par][1] | S.ovf[par][2] | S.ovf[par][3]) dU = __longlong_as_double(0x7FF0000000000000ll);
+        if (S.ovf[par][0] | S.ovf[par][1] | S.ovf[par][2] | S.ovf[par][3])
+            dU = __longlong_as_double(0x7FF0000000000000ll);
         const double lnp = lnp_counts + lnvol - dU;
         const bool accept = !cap_fail && u < exp(lnp < 0.0 ? lnp : 0.0);
-        if (cap_fail && tid == 0) atomicOr(a.err, ERR_INSERT_CAPACITY);
-        if (tid == 0 && a.log) {
-            const unsigned long long li = atomicAdd(a.log_n, 1ull);
-            if (li < a.log_cap) {
-                TrialRec& L = a.log[li];
-                L.sweep = (int64_t)s; L.cell = cellv[0]; L.trial = t; L.replica = (int32_t)r;
-                L.move = move; L.status = accept ? 1 : 0;
-                L.dU = dU; L.lnp = lnp; L.u = u;
+        if (tid == 0) {
+            if (cap_fail) atomicOr(a.err, ERR_INSERT_CAPACITY);
+            if (a.log) {
+                const unsigned long long li = atomicAdd(a.log_n, 1ull);
+                if (li < a.log_cap) {
+                    TrialRec& L = a.log[li];
+                    L.sweep = (int64_t)s; L.cell = cell0; L.trial = t; L.replica = (int32_t)r;
+                    L.move = move; L.status = accept ? 1 : 0;
+                    L.dU = dU; L.lnp = lnp; L.u = u;
+                }
             }
         }
         if (!accept) continue;
 
-        // ---- commit --------------------------------------------------------
+        // ---- commit: flip; deletions (higher index first within one cell);
+        //      insertions appended, cation before anion -----------------------
         if (tid == 0) {
             S.acc[move] += 1u;
             dE += dU;
-            uint4* ownv[2] = {own0, own1};
-            if (site >= 0) {
-                uint4& rc = ownv[ch[0].member][ch[0].own];
+            if (move <= 3) {
+                uint4& rc = (A.member ? own1 : own0)[A.own];
                 rc.w ^= 8u;
-                const uint32_t sid = rc.w >> 8;
                 const int now = rec_charged(rc.w);
-                const int g = R.site_group[sid];
-                atomicAdd(&R.group_ionized[g], now ? 1 : -1);
-                if (rec_kind(rc.w) == (int)KIND_ACID) S.dtot[0] += now ? 1 : -1;
-                else S.dtot[1] += now ? 1 : -1;
+                atomicAdd(&R.group_ionized[R.site_group[rc.w >> 8]], now ? 1 : -1);
+                S.dtot[move <= 1 ? 0 : 1] += now ? 1 : -1;
             }
-            // deletions: in one cell, the higher index first
-            int dm[2], di[2], nd = 0;
-            for (int i = 0; i < nch; ++i)
-                if (ch[i].pres_old && !ch[i].pres_new) { dm[nd] = ch[i].member; di[nd] = ch[i].own; ++nd; }
-            if (nd == 2 && dm[0] == dm[1] && di[1] > di[0]) {
-                int t0 = di[0]; di[0] = di[1]; di[1] = t0;
-            }
-            for (int i = 0; i < nd; ++i) {
-                uint4* L = ownv[dm[i]];
-                int& cnt = n_own[dm[i]];
-                L[di[i]] = L[cnt - 1];
-                --cnt;
-            }
-            for (int i = 0; i < nch; ++i)
-                if (!ch[i].pres_old && ch[i].pres_new) {
-                    uint4* L = ownv[ch[i].member];
-                    L[n_own[ch[i].member]++] = make_uint4(ch[i].x, ch[i].y, ch[i].z,
-                                                          make_meta(ch[i].q_new > 0 ? KIND_XPOS : KIND_XNEG, 1u, NO_SITE));
+            int l0 = n0, l1 = n1;
+            if (!insertion) {
+                // deleted: B always; A too for the salt move
+                int dm0 = B.member, di0 = B.own, dm1 = -1, di1 = -1;
+                if (move == 5) {
+                    // the cation (A) first unless the anion sits higher in the same cell
+                    dm0 = A.member; di0 = A.own; dm1 = B.member; di1 = B.own;
+                    if (dm0 == dm1 && di1 > di0) {
+                        int t0 = di0; di0 = di1; di1 = t0;
+                    }
                 }
-            if (ins_pos) S.dtot[2] += 1;
-            if (ins_neg) S.dtot[3] += 1;
-            if (del_pos >= 0) S.dtot[2] -= 1;
-            if (del_neg >= 0) S.dtot[3] -= 1;
-        } else {
-            // the same count bookkeeping in every thread (registers stay uniform)
-            for (int i = 0; i < nch; ++i) {
-                if (ch[i].pres_old && !ch[i].pres_new) n_own[ch[i].member]--;
-                if (!ch[i].pres_old && ch[i].pres_new) n_own[ch[i].member]++;
+                {
+                    uint4* Lst = dm0 ? own1 : own0;
+                    int& cnt = dm0 ? l1 : l0;
+                    Lst[di0] = Lst[cnt - 1];
+                    --cnt;
+                }
+                if (dm1 >= 0) {
+                    uint4* Lst = dm1 ? own1 : own0;
+                    int& cnt = dm1 ? l1 : l0;
+                    Lst[di1] = Lst[cnt - 1];
+                    --cnt;
+                }
+            } else {
+                if (move == 4) {
+                    uint4* Lst = A.member ? own1 : own0;
+                    int& cnt = A.member ? l1 : l0;
+                    Lst[cnt++] = make_uint4(A.x, A.y, A.z, make_meta(KIND_XPOS, 1u, NO_SITE));
+                }
+                uint4* Lst = B.member ? own1 : own0;
+                int& cnt = B.member ? l1 : l0;
+                Lst[cnt++] = make_uint4(B.x, B.y, B.z, make_meta(B.q_new > 0 ? KIND_XPOS : KIND_XNEG, 1u, NO_SITE));
             }
+            if (move == 0 || move == 4) S.dtot[2] += 1;
+            if (move == 2 || move == 4) S.dtot[3] += 1;
+            if (move == 1 || move == 5) S.dtot[2] -= 1;
+            if (move == 3 || move == 5) S.dtot[3] -= 1;
         }
+        n0 += grow0;
+        n1 += grow1;
         switch (move) {
         case 0: m0a--; mca++; npos++; break;
         case 1: m0a++; mca--; npos--; break;
@@ -749,12 +809,12 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
 
     // ---- write the domain's cells back --------------------------------------
     __syncthreads();
-    for (int i = tid; i < n_own[0]; i += PHASE_THREADS) recb[(size_t)cellv[0] * cap + i] = own0[i];
-    for (int i = tid; i < n_own[1]; i += PHASE_THREADS) recb[(size_t)cellv[1] * cap + i] = own1[i];
+    for (int i = tid; i < n0; i += PHASE_THREADS) recb[(size_t)cell0 * cap + i] = own0[i];
+    for (int i = tid; i < n1; i += PHASE_THREADS) recb[(size_t)cell1 * cap + i] = own1[i];
     if (tid == 0) {
-        cntb[cellv[0]] = (uint32_t)n_own[0];
-        if (ncell == 2) cntb[cellv[1]] = (uint32_t)n_own[1];
-        if (dE != 0.0) R.e_acc[cellv[0]] += dE;
+        cntb[cell0] = (uint32_t)n0;
+        if (ncell == 2) cntb[cell1] = (uint32_t)n1;
+        if (dE != 0.0) R.e_acc[cell0] += dE;
         for (int i = 0; i < 6; ++i) {
             if (S.att[i]) atomicAdd((unsigned long long*)&R.moves[i], (unsigned long long)S.att[i]);
             if (S.acc[i]) atomicAdd((unsigned long long*)&R.moves[6 + i], (unsigned long long)S.acc[i]);
@@ -767,7 +827,7 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
 // ------------------------------------------------------------------------
 // k_sweep_end: series row, group histograms, advance the sweep counter
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a, int64_t series_first)
+__global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a)
 {
     const uint64_t s = *a.sweep;
     for (uint32_t r = 0; r < a.nrep; ++r) {
@@ -779,7 +839,6 @@ __global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a, int64_t series_f
         for (uint32_t g = threadIdx.x; g < R.ngroups; g += blockDim.x)
             R.group_hist[R.group_hist_off[g] + R.group_ionized[g]] += 1;
     }
-    (void)series_first;
     __syncthreads();
     if (threadIdx.x == 0) *a.sweep = s + 1u;
 }
@@ -865,15 +924,10 @@ __global__ void k_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k
 // ------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------
-size_t phase_lds_bytes(uint32_t max_cap, int budget)
-{
-    (void)max_cap; // the pool holds the domain's cells and, when they fit, its neighbours
-    return (size_t)budget * sizeof(uint4);
-}
-
 hipError_t launch_bin(const SweepArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bin, dim3(a.ncell_total), dim3(BIN_THREADS), 0, s, a);
+    const uint32_t per = BIN_THREADS / 64;
+    hipLaunchKernelGGL(k_bin, dim3((a.ncell_total + per - 1) / per), dim3(BIN_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
@@ -886,9 +940,9 @@ hipError_t launch_phase(const SweepArgs& a, size_t lds, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sweep_end(const SweepArgs& a, int64_t series_first, hipStream_t s)
+hipError_t launch_sweep_end(const SweepArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, s, a, series_first);
+    hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -908,9 +962,6 @@ hipError_t launch_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k
     return hipGetLastError();
 }
 
-} // namespace crmc
-
-namespace crmc {
 hipError_t set_phase_lds_limit(size_t bytes)
 {
     hipError_t e = hipFuncSetAttribute((const void*)k_phase<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -918,4 +969,5 @@ hipError_t set_phase_lds_limit(size_t bytes)
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)k_phase<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
+
 } // namespace crmc

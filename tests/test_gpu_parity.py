@@ -59,21 +59,23 @@ CASES = {
 }
 
 
-def _oracle_for(s, model, cond, n_cells, trials, pairing, seed, replica=0, fixed_grid=False):
+def _oracle_for(s, model, cond, n_cells, trials, pairing, seed, replica=0, fixed_grid=False, site_trials=0):
     o = oracle.Oracle(s["L"], n_cells, model["lB"], cond["kappa"], model["rc"], eps=model["eps"],
                       ion_coupling=model["ion_coupling"], seed=seed, replica=replica)
     o.set_conditions(cond["pH"], cond["pKa"], cond["pKb"], cond["pIX_pos"], cond["pIX_neg"])
     o.set_particles(s["xyz"], s["kind"], charged=s.get("charged"))
     if len(s.get("core_R", [])):
         o.set_cores(s["core_xyz"], s["core_R"])
-    o.set_schedule(trials, fixed_grid=fixed_grid, pairing=pairing)
+    o.set_schedule(trials, fixed_grid=fixed_grid, pairing=pairing, site_trials=site_trials)
     return o
 
 
-def _gpu_system(crmc, s, model, n_rep, precision, trials, pairing, seed, lds_records=0, fixed_grid=False):
+def _gpu_system(crmc, s, model, n_rep, precision, trials, pairing, seed, lds_records=0, fixed_grid=False,
+                site_trials=0):
     S = crmc.System(n_replicas=n_rep, lB=model["lB"], rc=model["rc"], eps=model["eps"],
                     ion_coupling=model["ion_coupling"], precision=precision, trials_per_cell=trials,
-                    pairing=pairing, seed=seed, lds_records=lds_records, fixed_grid=fixed_grid)
+                    pairing=pairing, seed=seed, lds_records=lds_records, fixed_grid=fixed_grid,
+                    site_trials=site_trials)
     for r in range(n_rep):
         kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"], charged=s.get("charged"), group=s.get("group"))
         if len(s.get("core_R", [])):
@@ -91,17 +93,17 @@ def _same_state(gpu_particles, orc_particles):
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
-@pytest.mark.parametrize("trials,pairing", [(1, True), (2, True), (1, False)])
-def test_fp64_bit_exact(case, trials, pairing):
+@pytest.mark.parametrize("trials,pairing,site_trials", [(1, True, 0), (2, True, 0), (1, False, 0), (1, True, 12)])
+def test_fp64_bit_exact(case, trials, pairing, site_trials):
     crmc = _gpu()
     make, model, cond = CASES[case]
     s = make()
     nsw = 12
-    S = _gpu_system(crmc, s, model, 1, 64, trials, pairing, seed=77)
+    S = _gpu_system(crmc, s, model, 1, 64, trials, pairing, seed=77, site_trials=site_trials)
     S.sweep_ex([cond], nsw)
     obs = S.observe(0)
     assert obs["status"] == 0 and obs["error_flags"] & 3 == 0
-    o = _oracle_for(s, model, cond, obs["n_cells"], trials, pairing, seed=77)
+    o = _oracle_for(s, model, cond, obs["n_cells"], trials, pairing, seed=77, site_trials=site_trials)
     ser = o.sweeps(nsw)
     _same_state(S.particles(0), o.particles())
     assert np.array_equal(S.series(0, 0, nsw), ser)

@@ -334,3 +334,20 @@ def test_ion_just_outside_a_core_has_the_expanded_wca_energy():
     o.set_cores(np.array([[12.0, 12.0, 12.0]]), np.array([3.5]))
     s = 0.75  # r - Delta, up to the fixed-point rounding of the position
     assert o.energy() == pytest.approx(4 * (s ** -12 - s ** -6) + 1, rel=1e-6)
+
+
+def test_site_weighted_schedule_ring_enumeration():
+    """Extra trials in domains that hold sites (a state-independent schedule)
+    keep the exact 2^12 distribution of the ring (T-5)."""
+    L = 24.0
+    s = ring(12, L=L)
+    X = oracle.to_fixed(s["xyz"], L)
+    pIX = cf.pIX_from_salt(1.0, 4.5)
+    P, ex, _ = cf.enumerate_sites(X, [1] * 12, L, 2.0, 0.5, 6.0, 4.5, 4.5, 0.0, pIX, pIX, RHO)
+    o = oracle.Oracle(L, 4, 2.0, 0.5, 6.0, eps=1.0, ion_coupling=0, seed=14)
+    o.set_conditions(4.5, 4.5, 0.0, pIX, pIX)
+    o.set_particles(s["xyz"], s["kind"])
+    o.set_schedule(2, site_trials=24)
+    ser = o.sweeps(3000)
+    _within(ser[:, 0] / 12.0, ex)
+    _hist_within(ser[len(ser) // 10:, 0], P)
