@@ -93,6 +93,11 @@ def main():
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--site-trials", type=int, default=0, help="extra trials per 16 sites of a domain")
     ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per domain in records (0 = default)")
+    ap.add_argument("--phase-threads", type=int, default=256, choices=(64, 128, 256, 512))
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one in the timed region")
+    ap.add_argument("--kernel-steps", type=int, default=400, help="sweeps of the per-kernel event timing pass")
+    ap.add_argument("--light-records", type=int, default=0,
+                    help="LDS pool of the one-wavefront launch for light domains (0: single launch)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -119,26 +124,34 @@ def main():
     R = len(conds)
     S = crmc.System(n_replicas=R, lB=c["lB"], rc=c["rc"], eps=1.0, precision=args.precision,
                     trials_per_cell=args.trials, pairing=True, seed=2024, site_trials=args.site_trials,
-                    lds_records=args.lds_records)
+                    lds_records=args.lds_records, phase_threads=args.phase_threads,
+                    use_graph=not args.no_graph, light_records=args.light_records)
     for r in range(R):
         S.build_cells(r, c)
     S.sweep_ex(conds, args.warmup)
     torch.cuda.synchronize()
     before = [S.observe(r) for r in range(R)]
-    crmc.crmc_set_timing(S.h, True)
 
+    # timed region: exactly --steps sweeps, replayed as captured graphs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.sweep_ex(conds, args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-
-    ms, launches = crmc.crmc_get_timing(S.h)
     after = [S.observe(r) for r in range(R)]
     for o in after:
         if o["status"] != 0:
             raise SystemExit("device error: %s" % o)
     elapsed = t1 - t0
+
+    # kernel durations: the same kernels launched one by one, each bracketed
+    # by HIP events on the library's stream
+    n_kern = min(args.steps, args.kernel_steps)
+    crmc.crmc_set_timing(S.h, True)
+    S.sweep_ex(conds, n_kern)
+    torch.cuda.synchronize()
+    ms, launches = crmc.crmc_get_timing(S.h)
+    crmc.crmc_set_timing(S.h, False)
     trials = sum(sum(a["attempts"]) - sum(b["attempts"]) for a, b in zip(after, before))
     rate = trials / elapsed
 
@@ -171,7 +184,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_phase", "bytes_per_launch": round(bytes_launch),
-                "avg_launch_ms": round(phase_avg_ms, 5)}
+                "avg_launch_ms": round(phase_avg_ms, 5), "timed_launches": int(launches[1])}
 
     line = {
         "metric": METRIC, "value": round(rate, 1), "unit": "trial moves/s", "n_gpus": 1,
@@ -181,6 +194,8 @@ def main():
         "config": {"workload": "nanoparticle pair: 2000 acid + 2000 base sites, R=10, separation 25, "
                                "L=120, ~2e4 ions (pI_X=0.668), lB=2, kappa=0.5, rc=8; 9 replicas pH 3..11",
                    "replicas": R, "trials_per_cell": args.trials, "site_trials_per_16": args.site_trials,
+                   "phase_threads": args.phase_threads, "graph": not args.no_graph,
+                   "light_records": args.light_records,
                    "schedule": "shifted cells, paired domains",
                    "cells_per_edge": after[0]["n_cells"], "cell_capacity": after[0]["cell_capacity"]},
         "independent_samples_per_s": round(samples, 1),

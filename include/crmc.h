@@ -95,6 +95,12 @@ typedef struct {
     int32_t lds_records;     /* neighbour records staged on chip per domain (0 = default) */
     int32_t fixed_grid;      /* 1: never shift the grid (only for tests: not ergodic) */
     int32_t site_trials;     /* extra trials per 16 ionizable sites of a domain (rounded up) */
+    int32_t phase_threads;   /* threads per domain workgroup: 64, 128, 256 or 512 (0 = 256) */
+    int32_t use_graph;       /* 1: replay captured HIP graphs of whole sweeps; 0: launch each kernel */
+    int32_t light_records;   /* >0: domains whose cells, ln table and neighbours fit this many
+                                records of LDS run one wavefront each in a launch of their own,
+                                the rest in the phase_threads launch; 0: one launch for all */
+    int32_t reserved;
     double lB;               /* Bjerrum length (sigma) */
     double rc;               /* Coulomb cutoff (sigma) */
     double eps_wca;          /* excluded-volume strength (kT); 0 disables it */
@@ -211,6 +217,22 @@ int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out);
  */
 int crmc_set_timing(crmc_t h, int32_t on);
 int crmc_get_timing(crmc_t h, double ms[3], int64_t launches[3]);
+
+/*
+ * Per-workgroup trace of the trial-phase kernel (profiling): while capacity >
+ * 0, every domain workgroup appends one record.  The clock is the device's
+ * constant-rate wall clock (100 MHz on MI355X).
+ */
+typedef struct {
+    uint64_t t0, t1;          /* wall clock at the start and end of the workgroup */
+    uint32_t sweep, domain;   /* sweep; domain index over all replicas */
+    int32_t colour, trials;   /* colour of the phase; trials the domain ran */
+    int32_t neighbours, own;  /* neighbour records; records in the domain's cells */
+    int32_t staged, hw_id;    /* neighbours held in LDS; compute unit that ran it */
+} crmc_phase_trace;
+
+int crmc_enable_trace(crmc_t h, int64_t capacity);
+int crmc_read_trace(crmc_t h, int64_t cap, crmc_phase_trace* out, int64_t* n_out);
 
 /* Philox4x32-10 on the device: n counter blocks (ctr n*4 words) with key
    (k0, k1) into out (n*4 words).  For checking the generator. */

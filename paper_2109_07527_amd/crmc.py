@@ -32,6 +32,8 @@ class crmc_params(C.Structure):
     _fields_ = [("n_replicas", C.c_int32), ("precision", C.c_int32), ("trials_per_cell", C.c_int32),
                 ("pairing", C.c_int32), ("ion_coupling", C.c_int32), ("lds_records", C.c_int32),
                 ("fixed_grid", C.c_int32), ("site_trials", C.c_int32),
+                ("phase_threads", C.c_int32), ("use_graph", C.c_int32),
+                ("light_records", C.c_int32), ("reserved", C.c_int32),
                 ("lB", C.c_double), ("rc", C.c_double), ("eps_wca", C.c_double), ("rho0NA", C.c_double),
                 ("pKw", C.c_double), ("kappa", C.c_double), ("pKb", C.c_double),
                 ("seed", C.c_uint64), ("stream", C.c_void_p)]
@@ -87,6 +89,8 @@ def load():
         "crmc_read_log": (C.c_int, [vp, i64, P(crmc_trial_rec), P(i64)]),
         "crmc_philox": (C.c_int, [i64, P(u32), u32, u32, P(u32)]),
         "crmc_set_timing": (C.c_int, [vp, i32]),
+        "crmc_enable_trace": (C.c_int, [vp, i64]),
+        "crmc_read_trace": (C.c_int, [vp, i64, vp, P(i64)]),
         "crmc_get_timing": (C.c_int, [vp, P(d), P(i64)]),
         "crmc_pIX_from_salt": (d, [d, d, d]),
         "crmc_last_error": (C.c_char_p, [vp]),
@@ -247,6 +251,21 @@ def crmc_get_timing(h):
     return ms, n
 
 
+TRACE_DTYPE = np.dtype([("t0", "u8"), ("t1", "u8"), ("sweep", "u4"), ("domain", "u4"), ("colour", "i4"),
+                        ("trials", "i4"), ("neighbours", "i4"), ("own", "i4"), ("staged", "i4"), ("hw_id", "i4")])
+
+
+def crmc_enable_trace(h, capacity):
+    return _check(h, load().crmc_enable_trace(h, int(capacity)))
+
+
+def crmc_read_trace(h, cap):
+    n = C.c_int64(0)
+    buf = np.zeros(max(int(cap), 1), dtype=TRACE_DTYPE)
+    _check(h, load().crmc_read_trace(h, int(cap), C.c_void_p(buf.ctypes.data), C.byref(n)))
+    return buf[:min(n.value, int(cap))], n.value
+
+
 def crmc_pIX_from_salt(pIS, pH, pKw=14.0):
     return load().crmc_pIX_from_salt(float(pIS), float(pH), float(pKw))
 
@@ -274,7 +293,8 @@ class System:
 
     def __init__(self, n_replicas=1, lB=2.0, rc=6.0, eps=1.0, rho0NA=0.0269424, pKw=14.0, kappa=0.5,
                  pKb=5.0, seed=1234, precision=32, trials_per_cell=1, pairing=True, ion_coupling=True,
-                 lds_records=0, fixed_grid=False, site_trials=0, stream="torch"):
+                 lds_records=0, fixed_grid=False, site_trials=0, phase_threads=256, use_graph=True,
+                 light_records=0, stream="torch"):
         p = crmc_params()
         p.n_replicas = int(n_replicas)
         p.precision = int(precision)
@@ -284,6 +304,9 @@ class System:
         p.lds_records = int(lds_records)
         p.fixed_grid = int(bool(fixed_grid))
         p.site_trials = int(site_trials)
+        p.phase_threads = int(phase_threads)
+        p.use_graph = int(bool(use_graph))
+        p.light_records = int(light_records)
         p.lB, p.rc, p.eps_wca, p.rho0NA, p.pKw, p.kappa, p.pKb = lB, rc, eps, rho0NA, pKw, kappa, pKb
         p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         s = current_stream() if stream == "torch" else stream

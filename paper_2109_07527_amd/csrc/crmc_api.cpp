@@ -53,6 +53,9 @@ struct crmc_s {
     TrialRec* d_log = nullptr;
     unsigned long long* d_log_n = nullptr;
     int64_t log_cap = 0;
+    PhaseTrace* d_trace = nullptr;
+    unsigned long long* d_trace_n = nullptr;
+    int64_t trace_cap = 0;
     int64_t sweeps = 0;
     int pool = DEFAULT_POOL;
     bool lds_attr_set = false;
@@ -65,6 +68,11 @@ struct crmc_s {
     std::vector<hipEvent_t> free_events;
     double t_ms[3] = {0, 0, 0};
     int64_t t_n[3] = {0, 0, 0};
+    // captured sweeps: [0] one sweep, [1] GRAPH_SWEEPS sweeps
+    hipStream_t gstream = nullptr;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    uint64_t gkey = 0;
 };
 
 namespace {
@@ -119,8 +127,8 @@ hipError_t dalloc(T** p, size_t count)
 void free_replica(HostReplica& r)
 {
     Replica& d = r.d;
-    void* ptrs[] = {d.rec[0], d.rec[1], d.cnt[0], d.cnt[1], d.e_acc, d.occupancy, d.site_group,
-                    d.group_ionized, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
+    void* ptrs[] = {d.rec[0], d.rec[1], d.cnt[0], d.cnt[1], d.cnt0, d.e_acc, d.occupancy, d.site_group,
+                    d.group_count, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
                     d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -164,6 +172,10 @@ SweepArgs base_args(crmc_t h)
     a.site_trials = h->p.site_trials;
     a.budget = h->pool;
     a.precision = h->p.precision;
+    a.phase_threads = h->p.phase_threads ? h->p.phase_threads : 256;
+    a.trace = h->d_trace;
+    a.trace_n = h->d_trace_n;
+    a.trace_cap = (uint64_t)h->trace_cap;
     return a;
 }
 
@@ -262,6 +274,88 @@ int timed(crmc_t h, int kind, F&& launch)
     return CRMC_OK;
 }
 
+constexpr int GRAPH_SWEEPS = 16;
+
+// one colour phase: a single launch, or a one-wavefront launch for the light
+// domains followed by the phase_threads launch for the rest
+hipError_t enqueue_phase(crmc_t h, SweepArgs a, size_t lds, hipStream_t st)
+{
+    if (h->p.light_records <= 0) {
+        a.cls = 0;
+        return launch_phase(a, lds, st);
+    }
+    SweepArgs l = a;
+    l.cls = 1;
+    l.split = h->p.light_records;
+    l.budget = h->p.light_records;
+    l.phase_threads = 64;
+    hipError_t e = launch_phase(l, (size_t)h->p.light_records * sizeof(uint4), st);
+    if (e != hipSuccess) return e;
+    a.cls = 2;
+    a.split = h->p.light_records;
+    return launch_phase(a, lds, st);
+}
+
+void drop_graphs(crmc_t h)
+{
+    for (auto& g : h->gexec)
+        if (g) { (void)hipGraphExecDestroy(g); g = nullptr; }
+}
+
+// Sweeps as replays of captured graphs (GRAPH_SWEEPS at a time, then single
+// sweeps) on the library's own stream, ordered after and before the caller's
+// stream by events.  The kernels read the sweep counter and the conditions
+// from device memory, so a captured graph stays valid across calls; it is
+// recaptured when anything baked into its launch arguments changes.
+int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n)
+{
+    const uint64_t key = (uint64_t)(uintptr_t)a0.log * 1000003ull ^ (uint64_t)a0.log_cap * 7919ull ^
+                         (uint64_t)lds * 31ull ^ (uint64_t)(uintptr_t)a0.lntab ^
+                         (uint64_t)(uintptr_t)a0.trace * 65537ull ^ (uint64_t)a0.trace_cap * 131ull;
+    if (key != h->gkey) {
+        drop_graphs(h);
+        h->gkey = key;
+    }
+    if (!h->gstream) HIP_TRY(h, hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+    if (!h->ev_in) HIP_TRY(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
+    if (!h->ev_out) HIP_TRY(h, hipEventCreateWithFlags(&h->ev_out, hipEventDisableTiming));
+    const int counts[2] = {1, GRAPH_SWEEPS};
+    for (int g = 0; g < 2; ++g) {
+        if (h->gexec[g]) continue;
+        SweepArgs a = a0;
+        HIP_TRY(h, hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+        hipError_t err = hipSuccess;
+        for (int i = 0; i < counts[g] && err == hipSuccess; ++i) {
+            err = launch_bin(a, h->gstream);
+            for (int col = 0; col < 8 && err == hipSuccess; ++col) {
+                a.colour = col;
+                err = enqueue_phase(h, a, lds, h->gstream);
+            }
+            if (err == hipSuccess) err = launch_sweep_end(a, h->gstream);
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(h->gstream, &graph);
+        if (err != hipSuccess || e2 != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return fail(h, CRMC_E_DEVICE, std::string("graph capture failed: ") +
+                                              hipGetErrorString(err != hipSuccess ? err : e2));
+        }
+        hipError_t e3 = hipGraphInstantiate(&h->gexec[g], graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e3 != hipSuccess) {
+            h->gexec[g] = nullptr;
+            return fail(h, CRMC_E_DEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(e3));
+        }
+    }
+    HIP_TRY(h, hipEventRecord(h->ev_in, h->stream));
+    HIP_TRY(h, hipStreamWaitEvent(h->gstream, h->ev_in, 0));
+    for (; n >= GRAPH_SWEEPS; n -= GRAPH_SWEEPS) HIP_TRY(h, hipGraphLaunch(h->gexec[1], h->gstream));
+    for (; n > 0; --n) HIP_TRY(h, hipGraphLaunch(h->gexec[0], h->gstream));
+    HIP_TRY(h, hipEventRecord(h->ev_out, h->gstream));
+    HIP_TRY(h, hipStreamWaitEvent(h->stream, h->ev_out, 0));
+    return CRMC_OK;
+}
+
 int check_device_errors(crmc_t h)
 {
     uint32_t e = 0;
@@ -295,6 +389,10 @@ int crmc_create(const crmc_params* p, crmc_t* out)
     // the Coulomb cutoff must exceed the excluded-volume range 2^(1/6)
     if (!(p->rc > 1.2) || !(p->lB >= 0.0) || !(p->eps_wca >= 0.0) || !(p->rho0NA > 0.0)) return CRMC_E_ARG;
     if (p->lds_records < 0 || p->site_trials < 0 || p->site_trials > 4096) return CRMC_E_ARG;
+    if (p->light_records < 0 || p->light_records > 8192) return CRMC_E_ARG;
+    if (p->phase_threads != 0 && p->phase_threads != 64 && p->phase_threads != 128 && p->phase_threads != 256 &&
+        p->phase_threads != 512)
+        return CRMC_E_ARG;
     crmc_t h = new (std::nothrow) crmc_s;
     if (!h) return CRMC_E_NOMEM;
     h->p = *p;
@@ -425,14 +523,13 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     for (auto& kv : gid) kv.second = gi++;
     const uint32_t ngroups = (uint32_t)gid.size();
     std::vector<int32_t> site_group((size_t)std::max(n, 1), 0);
-    std::vector<int32_t> gsize(ngroups, 0), gion(ngroups, 0);
+    std::vector<int32_t> gsize(ngroups, 0);
     for (int32_t i = 0; i < n; ++i) {
         const uint32_t k = (uint32_t)kind[i];
         if (k == KIND_XPOS || k == KIND_XNEG) continue;
         const int32_t g = gid[group ? group[i] : 0];
         site_group[(size_t)i] = g;
         gsize[(size_t)g]++;
-        if (charged && charged[i]) gion[(size_t)g]++;
     }
     r.hist_off.assign(ngroups + 1, 0);
     for (uint32_t g = 0; g < ngroups; ++g) r.hist_off[g + 1] = r.hist_off[g] + gsize[g] + 1;
@@ -459,10 +556,11 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     HIP_TRY(h, dalloc(&d.rec[1], nrec));
     HIP_TRY(h, dalloc(&d.cnt[0], ncells));
     HIP_TRY(h, dalloc(&d.cnt[1], ncells));
+    HIP_TRY(h, dalloc(&d.cnt0, ncells));
     HIP_TRY(h, dalloc(&d.e_acc, ncells));
     HIP_TRY(h, dalloc(&d.occupancy, (size_t)std::max(n, 1)));
     HIP_TRY(h, dalloc(&d.site_group, (size_t)std::max(n, 1)));
-    HIP_TRY(h, dalloc(&d.group_ionized, std::max<uint32_t>(ngroups, 1)));
+    HIP_TRY(h, dalloc(&d.group_count, 2 * std::max<uint32_t>(ngroups, 1)));
     HIP_TRY(h, dalloc(&d.group_hist, (size_t)std::max(r.hist_off[ngroups], 1)));
     HIP_TRY(h, dalloc(&d.group_hist_off, ngroups + 1));
     HIP_TRY(h, dalloc(&d.core_x, cores.size()));
@@ -476,7 +574,7 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     HIP_TRY(h, hipMemset(d.e_acc, 0, ncells * sizeof(double)));
     HIP_TRY(h, hipMemset(d.occupancy, 0, (size_t)std::max(n, 1) * sizeof(uint64_t)));
     HIP_TRY(h, hipMemcpy(d.site_group, site_group.data(), site_group.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    if (ngroups) HIP_TRY(h, hipMemcpy(d.group_ionized, gion.data(), ngroups * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d.group_count, 0, 2 * std::max<uint32_t>(ngroups, 1) * sizeof(int32_t)));
     HIP_TRY(h, hipMemset(d.group_hist, 0, (size_t)std::max(r.hist_off[ngroups], 1) * sizeof(int64_t)));
     HIP_TRY(h, hipMemcpy(d.group_hist_off, r.hist_off.data(), (ngroups + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d.core_x, cores.data(), cores.size() * sizeof(uint4), hipMemcpyHostToDevice));
@@ -579,7 +677,8 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
         r.e0_kappa = r.d.kappa;
     }
     // the LDS pool must hold both cells of a domain
-    if (h->pool < (int)(2 * maxcap + 64)) h->pool = (int)(2 * maxcap + 64);
+    // ... and its ln k table (2 cap + 2 doubles = cap + 1 records)
+    if (h->pool < (int)(3 * maxcap + 64)) h->pool = (int)(3 * maxcap + 64);
     const size_t lds = (size_t)h->pool * sizeof(uint4);
     int dev = 0, maxlds = 0;
     HIP_TRY(h, hipGetDevice(&dev));
@@ -594,13 +693,19 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
     int rc = upload_descriptors(h);
     if (rc) return rc;
     SweepArgs a = base_args(h);
+    if (h->p.use_graph && !h->timing) {
+        rc = sweeps_by_graph(h, a, lds, n_sweeps);
+        if (rc) return rc;
+        h->sweeps += n_sweeps;
+        return CRMC_OK;
+    }
     hipStream_t st = h->stream;
     for (int64_t i = 0; i < n_sweeps; ++i) {
         rc = timed(h, 0, [&] { return launch_bin(a, st); });
         if (rc) return rc;
         for (int col = 0; col < 8; ++col) {
             a.colour = col;
-            rc = timed(h, 1, [&] { return launch_phase(a, lds, st); });
+            rc = timed(h, 1, [&] { return enqueue_phase(h, a, lds, st); });
             if (rc) return rc;
         }
         rc = timed(h, 2, [&] { return launch_sweep_end(a, st); });
@@ -770,6 +875,33 @@ int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out)
     return CRMC_OK;
 }
 
+int crmc_enable_trace(crmc_t h, int64_t capacity)
+{
+    static_assert(sizeof(crmc_phase_trace) == sizeof(PhaseTrace), "trace record layout");
+    if (!h || capacity < 0) return fail(h, CRMC_E_ARG, "bad arguments");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (h->d_trace) { (void)hipFree(h->d_trace); h->d_trace = nullptr; }
+    if (!h->d_trace_n) HIP_TRY(h, hipMalloc((void**)&h->d_trace_n, sizeof(unsigned long long)));
+    HIP_TRY(h, hipMemset(h->d_trace_n, 0, sizeof(unsigned long long)));
+    h->trace_cap = capacity;
+    if (capacity > 0) HIP_TRY(h, hipMalloc((void**)&h->d_trace, (size_t)capacity * sizeof(PhaseTrace)));
+    return CRMC_OK;
+}
+
+int crmc_read_trace(crmc_t h, int64_t cap, crmc_phase_trace* out, int64_t* n_out)
+{
+    if (!h || !n_out || cap < 0) return fail(h, CRMC_E_ARG, "bad arguments");
+    *n_out = 0;
+    if (!h->d_trace) return CRMC_OK;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    unsigned long long n = 0;
+    HIP_TRY(h, hipMemcpy(&n, h->d_trace_n, sizeof n, hipMemcpyDeviceToHost));
+    const int64_t m = std::min<int64_t>({(int64_t)n, h->trace_cap, cap});
+    if (m > 0) HIP_TRY(h, hipMemcpy(out, h->d_trace, (size_t)m * sizeof(PhaseTrace), hipMemcpyDeviceToHost));
+    *n_out = (int64_t)n;
+    return CRMC_OK;
+}
+
 int crmc_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out)
 {
     if (n < 0 || (n > 0 && (!ctr || !out))) return CRMC_E_ARG;
@@ -812,6 +944,11 @@ void crmc_destroy(crmc_t h)
     (void)hipStreamSynchronize(h->stream);
     for (auto& p : h->pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
     for (auto e : h->free_events) (void)hipEventDestroy(e);
+    if (h->gstream) (void)hipStreamSynchronize(h->gstream);
+    drop_graphs(h);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
+    if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+    if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     for (auto& r : h->reps)
         if (r.built) free_replica(r);
     if (h->d_reps) (void)hipFree(h->d_reps);
@@ -819,6 +956,8 @@ void crmc_destroy(crmc_t h)
     if (h->d_err) (void)hipFree(h->d_err);
     if (h->d_log) (void)hipFree(h->d_log);
     if (h->d_log_n) (void)hipFree(h->d_log_n);
+    if (h->d_trace) (void)hipFree(h->d_trace);
+    if (h->d_trace_n) (void)hipFree(h->d_trace_n);
     if (h->d_cell2rep) (void)hipFree(h->d_cell2rep);
     if (h->d_dom2rep) (void)hipFree(h->d_dom2rep);
     if (h->d_lntab) (void)hipFree(h->d_lntab);

@@ -14,7 +14,6 @@ constexpr uint32_t ERR_BIN_CAPACITY = 1u;
 constexpr uint32_t ERR_INSERT_CAPACITY = 2u;
 constexpr uint32_t INFO_UNSTAGED = 4u;
 
-constexpr int PHASE_THREADS = 256; // four wavefronts per domain
 constexpr int BIN_THREADS = 256;   // four wavefronts, one new cell each
 
 // Record: three fixed-point coordinates and a meta word
@@ -34,10 +33,11 @@ struct SweepTab {
 struct Replica {
     uint4* rec[2];           // ping-pong record buffers, ncells*cap records each
     uint32_t* cnt[2];        // records per cell
+    uint32_t* cnt0;          // records per cell as binned at the start of the sweep
     double* e_acc;           // per cell: accumulated energy change of accepted trials
     uint64_t* occupancy;     // per site: sweeps at whose start it was charged
     int32_t* site_group;     // per site: group index
-    int32_t* group_ionized;  // per group: ionized sites now
+    int32_t* group_count;    // 2 x ngroups: ionized sites per group at sweep start (by parity)
     int64_t* group_hist;     // per group histogram of ionized-site counts
     int32_t* group_hist_off; // ngroups+1 offsets into group_hist
     uint4* core_x;           // core centres (x, y, z, unused)
@@ -68,6 +68,15 @@ struct TrialRec {
     double dU, lnp, u;
 };
 
+// optional per-workgroup trace of the phase kernel (profiling)
+struct PhaseTrace {
+    uint64_t t0, t1;        // wall clock at start and end of the workgroup
+    uint32_t sweep, domain; // sweep, global domain index
+    int32_t colour, ntr;    // colour, trials run
+    int32_t nb, own;        // neighbour records, records in the domain's cells
+    int32_t staged, hw;     // neighbours staged on chip; hardware id of the wave
+};
+
 struct SweepArgs {
     Replica* reps;
     const uint32_t* cell2rep; // global cell index -> replica
@@ -87,6 +96,12 @@ struct SweepArgs {
     int32_t ion_coupling, trials, pairing, fixed_grid, site_trials;
     int32_t budget;    // LDS pool per domain, in records
     int32_t precision; // 32 or 64
+    int32_t phase_threads; // workgroup size of the phase kernel: 64, 128, 256 or 512
+    int32_t cls;       // 0: every domain; 1: light domains only; 2: heavy domains only
+    int32_t split;     // LDS records a light domain fits in (the light launch's pool)
+    PhaseTrace* trace;
+    unsigned long long* trace_n;
+    uint64_t trace_cap;
 };
 
 // launchers (device translation unit)

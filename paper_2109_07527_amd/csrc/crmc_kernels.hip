@@ -169,15 +169,18 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
                         const uint32_t pos = base + (uint32_t)__popcll(mask & lt);
                         if (pos < cap) dst[(size_t)k * cap + pos] = rec;
                         const uint32_t sid = rec.w >> 8;
-                        // each site lands in exactly one new cell: a non-returning add
-                        if (sid != NO_SITE && rec_charged(rec.w))
+                        // each site lands in exactly one new cell: non-returning adds
+                        if (sid != NO_SITE && rec_charged(rec.w)) {
                             atomicAdd((unsigned long long*)&R.occupancy[sid], 1ull);
+                            atomicAdd(&R.group_count[(s & 1u) * R.ngroups + (uint32_t)R.site_group[sid]], 1);
+                        }
                     }
                     base += (uint32_t)__popcll(mask);
                 }
             }
     if (lane == 0) {
         R.cnt[nxt][k] = base < cap ? base : cap;
+        R.cnt0[k] = base < cap ? base : cap;
         if (base > cap) atomicOr(a.err, ERR_BIN_CAPACITY);
         if (base > hw) atomicMax(R.hiwater, base); // rarely taken once the mark has settled
     }
@@ -330,13 +333,17 @@ __device__ __forceinline__ double wave_sum(double v)
 // ------------------------------------------------------------------------
 // k_phase: one colour of one sweep
 // ------------------------------------------------------------------------
+constexpr int MAX_LDS_CORES = 64; // nanoparticle cores held on chip (more are read from memory)
+
 struct PhaseShared {
     int32_t pre[53];       // prefix of the 52 neighbour segments (member 0, then 1)
     uint32_t seg_cell[52]; // neighbour cell of each segment
-    double red[2][4];
-    int32_t ovf[2][4];
+    double red[2][8];      // per wavefront partial sums (up to eight wavefronts), two trials deep
+    int32_t ovf[2][8];
     uint32_t att[6], acc[6];
     int32_t dtot[4];
+    uint4 core[MAX_LDS_CORES];
+    double core_delta[MAX_LDS_CORES];
 };
 
 // position g of the concatenated neighbour segments -> segment
@@ -356,10 +363,20 @@ __device__ __forceinline__ uint4 neighbour_global(const PhaseShared& S, const ui
     return recb[(size_t)S.seg_cell[q] * cap + (uint32_t)(g - S.pre[q])];
 }
 
+// LDS pool layout of a domain (offsets in records of smem):
+//   [0, room0) member 0's list | [room0, room0+room1) member 1's list |
+//   ln k table (doubles) | neighbour records (when they fit)
+struct Pool {
+    int room0, room1, ln_off, nb_off;
+    __device__ __forceinline__ int base(int member) const { return member ? room0 : 0; }
+};
+
+extern __shared__ uint4 smem[];
+
 // domain-order index of the k-th record of the domain matching the predicate
 // (member 0's list, then member 1's); each wavefront computes it alone
 template <typename Pred>
-__device__ __forceinline__ int domain_kth(const uint4* own0, int n0, const uint4* own1, int n1, Pred pred, int k)
+__device__ __forceinline__ int domain_kth(const Pool& pl, int n0, int n1, Pred pred, int k)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = lanemask_lt();
@@ -367,7 +384,7 @@ __device__ __forceinline__ int domain_kth(const uint4* own0, int n0, const uint4
     for (int b = 0; b < total; b += 64) {
         const int g = b + lane;
         bool p = false;
-        if (g < total) p = pred(g < n0 ? own0[g].w : own1[g - n0].w);
+        if (g < total) p = pred(smem[g < n0 ? g : pl.room0 + (g - n0)].w);
         const uint64_t mask = __ballot(p);
         const int cnt = __popcll(mask);
         if (k < cnt) {
@@ -380,21 +397,26 @@ __device__ __forceinline__ int domain_kth(const uint4* own0, int n0, const uint4
     return -1;
 }
 
-template <typename Real>
-__global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
+template <typename Real, int NT>
+__global__ __launch_bounds__(NT) void k_phase(SweepArgs a)
 {
-    extern __shared__ uint4 smem[];
     __shared__ PhaseShared S;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t t_start = a.trace ? wall_clock64() : 0;
     const uint32_t gd = blockIdx.x;
-    const uint32_t r = a.dom2rep[gd];
+    // the replica is uniform over the workgroup: keep its constants in scalar registers
+    const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.dom2rep[gd]);
     const Replica& R = a.reps[r];
     const uint32_t n = R.n, h = R.h, cap = R.cap;
     const uint64_t s = *a.sweep;
     const int buf = (int)((s + 1u) & 1u);
     uint4* __restrict__ recb = R.rec[buf];
     uint32_t* __restrict__ cntb = R.cnt[buf];
+    const uint32_t key0 = R.key0, key1 = R.key1;
+    const uint32_t ncores = R.ncores;
+    const uint4* __restrict__ core_g = R.core_x;
+    const double* __restrict__ cdel_g = R.core_delta;
     const int colour = a.colour;
     const uint32_t px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
 
@@ -417,17 +439,20 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
     const uint32_t cell0 = cc0[0] + n * (cc0[1] + n * cc0[2]);
     const uint32_t cell1 = cc1[0] + n * (cc1[1] + n * cc1[2]);
 
-    // LDS pool of a.budget records: each member's list, with room for the
-    // growth its trials can cause (two ions per trial, with the site count
-    // bounded by the record count), then the neighbours
-    int n0 = (int)cntb[cell0];
-    int n1 = ncell == 2 ? (int)cntb[cell1] : 0;
+    // the LDS pool: each member's list with room for the growth its trials can
+    // cause (two ions per trial, the site count bounded by the record count),
+    // the ln k table for every count the domain can reach, then the neighbours
+    // (the binned counts: cells of this colour are changed by this phase only)
+    int n0 = (int)R.cnt0[cell0];
+    int n1 = ncell == 2 ? (int)R.cnt0[cell1] : 0;
     const int ntr_max = a.trials * ncell + ((n0 + n1) * a.site_trials + 15) / 16;
-    const int room0 = min((int)cap, n0 + 2 * ntr_max);
-    const int room1 = ncell == 2 ? min((int)cap, n1 + 2 * ntr_max) : 0;
-    uint4* own0 = smem;
-    uint4* own1 = smem + room0;
-    uint4* nb = smem + room0 + room1;
+    Pool pl;
+    pl.room0 = min((int)cap, n0 + 2 * ntr_max);
+    pl.room1 = ncell == 2 ? min((int)cap, n1 + 2 * ntr_max) : 0;
+    const int nln = pl.room0 + pl.room1 + 2; // ln k for k < nln
+    pl.ln_off = pl.room0 + pl.room1;
+    pl.nb_off = pl.ln_off + (nln + 1) / 2;
+    double* lnt = reinterpret_cast<double*>(smem + pl.ln_off);
 
     // ---- neighbour segments: counts, then a wavefront prefix scan -----------
     if (wave == 0) {
@@ -457,20 +482,32 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
     }
     if (tid < 6) { S.att[tid] = 0; S.acc[tid] = 0; }
     if (tid < 4) S.dtot[tid] = 0;
-    for (int i = tid; i < n0; i += PHASE_THREADS) own0[i] = recb[(size_t)cell0 * cap + i];
-    for (int i = tid; i < n1; i += PHASE_THREADS) own1[i] = recb[(size_t)cell1 * cap + i];
     __syncthreads();
     const int nb_total = S.pre[52];
-    const bool staged = room0 + room1 + nb_total <= a.budget;
+    // A split launch takes one class of domains: light ones, whose lists, ln
+    // table and neighbours fit the small pool, go to a one-wavefront launch,
+    // the others to a wide one.  The decision uses the binned counts of the
+    // domain's cells and the counts of its neighbours (inactive cells), none of
+    // which any workgroup of this phase modifies, so both launches agree.
+    const int need = pl.nb_off + nb_total;
+    if ((a.cls == 1 && need > a.split) || (a.cls == 2 && need <= a.split)) return;
+    for (int i = tid; i < n0; i += NT) smem[i] = recb[(size_t)cell0 * cap + i];
+    for (int i = tid; i < n1; i += NT) smem[pl.room0 + i] = recb[(size_t)cell1 * cap + i];
+    for (int i = tid; i < nln; i += NT) lnt[i] = a.lntab[i];
+    for (int i = tid; i < (int)min(ncores, (uint32_t)MAX_LDS_CORES); i += NT) {
+        S.core[i] = core_g[i];
+        S.core_delta[i] = cdel_g[i];
+    }
+    const bool staged = pl.nb_off + nb_total <= a.budget;
     if (staged) {
-        for (int g = tid; g < nb_total; g += PHASE_THREADS) {
+        for (int g = tid; g < nb_total; g += NT) {
             const int q = segment_of(S, g);
-            nb[g] = recb[(size_t)S.seg_cell[q] * cap + (uint32_t)(g - S.pre[q])];
+            smem[pl.nb_off + g] = recb[(size_t)S.seg_cell[q] * cap + (uint32_t)(g - S.pre[q])];
         }
     } else if (tid == 0) {
         atomicOr(a.err, INFO_UNSTAGED);
     }
-    const int nbb0 = 0, nbc0 = S.pre[26];
+    const int nbc0 = S.pre[26];
     const int nbb1 = S.pre[26], nbc1 = S.pre[52] - S.pre[26];
     __syncthreads();
 
@@ -481,7 +518,7 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
         for (int b = 0; b < total; b += 64) {
             const int g = b + lane;
             uint32_t m = 0;
-            if (g < total) m = g < n0 ? own0[g].w : own1[g - n0].w;
+            if (g < total) m = smem[g < n0 ? g : pl.room0 + (g - n0)].w;
             const int kd = g < total ? rec_kind(m) : 0, ch = rec_charged(m);
             m0a += __popcll(__ballot(kd == (int)KIND_ACID && !ch));
             mca += __popcll(__ballot(kd == (int)KIND_ACID && ch));
@@ -519,7 +556,6 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
     }
     const double lnZm0 = (R.lnZ0 + lnk) + ((R.lnW[cc0[0]] + R.lnW[cc0[1]]) + R.lnW[cc0[2]]);
     const double lnZm1 = (R.lnZ0 + lnk) + ((R.lnW[cc1[0]] + R.lnW[cc1[1]]) + R.lnW[cc1[2]]);
-    const double* __restrict__ LN = a.lntab;
 
     PairParams P;
     P.scale_f = (float)R.scale;
@@ -533,14 +569,13 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
     P.ion_coupling = a.ion_coupling;
     const bool ev_on = a.eps > 0.0 && a.ion_coupling;
     const double lnKA = R.lnKA, lnKB = R.lnKB, lnKion = R.lnKion;
-    const uint32_t ncores = R.ncores;
 
     double dE = 0.0;
     for (int t = 0; t < ntr; ++t) {
         // 20 Philox words: lane b of every wavefront computes block b
         uint32_t wl[4];
         philox4x32_10((uint32_t)s, cell0, (uint32_t)t * 8u + (uint32_t)(lane < 5 ? lane : 0), TAG_TRIAL,
-                      R.key0, R.key1, wl);
+                      key0, key1, wl);
         uint32_t W[20];
 #pragma unroll
         for (int i = 0; i < 20; ++i) W[i] = (uint32_t)__builtin_amdgcn_readlane((int)wl[i & 3], i >> 2);
@@ -558,42 +593,42 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
         switch (move) {
         case 0:
             if (m0a == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && !rec_charged(m); },
+            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && !rec_charged(m); },
                                (int)pick32(W[1], (uint32_t)m0a));
-            lnp_counts = LN[m0a] - LN[mca + 1] - LN[npos + 1] + lnKA;
+            lnp_counts = lnt[m0a] - lnt[mca + 1] - lnt[npos + 1] + lnKA;
             break;
         case 1:
             if (mca == 0 || npos == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && rec_charged(m); },
+            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && rec_charged(m); },
                                (int)pick32(W[1], (uint32_t)mca));
-            b_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
+            b_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
                                (int)pick32(W[2], (uint32_t)npos));
-            lnp_counts = LN[mca] + LN[npos] - LN[m0a + 1] - lnKA;
+            lnp_counts = lnt[mca] + lnt[npos] - lnt[m0a + 1] - lnKA;
             break;
         case 2:
             if (m0b == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && !rec_charged(m); },
+            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && !rec_charged(m); },
                                (int)pick32(W[1], (uint32_t)m0b));
-            lnp_counts = LN[m0b] - LN[mcb + 1] - LN[nneg + 1] + lnKB;
+            lnp_counts = lnt[m0b] - lnt[mcb + 1] - lnt[nneg + 1] + lnKB;
             break;
         case 3:
             if (mcb == 0 || nneg == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && rec_charged(m); },
+            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && rec_charged(m); },
                                (int)pick32(W[1], (uint32_t)mcb));
-            b_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
+            b_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
                                (int)pick32(W[3], (uint32_t)nneg));
-            lnp_counts = LN[mcb] + LN[nneg] - LN[m0b + 1] - lnKB;
+            lnp_counts = lnt[mcb] + lnt[nneg] - lnt[m0b + 1] - lnKB;
             break;
         case 4:
-            lnp_counts = -LN[npos + 1] - LN[nneg + 1] + lnKion;
+            lnp_counts = -lnt[npos + 1] - lnt[nneg + 1] + lnKion;
             break;
         default:
             if (npos == 0 || nneg == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
+            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
                                (int)pick32(W[2], (uint32_t)npos));
-            b_idx = domain_kth(own0, n0, own1, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
+            b_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
                                (int)pick32(W[3], (uint32_t)nneg));
-            lnp_counts = LN[npos] + LN[nneg] - lnKion;
+            lnp_counts = lnt[npos] + lnt[nneg] - lnKion;
             break;
         }
         if (tid == 0) S.att[move] += 1u;
@@ -617,7 +652,7 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
             // A: the site flips
             A.member = a_idx < n0 ? 0 : 1;
             A.own = a_idx < n0 ? a_idx : a_idx - n0;
-            const uint4 rc = (A.member ? own1 : own0)[A.own];
+            const uint4 rc = smem[pl.base(A.member) + A.own];
             A.x = rc.x; A.y = rc.y; A.z = rc.z;
             const int chg = rec_charged(rc.w);
             const int sgn = rec_kind(rc.w) == (int)KIND_ACID ? -1 : 1;
@@ -641,16 +676,14 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
                 const int j = ncell == 1 ? 0 : (int)pick32(wc, (uint32_t)ncell);
                 B.member = j;
                 B.own = -1;
-                const uint32_t* ibj = j ? ib1 : ib0;
-                const uint32_t* iwj = j ? iw1 : iw0;
-                B.x = ibj[0] + pick64(W[wo + 0], W[wo + 1], iwj[0]);
-                B.y = ibj[1] + pick64(W[wo + 2], W[wo + 3], iwj[1]);
-                B.z = ibj[2] + pick64(W[wo + 4], W[wo + 5], iwj[2]);
+                B.x = (j ? ib1[0] : ib0[0]) + pick64(W[wo + 0], W[wo + 1], j ? iw1[0] : iw0[0]);
+                B.y = (j ? ib1[1] : ib0[1]) + pick64(W[wo + 2], W[wo + 3], j ? iw1[1] : iw0[1]);
+                B.z = (j ? ib1[2] : ib0[2]) + pick64(W[wo + 4], W[wo + 5], j ? iw1[2] : iw0[2]);
                 lnvol += j ? lnZm1 : lnZm0;
             } else {
                 B.member = b_idx < n0 ? 0 : 1;
                 B.own = b_idx < n0 ? b_idx : b_idx - n0;
-                const uint4 rc = (B.member ? own1 : own0)[B.own];
+                const uint4 rc = smem[pl.base(B.member) + B.own];
                 B.x = rc.x; B.y = rc.y; B.z = rc.z;
                 lnvol -= B.member ? lnZm1 : lnZm0;
             }
@@ -667,16 +700,14 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
                 const int j = ncell == 1 ? 0 : (int)pick32(W[18], (uint32_t)ncell);
                 A.member = j;
                 A.own = -1;
-                const uint32_t* ibj = j ? ib1 : ib0;
-                const uint32_t* iwj = j ? iw1 : iw0;
-                A.x = ibj[0] + pick64(W[4], W[5], iwj[0]);
-                A.y = ibj[1] + pick64(W[6], W[7], iwj[1]);
-                A.z = ibj[2] + pick64(W[8], W[9], iwj[2]);
+                A.x = (j ? ib1[0] : ib0[0]) + pick64(W[4], W[5], j ? iw1[0] : iw0[0]);
+                A.y = (j ? ib1[1] : ib0[1]) + pick64(W[6], W[7], j ? iw1[1] : iw0[1]);
+                A.z = (j ? ib1[2] : ib0[2]) + pick64(W[8], W[9], j ? iw1[2] : iw0[2]);
                 lnvol += j ? lnZm1 : lnZm0;
             } else {
                 A.member = a_idx < n0 ? 0 : 1;
                 A.own = a_idx < n0 ? a_idx : a_idx - n0;
-                const uint4 rc = (A.member ? own1 : own0)[A.own];
+                const uint4 rc = smem[pl.base(A.member) + A.own];
                 A.x = rc.x; A.y = rc.y; A.z = rc.z;
                 lnvol -= A.member ? lnZm1 : lnZm0;
             }
@@ -693,28 +724,29 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
         for (int j = 0; j < ncell; ++j) {
             const bool inA = A.member == j, inB = B.member == j;
             if (!inA && !inB) continue;
-            const uint4* own = j ? own1 : own0;
+            const int obase = pl.base(j);
             const int no = j ? n1 : n0;
             const int skipA = inA ? A.own : -1, skipB = inB ? B.own : -1;
-            const int nbb = j ? nbb1 : nbb0, nbc = j ? nbc1 : nbc0;
+            const int nbb = j ? nbb1 : 0, nbc = j ? nbc1 : nbc0;
             const int total = no + nbc;
-            for (int g = tid; g < total; g += PHASE_THREADS) {
+            for (int g = tid; g < total; g += NT) {
                 uint4 rc;
                 if (g < no) {
                     if (g == skipA || g == skipB) continue;
-                    rc = own[g];
+                    rc = smem[obase + g];
                 } else {
                     const int q = nbb + (g - no);
-                    rc = staged ? nb[q] : neighbour_global(S, recb, cap, q);
+                    rc = staged ? smem[pl.nb_off + q] : neighbour_global(S, recb, cap, q);
                 }
                 if (inA) acc += pair_term<Real>(rc, A, P, ov);
                 if (inB) acc += pair_term<Real>(rc, B, P, ov);
             }
         }
         if (ev_on && ncores) {
-            for (int k = tid; k < (int)ncores; k += PHASE_THREADS) {
-                const uint4 cx = R.core_x[k];
-                const double dl = R.core_delta[k];
+            for (int k = tid; k < (int)ncores; k += NT) {
+                const bool lds = k < MAX_LDS_CORES;
+                const uint4 cx = lds ? S.core[k] : core_g[k];
+                const double dl = lds ? S.core_delta[k] : cdel_g[k];
                 if (A.dw != 0) acc += wca_core<Real>(A, cx, dl, P, ov);
                 if (B.dw != 0) acc += wca_core<Real>(B, cx, dl, P, ov);
             }
@@ -725,9 +757,14 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
         const int par = t & 1;
         if (lane == 0) { S.red[par][wave] = wsum; S.ovf[par][wave] = wov; }
         __syncthreads();
-        double dU = ((S.red[par][0] + S.red[par][1]) + S.red[par][2]) + S.red[par][3];
-        if (S.ovf[par][0] | S.ovf[par][1] | S.ovf[par][2] | S.ovf[par][3])
-            dU = __longlong_as_double(0x7FF0000000000000ll);
+        double dU = S.red[par][0];
+        int any_ov = S.ovf[par][0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) {
+            dU += S.red[par][w];
+            any_ov |= S.ovf[par][w];
+        }
+        if (any_ov) dU = __longlong_as_double(0x7FF0000000000000ll);
         const double lnp = lnp_counts + lnvol - dU;
         const bool accept = !cap_fail && u < exp(lnp < 0.0 ? lnp : 0.0);
         if (tid == 0) {
@@ -750,11 +787,9 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
             S.acc[move] += 1u;
             dE += dU;
             if (move <= 3) {
-                uint4& rc = (A.member ? own1 : own0)[A.own];
+                uint4& rc = smem[pl.base(A.member) + A.own];
                 rc.w ^= 8u;
-                const int now = rec_charged(rc.w);
-                atomicAdd(&R.group_ionized[R.site_group[rc.w >> 8]], now ? 1 : -1);
-                S.dtot[move <= 1 ? 0 : 1] += now ? 1 : -1;
+                S.dtot[move <= 1 ? 0 : 1] += rec_charged(rc.w) ? 1 : -1;
             }
             int l0 = n0, l1 = n1;
             if (!insertion) {
@@ -768,26 +803,27 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
                     }
                 }
                 {
-                    uint4* Lst = dm0 ? own1 : own0;
                     int& cnt = dm0 ? l1 : l0;
-                    Lst[di0] = Lst[cnt - 1];
+                    const int bs = pl.base(dm0);
+                    smem[bs + di0] = smem[bs + cnt - 1];
                     --cnt;
                 }
                 if (dm1 >= 0) {
-                    uint4* Lst = dm1 ? own1 : own0;
                     int& cnt = dm1 ? l1 : l0;
-                    Lst[di1] = Lst[cnt - 1];
+                    const int bs = pl.base(dm1);
+                    smem[bs + di1] = smem[bs + cnt - 1];
                     --cnt;
                 }
             } else {
                 if (move == 4) {
-                    uint4* Lst = A.member ? own1 : own0;
                     int& cnt = A.member ? l1 : l0;
-                    Lst[cnt++] = make_uint4(A.x, A.y, A.z, make_meta(KIND_XPOS, 1u, NO_SITE));
+                    smem[pl.base(A.member) + cnt] = make_uint4(A.x, A.y, A.z, make_meta(KIND_XPOS, 1u, NO_SITE));
+                    ++cnt;
                 }
-                uint4* Lst = B.member ? own1 : own0;
                 int& cnt = B.member ? l1 : l0;
-                Lst[cnt++] = make_uint4(B.x, B.y, B.z, make_meta(B.q_new > 0 ? KIND_XPOS : KIND_XNEG, 1u, NO_SITE));
+                smem[pl.base(B.member) + cnt] =
+                    make_uint4(B.x, B.y, B.z, make_meta(B.q_new > 0 ? KIND_XPOS : KIND_XNEG, 1u, NO_SITE));
+                ++cnt;
             }
             if (move == 0 || move == 4) S.dtot[2] += 1;
             if (move == 2 || move == 4) S.dtot[3] += 1;
@@ -809,8 +845,19 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
 
     // ---- write the domain's cells back --------------------------------------
     __syncthreads();
-    for (int i = tid; i < n0; i += PHASE_THREADS) recb[(size_t)cell0 * cap + i] = own0[i];
-    for (int i = tid; i < n1; i += PHASE_THREADS) recb[(size_t)cell1 * cap + i] = own1[i];
+    for (int i = tid; i < n0; i += NT) recb[(size_t)cell0 * cap + i] = smem[i];
+    for (int i = tid; i < n1; i += NT) recb[(size_t)cell1 * cap + i] = smem[pl.room0 + i];
+    if (tid == 0 && a.trace) {
+        const unsigned long long ti = atomicAdd(a.trace_n, 1ull);
+        if (ti < a.trace_cap) {
+            PhaseTrace& T = a.trace[ti];
+            T.t0 = t_start;
+            T.t1 = wall_clock64();
+            T.sweep = (uint32_t)s; T.domain = gd; T.colour = colour; T.ntr = ntr;
+            T.nb = nb_total; T.own = n0 + n1; T.staged = staged;
+            T.hw = (int32_t)__smid();
+        }
+    }
     if (tid == 0) {
         cntb[cell0] = (uint32_t)n0;
         if (ncell == 2) cntb[cell1] = (uint32_t)n1;
@@ -824,6 +871,7 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
     }
 }
 
+
 // ------------------------------------------------------------------------
 // k_sweep_end: series row, group histograms, advance the sweep counter
 // ------------------------------------------------------------------------
@@ -836,8 +884,13 @@ __global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a)
             const int64_t row = (int64_t)(s % (uint64_t)R.series_cap);
             R.series[row * 4 + threadIdx.x] = (int32_t)R.totals[threadIdx.x];
         }
-        for (uint32_t g = threadIdx.x; g < R.ngroups; g += blockDim.x)
-            R.group_hist[R.group_hist_off[g] + R.group_ionized[g]] += 1;
+        // ionized sites per group at the start of this sweep (counted by the
+        // re-binning); the slot is cleared for the sweep after next
+        int32_t* gc = R.group_count + (s & 1u) * R.ngroups;
+        for (uint32_t g = threadIdx.x; g < R.ngroups; g += blockDim.x) {
+            R.group_hist[R.group_hist_off[g] + gc[g]] += 1;
+            gc[g] = 0;
+        }
     }
     __syncthreads();
     if (threadIdx.x == 0) *a.sweep = s + 1u;
@@ -931,13 +984,21 @@ hipError_t launch_bin(const SweepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename Real>
+static hipError_t launch_phase_t(const SweepArgs& a, size_t lds, hipStream_t s)
+{
+    switch (a.phase_threads) {
+    case 64: hipLaunchKernelGGL((k_phase<Real, 64>), dim3(a.ndom_total), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_phase<Real, 128>), dim3(a.ndom_total), dim3(128), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_phase<Real, 512>), dim3(a.ndom_total), dim3(512), lds, s, a); break;
+    default: hipLaunchKernelGGL((k_phase<Real, 256>), dim3(a.ndom_total), dim3(256), lds, s, a); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_phase(const SweepArgs& a, size_t lds, hipStream_t s)
 {
-    if (a.precision == 64)
-        hipLaunchKernelGGL(k_phase<double>, dim3(a.ndom_total), dim3(PHASE_THREADS), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_phase<float>, dim3(a.ndom_total), dim3(PHASE_THREADS), lds, s, a);
-    return hipGetLastError();
+    return a.precision == 64 ? launch_phase_t<double>(a, lds, s) : launch_phase_t<float>(a, lds, s);
 }
 
 hipError_t launch_sweep_end(const SweepArgs& a, hipStream_t s)
@@ -964,10 +1025,15 @@ hipError_t launch_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k
 
 hipError_t set_phase_lds_limit(size_t bytes)
 {
-    hipError_t e = hipFuncSetAttribute((const void*)k_phase<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_phase<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void* fns[] = {(const void*)k_phase<float, 64>, (const void*)k_phase<float, 128>,
+                         (const void*)k_phase<float, 256>, (const void*)k_phase<float, 512>,
+                         (const void*)k_phase<double, 64>, (const void*)k_phase<double, 128>,
+                         (const void*)k_phase<double, 256>, (const void*)k_phase<double, 512>};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 } // namespace crmc

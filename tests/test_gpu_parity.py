@@ -165,15 +165,16 @@ def test_unstaged_neighbours_bit_exact():
     _, model, _ = CASES["mixed"]
     s = _mixed()
     cond = _cond(6.0, 5.0, 5.0, -0.8, -0.8, 0.5)  # dense salt: neighbourhoods outgrow the pool
-    S = crmc.System(n_replicas=1, lB=2.0, rc=6.0, eps=1.0, precision=64, trials_per_cell=2, seed=9,
+    S = crmc.System(n_replicas=1, lB=2.0, rc=6.0, eps=1.0, precision=64, trials_per_cell=4, seed=9,
                     lds_records=1)
     S.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"],
-                  cell_capacity=256)
-    S.sweep_ex([cond], 8)
+                  cell_capacity=160)
+    S.sweep_ex([cond], 24)
     obs = S.observe(0)
+    assert obs["status"] == 0
     assert obs["error_flags"] & 4  # the slow path was taken
-    o = _oracle_for(s, model, cond, obs["n_cells"], 2, True, seed=9)
-    o.sweeps(8)
+    o = _oracle_for(s, model, cond, obs["n_cells"], 4, True, seed=9)
+    o.sweeps(24)
     _same_state(S.particles(0), o.particles())
 
 
@@ -264,3 +265,29 @@ def test_config2_full_size_sampled_replicas():
         o.sweeps(nsw)
         n, _ = _compare_logs(glog[glog["replica"] == r], o.log())
         assert n > 1000
+
+
+@pytest.mark.parametrize("case", ["mixed", "np_pair_small", "chain40"])
+@pytest.mark.parametrize("light", [200, 700])
+def test_split_light_heavy_launch_bit_exact(case, light):
+    """Light domains in a one-wavefront launch, the rest in the wide one: every
+    domain is processed exactly once and the chain is unchanged."""
+    crmc = _gpu()
+    make, model, cond = CASES[case]
+    s = make()
+    S = crmc.System(n_replicas=1, lB=model["lB"], rc=model["rc"], eps=model["eps"],
+                    ion_coupling=model["ion_coupling"], precision=64, trials_per_cell=3, seed=41,
+                    light_records=light)
+    kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"])
+    if len(s.get("core_R", [])):
+        kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
+    S.build_cells(0, **kw)
+    S.sweep_ex([cond], 12)
+    obs = S.observe(0)
+    assert obs["status"] == 0
+    o = _oracle_for(s, model, cond, obs["n_cells"], 3, True, seed=41)
+    ser = o.sweeps(12)
+    _same_state(S.particles(0), o.particles())
+    assert np.array_equal(S.series(0, 0, 12), ser)
+    att, acc = o.move_stats()
+    assert list(att) == obs["attempts"] and list(acc) == obs["accepts"]
