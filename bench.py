@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "CR-MC trial moves/s and indep. samples/s at matched <alpha>; % HBM roofline"
 HBM_PEAK_GBS = 8000.0
 PHASE_SOURCES = ["paper_2109_07527_amd/csrc/crmc_kernels.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "phase_traffic_config2.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_phase_nanoparticle_pair_traffic.md")
 
 
 def phase_source_hash() -> str:
@@ -51,6 +51,25 @@ def stencil_bytes_per_sweep(n_records: float, n_cells: int) -> float:
     cell, 26 times as a neighbour and written back once (16 B each); every
     cell count is read 27 times and written once (4 B)."""
     return n_records * 16.0 * 28.0 + n_cells * 4.0 * 28.0
+
+
+def read_traffic(args):
+    """HBM bytes per phase launch from the committed counter summary, if it
+    was taken on this kernel source with this launch configuration."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                kv[k.strip()] = v.strip().strip("`")
+    want = {"source_hash": phase_source_hash(), "trials_per_cell": str(args.trials),
+            "precision": str(args.precision), "phase_threads": str(args.phase_threads),
+            "site_trials": str(args.site_trials), "light_records": str(args.light_records)}
+    if any(kv.get(k) != v for k, v in want.items()) or "bytes_per_launch" not in kv:
+        return None
+    return float(kv["bytes_per_launch"])
 
 
 def cpu_baseline(system, cond, trials, site_trials, seconds):
@@ -87,9 +106,9 @@ def cpu_baseline(system, cond, trials, site_trials, seconds):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=300)
-    ap.add_argument("--trials", type=int, default=2, help="trials per cell per sweep")
+    ap.add_argument("--trials", type=int, default=8, help="trials per cell per sweep")
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--site-trials", type=int, default=0, help="extra trials per 16 sites of a domain")
     ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per domain in records (0 = default)")
@@ -100,6 +119,8 @@ def main():
                     help="LDS pool of the one-wavefront launch for light domains (0: single launch)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB ten times (counter calibration) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -118,6 +139,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        n = args.copy_probe << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n, "launches": 10}), flush=True)
+        return
     c = config2()
     conds = [dict(pH=pH, pKa=c["pKa"], pKb=c["pKb"], pIX_pos=c["pIX"], pIX_neg=c["pIX"], kappa=c["kappa"])
              for pH in c["pH_list"]]
@@ -175,12 +205,7 @@ def main():
     bytes_launch = bytes_sweep / 8.0
     phase_avg_ms = ms[1] / max(launches[1], 1)
     achieved = bytes_launch / (phase_avg_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("source_hash") == phase_source_hash():
-            traffic = tr.get("bytes_per_launch")
+    traffic = read_traffic(args)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_phase", "bytes_per_launch": round(bytes_launch),
