@@ -65,8 +65,8 @@ def read_traffic(args):
                 k, v = line[2:].split(": ", 1)
                 kv[k.strip()] = v.strip().strip("`")
     want = {"source_hash": phase_source_hash(), "trials_per_cell": str(args.trials),
-            "precision": str(args.precision), "phase_threads": str(args.phase_threads),
-            "site_trials": str(args.site_trials), "light_records": str(args.light_records)}
+            "precision": str(args.precision), "lds_records": str(args.lds_records),
+            "site_trials": str(args.site_trials), "light_neighbours": str(args.light_neighbours)}
     if any(kv.get(k) != v for k, v in want.items()) or "bytes_per_launch" not in kv:
         return None
     return float(kv["bytes_per_launch"])
@@ -112,11 +112,10 @@ def main():
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--site-trials", type=int, default=0, help="extra trials per 16 sites of a domain")
     ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per domain in records (0 = default)")
-    ap.add_argument("--phase-threads", type=int, default=256, choices=(64, 128, 256, 512))
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one in the timed region")
     ap.add_argument("--kernel-steps", type=int, default=400, help="sweeps of the per-kernel event timing pass")
-    ap.add_argument("--light-records", type=int, default=0,
-                    help="LDS pool of the one-wavefront launch for light domains (0: single launch)")
+    ap.add_argument("--light-neighbours", type=int, default=0,
+                    help="neighbour records up to which a domain runs on one wavefront (0 = library default)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -154,8 +153,8 @@ def main():
     R = len(conds)
     S = crmc.System(n_replicas=R, lB=c["lB"], rc=c["rc"], eps=1.0, precision=args.precision,
                     trials_per_cell=args.trials, pairing=True, seed=2024, site_trials=args.site_trials,
-                    lds_records=args.lds_records, phase_threads=args.phase_threads,
-                    use_graph=not args.no_graph, light_records=args.light_records)
+                    lds_records=args.lds_records, use_graph=not args.no_graph,
+                    light_neighbours=args.light_neighbours)
     for r in range(R):
         S.build_cells(r, c)
     S.sweep_ex(conds, args.warmup)
@@ -219,8 +218,8 @@ def main():
         "config": {"workload": "nanoparticle pair: 2000 acid + 2000 base sites, R=10, separation 25, "
                                "L=120, ~2e4 ions (pI_X=0.668), lB=2, kappa=0.5, rc=8; 9 replicas pH 3..11",
                    "replicas": R, "trials_per_cell": args.trials, "site_trials_per_16": args.site_trials,
-                   "phase_threads": args.phase_threads, "graph": not args.no_graph,
-                   "light_records": args.light_records,
+                   "graph": not args.no_graph, "light_neighbours": args.light_neighbours,
+                   "lds_records": args.lds_records,
                    "schedule": "shifted cells, paired domains",
                    "cells_per_edge": after[0]["n_cells"], "cell_capacity": after[0]["cell_capacity"]},
         "independent_samples_per_s": round(samples, 1),

@@ -92,15 +92,18 @@ typedef struct {
     int32_t trials_per_cell; /* trials per active cell per phase (>= 1) */
     int32_t pairing;         /* 1: domains are reflection-paired cells; 0: single cells */
     int32_t ion_coupling;    /* 1: ions interact; 0: ideal ions (test systems) */
-    int32_t lds_records;     /* neighbour records staged on chip per domain (0 = default) */
+    int32_t lds_records;     /* LDS pool of a phase workgroup in 16-byte records (0 = 4096); raised
+                                to 3 * cell_capacity + 128 when smaller.  A heavy domain has the
+                                whole pool, a light domain a quarter of it */
     int32_t fixed_grid;      /* 1: never shift the grid (only for tests: not ergodic) */
     int32_t site_trials;     /* extra trials per 16 ionizable sites of a domain (rounded up) */
-    int32_t phase_threads;   /* threads per domain workgroup: 64, 128, 256 or 512 (0 = 256) */
+    int32_t light_neighbours; /* a domain whose 26-cell neighbourhoods held at most this many
+                                 records at the start of the sweep, and whose lists fit a quarter
+                                 of the pool, runs on one wavefront; the others on a whole
+                                 256-thread workgroup (0 = 768; 1..65536).  Results do not
+                                 depend on it */
     int32_t use_graph;       /* 1: replay captured HIP graphs of whole sweeps; 0: launch each kernel */
-    int32_t light_records;   /* >0: domains whose cells, ln table and neighbours fit this many
-                                records of LDS run one wavefront each in a launch of their own,
-                                the rest in the phase_threads launch; 0: one launch for all */
-    int32_t reserved;
+    int32_t reserved0, reserved1; /* must be 0 */
     double lB;               /* Bjerrum length (sigma) */
     double rc;               /* Coulomb cutoff (sigma) */
     double eps_wca;          /* excluded-volume strength (kT); 0 disables it */
@@ -127,8 +130,10 @@ typedef struct {
     int64_t accepts[6];
     uint32_t error_flags;     /* bit 0: cell capacity exceeded in binning;
                                  bit 1: capacity exceeded by an insertion;
-                                 bit 2: (info) a domain's neighbours did not fit on
-                                 chip and were read from memory */
+                                 bit 2: (info) some neighbours of a domain did not fit
+                                 on chip and were read from memory during its trials;
+                                 bit 3: a domain did not fit its LDS pool and was
+                                 skipped (an internal error; reported as CRMC_E_DEVICE) */
     int32_t n_cells;          /* cells per box edge */
     int32_t cell_capacity;
     int32_t max_cell_count;   /* most records any cell has held after re-binning */

@@ -32,8 +32,8 @@ class crmc_params(C.Structure):
     _fields_ = [("n_replicas", C.c_int32), ("precision", C.c_int32), ("trials_per_cell", C.c_int32),
                 ("pairing", C.c_int32), ("ion_coupling", C.c_int32), ("lds_records", C.c_int32),
                 ("fixed_grid", C.c_int32), ("site_trials", C.c_int32),
-                ("phase_threads", C.c_int32), ("use_graph", C.c_int32),
-                ("light_records", C.c_int32), ("reserved", C.c_int32),
+                ("light_neighbours", C.c_int32), ("use_graph", C.c_int32),
+                ("reserved0", C.c_int32), ("reserved1", C.c_int32),
                 ("lB", C.c_double), ("rc", C.c_double), ("eps_wca", C.c_double), ("rho0NA", C.c_double),
                 ("pKw", C.c_double), ("kappa", C.c_double), ("pKb", C.c_double),
                 ("seed", C.c_uint64), ("stream", C.c_void_p)]
@@ -293,8 +293,8 @@ class System:
 
     def __init__(self, n_replicas=1, lB=2.0, rc=6.0, eps=1.0, rho0NA=0.0269424, pKw=14.0, kappa=0.5,
                  pKb=5.0, seed=1234, precision=32, trials_per_cell=1, pairing=True, ion_coupling=True,
-                 lds_records=0, fixed_grid=False, site_trials=0, phase_threads=256, use_graph=True,
-                 light_records=0, stream="torch"):
+                 lds_records=0, fixed_grid=False, site_trials=0, light_neighbours=0, use_graph=True,
+                 stream="torch"):
         p = crmc_params()
         p.n_replicas = int(n_replicas)
         p.precision = int(precision)
@@ -304,9 +304,8 @@ class System:
         p.lds_records = int(lds_records)
         p.fixed_grid = int(bool(fixed_grid))
         p.site_trials = int(site_trials)
-        p.phase_threads = int(phase_threads)
+        p.light_neighbours = int(light_neighbours)
         p.use_graph = int(bool(use_graph))
-        p.light_records = int(light_records)
         p.lB, p.rc, p.eps_wca, p.rho0NA, p.pKw, p.kappa, p.pKb = lB, rc, eps, rho0NA, pKw, kappa, pKb
         p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         s = current_stream() if stream == "torch" else stream

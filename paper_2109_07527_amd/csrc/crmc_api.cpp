@@ -22,7 +22,7 @@ namespace {
 
 constexpr double TWO32 = 4294967296.0;
 constexpr double LN10 = 2.302585092994045684017991454684364208;
-constexpr int DEFAULT_POOL = 3072;          // LDS pool per domain (records, 48 KB)
+constexpr int DEFAULT_POOL = 4096;          // LDS pool per phase workgroup (records, 64 KB)
 constexpr int64_t DEFAULT_SERIES = 16384;   // retained sweeps of the series
 
 struct HostReplica {
@@ -50,6 +50,9 @@ struct crmc_s {
     uint32_t ncell_total = 0, ndom_total = 0;
     uint64_t* d_sweep = nullptr;
     uint32_t* d_err = nullptr;
+    uint32_t* d_plan_n = nullptr;     // per colour: heavy and light domain counts
+    uint32_t* d_plan_heavy = nullptr; // per colour: ndom_total domain slots
+    uint32_t* d_plan_light = nullptr;
     TrialRec* d_log = nullptr;
     unsigned long long* d_log_n = nullptr;
     int64_t log_cap = 0;
@@ -170,9 +173,12 @@ SweepArgs base_args(crmc_t h)
     a.pairing = h->p.pairing;
     a.fixed_grid = h->p.fixed_grid;
     a.site_trials = h->p.site_trials;
-    a.budget = h->pool;
+    a.pool = h->pool;
     a.precision = h->p.precision;
-    a.phase_threads = h->p.phase_threads ? h->p.phase_threads : 256;
+    a.light_nb = h->p.light_neighbours > 0 ? h->p.light_neighbours : DEFAULT_LIGHT_NB;
+    a.plan_n = h->d_plan_n;
+    a.plan_heavy = h->d_plan_heavy;
+    a.plan_light = h->d_plan_light;
     a.trace = h->d_trace;
     a.trace_n = h->d_trace_n;
     a.trace_cap = (uint64_t)h->trace_cap;
@@ -209,8 +215,12 @@ int upload_descriptors(crmc_t h)
         if (h->d_cell2rep) (void)hipFree(h->d_cell2rep);
         if (h->d_dom2rep) (void)hipFree(h->d_dom2rep);
         if (h->d_lntab) (void)hipFree(h->d_lntab);
+        if (h->d_plan_n) (void)hipFree(h->d_plan_n);
+        if (h->d_plan_heavy) (void)hipFree(h->d_plan_heavy);
+        if (h->d_plan_light) (void)hipFree(h->d_plan_light);
         h->d_cell2rep = h->d_dom2rep = nullptr;
         h->d_lntab = nullptr;
+        h->d_plan_n = h->d_plan_heavy = h->d_plan_light = nullptr;
         // ln k for every count a domain can reach (two cells of capacity maxcap, plus one)
         h->lntab_n = (int32_t)(2u * maxcap + 2u);
         std::vector<double> lt((size_t)h->lntab_n, 0.0);
@@ -218,6 +228,10 @@ int upload_descriptors(crmc_t h)
         HIP_TRY(h, dalloc(&h->d_cell2rep, c2r.size()));
         HIP_TRY(h, dalloc(&h->d_dom2rep, d2r.size()));
         HIP_TRY(h, dalloc(&h->d_lntab, lt.size()));
+        HIP_TRY(h, dalloc(&h->d_plan_n, 16));
+        HIP_TRY(h, dalloc(&h->d_plan_heavy, (size_t)8 * doms));
+        HIP_TRY(h, dalloc(&h->d_plan_light, (size_t)8 * doms));
+        HIP_TRY(h, hipMemset(h->d_plan_n, 0, 16 * sizeof(uint32_t)));
         HIP_TRY(h, hipMemcpy(h->d_cell2rep, c2r.data(), c2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(h->d_dom2rep, d2r.data(), d2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(h->d_lntab, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -276,24 +290,11 @@ int timed(crmc_t h, int kind, F&& launch)
 
 constexpr int GRAPH_SWEEPS = 16;
 
-// one colour phase: a single launch, or a one-wavefront launch for the light
-// domains followed by the phase_threads launch for the rest
-hipError_t enqueue_phase(crmc_t h, SweepArgs a, size_t lds, hipStream_t st)
+// the start of a sweep: re-binning, then the plan of its eight phases
+hipError_t enqueue_bin_plan(const SweepArgs& a, hipStream_t st)
 {
-    if (h->p.light_records <= 0) {
-        a.cls = 0;
-        return launch_phase(a, lds, st);
-    }
-    SweepArgs l = a;
-    l.cls = 1;
-    l.split = h->p.light_records;
-    l.budget = h->p.light_records;
-    l.phase_threads = 64;
-    hipError_t e = launch_phase(l, (size_t)h->p.light_records * sizeof(uint4), st);
-    if (e != hipSuccess) return e;
-    a.cls = 2;
-    a.split = h->p.light_records;
-    return launch_phase(a, lds, st);
+    hipError_t e = launch_bin(a, st);
+    return e == hipSuccess ? launch_plan(a, st) : e;
 }
 
 void drop_graphs(crmc_t h)
@@ -311,7 +312,9 @@ int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n)
 {
     const uint64_t key = (uint64_t)(uintptr_t)a0.log * 1000003ull ^ (uint64_t)a0.log_cap * 7919ull ^
                          (uint64_t)lds * 31ull ^ (uint64_t)(uintptr_t)a0.lntab ^
-                         (uint64_t)(uintptr_t)a0.trace * 65537ull ^ (uint64_t)a0.trace_cap * 131ull;
+                         (uint64_t)(uintptr_t)a0.trace * 65537ull ^ (uint64_t)a0.trace_cap * 131ull ^
+                         (uint64_t)(uintptr_t)a0.plan_heavy * 17ull ^ (uint64_t)(uintptr_t)a0.plan_light * 257ull ^
+                         (uint64_t)(uintptr_t)a0.plan_n * 4099ull;
     if (key != h->gkey) {
         drop_graphs(h);
         h->gkey = key;
@@ -326,10 +329,10 @@ int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n)
         HIP_TRY(h, hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
         hipError_t err = hipSuccess;
         for (int i = 0; i < counts[g] && err == hipSuccess; ++i) {
-            err = launch_bin(a, h->gstream);
+            err = enqueue_bin_plan(a, h->gstream);
             for (int col = 0; col < 8 && err == hipSuccess; ++col) {
                 a.colour = col;
-                err = enqueue_phase(h, a, lds, h->gstream);
+                err = launch_phase(a, lds, h->gstream);
             }
             if (err == hipSuccess) err = launch_sweep_end(a, h->gstream);
         }
@@ -361,6 +364,7 @@ int check_device_errors(crmc_t h)
     uint32_t e = 0;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     HIP_TRY(h, hipMemcpy(&e, h->d_err, sizeof e, hipMemcpyDeviceToHost));
+    if (e & ERR_POOL) return fail(h, CRMC_E_DEVICE, "internal error: a domain did not fit its LDS pool");
     if (e & (ERR_BIN_CAPACITY | ERR_INSERT_CAPACITY))
         return fail(h, CRMC_E_CAPACITY, "a cell exceeded its record capacity (flags " + std::to_string(e) +
                                             "); rebuild with a larger cell_capacity");
@@ -389,10 +393,8 @@ int crmc_create(const crmc_params* p, crmc_t* out)
     // the Coulomb cutoff must exceed the excluded-volume range 2^(1/6)
     if (!(p->rc > 1.2) || !(p->lB >= 0.0) || !(p->eps_wca >= 0.0) || !(p->rho0NA > 0.0)) return CRMC_E_ARG;
     if (p->lds_records < 0 || p->site_trials < 0 || p->site_trials > 4096) return CRMC_E_ARG;
-    if (p->light_records < 0 || p->light_records > 8192) return CRMC_E_ARG;
-    if (p->phase_threads != 0 && p->phase_threads != 64 && p->phase_threads != 128 && p->phase_threads != 256 &&
-        p->phase_threads != 512)
-        return CRMC_E_ARG;
+    if (p->light_neighbours < 0 || p->light_neighbours > 65536) return CRMC_E_ARG;
+    if (p->reserved0 != 0 || p->reserved1 != 0) return CRMC_E_ARG;
     crmc_t h = new (std::nothrow) crmc_s;
     if (!h) return CRMC_E_NOMEM;
     h->p = *p;
@@ -676,9 +678,10 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
         r.E0 = E;
         r.e0_kappa = r.d.kappa;
     }
-    // the LDS pool must hold both cells of a domain
-    // ... and its ln k table (2 cap + 2 doubles = cap + 1 records)
-    if (h->pool < (int)(3 * maxcap + 64)) h->pool = (int)(3 * maxcap + 64);
+    // the pool of a heavy domain must hold both cells' lists (2 cap), the ln k
+    // table (2 cap + 2 doubles) and up to 64 cores with their Deltas (96 records)
+    if (h->pool < (int)(3 * maxcap + 128)) h->pool = (int)(3 * maxcap + 128);
+    h->pool = (h->pool + 3) & ~3; // four equal quarters for light domains
     const size_t lds = (size_t)h->pool * sizeof(uint4);
     int dev = 0, maxlds = 0;
     HIP_TRY(h, hipGetDevice(&dev));
@@ -701,11 +704,11 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
     }
     hipStream_t st = h->stream;
     for (int64_t i = 0; i < n_sweeps; ++i) {
-        rc = timed(h, 0, [&] { return launch_bin(a, st); });
+        rc = timed(h, 0, [&] { return enqueue_bin_plan(a, st); });
         if (rc) return rc;
         for (int col = 0; col < 8; ++col) {
             a.colour = col;
-            rc = timed(h, 1, [&] { return enqueue_phase(h, a, lds, st); });
+            rc = timed(h, 1, [&] { return launch_phase(a, lds, st); });
             if (rc) return rc;
         }
         rc = timed(h, 2, [&] { return launch_sweep_end(a, st); });
@@ -961,6 +964,9 @@ void crmc_destroy(crmc_t h)
     if (h->d_cell2rep) (void)hipFree(h->d_cell2rep);
     if (h->d_dom2rep) (void)hipFree(h->d_dom2rep);
     if (h->d_lntab) (void)hipFree(h->d_lntab);
+    if (h->d_plan_n) (void)hipFree(h->d_plan_n);
+    if (h->d_plan_heavy) (void)hipFree(h->d_plan_heavy);
+    if (h->d_plan_light) (void)hipFree(h->d_plan_light);
     delete h;
 }
 

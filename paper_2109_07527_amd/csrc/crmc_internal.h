@@ -12,9 +12,12 @@ constexpr uint32_t NO_SITE = 0xFFFFFFu;
 
 constexpr uint32_t ERR_BIN_CAPACITY = 1u;
 constexpr uint32_t ERR_INSERT_CAPACITY = 2u;
-constexpr uint32_t INFO_UNSTAGED = 4u;
+constexpr uint32_t INFO_UNSTAGED = 4u;   // some neighbours were read from memory during trials
+constexpr uint32_t ERR_POOL = 8u;        // a domain did not fit its LDS pool (not processed)
 
-constexpr int BIN_THREADS = 256;   // four wavefronts, one new cell each
+constexpr int BIN_THREADS = 256;    // four wavefronts, one new cell each
+constexpr int PHASE_THREADS = 256;  // one heavy domain, or four light domains (one per wavefront)
+constexpr int DEFAULT_LIGHT_NB = 768;
 
 // Record: three fixed-point coordinates and a meta word
 //   bits 0-2 kind, bit 3 charged flag, bits 8-31 site id (NO_SITE for ions)
@@ -94,11 +97,12 @@ struct SweepArgs {
     uint64_t log_cap;
     double lB, eps, ln2;
     int32_t ion_coupling, trials, pairing, fixed_grid, site_trials;
-    int32_t budget;    // LDS pool per domain, in records
+    int32_t pool;      // LDS pool of a phase workgroup, in records (a light domain gets a quarter)
     int32_t precision; // 32 or 64
-    int32_t phase_threads; // workgroup size of the phase kernel: 64, 128, 256 or 512
-    int32_t cls;       // 0: every domain; 1: light domains only; 2: heavy domains only
-    int32_t split;     // LDS records a light domain fits in (the light launch's pool)
+    int32_t light_nb;  // neighbour records up to which a domain may run on one wavefront
+    uint32_t* plan_n;      // per colour: heavy count, light count
+    uint32_t* plan_heavy;  // per colour: ndom_total slots of domain indices
+    uint32_t* plan_light;
     PhaseTrace* trace;
     unsigned long long* trace_n;
     uint64_t trace_cap;
@@ -106,6 +110,7 @@ struct SweepArgs {
 
 // launchers (device translation unit)
 hipError_t launch_bin(const SweepArgs& a, hipStream_t s);
+hipError_t launch_plan(const SweepArgs& a, hipStream_t s);
 hipError_t launch_phase(const SweepArgs& a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_sweep_end(const SweepArgs& a, hipStream_t s);
 hipError_t launch_energy(const Replica* rep_dev, const Replica& rep_host, double lB, double eps,

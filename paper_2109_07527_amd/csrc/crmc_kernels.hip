@@ -5,14 +5,17 @@
 //                cell), sample per-site occupancy, publish the sweep's shift and
 //                pairing table.  One wavefront per new cell gathers from the old
 //                cells that overlap it (at most 27, usually 8): no atomics, no scan.
-//   k_phase<R>   per colour: one 256-thread workgroup per domain (one cell, or
-//                two reflection-paired cells of the colour).  Stages the
-//                domain's cells and their 26-cell neighbourhoods in LDS, then
-//                runs the domain's trials back to back: Philox words, move and
-//                participants, pair sum of the energy change over the staged
-//                records (R = float or double terms, FP64 accumulation,
-//                wavefront + workgroup reduction), acceptance of Sec. II C,
-//                commit in LDS.  Writes the cells back at the end.
+//   k_plan       per sweep: sorts the domains of every colour into light ones
+//                (one wavefront each) and heavy ones (a whole workgroup).
+//   k_phase<R>   per colour: every domain (one cell, or two reflection-paired
+//                cells of the colour) runs its trials back to back: Philox
+//                words twelve trials at a time, move and participants, pair
+//                sum of the energy change over the domain's own lists (LDS)
+//                and its 26-cell neighbourhoods (staged in LDS once, the excess
+//                read from memory), R = float or double terms with FP64
+//                accumulation,
+//                acceptance of Sec. II C, commit in LDS; writes the cells back
+//                at the end.
 //   k_sweep_end  per sweep: series row, group histograms, sweep counter.
 //   k_energy     total energy of a replica from scratch (FP64), per cell.
 #include "crmc_internal.h"
@@ -82,6 +85,8 @@ __device__ __forceinline__ int rec_q(uint32_t meta)
     return 0;
 }
 
+__device__ __forceinline__ uint32_t rdl0(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 0); }
+
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
     const uint32_t lane = threadIdx.x & 63u;
@@ -113,6 +118,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     if (s == 0) { oo[0] = oo[1] = oo[2] = 0u; }
     else grid_shift(R.key0, R.key1, s - 1, a.fixed_grid, oo);
 
+    if (gcell == 0 && lane < 16) a.plan_n[lane] = 0u; // the planning kernel that follows counts anew
     if (k == 0 && lane < 12) {
         // the sweep's table: shift, and the pairing centre of every colour
         const uint32_t M = R.h * R.h * R.h;
@@ -191,9 +197,10 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
 // ------------------------------------------------------------------------
 template <typename Real> struct Math;
 template <> struct Math<float> {
-    __device__ static __forceinline__ float rsqrt(float x) { return rsqrtf(x); }
+    // the hardware approximations (about 1 ulp; r^2 >= 1/4 wherever they matter)
+    __device__ static __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
     __device__ static __forceinline__ float ex(float x) { return __expf(x); }
-    __device__ static __forceinline__ float rcp(float x) { return __frcp_rn(x); }
+    __device__ static __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     __device__ static __forceinline__ float sqrt_(float x) { return sqrtf(x); }
 };
 template <> struct Math<double> {
@@ -202,6 +209,123 @@ template <> struct Math<double> {
     __device__ static __forceinline__ double rcp(double x) { return 1.0 / x; }
     __device__ static __forceinline__ double sqrt_(double x) { return sqrt(x); }
 };
+
+// ------------------------------------------------------------------------
+// k_plan and k_phase: one colour of one sweep
+// ------------------------------------------------------------------------
+// A domain is one active cell, or two reflection-paired active cells of the
+// colour.  The planning kernel (once per sweep, after the re-binning) sorts the
+// domains of every colour into two lists: light domains run one per wavefront
+// (four per workgroup, each with a quarter of the LDS pool), heavy ones
+// (nanoparticle surfaces) get a whole workgroup.  A domain's own cells change
+// only in its own phase, so the binned counts the plan uses size its pool
+// exactly; its neighbour cells may have changed in earlier phases, which only
+// changes how many neighbour records fit on chip.
+constexpr int MAX_LDS_CORES = 64; // nanoparticle cores copied on chip (more are read from memory)
+
+// LDS pool of one domain, offsets in 16-byte records:
+//   member 0's list | member 1's list | ln k table (doubles) | cores | core
+//   Deltas (doubles) | neighbour records (as many as fit)
+struct Pool {
+    int room0, room1;
+    int ln_off, nln;
+    int core_off, cdel_off, ncl;
+    int st_off;
+    __device__ __forceinline__ int base(int member) const { return member ? room0 : 0; }
+};
+
+__device__ __forceinline__ Pool pool_layout(int n0, int n1, int ncell, int ntr_max, uint32_t cap, uint32_t ncores)
+{
+    Pool p;
+    // room for the growth the trials can cause: two ions per trial
+    p.room0 = min((int)cap, n0 + 2 * ntr_max);
+    p.room1 = ncell == 2 ? min((int)cap, n1 + 2 * ntr_max) : 0;
+    p.ln_off = p.room0 + p.room1;
+    p.nln = p.room0 + p.room1 + 2; // ln k for every count the domain can reach
+    p.core_off = p.ln_off + (p.nln + 1) / 2;
+    p.ncl = ncores <= (uint32_t)MAX_LDS_CORES ? (int)ncores : 0;
+    p.cdel_off = p.core_off + p.ncl;
+    p.st_off = p.cdel_off + (p.ncl + 1) / 2;
+    return p;
+}
+
+struct DomGeo {
+    uint32_t cell0, cell1;
+    uint32_t cc0[3], cc1[3];
+    int ncell;
+};
+
+// active cells of domain d (0-based within the replica) in a colour
+__device__ __forceinline__ DomGeo domain_geometry(const Replica& R, uint32_t d, int colour, int pairing)
+{
+    const uint32_t n = R.n, h = R.h, M = h * h * h;
+    const uint32_t px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
+    uint32_t ma, mb;
+    if (pairing) {
+        const uint32_t c = R.tab->pairc[colour];
+        const uint32_t half = c >> 1;
+        if (d <= half) { ma = d; mb = c - d; }
+        else { ma = c + 1u + (d - half - 1u); mb = M + c - ma; }
+    } else {
+        ma = mb = d;
+    }
+    DomGeo g;
+    g.ncell = (ma == mb) ? 1 : 2;
+    g.cc0[0] = 2u * (ma % h) + px; g.cc0[1] = 2u * ((ma / h) % h) + py; g.cc0[2] = 2u * (ma / (h * h)) + pz;
+    g.cc1[0] = 2u * (mb % h) + px; g.cc1[1] = 2u * ((mb / h) % h) + py; g.cc1[2] = 2u * (mb / (h * h)) + pz;
+    g.cell0 = g.cc0[0] + n * (g.cc0[1] + n * g.cc0[2]);
+    g.cell1 = g.cc1[0] + n * (g.cc1[1] + n * g.cc1[2]);
+    return g;
+}
+
+// neighbour o (0..25, the 3x3x3 block without its centre) of cell (x, y, z)
+__device__ __forceinline__ uint32_t neighbour_cell(uint32_t x, uint32_t y, uint32_t z, int o, uint32_t n)
+{
+    const int oo = o < 13 ? o : o + 1;
+    const uint32_t nx = (x + n + (uint32_t)(oo % 3) - 1u) % n;
+    const uint32_t ny = (y + n + (uint32_t)((oo / 3) % 3) - 1u) % n;
+    const uint32_t nz = (z + n + (uint32_t)(oo / 9) - 1u) % n;
+    return nx + n * (ny + n * nz);
+}
+
+// one thread per domain, one colour per workgroup (blockIdx.y); the list
+// slots are claimed with one atomic per wavefront and class
+__global__ __launch_bounds__(64) void k_plan(SweepArgs a)
+{
+    const int colour = (int)blockIdx.y;
+    const uint32_t gd = blockIdx.x * 64u + threadIdx.x;
+    bool valid = gd < a.ndom_total, light = false;
+    if (valid) {
+        const Replica& R = a.reps[a.dom2rep[gd]];
+        const DomGeo G = domain_geometry(R, gd - R.dom_begin, colour, a.pairing);
+        const uint32_t* cntb = R.cnt[(*a.sweep + 1u) & 1u];
+        int nb = 0;
+#pragma unroll
+        for (int o = 0; o < 26; ++o) nb += (int)cntb[neighbour_cell(G.cc0[0], G.cc0[1], G.cc0[2], o, R.n)];
+        if (G.ncell == 2) {
+#pragma unroll
+            for (int o = 0; o < 26; ++o) nb += (int)cntb[neighbour_cell(G.cc1[0], G.cc1[1], G.cc1[2], o, R.n)];
+        }
+        const int n0 = (int)R.cnt0[G.cell0];
+        const int n1 = G.ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
+        const int ntr_max = a.trials * G.ncell + ((n0 + n1) * a.site_trials + 15) / 16;
+        const Pool p = pool_layout(n0, n1, G.ncell, ntr_max, R.cap, R.ncores);
+        light = nb <= a.light_nb && p.st_off <= a.pool / 4;
+    }
+    const uint64_t ml = __ballot(valid && light), mh = __ballot(valid && !light);
+    const uint32_t lane = threadIdx.x;
+    uint32_t bl = 0, bh = 0;
+    if (lane == 0) {
+        if (ml) bl = atomicAdd(&a.plan_n[2 * colour + 1], (uint32_t)__popcll(ml));
+        if (mh) bh = atomicAdd(&a.plan_n[2 * colour], (uint32_t)__popcll(mh));
+    }
+    bl = rdl0(bl);
+    bh = rdl0(bh);
+    if (!valid) return;
+    const uint64_t lt = lanemask_lt();
+    if (light) a.plan_light[(size_t)colour * a.ndom_total + bl + (uint32_t)__popcll(ml & lt)] = gd;
+    else a.plan_heavy[(size_t)colour * a.ndom_total + bh + (uint32_t)__popcll(mh & lt)] = gd;
+}
 
 // a particle whose state the trial changes
 struct Chg {
@@ -228,49 +352,54 @@ __device__ __forceinline__ Real scale_of(const PairParams& P)
     return sizeof(Real) == 4 ? (Real)P.scale_f : (Real)P.scale_d;
 }
 
-template <typename Real>
-__device__ __forceinline__ double pair_term(const uint4& rec, const Chg& c, const PairParams& P, int& ov)
+// Charge code of a staged neighbour record (replaces its meta word in the
+// on-chip copy): bits 0-1 the charge (two's complement), bit 2 free ion.
+__device__ __forceinline__ uint32_t charge_code(uint32_t meta)
 {
-    // distance first: most records of a 27-cell neighbourhood lie beyond rc
+    return ((uint32_t)rec_q(meta) & 3u) | ((uint32_t)rec_is_ion(meta) << 2);
+}
+__device__ __forceinline__ int code_q(uint32_t code) { return ((int)(code << 30)) >> 30; }
+__device__ __forceinline__ int code_ion(uint32_t code) { return (int)((code >> 2) & 1u); }
+
+// Per-lane sums for one changed particle c: aq = sum of q_j phi(r) over the
+// records inside the Coulomb cutoff (times lB dq at the end), aw = excluded
+// volume change; ov set on an overlap created by an insertion.  valid = 0
+// masks the lane out.  Branch-free on the common path (the 64 lanes diverge
+// anyway); the rare cases (a distance within 1e-5 of rc, or within the WCA
+// range) are handled behind wavefront-uniform tests.
+template <typename Real>
+__device__ __forceinline__ void pair_acc(const uint4& rec, uint32_t code, bool valid, const Chg& c,
+                                         const PairParams& P, double& aq, double& aw, int& ov)
+{
     const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
     const Real sc = scale_of<Real>(P);
     const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
     const Real r2 = fx * fx + fy * fy + fz * fz;
-    if (r2 > (Real)P.rc2_hi) return 0.0;
-    const int ionj = rec_is_ion(rec.w);
-    if (!P.ion_coupling && ionj) return 0.0;
-    const int qj = rec_q(rec.w);
-    const bool coul = c.dq != 0 && qj != 0;
-    const bool ev = c.dw != 0;
-    if (!coul && !ev) return 0.0;
-    double e = 0.0;
-    if (coul) {
-        // inside/outside the cutoff as decided on the exact integer squared
-        // distance; the float distance settles it outside a +-1e-5 band
+    const bool coupled = valid && (P.ion_coupling || !code_ion(code));
+    if (c.dq != 0) {
         bool in = r2 < (Real)P.rc2_lo;
-        if (!in) {
+        const bool band = !in && r2 <= (Real)P.rc2_hi;
+        if (__ballot(band)) {
             const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
-            const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
-            in = r2i < P.R2;
+            const bool exact = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az < P.R2;
+            in = in || (band && exact);
         }
-        if (in) {
-            const Real rinv = Math<Real>::rsqrt(r2);
-            const Real r = r2 * rinv;
-            const Real phi = Math<Real>::ex(-(Real)P.kappa * r) * rinv;
-            e += P.lB * (double)(c.dq * qj) * (double)phi;
-        }
+        const Real rinv = Math<Real>::rsqrt(r2);
+        const Real phi = Math<Real>::ex(-(Real)P.kappa * (r2 * rinv)) * rinv;
+        const Real qphi = (Real)code_q(code) * phi;
+        aq += (double)((in && coupled) ? qphi : (Real)0);
     }
-    if (ev && r2 < (Real)1.2599210498948731647672106) {
-        if (r2 < (Real)0.25) {
-            if (c.dw > 0) ov = 1;
-        } else {
+    if (c.dw != 0) {
+        const bool near = coupled && r2 < (Real)1.2599210498948731647672106;
+        if (__ballot(near)) {
+            const bool over = near && r2 < (Real)0.25;
             const Real ir2 = Math<Real>::rcp(r2);
             const Real ir6 = ir2 * ir2 * ir2;
             const Real w = (Real)4.0 * (Real)P.eps * (ir6 * ir6 - ir6) + (Real)P.eps;
-            e += (double)c.dw * (double)w;
+            aw += (double)((near && !over) ? (Real)c.dw * w : (Real)0);
+            if (over && c.dw > 0) ov = 1;
         }
     }
-    return e;
 }
 
 template <typename Real>
@@ -330,85 +459,159 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// ------------------------------------------------------------------------
-// k_phase: one colour of one sweep
-// ------------------------------------------------------------------------
-constexpr int MAX_LDS_CORES = 64; // nanoparticle cores held on chip (more are read from memory)
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-struct PhaseShared {
-    int32_t pre[53];       // prefix of the 52 neighbour segments (member 0, then 1)
-    uint32_t seg_cell[52]; // neighbour cell of each segment
-    double red[2][8];      // per wavefront partial sums (up to eight wavefronts), two trials deep
-    int32_t ovf[2][8];
-    uint32_t att[6], acc[6];
-    int32_t dtot[4];
-    uint4 core[MAX_LDS_CORES];
-    double core_delta[MAX_LDS_CORES];
-};
-
-// position g of the concatenated neighbour segments -> segment
-__device__ __forceinline__ int segment_of(const PhaseShared& S, int g)
+// v from another lane through a DPP pattern (both halves of a double)
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
 {
-    int lo = 0, hi = 52; // pre[lo] <= g < pre[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (S.pre[mid] <= g) lo = mid; else hi = mid;
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
+}
+
+// sum over the 64 lanes, returned in every lane: quad butterflies and row
+// rotations (DPP) give each 16-lane row its sum, then the four row sums
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_d<0xB1>(v);  // quad_perm(1,0,3,2)
+    v += dpp_d<0x4E>(v);  // quad_perm(2,3,0,1)
+    v += dpp_d<0x124>(v); // row_ror:4
+    v += dpp_d<0x128>(v); // row_ror:8
+    const long long b = __double_as_longlong(v);
+    double r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 16 * k);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * k);
+        r[k] = __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
     }
-    return lo;
+    return (r[0] + r[1]) + (r[2] + r[3]);
 }
-
-__device__ __forceinline__ uint4 neighbour_global(const PhaseShared& S, const uint4* recb, uint32_t cap, int g)
+__device__ __forceinline__ uint32_t rflu(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ uint32_t rdl(uint32_t v, int lane) { return (uint32_t)__builtin_amdgcn_readlane((int)v, lane); }
+__device__ __forceinline__ double rfld(double v)
 {
-    const int q = segment_of(S, g);
-    return recb[(size_t)S.seg_cell[q] * cap + (uint32_t)(g - S.pre[q])];
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)b);
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
+}
+// uniform values computed on the vector unit go back to scalar registers
+__device__ __forceinline__ void uniform_chg(Chg& c)
+{
+    c.x = rflu(c.x); c.y = rflu(c.y); c.z = rflu(c.z);
+    c.dq = rfl(c.dq); c.dw = rfl(c.dw); c.member = rfl(c.member); c.own = rfl(c.own);
+    c.q_old = rfl(c.q_old); c.q_new = rfl(c.q_new); c.ion = rfl(c.ion);
+    c.pres_old = rfl(c.pres_old); c.pres_new = rfl(c.pres_new);
 }
 
-// LDS pool layout of a domain (offsets in records of smem):
-//   [0, room0) member 0's list | [room0, room0+room1) member 1's list |
-//   ln k table (doubles) | neighbour records (when they fit)
-struct Pool {
-    int room0, room1, ln_off, nb_off;
-    __device__ __forceinline__ int base(int member) const { return member ? room0 : 0; }
+// LDS written by one lane becomes visible to the other lanes of its wavefront
+// in program order; this keeps the compiler from moving memory accesses across
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Neighbour slots: the 26 neighbour cells of member 0, then those of member
+// 1, concatenated; pre_v (lane q) holds the end of segment q, cell_v its cell.
+// For the 64 slots g0 + lane, the source cell and index inside it; q is a
+// cursor over the segments that only moves forward (uniform).
+__device__ __forceinline__ void chunk_src(int g0, int lane, int& q, int pre_v, uint32_t cell_v, uint32_t& cell, int& off)
+{
+    while (q < 52 && (int)rdl((uint32_t)pre_v, q) <= g0) ++q;
+    const int g = g0 + lane;
+    cell = 0u;
+    off = 0;
+    for (int qq = q; qq < 52; ++qq) {
+        const int st = qq ? (int)rdl((uint32_t)pre_v, qq - 1) : 0;
+        if (st >= g0 + 64) break;
+        const int en = (int)rdl((uint32_t)pre_v, qq);
+        if (g >= st && g < en) {
+            cell = rdl(cell_v, qq);
+            off = g - st;
+        }
+    }
+}
+
+struct MemberCounts {
+    int a0, ac, b0, bc, xp, xn; // neutral / charged acids and bases, cations, anions
 };
 
-extern __shared__ uint4 smem[];
-
-// domain-order index of the k-th record of the domain matching the predicate
-// (member 0's list, then member 1's); each wavefront computes it alone
-template <typename Pred>
-__device__ __forceinline__ int domain_kth(const Pool& pl, int n0, int n1, Pred pred, int k)
+__device__ __forceinline__ MemberCounts rfl_counts(const MemberCounts& c)
 {
-    const int lane = threadIdx.x & 63;
+    return MemberCounts{rfl(c.a0), rfl(c.ac), rfl(c.b0), rfl(c.bc), rfl(c.xp), rfl(c.xn)};
+}
+
+// count changes of an accepted move: A's member gets the site change (moves
+// 0-3) or the cation (4, 5), B's member the ion
+__device__ __forceinline__ void apply_counts(MemberCounts& c, int move, bool hasA, bool hasB)
+{
+    const int s = (move & 1) ? -1 : 1; // forward / insertion: +1
+    const bool acid = move <= 1, base = move == 2 || move == 3, salt = move >= 4;
+    c.a0 -= (hasA && acid) ? s : 0;
+    c.ac += (hasA && acid) ? s : 0;
+    c.b0 -= (hasA && base) ? s : 0;
+    c.bc += (hasA && base) ? s : 0;
+    c.xp += ((hasA && salt) || (hasB && acid)) ? s : 0;
+    c.xn += (hasB && !acid) ? s : 0;
+}
+
+__device__ __forceinline__ MemberCounts count_member(const uint4* pool, int base, int nn, int lane)
+{
+    MemberCounts c{0, 0, 0, 0, 0, 0};
+    for (int b0 = 0; b0 < nn; b0 += 64) {
+        const int g = b0 + lane;
+        const uint32_t m = g < nn ? pool[base + g].w : 0u;
+        const int kd = rec_kind(m), ch = rec_charged(m);
+        c.a0 += __popcll(__ballot(kd == (int)KIND_ACID && !ch));
+        c.ac += __popcll(__ballot(kd == (int)KIND_ACID && ch));
+        c.b0 += __popcll(__ballot(kd == (int)KIND_BASE && !ch));
+        c.bc += __popcll(__ballot(kd == (int)KIND_BASE && ch));
+        c.xp += __popcll(__ballot(kd == (int)KIND_XPOS));
+        c.xn += __popcll(__ballot(kd == (int)KIND_XNEG));
+    }
+    return c;
+}
+
+// index (in one member's list) of the k-th record whose meta word has
+// (meta & mask) == value
+__device__ __forceinline__ int member_kth(const uint4* pool, int base, int nn, uint32_t mask, uint32_t value, int k,
+                                          int lane)
+{
     const uint64_t lt = lanemask_lt();
-    const int total = n0 + n1;
-    for (int b = 0; b < total; b += 64) {
-        const int g = b + lane;
-        bool p = false;
-        if (g < total) p = pred(smem[g < n0 ? g : pl.room0 + (g - n0)].w);
-        const uint64_t mask = __ballot(p);
-        const int cnt = __popcll(mask);
-        if (k < cnt) {
-            const bool mine = p && __popcll(mask & lt) == k;
-            const uint64_t hit = __ballot(mine);
-            return b + (__ffsll((long long)hit) - 1);
+    for (int b0 = 0; b0 < nn; b0 += 64) {
+        const int g = b0 + lane;
+        const bool p = g < nn && (pool[base + g].w & mask) == value;
+        const uint64_t m = __ballot(p);
+        const int c = __popcll(m);
+        if (k < c) {
+            const uint64_t hit = __ballot(p && __popcll(m & lt) == k);
+            return b0 + (int)__builtin_ctzll(hit);
         }
-        k -= cnt;
+        k -= c;
     }
     return -1;
 }
 
-template <typename Real, int NT>
-__global__ __launch_bounds__(NT) void k_phase(SweepArgs a)
+// class of a participant: meta mask and value
+constexpr uint32_t CLS_MASK_SITE = 0xFu, CLS_MASK_ION = 0x7u;
+// The domain's trials.  wpd wavefronts share the pair sums (wpd = 1: light
+// domain, no workgroup barriers; wpd = 4: heavy domain, the whole workgroup;
+// uniform over the workgroup).
+template <typename Real>
+__device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint4* __restrict__ pool,
+                                           int pool_records, int wid, const int wpd, double (*red)[4], int (*ovf)[4])
 {
-    __shared__ PhaseShared S;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nt = 64 * wpd;
+    const int lane = threadIdx.x & 63;
+    const int tid = wid * 64 + lane;
     const uint64_t t_start = a.trace ? wall_clock64() : 0;
-    const uint32_t gd = blockIdx.x;
-    // the replica is uniform over the workgroup: keep its constants in scalar registers
-    const uint32_t r = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.dom2rep[gd]);
+    const uint32_t r = rflu(a.dom2rep[gd]);
     const Replica& R = a.reps[r];
-    const uint32_t n = R.n, h = R.h, cap = R.cap;
+    const uint32_t n = R.n, cap = R.cap;
     const uint64_t s = *a.sweep;
     const int buf = (int)((s + 1u) & 1u);
     uint4* __restrict__ recb = R.rec[buf];
@@ -418,144 +621,120 @@ __global__ __launch_bounds__(NT) void k_phase(SweepArgs a)
     const uint4* __restrict__ core_g = R.core_x;
     const double* __restrict__ cdel_g = R.core_delta;
     const int colour = a.colour;
-    const uint32_t px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
+    const DomGeo G = domain_geometry(R, gd - R.dom_begin, colour, a.pairing);
+    const int ncell = G.ncell;
 
-    // ---- the domain of this workgroup -------------------------------------
-    const uint32_t M = h * h * h;
-    const uint32_t d = gd - R.dom_begin;
-    uint32_t ma, mb;
-    if (a.pairing) {
-        const uint32_t c = R.tab->pairc[colour];
-        const uint32_t half = c >> 1;
-        if (d <= half) { ma = d; mb = c - d; }
-        else { ma = c + 1u + (d - half - 1u); mb = M + c - ma; }
-    } else {
-        ma = mb = d;
-    }
-    const int ncell = (ma == mb) ? 1 : 2;
-    uint32_t cc0[3], cc1[3];
-    cc0[0] = 2u * (ma % h) + px; cc0[1] = 2u * ((ma / h) % h) + py; cc0[2] = 2u * (ma / (h * h)) + pz;
-    cc1[0] = 2u * (mb % h) + px; cc1[1] = 2u * ((mb / h) % h) + py; cc1[2] = 2u * (mb / (h * h)) + pz;
-    const uint32_t cell0 = cc0[0] + n * (cc0[1] + n * cc0[2]);
-    const uint32_t cell1 = cc1[0] + n * (cc1[1] + n * cc1[2]);
-
-    // the LDS pool: each member's list with room for the growth its trials can
-    // cause (two ions per trial, the site count bounded by the record count),
-    // the ln k table for every count the domain can reach, then the neighbours
-    // (the binned counts: cells of this colour are changed by this phase only)
-    int n0 = (int)R.cnt0[cell0];
-    int n1 = ncell == 2 ? (int)R.cnt0[cell1] : 0;
+    int n0 = (int)R.cnt0[G.cell0];
+    int n1 = ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
     const int ntr_max = a.trials * ncell + ((n0 + n1) * a.site_trials + 15) / 16;
-    Pool pl;
-    pl.room0 = min((int)cap, n0 + 2 * ntr_max);
-    pl.room1 = ncell == 2 ? min((int)cap, n1 + 2 * ntr_max) : 0;
-    const int nln = pl.room0 + pl.room1 + 2; // ln k for k < nln
-    pl.ln_off = pl.room0 + pl.room1;
-    pl.nb_off = pl.ln_off + (nln + 1) / 2;
-    double* lnt = reinterpret_cast<double*>(smem + pl.ln_off);
+    const Pool pl = pool_layout(n0, n1, ncell, ntr_max, cap, ncores);
+    if (pl.st_off > pool_records) { // the plan and the host size pools so that this never happens
+        if (tid == 0) atomicOr(a.err, ERR_POOL);
+        return;
+    }
 
     // ---- neighbour segments: counts, then a wavefront prefix scan -----------
-    if (wave == 0) {
-        int cnt = 0;
-        uint32_t nc = 0;
-        if (lane < 52) {
-            const int j = lane / 26, q = lane % 26;
-            const int o = q < 13 ? q : q + 1;
-            const uint32_t* cc = j ? cc1 : cc0;
-            if (j < ncell) {
-                const uint32_t x = (cc[0] + n + (uint32_t)(o % 3) - 1u) % n;
-                const uint32_t y = (cc[1] + n + (uint32_t)((o / 3) % 3) - 1u) % n;
-                const uint32_t z = (cc[2] + n + (uint32_t)(o / 9) - 1u) % n;
-                nc = x + n * (y + n * z);
-                cnt = (int)cntb[nc];
-            }
-            S.seg_cell[lane] = nc;
+    int cnt = 0;
+    uint32_t seg_cell = 0;
+    if (lane < 52) {
+        const int j = lane / 26;
+        if (j < ncell) {
+            seg_cell = j ? neighbour_cell(G.cc1[0], G.cc1[1], G.cc1[2], lane - 26, n)
+                         : neighbour_cell(G.cc0[0], G.cc0[1], G.cc0[2], lane, n);
+            cnt = (int)cntb[seg_cell];
         }
-        int incl = cnt;
+    }
+    int pre_v = cnt;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int v = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += v;
-        }
-        if (lane < 52) S.pre[lane + 1] = incl;
-        if (lane == 0) S.pre[0] = 0;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(pre_v, off, 64);
+        if (lane >= off) pre_v += v;
     }
-    if (tid < 6) { S.att[tid] = 0; S.acc[tid] = 0; }
-    if (tid < 4) S.dtot[tid] = 0;
-    __syncthreads();
-    const int nb_total = S.pre[52];
-    // A split launch takes one class of domains: light ones, whose lists, ln
-    // table and neighbours fit the small pool, go to a one-wavefront launch,
-    // the others to a wide one.  The decision uses the binned counts of the
-    // domain's cells and the counts of its neighbours (inactive cells), none of
-    // which any workgroup of this phase modifies, so both launches agree.
-    const int need = pl.nb_off + nb_total;
-    if ((a.cls == 1 && need > a.split) || (a.cls == 2 && need <= a.split)) return;
-    for (int i = tid; i < n0; i += NT) smem[i] = recb[(size_t)cell0 * cap + i];
-    for (int i = tid; i < n1; i += NT) smem[pl.room0 + i] = recb[(size_t)cell1 * cap + i];
-    for (int i = tid; i < nln; i += NT) lnt[i] = a.lntab[i];
-    for (int i = tid; i < (int)min(ncores, (uint32_t)MAX_LDS_CORES); i += NT) {
-        S.core[i] = core_g[i];
-        S.core_delta[i] = cdel_g[i];
-    }
-    const bool staged = pl.nb_off + nb_total <= a.budget;
-    if (staged) {
-        for (int g = tid; g < nb_total; g += NT) {
-            const int q = segment_of(S, g);
-            smem[pl.nb_off + g] = recb[(size_t)S.seg_cell[q] * cap + (uint32_t)(g - S.pre[q])];
-        }
-    } else if (tid == 0) {
-        atomicOr(a.err, INFO_UNSTAGED);
-    }
-    const int nbc0 = S.pre[26];
-    const int nbb1 = S.pre[26], nbc1 = S.pre[52] - S.pre[26];
-    __syncthreads();
+    const int nb_total = (int)rdl((uint32_t)pre_v, 51);
+    const int nbc0 = (int)rdl((uint32_t)pre_v, 25);
 
-    // ---- counts of the domain, one pass -------------------------------------
-    int m0a = 0, mca = 0, m0b = 0, mcb = 0, npos = 0, nneg = 0;
+    // ---- neighbours: staged in the rest of the pool, the excess read from memory
+    const int st_end = min(nb_total, pool_records - pl.st_off);
     {
-        const int total = n0 + n1;
-        for (int b = 0; b < total; b += 64) {
-            const int g = b + lane;
-            uint32_t m = 0;
-            if (g < total) m = smem[g < n0 ? g : pl.room0 + (g - n0)].w;
-            const int kd = g < total ? rec_kind(m) : 0, ch = rec_charged(m);
-            m0a += __popcll(__ballot(kd == (int)KIND_ACID && !ch));
-            mca += __popcll(__ballot(kd == (int)KIND_ACID && ch));
-            m0b += __popcll(__ballot(kd == (int)KIND_BASE && !ch));
-            mcb += __popcll(__ballot(kd == (int)KIND_BASE && ch));
-            npos += __popcll(__ballot(kd == (int)KIND_XPOS));
-            nneg += __popcll(__ballot(kd == (int)KIND_XNEG));
+        // four chunks per round: their loads are in flight together
+        int q = 0;
+        for (int g0 = 64 * wid; g0 < st_end; g0 += 4 * nt) {
+            uint4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int gu = g0 + u * nt;
+                v[u] = make_uint4(0u, 0u, 0u, 0u);
+                if (gu < st_end) {
+                    uint32_t c;
+                    int off;
+                    chunk_src(gu, lane, q, pre_v, seg_cell, c, off);
+                    if (gu + lane < st_end) v[u] = recb[(size_t)c * cap + off];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int gl = g0 + u * nt + lane;
+                if (gl < st_end) {
+                    uint4 w = v[u];
+                    w.w = charge_code(w.w);
+                    pool[pl.st_off + gl] = w;
+                }
+            }
         }
     }
-    // trials of this domain: the state-independent schedule
-    const int ntr = a.trials * ncell + ((m0a + mca + m0b + mcb) * a.site_trials + 15) / 16;
-    int react0 = 2, react1 = 2;
-    int nreact = 1;
+    const bool spill = nb_total > st_end;
+    if (spill && tid == 0) atomicOr(a.err, INFO_UNSTAGED);
+
+    // ---- own lists, ln table, cores -----------------------------------------
+    double* lnt = reinterpret_cast<double*>(pool + pl.ln_off);
+    uint4* lcore = pool + pl.core_off;
+    double* lcdel = reinterpret_cast<double*>(pool + pl.cdel_off);
     {
-        const bool ha = m0a + mca > 0, hb = m0b + mcb > 0;
+        // one round loads a share of every table, all in flight together
+        const int len = max(max(n0, n1), max(pl.nln, pl.ncl));
+        for (int i = tid; i < len; i += nt) {
+            uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0, cx = r0;
+            double l = 0.0, dl = 0.0;
+            if (i < n0) r0 = recb[(size_t)G.cell0 * cap + i];
+            if (i < n1) r1 = recb[(size_t)G.cell1 * cap + i];
+            if (i < pl.nln) l = a.lntab[i];
+            if (i < pl.ncl) { cx = core_g[i]; dl = cdel_g[i]; }
+            if (i < n0) pool[i] = r0;
+            if (i < n1) pool[pl.room0 + i] = r1;
+            if (i < pl.nln) lnt[i] = l;
+            if (i < pl.ncl) { lcore[i] = cx; lcdel[i] = dl; }
+        }
+    }
+    if (wpd > 1) __syncthreads(); else wave_sync();
+
+    // ---- counts per member ----------------------------------------------------
+    MemberCounts c0 = count_member(pool, 0, n0, lane);
+    MemberCounts c1 = count_member(pool, pl.room0, n1, lane);
+    const int nsites = c0.a0 + c0.ac + c0.b0 + c0.bc + c1.a0 + c1.ac + c1.b0 + c1.bc;
+    // trials of this domain: the state-independent schedule
+    const int ntr = rfl(a.trials * ncell + (nsites * a.site_trials + 15) / 16);
+    int react0 = 2, react1 = 2, nreact = 1;
+    {
+        const bool ha = c0.a0 + c0.ac + c1.a0 + c1.ac > 0, hb = c0.b0 + c0.bc + c1.b0 + c1.bc > 0;
         if (ha && hb) { react0 = 0; react1 = 1; nreact = 3; }
         else if (ha) { react0 = 0; nreact = 2; }
         else if (hb) { react0 = 1; nreact = 2; }
     }
 
     // insertion regions and volume terms of the members (tables built on the host)
-    const uint32_t o0 = R.tab->o[0], o1 = R.tab->o[1], o2 = R.tab->o[2];
     const uint32_t* bnd = R.bnd;
     const double lnk = ncell == 2 ? a.ln2 : 0.0;
     uint32_t ib0[3], iw0[3], ib1[3], iw1[3];
-    {
-        const uint32_t oo[3] = {o0, o1, o2};
 #pragma unroll
-        for (int dd = 0; dd < 3; ++dd) {
-            const uint32_t l0 = bnd[cc0[dd]], h0 = bnd[cc0[dd] + 1];
-            const uint32_t l1 = bnd[cc1[dd]], h1 = bnd[cc1[dd] + 1];
-            ib0[dd] = oo[dd] + l0; iw0[dd] = h0 - l0;
-            ib1[dd] = oo[dd] + l1; iw1[dd] = h1 - l1;
-        }
+    for (int dd = 0; dd < 3; ++dd) {
+        const uint32_t oo = R.tab->o[dd];
+        const uint32_t l0 = bnd[G.cc0[dd]], h0 = bnd[G.cc0[dd] + 1];
+        const uint32_t l1 = bnd[G.cc1[dd]], h1 = bnd[G.cc1[dd] + 1];
+        ib0[dd] = oo + l0; iw0[dd] = h0 - l0;
+        ib1[dd] = oo + l1; iw1[dd] = h1 - l1;
     }
-    const double lnZm0 = (R.lnZ0 + lnk) + ((R.lnW[cc0[0]] + R.lnW[cc0[1]]) + R.lnW[cc0[2]]);
-    const double lnZm1 = (R.lnZ0 + lnk) + ((R.lnW[cc1[0]] + R.lnW[cc1[1]]) + R.lnW[cc1[2]]);
+    const double lnZm0 = (R.lnZ0 + lnk) + ((R.lnW[G.cc0[0]] + R.lnW[G.cc0[1]]) + R.lnW[G.cc0[2]]);
+    const double lnZm1 = (R.lnZ0 + lnk) + ((R.lnW[G.cc1[0]] + R.lnW[G.cc1[1]]) + R.lnW[G.cc1[2]]);
 
     PairParams P;
     P.scale_f = (float)R.scale;
@@ -570,74 +749,106 @@ __global__ __launch_bounds__(NT) void k_phase(SweepArgs a)
     const bool ev_on = a.eps > 0.0 && a.ion_coupling;
     const double lnKA = R.lnKA, lnKB = R.lnKB, lnKion = R.lnKion;
 
+    // attempts and accepts per move, three 21-bit fields per word (moves 0-2, 3-5)
+    uint64_t attL = 0, attH = 0, acpL = 0, acpH = 0;
+    int dA = 0, dB = 0, dXp = 0, dXm = 0; // changes of nA-, nB+, nX+, nX-
     double dE = 0.0;
+    uint32_t ph0 = 0, ph1 = 0, ph2 = 0, ph3 = 0;
+    int nred = 0;
     for (int t = 0; t < ntr; ++t) {
-        // 20 Philox words: lane b of every wavefront computes block b
-        uint32_t wl[4];
-        philox4x32_10((uint32_t)s, cell0, (uint32_t)t * 8u + (uint32_t)(lane < 5 ? lane : 0), TAG_TRIAL,
-                      key0, key1, wl);
+        // the loop-carried state is uniform: keep it in scalar registers
+        n0 = rfl(n0);
+        n1 = rfl(n1);
+        c0 = rfl_counts(c0);
+        c1 = rfl_counts(c1);
+        nred = rfl(nred);
+        // Philox words, twelve trials at a time: lane 5i + b holds block b of
+        // trial i of the batch
+        const int tl = t % 12;
+        if (tl == 0) {
+            uint32_t w[4];
+            philox4x32_10((uint32_t)s, G.cell0, (uint32_t)(t + lane / 5) * 8u + (uint32_t)(lane % 5), TAG_TRIAL,
+                          key0, key1, w);
+            ph0 = w[0]; ph1 = w[1]; ph2 = w[2]; ph3 = w[3];
+        }
         uint32_t W[20];
 #pragma unroll
-        for (int i = 0; i < 20; ++i) W[i] = (uint32_t)__builtin_amdgcn_readlane((int)wl[i & 3], i >> 2);
+        for (int b = 0; b < 5; ++b) {
+            const int src = 5 * tl + b;
+            W[4 * b + 0] = rdl(ph0, src);
+            W[4 * b + 1] = rdl(ph1, src);
+            W[4 * b + 2] = rdl(ph2, src);
+            W[4 * b + 3] = rdl(ph3, src);
+        }
 
         const uint32_t kk = pick32(W[0], (uint32_t)(2 * nreact));
         const int rsel = (int)(kk >> 1);
         const int reaction = rsel == 0 ? react0 : (rsel == 1 ? react1 : 2);
-        const int move = 2 * reaction + (int)(kk & 1u);
-        const double u = unit53(W[16], W[17]);
+        const int move = rfl(2 * reaction + (int)(kk & 1u));
+        const double u = rfld(unit53(W[16], W[17]));
+        const int m0a = c0.a0 + c1.a0, mca = c0.ac + c1.ac, m0b = c0.b0 + c1.b0, mcb = c0.bc + c1.bc;
+        const int npos = c0.xp + c1.xp, nneg = c0.xn + c1.xn;
 
-        // participants: A is the site (moves 0-3) or the cation (4, 5); B is the ion
-        int a_idx = -1, b_idx = -1; // domain-order indices of existing participants
+        // participants: A is the site (moves 0-3) or the cation (4, 5); B is the
+        // ion deleted with it.  Each is the k-th of its class in domain order.
+        int a_mem = -1, a_own = -1, b_mem = -1, b_own = -1;
         bool auto_reject = false;
         double lnp_counts = 0.0;
+        uint32_t am = 0, av = 0, bm = 0, bv = 0; // classes (mask, value); mask 0: none
+        int ak = 0, bk = 0, ac0 = 0, bc0 = 0;   // rank in the domain, count in member 0
         switch (move) {
         case 0:
-            if (m0a == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && !rec_charged(m); },
-                               (int)pick32(W[1], (uint32_t)m0a));
-            lnp_counts = lnt[m0a] - lnt[mca + 1] - lnt[npos + 1] + lnKA;
+            auto_reject = m0a == 0;
+            am = CLS_MASK_SITE; av = KIND_ACID; ak = (int)pick32(W[1], (uint32_t)m0a); ac0 = c0.a0;
+            if (!auto_reject) lnp_counts = lnt[m0a] - lnt[mca + 1] - lnt[npos + 1] + lnKA;
             break;
         case 1:
-            if (mca == 0 || npos == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_ACID && rec_charged(m); },
-                               (int)pick32(W[1], (uint32_t)mca));
-            b_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
-                               (int)pick32(W[2], (uint32_t)npos));
-            lnp_counts = lnt[mca] + lnt[npos] - lnt[m0a + 1] - lnKA;
+            auto_reject = mca == 0 || npos == 0;
+            am = CLS_MASK_SITE; av = KIND_ACID | 8u; ak = (int)pick32(W[1], (uint32_t)mca); ac0 = c0.ac;
+            bm = CLS_MASK_ION; bv = KIND_XPOS; bk = (int)pick32(W[2], (uint32_t)npos); bc0 = c0.xp;
+            if (!auto_reject) lnp_counts = lnt[mca] + lnt[npos] - lnt[m0a + 1] - lnKA;
             break;
         case 2:
-            if (m0b == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && !rec_charged(m); },
-                               (int)pick32(W[1], (uint32_t)m0b));
-            lnp_counts = lnt[m0b] - lnt[mcb + 1] - lnt[nneg + 1] + lnKB;
+            auto_reject = m0b == 0;
+            am = CLS_MASK_SITE; av = KIND_BASE; ak = (int)pick32(W[1], (uint32_t)m0b); ac0 = c0.b0;
+            if (!auto_reject) lnp_counts = lnt[m0b] - lnt[mcb + 1] - lnt[nneg + 1] + lnKB;
             break;
         case 3:
-            if (mcb == 0 || nneg == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_BASE && rec_charged(m); },
-                               (int)pick32(W[1], (uint32_t)mcb));
-            b_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
-                               (int)pick32(W[3], (uint32_t)nneg));
-            lnp_counts = lnt[mcb] + lnt[nneg] - lnt[m0b + 1] - lnKB;
+            auto_reject = mcb == 0 || nneg == 0;
+            am = CLS_MASK_SITE; av = KIND_BASE | 8u; ak = (int)pick32(W[1], (uint32_t)mcb); ac0 = c0.bc;
+            bm = CLS_MASK_ION; bv = KIND_XNEG; bk = (int)pick32(W[3], (uint32_t)nneg); bc0 = c0.xn;
+            if (!auto_reject) lnp_counts = lnt[mcb] + lnt[nneg] - lnt[m0b + 1] - lnKB;
             break;
         case 4:
             lnp_counts = -lnt[npos + 1] - lnt[nneg + 1] + lnKion;
             break;
         default:
-            if (npos == 0 || nneg == 0) { auto_reject = true; break; }
-            a_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XPOS; },
-                               (int)pick32(W[2], (uint32_t)npos));
-            b_idx = domain_kth(pl, n0, n1, [](uint32_t m) { return rec_kind(m) == (int)KIND_XNEG; },
-                               (int)pick32(W[3], (uint32_t)nneg));
-            lnp_counts = lnt[npos] + lnt[nneg] - lnKion;
+            auto_reject = npos == 0 || nneg == 0;
+            am = CLS_MASK_ION; av = KIND_XPOS; ak = (int)pick32(W[2], (uint32_t)npos); ac0 = c0.xp;
+            bm = CLS_MASK_ION; bv = KIND_XNEG; bk = (int)pick32(W[3], (uint32_t)nneg); bc0 = c0.xn;
+            if (!auto_reject) lnp_counts = lnt[npos] + lnt[nneg] - lnKion;
             break;
         }
-        if (tid == 0) S.att[move] += 1u;
+        if (!auto_reject) {
+#pragma unroll 1
+            for (int pidx = 0; pidx < 2; ++pidx) {
+                const uint32_t cm = pidx ? bm : am, cv = pidx ? bv : av;
+                if (!cm) continue;
+                const int k = pidx ? bk : ak, k0 = pidx ? bc0 : ac0;
+                const int mem = k < k0 ? 0 : 1;
+                const int own = rfl(member_kth(pool, mem ? pl.room0 : 0, mem ? n1 : n0, cm, cv, mem ? k - k0 : k,
+                                               lane));
+                if (pidx) { b_mem = mem; b_own = own; } else { a_mem = mem; a_own = own; }
+            }
+        }
+        const uint64_t mv_one = 1ull << (21 * (move % 3));
+        if (move < 3) attL += mv_one; else attH += mv_one;
         if (auto_reject) {
             if (tid == 0 && a.log) {
                 const unsigned long long li = atomicAdd(a.log_n, 1ull);
                 if (li < a.log_cap) {
                     TrialRec& L = a.log[li];
-                    L.sweep = (int64_t)s; L.cell = cell0; L.trial = t; L.replica = (int32_t)r;
+                    L.sweep = (int64_t)s; L.cell = G.cell0; L.trial = t; L.replica = (int32_t)r;
                     L.move = move; L.status = 2;
                     L.dU = __longlong_as_double(0x7FF8000000000000ll); L.lnp = L.dU; L.u = u;
                 }
@@ -645,23 +856,23 @@ __global__ __launch_bounds__(NT) void k_phase(SweepArgs a)
             continue;
         }
 
-        // ---- the two changed particles -------------------------------------
+        // ---- the two changed particles (uniform) ------------------------------
         Chg A, B;
         double lnvol = 0.0;
+        const bool insertion = move == 0 || move == 2 || move == 4;
         if (move <= 3) {
             // A: the site flips
-            A.member = a_idx < n0 ? 0 : 1;
-            A.own = a_idx < n0 ? a_idx : a_idx - n0;
-            const uint4 rc = smem[pl.base(A.member) + A.own];
-            A.x = rc.x; A.y = rc.y; A.z = rc.z;
-            const int chg = rec_charged(rc.w);
-            const int sgn = rec_kind(rc.w) == (int)KIND_ACID ? -1 : 1;
+            const uint4 rc = pool[pl.base(a_mem) + a_own];
+            A.member = a_mem; A.own = a_own;
+            A.x = rflu(rc.x); A.y = rflu(rc.y); A.z = rflu(rc.z);
+            const uint32_t mw = rflu(rc.w);
+            const int chg = rec_charged(mw);
+            const int sgn = rec_kind(mw) == (int)KIND_ACID ? -1 : 1;
             A.q_old = sgn * chg; A.q_new = sgn * (1 - chg);
             A.dq = A.q_new - A.q_old; A.dw = 0; A.ion = 0; A.pres_old = 1; A.pres_new = 1;
         }
-        const bool insertion = move == 0 || move == 2 || move == 4;
-        // B (and A for salt moves): ions in or out
         {
+            // B (and A for salt moves): ions in or out
             const int qB = (move <= 1) ? 1 : -1; // cation for acid moves, anion otherwise
             B.ion = 1;
             B.q_old = insertion ? 0 : qB;
@@ -681,11 +892,10 @@ __global__ __launch_bounds__(NT) void k_phase(SweepArgs a)
                 B.z = (j ? ib1[2] : ib0[2]) + pick64(W[wo + 4], W[wo + 5], j ? iw1[2] : iw0[2]);
                 lnvol += j ? lnZm1 : lnZm0;
             } else {
-                B.member = b_idx < n0 ? 0 : 1;
-                B.own = b_idx < n0 ? b_idx : b_idx - n0;
-                const uint4 rc = smem[pl.base(B.member) + B.own];
-                B.x = rc.x; B.y = rc.y; B.z = rc.z;
-                lnvol -= B.member ? lnZm1 : lnZm0;
+                const uint4 rc = pool[pl.base(b_mem) + b_own];
+                B.member = b_mem; B.own = b_own;
+                B.x = rflu(rc.x); B.y = rflu(rc.y); B.z = rflu(rc.z);
+                lnvol -= b_mem ? lnZm1 : lnZm0;
             }
         }
         if (move >= 4) {
@@ -705,75 +915,102 @@ __global__ __launch_bounds__(NT) void k_phase(SweepArgs a)
                 A.z = (j ? ib1[2] : ib0[2]) + pick64(W[8], W[9], j ? iw1[2] : iw0[2]);
                 lnvol += j ? lnZm1 : lnZm0;
             } else {
-                A.member = a_idx < n0 ? 0 : 1;
-                A.own = a_idx < n0 ? a_idx : a_idx - n0;
-                const uint4 rc = smem[pl.base(A.member) + A.own];
-                A.x = rc.x; A.y = rc.y; A.z = rc.z;
-                lnvol -= A.member ? lnZm1 : lnZm0;
+                const uint4 rc = pool[pl.base(a_mem) + a_own];
+                A.member = a_mem; A.own = a_own;
+                A.x = rflu(rc.x); A.y = rflu(rc.y); A.z = rflu(rc.z);
+                lnvol -= a_mem ? lnZm1 : lnZm0;
             }
         }
+        uniform_chg(A);
+        uniform_chg(B);
+        lnvol = rfld(lnvol);
+        lnp_counts = rfld(lnp_counts);
         // per-member growth check against the cell capacity
         const int gA = A.pres_new - A.pres_old, gB = B.pres_new - B.pres_old;
         const int grow0 = (A.member == 0 ? gA : 0) + (B.member == 0 ? gB : 0);
         const int grow1 = (A.member == 1 ? gA : 0) + (B.member == 1 ? gB : 0);
         const bool cap_fail = n0 + grow0 > (int)cap || n1 + grow1 > (int)cap;
 
-        // ---- energy change: every wavefront sums a share of the records ------
-        double acc = 0.0;
+        // ---- energy change: every lane sums a share of the records -----------
+        // member j's own list (changing: read from the pool), its staged
+        // neighbour slots, and any neighbours left in memory
+        double aqA = 0.0, aqB = 0.0, aw = 0.0;
         int ov = 0;
+#pragma unroll 1
         for (int j = 0; j < ncell; ++j) {
             const bool inA = A.member == j, inB = B.member == j;
             if (!inA && !inB) continue;
-            const int obase = pl.base(j);
-            const int no = j ? n1 : n0;
-            const int skipA = inA ? A.own : -1, skipB = inB ? B.own : -1;
-            const int nbb = j ? nbb1 : 0, nbc = j ? nbc1 : nbc0;
-            const int total = no + nbc;
-            for (int g = tid; g < total; g += NT) {
-                uint4 rc;
-                if (g < no) {
-                    if (g == skipA || g == skipB) continue;
-                    rc = smem[obase + g];
-                } else {
-                    const int q = nbb + (g - no);
-                    rc = staged ? smem[pl.nb_off + q] : neighbour_global(S, recb, cap, q);
+            const int bs = pl.base(j), nn = j ? n1 : n0;
+            const int skA = inA ? A.own : -1, skB = inB ? B.own : -1;
+            for (int g0 = 0; g0 < nn; g0 += nt) {
+                const int g = g0 + tid;
+                const bool v = g < nn && g != skA && g != skB;
+                const uint4 rc = pool[bs + min(g, nn - 1)];
+                const uint32_t code = charge_code(rc.w);
+                if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov);
+                if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov);
+            }
+            const int lo = j ? nbc0 : 0, hi = j ? nb_total : nbc0;
+            const int s1 = min(hi, st_end);
+#pragma unroll 2
+            for (int g0 = lo; g0 < s1; g0 += nt) {
+                const int g = g0 + tid;
+                const bool v = g < s1;
+                const uint4 rc = pool[pl.st_off + min(g, s1 - 1)];
+                if (inA) pair_acc<Real>(rc, rc.w, v, A, P, aqA, aw, ov);
+                if (inB) pair_acc<Real>(rc, rc.w, v, B, P, aqB, aw, ov);
+            }
+            if (hi > st_end) {
+                int q = 0;
+                const int m0 = max(lo, st_end);
+                for (int g0 = m0 + 64 * wid; g0 < hi; g0 += nt) {
+                    uint32_t c;
+                    int off;
+                    chunk_src(g0, lane, q, pre_v, seg_cell, c, off);
+                    const bool v = g0 + lane < hi;
+                    const uint4 rc = v ? recb[(size_t)c * cap + off] : make_uint4(0u, 0u, 0u, 0u);
+                    const uint32_t code = charge_code(rc.w);
+                    if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov);
+                    if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov);
                 }
-                if (inA) acc += pair_term<Real>(rc, A, P, ov);
-                if (inB) acc += pair_term<Real>(rc, B, P, ov);
             }
         }
-        if (ev_on && ncores) {
-            for (int k = tid; k < (int)ncores; k += NT) {
-                const bool lds = k < MAX_LDS_CORES;
-                const uint4 cx = lds ? S.core[k] : core_g[k];
-                const double dl = lds ? S.core_delta[k] : cdel_g[k];
+        double acc = P.lB * ((double)A.dq * aqA + (double)B.dq * aqB) + aw;
+        if (ev_on && ncores && (A.dw != 0 || B.dw != 0)) {
+            for (int k = tid; k < (int)ncores; k += nt) {
+                const uint4 cx = pl.ncl ? lcore[k] : core_g[k];
+                const double dl = pl.ncl ? lcdel[k] : cdel_g[k];
                 if (A.dw != 0) acc += wca_core<Real>(A, cx, dl, P, ov);
                 if (B.dw != 0) acc += wca_core<Real>(B, cx, dl, P, ov);
             }
         }
         if (tid == 0) acc += changed_pair<Real>(A, B, P, ev_on, ov);
-        const double wsum = wave_sum(acc);
-        const int wov = __ballot(ov) != 0ull;
-        const int par = t & 1;
-        if (lane == 0) { S.red[par][wave] = wsum; S.ovf[par][wave] = wov; }
-        __syncthreads();
-        double dU = S.red[par][0];
-        int any_ov = S.ovf[par][0];
-#pragma unroll
-        for (int w = 1; w < NT / 64; ++w) {
-            dU += S.red[par][w];
-            any_ov |= S.ovf[par][w];
+        double dU = wave_sum_dpp(acc);
+        int any_ov = __ballot(ov) != 0ull;
+        if (wpd > 1) {
+            // alternate buffers by reduction: between two writes of one buffer
+            // every wavefront has passed the other reduction's barrier, so it
+            // has read the first
+            const int par = nred & 1;
+            ++nred;
+            if (lane == 0) { red[par][wid] = dU; ovf[par][wid] = any_ov; }
+            __syncthreads();
+            dU = ((red[par][0] + red[par][1]) + red[par][2]) + red[par][3];
+            any_ov = ovf[par][0] | ovf[par][1] | ovf[par][2] | ovf[par][3];
         }
-        if (any_ov) dU = __longlong_as_double(0x7FF0000000000000ll);
+        // every lane holds the same sums: make that explicit, so that the
+        // decision and the loop stay scalar
+        dU = rfld(dU);
+        if (rfl(any_ov)) dU = __longlong_as_double(0x7FF0000000000000ll);
         const double lnp = lnp_counts + lnvol - dU;
-        const bool accept = !cap_fail && u < exp(lnp < 0.0 ? lnp : 0.0);
+        const bool accept = rfl(!cap_fail && u < exp(lnp < 0.0 ? lnp : 0.0)) != 0;
         if (tid == 0) {
             if (cap_fail) atomicOr(a.err, ERR_INSERT_CAPACITY);
             if (a.log) {
                 const unsigned long long li = atomicAdd(a.log_n, 1ull);
                 if (li < a.log_cap) {
                     TrialRec& L = a.log[li];
-                    L.sweep = (int64_t)s; L.cell = cell0; L.trial = t; L.replica = (int32_t)r;
+                    L.sweep = (int64_t)s; L.cell = G.cell0; L.trial = t; L.replica = (int32_t)r;
                     L.move = move; L.status = accept ? 1 : 0;
                     L.dU = dU; L.lnp = lnp; L.u = u;
                 }
@@ -783,14 +1020,10 @@ __global__ __launch_bounds__(NT) void k_phase(SweepArgs a)
 
         // ---- commit: flip; deletions (higher index first within one cell);
         //      insertions appended, cation before anion -----------------------
+        if (move < 3) acpL += mv_one; else acpH += mv_one;
+        dE += dU;
         if (tid == 0) {
-            S.acc[move] += 1u;
-            dE += dU;
-            if (move <= 3) {
-                uint4& rc = smem[pl.base(A.member) + A.own];
-                rc.w ^= 8u;
-                S.dtot[move <= 1 ? 0 : 1] += rec_charged(rc.w) ? 1 : -1;
-            }
+            if (move <= 3) pool[pl.base(A.member) + A.own].w ^= 8u;
             int l0 = n0, l1 = n1;
             if (!insertion) {
                 // deleted: B always; A too for the salt move
@@ -799,78 +1032,102 @@ __global__ __launch_bounds__(NT) void k_phase(SweepArgs a)
                     // the cation (A) first unless the anion sits higher in the same cell
                     dm0 = A.member; di0 = A.own; dm1 = B.member; di1 = B.own;
                     if (dm0 == dm1 && di1 > di0) {
-                        int t0 = di0; di0 = di1; di1 = t0;
+                        const int t0 = di0; di0 = di1; di1 = t0;
                     }
                 }
                 {
-                    int& cnt = dm0 ? l1 : l0;
+                    int& cn = dm0 ? l1 : l0;
                     const int bs = pl.base(dm0);
-                    smem[bs + di0] = smem[bs + cnt - 1];
-                    --cnt;
+                    pool[bs + di0] = pool[bs + cn - 1];
+                    --cn;
                 }
                 if (dm1 >= 0) {
-                    int& cnt = dm1 ? l1 : l0;
+                    int& cn = dm1 ? l1 : l0;
                     const int bs = pl.base(dm1);
-                    smem[bs + di1] = smem[bs + cnt - 1];
-                    --cnt;
+                    pool[bs + di1] = pool[bs + cn - 1];
+                    --cn;
                 }
             } else {
                 if (move == 4) {
-                    int& cnt = A.member ? l1 : l0;
-                    smem[pl.base(A.member) + cnt] = make_uint4(A.x, A.y, A.z, make_meta(KIND_XPOS, 1u, NO_SITE));
-                    ++cnt;
+                    int& cn = A.member ? l1 : l0;
+                    pool[pl.base(A.member) + cn] = make_uint4(A.x, A.y, A.z, make_meta(KIND_XPOS, 1u, NO_SITE));
+                    ++cn;
                 }
-                int& cnt = B.member ? l1 : l0;
-                smem[pl.base(B.member) + cnt] =
+                int& cn = B.member ? l1 : l0;
+                pool[pl.base(B.member) + cn] =
                     make_uint4(B.x, B.y, B.z, make_meta(B.q_new > 0 ? KIND_XPOS : KIND_XNEG, 1u, NO_SITE));
-                ++cnt;
+                ++cn;
             }
-            if (move == 0 || move == 4) S.dtot[2] += 1;
-            if (move == 2 || move == 4) S.dtot[3] += 1;
-            if (move == 1 || move == 5) S.dtot[2] -= 1;
-            if (move == 3 || move == 5) S.dtot[3] -= 1;
+        }
+        // counts
+        apply_counts(c0, move, A.member == 0, B.member == 0);
+        apply_counts(c1, move, A.member == 1, B.member == 1);
+        {
+            const int sg = (move & 1) ? -1 : 1;
+            dA += move <= 1 ? sg : 0;
+            dB += (move == 2 || move == 3) ? sg : 0;
+            dXp += (move <= 1 || move >= 4) ? sg : 0;
+            dXm += move >= 2 ? sg : 0;
         }
         n0 += grow0;
         n1 += grow1;
-        switch (move) {
-        case 0: m0a--; mca++; npos++; break;
-        case 1: m0a++; mca--; npos--; break;
-        case 2: m0b--; mcb++; nneg++; break;
-        case 3: m0b++; mcb--; nneg--; break;
-        case 4: npos++; nneg++; break;
-        default: npos--; nneg--; break;
-        }
-        __syncthreads();
+        if (wpd > 1) __syncthreads(); else wave_sync();
     }
 
-    // ---- write the domain's cells back --------------------------------------
-    __syncthreads();
-    for (int i = tid; i < n0; i += NT) recb[(size_t)cell0 * cap + i] = smem[i];
-    for (int i = tid; i < n1; i += NT) recb[(size_t)cell1 * cap + i] = smem[pl.room0 + i];
-    if (tid == 0 && a.trace) {
-        const unsigned long long ti = atomicAdd(a.trace_n, 1ull);
-        if (ti < a.trace_cap) {
-            PhaseTrace& T = a.trace[ti];
-            T.t0 = t_start;
-            T.t1 = wall_clock64();
-            T.sweep = (uint32_t)s; T.domain = gd; T.colour = colour; T.ntr = ntr;
-            T.nb = nb_total; T.own = n0 + n1; T.staged = staged;
-            T.hw = (int32_t)__smid();
-        }
-    }
+    // ---- write the domain's cells back ----------------------------------------
+    if (wpd > 1) __syncthreads(); else wave_sync();
+    for (int i = tid; i < n0; i += nt) recb[(size_t)G.cell0 * cap + i] = pool[i];
+    for (int i = tid; i < n1; i += nt) recb[(size_t)G.cell1 * cap + i] = pool[pl.room0 + i];
     if (tid == 0) {
-        cntb[cell0] = (uint32_t)n0;
-        if (ncell == 2) cntb[cell1] = (uint32_t)n1;
-        if (dE != 0.0) R.e_acc[cell0] += dE;
+        cntb[G.cell0] = (uint32_t)n0;
+        if (ncell == 2) cntb[G.cell1] = (uint32_t)n1;
+        if (dE != 0.0) R.e_acc[G.cell0] += dE;
         for (int i = 0; i < 6; ++i) {
-            if (S.att[i]) atomicAdd((unsigned long long*)&R.moves[i], (unsigned long long)S.att[i]);
-            if (S.acc[i]) atomicAdd((unsigned long long*)&R.moves[6 + i], (unsigned long long)S.acc[i]);
+            const int sh = 21 * (i % 3);
+            const unsigned long long na = ((i < 3 ? attL : attH) >> sh) & 0x1FFFFFull;
+            const unsigned long long nc = ((i < 3 ? acpL : acpH) >> sh) & 0x1FFFFFull;
+            if (na) atomicAdd((unsigned long long*)&R.moves[i], na);
+            if (nc) atomicAdd((unsigned long long*)&R.moves[6 + i], nc);
         }
-        for (int i = 0; i < 4; ++i)
-            if (S.dtot[i]) atomicAdd((unsigned long long*)&R.totals[i], (unsigned long long)(long long)S.dtot[i]);
+        if (dA) atomicAdd((unsigned long long*)&R.totals[0], (unsigned long long)(long long)dA);
+        if (dB) atomicAdd((unsigned long long*)&R.totals[1], (unsigned long long)(long long)dB);
+        if (dXp) atomicAdd((unsigned long long*)&R.totals[2], (unsigned long long)(long long)dXp);
+        if (dXm) atomicAdd((unsigned long long*)&R.totals[3], (unsigned long long)(long long)dXm);
+        if (a.trace) {
+            const unsigned long long ti = atomicAdd(a.trace_n, 1ull);
+            if (ti < a.trace_cap) {
+                PhaseTrace& T = a.trace[ti];
+                T.t0 = t_start;
+                T.t1 = wall_clock64();
+                T.sweep = (uint32_t)s; T.domain = gd; T.colour = colour; T.ntr = ntr;
+                T.nb = nb_total; T.own = n0 + n1; T.staged = spill ? 0 : 1;
+                T.hw = (int32_t)(wpd * 1000 + (int)__smid());
+            }
+        }
     }
 }
 
+extern __shared__ uint4 smem[];
+
+// heavy domains first (one workgroup each), then light ones (four per
+// workgroup, one per wavefront); the grid is an upper bound
+template <typename Real>
+__global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
+{
+    __shared__ double red[2][4];
+    __shared__ int ovf[2][4];
+    const int colour = a.colour;
+    const uint32_t nh = a.plan_n[2 * colour], nl = a.plan_n[2 * colour + 1];
+    const uint32_t b = blockIdx.x;
+    const int wave = (int)(threadIdx.x >> 6);
+    const bool heavy = b < nh;
+    const uint32_t j = heavy ? b : (b - nh) * 4u + (uint32_t)wave;
+    if (!heavy && j >= nl) return;
+    const int q = heavy ? a.pool : a.pool / 4;
+    const uint32_t gd = heavy ? a.plan_heavy[(size_t)colour * a.ndom_total + j]
+                              : a.plan_light[(size_t)colour * a.ndom_total + j];
+    run_domain<Real>(a, gd, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0, heavy ? 4 : 1, red, ovf);
+}
 
 // ------------------------------------------------------------------------
 // k_sweep_end: series row, group histograms, advance the sweep counter
@@ -984,21 +1241,19 @@ hipError_t launch_bin(const SweepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename Real>
-static hipError_t launch_phase_t(const SweepArgs& a, size_t lds, hipStream_t s)
+hipError_t launch_plan(const SweepArgs& a, hipStream_t s)
 {
-    switch (a.phase_threads) {
-    case 64: hipLaunchKernelGGL((k_phase<Real, 64>), dim3(a.ndom_total), dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((k_phase<Real, 128>), dim3(a.ndom_total), dim3(128), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_phase<Real, 512>), dim3(a.ndom_total), dim3(512), lds, s, a); break;
-    default: hipLaunchKernelGGL((k_phase<Real, 256>), dim3(a.ndom_total), dim3(256), lds, s, a); break;
-    }
+    hipLaunchKernelGGL(k_plan, dim3((a.ndom_total + 63u) / 64u, 8), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_phase(const SweepArgs& a, size_t lds, hipStream_t s)
 {
-    return a.precision == 64 ? launch_phase_t<double>(a, lds, s) : launch_phase_t<float>(a, lds, s);
+    if (a.precision == 64)
+        hipLaunchKernelGGL(k_phase<double>, dim3(a.ndom_total), dim3(PHASE_THREADS), lds, s, a);
+    else
+        hipLaunchKernelGGL(k_phase<float>, dim3(a.ndom_total), dim3(PHASE_THREADS), lds, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_end(const SweepArgs& a, hipStream_t s)
@@ -1025,10 +1280,7 @@ hipError_t launch_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k
 
 hipError_t set_phase_lds_limit(size_t bytes)
 {
-    const void* fns[] = {(const void*)k_phase<float, 64>, (const void*)k_phase<float, 128>,
-                         (const void*)k_phase<float, 256>, (const void*)k_phase<float, 512>,
-                         (const void*)k_phase<double, 64>, (const void*)k_phase<double, 128>,
-                         (const void*)k_phase<double, 256>, (const void*)k_phase<double, 512>};
+    const void* fns[] = {(const void*)k_phase<float>, (const void*)k_phase<double>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
