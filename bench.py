@@ -1,11 +1,14 @@
 #!/usr/bin/env python
 """Benchmark of the CR-MC hot path on one MI355X.
 
-Workload (default): two oppositely charged nanoparticles (radius 10, 2000
+Workload (default, --workload pair): two oppositely charged nanoparticles (radius 10, 2000
 acid sites with pKa 5 on one, 2000 base sites with pKb 5 on the other,
 centres 25 apart) in a periodic box L = 120 with about 2x10^4 free ions
 (pI_X = 0.668), lB = 2, kappa = 0.5, rc = 8, scanned over pH 3..11 as nine
 replicas advanced together; FP32 pair terms, FP64 sums and acceptance.
+
+--workload chains: the 256-replica batch of uneven weak-acid chains over a
+pH x kappa grid, all replicas advanced by the same launches.
 
 A step is one sweep of every replica: re-binning into the shifted cell grid
 plus the eight colour phases (every cell gets `trials` trials) plus the
@@ -72,16 +75,17 @@ def read_traffic(args):
     return float(kv["bytes_per_launch"])
 
 
-def cpu_baseline(system, cond, trials, site_trials, seconds):
+def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4):
     """The oracle as it stands (plain FP64 C, one core) on the same system at
     one pH, started from the same neutral state; rate over the sweeps of the
     last half of the sample."""
     import oracle
     o = oracle.Oracle(system["L"], system["n_cells"], system["lB"], cond["kappa"], system["rc"],
-                      eps=1.0, seed=2024, replica=4)
+                      eps=1.0, seed=2024, replica=replica)
     o.set_conditions(cond["pH"], cond["pKa"], cond["pKb"], cond["pIX_pos"], cond["pIX_neg"])
     o.set_particles(system["xyz"], system["kind"])
-    o.set_cores(system["core_xyz"], system["core_R"])
+    if len(system.get("core_R", [])):
+        o.set_cores(system["core_xyz"], system["core_R"])
     o.set_schedule(trials, pairing=True, site_trials=site_trials)
     t_start = time.perf_counter()
     marks = []
@@ -103,15 +107,38 @@ def cpu_baseline(system, cond, trials, site_trials, seconds):
                       % (cond["pH"], len(marks), time.perf_counter() - t_start, len(tail), c["nXp"] + c["nXm"])}
 
 
+WORKLOADS = {
+    "pair": "nanoparticle pair: 2000 acid + 2000 base sites, R=10, separation 25, L=120, ~2e4 ions "
+            "(pI_X=0.668), lB=2, kappa=0.5, rc=8; 9 replicas pH 3..11",
+    "chains": "256 weak-acid chains of seeded uneven length 50..2000 (pKa 4.5, pI_S 2), 16x16 grid of "
+              "pH 2..12 x kappa 0.1..1.0, lB=2, rc=6, L_r = 12 ceil(40 (N_r/40)^(1/3) / 12); one launch per phase",
+}
+
+
+def load_workload(name):
+    """(systems, per-replica conditions, model constants) of a workload."""
+    from workloads import config2, config3
+    if name == "pair":
+        c = config2()
+        conds = [dict(pH=pH, pKa=c["pKa"], pKb=c["pKb"], pIX_pos=c["pIX"], pIX_neg=c["pIX"], kappa=c["kappa"])
+                 for pH in c["pH_list"]]
+        return [c] * len(conds), conds, dict(lB=c["lB"], rc=c["rc"])
+    reps = config3()
+    conds = [dict(pH=r["pH"], pKa=r["pKa"], pKb=r["pKb"], pIX_pos=r["pIX"], pIX_neg=r["pIX"], kappa=r["kappa"])
+             for r in reps]
+    return reps, conds, dict(lB=reps[0]["lB"], rc=reps[0]["rc"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="pair")
+    ap.add_argument("--steps", type=int, default=None, help="timed sweeps (default 10000 pair, 1000 chains)")
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--trials", type=int, default=8, help="trials per cell per sweep")
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--site-trials", type=int, default=0, help="extra trials per 16 sites of a domain")
-    ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per domain in records (0 = default)")
+    ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per phase workgroup in records (0 = default)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one in the timed region")
     ap.add_argument("--kernel-steps", type=int, default=400, help="sweeps of the per-kernel event timing pass")
     ap.add_argument("--light-neighbours", type=int, default=0,
@@ -121,6 +148,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (counter calibration) and exit")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 10000 if args.workload == "pair" else 1000
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -134,7 +163,6 @@ def main():
 
     from paper_2109_07527_amd import crmc
     from paper_2109_07527_amd.stats import tau_int
-    from workloads import config2
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -147,16 +175,14 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n, "launches": 10}), flush=True)
         return
-    c = config2()
-    conds = [dict(pH=pH, pKa=c["pKa"], pKb=c["pKb"], pIX_pos=c["pIX"], pIX_neg=c["pIX"], kappa=c["kappa"])
-             for pH in c["pH_list"]]
+    systems, conds, model = load_workload(args.workload)
     R = len(conds)
-    S = crmc.System(n_replicas=R, lB=c["lB"], rc=c["rc"], eps=1.0, precision=args.precision,
+    S = crmc.System(n_replicas=R, lB=model["lB"], rc=model["rc"], eps=1.0, precision=args.precision,
                     trials_per_cell=args.trials, pairing=True, seed=2024, site_trials=args.site_trials,
                     lds_records=args.lds_records, use_graph=not args.no_graph,
                     light_neighbours=args.light_neighbours)
     for r in range(R):
-        S.build_cells(r, c)
+        S.build_cells(r, systems[r])
     S.sweep_ex(conds, args.warmup)
     torch.cuda.synchronize()
     before = [S.observe(r) for r in range(R)]
@@ -182,6 +208,7 @@ def main():
     ms, launches = crmc.crmc_get_timing(S.h)
     crmc.crmc_set_timing(S.h, False)
     trials = sum(sum(a["attempts"]) - sum(b["attempts"]) for a, b in zip(after, before))
+    accepts = sum(sum(a["accepts"]) - sum(b["accepts"]) for a, b in zip(after, before))
     rate = trials / elapsed
 
     # independent samples: per replica, tau_int (in sweeps) of the ionized-site count
@@ -193,8 +220,8 @@ def main():
         t = tau_int(q)
         taus.append(round(t, 2))
         samples += sweeps_per_s / (2.0 * t)
-        alphaA.append(round(float(ser[:, 0].mean()) / after[r]["n_acid"], 5))
-        alphaB.append(round(float(ser[:, 1].mean()) / after[r]["n_base"], 5))
+        alphaA.append(round(float(ser[:, 0].mean()) / max(after[r]["n_acid"], 1), 5))
+        alphaB.append(round(float(ser[:, 1].mean()) / max(after[r]["n_base"], 1), 5))
 
     # roofline of the phase kernel
     n_rec = [0.5 * (a["n_acid"] + a["n_base"] + a["n_xpos"] + a["n_xneg"]
@@ -204,35 +231,46 @@ def main():
     bytes_launch = bytes_sweep / 8.0
     phase_avg_ms = ms[1] / max(launches[1], 1)
     achieved = bytes_launch / (phase_avg_ms * 1e-3) / 1e9
-    traffic = read_traffic(args)
+    traffic = read_traffic(args) if args.workload == "pair" else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_phase", "bytes_per_launch": round(bytes_launch),
                 "avg_launch_ms": round(phase_avg_ms, 5), "timed_launches": int(launches[1])}
 
+    config = {"workload": WORKLOADS[args.workload], "replicas": R, "trials_per_cell": args.trials,
+              "site_trials_per_16": args.site_trials, "graph": not args.no_graph,
+              "light_neighbours": args.light_neighbours, "lds_records": args.lds_records,
+              "schedule": "shifted cells, paired domains",
+              "cells_total": int(sum(cells)), "records_mean": round(float(sum(n_rec)), 1)}
+    if args.workload == "pair":
+        config.update(cells_per_edge=after[0]["n_cells"], cell_capacity=after[0]["cell_capacity"])
     line = {
         "metric": METRIC, "value": round(rate, 1), "unit": "trial moves/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
-        "config": {"workload": "nanoparticle pair: 2000 acid + 2000 base sites, R=10, separation 25, "
-                               "L=120, ~2e4 ions (pI_X=0.668), lB=2, kappa=0.5, rc=8; 9 replicas pH 3..11",
-                   "replicas": R, "trials_per_cell": args.trials, "site_trials_per_16": args.site_trials,
-                   "graph": not args.no_graph, "light_neighbours": args.light_neighbours,
-                   "lds_records": args.lds_records,
-                   "schedule": "shifted cells, paired domains",
-                   "cells_per_edge": after[0]["n_cells"], "cell_capacity": after[0]["cell_capacity"]},
+        "config": config,
         "independent_samples_per_s": round(samples, 1),
-        "tau_int_sweeps": taus, "alpha_acid": alphaA, "alpha_base": alphaB,
-        "kernel_ms": {"bin": round(ms[0] / max(launches[0], 1), 5), "phase": round(phase_avg_ms, 5),
+        "acceptance": round(accepts / max(trials, 1), 4),
+        "kernel_ms": {"bin_plan": round(ms[0] / max(launches[0], 1), 5), "phase": round(phase_avg_ms, 5),
                       "sweep_end": round(ms[2] / max(launches[2], 1), 5)},
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if args.workload == "pair":
+        line.update(tau_int_sweeps=taus, alpha_acid=alphaA, alpha_base=alphaB)
+    else:
+        line.update(tau_int_sweeps_median=float(np.median(taus)), tau_int_sweeps_max=float(np.max(taus)),
+                    alpha_acid_range=[float(np.min(alphaA)), float(np.max(alphaA))])
     if not args.no_cpu_baseline:
-        sysd = dict(c)
-        sysd["n_cells"] = after[0]["n_cells"]
-        line["cpu_baseline"] = cpu_baseline(sysd, conds[4], args.trials, args.site_trials, args.cpu_seconds)
+        rb = 4 if args.workload == "pair" else int(np.argsort([len(sy["kind"]) for sy in systems])[R // 2])
+        sysd = dict(systems[rb])
+        sysd["n_cells"] = after[rb]["n_cells"]
+        sysd["lB"], sysd["rc"] = model["lB"], model["rc"]
+        line["cpu_baseline"] = cpu_baseline(sysd, conds[rb], args.trials, args.site_trials, args.cpu_seconds,
+                                            replica=rb)
+        if args.workload != "pair":
+            line["cpu_baseline"]["sample"] += " (median-length chain, replica %d)" % rb
     print(json.dumps(line), flush=True)
 
 

@@ -292,3 +292,34 @@ def test_light_and_heavy_domains_bit_exact(case, light):
     assert np.array_equal(S.series(0, 0, 12), ser)
     att, acc = o.move_stats()
     assert list(att) == obs["attempts"] and list(acc) == obs["accepts"]
+
+
+def test_uneven_replica_batch_bit_exact():
+    """Replicas of different size, box, screening length and pH advance in the
+    same launches; each must follow the oracle with its own Philox key."""
+    crmc = _gpu()
+    from workloads import random_walk_chain
+    sizes = [(30, 24.0), (70, 36.0), (12, 24.0), (45, 30.0), (90, 36.0)]
+    systems, conds = [], []
+    for i, (n, L) in enumerate(sizes):
+        rng = np.random.default_rng([7, i])
+        xyz = random_walk_chain(n, L, rng)
+        systems.append(dict(L=L, xyz=xyz, kind=np.full(n, 1, np.int32)))
+        pH = 3.5 + 0.6 * i
+        conds.append(_cond(pH, 4.5, 5.0, cf.pIX_from_salt(1.5, pH), cf.pIX_from_salt(1.5, pH), 0.2 + 0.2 * i))
+    model = dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=1)
+    S = crmc.System(n_replicas=len(sizes), lB=2.0, rc=6.0, eps=1.0, precision=64, trials_per_cell=2, seed=31)
+    for r, s in enumerate(systems):
+        S.build_cells(r, L=s["L"], xyz=s["xyz"], kind=s["kind"])
+    nsw = 10
+    S.sweep_ex(conds, nsw)
+    for r, s in enumerate(systems):
+        obs = S.observe(r)
+        assert obs["status"] == 0 and obs["error_flags"] & 11 == 0
+        o = _oracle_for(s, model, conds[r], obs["n_cells"], 2, True, seed=31, replica=r)
+        ser = o.sweeps(nsw)
+        _same_state(S.particles(r), o.particles())
+        assert np.array_equal(S.series(r, 0, nsw), ser), r
+        att, acc = o.move_stats()
+        assert list(att) == obs["attempts"] and list(acc) == obs["accepts"]
+        assert obs["energy"] == pytest.approx(o.running_energy(), rel=1e-9, abs=1e-9)
