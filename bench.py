@@ -143,6 +143,8 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=400, help="sweeps of the per-kernel event timing pass")
     ap.add_argument("--light-neighbours", type=int, default=0,
                     help="neighbour records up to which a domain runs on one wavefront (0 = library default)")
+    ap.add_argument("--autotune", type=int, default=0, metavar="SWEEPS",
+                    help="before the warm-up, time SWEEPS sweeps per launch shape and keep the fastest")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -183,6 +185,9 @@ def main():
                     light_neighbours=args.light_neighbours)
     for r in range(R):
         S.build_cells(r, systems[r])
+    tuned = None
+    if args.autotune:
+        tuned = S.autotune(conds, args.autotune)
     S.sweep_ex(conds, args.warmup)
     torch.cuda.synchronize()
     before = [S.observe(r) for r in range(R)]
@@ -242,6 +247,10 @@ def main():
               "light_neighbours": args.light_neighbours, "lds_records": args.lds_records,
               "schedule": "shifted cells, paired domains",
               "cells_total": int(sum(cells)), "records_mean": round(float(sum(n_rec)), 1)}
+    if tuned is not None:
+        config["autotuned"] = {"light_neighbours": tuned["light_neighbours"], "lds_records": tuned["lds_records"],
+                               "candidates": len(tuned["candidates"]),
+                               "best_ms_per_sweep": round(tuned["best_ms_per_sweep"], 4)}
     if args.workload == "pair":
         config.update(cells_per_edge=after[0]["n_cells"], cell_capacity=after[0]["cell_capacity"])
     line = {

@@ -214,10 +214,34 @@ int crmc_enable_log(crmc_t h, int64_t capacity);
 int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out);
 
 /*
+ * Launch-shape autotuner.  Times sweeps_per_candidate sweeps (after one
+ * warm-up sweep) for every candidate pair of light_neighbours (which domains
+ * run on one wavefront) and LDS pool size (lds_records) that the device and
+ * the cell capacity allow, then keeps the fastest.  Neither knob changes any
+ * result: the chain depends only on the seed, the schedule and the
+ * conditions, so the tuning sweeps are ordinary sweeps of the chain (they
+ * advance it by out->sweeps_used sweeps under per_replica conditions).
+ * Every replica must be built.  Synchronizes.  Errors: CRMC_E_ARG for
+ * sweeps_per_candidate outside 1..100000, CRMC_E_STATE before build; on a
+ * device error the previous launch shape is kept.
+ */
+#define CRMC_TUNE_MAX 32
+typedef struct {
+    int32_t light_neighbours, lds_records; /* chosen launch shape */
+    int32_t n_candidates;
+    int32_t reserved;
+    int64_t sweeps_used;                   /* sweeps the tuning advanced the chain by */
+    double best_ms_per_sweep;
+    double ms_per_sweep[CRMC_TUNE_MAX];    /* per candidate */
+    int32_t cand_light[CRMC_TUNE_MAX], cand_lds[CRMC_TUNE_MAX];
+} crmc_tune;
+int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_candidate, crmc_tune* out);
+
+/*
  * Kernel timing.  While on, every kernel that crmc_sweep / crmc_sweep_ex
  * enqueues is bracketed by HIP events on the library's stream.
  * crmc_get_timing (synchronizes) returns the accumulated device milliseconds
- * and launch counts per kernel kind: [0] re-binning, [1] trial phases,
+ * and launch counts per kernel kind: [0] re-binning and planning, [1] trial phases,
  * [2] end-of-sweep bookkeeping; crmc_set_timing(h, 1) also resets them.
  */
 int crmc_set_timing(crmc_t h, int32_t on);

@@ -58,6 +58,16 @@ class crmc_trial_rec(C.Structure):
                 ("dU", C.c_double), ("lnp", C.c_double), ("u", C.c_double)]
 
 
+TUNE_MAX = 32
+
+
+class crmc_tune(C.Structure):
+    _fields_ = [("light_neighbours", C.c_int32), ("lds_records", C.c_int32), ("n_candidates", C.c_int32),
+                ("reserved", C.c_int32), ("sweeps_used", C.c_int64), ("best_ms_per_sweep", C.c_double),
+                ("ms_per_sweep", C.c_double * TUNE_MAX), ("cand_light", C.c_int32 * TUNE_MAX),
+                ("cand_lds", C.c_int32 * TUNE_MAX)]
+
+
 TRIAL_DTYPE = np.dtype([("sweep", "i8"), ("cell", "i8"), ("trial", "i4"), ("replica", "i4"), ("move", "i4"),
                         ("status", "i4"), ("dU", "f8"), ("lnp", "f8"), ("u", "f8")])
 
@@ -79,6 +89,7 @@ def load():
         "crmc_build_cells": (C.c_int, [vp, i32, d, i32, i32, i32, P(d), P(i32), P(i32), P(i32), i32, P(d), P(d)]),
         "crmc_sweep": (C.c_int, [vp, d, d, d, i64]),
         "crmc_sweep_ex": (C.c_int, [vp, P(crmc_cond), i64]),
+        "crmc_autotune": (C.c_int, [vp, P(crmc_cond), i32, P(crmc_tune)]),
         "crmc_observe": (C.c_int, [vp, i32, P(crmc_obs)]),
         "crmc_get_series": (C.c_int, [vp, i32, i64, i64, P(i32)]),
         "crmc_get_particles": (C.c_int, [vp, i32, i32, P(u32), P(i32), P(i32), P(i32), P(i32)]),
@@ -239,6 +250,18 @@ def crmc_philox(ctr, k0, k1):
     return out
 
 
+def crmc_autotune(h, conds, sweeps_per_candidate):
+    arr = (crmc_cond * len(conds))()
+    for i, c in enumerate(conds):
+        arr[i] = crmc_cond(*[float(c[k]) for k in ("pH", "pKa", "pKb", "pIX_pos", "pIX_neg", "kappa")])
+    t = crmc_tune()
+    _check(h, load().crmc_autotune(h, arr, int(sweeps_per_candidate), C.byref(t)))
+    n = t.n_candidates
+    return {"light_neighbours": t.light_neighbours, "lds_records": t.lds_records, "sweeps_used": t.sweeps_used,
+            "best_ms_per_sweep": t.best_ms_per_sweep,
+            "candidates": [(t.cand_light[i], t.cand_lds[i], t.ms_per_sweep[i]) for i in range(n)]}
+
+
 def crmc_set_timing(h, on):
     return _check(h, load().crmc_set_timing(h, int(bool(on))))
 
@@ -342,6 +365,9 @@ class System:
 
     def sweep_ex(self, conds, n_sweeps):
         return crmc_sweep_ex(self.h, conds, n_sweeps)
+
+    def autotune(self, conds, sweeps_per_candidate=10):
+        return crmc_autotune(self.h, conds, sweeps_per_candidate)
 
     def observe(self, replica=0):
         return crmc_observe(self.h, replica)

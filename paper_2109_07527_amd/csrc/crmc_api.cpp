@@ -61,7 +61,7 @@ struct crmc_s {
     int64_t trace_cap = 0;
     int64_t sweeps = 0;
     int pool = DEFAULT_POOL;
-    bool lds_attr_set = false;
+    size_t lds_attr = 0; // dynamic LDS the phase kernel is currently allowed
     hipStream_t stream = nullptr;
     std::string err;
     // kernel timing
@@ -314,7 +314,8 @@ int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n)
                          (uint64_t)lds * 31ull ^ (uint64_t)(uintptr_t)a0.lntab ^
                          (uint64_t)(uintptr_t)a0.trace * 65537ull ^ (uint64_t)a0.trace_cap * 131ull ^
                          (uint64_t)(uintptr_t)a0.plan_heavy * 17ull ^ (uint64_t)(uintptr_t)a0.plan_light * 257ull ^
-                         (uint64_t)(uintptr_t)a0.plan_n * 4099ull;
+                         (uint64_t)(uintptr_t)a0.plan_n * 4099ull ^ (uint64_t)a0.light_nb * 1000033ull ^
+                         (uint64_t)a0.pool * 7777ull;
     if (key != h->gkey) {
         drop_graphs(h);
         h->gkey = key;
@@ -689,9 +690,9 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
     if (lds + 1024 > (size_t)maxlds)
         return fail(h, CRMC_E_ARG, "cell capacity too large for on-chip staging (" + std::to_string(lds) +
                                         " bytes of LDS needed)");
-    if (!h->lds_attr_set) {
+    if (lds > h->lds_attr) {
         HIP_TRY(h, set_phase_lds_limit(lds));
-        h->lds_attr_set = true;
+        h->lds_attr = lds;
     }
     int rc = upload_descriptors(h);
     if (rc) return rc;
@@ -715,6 +716,80 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
         if (rc) return rc;
         h->sweeps++;
     }
+    return CRMC_OK;
+}
+
+int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_candidate, crmc_tune* out)
+{
+    if (!h || !per_replica || !out || sweeps_per_candidate < 1 || sweeps_per_candidate > 100000)
+        return fail(h, CRMC_E_ARG, "invalid autotune arguments");
+    uint32_t maxcap = 0;
+    for (auto& r : h->reps) {
+        if (!r.built) return fail(h, CRMC_E_STATE, "every replica must be built before tuning");
+        maxcap = std::max(maxcap, r.cap);
+    }
+    int dev = 0, maxlds = 0;
+    HIP_TRY(h, hipGetDevice(&dev));
+    HIP_TRY(h, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const int pool_min = (int)(3 * maxcap + 128);
+    const int pool_max = (maxlds - 1024) / (int)sizeof(uint4);
+    const int light_c[] = {256, 512, 768, 1024, 1536};
+    const int pool_c[] = {pool_min, 3072, 4096, 6144, 8192};
+    std::memset(out, 0, sizeof *out);
+    const int keep_light = h->p.light_neighbours, keep_pool = h->pool;
+    const bool keep_timing = h->timing;
+    h->timing = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(h, hipEventCreate(&e0));
+    HIP_TRY(h, hipEventCreate(&e1));
+    double best = 1e300;
+    int best_l = keep_light, best_p = keep_pool, rc = CRMC_OK;
+    for (int pc : pool_c) {
+        if (pc < pool_min || pc > pool_max) continue;
+        bool dup = false;
+        for (int i = 0; i < out->n_candidates; ++i) dup = dup || out->cand_lds[i] == ((pc + 3) & ~3);
+        if (dup) continue;
+        for (int lc : light_c) {
+            if (out->n_candidates >= CRMC_TUNE_MAX) break;
+            h->p.light_neighbours = lc;
+            h->pool = pc;
+            rc = crmc_sweep_ex(h, per_replica, 1); // warm-up: capture, LDS limit
+            if (rc) break;
+            if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = CRMC_E_DEVICE; break; }
+            rc = crmc_sweep_ex(h, per_replica, sweeps_per_candidate);
+            if (rc) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = CRMC_E_DEVICE;
+                break;
+            }
+            const int i = out->n_candidates++;
+            out->cand_light[i] = lc;
+            out->cand_lds[i] = h->pool;
+            out->ms_per_sweep[i] = ms / sweeps_per_candidate;
+            if (out->ms_per_sweep[i] < best) {
+                best = out->ms_per_sweep[i];
+                best_l = lc;
+                best_p = h->pool;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->timing = keep_timing;
+    if (rc) {
+        h->p.light_neighbours = keep_light;
+        h->pool = keep_pool;
+        return rc;
+    }
+    h->p.light_neighbours = best_l;
+    h->pool = best_p;
+    out->light_neighbours = best_l;
+    out->lds_records = best_p;
+    out->best_ms_per_sweep = best;
+    out->sweeps_used = (int64_t)out->n_candidates * (sweeps_per_candidate + 1);
     return CRMC_OK;
 }
 

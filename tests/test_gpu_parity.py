@@ -323,3 +323,26 @@ def test_uneven_replica_batch_bit_exact():
         att, acc = o.move_stats()
         assert list(att) == obs["attempts"] and list(acc) == obs["accepts"]
         assert obs["energy"] == pytest.approx(o.running_energy(), rel=1e-9, abs=1e-9)
+
+
+def test_autotune_keeps_the_chain():
+    """The tuner's sweeps are ordinary sweeps under every launch shape it
+    tries: the chain after tuning plus more sweeps is the oracle's."""
+    crmc = _gpu()
+    make, model, cond = CASES["np_pair_small"]
+    s = make()
+    S = crmc.System(n_replicas=1, lB=model["lB"], rc=model["rc"], eps=model["eps"], precision=64,
+                    trials_per_cell=2, seed=55)
+    S.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"])
+    res = S.autotune([cond], sweeps_per_candidate=2)
+    assert len(res["candidates"]) > 1
+    assert (res["light_neighbours"], res["lds_records"]) in [(c[0], c[1]) for c in res["candidates"]]
+    assert res["sweeps_used"] == 3 * len(res["candidates"])
+    S.sweep_ex([cond], 4)
+    obs = S.observe(0)
+    assert obs["status"] == 0 and obs["error_flags"] & 11 == 0
+    total = res["sweeps_used"] + 4
+    o = _oracle_for(s, model, cond, obs["n_cells"], 2, True, seed=55)
+    ser = o.sweeps(total)
+    _same_state(S.particles(0), o.particles())
+    assert np.array_equal(S.series(0, 0, total), ser)
