@@ -86,6 +86,16 @@ def lib():
         L.orc_cutoff_R2.argtypes = [d, d]
         L.orc_to_fixed.argtypes = [i64, P(d), d, P(u32)]
         L.orc_shift.argtypes = [vp, u64, P(u32)]
+        L.orc_mlp_params.restype = C.c_int
+        L.orc_mlp_logit.restype = d
+        L.orc_mlp_logit.argtypes = [P(d), P(d)]
+        L.orc_mlp_loss_grad.restype = d
+        L.orc_mlp_loss_grad.argtypes = [P(d), P(d), P(d), C.c_int, P(d)]
+        L.orc_adam_step.argtypes = [P(d), P(d), P(d), P(d), i64, d, d, d, d]
+        L.orc_set_learned.restype = C.c_int
+        L.orc_set_learned.argtypes = [vp, P(d), d, C.c_int]
+        L.orc_features_of_cell_sites.restype = C.c_int
+        L.orc_features_of_cell_sites.argtypes = [vp, C.c_int, C.c_int, P(i32), P(d)]
         _lib = L
     return _lib
 
@@ -112,6 +122,41 @@ def to_fixed(xyz, L):
 
 def cutoff_R2(rc, L):
     return int(lib().orc_cutoff_R2(float(rc), float(L)))
+
+
+MLP_IN, MLP_H = 32, 128
+
+
+def mlp_params():
+    """Number of network parameters: W1[128][32], b1[128], W2[128][128],
+    b2[128], w3[128], b3 in that order."""
+    return int(lib().orc_mlp_params())
+
+
+def mlp_logit(par, x):
+    """Network logit for one 32-vector of features (FP64)."""
+    par = np.ascontiguousarray(par, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    return float(lib().orc_mlp_logit(_ptr(par, C.c_double), _ptr(x, C.c_double)))
+
+
+def mlp_loss_grad(par, X, y):
+    """Mean binary cross-entropy over the rows of X (labels y) and its gradient."""
+    par = np.ascontiguousarray(par, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, MLP_IN)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = np.zeros(par.size)
+    loss = lib().orc_mlp_loss_grad(_ptr(par, C.c_double), _ptr(X, C.c_double), _ptr(y, C.c_double),
+                                   X.shape[0], _ptr(g, C.c_double))
+    return float(loss), g
+
+
+def adam_step(par, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In place: one Adam step of par (FP64) with moments m, v at step t >= 1."""
+    for a in (par, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().orc_adam_step(_ptr(par, C.c_double), _ptr(grad, C.c_double), _ptr(m, C.c_double),
+                        _ptr(v, C.c_double), int(t), lr, b1, b2, eps)
 
 
 class Oracle:
@@ -172,6 +217,23 @@ class Oracle:
         radius = np.ascontiguousarray(radius, dtype=np.float64)
         X = np.ascontiguousarray(to_fixed(xyz, self.box).reshape(-1))
         self._L.orc_set_cores(self.h, radius.size, _ptr(X, C.c_uint32), _ptr(radius, C.c_double))
+
+    def set_learned(self, par, eps=0.1, on=True):
+        """Learned site proposal with network parameters par (FP64 values)
+        mixed with the uniform pick at weight eps."""
+        par = np.ascontiguousarray(par, dtype=np.float64)
+        assert par.size == mlp_params()
+        rc = self._L.orc_set_learned(self.h, _ptr(par, C.c_double), float(eps), int(bool(on)))
+        if rc:
+            raise ValueError("eps must lie in (0, 1]")
+
+    def cell_site_features(self, cell, cap=4096):
+        """(site ids, features) of the sites in one cell of the last sweep's grid."""
+        sid = np.zeros(cap, dtype=np.int32)
+        X = np.zeros((cap, MLP_IN))
+        n = self._L.orc_features_of_cell_sites(self.h, int(cell), cap, _ptr(sid, C.c_int32), _ptr(X, C.c_double))
+        n = min(n, cap)
+        return sid[:n], X[:n]
 
     def enable_log(self, cap):
         self._log = (TrialRecord * int(cap))()

@@ -41,6 +41,19 @@
  * distance of the fixed-point coordinates.  A free-ion pair closer than 0.5
  * (or an ion closer than Delta + 0.5 to a core centre) has infinite energy.
  *
+ * Learned proposal (cell mode, optional; not in the paper): the site of an
+ * acid/base move is drawn with probability q(i) = eps/m + (1-eps) w_i / W over
+ * the m eligible sites of the domain, w_i = p_i for a move that ionizes and
+ * 1 - p_i for one that neutralizes, where p_i is the output of a small
+ * multilayer perceptron (32 -> 128 -> 128 -> 1, ReLU, logistic) on the site's
+ * environment: counts of charged particles in 16 equal radial shells within
+ * rc, split into charges opposite to and equal to the site's ionized charge,
+ * over the particles that lie outside the site's own cell.  Those cells are
+ * inactive for the whole colour phase, so p_i is fixed during the domain's
+ * trials and the Metropolis-Hastings ratio q_rev / q_fwd (replacing the
+ * uniform-pick count ratio of Sec. II C) makes every trial satisfy detailed
+ * balance for the frozen environment.
+ *
  * Everything is FP64.  Random numbers are Philox4x32-10 (Salmon, Moraes, Dror,
  * Shaw, SC'11), written here from its published definition.
  */
@@ -144,7 +157,24 @@ typedef struct {
        energy difference and the largest deviation is kept */
     int check_dU;
     double max_dU_err;
+    /* learned proposal */
+    int learned;
+    double lp_eps;
+    double* lp_par;      /* ORC_MLP_PARAMS values */
+    double* lp_phat;     /* per site id: network output for the current phase */
+    int lp_nsites;
+    uint64_t R2sh[17];   /* shell k holds lattice squared distances in [R2sh[k], R2sh[k+1]) */
 } orc_sys;
+
+/* network parameters: W1[128][32], b1[128], W2[128][128], b2[128], w3[128], b3 */
+#define ORC_MLP_IN 32
+#define ORC_MLP_H 128
+#define ORC_MLP_PARAMS (ORC_MLP_H * ORC_MLP_IN + ORC_MLP_H + ORC_MLP_H * ORC_MLP_H + ORC_MLP_H + ORC_MLP_H + 1)
+#define ORC_P_B1 (ORC_MLP_H * ORC_MLP_IN)
+#define ORC_P_W2 (ORC_P_B1 + ORC_MLP_H)
+#define ORC_P_B2 (ORC_P_W2 + ORC_MLP_H * ORC_MLP_H)
+#define ORC_P_W3 (ORC_P_B2 + ORC_MLP_H)
+#define ORC_P_B3 (ORC_P_W3 + ORC_MLP_H)
 
 /* ------------------------------------------------------------------------- */
 /* Small helpers                                                              */
@@ -321,7 +351,178 @@ void orc_destroy(orc_sys* S)
     if (!S) return;
     for (int c = 0; c < S->ncells; ++c) free(S->cells[c].p);
     free(S->cells); free(S->flat); free(S->P); free(S->core_x); free(S->core_delta);
+    free(S->lp_par); free(S->lp_phat);
     free(S);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Learned proposal: features and network                                     */
+/* ------------------------------------------------------------------------- */
+int orc_mlp_params(void) { return ORC_MLP_PARAMS; }
+
+/* logit of the network for one feature vector */
+double orc_mlp_logit(const double* par, const double* x)
+{
+    double h1[ORC_MLP_H], h2[ORC_MLP_H];
+    for (int o = 0; o < ORC_MLP_H; ++o) {
+        double a = par[ORC_P_B1 + o];
+        for (int i = 0; i < ORC_MLP_IN; ++i) a += par[o * ORC_MLP_IN + i] * x[i];
+        h1[o] = a > 0.0 ? a : 0.0;
+    }
+    for (int o = 0; o < ORC_MLP_H; ++o) {
+        double a = par[ORC_P_B2 + o];
+        for (int i = 0; i < ORC_MLP_H; ++i) a += par[ORC_P_W2 + o * ORC_MLP_H + i] * h1[i];
+        h2[o] = a > 0.0 ? a : 0.0;
+    }
+    double z = par[ORC_P_B3];
+    for (int i = 0; i < ORC_MLP_H; ++i) z += par[ORC_P_W3 + i] * h2[i];
+    return z;
+}
+
+/* site probability used by the proposal: the logistic of the logit, kept
+   inside [1e-6, 1 - 1e-6] so that every eligible site has positive weight */
+static double site_prob(double z)
+{
+    double p = 1.0 / (1.0 + exp(-z));
+    if (p < 1e-6) p = 1e-6;
+    if (p > 1.0 - 1e-6) p = 1.0 - 1e-6;
+    return p;
+}
+
+/* Mean binary cross-entropy of the network over n labelled feature vectors
+   and its gradient with respect to every parameter (backpropagation). */
+double orc_mlp_loss_grad(const double* par, const double* X, const double* y, int n, double* grad)
+{
+    double loss = 0.0;
+    if (grad) memset(grad, 0, sizeof(double) * ORC_MLP_PARAMS);
+    for (int r = 0; r < n; ++r) {
+        const double* x = X + (size_t)r * ORC_MLP_IN;
+        double a1[ORC_MLP_H], h1[ORC_MLP_H], a2[ORC_MLP_H], h2[ORC_MLP_H];
+        for (int o = 0; o < ORC_MLP_H; ++o) {
+            double a = par[ORC_P_B1 + o];
+            for (int i = 0; i < ORC_MLP_IN; ++i) a += par[o * ORC_MLP_IN + i] * x[i];
+            a1[o] = a;
+            h1[o] = a > 0.0 ? a : 0.0;
+        }
+        for (int o = 0; o < ORC_MLP_H; ++o) {
+            double a = par[ORC_P_B2 + o];
+            for (int i = 0; i < ORC_MLP_H; ++i) a += par[ORC_P_W2 + o * ORC_MLP_H + i] * h1[i];
+            a2[o] = a;
+            h2[o] = a > 0.0 ? a : 0.0;
+        }
+        double z = par[ORC_P_B3];
+        for (int i = 0; i < ORC_MLP_H; ++i) z += par[ORC_P_W3 + i] * h2[i];
+        /* BCE with logits: softplus(z) - y z, stable form */
+        loss += (z > 0.0 ? z + log1p(exp(-z)) : log1p(exp(z))) - y[r] * z;
+        if (!grad) continue;
+        const double dz = (1.0 / (1.0 + exp(-z)) - y[r]) / n;
+        double d2[ORC_MLP_H], d1[ORC_MLP_H];
+        grad[ORC_P_B3] += dz;
+        for (int i = 0; i < ORC_MLP_H; ++i) {
+            grad[ORC_P_W3 + i] += dz * h2[i];
+            d2[i] = a2[i] > 0.0 ? dz * par[ORC_P_W3 + i] : 0.0;
+        }
+        for (int i = 0; i < ORC_MLP_H; ++i) d1[i] = 0.0;
+        for (int o = 0; o < ORC_MLP_H; ++o) {
+            if (d2[o] == 0.0) continue;
+            grad[ORC_P_B2 + o] += d2[o];
+            for (int i = 0; i < ORC_MLP_H; ++i) {
+                grad[ORC_P_W2 + o * ORC_MLP_H + i] += d2[o] * h1[i];
+                d1[i] += d2[o] * par[ORC_P_W2 + o * ORC_MLP_H + i];
+            }
+        }
+        for (int o = 0; o < ORC_MLP_H; ++o) {
+            const double g = a1[o] > 0.0 ? d1[o] : 0.0;
+            if (g == 0.0) continue;
+            grad[ORC_P_B1 + o] += g;
+            for (int i = 0; i < ORC_MLP_IN; ++i) grad[o * ORC_MLP_IN + i] += g * x[i];
+        }
+    }
+    return loss / n;
+}
+
+/* one Adam step (Kingma & Ba 2015) on every parameter; m, v are the moment
+   estimates, t the 1-based step number */
+void orc_adam_step(double* par, const double* grad, double* m, double* v, int64_t t, double lr, double b1,
+                   double b2, double eps)
+{
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int i = 0; i < ORC_MLP_PARAMS; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * grad[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * grad[i] * grad[i];
+        par[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
+/* shell of a lattice squared distance below the cutoff: the largest k with
+   R2sh[k] <= d2 (R2sh[0] = 0, R2sh[16] = the cutoff) */
+static int shell_of(const orc_sys* S, uint64_t d2)
+{
+    int k = 15;
+    while (k > 0 && d2 < S->R2sh[k]) --k;
+    return k;
+}
+
+/* Features of site p in cell c: charged particles of the 26 neighbour cells
+   within rc, by shell; x[0..15] charges opposite to the site's ionized
+   charge, x[16..31] equal ones. */
+static void site_features(const orc_sys* S, const orc_particle* p, int c, double* x)
+{
+    int n = S->n;
+    int cx = c % n, cy = (c / n) % n, cz = c / (n * n);
+    int qion = p->kind == ORC_ACID ? -1 : 1;
+    for (int i = 0; i < ORC_MLP_IN; ++i) x[i] = 0.0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy && !dz) continue;
+                int nc = ((cx + dx + n) % n) + n * (((cy + dy + n) % n) + n * ((cz + dz + n) % n));
+                const orc_list* l = &S->cells[nc];
+                for (int j = 0; j < l->n; ++j) {
+                    int q = charge_of(l->p[j].kind, l->p[j].charged);
+                    if (q == 0) continue;
+                    int32_t d[3];
+                    lattice_delta(p->x, l->p[j].x, d);
+                    uint64_t d2 = (uint64_t)((int64_t)d[0] * d[0]) + (uint64_t)((int64_t)d[1] * d[1]) +
+                                  (uint64_t)((int64_t)d[2] * d[2]);
+                    if (d2 >= S->R2) continue;
+                    x[(q * qion < 0 ? 0 : 16) + shell_of(S, d2)] += 1.0;
+                }
+            }
+}
+
+/* features of every site in the cell grid of the current sweep (tests) */
+int orc_features_of_cell_sites(const orc_sys* S, int c, int cap, int32_t* sid, double* X)
+{
+    const orc_list* l = &S->cells[c];
+    int k = 0;
+    for (int j = 0; j < l->n; ++j) {
+        const orc_particle* p = &l->p[j];
+        if (p->kind != ORC_ACID && p->kind != ORC_BASE) continue;
+        if (k < cap) {
+            sid[k] = p->sid;
+            site_features(S, p, c, X + (size_t)k * ORC_MLP_IN);
+        }
+        ++k;
+    }
+    return k;
+}
+
+/* Enable the learned proposal with the given network parameters and uniform
+   mixing eps (0 < eps <= 1; eps = 1 is the plain uniform proposal). */
+int orc_set_learned(orc_sys* S, const double* par, double eps, int on)
+{
+    if (on && (!(eps > 0.0) || eps > 1.0)) return -1;
+    S->learned = on;
+    S->lp_eps = eps;
+    if (!S->lp_par) S->lp_par = (double*)malloc(sizeof(double) * ORC_MLP_PARAMS);
+    if (par) memcpy(S->lp_par, par, sizeof(double) * ORC_MLP_PARAMS);
+    for (int k = 0; k <= 16; ++k) {
+        double t = (k * S->rc / 16.0 / S->L) * TWO32;
+        S->R2sh[k] = (uint64_t)ceil(t * t);
+    }
+    S->R2sh[0] = 0;
+    return 0;
 }
 
 void orc_set_conditions(orc_sys* S, double pH, double pKa, double pKb, double pIXp, double pIXm,
@@ -407,6 +608,12 @@ int orc_set_particles(orc_sys* S, int np, const uint32_t* xyz, const int32_t* ki
         p->charged = is_ion(kind[i]) ? 1 : (charged ? charged[i] : 0);
         p->sid = sid ? sid[i] : (is_ion(kind[i]) ? -1 : i);
     }
+    int maxsid = -1;
+    for (int i = 0; i < np; ++i)
+        if (S->P[i].sid > maxsid) maxsid = S->P[i].sid;
+    free(S->lp_phat);
+    S->lp_nsites = maxsid + 1;
+    S->lp_phat = (double*)calloc((size_t)(maxsid + 2), sizeof(double));
     uint32_t o[3] = {0, 0, 0};
     bin_into_cells(S, o);
     gather_from_cells(S);
@@ -516,6 +723,7 @@ typedef struct {
     int nreact;
     int react[3];
     int paper;
+    const orc_sys* sys; /* learned proposal: weights by site id (NULL: uniform picks) */
 } orc_dom;
 
 /* domain-order index -> (cell j, local index) */
@@ -561,6 +769,55 @@ static int count_of(const orc_dom* D, int kind, int charged)
         if (p->kind == kind && (is_ion(kind) || p->charged == charged)) ++c;
     }
     return c;
+}
+
+/* weight of a site for a move that ionizes (fwd = 1) or neutralizes it */
+static double site_weight(const orc_dom* D, const orc_particle* p, int fwd)
+{
+    double ph = D->sys->lp_phat[p->sid];
+    return fwd ? ph : 1.0 - ph;
+}
+
+/* sum of the weights of the eligible sites of a class */
+static double class_weight(const orc_dom* D, int kind, int charged, int fwd)
+{
+    double w = 0.0;
+    int n = dom_size(D);
+    for (int g = 0; g < n; ++g) {
+        const orc_particle* p = dom_at(D, g);
+        if (p->kind == kind && p->charged == charged) w += site_weight(D, p, fwd);
+    }
+    return w;
+}
+
+/* the learned pick: uniform over the m eligible sites with probability eps
+   (words: e, then k as in the plain pick), otherwise proportional to the
+   weights (a 53-bit uniform t scaled by the total weight W, the first
+   eligible site whose cumulative weight exceeds it; the last one if
+   rounding leaves none) */
+static int learned_pick(const orc_dom* D, int kind, int charged, int fwd, int m, double W, uint32_t we,
+                        uint32_t wk, uint32_t wt0, uint32_t wt1)
+{
+    double eps = D->sys->lp_eps;
+    if ((double)we * (1.0 / TWO32) < eps) return kth(D, kind, charged, (int)pick32(wk, (uint32_t)m));
+    double target = unit53(wt0, wt1) * W, cum = 0.0;
+    int n = dom_size(D), last = -1;
+    for (int g = 0; g < n; ++g) {
+        const orc_particle* p = dom_at(D, g);
+        if (p->kind != kind || p->charged != charged) continue;
+        cum += site_weight(D, p, fwd);
+        last = g;
+        if (cum > target) return g;
+    }
+    return last;
+}
+
+/* log of the learned proposal probability of site p among m eligible sites of
+   total weight W */
+static double ln_q(const orc_dom* D, const orc_particle* p, int fwd, int m, double W)
+{
+    double eps = D->sys->lp_eps;
+    return log(eps / m + (1.0 - eps) * site_weight(D, p, fwd) / W);
 }
 
 /* insertion point: choose a cell of the domain uniformly (word wc), then a
@@ -656,6 +913,24 @@ static void do_trial(orc_sys* S, orc_dom* D, const uint32_t* w, int64_t cell, in
         del_neg = kth(D, ORC_XNEG, 1, (int)pick32(w[3], (uint32_t)nneg));
         lnp_counts = log((double)npos) + log((double)nneg) - S->lnKion;
         break;
+    }
+    if (D->sys && move <= 3 && !auto_reject) {
+        /* learned site pick: the count ratio of the uniform picks becomes
+           ln q_rev(i | s') - ln q_fwd(i | s) */
+        const int kind = move <= 1 ? ORC_ACID : ORC_BASE, fwd = !(move & 1), ch = move & 1;
+        const int m = kind == ORC_ACID ? (ch ? mca : m0a) : (ch ? mcb : m0b);
+        const int mr = (kind == ORC_ACID ? (ch ? m0a : mca) : (ch ? m0b : mcb)) + 1;
+        const double W = class_weight(D, kind, ch, fwd);
+        site = learned_pick(D, kind, ch, fwd, m, W, w[20], w[1], w[21], w[22]);
+        const orc_particle* ps = dom_at(D, site);
+        const double Wr = class_weight(D, kind, !ch, !fwd) + site_weight(D, ps, !fwd);
+        const double lnq = ln_q(D, ps, !fwd, mr, Wr) - ln_q(D, ps, fwd, m, W);
+        switch (move) {
+        case 0: lnp_counts = lnq - log((double)(npos + 1)) + S->lnKA; break;
+        case 1: lnp_counts = lnq + log((double)npos) - S->lnKA; break;
+        case 2: lnp_counts = lnq - log((double)(nneg + 1)) + S->lnKB; break;
+        default: lnp_counts = lnq + log((double)nneg) - S->lnKB; break;
+        }
     }
     S->attempts[move]++;
     double u = unit53(w[16], w[17]);
@@ -798,9 +1073,9 @@ uint32_t orc_partner(const orc_sys* S, uint64_t sweep, int colour, uint32_t a, u
     return (uint32_t)((c + M - a) % M);
 }
 
-static void trial_words(const orc_sys* S, uint32_t tag, uint32_t c0, uint32_t c1, uint32_t c2base, uint32_t w[20])
+static void trial_words(const orc_sys* S, uint32_t tag, uint32_t c0, uint32_t c1, uint32_t c2base, uint32_t w[24])
 {
-    for (uint32_t b = 0; b < 5; ++b) {
+    for (uint32_t b = 0; b < 6; ++b) {
         uint32_t ctr[4] = {c0, c1, c2base + b, tag};
         orc_philox(ctr, S->key, &w[4 * b]);
     }
@@ -858,9 +1133,22 @@ static void one_sweep(orc_sys* S, int32_t* series)
             if (has_acid) D.react[D.nreact++] = 0;
             if (has_base) D.react[D.nreact++] = 1;
             D.react[D.nreact++] = 2;
+            if (S->learned) {
+                /* the domain's site probabilities: their environment (the
+                   neighbour cells) does not change during this phase */
+                D.sys = S;
+                for (int j = 0; j < D.ncell; ++j)
+                    for (int q = 0; q < D.list[j]->n; ++q) {
+                        const orc_particle* sp = &D.list[j]->p[q];
+                        if (sp->kind != ORC_ACID && sp->kind != ORC_BASE) continue;
+                        double x[ORC_MLP_IN];
+                        site_features(S, sp, D.cell[j], x);
+                        S->lp_phat[sp->sid] = site_prob(orc_mlp_logit(S->lp_par, x));
+                    }
+            }
             int ntr = S->trials * D.ncell + (nsites * S->site_trials + 15) / 16;
             for (int t = 0; t < ntr; ++t) {
-                uint32_t w[20];
+                uint32_t w[24];
                 trial_words(S, TAG_TRIAL, (uint32_t)S->sweep, (uint32_t)D.cell[0], (uint32_t)t * 8u, w);
                 do_trial(S, &D, w, D.cell[0], t);
             }
@@ -900,7 +1188,7 @@ int orc_paper_trials(orc_sys* S, int64_t ntrials, int64_t sample_every, int32_t*
     int64_t cnt[6];
     int64_t row = 0;
     for (int64_t t = 0; t < ntrials; ++t) {
-        uint32_t w[20];
+        uint32_t w[24];
         int64_t g = S->paper_trial++;
         trial_words(S, TAG_PAPER, (uint32_t)g, (uint32_t)(g >> 32), 0u, w);
         whole.n = S->np; whole.cap = S->npcap; whole.p = S->P;
