@@ -103,7 +103,9 @@ typedef struct {
                                  256-thread workgroup (0 = 768; 1..65536).  Results do not
                                  depend on it */
     int32_t use_graph;       /* 1: replay captured HIP graphs of whole sweeps; 0: launch each kernel */
-    int32_t reserved0, reserved1; /* must be 0 */
+    int32_t learned_proposal; /* 1: acid/base sites picked by the learned proposal (see
+                                 crmc_set_proposal); 0: uniform picks */
+    int32_t reserved1;       /* must be 0 */
     double lB;               /* Bjerrum length (sigma) */
     double rc;               /* Coulomb cutoff (sigma) */
     double eps_wca;          /* excluded-volume strength (kT); 0 disables it */
@@ -111,6 +113,7 @@ typedef struct {
     double pKw;              /* water: pOH = pKw - pH */
     double kappa;            /* default inverse screening length (sigma^-1) */
     double pKb;              /* default base pK used by crmc_sweep */
+    double learned_eps;      /* weight of the uniform pick in the learned proposal, in (0, 1] */
     uint64_t seed;           /* Philox key: (seed low word, seed high word ^ replica) */
     void* stream;            /* hipStream_t on which every call is ordered */
 } crmc_params;
@@ -214,6 +217,55 @@ int crmc_enable_log(crmc_t h, int64_t capacity);
 int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out);
 
 /*
+ * Learned site proposal (an extension of the method; the paper picks sites
+ * uniformly, Sec. II C).  For an acid or base move the site is drawn with
+ * probability q(i) = eps/m + (1 - eps) w_i / W over the m eligible sites of
+ * the domain, w_i = p_i for a move that ionizes the site and 1 - p_i for one
+ * that neutralizes it, W their sum; the acceptance uses ln q_rev - ln q_fwd in
+ * place of the count ratio of the uniform pick (detailed balance, eq.
+ * accrat).  p_i is the logistic of a 32 -> 128 -> 128 -> 1 ReLU network on
+ * the site's environment: counts of charged particles within rc outside the
+ * site's own cell, in 16 equal radial shells (exact integer thresholds
+ * ceil((k rc / 16 / L 2^32)^2) on the squared lattice distance), the first 16
+ * for charges opposite to the site's ionized charge, the last 16 for equal
+ * ones.  Those cells are inactive during a colour phase, so the weights are
+ * fixed during the domain's trials.  FP32 runs evaluate the network with BF16
+ * matrix-core products (FP32 accumulation), FP64 runs in FP64.  The extra
+ * random words of a trial come from Philox block 5 of its counter.
+ *
+ * crmc_set_proposal: learned = 1 turns it on with uniform weight eps in
+ *   (0, 1] (eps = 1 is the uniform pick); learned = 0 off.
+ * crmc_set_proposal_weights / crmc_get_proposal_weights: the network's
+ *   CRMC_MLP_PARAMS FP32 parameters, W1[128][32], b1[128], W2[128][128],
+ *   b2[128], w3[128], b3 (rows are output units); setting them restarts Adam.
+ *   Before any are set, all are zero (every site weight 1/2).
+ * crmc_collect_training: while capacity > 0, every sweep appends one row per
+ *   site and phase (32 features, then 1 if the site is ionized at the start
+ *   of the phase) to a device buffer of that many rows (further rows are
+ *   dropped); 0 stops and frees it.  crmc_training_rows / crmc_read_training
+ *   read it back (rows of 33 floats).
+ * crmc_train: epochs over the collected rows in shuffled minibatches of
+ *   batch rows (seeded), mean binary cross-entropy, Adam (lr, betas 0.9 and
+ *   0.999) on FP32 master parameters with BF16 matrix-core forward and
+ *   backward products; last_loss receives the mean loss of the last epoch.
+ * crmc_mlp_forward / crmc_mlp_gradient: the network's logits for n host
+ *   feature rows (n x 32), and the mean-cross-entropy gradient and loss of n
+ *   host rows (n x 33), on the same kernels (checks).
+ * All synchronize; errors: CRMC_E_ARG for invalid arguments, CRMC_E_STATE
+ * for training with fewer rows than one batch.
+ */
+#define CRMC_MLP_PARAMS 20865
+int crmc_set_proposal(crmc_t h, int32_t learned, double eps);
+int crmc_set_proposal_weights(crmc_t h, const float* w, int64_t n);
+int crmc_get_proposal_weights(crmc_t h, float* w, int64_t n);
+int crmc_collect_training(crmc_t h, int64_t capacity);
+int crmc_training_rows(crmc_t h, int64_t* n);
+int crmc_read_training(crmc_t h, int64_t first, int64_t count, float* out);
+int crmc_train(crmc_t h, int32_t epochs, int32_t batch, double lr, uint64_t seed, double* last_loss);
+int crmc_mlp_forward(crmc_t h, const float* X, int32_t n, float* logits);
+int crmc_mlp_gradient(crmc_t h, const float* rows, int32_t n, float* grad, double* loss);
+
+/*
  * Launch-shape autotuner.  Times sweeps_per_candidate sweeps (after one
  * warm-up sweep) for every candidate pair of light_neighbours (which domains
  * run on one wavefront) and LDS pool size (lds_records) that the device and
@@ -241,7 +293,8 @@ int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_can
  * Kernel timing.  While on, every kernel that crmc_sweep / crmc_sweep_ex
  * enqueues is bracketed by HIP events on the library's stream.
  * crmc_get_timing (synchronizes) returns the accumulated device milliseconds
- * and launch counts per kernel kind: [0] re-binning and planning, [1] trial phases,
+ * and launch counts per kernel kind: [0] re-binning, planning and the learned
+ * proposal's feature and network kernels, [1] trial phases,
  * [2] end-of-sweep bookkeeping; crmc_set_timing(h, 1) also resets them.
  */
 int crmc_set_timing(crmc_t h, int32_t on);

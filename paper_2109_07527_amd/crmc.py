@@ -33,9 +33,9 @@ class crmc_params(C.Structure):
                 ("pairing", C.c_int32), ("ion_coupling", C.c_int32), ("lds_records", C.c_int32),
                 ("fixed_grid", C.c_int32), ("site_trials", C.c_int32),
                 ("light_neighbours", C.c_int32), ("use_graph", C.c_int32),
-                ("reserved0", C.c_int32), ("reserved1", C.c_int32),
+                ("learned_proposal", C.c_int32), ("reserved1", C.c_int32),
                 ("lB", C.c_double), ("rc", C.c_double), ("eps_wca", C.c_double), ("rho0NA", C.c_double),
-                ("pKw", C.c_double), ("kappa", C.c_double), ("pKb", C.c_double),
+                ("pKw", C.c_double), ("kappa", C.c_double), ("pKb", C.c_double), ("learned_eps", C.c_double),
                 ("seed", C.c_uint64), ("stream", C.c_void_p)]
 
 
@@ -90,6 +90,15 @@ def load():
         "crmc_sweep": (C.c_int, [vp, d, d, d, i64]),
         "crmc_sweep_ex": (C.c_int, [vp, P(crmc_cond), i64]),
         "crmc_autotune": (C.c_int, [vp, P(crmc_cond), i32, P(crmc_tune)]),
+        "crmc_set_proposal": (C.c_int, [vp, i32, d]),
+        "crmc_set_proposal_weights": (C.c_int, [vp, P(C.c_float), i64]),
+        "crmc_get_proposal_weights": (C.c_int, [vp, P(C.c_float), i64]),
+        "crmc_collect_training": (C.c_int, [vp, i64]),
+        "crmc_training_rows": (C.c_int, [vp, P(i64)]),
+        "crmc_read_training": (C.c_int, [vp, i64, i64, P(C.c_float)]),
+        "crmc_train": (C.c_int, [vp, i32, i32, d, u64, P(d)]),
+        "crmc_mlp_forward": (C.c_int, [vp, P(C.c_float), i32, P(C.c_float)]),
+        "crmc_mlp_gradient": (C.c_int, [vp, P(C.c_float), i32, P(C.c_float), P(d)]),
         "crmc_observe": (C.c_int, [vp, i32, P(crmc_obs)]),
         "crmc_get_series": (C.c_int, [vp, i32, i64, i64, P(i32)]),
         "crmc_get_particles": (C.c_int, [vp, i32, i32, P(u32), P(i32), P(i32), P(i32), P(i32)]),
@@ -262,6 +271,63 @@ def crmc_autotune(h, conds, sweeps_per_candidate):
             "candidates": [(t.cand_light[i], t.cand_lds[i], t.ms_per_sweep[i]) for i in range(n)]}
 
 
+MLP_PARAMS = 20865
+
+
+def crmc_set_proposal(h, learned, eps=0.1):
+    return _check(h, load().crmc_set_proposal(h, int(bool(learned)), float(eps)))
+
+
+def crmc_set_proposal_weights(h, w):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    return _check(h, load().crmc_set_proposal_weights(h, _p(w, C.c_float), w.size))
+
+
+def crmc_get_proposal_weights(h):
+    w = np.zeros(MLP_PARAMS, dtype=np.float32)
+    _check(h, load().crmc_get_proposal_weights(h, _p(w, C.c_float), w.size))
+    return w
+
+
+def crmc_collect_training(h, capacity):
+    return _check(h, load().crmc_collect_training(h, int(capacity)))
+
+
+def crmc_training_rows(h):
+    n = C.c_int64()
+    _check(h, load().crmc_training_rows(h, C.byref(n)))
+    return n.value
+
+
+def crmc_read_training(h, first=0, count=None):
+    if count is None:
+        count = crmc_training_rows(h) - first
+    out = np.zeros((int(count), 33), dtype=np.float32)
+    _check(h, load().crmc_read_training(h, int(first), int(count), _p(out, C.c_float)))
+    return out
+
+
+def crmc_train(h, epochs, batch=256, lr=1e-3, seed=1):
+    loss = C.c_double()
+    _check(h, load().crmc_train(h, int(epochs), int(batch), float(lr), int(seed), C.byref(loss)))
+    return loss.value
+
+
+def crmc_mlp_forward(h, X):
+    X = np.ascontiguousarray(X, dtype=np.float32).reshape(-1, 32)
+    out = np.zeros(X.shape[0], dtype=np.float32)
+    _check(h, load().crmc_mlp_forward(h, _p(X, C.c_float), X.shape[0], _p(out, C.c_float)))
+    return out
+
+
+def crmc_mlp_gradient(h, rows):
+    rows = np.ascontiguousarray(rows, dtype=np.float32).reshape(-1, 33)
+    g = np.zeros(MLP_PARAMS, dtype=np.float32)
+    loss = C.c_double()
+    _check(h, load().crmc_mlp_gradient(h, _p(rows, C.c_float), rows.shape[0], _p(g, C.c_float), C.byref(loss)))
+    return loss.value, g
+
+
 def crmc_set_timing(h, on):
     return _check(h, load().crmc_set_timing(h, int(bool(on))))
 
@@ -317,7 +383,7 @@ class System:
     def __init__(self, n_replicas=1, lB=2.0, rc=6.0, eps=1.0, rho0NA=0.0269424, pKw=14.0, kappa=0.5,
                  pKb=5.0, seed=1234, precision=32, trials_per_cell=1, pairing=True, ion_coupling=True,
                  lds_records=0, fixed_grid=False, site_trials=0, light_neighbours=0, use_graph=True,
-                 stream="torch"):
+                 learned=False, learned_eps=0.1, stream="torch"):
         p = crmc_params()
         p.n_replicas = int(n_replicas)
         p.precision = int(precision)
@@ -329,6 +395,8 @@ class System:
         p.site_trials = int(site_trials)
         p.light_neighbours = int(light_neighbours)
         p.use_graph = int(bool(use_graph))
+        p.learned_proposal = int(bool(learned))
+        p.learned_eps = float(learned_eps)
         p.lB, p.rc, p.eps_wca, p.rho0NA, p.pKw, p.kappa, p.pKb = lB, rc, eps, rho0NA, pKw, kappa, pKb
         p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
         s = current_stream() if stream == "torch" else stream
@@ -365,6 +433,33 @@ class System:
 
     def sweep_ex(self, conds, n_sweeps):
         return crmc_sweep_ex(self.h, conds, n_sweeps)
+
+    def set_proposal(self, learned, eps=0.1):
+        return crmc_set_proposal(self.h, learned, eps)
+
+    def set_proposal_weights(self, w):
+        return crmc_set_proposal_weights(self.h, w)
+
+    def proposal_weights(self):
+        return crmc_get_proposal_weights(self.h)
+
+    def collect_training(self, capacity):
+        return crmc_collect_training(self.h, capacity)
+
+    def training_rows(self):
+        return crmc_training_rows(self.h)
+
+    def read_training(self, first=0, count=None):
+        return crmc_read_training(self.h, first, count)
+
+    def train(self, epochs, batch=256, lr=1e-3, seed=1):
+        return crmc_train(self.h, epochs, batch, lr, seed)
+
+    def mlp_forward(self, X):
+        return crmc_mlp_forward(self.h, X)
+
+    def mlp_gradient(self, rows):
+        return crmc_mlp_gradient(self.h, rows)
 
     def autotune(self, conds, sweeps_per_candidate=10):
         return crmc_autotune(self.h, conds, sweeps_per_candidate)

@@ -53,6 +53,26 @@ struct crmc_s {
     uint32_t* d_plan_n = nullptr;     // per colour: heavy and light domain counts
     uint32_t* d_plan_heavy = nullptr; // per colour: ndom_total domain slots
     uint32_t* d_plan_light = nullptr;
+    // learned proposal
+    bool learned = false;
+    double learn_eps = 0.1;
+    uint32_t* d_act2rep = nullptr;   // active cell (of one phase) -> replica
+    uint32_t nact_total = 0;
+    uint64_t* d_R2sh = nullptr;      // 17 shell thresholds per replica
+    float* d_p32 = nullptr;          // FP32 master parameters
+    double* d_p64 = nullptr;
+    short* d_w1b = nullptr;
+    short* d_w2b = nullptr;
+    float* d_adam_m = nullptr;
+    float* d_adam_v = nullptr;
+    float* d_grad = nullptr;
+    double* d_loss = nullptr;
+    int64_t adam_t = 0;
+    float* d_data = nullptr;         // training rows (32 features + label)
+    unsigned long long* d_data_n = nullptr;
+    int64_t data_cap = 0;
+    bool collecting = false;
+    bool learn_lds_set = false;
     TrialRec* d_log = nullptr;
     unsigned long long* d_log_n = nullptr;
     int64_t log_cap = 0;
@@ -132,7 +152,7 @@ void free_replica(HostReplica& r)
     Replica& d = r.d;
     void* ptrs[] = {d.rec[0], d.rec[1], d.cnt[0], d.cnt[1], d.cnt0, d.e_acc, d.occupancy, d.site_group,
                     d.group_count, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
-                    d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab};
+                    d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab, d.phat};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = Replica{};
@@ -179,6 +199,8 @@ SweepArgs base_args(crmc_t h)
     a.plan_n = h->d_plan_n;
     a.plan_heavy = h->d_plan_heavy;
     a.plan_light = h->d_plan_light;
+    a.learned = h->learned ? 1 : 0;
+    a.learn_eps = h->learn_eps;
     a.trace = h->d_trace;
     a.trace_n = h->d_trace_n;
     a.trace_cap = (uint64_t)h->trace_cap;
@@ -188,14 +210,16 @@ SweepArgs base_args(crmc_t h)
 int upload_descriptors(crmc_t h)
 {
     std::vector<Replica> v(h->reps.size());
-    uint32_t cells = 0, doms = 0;
+    uint32_t cells = 0, doms = 0, acts = 0;
     for (size_t i = 0; i < h->reps.size(); ++i) {
         HostReplica& r = h->reps[i];
         r.d.cell_begin = cells;
         r.d.dom_begin = doms;
+        r.d.act_begin = acts;
         cells += r.ncells;
         const uint32_t M = r.d.h * r.d.h * r.d.h;
         doms += h->p.pairing ? (M + 1u) / 2u : M;
+        acts += M;
         v[i] = r.d;
     }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -238,7 +262,78 @@ int upload_descriptors(crmc_t h)
         h->ncell_total = cells;
         h->ndom_total = doms;
     }
+    if (acts != h->nact_total || !h->d_act2rep) {
+        // active cells of a phase -> replica, and the shell thresholds of the
+        // learned proposal's features: ceil((k rc / 16 / L 2^32)^2), k = 0..16
+        std::vector<uint32_t> a2r(acts);
+        std::vector<uint64_t> sh(17 * h->reps.size());
+        for (size_t i = 0; i < h->reps.size(); ++i) {
+            const HostReplica& r = h->reps[i];
+            const uint32_t M = r.d.h * r.d.h * r.d.h;
+            std::fill(a2r.begin() + r.d.act_begin, a2r.begin() + r.d.act_begin + M, (uint32_t)i);
+            for (int k = 0; k <= 16; ++k) {
+                const double t = (k * h->p.rc / 16.0 / r.L) * TWO32;
+                sh[17 * i + k] = k ? (uint64_t)std::ceil(t * t) : 0;
+            }
+        }
+        if (h->d_act2rep) (void)hipFree(h->d_act2rep);
+        if (h->d_R2sh) (void)hipFree(h->d_R2sh);
+        h->d_act2rep = nullptr;
+        h->d_R2sh = nullptr;
+        HIP_TRY(h, dalloc(&h->d_act2rep, a2r.size()));
+        HIP_TRY(h, dalloc(&h->d_R2sh, sh.size()));
+        HIP_TRY(h, hipMemcpy(h->d_act2rep, a2r.data(), a2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(h->d_R2sh, sh.data(), sh.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+        h->nact_total = acts;
+    }
     return CRMC_OK;
+}
+
+int ensure_params(crmc_t h)
+{
+    if (h->d_p32) return CRMC_OK;
+    HIP_TRY(h, dalloc(&h->d_p32, MLP_PARAMS));
+    HIP_TRY(h, dalloc(&h->d_p64, MLP_PARAMS));
+    HIP_TRY(h, dalloc(&h->d_w1b, MLP_H * MLP_IN));
+    HIP_TRY(h, dalloc(&h->d_w2b, MLP_H * MLP_H));
+    HIP_TRY(h, dalloc(&h->d_adam_m, MLP_PARAMS));
+    HIP_TRY(h, dalloc(&h->d_adam_v, MLP_PARAMS));
+    HIP_TRY(h, dalloc(&h->d_grad, MLP_PARAMS));
+    HIP_TRY(h, dalloc(&h->d_loss, 1));
+    HIP_TRY(h, hipMemset(h->d_p32, 0, MLP_PARAMS * sizeof(float)));
+    HIP_TRY(h, hipMemset(h->d_adam_m, 0, MLP_PARAMS * sizeof(float)));
+    HIP_TRY(h, hipMemset(h->d_adam_v, 0, MLP_PARAMS * sizeof(float)));
+    HIP_TRY(h, hipMemset(h->d_grad, 0, MLP_PARAMS * sizeof(float)));
+    if (!h->learn_lds_set) {
+        HIP_TRY(h, set_learn_lds_limit());
+        h->learn_lds_set = true;
+    }
+    LearnArgs g{};
+    g.p32 = h->d_p32;
+    g.p64 = h->d_p64;
+    g.w1b = h->d_w1b;
+    g.w2b = h->d_w2b;
+    HIP_TRY(h, launch_params_convert(g, h->stream)); // all-zero network: every site weight 1/2
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return CRMC_OK;
+}
+
+LearnArgs learn_args(crmc_t h, uint32_t maxcap)
+{
+    LearnArgs g{};
+    g.act2rep = h->d_act2rep;
+    g.nact_total = h->nact_total;
+    g.parts = (maxcap + 63u) / 64u;
+    g.R2sh = h->d_R2sh;
+    g.p32 = h->d_p32;
+    g.p64 = h->d_p64;
+    g.w1b = h->d_w1b;
+    g.w2b = h->d_w2b;
+    g.data = h->collecting ? h->d_data : nullptr;
+    g.data_n = h->d_data_n;
+    g.data_cap = (uint64_t)h->data_cap;
+    g.infer = h->learned ? 1 : 0;
+    return g;
 }
 
 hipError_t event_get(crmc_t h, hipEvent_t* e)
@@ -308,14 +403,17 @@ void drop_graphs(crmc_t h)
 // stream by events.  The kernels read the sweep counter and the conditions
 // from device memory, so a captured graph stays valid across calls; it is
 // recaptured when anything baked into its launch arguments changes.
-int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n)
+int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n, bool use_learn, const LearnArgs& lg)
 {
     const uint64_t key = (uint64_t)(uintptr_t)a0.log * 1000003ull ^ (uint64_t)a0.log_cap * 7919ull ^
                          (uint64_t)lds * 31ull ^ (uint64_t)(uintptr_t)a0.lntab ^
                          (uint64_t)(uintptr_t)a0.trace * 65537ull ^ (uint64_t)a0.trace_cap * 131ull ^
                          (uint64_t)(uintptr_t)a0.plan_heavy * 17ull ^ (uint64_t)(uintptr_t)a0.plan_light * 257ull ^
                          (uint64_t)(uintptr_t)a0.plan_n * 4099ull ^ (uint64_t)a0.light_nb * 1000033ull ^
-                         (uint64_t)a0.pool * 7777ull;
+                         (uint64_t)a0.pool * 7777ull ^ (uint64_t)a0.learned * 99991ull ^
+                         (uint64_t)(a0.learn_eps * 1e12) * 13ull ^ (uint64_t)use_learn * 424243ull ^
+                         (uint64_t)(uintptr_t)lg.data * 3ull ^ (uint64_t)lg.parts * 5ull ^
+                         (uint64_t)(uintptr_t)lg.act2rep * 11ull ^ (uint64_t)(uintptr_t)a0.reps * 101ull;
     if (key != h->gkey) {
         drop_graphs(h);
         h->gkey = key;
@@ -333,7 +431,8 @@ int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n)
             err = enqueue_bin_plan(a, h->gstream);
             for (int col = 0; col < 8 && err == hipSuccess; ++col) {
                 a.colour = col;
-                err = launch_phase(a, lds, h->gstream);
+                if (use_learn) err = launch_learn(a, lg, h->gstream);
+                if (err == hipSuccess) err = launch_phase(a, lds, h->gstream);
             }
             if (err == hipSuccess) err = launch_sweep_end(a, h->gstream);
         }
@@ -395,13 +494,16 @@ int crmc_create(const crmc_params* p, crmc_t* out)
     if (!(p->rc > 1.2) || !(p->lB >= 0.0) || !(p->eps_wca >= 0.0) || !(p->rho0NA > 0.0)) return CRMC_E_ARG;
     if (p->lds_records < 0 || p->site_trials < 0 || p->site_trials > 4096) return CRMC_E_ARG;
     if (p->light_neighbours < 0 || p->light_neighbours > 65536) return CRMC_E_ARG;
-    if (p->reserved0 != 0 || p->reserved1 != 0) return CRMC_E_ARG;
+    if (p->reserved1 != 0 || (p->learned_proposal != 0 && p->learned_proposal != 1)) return CRMC_E_ARG;
+    if (p->learned_proposal && (!(p->learned_eps > 0.0) || p->learned_eps > 1.0)) return CRMC_E_ARG;
     crmc_t h = new (std::nothrow) crmc_s;
     if (!h) return CRMC_E_NOMEM;
     h->p = *p;
     h->reps.resize((size_t)p->n_replicas);
     h->stream = (hipStream_t)p->stream;
     h->pool = p->lds_records > 0 ? p->lds_records : DEFAULT_POOL;
+    h->learned = p->learned_proposal != 0;
+    h->learn_eps = p->learned_proposal ? p->learned_eps : 0.1;
     crmc_cond c{};
     c.pH = 7.0; c.pKa = 4.5; c.pKb = p->pKb; c.pIX_pos = c.pIX_neg = 1.0; c.kappa = p->kappa;
     for (auto& r : h->reps) r.cond = c;
@@ -571,6 +673,7 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     HIP_TRY(h, dalloc(&d.totals, 4));
     HIP_TRY(h, dalloc(&d.moves, 12));
     HIP_TRY(h, dalloc(&d.series, (size_t)series_cap * 4));
+    HIP_TRY(h, dalloc(&d.phat, (size_t)std::max(n, 1)));
     HIP_TRY(h, hipMemcpy(d.rec[0], cells.data(), nrec * sizeof(uint4), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d.cnt[0], counts.data(), ncells * sizeof(uint32_t), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d.cnt[1], 0, ncells * sizeof(uint32_t)));
@@ -697,8 +800,15 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
     int rc = upload_descriptors(h);
     if (rc) return rc;
     SweepArgs a = base_args(h);
+    const bool use_learn = h->learned || h->collecting;
+    LearnArgs lg{};
+    if (use_learn) {
+        rc = ensure_params(h);
+        if (rc) return rc;
+        lg = learn_args(h, maxcap);
+    }
     if (h->p.use_graph && !h->timing) {
-        rc = sweeps_by_graph(h, a, lds, n_sweeps);
+        rc = sweeps_by_graph(h, a, lds, n_sweeps, use_learn, lg);
         if (rc) return rc;
         h->sweeps += n_sweeps;
         return CRMC_OK;
@@ -709,6 +819,10 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
         if (rc) return rc;
         for (int col = 0; col < 8; ++col) {
             a.colour = col;
+            if (use_learn) {
+                rc = timed(h, 0, [&] { return launch_learn(a, lg, st); });
+                if (rc) return rc;
+            }
             rc = timed(h, 1, [&] { return launch_phase(a, lds, st); });
             if (rc) return rc;
         }
@@ -790,6 +904,176 @@ int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_can
     out->lds_records = best_p;
     out->best_ms_per_sweep = best;
     out->sweeps_used = (int64_t)out->n_candidates * (sweeps_per_candidate + 1);
+    return CRMC_OK;
+}
+
+int crmc_set_proposal(crmc_t h, int32_t learned, double eps)
+{
+    if (!h || (learned != 0 && learned != 1)) return fail(h, CRMC_E_ARG, "invalid proposal");
+    if (learned && (!(eps > 0.0) || eps > 1.0)) return fail(h, CRMC_E_ARG, "eps must lie in (0, 1]");
+    h->learned = learned != 0;
+    if (learned) h->learn_eps = eps;
+    return CRMC_OK;
+}
+
+int crmc_set_proposal_weights(crmc_t h, const float* w, int64_t n)
+{
+    if (!h || !w || n != MLP_PARAMS) return fail(h, CRMC_E_ARG, "expected the network's parameters");
+    int rc = ensure_params(h);
+    if (rc) return rc;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(h->d_p32, w, MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
+    LearnArgs g = learn_args(h, 0);
+    HIP_TRY(h, launch_params_convert(g, h->stream));
+    HIP_TRY(h, hipMemsetAsync(h->d_adam_m, 0, MLP_PARAMS * sizeof(float), h->stream));
+    HIP_TRY(h, hipMemsetAsync(h->d_adam_v, 0, MLP_PARAMS * sizeof(float), h->stream));
+    h->adam_t = 0;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return CRMC_OK;
+}
+
+int crmc_get_proposal_weights(crmc_t h, float* w, int64_t n)
+{
+    if (!h || !w || n != MLP_PARAMS) return fail(h, CRMC_E_ARG, "expected room for the network's parameters");
+    int rc = ensure_params(h);
+    if (rc) return rc;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(w, h->d_p32, MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
+    return CRMC_OK;
+}
+
+int crmc_collect_training(crmc_t h, int64_t capacity)
+{
+    if (!h || capacity < 0 || capacity > (int64_t)1 << 28) return fail(h, CRMC_E_ARG, "invalid capacity");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (h->d_data) (void)hipFree(h->d_data);
+    h->d_data = nullptr;
+    h->data_cap = 0;
+    h->collecting = false;
+    if (!h->d_data_n) HIP_TRY(h, dalloc(&h->d_data_n, 1));
+    HIP_TRY(h, hipMemset(h->d_data_n, 0, sizeof(unsigned long long)));
+    if (capacity == 0) return CRMC_OK;
+    HIP_TRY(h, dalloc(&h->d_data, (size_t)capacity * (MLP_IN + 1)));
+    h->data_cap = capacity;
+    h->collecting = true;
+    return CRMC_OK;
+}
+
+int crmc_training_rows(crmc_t h, int64_t* n)
+{
+    if (!h || !n) return CRMC_E_ARG;
+    *n = 0;
+    if (!h->d_data_n) return CRMC_OK;
+    unsigned long long v = 0;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(&v, h->d_data_n, sizeof v, hipMemcpyDeviceToHost));
+    *n = (int64_t)std::min<unsigned long long>(v, (unsigned long long)h->data_cap);
+    return CRMC_OK;
+}
+
+int crmc_read_training(crmc_t h, int64_t first, int64_t count, float* out)
+{
+    int64_t n = 0;
+    int rc = crmc_training_rows(h, &n);
+    if (rc) return rc;
+    if (!out || first < 0 || count < 0 || first + count > n) return fail(h, CRMC_E_ARG, "rows out of range");
+    HIP_TRY(h, hipMemcpy(out, h->d_data + (size_t)first * (MLP_IN + 1), (size_t)count * (MLP_IN + 1) * sizeof(float),
+                         hipMemcpyDeviceToHost));
+    return CRMC_OK;
+}
+
+int crmc_train(crmc_t h, int32_t epochs, int32_t batch, double lr, uint64_t seed, double* last_loss)
+{
+    if (!h || epochs < 0 || batch < 16 || batch > 65536 || !(lr > 0.0)) return fail(h, CRMC_E_ARG, "invalid training");
+    int64_t n = 0;
+    int rc = crmc_training_rows(h, &n);
+    if (rc) return rc;
+    if (n < batch) return fail(h, CRMC_E_STATE, "fewer training rows than one batch");
+    rc = ensure_params(h);
+    if (rc) return rc;
+    LearnArgs g = learn_args(h, 0);
+    int* d_rows = nullptr;
+    HIP_TRY(h, dalloc(&d_rows, (size_t)n));
+    std::vector<int> perm((size_t)n);
+    for (int64_t i = 0; i < n; ++i) perm[(size_t)i] = (int)i;
+    uint64_t st = seed * 6364136223846793005ull + 1442695040888963407ull;
+    double epoch_loss = 0.0;
+    const int64_t nb = n / batch;
+    for (int e = 0; e < epochs; ++e) {
+        for (int64_t i = n - 1; i > 0; --i) { // Fisher-Yates with a 64-bit LCG
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            const int64_t j = (int64_t)((st >> 33) % (uint64_t)(i + 1));
+            std::swap(perm[(size_t)i], perm[(size_t)j]);
+        }
+        if (hipMemcpy(d_rows, perm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(d_rows);
+            return fail(h, CRMC_E_DEVICE, "row upload failed");
+        }
+        hipError_t err = hipMemsetAsync(h->d_loss, 0, sizeof(double), h->stream);
+        for (int64_t b = 0; b < nb && err == hipSuccess; ++b) {
+            err = launch_mlp_grad(g, h->d_data, d_rows + b * batch, batch, 1.0f / batch, h->d_grad, h->d_loss,
+                                  h->stream);
+            ++h->adam_t;
+            const float c1 = (float)(1.0 - std::pow(0.9, (double)h->adam_t));
+            const float c2 = (float)(1.0 - std::pow(0.999, (double)h->adam_t));
+            if (err == hipSuccess) err = launch_adam(g, h->d_grad, h->d_adam_m, h->d_adam_v, (float)lr, c1, c2, h->stream);
+        }
+        double lsum = 0.0;
+        if (err == hipSuccess) err = hipStreamSynchronize(h->stream);
+        if (err == hipSuccess) err = hipMemcpy(&lsum, h->d_loss, sizeof(double), hipMemcpyDeviceToHost);
+        if (err != hipSuccess) {
+            (void)hipFree(d_rows);
+            return fail(h, CRMC_E_DEVICE, std::string("training failed: ") + hipGetErrorString(err));
+        }
+        epoch_loss = lsum / (double)nb;
+    }
+    (void)hipFree(d_rows);
+    if (last_loss) *last_loss = epoch_loss;
+    return CRMC_OK;
+}
+
+int crmc_mlp_forward(crmc_t h, const float* X, int32_t n, float* logits)
+{
+    if (!h || !X || !logits || n < 0) return fail(h, CRMC_E_ARG, "invalid arguments");
+    int rc = ensure_params(h);
+    if (rc) return rc;
+    float *dX = nullptr, *dz = nullptr;
+    HIP_TRY(h, dalloc(&dX, (size_t)n * MLP_IN));
+    HIP_TRY(h, dalloc(&dz, (size_t)n));
+    hipError_t e = hipMemcpy(dX, X, (size_t)n * MLP_IN * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_mlp_fwd(learn_args(h, 0), dX, n, dz, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(logits, dz, (size_t)n * sizeof(float), hipMemcpyDeviceToHost);
+    (void)hipFree(dX);
+    (void)hipFree(dz);
+    if (e != hipSuccess) return fail(h, CRMC_E_DEVICE, hipGetErrorString(e));
+    return CRMC_OK;
+}
+
+int crmc_mlp_gradient(crmc_t h, const float* rows, int32_t n, float* grad, double* loss)
+{
+    if (!h || !rows || !grad || n < 1) return fail(h, CRMC_E_ARG, "invalid arguments");
+    int rc = ensure_params(h);
+    if (rc) return rc;
+    float* dD = nullptr;
+    int* dr = nullptr;
+    HIP_TRY(h, dalloc(&dD, (size_t)n * (MLP_IN + 1)));
+    HIP_TRY(h, dalloc(&dr, (size_t)n));
+    std::vector<int> idx((size_t)n);
+    for (int i = 0; i < n; ++i) idx[(size_t)i] = i;
+    hipError_t e = hipMemcpy(dD, rows, (size_t)n * (MLP_IN + 1) * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dr, idx.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemsetAsync(h->d_grad, 0, MLP_PARAMS * sizeof(float), h->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->d_loss, 0, sizeof(double), h->stream);
+    if (e == hipSuccess) e = launch_mlp_grad(learn_args(h, 0), dD, dr, n, 1.0f / n, h->d_grad, h->d_loss, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(grad, h->d_grad, MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && loss) e = hipMemcpy(loss, h->d_loss, sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemsetAsync(h->d_grad, 0, MLP_PARAMS * sizeof(float), h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    (void)hipFree(dD);
+    (void)hipFree(dr);
+    if (e != hipSuccess) return fail(h, CRMC_E_DEVICE, hipGetErrorString(e));
     return CRMC_OK;
 }
 
@@ -1042,6 +1326,10 @@ void crmc_destroy(crmc_t h)
     if (h->d_plan_n) (void)hipFree(h->d_plan_n);
     if (h->d_plan_heavy) (void)hipFree(h->d_plan_heavy);
     if (h->d_plan_light) (void)hipFree(h->d_plan_light);
+    void* lp[] = {h->d_act2rep, h->d_R2sh, h->d_p32, h->d_p64, h->d_w1b, h->d_w2b, h->d_adam_m, h->d_adam_v,
+                  h->d_grad, h->d_loss, h->d_data, h->d_data_n};
+    for (void* q : lp)
+        if (q) (void)hipFree(q);
     delete h;
 }
 

@@ -19,6 +19,15 @@ constexpr int BIN_THREADS = 256;    // four wavefronts, one new cell each
 constexpr int PHASE_THREADS = 256;  // one heavy domain, or four light domains (one per wavefront)
 constexpr int DEFAULT_LIGHT_NB = 768;
 
+// learned proposal network: W1[128][32], b1[128], W2[128][128], b2[128], w3[128], b3
+constexpr int MLP_IN = 32, MLP_H = 128;
+constexpr int MLP_B1 = MLP_H * MLP_IN;
+constexpr int MLP_W2 = MLP_B1 + MLP_H;
+constexpr int MLP_B2 = MLP_W2 + MLP_H * MLP_H;
+constexpr int MLP_W3 = MLP_B2 + MLP_H;
+constexpr int MLP_B3 = MLP_W3 + MLP_H;
+constexpr int MLP_PARAMS = MLP_B3 + 1;
+
 // Record: three fixed-point coordinates and a meta word
 //   bits 0-2 kind, bit 3 charged flag, bits 8-31 site id (NO_SITE for ions)
 __host__ __device__ inline uint32_t make_meta(uint32_t kind, uint32_t charged, uint32_t sid)
@@ -58,7 +67,8 @@ struct Replica {
     uint32_t key0, key1;
     uint32_t cell_begin;     // prefix of cells over replicas (binning grid)
     uint32_t dom_begin;      // prefix of domains per phase over replicas
-    uint32_t pad0;
+    uint32_t act_begin;      // prefix of active cells per phase over replicas
+    double* phat;            // per site: network output of the current phase (learned proposal)
     double L, scale, lnZ0;   // scale = L / 2^32; lnZ0 = ln(rho0 NA) + 3 ln(scale)
     uint64_t R2;             // Coulomb cutoff on the integer squared distance
     double lnKA, lnKB, lnKion, kappa;
@@ -103,12 +113,30 @@ struct SweepArgs {
     uint32_t* plan_n;      // per colour: heavy count, light count
     uint32_t* plan_heavy;  // per colour: ndom_total slots of domain indices
     uint32_t* plan_light;
+    int32_t learned;   // site picks by the learned proposal
+    double learn_eps;  // weight of the uniform pick in it
     PhaseTrace* trace;
     unsigned long long* trace_n;
     uint64_t trace_cap;
 };
 
-// launchers (device translation unit)
+// arguments of the learned-proposal kernels
+struct LearnArgs {
+    const uint32_t* act2rep;  // global active-cell index (of one phase) -> replica
+    uint32_t nact_total;
+    uint32_t parts;           // workgroups per active cell (64 sites each)
+    const uint64_t* R2sh;     // per replica: 17 shell thresholds on the squared lattice distance
+    float* p32;               // FP32 master parameters
+    double* p64;              // FP64 copy (FP64 inference)
+    short* w1b;               // BF16 W1 [128][32]
+    short* w2b;               // BF16 W2 [128][128]
+    float* data;              // training rows: 32 features + label
+    unsigned long long* data_n;
+    uint64_t data_cap;
+    int32_t infer;            // compute site probabilities (else features / rows only)
+};
+
+// launchers (device translation units)
 hipError_t launch_bin(const SweepArgs& a, hipStream_t s);
 hipError_t launch_plan(const SweepArgs& a, hipStream_t s);
 hipError_t launch_phase(const SweepArgs& a, size_t lds_bytes, hipStream_t s);
@@ -118,5 +146,13 @@ hipError_t launch_energy(const Replica* rep_dev, const Replica& rep_host, double
 hipError_t launch_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,
                          hipStream_t s);
 hipError_t set_phase_lds_limit(size_t bytes);
+hipError_t launch_learn(const SweepArgs& a, const LearnArgs& g, hipStream_t s);
+hipError_t launch_mlp_fwd(const LearnArgs& g, const float* X, int nrows, float* out, hipStream_t s);
+hipError_t launch_mlp_grad(const LearnArgs& g, const float* data, const int* rows, int nrows, float inv_batch,
+                           float* grad, double* loss, hipStream_t s);
+hipError_t launch_adam(const LearnArgs& g, float* grad, float* m, float* v, float lr, float c1, float c2,
+                       hipStream_t s);
+hipError_t launch_params_convert(const LearnArgs& g, hipStream_t s);
+hipError_t set_learn_lds_limit();
 
 } // namespace crmc

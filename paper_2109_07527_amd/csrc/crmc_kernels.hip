@@ -230,11 +230,13 @@ struct Pool {
     int room0, room1;
     int ln_off, nln;
     int core_off, cdel_off, ncl;
+    int aux_off;   // learned proposal: site probability per list slot (doubles)
     int st_off;
     __device__ __forceinline__ int base(int member) const { return member ? room0 : 0; }
 };
 
-__device__ __forceinline__ Pool pool_layout(int n0, int n1, int ncell, int ntr_max, uint32_t cap, uint32_t ncores)
+__device__ __forceinline__ Pool pool_layout(int n0, int n1, int ncell, int ntr_max, uint32_t cap, uint32_t ncores,
+                                            int learned)
 {
     Pool p;
     // room for the growth the trials can cause: two ions per trial
@@ -245,7 +247,8 @@ __device__ __forceinline__ Pool pool_layout(int n0, int n1, int ncell, int ntr_m
     p.core_off = p.ln_off + (p.nln + 1) / 2;
     p.ncl = ncores <= (uint32_t)MAX_LDS_CORES ? (int)ncores : 0;
     p.cdel_off = p.core_off + p.ncl;
-    p.st_off = p.cdel_off + (p.ncl + 1) / 2;
+    p.aux_off = p.cdel_off + (p.ncl + 1) / 2;
+    p.st_off = p.aux_off + (learned ? (p.room0 + p.room1 + 1) / 2 : 0);
     return p;
 }
 
@@ -309,7 +312,7 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
         const int n0 = (int)R.cnt0[G.cell0];
         const int n1 = G.ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
         const int ntr_max = a.trials * G.ncell + ((n0 + n1) * a.site_trials + 15) / 16;
-        const Pool p = pool_layout(n0, n1, G.ncell, ntr_max, R.cap, R.ncores);
+        const Pool p = pool_layout(n0, n1, G.ncell, ntr_max, R.cap, R.ncores, a.learned);
         light = nb <= a.light_nb && p.st_off <= a.pool / 4;
     }
     const uint64_t ml = __ballot(valid && light), mh = __ballot(valid && !light);
@@ -596,6 +599,57 @@ __device__ __forceinline__ int member_kth(const uint4* pool, int base, int nn, u
     return -1;
 }
 
+// Learned pick within one member's list: the first eligible slot (meta &
+// mask == value) whose cumulative weight (p or 1 - p of the slot's site,
+// from aux) exceeds target; the last eligible slot if rounding leaves none.
+__device__ __forceinline__ int member_kth_weighted(const uint4* pool, const double* aux, int base, int nn, uint32_t mask,
+                                                   uint32_t value, bool fwd, double target, int lane)
+{
+    double acc = 0.0;
+    int last = -1;
+    for (int b0 = 0; b0 < nn; b0 += 64) {
+        const int g = b0 + lane;
+        const bool el = g < nn && (pool[base + g].w & mask) == value;
+        const double a = el ? aux[base + g] : 0.0;
+        double c = el ? (fwd ? a : 1.0 - a) : 0.0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const double v = __shfl_up(c, off, 64);
+            if (lane >= off) c += v;
+        }
+        c += acc;
+        const uint64_t hit = __ballot(el && c > target);
+        if (hit) return b0 + (int)__builtin_ctzll(hit);
+        const uint64_t em = __ballot(el);
+        if (em) last = b0 + 63 - (int)__builtin_clzll(em);
+        acc = __shfl(c, 63, 64);
+    }
+    return last;
+}
+
+// per member: sum of p over neutral acids, of 1 - p over charged acids, and
+// the same for bases (the weights of the learned picks)
+struct ClassW {
+    double a0_0, a0_1, ac_0, ac_1, b0_0, b0_1, bc_0, bc_1;
+};
+
+__device__ __forceinline__ void class_sums(const uint4* pool, const double* aux, int base, int nn, int lane,
+                                           double& a0, double& ac, double& b0, double& bc)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int b = lane; b < nn; b += 64) {
+        const uint32_t m = pool[base + b].w;
+        const double p = aux[base + b];
+        const int kd = rec_kind(m), ch = rec_charged(m);
+        if (kd == (int)KIND_ACID) { if (ch) s1 += 1.0 - p; else s0 += p; }
+        if (kd == (int)KIND_BASE) { if (ch) s3 += 1.0 - p; else s2 += p; }
+    }
+    a0 = wave_sum_dpp(s0);
+    ac = wave_sum_dpp(s1);
+    b0 = wave_sum_dpp(s2);
+    bc = wave_sum_dpp(s3);
+}
+
 // class of a participant: meta mask and value
 constexpr uint32_t CLS_MASK_SITE = 0xFu, CLS_MASK_ION = 0x7u;
 // The domain's trials.  wpd wavefronts share the pair sums (wpd = 1: light
@@ -627,7 +681,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     int n0 = (int)R.cnt0[G.cell0];
     int n1 = ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
     const int ntr_max = a.trials * ncell + ((n0 + n1) * a.site_trials + 15) / 16;
-    const Pool pl = pool_layout(n0, n1, ncell, ntr_max, cap, ncores);
+    const Pool pl = pool_layout(n0, n1, ncell, ntr_max, cap, ncores, a.learned);
     if (pl.st_off > pool_records) { // the plan and the host size pools so that this never happens
         if (tid == 0) atomicOr(a.err, ERR_POOL);
         return;
@@ -707,6 +761,23 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     }
     if (wpd > 1) __syncthreads(); else wave_sync();
 
+    // ---- learned proposal: site probabilities of the lists, class weights ------
+    double* aux = reinterpret_cast<double*>(pool + pl.aux_off);
+    ClassW cw{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const bool learned = a.learned != 0;
+    if (learned) {
+        const double* phat = R.phat;
+        for (int i = tid; i < n0 + n1; i += nt) {
+            const int slot = i < n0 ? i : pl.room0 + (i - n0);
+            const uint32_t m = pool[slot].w;
+            const int kd = rec_kind(m);
+            aux[slot] = (kd == (int)KIND_ACID || kd == (int)KIND_BASE) ? phat[m >> 8] : 0.0;
+        }
+        if (wpd > 1) __syncthreads(); else wave_sync();
+        class_sums(pool, aux, 0, n0, lane, cw.a0_0, cw.ac_0, cw.b0_0, cw.bc_0);
+        class_sums(pool, aux, pl.room0, n1, lane, cw.a0_1, cw.ac_1, cw.b0_1, cw.bc_1);
+    }
+
     // ---- counts per member ----------------------------------------------------
     MemberCounts c0 = count_member(pool, 0, n0, lane);
     MemberCounts c1 = count_member(pool, pl.room0, n1, lane);
@@ -762,19 +833,19 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         c0 = rfl_counts(c0);
         c1 = rfl_counts(c1);
         nred = rfl(nred);
-        // Philox words, twelve trials at a time: lane 5i + b holds block b of
-        // trial i of the batch
-        const int tl = t % 12;
+        // Philox words, ten trials at a time: lane 6i + b holds block b of
+        // trial i of the batch (blocks 0-4 every trial, 5 the learned pick)
+        const int tl = t % 10;
         if (tl == 0) {
             uint32_t w[4];
-            philox4x32_10((uint32_t)s, G.cell0, (uint32_t)(t + lane / 5) * 8u + (uint32_t)(lane % 5), TAG_TRIAL,
+            philox4x32_10((uint32_t)s, G.cell0, (uint32_t)(t + lane / 6) * 8u + (uint32_t)(lane % 6), TAG_TRIAL,
                           key0, key1, w);
             ph0 = w[0]; ph1 = w[1]; ph2 = w[2]; ph3 = w[3];
         }
         uint32_t W[20];
 #pragma unroll
         for (int b = 0; b < 5; ++b) {
-            const int src = 5 * tl + b;
+            const int src = 6 * tl + b;
             W[4 * b + 0] = rdl(ph0, src);
             W[4 * b + 1] = rdl(ph1, src);
             W[4 * b + 2] = rdl(ph2, src);
@@ -829,9 +900,27 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
             if (!auto_reject) lnp_counts = lnt[npos] + lnt[nneg] - lnKion;
             break;
         }
+        // learned site pick (moves 0-3): uniform with probability eps (word
+        // 20), else by weight (words 21, 22)
+        bool weighted = false;
+        double lp_w = 0.0, lp_W0 = 0.0, lp_W1 = 0.0;
+        if (learned && move <= 3 && !auto_reject) {
+            const int src = 6 * tl + 5;
+            const uint32_t we = rdl(ph0, src), wt0 = rdl(ph1, src), wt1 = rdl(ph2, src);
+            weighted = !((double)we * (1.0 / 4294967296.0) < a.learn_eps);
+            lp_W0 = move == 0 ? cw.a0_0 : move == 1 ? cw.ac_0 : move == 2 ? cw.b0_0 : cw.bc_0;
+            lp_W1 = move == 0 ? cw.a0_1 : move == 1 ? cw.ac_1 : move == 2 ? cw.b0_1 : cw.bc_1;
+            if (weighted) {
+                const double target = unit53(wt0, wt1) * (lp_W0 + lp_W1);
+                const int mem = (target < lp_W0 && lp_W0 > 0.0) || lp_W1 <= 0.0 ? 0 : 1;
+                a_mem = mem;
+                a_own = rfl(member_kth_weighted(pool, aux, mem ? pl.room0 : 0, mem ? n1 : n0, am, av, !(move & 1),
+                                                mem ? target - lp_W0 : target, lane));
+            }
+        }
         if (!auto_reject) {
 #pragma unroll 1
-            for (int pidx = 0; pidx < 2; ++pidx) {
+            for (int pidx = weighted ? 1 : 0; pidx < 2; ++pidx) {
                 const uint32_t cm = pidx ? bm : am, cv = pidx ? bv : av;
                 if (!cm) continue;
                 const int k = pidx ? bk : ak, k0 = pidx ? bc0 : ac0;
@@ -839,6 +928,25 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const int own = rfl(member_kth(pool, mem ? pl.room0 : 0, mem ? n1 : n0, cm, cv, mem ? k - k0 : k,
                                                lane));
                 if (pidx) { b_mem = mem; b_own = own; } else { a_mem = mem; a_own = own; }
+            }
+            if (learned && move <= 3) {
+                // ln q_rev(i | s') - ln q_fwd(i | s) replaces the count ratio
+                const bool fwd = !(move & 1);
+                const double p_i = rfld(aux[(a_mem ? pl.room0 : 0) + a_own]);
+                const double wi = fwd ? p_i : 1.0 - p_i, wr = 1.0 - wi;
+                const int m = move == 0 ? m0a : move == 1 ? mca : move == 2 ? m0b : mcb;
+                const int mr = (move == 0 ? mca : move == 1 ? m0a : move == 2 ? mcb : m0b) + 1;
+                const double Wr = (move == 0 ? cw.ac_0 + cw.ac_1 : move == 1 ? cw.a0_0 + cw.a0_1
+                                   : move == 2 ? cw.bc_0 + cw.bc_1 : cw.b0_0 + cw.b0_1) + wr;
+                const double eps = a.learn_eps;
+                const double lnq = log(eps / mr + (1.0 - eps) * wr / Wr) - log(eps / m + (1.0 - eps) * wi / (lp_W0 + lp_W1));
+                lp_w = p_i;
+                switch (move) {
+                case 0: lnp_counts = lnq - lnt[npos + 1] + lnKA; break;
+                case 1: lnp_counts = lnq + lnt[npos] - lnKA; break;
+                case 2: lnp_counts = lnq - lnt[nneg + 1] + lnKB; break;
+                default: lnp_counts = lnq + lnt[nneg] - lnKB; break;
+                }
             }
         }
         const uint64_t mv_one = 1ull << (21 * (move % 3));
@@ -1039,24 +1147,39 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                     int& cn = dm0 ? l1 : l0;
                     const int bs = pl.base(dm0);
                     pool[bs + di0] = pool[bs + cn - 1];
+                    if (learned) aux[bs + di0] = aux[bs + cn - 1];
                     --cn;
                 }
                 if (dm1 >= 0) {
                     int& cn = dm1 ? l1 : l0;
                     const int bs = pl.base(dm1);
                     pool[bs + di1] = pool[bs + cn - 1];
+                    if (learned) aux[bs + di1] = aux[bs + cn - 1];
                     --cn;
                 }
             } else {
                 if (move == 4) {
                     int& cn = A.member ? l1 : l0;
                     pool[pl.base(A.member) + cn] = make_uint4(A.x, A.y, A.z, make_meta(KIND_XPOS, 1u, NO_SITE));
+                    if (learned) aux[pl.base(A.member) + cn] = 0.0;
                     ++cn;
                 }
                 int& cn = B.member ? l1 : l0;
                 pool[pl.base(B.member) + cn] =
                     make_uint4(B.x, B.y, B.z, make_meta(B.q_new > 0 ? KIND_XPOS : KIND_XNEG, 1u, NO_SITE));
+                if (learned) aux[pl.base(B.member) + cn] = 0.0;
                 ++cn;
+            }
+        }
+        // class weights of the learned picks: the flipped site changes class
+        if (learned && move <= 3) {
+            const double p = lp_w, q = 1.0 - lp_w;
+            const bool m1 = A.member != 0;
+            switch (move) {
+            case 0: if (m1) { cw.a0_1 -= p; cw.ac_1 += q; } else { cw.a0_0 -= p; cw.ac_0 += q; } break;
+            case 1: if (m1) { cw.ac_1 -= q; cw.a0_1 += p; } else { cw.ac_0 -= q; cw.a0_0 += p; } break;
+            case 2: if (m1) { cw.b0_1 -= p; cw.bc_1 += q; } else { cw.b0_0 -= p; cw.bc_0 += q; } break;
+            default: if (m1) { cw.bc_1 -= q; cw.b0_1 += p; } else { cw.bc_0 -= q; cw.b0_0 += p; } break;
             }
         }
         // counts

@@ -1,0 +1,189 @@
+"""GPU learned proposal against the oracle (needs an MI355X).
+
+The network's BF16 matrix-core forward and backward passes against the FP64
+oracle at the same (BF16-rounded) parameters; the FP64 chain with the learned
+proposal bit for bit against the oracle's; eps = 1 against the plain chain;
+training rows and a short training run.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import random_sites, nanoparticle_pair, config1
+
+pytestmark = pytest.mark.gpu
+NP_ = 20865
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_07527_amd import crmc
+    return crmc
+
+
+def _params(seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    W1 = rng.normal(0, np.sqrt(2.0 / 32), (128, 32)) * scale
+    b1 = rng.normal(0, 0.1, 128)
+    W2 = rng.normal(0, np.sqrt(2.0 / 128), (128, 128)) * scale
+    b2 = rng.normal(0, 0.1, 128)
+    w3 = rng.normal(0, np.sqrt(2.0 / 128), 128) * scale
+    b3 = rng.normal(0, 0.5, 1)
+    return np.concatenate([W1.ravel(), b1, W2.ravel(), b2, w3, b3]).astype(np.float32)
+
+
+def _bf16(x):
+    """round-to-nearest-even to bfloat16, as float64"""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _bf16_params(p32):
+    p = p32.astype(np.float64)
+    p[:4096] = _bf16(p32[:4096])
+    p[4224:4224 + 16384] = _bf16(p32[4224:4224 + 16384])
+    return p
+
+
+def test_forward_matches_oracle():
+    crmc = _gpu()
+    S = crmc.System(n_replicas=1)
+    p = _params(3)
+    S.set_proposal_weights(p)
+    assert np.array_equal(S.proposal_weights(), p)
+    rng = np.random.default_rng(4)
+    X = rng.integers(0, 7, (200, 32)).astype(np.float32)
+    z = S.mlp_forward(X)
+    pr = _bf16_params(p)
+    ref = np.array([oracle.mlp_logit(pr, x) for x in X.astype(np.float64)])
+    # BF16 operands (unit roundoff 2^-9) in both products, the hidden layer
+    # included: about 4e-3 typical, a few times that at worst
+    err = np.abs(z - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.mean() < 5e-3 and err.max() < 3e-2, (err.mean(), err.max())
+
+
+def test_gradient_matches_oracle():
+    crmc = _gpu()
+    S = crmc.System(n_replicas=1)
+    p = _params(5)
+    S.set_proposal_weights(p)
+    rng = np.random.default_rng(6)
+    X = rng.integers(0, 6, (96, 32)).astype(np.float32)
+    y = (rng.random(96) < 0.4).astype(np.float32)
+    loss, g = S.mlp_gradient(np.concatenate([X, y[:, None]], 1))
+    lref, gref = oracle.mlp_loss_grad(_bf16_params(p), X.astype(np.float64), y.astype(np.float64))
+    assert loss == pytest.approx(lref, rel=2e-2)
+    for lo, hi in ((0, 4096), (4096, 4224), (4224, 20608), (20608, 20736), (20736, 20864), (20864, 20865)):
+        d = np.linalg.norm(g[lo:hi] - gref[lo:hi]) / max(np.linalg.norm(gref[lo:hi]), 1e-12)
+        assert d < 2e-2, (lo, hi, d)
+
+
+def _case(name):
+    if name == "mixed":
+        s = random_sites(12, 10, 24.0, 3, min_dist=1.0)
+        s["core_xyz"] = np.array([[12.0, 12.0, 12.0]])
+        s["core_R"] = np.array([3.0])
+        return s, dict(lB=2.0, rc=6.0), dict(pH=6.0, pKa=5.0, pKb=5.0, pIX_pos=0.5, pIX_neg=0.7, kappa=0.5)
+    if name == "np_pair_small":
+        s = nanoparticle_pair(seed=4, L=40.0, R=4.0, sites=120, separation=11.0)
+        return s, dict(lB=2.0, rc=6.0), dict(pH=7.0, pKa=5.0, pKb=5.0, pIX_pos=0.8, pIX_neg=0.8, kappa=0.5)
+    s = config1()
+    return s, dict(lB=2.0, rc=6.0), dict(pH=4.5, pKa=4.5, pKb=5.0, pIX_pos=s["pIX"], pIX_neg=s["pIX"], kappa=0.5)
+
+
+def _run_pair(crmc, name, eps, learned_gpu=True, learned_oracle=True, nsw=12, trials=2, seed=71, scale=2.0):
+    s, m, c = _case(name)
+    p = _params(9, scale)
+    S = crmc.System(n_replicas=1, lB=m["lB"], rc=m["rc"], precision=64, trials_per_cell=trials, seed=seed)
+    kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"])
+    if len(s.get("core_R", [])):
+        kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
+    S.build_cells(0, **kw)
+    S.set_proposal_weights(p)
+    if learned_gpu:
+        S.set_proposal(True, eps)
+    S.sweep_ex([c], nsw)
+    obs = S.observe(0)
+    assert obs["status"] == 0 and obs["error_flags"] & 11 == 0
+    o = oracle.Oracle(s["L"], obs["n_cells"], m["lB"], c["kappa"], m["rc"], seed=seed)
+    o.set_conditions(c["pH"], c["pKa"], c["pKb"], c["pIX_pos"], c["pIX_neg"])
+    o.set_particles(s["xyz"], s["kind"])
+    if len(s.get("core_R", [])):
+        o.set_cores(s["core_xyz"], s["core_R"])
+    o.set_schedule(trials)
+    if learned_oracle:
+        o.set_learned(p.astype(np.float64), eps)
+    ser = o.sweeps(nsw)
+    return S, obs, o, ser, nsw
+
+
+@pytest.mark.parametrize("name", ["mixed", "np_pair_small", "chain40"])
+def test_fp64_learned_chain_bit_exact(name):
+    crmc = _gpu()
+    S, obs, o, ser, nsw = _run_pair(crmc, name, 0.1)
+    for a, b in zip(S.particles(0), o.particles()):
+        assert np.array_equal(np.asarray(a).astype(np.int64), np.asarray(b).astype(np.int64))
+    assert np.array_equal(S.series(0, 0, nsw), ser)
+    att, acc = o.move_stats()
+    assert list(att) == obs["attempts"] and list(acc) == obs["accepts"]
+    assert sum(acc[:4]) > 0
+
+
+def test_uniform_weight_one_is_the_plain_chain():
+    crmc = _gpu()
+    S, obs, o, ser, nsw = _run_pair(crmc, "np_pair_small", 1.0, learned_oracle=False)
+    assert np.array_equal(S.series(0, 0, nsw), ser)
+    for a, b in zip(S.particles(0), o.particles()):
+        assert np.array_equal(np.asarray(a).astype(np.int64), np.asarray(b).astype(np.int64))
+
+
+def test_fp32_learned_chain_statistics():
+    """BF16 network: picks differ from the FP64 oracle near boundaries, so the
+    chains are compared by their means (the nanoparticle pair, 9 acid/base
+    sites' worth of statistics per sweep)."""
+    crmc = _gpu()
+    from paper_2109_07527_amd.stats import mean_se
+    s, m, c = _case("np_pair_small")
+    p = _params(9, 2.0)
+    S = crmc.System(n_replicas=1, lB=2.0, rc=6.0, precision=32, trials_per_cell=4, seed=3, learned=True,
+                    learned_eps=0.1)
+    S.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"])
+    S.set_proposal_weights(p)
+    S.sweep_ex([c], 3000)
+    g = S.series(0, 300, 2700).astype(float)
+    o = oracle.Oracle(s["L"], S.observe(0)["n_cells"], 2.0, 0.5, 6.0, seed=3)
+    o.set_conditions(c["pH"], c["pKa"], c["pKb"], c["pIX_pos"], c["pIX_neg"])
+    o.set_particles(s["xyz"], s["kind"])
+    o.set_cores(s["core_xyz"], s["core_R"])
+    o.set_schedule(4)
+    o.set_learned(p.astype(np.float64), 0.1)
+    r = o.sweeps(1500)[150:].astype(float)
+    for col in (0, 1):
+        m1, s1, _ = mean_se(g[:, col])
+        m2, s2, _ = mean_se(r[:, col])
+        assert abs(m1 - m2) < 4.0 * np.hypot(s1, s2), (col, m1, s1, m2, s2)
+
+
+def test_training_rows_and_a_short_training_run():
+    crmc = _gpu()
+    s, m, c = _case("np_pair_small")
+    S = crmc.System(n_replicas=1, lB=2.0, rc=6.0, precision=32, trials_per_cell=4, seed=3)
+    S.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"])
+    S.sweep_ex([c], 50)
+    S.collect_training(100000)
+    S.sweep_ex([c], 40)
+    n = S.training_rows()
+    assert n == 40 * 240  # every site once per sweep
+    rows = S.read_training()
+    F, y = rows[:, :32], rows[:, 32]
+    assert np.all(F >= 0) and np.array_equal(F, np.round(F)) and set(np.unique(y)) <= {0.0, 1.0}
+    assert 0.0 < y.mean() < 1.0
+    S.set_proposal_weights(_params(11, 0.5))
+    l1 = S.train(1, batch=256, lr=2e-3, seed=1)
+    l5 = S.train(6, batch=256, lr=2e-3, seed=2)
+    assert np.isfinite(l1) and l5 < l1
+    w = S.proposal_weights()
+    assert np.isfinite(w).all() and not np.array_equal(w, _params(11, 0.5))
