@@ -145,6 +145,13 @@ def main():
                     help="neighbour records up to which a domain runs on one wavefront (0 = library default)")
     ap.add_argument("--autotune", type=int, default=0, metavar="SWEEPS",
                     help="before the warm-up, time SWEEPS sweeps per launch shape and keep the fastest")
+    ap.add_argument("--learned", action="store_true",
+                    help="learned site proposal: collect rows from plain sweeps after the warm-up, train the "
+                         "network on the GPU, then time sweeps with the learned proposal")
+    ap.add_argument("--train-rows", type=int, default=1_000_000)
+    ap.add_argument("--epochs", type=int, default=3)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--learned-eps", type=float, default=0.1)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -190,6 +197,24 @@ def main():
         tuned = S.autotune(conds, args.autotune)
     S.sweep_ex(conds, args.warmup)
     torch.cuda.synchronize()
+    learned = None
+    if args.learned:
+        # rows from plain sweeps, BF16 matrix-core training, then the learned proposal
+        per_sweep = sum(int(((sy["kind"] == 1) | (sy["kind"] == 2)).sum()) for sy in systems)
+        S.collect_training(args.train_rows)
+        S.sweep_ex(conds, max(1, -(-args.train_rows // max(per_sweep, 1))))
+        rows = S.training_rows()
+        torch.cuda.synchronize()
+        tt = time.perf_counter()
+        loss = S.train(args.epochs, batch=1024, lr=args.lr, seed=7)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - tt
+        S.collect_training(0)
+        S.set_proposal(True, args.learned_eps)
+        S.sweep_ex(conds, 100)
+        torch.cuda.synchronize()
+        learned = {"train_rows": int(rows), "epochs": args.epochs, "batch": 1024, "lr": args.lr,
+                   "final_loss": round(loss, 5), "train_seconds": round(train_s, 3), "eps": args.learned_eps}
     before = [S.observe(r) for r in range(R)]
 
     # timed region: exactly --steps sweeps, replayed as captured graphs
@@ -247,6 +272,8 @@ def main():
               "light_neighbours": args.light_neighbours, "lds_records": args.lds_records,
               "schedule": "shifted cells, paired domains",
               "cells_total": int(sum(cells)), "records_mean": round(float(sum(n_rec)), 1)}
+    if learned is not None:
+        config["learned_proposal"] = learned
     if tuned is not None:
         config["autotuned"] = {"light_neighbours": tuned["light_neighbours"], "lds_records": tuned["lds_records"],
                                "candidates": len(tuned["candidates"]),

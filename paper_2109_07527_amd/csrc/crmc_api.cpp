@@ -29,6 +29,7 @@ struct HostReplica {
     bool built = false;
     double L = 0.0;
     uint32_t n = 0, cap = 0, ncells = 0, ncores = 0, nsites = 0, ngroups = 0;
+    uint32_t site_bound = 0;  // most non-ion particles any shifted cell can hold
     int64_t nA = 0, nB = 0;
     double E0 = 0.0;          // energy at the last restart of the running sum
     double e0_kappa = 0.0;    // screening length E0 was computed with (NaN: not yet)
@@ -73,6 +74,9 @@ struct crmc_s {
     int64_t data_cap = 0;
     bool collecting = false;
     bool learn_lds_set = false;
+    uint2* d_list = nullptr;         // per phase: listed sites and their features
+    float* d_feat = nullptr;
+    uint32_t list_cap = 0;
     TrialRec* d_log = nullptr;
     unsigned long long* d_log_n = nullptr;
     int64_t log_cap = 0;
@@ -252,10 +256,10 @@ int upload_descriptors(crmc_t h)
         HIP_TRY(h, dalloc(&h->d_cell2rep, c2r.size()));
         HIP_TRY(h, dalloc(&h->d_dom2rep, d2r.size()));
         HIP_TRY(h, dalloc(&h->d_lntab, lt.size()));
-        HIP_TRY(h, dalloc(&h->d_plan_n, 16));
+        HIP_TRY(h, dalloc(&h->d_plan_n, 24));
         HIP_TRY(h, dalloc(&h->d_plan_heavy, (size_t)8 * doms));
         HIP_TRY(h, dalloc(&h->d_plan_light, (size_t)8 * doms));
-        HIP_TRY(h, hipMemset(h->d_plan_n, 0, 16 * sizeof(uint32_t)));
+        HIP_TRY(h, hipMemset(h->d_plan_n, 0, 24 * sizeof(uint32_t)));
         HIP_TRY(h, hipMemcpy(h->d_cell2rep, c2r.data(), c2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(h->d_dom2rep, d2r.data(), d2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(h->d_lntab, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice));
@@ -333,7 +337,27 @@ LearnArgs learn_args(crmc_t h, uint32_t maxcap)
     g.data_n = h->d_data_n;
     g.data_cap = (uint64_t)h->data_cap;
     g.infer = h->learned ? 1 : 0;
+    g.list_n = h->d_plan_n ? h->d_plan_n + 16 : nullptr;
+    g.list = h->d_list;
+    g.feat = h->d_feat;
+    g.list_cap = h->list_cap;
     return g;
+}
+
+// room for every site of every replica in the per-phase list
+int ensure_list(crmc_t h)
+{
+    uint64_t sites = 0;
+    for (auto& r : h->reps) sites += r.nsites;
+    if (sites <= h->list_cap && h->d_list) return CRMC_OK;
+    if (h->d_list) (void)hipFree(h->d_list);
+    if (h->d_feat) (void)hipFree(h->d_feat);
+    h->d_list = nullptr;
+    h->d_feat = nullptr;
+    HIP_TRY(h, dalloc(&h->d_list, (size_t)std::max<uint64_t>(sites, 1)));
+    HIP_TRY(h, dalloc(&h->d_feat, (size_t)std::max<uint64_t>(sites, 1) * MLP_IN));
+    h->list_cap = (uint32_t)std::max<uint64_t>(sites, 1);
+    return CRMC_OK;
 }
 
 hipError_t event_get(crmc_t h, hipEvent_t* e)
@@ -605,6 +629,7 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
         }
         for (uint32_t v : f) site_bound = std::max(site_bound, v);
     }
+    r.site_bound = site_bound;
     uint32_t cap;
     if (cell_capacity == 0) {
         // sites, as many counter-ions again, and room for salt
@@ -804,8 +829,11 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
     LearnArgs lg{};
     if (use_learn) {
         rc = ensure_params(h);
+        if (!rc) rc = ensure_list(h);
         if (rc) return rc;
-        lg = learn_args(h, maxcap);
+        uint32_t sb = 1;
+        for (auto& r : h->reps) sb = std::max(sb, r.site_bound);
+        lg = learn_args(h, sb);
     }
     if (h->p.use_graph && !h->timing) {
         rc = sweeps_by_graph(h, a, lds, n_sweeps, use_learn, lg);
@@ -1327,7 +1355,7 @@ void crmc_destroy(crmc_t h)
     if (h->d_plan_heavy) (void)hipFree(h->d_plan_heavy);
     if (h->d_plan_light) (void)hipFree(h->d_plan_light);
     void* lp[] = {h->d_act2rep, h->d_R2sh, h->d_p32, h->d_p64, h->d_w1b, h->d_w2b, h->d_adam_m, h->d_adam_v,
-                  h->d_grad, h->d_loss, h->d_data, h->d_data_n};
+                  h->d_grad, h->d_loss, h->d_data, h->d_data_n, h->d_list, h->d_feat};
     for (void* q : lp)
         if (q) (void)hipFree(q);
     delete h;

@@ -134,6 +134,10 @@ struct LearnArgs {
     unsigned long long* data_n;
     uint64_t data_cap;
     int32_t infer;            // compute site probabilities (else features / rows only)
+    uint32_t* list_n;         // per colour: listed sites of the phase (cleared by the re-binning)
+    uint2* list;              // (replica, site id) of the listed sites
+    float* feat;              // their features, 32 per row
+    uint32_t list_cap;
 };
 
 // launchers (device translation units)

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     if (s == 0) { oo[0] = oo[1] = oo[2] = 0u; }
     else grid_shift(R.key0, R.key1, s - 1, a.fixed_grid, oo);
 
-    if (gcell == 0 && lane < 16) a.plan_n[lane] = 0u; // the planning kernel that follows counts anew
+    if (gcell == 0 && lane < 24) a.plan_n[lane] = 0u; // plan and learned-proposal list counters of the sweep
     if (k == 0 && lane < 12) {
         // the sweep's table: shift, and the pairing centre of every colour
         const uint32_t M = R.h * R.h * R.h;

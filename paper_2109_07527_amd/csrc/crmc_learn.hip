@@ -1,13 +1,14 @@
 // CDNA4 (gfx950) kernels of the learned site proposal.
 //
-//   k_learn<R>   per colour phase: for the sites of every active cell, the
+//   k_learn      per colour phase: for the sites of every active cell, the
 //                environment features (charged particles of the 26 neighbour
 //                cells within rc, by radial shell and sign relative to the
-//                site's ionized charge) and the network output p = logistic
-//                of a 32 -> 128 -> 128 -> 1 ReLU perceptron; optionally one
-//                labelled training row per site.  R = float: BF16 matrix
-//                cores (v_mfma_f32_16x16x16bf16_1k) with FP32 accumulation;
-//                R = double: FP64 on the vector unit.
+//                site's ionized charge), appended to the phase's list; and
+//                optionally one labelled training row per site.
+//   k_mlp_infer<R> per colour phase: the network output p = logistic of a
+//                32 -> 128 -> 128 -> 1 ReLU perceptron for every listed site.
+//                R = float: BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k)
+//                with FP32 accumulation; R = double: FP64, vector unit.
 //   k_mlp_grad   mean binary cross-entropy gradient of a minibatch on the
 //                matrix cores (BF16 operands, FP32 accumulation).
 //   k_adam       Adam step on the FP32 master parameters, refreshing the
@@ -50,18 +51,6 @@ __device__ __forceinline__ int q_of(uint32_t meta)
     if (k == KIND_XPOS) return 1;
     if (k == KIND_XNEG) return -1;
     return 0;
-}
-
-// shell of a lattice squared distance below the cutoff (R2sh[0] = 0,
-// R2sh[16] = cutoff): an estimate from the float distance, corrected on the
-// exact integer thresholds
-__device__ __forceinline__ int shell_of(uint64_t d2, const uint64_t* R2sh, float inv_w)
-{
-    int k = (int)(sqrtf((float)d2) * inv_w);
-    k = k < 0 ? 0 : (k > 15 ? 15 : k);
-    while (k > 0 && d2 < R2sh[k]) --k;
-    while (k < 15 && d2 >= R2sh[k + 1]) ++k;
-    return k;
 }
 
 // ---------------------------------------------------------------------------
@@ -178,13 +167,13 @@ struct LearnShared {
     int seg[27];                 // prefix of the 26 neighbour counts
     uint32_t segcell[26];
     int nsite, nstaged;
+    uint32_t slot0;
+    uint64_t r2sh[17];
 };
 
-template <typename Real>
 __global__ __launch_bounds__(256) void k_learn(SweepArgs a, LearnArgs g)
 {
     __shared__ LearnShared S;
-    extern __shared__ short lsh[]; // bf16 weights, then per-wave X and H tiles (FP32 path)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t act = blockIdx.x, part = blockIdx.y;
     const uint32_t r = g.act2rep[act];
@@ -200,6 +189,8 @@ __global__ __launch_bounds__(256) void k_learn(SweepArgs a, LearnArgs g)
     const uint4* recb = R.rec[buf];
     const uint32_t* cntb = R.cnt[buf];
     const int nown = (int)cntb[cell];
+    // a cell with at most part*64 records has no sites for this workgroup
+    if (nown <= (int)part * SITES_PER_WG) return;
 
     // this workgroup's share of the cell's sites: sites part*64 .. part*64+63
     if (tid == 0) S.nsite = 0;
@@ -252,19 +243,26 @@ __global__ __launch_bounds__(256) void k_learn(SweepArgs a, LearnArgs g)
         for (int q = 0; q < 26; ++q) { S.seg[q] = acc; acc += (int)cntb[S.segcell[q]]; }
         S.seg[26] = acc;
     }
+    if (tid < 17) S.r2sh[tid] = g.R2sh[(size_t)r * 17 + tid];
     __syncthreads();
     const int nbt = S.seg[26];
-    const float inv_w = 16.0f / (float)sqrtf((float)g.R2sh[r * 17 + 16]);
-    const uint64_t* R2sh = g.R2sh + (size_t)r * 17;
+    const uint64_t* R2sh = S.r2sh;
     const uint64_t R2 = R2sh[16];
+    // shell k holds sqrt(d2) / c in [k, k + 1) with c = rc / 16 in lattice
+    // units; the float quotient decides unless it lies within 1e-4 of an
+    // integer, where the exact integer thresholds do
+    const float inv_c = 16.0f / sqrtf((float)R2);
 
     // rounds of staged charged neighbours; lane = site, waves split the records
     for (int r0 = 0; r0 < nbt; r0 += STAGE) {
         if (tid == 0) S.nstaged = 0;
         __syncthreads();
         for (int i = r0 + tid; i < min(nbt, r0 + STAGE); i += 256) {
-            int q = 0;
-            while (S.seg[q + 1] <= i) ++q;
+            int q = 0, hi = 26; // seg[q] <= i < seg[hi]
+            while (hi - q > 1) {
+                const int mid = (q + hi) >> 1;
+                if (S.seg[mid] <= i) q = mid; else hi = mid;
+            }
             const uint4 v = recb[(size_t)S.segcell[q] * cap + (uint32_t)(i - S.seg[q])];
             const int qq = q_of(v.w);
             if (qq != 0) {
@@ -280,13 +278,22 @@ __global__ __launch_bounds__(256) void k_learn(SweepArgs a, LearnArgs g)
             for (int j = wave; j < ns; j += 4) {
                 const uint4 o = S.nb[j];
                 const int32_t dx = (int32_t)(o.x - me.x), dy = (int32_t)(o.y - me.y), dz = (int32_t)(o.z - me.z);
-                const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
-                const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
-                if (d2 < R2) {
-                    const int k = shell_of(d2, R2sh, inv_w);
-                    const int ch = ((int)o.w * qion < 0) ? 0 : 16;
-                    atomicAdd(&S.hist[lane][ch + k], 1);
+                const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
+                const float t = sqrtf(fx * fx + fy * fy + fz * fz) * inv_c;
+                if (!(t < 16.0001f)) continue;
+                int k = (int)t;
+                const float fr = t - (float)k;
+                if (fr < 1e-4f || fr > 0.9999f) {
+                    // near a shell boundary or the cutoff: exact integer thresholds
+                    const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
+                    const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+                    if (d2 >= R2) continue;
+                    k = k > 15 ? 15 : k;
+                    while (k > 0 && d2 < R2sh[k]) --k;
+                    while (k < 15 && d2 >= R2sh[k + 1]) ++k;
                 }
+                const int ch = ((int)o.w * qion < 0) ? 0 : 16;
+                atomicAdd(&S.hist[lane][ch + k], 1);
             }
         }
         __syncthreads();
@@ -301,18 +308,35 @@ __global__ __launch_bounds__(256) void k_learn(SweepArgs a, LearnArgs g)
         }
     }
     if (!g.infer) return;
+    // the phase's list of sites for the network: (replica, site id), features
+    if (tid == 0) S.slot0 = atomicAdd(&g.list_n[colour], (uint32_t)nsite);
+    __syncthreads();
+    for (int i = tid; i < nsite * LIN; i += 256) {
+        const uint32_t slot = S.slot0 + (uint32_t)(i / LIN);
+        if (slot < g.list_cap) g.feat[(size_t)slot * LIN + i % LIN] = (float)S.hist[i / LIN][i % LIN];
+    }
+    if (tid < nsite && S.slot0 + (uint32_t)tid < g.list_cap) g.list[S.slot0 + tid] = make_uint2(r, S.site[tid].w >> 8);
+}
 
-    double* phat = R.phat;
+// network outputs of the listed sites of a phase: 64 per workgroup
+template <typename Real>
+__global__ __launch_bounds__(256) void k_mlp_infer(SweepArgs a, LearnArgs g)
+{
+    extern __shared__ short lsh[]; // bf16 weights, then per-wave X and H tiles (FP32 path)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t nlist = min(g.list_n[a.colour], g.list_cap);
+    const uint32_t b0 = blockIdx.x * 64u;
+    if (b0 >= nlist) return;
+    const int nrow = (int)min(64u, nlist - b0);
     if (sizeof(Real) == 8) {
-        // FP64 network, one site per thread
-        if (tid < nsite) {
+        if (tid < nrow) {
             double x[LIN];
-            for (int i = 0; i < LIN; ++i) x[i] = (double)S.hist[tid][i];
-            phat[S.site[tid].w >> 8] = site_prob(mlp_row_f64(g.p64, x));
+            for (int i = 0; i < LIN; ++i) x[i] = (double)g.feat[(size_t)(b0 + tid) * LIN + i];
+            const uint2 e = g.list[b0 + tid];
+            a.reps[e.x].phat[e.y] = site_prob(mlp_row_f64(g.p64, x));
         }
         return;
     }
-    // BF16 matrix cores: weights to LDS, 16 rows per wavefront
     short* W1b = lsh;
     short* W2b = W1b + LH * LIN;
     short* Xw = W2b + LH * LH + wave * (16 * LIN);
@@ -321,17 +345,19 @@ __global__ __launch_bounds__(256) void k_learn(SweepArgs a, LearnArgs g)
     for (int i = tid; i < LH * LH; i += 256) W2b[i] = g.w2b[i];
     __syncthreads();
     const int row0 = wave * 16;
+    if (row0 >= nrow) return;
     for (int i = lane; i < 16 * LIN; i += 64) {
-        const int rr = i / LIN, c = i % LIN;
-        Xw[i] = row0 + rr < nsite ? f2bf((float)S.hist[row0 + rr][c]) : (short)0;
+        const int rr = row0 + i / LIN;
+        Xw[i] = rr < nrow ? f2bf(g.feat[(size_t)(b0 + rr) * LIN + i % LIN]) : (short)0;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (row0 < nsite) {
-        const float z = mlp_rows16(W1b, W2b, g.p32 + MLP_B1, g.p32 + MLP_B2, g.p32 + MLP_W3, g.p32[MLP_B3], Xw, Hw,
-                                   nullptr);
-        const int rr = row0 + (lane & 15);
-        if (lane < 16 && rr < nsite) phat[S.site[rr].w >> 8] = site_prob((double)z);
+    const float z = mlp_rows16(W1b, W2b, g.p32 + MLP_B1, g.p32 + MLP_B2, g.p32 + MLP_W3, g.p32[MLP_B3], Xw, Hw,
+                               nullptr);
+    const int rr = row0 + (lane & 15);
+    if (lane < 16 && rr < nrow) {
+        const uint2 e = g.list[b0 + rr];
+        a.reps[e.x].phat[e.y] = site_prob((double)z);
     }
 }
 
@@ -541,7 +567,7 @@ size_t grad_lds_bytes()
 
 hipError_t set_learn_lds_limit()
 {
-    hipError_t e = hipFuncSetAttribute((const void*)k_learn<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_mlp_infer<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)learn_lds_bytes());
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)k_mlp_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -554,11 +580,14 @@ hipError_t set_learn_lds_limit()
 
 hipError_t launch_learn(const SweepArgs& a, const LearnArgs& g, hipStream_t s)
 {
-    const dim3 grid(g.nact_total, g.parts);
-    if (a.precision == 64 || !g.infer)
-        hipLaunchKernelGGL(k_learn<double>, grid, dim3(256), 0, s, a, g);
+    hipLaunchKernelGGL(k_learn, dim3(g.nact_total, g.parts), dim3(256), 0, s, a, g);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !g.infer) return e;
+    const dim3 grid((g.list_cap + 63u) / 64u);
+    if (a.precision == 64)
+        hipLaunchKernelGGL(k_mlp_infer<double>, grid, dim3(256), 0, s, a, g);
     else
-        hipLaunchKernelGGL(k_learn<float>, grid, dim3(256), learn_lds_bytes(), s, a, g);
+        hipLaunchKernelGGL(k_mlp_infer<float>, grid, dim3(256), learn_lds_bytes(), s, a, g);
     return hipGetLastError();
 }
 
