@@ -57,8 +57,6 @@ struct crmc_s {
     // learned proposal
     bool learned = false;
     double learn_eps = 0.1;
-    uint32_t* d_act2rep = nullptr;   // active cell (of one phase) -> replica
-    uint32_t nact_total = 0;
     uint64_t* d_R2sh = nullptr;      // 17 shell thresholds per replica
     float* d_p32 = nullptr;          // FP32 master parameters
     double* d_p64 = nullptr;
@@ -74,9 +72,9 @@ struct crmc_s {
     int64_t data_cap = 0;
     bool collecting = false;
     bool learn_lds_set = false;
-    uint2* d_list = nullptr;         // per phase: listed sites and their features
-    float* d_feat = nullptr;
-    uint32_t list_cap = 0;
+    int ncu = 0;                     // compute units of the device
+    uint4* d_lwork = nullptr;        // per colour: work items of the feature kernel
+    uint32_t lwork_cap = 0;
     TrialRec* d_log = nullptr;
     unsigned long long* d_log_n = nullptr;
     int64_t log_cap = 0;
@@ -156,7 +154,7 @@ void free_replica(HostReplica& r)
     Replica& d = r.d;
     void* ptrs[] = {d.rec[0], d.rec[1], d.cnt[0], d.cnt[1], d.cnt0, d.e_acc, d.occupancy, d.site_group,
                     d.group_count, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
-                    d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab, d.phat};
+                    d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab, d.phat, d.nsc};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = Replica{};
@@ -214,16 +212,14 @@ SweepArgs base_args(crmc_t h)
 int upload_descriptors(crmc_t h)
 {
     std::vector<Replica> v(h->reps.size());
-    uint32_t cells = 0, doms = 0, acts = 0;
+    uint32_t cells = 0, doms = 0;
     for (size_t i = 0; i < h->reps.size(); ++i) {
         HostReplica& r = h->reps[i];
         r.d.cell_begin = cells;
         r.d.dom_begin = doms;
-        r.d.act_begin = acts;
         cells += r.ncells;
         const uint32_t M = r.d.h * r.d.h * r.d.h;
         doms += h->p.pairing ? (M + 1u) / 2u : M;
-        acts += M;
         v[i] = r.d;
     }
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -256,39 +252,29 @@ int upload_descriptors(crmc_t h)
         HIP_TRY(h, dalloc(&h->d_cell2rep, c2r.size()));
         HIP_TRY(h, dalloc(&h->d_dom2rep, d2r.size()));
         HIP_TRY(h, dalloc(&h->d_lntab, lt.size()));
-        HIP_TRY(h, dalloc(&h->d_plan_n, 24));
+        HIP_TRY(h, dalloc(&h->d_plan_n, PLAN_N));
         HIP_TRY(h, dalloc(&h->d_plan_heavy, (size_t)8 * doms));
         HIP_TRY(h, dalloc(&h->d_plan_light, (size_t)8 * doms));
-        HIP_TRY(h, hipMemset(h->d_plan_n, 0, 24 * sizeof(uint32_t)));
+        HIP_TRY(h, hipMemset(h->d_plan_n, 0, PLAN_N * sizeof(uint32_t)));
         HIP_TRY(h, hipMemcpy(h->d_cell2rep, c2r.data(), c2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(h->d_dom2rep, d2r.data(), d2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(h->d_lntab, lt.data(), lt.size() * sizeof(double), hipMemcpyHostToDevice));
         h->ncell_total = cells;
         h->ndom_total = doms;
     }
-    if (acts != h->nact_total || !h->d_act2rep) {
-        // active cells of a phase -> replica, and the shell thresholds of the
-        // learned proposal's features: ceil((k rc / 16 / L 2^32)^2), k = 0..16
-        std::vector<uint32_t> a2r(acts);
+    {
+        // the shell thresholds of the learned proposal's features:
+        // ceil((k rc / 16 / L 2^32)^2), k = 0..16, per replica
         std::vector<uint64_t> sh(17 * h->reps.size());
         for (size_t i = 0; i < h->reps.size(); ++i) {
             const HostReplica& r = h->reps[i];
-            const uint32_t M = r.d.h * r.d.h * r.d.h;
-            std::fill(a2r.begin() + r.d.act_begin, a2r.begin() + r.d.act_begin + M, (uint32_t)i);
             for (int k = 0; k <= 16; ++k) {
                 const double t = (k * h->p.rc / 16.0 / r.L) * TWO32;
                 sh[17 * i + k] = k ? (uint64_t)std::ceil(t * t) : 0;
             }
         }
-        if (h->d_act2rep) (void)hipFree(h->d_act2rep);
-        if (h->d_R2sh) (void)hipFree(h->d_R2sh);
-        h->d_act2rep = nullptr;
-        h->d_R2sh = nullptr;
-        HIP_TRY(h, dalloc(&h->d_act2rep, a2r.size()));
-        HIP_TRY(h, dalloc(&h->d_R2sh, sh.size()));
-        HIP_TRY(h, hipMemcpy(h->d_act2rep, a2r.data(), a2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        if (!h->d_R2sh) HIP_TRY(h, dalloc(&h->d_R2sh, sh.size()));
         HIP_TRY(h, hipMemcpy(h->d_R2sh, sh.data(), sh.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
-        h->nact_total = acts;
     }
     return CRMC_OK;
 }
@@ -322,12 +308,11 @@ int ensure_params(crmc_t h)
     return CRMC_OK;
 }
 
-LearnArgs learn_args(crmc_t h, uint32_t maxcap)
+LearnArgs learn_args(crmc_t h)
 {
     LearnArgs g{};
-    g.act2rep = h->d_act2rep;
-    g.nact_total = h->nact_total;
-    g.parts = (maxcap + 63u) / 64u;
+    // one workgroup per compute unit (the kernel holds the network in LDS)
+    g.grid = std::max<uint32_t>(1u, std::min<uint32_t>(h->lwork_cap, (uint32_t)std::max(h->ncu, 1)));
     g.R2sh = h->d_R2sh;
     g.p32 = h->d_p32;
     g.p64 = h->d_p64;
@@ -337,26 +322,31 @@ LearnArgs learn_args(crmc_t h, uint32_t maxcap)
     g.data_n = h->d_data_n;
     g.data_cap = (uint64_t)h->data_cap;
     g.infer = h->learned ? 1 : 0;
-    g.list_n = h->d_plan_n ? h->d_plan_n + 16 : nullptr;
-    g.list = h->d_list;
-    g.feat = h->d_feat;
-    g.list_cap = h->list_cap;
     return g;
 }
 
-// room for every site of every replica in the per-phase list
-int ensure_list(crmc_t h)
+// The feature kernel's work items, per colour.  A colour's cells with sites
+// number at most min(h^3, sites) per replica and hold ceil(count / 64) parts
+// each, so min(h^3, sites) + ceil(sites / 64) items bound a replica's.
+int ensure_learn_buffers(crmc_t h)
 {
-    uint64_t sites = 0;
-    for (auto& r : h->reps) sites += r.nsites;
-    if (sites <= h->list_cap && h->d_list) return CRMC_OK;
-    if (h->d_list) (void)hipFree(h->d_list);
-    if (h->d_feat) (void)hipFree(h->d_feat);
-    h->d_list = nullptr;
-    h->d_feat = nullptr;
-    HIP_TRY(h, dalloc(&h->d_list, (size_t)std::max<uint64_t>(sites, 1)));
-    HIP_TRY(h, dalloc(&h->d_feat, (size_t)std::max<uint64_t>(sites, 1) * MLP_IN));
-    h->list_cap = (uint32_t)std::max<uint64_t>(sites, 1);
+    uint64_t items = 0;
+    for (auto& r : h->reps) {
+        const uint64_t M = (uint64_t)r.d.h * r.d.h * r.d.h;
+        items += std::min<uint64_t>(M, r.nsites) + (r.nsites + 63u) / 64u;
+    }
+    if (items * 8 > 0xFFFFFFFFull) return fail(h, CRMC_E_ARG, "too many sites for the learned proposal's work lists");
+    if (items > h->lwork_cap || !h->d_lwork) {
+        if (h->d_lwork) (void)hipFree(h->d_lwork);
+        h->d_lwork = nullptr;
+        HIP_TRY(h, dalloc(&h->d_lwork, (size_t)8 * std::max<uint64_t>(items, 1)));
+        h->lwork_cap = (uint32_t)std::max<uint64_t>(items, 1);
+    }
+    if (!h->ncu) {
+        int dev = 0;
+        HIP_TRY(h, hipGetDevice(&dev));
+        HIP_TRY(h, hipDeviceGetAttribute(&h->ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     return CRMC_OK;
 }
 
@@ -436,8 +426,9 @@ int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n, bool u
                          (uint64_t)(uintptr_t)a0.plan_n * 4099ull ^ (uint64_t)a0.light_nb * 1000033ull ^
                          (uint64_t)a0.pool * 7777ull ^ (uint64_t)a0.learned * 99991ull ^
                          (uint64_t)(a0.learn_eps * 1e12) * 13ull ^ (uint64_t)use_learn * 424243ull ^
-                         (uint64_t)(uintptr_t)lg.data * 3ull ^ (uint64_t)lg.parts * 5ull ^
-                         (uint64_t)(uintptr_t)lg.act2rep * 11ull ^ (uint64_t)(uintptr_t)a0.reps * 101ull;
+                         (uint64_t)(uintptr_t)lg.data * 3ull ^ (uint64_t)lg.grid * 5ull ^
+                         (uint64_t)(uintptr_t)a0.lwork * 11ull ^ (uint64_t)a0.lwork_cap * 29ull ^
+                         (uint64_t)(uintptr_t)a0.reps * 101ull;
     if (key != h->gkey) {
         drop_graphs(h);
         h->gkey = key;
@@ -699,6 +690,8 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     HIP_TRY(h, dalloc(&d.moves, 12));
     HIP_TRY(h, dalloc(&d.series, (size_t)series_cap * 4));
     HIP_TRY(h, dalloc(&d.phat, (size_t)std::max(n, 1)));
+    HIP_TRY(h, dalloc(&d.nsc, ncells));
+    HIP_TRY(h, hipMemset(d.nsc, 0, ncells * sizeof(uint32_t)));
     HIP_TRY(h, hipMemcpy(d.rec[0], cells.data(), nrec * sizeof(uint4), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d.cnt[0], counts.data(), ncells * sizeof(uint32_t), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d.cnt[1], 0, ncells * sizeof(uint32_t)));
@@ -822,18 +815,21 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
         HIP_TRY(h, set_phase_lds_limit(lds));
         h->lds_attr = lds;
     }
-    int rc = upload_descriptors(h);
-    if (rc) return rc;
-    SweepArgs a = base_args(h);
     const bool use_learn = h->learned || h->collecting;
-    LearnArgs lg{};
+    int rc = CRMC_OK;
     if (use_learn) {
         rc = ensure_params(h);
-        if (!rc) rc = ensure_list(h);
+        if (!rc) rc = ensure_learn_buffers(h);
         if (rc) return rc;
-        uint32_t sb = 1;
-        for (auto& r : h->reps) sb = std::max(sb, r.site_bound);
-        lg = learn_args(h, sb);
+    }
+    rc = upload_descriptors(h);
+    if (rc) return rc;
+    SweepArgs a = base_args(h);
+    LearnArgs lg{};
+    if (use_learn) {
+        a.lwork = h->d_lwork;
+        a.lwork_cap = h->lwork_cap;
+        lg = learn_args(h);
     }
     if (h->p.use_graph && !h->timing) {
         rc = sweeps_by_graph(h, a, lds, n_sweeps, use_learn, lg);
@@ -951,7 +947,7 @@ int crmc_set_proposal_weights(crmc_t h, const float* w, int64_t n)
     if (rc) return rc;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     HIP_TRY(h, hipMemcpy(h->d_p32, w, MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
-    LearnArgs g = learn_args(h, 0);
+    LearnArgs g = learn_args(h);
     HIP_TRY(h, launch_params_convert(g, h->stream));
     HIP_TRY(h, hipMemsetAsync(h->d_adam_m, 0, MLP_PARAMS * sizeof(float), h->stream));
     HIP_TRY(h, hipMemsetAsync(h->d_adam_v, 0, MLP_PARAMS * sizeof(float), h->stream));
@@ -1019,7 +1015,7 @@ int crmc_train(crmc_t h, int32_t epochs, int32_t batch, double lr, uint64_t seed
     if (n < batch) return fail(h, CRMC_E_STATE, "fewer training rows than one batch");
     rc = ensure_params(h);
     if (rc) return rc;
-    LearnArgs g = learn_args(h, 0);
+    LearnArgs g = learn_args(h);
     int* d_rows = nullptr;
     HIP_TRY(h, dalloc(&d_rows, (size_t)n));
     std::vector<int> perm((size_t)n);
@@ -1069,7 +1065,7 @@ int crmc_mlp_forward(crmc_t h, const float* X, int32_t n, float* logits)
     HIP_TRY(h, dalloc(&dX, (size_t)n * MLP_IN));
     HIP_TRY(h, dalloc(&dz, (size_t)n));
     hipError_t e = hipMemcpy(dX, X, (size_t)n * MLP_IN * sizeof(float), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_mlp_fwd(learn_args(h, 0), dX, n, dz, h->stream);
+    if (e == hipSuccess) e = launch_mlp_fwd(learn_args(h), dX, n, dz, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e == hipSuccess) e = hipMemcpy(logits, dz, (size_t)n * sizeof(float), hipMemcpyDeviceToHost);
     (void)hipFree(dX);
@@ -1093,7 +1089,7 @@ int crmc_mlp_gradient(crmc_t h, const float* rows, int32_t n, float* grad, doubl
     if (e == hipSuccess) e = hipMemcpy(dr, idx.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemsetAsync(h->d_grad, 0, MLP_PARAMS * sizeof(float), h->stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->d_loss, 0, sizeof(double), h->stream);
-    if (e == hipSuccess) e = launch_mlp_grad(learn_args(h, 0), dD, dr, n, 1.0f / n, h->d_grad, h->d_loss, h->stream);
+    if (e == hipSuccess) e = launch_mlp_grad(learn_args(h), dD, dr, n, 1.0f / n, h->d_grad, h->d_loss, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e == hipSuccess) e = hipMemcpy(grad, h->d_grad, MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost);
     if (e == hipSuccess && loss) e = hipMemcpy(loss, h->d_loss, sizeof(double), hipMemcpyDeviceToHost);
@@ -1354,8 +1350,8 @@ void crmc_destroy(crmc_t h)
     if (h->d_plan_n) (void)hipFree(h->d_plan_n);
     if (h->d_plan_heavy) (void)hipFree(h->d_plan_heavy);
     if (h->d_plan_light) (void)hipFree(h->d_plan_light);
-    void* lp[] = {h->d_act2rep, h->d_R2sh, h->d_p32, h->d_p64, h->d_w1b, h->d_w2b, h->d_adam_m, h->d_adam_v,
-                  h->d_grad, h->d_loss, h->d_data, h->d_data_n, h->d_list, h->d_feat};
+    void* lp[] = {h->d_R2sh, h->d_p32, h->d_p64, h->d_w1b, h->d_w2b, h->d_adam_m, h->d_adam_v,
+                  h->d_grad, h->d_loss, h->d_data, h->d_data_n, h->d_lwork};
     for (void* q : lp)
         if (q) (void)hipFree(q);
     delete h;

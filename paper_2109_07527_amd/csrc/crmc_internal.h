@@ -19,6 +19,10 @@ constexpr int BIN_THREADS = 256;    // four wavefronts, one new cell each
 constexpr int PHASE_THREADS = 256;  // one heavy domain, or four light domains (one per wavefront)
 constexpr int DEFAULT_LIGHT_NB = 768;
 
+// sweep plan counters (cleared by the re-binning kernel)
+constexpr int PLAN_LWORK = 24;  // + colour: work items of the feature kernel
+constexpr int PLAN_N = 32;
+
 // learned proposal network: W1[128][32], b1[128], W2[128][128], b2[128], w3[128], b3
 constexpr int MLP_IN = 32, MLP_H = 128;
 constexpr int MLP_B1 = MLP_H * MLP_IN;
@@ -67,7 +71,7 @@ struct Replica {
     uint32_t key0, key1;
     uint32_t cell_begin;     // prefix of cells over replicas (binning grid)
     uint32_t dom_begin;      // prefix of domains per phase over replicas
-    uint32_t act_begin;      // prefix of active cells per phase over replicas
+    uint32_t* nsc;           // per cell: acid and base sites as binned at the start of the sweep
     double* phat;            // per site: network output of the current phase (learned proposal)
     double L, scale, lnZ0;   // scale = L / 2^32; lnZ0 = ln(rho0 NA) + 3 ln(scale)
     uint64_t R2;             // Coulomb cutoff on the integer squared distance
@@ -110,9 +114,13 @@ struct SweepArgs {
     int32_t pool;      // LDS pool of a phase workgroup, in records (a light domain gets a quarter)
     int32_t precision; // 32 or 64
     int32_t light_nb;  // neighbour records up to which a domain may run on one wavefront
-    uint32_t* plan_n;      // per colour: heavy count, light count
+    uint32_t* plan_n;      // [2c], [2c+1]: heavy and light domains of colour c; [24+c]: work
+                           // items of the learned proposal's feature kernel
     uint32_t* plan_heavy;  // per colour: ndom_total slots of domain indices
     uint32_t* plan_light;
+    uint4* lwork;          // per colour: lwork_cap work items (replica, cell, part, 0) of the
+                           // feature kernel, or null when no learned-proposal kernel runs
+    uint32_t lwork_cap;
     int32_t learned;   // site picks by the learned proposal
     double learn_eps;  // weight of the uniform pick in it
     PhaseTrace* trace;
@@ -122,9 +130,7 @@ struct SweepArgs {
 
 // arguments of the learned-proposal kernels
 struct LearnArgs {
-    const uint32_t* act2rep;  // global active-cell index (of one phase) -> replica
-    uint32_t nact_total;
-    uint32_t parts;           // workgroups per active cell (64 sites each)
+    uint32_t grid;            // workgroups of the feature kernel (they stride over the work items)
     const uint64_t* R2sh;     // per replica: 17 shell thresholds on the squared lattice distance
     float* p32;               // FP32 master parameters
     double* p64;              // FP64 copy (FP64 inference)
@@ -134,10 +140,6 @@ struct LearnArgs {
     unsigned long long* data_n;
     uint64_t data_cap;
     int32_t infer;            // compute site probabilities (else features / rows only)
-    uint32_t* list_n;         // per colour: listed sites of the phase (cleared by the re-binning)
-    uint2* list;              // (replica, site id) of the listed sites
-    float* feat;              // their features, 32 per row
-    uint32_t list_cap;
 };
 
 // launchers (device translation units)

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     if (s == 0) { oo[0] = oo[1] = oo[2] = 0u; }
     else grid_shift(R.key0, R.key1, s - 1, a.fixed_grid, oo);
 
-    if (gcell == 0 && lane < 24) a.plan_n[lane] = 0u; // plan and learned-proposal list counters of the sweep
+    if (gcell == 0 && lane < PLAN_N) a.plan_n[lane] = 0u; // plan and learned-proposal counters of the sweep
     if (k == 0 && lane < 12) {
         // the sweep's table: shift, and the pairing centre of every colour
         const uint32_t M = R.h * R.h * R.h;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     }
 
     const uint64_t lt = lanemask_lt();
-    uint32_t base = 0;
+    uint32_t base = 0, nsite = 0;
     for (int iz = 0; iz < ncand[2]; ++iz)
         for (int iy = 0; iy < ncand[1]; ++iy)
             for (int ix = 0; ix < ncand[0]; ++ix) {
@@ -171,6 +171,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
                                 cell_of(rec.z - on[2], n) == kc[2];
                     }
                     const uint64_t mask = __ballot(match);
+                    const uint32_t kd = rec.w & 7u;
+                    nsite += (uint32_t)__popcll(__ballot(match && (kd == KIND_ACID || kd == KIND_BASE)));
                     if (match) {
                         const uint32_t pos = base + (uint32_t)__popcll(mask & lt);
                         if (pos < cap) dst[(size_t)k * cap + pos] = rec;
@@ -187,6 +189,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     if (lane == 0) {
         R.cnt[nxt][k] = base < cap ? base : cap;
         R.cnt0[k] = base < cap ? base : cap;
+        R.nsc[k] = nsite;
         if (base > cap) atomicOr(a.err, ERR_BIN_CAPACITY);
         if (base > hw) atomicMax(R.hiwater, base); // rarely taken once the mark has settled
     }
@@ -292,15 +295,31 @@ __device__ __forceinline__ uint32_t neighbour_cell(uint32_t x, uint32_t y, uint3
 }
 
 // one thread per domain, one colour per workgroup (blockIdx.y); the list
-// slots are claimed with one atomic per wavefront and class
+// slots are claimed with one atomic per wavefront and class.  With the
+// learned proposal on, each cell of the domain also gets its work items for
+// the feature kernel: one per 64 sites (sites never change cells within a
+// sweep, so the counts of the re-binning hold for all phases).
 __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
 {
     const int colour = (int)blockIdx.y;
     const uint32_t gd = blockIdx.x * 64u + threadIdx.x;
     bool valid = gd < a.ndom_total, light = false;
     if (valid) {
-        const Replica& R = a.reps[a.dom2rep[gd]];
+        const uint32_t r = a.dom2rep[gd];
+        const Replica& R = a.reps[r];
         const DomGeo G = domain_geometry(R, gd - R.dom_begin, colour, a.pairing);
+        if (a.lwork) {
+            for (int c = 0; c < G.ncell; ++c) {
+                const uint32_t cell = c ? G.cell1 : G.cell0;
+                const uint32_t m = (R.nsc[cell] + 63u) / 64u;
+                if (m == 0u) continue;
+                // the capacity bounds every sweep's items (sites / 64 + cells with sites)
+                const uint32_t b = atomicAdd(&a.plan_n[PLAN_LWORK + colour], m);
+                for (uint32_t i = 0; i < m && b + i < a.lwork_cap; ++i)
+                    a.lwork[(size_t)colour * a.lwork_cap + b + i] =
+                        make_uint4(r, cell, i, 0u);
+            }
+        }
         const uint32_t* cntb = R.cnt[(*a.sweep + 1u) & 1u];
         int nb = 0;
 #pragma unroll

@@ -1,19 +1,19 @@
 // CDNA4 (gfx950) kernels of the learned site proposal.
 //
-//   k_learn      per colour phase: for the sites of every active cell, the
+//   k_learn<R>   per colour phase: for the sites of every active cell, the
 //                environment features (charged particles of the 26 neighbour
 //                cells within rc, by radial shell and sign relative to the
-//                site's ionized charge), appended to the phase's list; and
-//                optionally one labelled training row per site.
-//   k_mlp_infer<R> per colour phase: the network output p = logistic of a
-//                32 -> 128 -> 128 -> 1 ReLU perceptron for every listed site.
-//                R = float: BF16 matrix cores (v_mfma_f32_16x16x16bf16_1k)
-//                with FP32 accumulation; R = double: FP64, vector unit.
+//                site's ionized charge); a labelled training row per site
+//                while rows are being collected; with the proposal on, the
+//                network output p = logistic of a 32 -> 128 -> 128 -> 1 ReLU
+//                perceptron.  R = float: BF16 matrix cores
+//                (v_mfma_f32_16x16x16bf16_1k) with FP32 accumulation;
+//                R = double: FP64, vector unit.
 //   k_mlp_grad   mean binary cross-entropy gradient of a minibatch on the
 //                matrix cores (BF16 operands, FP32 accumulation).
 //   k_adam       Adam step on the FP32 master parameters, refreshing the
 //                BF16 copies the inference uses.
-//   k_mlp_fwd    logits of given feature rows (same path as k_learn).
+//   k_mlp_fwd    logits of given feature rows (the same network code as k_learn<float>).
 //
 // The neighbour cells are inactive during the phase, so the outputs fix the
 // proposal weights of the phase's trials (detailed balance holds for the
@@ -27,7 +27,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int LIN = MLP_IN, LH = MLP_H;
 constexpr int SITES_PER_WG = 64;    // sites of one cell handled by one workgroup
-constexpr int STAGE = 1024;         // neighbour records staged per round
+constexpr int LEARN_THREADS = 1024; // sixteen wavefronts: each takes every 16th staged record
+constexpr int LEARN_WAVES = LEARN_THREADS / 64;
+constexpr int STAGE = 2048;         // neighbour records staged per round
 
 __device__ __forceinline__ uint64_t lanes_below()
 {
@@ -58,7 +60,10 @@ __device__ __forceinline__ int q_of(uint32_t meta)
 // ---------------------------------------------------------------------------
 // LDS operands: W1b [128][32] and W2b [128][128] as bf16 (row = output
 // unit); X [16][32] bf16 rows of this wavefront; H [16][128] bf16 scratch.
-// Returns the logit of row (lane & 15) in every lane of that row group.
+// Rows are XS, HS, W1S, W2S elements apart (padding spreads the 16 rows a
+// matrix-core operand reads across the LDS banks).  Returns the logit of
+// row (lane & 15) in every lane of that row group.
+template <int XS = MLP_IN, int HS = MLP_H, int W1S = MLP_IN, int W2S = MLP_H>
 __device__ __forceinline__ float mlp_rows16(const short* W1b, const short* W2b, const float* b1, const float* b2,
                                             const float* w3, float b3, const short* X, short* H, float* h2out)
 {
@@ -72,12 +77,12 @@ __device__ __forceinline__ float mlp_rows16(const short* W1b, const short* W2b, 
     for (int ks = 0; ks < LIN / 16; ++ks) {
         bf16x4 a;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[e] = X[col * LIN + ks * 16 + 4 * grp + e];
+        for (int e = 0; e < 4; ++e) a[e] = X[col * XS + ks * 16 + 4 * grp + e];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             bf16x4 b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) b[e] = W1b[(t * 16 + col) * LIN + ks * 16 + 4 * grp + e];
+            for (int e = 0; e < 4; ++e) b[e] = W1b[(t * 16 + col) * W1S + ks * 16 + 4 * grp + e];
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
         }
     }
@@ -88,7 +93,7 @@ __device__ __forceinline__ float mlp_rows16(const short* W1b, const short* W2b, 
         for (int e = 0; e < 4; ++e) {
             const int m = 4 * grp + e, n = t * 16 + col;
             const float v = acc[t][e] + b1[n];
-            H[m * LH + n] = f2bf(v > 0.f ? v : 0.f);
+            H[m * HS + n] = f2bf(v > 0.f ? v : 0.f);
         }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -99,12 +104,12 @@ __device__ __forceinline__ float mlp_rows16(const short* W1b, const short* W2b, 
     for (int ks = 0; ks < LH / 16; ++ks) {
         bf16x4 a;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[e] = H[col * LH + ks * 16 + 4 * grp + e];
+        for (int e = 0; e < 4; ++e) a[e] = H[col * HS + ks * 16 + 4 * grp + e];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             bf16x4 b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) b[e] = W2b[(t * 16 + col) * LH + ks * 16 + 4 * grp + e];
+            for (int e = 0; e < 4; ++e) b[e] = W2b[(t * 16 + col) * W2S + ks * 16 + 4 * grp + e];
             acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
         }
     }
@@ -158,46 +163,84 @@ __device__ __forceinline__ double site_prob(double z)
 }
 
 // ---------------------------------------------------------------------------
-// k_learn: features and site probabilities of the active sites of a phase
+// k_learn: features and network outputs of the sites of a phase
 // ---------------------------------------------------------------------------
+// Work item (replica, cell, part): the cell's sites of rank 64 part ..
+// 64 part + 63 in its record order (no kernel moves records during this
+// launch).  One workgroup counts their features against the charged records
+// of the 26 neighbour cells, writes training rows while rows are being
+// collected, and with the proposal on evaluates the network on the 64 rows
+// (R = float: BF16 matrix cores with the weights held in LDS for all its
+// items; R = double: FP64 per thread).  The workgroups stride over the
+// phase's items.
+constexpr int XS = LIN + 8, HS = LH + 8, W1S = LIN + 8, W2S = LH + 8; // padded LDS rows
+
 struct LearnShared {
-    uint4 site[SITES_PER_WG];    // x, y, z, meta of this workgroup's sites
-    int hist[SITES_PER_WG][LIN]; // feature counts
-    uint4 nb[STAGE];             // staged charged neighbours: x, y, z, charge
-    int seg[27];                 // prefix of the 26 neighbour counts
+    uint4 site[SITES_PER_WG];             // x, y, z, meta of the item's sites
+    int hist[SITES_PER_WG][LIN + 1];      // counts (rows padded against bank conflicts)
+    int4 nb[STAGE];                       // staged charged neighbours: offsets from site 0, charge
+    int seg[27];                          // prefix of the 26 neighbour counts
     uint32_t segcell[26];
-    int nsite, nstaged;
-    uint32_t slot0;
+    int box[6];                           // least and largest site offsets from site 0 per axis
+    int nstaged;
+    int wcount[LEARN_WAVES];
     uint64_t r2sh[17];
 };
 
-__global__ __launch_bounds__(256) void k_learn(SweepArgs a, LearnArgs g)
+size_t learn_infer_lds_bytes() { return sizeof(short) * (LH * W1S + LH * W2S + 4 * 16 * XS + 4 * 16 * HS); }
+
+template <typename Real>
+__global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs g)
 {
     __shared__ LearnShared S;
+    extern __shared__ uint4 lsh4[]; // FP32 network: W1b, W2b, then per-wave X and H tiles
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t act = blockIdx.x, part = blockIdx.y;
-    const uint32_t r = g.act2rep[act];
-    const Replica& R = a.reps[r];
-    const uint32_t n = R.n, h = R.h, cap = R.cap;
     const int colour = a.colour;
-    const uint32_t px = colour & 1, py = (colour >> 1) & 1, pz = (colour >> 2) & 1;
-    const uint32_t m = act - R.act_begin;
-    const uint32_t cx = 2u * (m % h) + px, cy = 2u * ((m / h) % h) + py, cz = 2u * (m / (h * h)) + pz;
-    const uint32_t cell = cx + n * (cy + n * cz);
+    const uint32_t nwork = min(a.plan_n[PLAN_LWORK + colour], a.lwork_cap);
+    if (blockIdx.x >= nwork) return;
     const uint64_t s = *a.sweep;
     const int buf = (int)((s + 1u) & 1u);
-    const uint4* recb = R.rec[buf];
-    const uint32_t* cntb = R.cnt[buf];
-    const int nown = (int)cntb[cell];
-    // a cell with at most part*64 records has no sites for this workgroup
-    if (nown <= (int)part * SITES_PER_WG) return;
+    const bool mfma = sizeof(Real) == 4 && g.infer;
+    short* W1b = (short*)lsh4;
+    short* W2b = W1b + LH * W1S;
+    short* Xw = W2b + LH * W2S + wave * (16 * XS);
+    short* Hw = W2b + LH * W2S + 4 * 16 * XS + wave * (16 * HS);
+    if (mfma) {
+        // padded copies of the BF16 weights (rows of 16-byte chunks)
+        const uint4* w1 = (const uint4*)g.w1b;
+        const uint4* w2 = (const uint4*)g.w2b;
+        for (int i = tid; i < LH * LIN / 8; i += LEARN_THREADS)
+            *(uint4*)(W1b + (i / (LIN / 8)) * W1S + (i % (LIN / 8)) * 8) = w1[i];
+        for (int i = tid; i < LH * LH / 8; i += LEARN_THREADS)
+            *(uint4*)(W2b + (i / (LH / 8)) * W2S + (i % (LH / 8)) * 8) = w2[i];
+    }
+    for (uint32_t it = blockIdx.x; it < nwork; it += gridDim.x) {
+        const uint4 w = a.lwork[(size_t)colour * a.lwork_cap + it];
+        const uint32_t r = w.x, cell = w.y, part = w.z;
+        const Replica& R = a.reps[r];
+        const uint32_t n = R.n, cap = R.cap;
+        const uint4* recb = R.rec[buf];
+        const uint32_t* cntb = R.cnt[buf];
+        const int nown = (int)cntb[cell];
+        const int lo = (int)part * SITES_PER_WG;
 
-    // this workgroup's share of the cell's sites: sites part*64 .. part*64+63
-    if (tid == 0) S.nsite = 0;
-    __syncthreads();
-    {
+        // neighbour cells, shell thresholds, cleared counts
+        if (tid < 26) {
+            const uint32_t cx = cell % n, cy = (cell / n) % n, cz = cell / (n * n);
+            const int oo = tid < 13 ? tid : tid + 1;
+            const uint32_t x = (cx + n + (uint32_t)(oo % 3) - 1u) % n, y = (cy + n + (uint32_t)((oo / 3) % 3) - 1u) % n,
+                           z = (cz + n + (uint32_t)(oo / 9) - 1u) % n;
+            const uint32_t c = x + n * (y + n * z);
+            S.segcell[tid] = c;
+            S.seg[tid + 1] = (int)cntb[c]; // counts now, prefix below
+        }
+        if (tid < 17) S.r2sh[tid] = g.R2sh[(size_t)r * 17 + tid];
+        if (tid < 6) S.box[tid] = tid < 3 ? 0x7FFFFFFF : (int)0x80000000;
+        for (int i = tid; i < SITES_PER_WG * (LIN + 1); i += LEARN_THREADS) (&S.hist[0][0])[i] = 0;
+
+        // the item's sites: rank among the cell's sites (block prefix over wave ballots)
         int base = 0;
-        for (int b0 = 0; b0 < nown; b0 += 256) {
+        for (int b0 = 0; b0 < nown; b0 += LEARN_THREADS) {
             const int i = b0 + tid;
             uint4 v = make_uint4(0, 0, 0, 0);
             bool site = false;
@@ -206,158 +249,156 @@ __global__ __launch_bounds__(256) void k_learn(SweepArgs a, LearnArgs g)
                 const uint32_t k = v.w & 7u;
                 site = k == KIND_ACID || k == KIND_BASE;
             }
-            // rank among the sites (block-wide prefix through the wave ballots)
-            __shared__ int wcount[4];
             const uint64_t mask = __ballot(site);
-            if (lane == 0) wcount[wave] = __popcll(mask);
+            if (lane == 0) S.wcount[wave] = __popcll(mask);
             __syncthreads();
-            int before = base;
-            for (int w = 0; w < wave; ++w) before += wcount[w];
+            int before = base, tot = 0;
+            for (int q = 0; q < LEARN_WAVES; ++q) {
+                before += q < wave ? S.wcount[q] : 0;
+                tot += S.wcount[q];
+            }
             const int rank = before + __popcll(mask & lanes_below());
-            const int lo = (int)part * SITES_PER_WG;
             if (site && rank >= lo && rank < lo + SITES_PER_WG) S.site[rank - lo] = v;
-            int tot = 0;
-            for (int w = 0; w < 4; ++w) tot += wcount[w];
             base += tot;
             __syncthreads();
         }
-        if (tid == 0) {
-            const int lo = (int)part * SITES_PER_WG;
-            S.nsite = base <= lo ? 0 : min(SITES_PER_WG, base - lo);
-        }
-    }
-    __syncthreads();
-    const int nsite = S.nsite;
-    if (nsite == 0) return;
-    for (int i = tid; i < SITES_PER_WG * LIN; i += 256) (&S.hist[0][0])[i] = 0;
-    // neighbour segments
-    if (tid < 26) {
-        const int oo = tid < 13 ? tid : tid + 1;
-        const uint32_t x = (cx + n + (uint32_t)(oo % 3) - 1u) % n, y = (cy + n + (uint32_t)((oo / 3) % 3) - 1u) % n,
-                       z = (cz + n + (uint32_t)(oo / 9) - 1u) % n;
-        S.segcell[tid] = x + n * (y + n * z);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int acc = 0;
-        for (int q = 0; q < 26; ++q) { S.seg[q] = acc; acc += (int)cntb[S.segcell[q]]; }
-        S.seg[26] = acc;
-    }
-    if (tid < 17) S.r2sh[tid] = g.R2sh[(size_t)r * 17 + tid];
-    __syncthreads();
-    const int nbt = S.seg[26];
-    const uint64_t* R2sh = S.r2sh;
-    const uint64_t R2 = R2sh[16];
-    // shell k holds sqrt(d2) / c in [k, k + 1) with c = rc / 16 in lattice
-    // units; the float quotient decides unless it lies within 1e-4 of an
-    // integer, where the exact integer thresholds do
-    const float inv_c = 16.0f / sqrtf((float)R2);
+        const int nsite = base <= lo ? 0 : min(SITES_PER_WG, base - lo);
+        if (nsite == 0) continue; // uniform: base is the same in every thread
 
-    // rounds of staged charged neighbours; lane = site, waves split the records
-    for (int r0 = 0; r0 < nbt; r0 += STAGE) {
-        if (tid == 0) S.nstaged = 0;
-        __syncthreads();
-        for (int i = r0 + tid; i < min(nbt, r0 + STAGE); i += 256) {
-            int q = 0, hi = 26; // seg[q] <= i < seg[hi]
-            while (hi - q > 1) {
-                const int mid = (q + hi) >> 1;
-                if (S.seg[mid] <= i) q = mid; else hi = mid;
-            }
-            const uint4 v = recb[(size_t)S.segcell[q] * cap + (uint32_t)(i - S.seg[q])];
-            const int qq = q_of(v.w);
-            if (qq != 0) {
-                const int slot = atomicAdd(&S.nstaged, 1);
-                S.nb[slot] = make_uint4(v.x, v.y, v.z, (uint32_t)qq);
-            }
+        const uint4 s0 = S.site[0];
+        if (tid == 0) {
+            int acc = 0;
+            S.seg[0] = 0;
+            for (int q = 1; q <= 26; ++q) { acc += S.seg[q]; S.seg[q] = acc; }
         }
-        __syncthreads();
-        const int ns = S.nstaged;
+        int so[3] = {0, 0, 0}; // this lane's site as offsets from site 0
+        int qion = 1;
         if (lane < nsite) {
             const uint4 me = S.site[lane];
-            const int qion = (me.w & 7u) == KIND_ACID ? -1 : 1;
-            for (int j = wave; j < ns; j += 4) {
-                const uint4 o = S.nb[j];
-                const int32_t dx = (int32_t)(o.x - me.x), dy = (int32_t)(o.y - me.y), dz = (int32_t)(o.z - me.z);
-                const float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-                const float t = sqrtf(fx * fx + fy * fy + fz * fz) * inv_c;
-                if (!(t < 16.0001f)) continue;
-                int k = (int)t;
-                const float fr = t - (float)k;
-                if (fr < 1e-4f || fr > 0.9999f) {
-                    // near a shell boundary or the cutoff: exact integer thresholds
-                    const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
-                    const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
-                    if (d2 >= R2) continue;
-                    k = k > 15 ? 15 : k;
-                    while (k > 0 && d2 < R2sh[k]) --k;
-                    while (k < 15 && d2 >= R2sh[k + 1]) ++k;
+            so[0] = (int32_t)(me.x - s0.x);
+            so[1] = (int32_t)(me.y - s0.y);
+            so[2] = (int32_t)(me.z - s0.z);
+            qion = (me.w & 7u) == KIND_ACID ? -1 : 1;
+            if (wave == 0) {
+                for (int d = 0; d < 3; ++d) {
+                    atomicMin(&S.box[d], so[d]);
+                    atomicMax(&S.box[3 + d], so[d]);
                 }
-                const int ch = ((int)o.w * qion < 0) ? 0 : 16;
-                atomicAdd(&S.hist[lane][ch + k], 1);
             }
         }
         __syncthreads();
-    }
+        const uint64_t* R2sh = S.r2sh;
+        const uint64_t R2 = R2sh[16];
+        // shell k holds sqrt(d2) / c in [k, k + 1) with c = rc / 16 in lattice
+        // units.  The float offsets are within 2^-24 relative of the exact ones,
+        // so the float quotient is off by far less than 1e-4: it decides unless
+        // it lies within 1e-4 of an integer, where the integer thresholds do.
+        const float R2f = (float)R2;
+        const float r2hi = R2f * 1.0004f;
+        const float inv_c = 16.0f / sqrtf(R2f);
+        // records farther than rc from the sites' bounding box along any axis
+        // cannot count
+        const int64_t rcl = (int64_t)ceil(sqrt((double)R2)) + 1;
+        const int64_t blo[3] = {S.box[0] - rcl, S.box[1] - rcl, S.box[2] - rcl};
+        const int64_t bhi[3] = {S.box[3] + rcl, S.box[4] + rcl, S.box[5] + rcl};
+        const float sf[3] = {(float)so[0], (float)so[1], (float)so[2]};
+        const int nbt = S.seg[26];
 
-    // training rows: features and the site's ionization at the start of the phase
-    if (g.data && tid < nsite) {
-        const unsigned long long row = atomicAdd(g.data_n, 1ull);
-        if (row < g.data_cap) {
-            for (int i = 0; i < LIN; ++i) g.data[row * (LIN + 1) + i] = (float)S.hist[tid][i];
-            g.data[row * (LIN + 1) + LIN] = (float)((S.site[tid].w >> 3) & 1u);
+        for (int r0 = 0; r0 < nbt; r0 += STAGE) {
+            if (tid == 0) S.nstaged = 0;
+            __syncthreads();
+            const int r1 = min(nbt, r0 + STAGE);
+            // two records per thread in flight, then the kept ones compacted
+            for (int b0 = r0; b0 < r1; b0 += 2 * LEARN_THREADS) {
+                uint4 v[2];
+                bool in[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int i = b0 + u * LEARN_THREADS + tid;
+                    in[u] = i < r1;
+                    v[u] = make_uint4(0, 0, 0, 0);
+                    if (in[u]) {
+                        int q = 0, hi = 26; // seg[q] <= i < seg[hi]
+                        while (hi - q > 1) {
+                            const int mid = (q + hi) >> 1;
+                            if (S.seg[mid] <= i) q = mid; else hi = mid;
+                        }
+                        v[u] = recb[(size_t)S.segcell[q] * cap + (uint32_t)(i - S.seg[q])];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int qq = in[u] ? q_of(v[u].w) : 0;
+                    const int ox = (int32_t)(v[u].x - s0.x), oy = (int32_t)(v[u].y - s0.y),
+                              oz = (int32_t)(v[u].z - s0.z);
+                    const bool keep = qq != 0 && ox >= blo[0] && ox <= bhi[0] && oy >= blo[1] && oy <= bhi[1] &&
+                                      oz >= blo[2] && oz <= bhi[2];
+                    // one LDS atomic per wavefront for the records it keeps
+                    const uint64_t mask = __ballot(keep);
+                    int slot = 0;
+                    if (lane == 0 && mask) slot = atomicAdd(&S.nstaged, __popcll(mask));
+                    slot = __shfl(slot, 0, 64) + __popcll(mask & lanes_below());
+                    if (keep) S.nb[slot] = make_int4(ox, oy, oz, qq);
+                }
+            }
+            __syncthreads();
+            const int ns = S.nstaged;
+            if (lane < nsite) {
+                for (int j = wave; j < ns; j += LEARN_WAVES) {
+                    const int4 o = S.nb[j];
+                    const float dx = (float)o.x - sf[0], dy = (float)o.y - sf[1], dz = (float)o.z - sf[2];
+                    const float d2f = dx * dx + dy * dy + dz * dz;
+                    bool inr = d2f < r2hi;
+                    const float t = __builtin_amdgcn_sqrtf(d2f) * inv_c;
+                    int k = (int)t;
+                    const float fr = t - (float)k;
+                    if (inr && (fr < 1e-4f || fr > 0.9999f || k > 15)) {
+                        // near a shell boundary or the cutoff: the exact integer thresholds
+                        const uint32_t ax = (uint32_t)abs((int32_t)((uint32_t)o.x - (uint32_t)so[0]));
+                        const uint32_t ay = (uint32_t)abs((int32_t)((uint32_t)o.y - (uint32_t)so[1]));
+                        const uint32_t az = (uint32_t)abs((int32_t)((uint32_t)o.z - (uint32_t)so[2]));
+                        const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+                        inr = d2 < R2;
+                        k = k > 15 ? 15 : k;
+                        while (k > 0 && d2 < R2sh[k]) --k;
+                        while (k < 15 && d2 >= R2sh[k + 1]) ++k;
+                    }
+                    if (inr) atomicAdd(&S.hist[lane][((o.w * qion < 0) ? 0 : 16) + k], 1);
+                }
+            }
+            __syncthreads();
         }
-    }
-    if (!g.infer) return;
-    // the phase's list of sites for the network: (replica, site id), features
-    if (tid == 0) S.slot0 = atomicAdd(&g.list_n[colour], (uint32_t)nsite);
-    __syncthreads();
-    for (int i = tid; i < nsite * LIN; i += 256) {
-        const uint32_t slot = S.slot0 + (uint32_t)(i / LIN);
-        if (slot < g.list_cap) g.feat[(size_t)slot * LIN + i % LIN] = (float)S.hist[i / LIN][i % LIN];
-    }
-    if (tid < nsite && S.slot0 + (uint32_t)tid < g.list_cap) g.list[S.slot0 + tid] = make_uint2(r, S.site[tid].w >> 8);
-}
 
-// network outputs of the listed sites of a phase: 64 per workgroup
-template <typename Real>
-__global__ __launch_bounds__(256) void k_mlp_infer(SweepArgs a, LearnArgs g)
-{
-    extern __shared__ short lsh[]; // bf16 weights, then per-wave X and H tiles (FP32 path)
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t nlist = min(g.list_n[a.colour], g.list_cap);
-    const uint32_t b0 = blockIdx.x * 64u;
-    if (b0 >= nlist) return;
-    const int nrow = (int)min(64u, nlist - b0);
-    if (sizeof(Real) == 8) {
-        if (tid < nrow) {
-            double x[LIN];
-            for (int i = 0; i < LIN; ++i) x[i] = (double)g.feat[(size_t)(b0 + tid) * LIN + i];
-            const uint2 e = g.list[b0 + tid];
-            a.reps[e.x].phat[e.y] = site_prob(mlp_row_f64(g.p64, x));
+        // training rows: the features and the site's ionization at the start of the phase
+        if (g.data && tid < nsite) {
+            const unsigned long long row = atomicAdd(g.data_n, 1ull);
+            if (row < g.data_cap) {
+                for (int i = 0; i < LIN; ++i) g.data[row * (LIN + 1) + i] = (float)S.hist[tid][i];
+                g.data[row * (LIN + 1) + LIN] = (float)((S.site[tid].w >> 3) & 1u);
+            }
         }
-        return;
-    }
-    short* W1b = lsh;
-    short* W2b = W1b + LH * LIN;
-    short* Xw = W2b + LH * LH + wave * (16 * LIN);
-    short* Hw = W2b + LH * LH + 4 * 16 * LIN + wave * (16 * LH);
-    for (int i = tid; i < LH * LIN; i += 256) W1b[i] = g.w1b[i];
-    for (int i = tid; i < LH * LH; i += 256) W2b[i] = g.w2b[i];
-    __syncthreads();
-    const int row0 = wave * 16;
-    if (row0 >= nrow) return;
-    for (int i = lane; i < 16 * LIN; i += 64) {
-        const int rr = row0 + i / LIN;
-        Xw[i] = rr < nrow ? f2bf(g.feat[(size_t)(b0 + rr) * LIN + i % LIN]) : (short)0;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const float z = mlp_rows16(W1b, W2b, g.p32 + MLP_B1, g.p32 + MLP_B2, g.p32 + MLP_W3, g.p32[MLP_B3], Xw, Hw,
-                               nullptr);
-    const int rr = row0 + (lane & 15);
-    if (lane < 16 && rr < nrow) {
-        const uint2 e = g.list[b0 + rr];
-        a.reps[e.x].phat[e.y] = site_prob((double)z);
+        if (g.infer) {
+            if (mfma) {
+                const int row0 = wave * 16;
+                if (row0 < nsite) {
+                    for (int i = lane; i < 16 * LIN; i += 64) {
+                        const int rr = row0 + i / LIN;
+                        Xw[(i / LIN) * XS + i % LIN] = rr < nsite ? f2bf((float)S.hist[rr][i % LIN]) : (short)0;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    const float z = mlp_rows16<XS, HS, W1S, W2S>(W1b, W2b, g.p32 + MLP_B1, g.p32 + MLP_B2,
+                                                                 g.p32 + MLP_W3, g.p32[MLP_B3], Xw, Hw, nullptr);
+                    const int rr = row0 + (lane & 15);
+                    if (lane < 16 && rr < nsite) R.phat[S.site[rr].w >> 8] = site_prob((double)z);
+                }
+            } else if (tid < nsite) {
+                double x[LIN];
+                for (int i = 0; i < LIN; ++i) x[i] = (double)S.hist[tid][i];
+                R.phat[S.site[tid].w >> 8] = site_prob(mlp_row_f64(g.p64, x));
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -567,8 +608,8 @@ size_t grad_lds_bytes()
 
 hipError_t set_learn_lds_limit()
 {
-    hipError_t e = hipFuncSetAttribute((const void*)k_mlp_infer<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)learn_lds_bytes());
+    hipError_t e = hipFuncSetAttribute((const void*)k_learn<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)learn_infer_lds_bytes());
     if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)k_mlp_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)learn_lds_bytes());
@@ -580,14 +621,10 @@ hipError_t set_learn_lds_limit()
 
 hipError_t launch_learn(const SweepArgs& a, const LearnArgs& g, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_learn, dim3(g.nact_total, g.parts), dim3(256), 0, s, a, g);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !g.infer) return e;
-    const dim3 grid((g.list_cap + 63u) / 64u);
-    if (a.precision == 64)
-        hipLaunchKernelGGL(k_mlp_infer<double>, grid, dim3(256), 0, s, a, g);
+    if (a.precision == 64 || !g.infer)
+        hipLaunchKernelGGL(k_learn<double>, dim3(g.grid), dim3(LEARN_THREADS), 0, s, a, g);
     else
-        hipLaunchKernelGGL(k_mlp_infer<float>, grid, dim3(256), learn_lds_bytes(), s, a, g);
+        hipLaunchKernelGGL(k_learn<float>, dim3(g.grid), dim3(LEARN_THREADS), learn_infer_lds_bytes(), s, a, g);
     return hipGetLastError();
 }
 
