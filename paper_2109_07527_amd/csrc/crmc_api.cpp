@@ -312,7 +312,7 @@ LearnArgs learn_args(crmc_t h)
 {
     LearnArgs g{};
     // one workgroup per compute unit (the kernel holds the network in LDS)
-    g.grid = std::max<uint32_t>(1u, std::min<uint32_t>(h->lwork_cap, (uint32_t)std::max(h->ncu, 1)));
+    g.grid = (uint32_t)std::max(h->ncu, 1);
     g.R2sh = h->d_R2sh;
     g.p32 = h->d_p32;
     g.p64 = h->d_p64;
@@ -339,8 +339,9 @@ int ensure_learn_buffers(crmc_t h)
     if (items > h->lwork_cap || !h->d_lwork) {
         if (h->d_lwork) (void)hipFree(h->d_lwork);
         h->d_lwork = nullptr;
-        HIP_TRY(h, dalloc(&h->d_lwork, (size_t)8 * std::max<uint64_t>(items, 1)));
-        h->lwork_cap = (uint32_t)std::max<uint64_t>(items, 1);
+        const size_t m = (size_t)std::max<uint64_t>(items, 1);
+        HIP_TRY(h, dalloc(&h->d_lwork, 8 * m));
+        h->lwork_cap = (uint32_t)m;
     }
     if (!h->ncu) {
         int dev = 0;

@@ -29,7 +29,7 @@ constexpr int LIN = MLP_IN, LH = MLP_H;
 constexpr int SITES_PER_WG = 64;    // sites of one cell handled by one workgroup
 constexpr int LEARN_THREADS = 1024; // sixteen wavefronts: each takes every 16th staged record
 constexpr int LEARN_WAVES = LEARN_THREADS / 64;
-constexpr int STAGE = 2048;         // neighbour records staged per round
+constexpr int STAGE = 1536;         // neighbour records staged per round
 
 __device__ __forceinline__ uint64_t lanes_below()
 {
@@ -167,10 +167,10 @@ __device__ __forceinline__ double site_prob(double z)
 // ---------------------------------------------------------------------------
 // Work item (replica, cell, part): the cell's sites of rank 64 part ..
 // 64 part + 63 in its record order (no kernel moves records during this
-// launch).  One workgroup counts their features against the charged records
-// of the 26 neighbour cells, writes training rows while rows are being
-// collected, and with the proposal on evaluates the network on the 64 rows
-// (R = float: BF16 matrix cores with the weights held in LDS for all its
+// launch), counted against the charged records of the 26 neighbour cells by
+// one workgroup, which then writes the training rows while rows are being
+// collected and, with the proposal on, evaluates the network on the item's
+// rows (R = float: BF16 matrix cores with the weights held in LDS for all its
 // items; R = double: FP64 per thread).  The workgroups stride over the
 // phase's items.
 constexpr int XS = LIN + 8, HS = LH + 8, W1S = LIN + 8, W2S = LH + 8; // padded LDS rows
@@ -178,7 +178,8 @@ constexpr int XS = LIN + 8, HS = LH + 8, W1S = LIN + 8, W2S = LH + 8; // padded 
 struct LearnShared {
     uint4 site[SITES_PER_WG];             // x, y, z, meta of the item's sites
     int hist[SITES_PER_WG][LIN + 1];      // counts (rows padded against bank conflicts)
-    int4 nb[STAGE];                       // staged charged neighbours: offsets from site 0, charge
+    float4 nbf[STAGE];                    // staged charged neighbours: float offsets from site 0, sign code
+    int4 nbi[STAGE];                      // the same offsets as exact integers
     int seg[27];                          // prefix of the 26 neighbour counts
     uint32_t segcell[26];
     int box[6];                           // least and largest site offsets from site 0 per axis
@@ -272,13 +273,13 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
             for (int q = 1; q <= 26; ++q) { acc += S.seg[q]; S.seg[q] = acc; }
         }
         int so[3] = {0, 0, 0}; // this lane's site as offsets from site 0
-        int qion = 1;
+        int sq = 0;            // 16 when the site's ionized charge is positive
         if (lane < nsite) {
             const uint4 me = S.site[lane];
             so[0] = (int32_t)(me.x - s0.x);
             so[1] = (int32_t)(me.y - s0.y);
             so[2] = (int32_t)(me.z - s0.z);
-            qion = (me.w & 7u) == KIND_ACID ? -1 : 1;
+            sq = (me.w & 7u) == KIND_ACID ? 0 : 16;
             if (wave == 0) {
                 for (int d = 0; d < 3; ++d) {
                     atomicMin(&S.box[d], so[d]);
@@ -289,19 +290,19 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
         __syncthreads();
         const uint64_t* R2sh = S.r2sh;
         const uint64_t R2 = R2sh[16];
-        // shell k holds sqrt(d2) / c in [k, k + 1) with c = rc / 16 in lattice
+        // Shell k holds sqrt(d2) / c in [k, k + 1) with c = rc / 16 in lattice
         // units.  The float offsets are within 2^-24 relative of the exact ones,
-        // so the float quotient is off by far less than 1e-4: it decides unless
-        // it lies within 1e-4 of an integer, where the integer thresholds do.
-        const float R2f = (float)R2;
-        const float r2hi = R2f * 1.0004f;
-        const float inv_c = 16.0f / sqrtf(R2f);
+        // so the float quotient t is off by far less than 1e-4: it decides
+        // unless it lies within 1e-4 of an integer up to 16, where the integer
+        // thresholds do.
+        const float inv_c = 16.0f / sqrtf((float)R2);
         // records farther than rc from the sites' bounding box along any axis
         // cannot count
         const int64_t rcl = (int64_t)ceil(sqrt((double)R2)) + 1;
         const int64_t blo[3] = {S.box[0] - rcl, S.box[1] - rcl, S.box[2] - rcl};
         const int64_t bhi[3] = {S.box[3] + rcl, S.box[4] + rcl, S.box[5] + rcl};
-        const float sf[3] = {(float)so[0], (float)so[1], (float)so[2]};
+        const float sfx = (float)so[0], sfy = (float)so[1], sfz = (float)so[2];
+        const int hrow = lane * (LIN + 1) + 16; // - (code ^ sq) + k: channel 16 for equal signs, else 0
         const int nbt = S.seg[26];
 
         for (int r0 = 0; r0 < nbt; r0 += STAGE) {
@@ -313,24 +314,24 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
                 uint4 v[2];
                 bool in[2];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int i = b0 + u * LEARN_THREADS + tid;
-                    in[u] = i < r1;
-                    v[u] = make_uint4(0, 0, 0, 0);
-                    if (in[u]) {
+                for (int uu = 0; uu < 2; ++uu) {
+                    const int i = b0 + uu * LEARN_THREADS + tid;
+                    in[uu] = i < r1;
+                    v[uu] = make_uint4(0, 0, 0, 0);
+                    if (in[uu]) {
                         int q = 0, hi = 26; // seg[q] <= i < seg[hi]
                         while (hi - q > 1) {
                             const int mid = (q + hi) >> 1;
                             if (S.seg[mid] <= i) q = mid; else hi = mid;
                         }
-                        v[u] = recb[(size_t)S.segcell[q] * cap + (uint32_t)(i - S.seg[q])];
+                        v[uu] = recb[(size_t)S.segcell[q] * cap + (uint32_t)(i - S.seg[q])];
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int qq = in[u] ? q_of(v[u].w) : 0;
-                    const int ox = (int32_t)(v[u].x - s0.x), oy = (int32_t)(v[u].y - s0.y),
-                              oz = (int32_t)(v[u].z - s0.z);
+                for (int uu = 0; uu < 2; ++uu) {
+                    const int qq = in[uu] ? q_of(v[uu].w) : 0;
+                    const int ox = (int32_t)(v[uu].x - s0.x), oy = (int32_t)(v[uu].y - s0.y),
+                              oz = (int32_t)(v[uu].z - s0.z);
                     const bool keep = qq != 0 && ox >= blo[0] && ox <= bhi[0] && oy >= blo[1] && oy <= bhi[1] &&
                                       oz >= blo[2] && oz <= bhi[2];
                     // one LDS atomic per wavefront for the records it keeps
@@ -338,32 +339,36 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
                     int slot = 0;
                     if (lane == 0 && mask) slot = atomicAdd(&S.nstaged, __popcll(mask));
                     slot = __shfl(slot, 0, 64) + __popcll(mask & lanes_below());
-                    if (keep) S.nb[slot] = make_int4(ox, oy, oz, qq);
+                    if (keep) {
+                        S.nbf[slot] = make_float4((float)ox, (float)oy, (float)oz, __int_as_float(qq > 0 ? 16 : 0));
+                        S.nbi[slot] = make_int4(ox, oy, oz, 0);
+                    }
                 }
             }
             __syncthreads();
             const int ns = S.nstaged;
             if (lane < nsite) {
                 for (int j = wave; j < ns; j += LEARN_WAVES) {
-                    const int4 o = S.nb[j];
-                    const float dx = (float)o.x - sf[0], dy = (float)o.y - sf[1], dz = (float)o.z - sf[2];
+                    const float4 o = S.nbf[j];
+                    const float dx = o.x - sfx, dy = o.y - sfy, dz = o.z - sfz;
                     const float d2f = dx * dx + dy * dy + dz * dz;
-                    bool inr = d2f < r2hi;
                     const float t = __builtin_amdgcn_sqrtf(d2f) * inv_c;
+                    const float tr = __builtin_rintf(t);
+                    bool inr = t < 16.0f;
                     int k = (int)t;
-                    const float fr = t - (float)k;
-                    if (inr && (fr < 1e-4f || fr > 0.9999f || k > 15)) {
+                    if (fabsf(t - tr) < 1e-4f && tr < 16.5f) {
                         // near a shell boundary or the cutoff: the exact integer thresholds
-                        const uint32_t ax = (uint32_t)abs((int32_t)((uint32_t)o.x - (uint32_t)so[0]));
-                        const uint32_t ay = (uint32_t)abs((int32_t)((uint32_t)o.y - (uint32_t)so[1]));
-                        const uint32_t az = (uint32_t)abs((int32_t)((uint32_t)o.z - (uint32_t)so[2]));
+                        const int4 oi = S.nbi[j];
+                        const uint32_t ax = (uint32_t)abs((int32_t)((uint32_t)oi.x - (uint32_t)so[0]));
+                        const uint32_t ay = (uint32_t)abs((int32_t)((uint32_t)oi.y - (uint32_t)so[1]));
+                        const uint32_t az = (uint32_t)abs((int32_t)((uint32_t)oi.z - (uint32_t)so[2]));
                         const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
                         inr = d2 < R2;
                         k = k > 15 ? 15 : k;
                         while (k > 0 && d2 < R2sh[k]) --k;
                         while (k < 15 && d2 >= R2sh[k + 1]) ++k;
                     }
-                    if (inr) atomicAdd(&S.hist[lane][((o.w * qion < 0) ? 0 : 16) + k], 1);
+                    if (inr) atomicAdd(&(&S.hist[0][0])[hrow - (__float_as_int(o.w) ^ sq) + k], 1);
                 }
             }
             __syncthreads();
