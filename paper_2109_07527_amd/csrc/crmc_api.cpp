@@ -73,7 +73,7 @@ struct crmc_s {
     bool collecting = false;
     bool learn_lds_set = false;
     int ncu = 0;                     // compute units of the device
-    uint4* d_lwork = nullptr;        // per colour: work items of the feature kernel
+    LearnItem* d_lwork = nullptr;    // per colour: work items of the feature kernel
     uint32_t lwork_cap = 0;
     TrialRec* d_log = nullptr;
     unsigned long long* d_log_n = nullptr;

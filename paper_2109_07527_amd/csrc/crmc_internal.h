@@ -118,14 +118,23 @@ struct SweepArgs {
                            // items of the learned proposal's feature kernel
     uint32_t* plan_heavy;  // per colour: ndom_total slots of domain indices
     uint32_t* plan_light;
-    uint4* lwork;          // per colour: lwork_cap work items (replica, cell, part, 0) of the
-                           // feature kernel, or null when no learned-proposal kernel runs
+    struct LearnItem* lwork; // per colour: lwork_cap work items of the feature kernel, or null
+                             // when no learned-proposal kernel runs
     uint32_t lwork_cap;
     int32_t learned;   // site picks by the learned proposal
     double learn_eps;  // weight of the uniform pick in it
     PhaseTrace* trace;
     unsigned long long* trace_n;
     uint64_t trace_cap;
+};
+
+// A work item of the feature kernel: sites 64 part .. 64 part + 63 of one
+// cell, with what the kernel needs of the replica resolved for the sweep
+struct LearnItem {
+    const uint4* rec;      // the sweep's record buffer of the replica
+    const uint32_t* cnt;   // its cell counts
+    double* phat;          // per site network outputs
+    uint32_t cell, part, r, n, cap, pad;
 };
 
 // arguments of the learned-proposal kernels

@@ -315,9 +315,19 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
                 if (m == 0u) continue;
                 // the capacity bounds every sweep's items (sites / 64 + cells with sites)
                 const uint32_t b = atomicAdd(&a.plan_n[PLAN_LWORK + colour], m);
-                for (uint32_t i = 0; i < m && b + i < a.lwork_cap; ++i)
-                    a.lwork[(size_t)colour * a.lwork_cap + b + i] =
-                        make_uint4(r, cell, i, 0u);
+                const int buf = (int)((*a.sweep + 1u) & 1u);
+                for (uint32_t i = 0; i < m && b + i < a.lwork_cap; ++i) {
+                    LearnItem& L = a.lwork[(size_t)colour * a.lwork_cap + b + i];
+                    L.rec = R.rec[buf];
+                    L.cnt = R.cnt[buf];
+                    L.phat = R.phat;
+                    L.cell = cell;
+                    L.part = i;
+                    L.r = r;
+                    L.n = R.n;
+                    L.cap = R.cap;
+                    L.pad = 0;
+                }
             }
         }
         const uint32_t* cntb = R.cnt[(*a.sweep + 1u) & 1u];

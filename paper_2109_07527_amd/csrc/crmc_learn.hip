@@ -29,7 +29,8 @@ constexpr int LIN = MLP_IN, LH = MLP_H;
 constexpr int SITES_PER_WG = 64;    // sites of one cell handled by one workgroup
 constexpr int LEARN_THREADS = 1024; // sixteen wavefronts: each takes every 16th staged record
 constexpr int LEARN_WAVES = LEARN_THREADS / 64;
-constexpr int STAGE = 1536;         // neighbour records staged per round
+constexpr int RAW_PER_THREAD = 4;
+constexpr int STAGE = LEARN_THREADS * RAW_PER_THREAD; // neighbour records examined per round
 
 __device__ __forceinline__ uint64_t lanes_below()
 {
@@ -172,29 +173,47 @@ __device__ __forceinline__ double site_prob(double z)
 // collected and, with the proposal on, evaluates the network on the item's
 // rows (R = float: BF16 matrix cores with the weights held in LDS for all its
 // items; R = double: FP64 per thread).  The workgroups stride over the
-// phase's items.
+// phase's items.  The loads of an item are issued in as few dependent rounds
+// as possible (item, then the cell counts, then the own and neighbour records
+// together): the kernel is bound by memory latency, not by arithmetic.
 constexpr int XS = LIN + 8, HS = LH + 8, W1S = LIN + 8, W2S = LH + 8; // padded LDS rows
 
 struct LearnShared {
     uint4 site[SITES_PER_WG];             // x, y, z, meta of the item's sites
     int hist[SITES_PER_WG][LIN + 1];      // counts (rows padded against bank conflicts)
-    float4 nbf[STAGE];                    // staged charged neighbours: float offsets from site 0, sign code
-    int4 nbi[STAGE];                      // the same offsets as exact integers
     int seg[27];                          // prefix of the 26 neighbour counts
     uint32_t segcell[26];
     int box[6];                           // least and largest site offsets from site 0 per axis
-    int nstaged;
     int wcount[LEARN_WAVES];
+    int kcount[RAW_PER_THREAD][LEARN_WAVES]; // kept records per round slot and wavefront
     uint64_t r2sh[17];
 };
 
-size_t learn_infer_lds_bytes() { return sizeof(short) * (LH * W1S + LH * W2S + 4 * 16 * XS + 4 * 16 * HS); }
+// dynamic LDS: kept neighbour records, then (FP32 network) the padded BF16
+// weights, the per-wave X and H tiles, and b1, b2, w3, b3
+size_t learn_stage_bytes() { return sizeof(int4) * STAGE; }
+size_t learn_infer_lds_bytes()
+{
+    return learn_stage_bytes() + sizeof(short) * (LH * W1S + LH * W2S + 4 * 16 * XS + 4 * 16 * HS) +
+           sizeof(float) * (3 * LH + 4);
+}
+
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
 
 template <typename Real>
 __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs g)
 {
     __shared__ LearnShared S;
-    extern __shared__ uint4 lsh4[]; // FP32 network: W1b, W2b, then per-wave X and H tiles
+    extern __shared__ uint4 lsh4[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int colour = a.colour;
     const uint32_t nwork = min(a.plan_n[PLAN_LWORK + colour], a.lwork_cap);
@@ -202,52 +221,88 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
     const uint64_t s = *a.sweep;
     const int buf = (int)((s + 1u) & 1u);
     const bool mfma = sizeof(Real) == 4 && g.infer;
-    short* W1b = (short*)lsh4;
+    int4* nb = (int4*)lsh4; // kept records: offsets from site 0, 16 for a positive charge else 0
+    short* W1b = (short*)(lsh4 + STAGE);
     short* W2b = W1b + LH * W1S;
-    short* Xw = W2b + LH * W2S + wave * (16 * XS);
-    short* Hw = W2b + LH * W2S + 4 * 16 * XS + wave * (16 * HS);
+    short* Xw = W2b + LH * W2S + (wave & 3) * (16 * XS);
+    short* Hw = W2b + LH * W2S + 4 * 16 * XS + (wave & 3) * (16 * HS);
+    float* b1 = (float*)(W2b + LH * W2S + 4 * 16 * XS + 4 * 16 * HS);
+    float* b2 = b1 + LH;
+    float* w3 = b2 + LH;
     if (mfma) {
-        // padded copies of the BF16 weights (rows of 16-byte chunks)
-        const uint4* w1 = (const uint4*)g.w1b;
-        const uint4* w2 = (const uint4*)g.w2b;
+        // padded copies of the BF16 weights (rows of 16-byte chunks) and the FP32 vectors
+        const uint4* gw1 = (const uint4*)g.w1b;
+        const uint4* gw2 = (const uint4*)g.w2b;
         for (int i = tid; i < LH * LIN / 8; i += LEARN_THREADS)
-            *(uint4*)(W1b + (i / (LIN / 8)) * W1S + (i % (LIN / 8)) * 8) = w1[i];
+            *(uint4*)(W1b + (i / (LIN / 8)) * W1S + (i % (LIN / 8)) * 8) = gw1[i];
         for (int i = tid; i < LH * LH / 8; i += LEARN_THREADS)
-            *(uint4*)(W2b + (i / (LH / 8)) * W2S + (i % (LH / 8)) * 8) = w2[i];
+            *(uint4*)(W2b + (i / (LH / 8)) * W2S + (i % (LH / 8)) * 8) = gw2[i];
+        if (tid <= 3 * LH) // b1, b2, then w3 and b3 (stored after w3)
+            b1[tid] = g.p32[tid < LH ? MLP_B1 + tid : (tid < 2 * LH ? MLP_B2 + tid - LH : MLP_W3 + tid - 2 * LH)];
     }
     for (uint32_t it = blockIdx.x; it < nwork; it += gridDim.x) {
-        const uint4 w = a.lwork[(size_t)colour * a.lwork_cap + it];
-        const uint32_t r = w.x, cell = w.y, part = w.z;
-        const Replica& R = a.reps[r];
-        const uint32_t n = R.n, cap = R.cap;
-        const uint4* recb = R.rec[buf];
-        const uint32_t* cntb = R.cnt[buf];
-        const int nown = (int)cntb[cell];
+        const LearnItem& I = a.lwork[(size_t)colour * a.lwork_cap + it];
+        const uint32_t r = I.r, cell = I.cell, part = I.part, n = I.n, cap = I.cap;
+        const uint4* recb = I.rec;
+        const uint32_t* cntb = I.cnt;
+        double* phat = I.phat;
         const int lo = (int)part * SITES_PER_WG;
+        // the cell's records are read before its count arrives (the slots up
+        // to the capacity are all inside the cell's storage)
+        uint4 own = make_uint4(0, 0, 0, 0);
+        if (tid < (int)cap) own = recb[(size_t)cell * cap + tid];
+        const int nown = (int)cntb[cell];
 
-        // neighbour cells, shell thresholds, cleared counts
-        if (tid < 26) {
-            const uint32_t cx = cell % n, cy = (cell / n) % n, cz = cell / (n * n);
-            const int oo = tid < 13 ? tid : tid + 1;
-            const uint32_t x = (cx + n + (uint32_t)(oo % 3) - 1u) % n, y = (cy + n + (uint32_t)((oo / 3) % 3) - 1u) % n,
-                           z = (cz + n + (uint32_t)(oo / 9) - 1u) % n;
-            const uint32_t c = x + n * (y + n * z);
-            S.segcell[tid] = c;
-            S.seg[tid + 1] = (int)cntb[c]; // counts now, prefix below
+        // neighbour cells and the prefix of their counts (wave 0), thresholds, cleared counts
+        if (wave == 0) {
+            int cv = 0;
+            if (lane < 26) {
+                const uint32_t cx = cell % n, cy = (cell / n) % n, cz = cell / (n * n);
+                const int oo = lane < 13 ? lane : lane + 1;
+                const uint32_t x = (cx + n + (uint32_t)(oo % 3) - 1u) % n,
+                               y = (cy + n + (uint32_t)((oo / 3) % 3) - 1u) % n, z = (cz + n + (uint32_t)(oo / 9) - 1u) % n;
+                const uint32_t c = x + n * (y + n * z);
+                S.segcell[lane] = c;
+                cv = (int)cntb[c];
+            }
+            for (int off = 1; off < 32; off <<= 1) {
+                const int y = __shfl_up(cv, off, 64);
+                if (lane >= off) cv += y;
+            }
+            if (lane < 26) S.seg[lane + 1] = cv;
+            if (lane == 0) S.seg[0] = 0;
         }
-        if (tid < 17) S.r2sh[tid] = g.R2sh[(size_t)r * 17 + tid];
-        if (tid < 6) S.box[tid] = tid < 3 ? 0x7FFFFFFF : (int)0x80000000;
+        if (tid >= 64 && tid < 64 + 17) S.r2sh[tid - 64] = g.R2sh[(size_t)r * 17 + tid - 64];
         for (int i = tid; i < SITES_PER_WG * (LIN + 1); i += LEARN_THREADS) (&S.hist[0][0])[i] = 0;
+        __syncthreads();
+        const int nbt = S.seg[26];
+
+        // the first round of neighbour records, in flight while the sites are ranked
+        uint4 v[RAW_PER_THREAD];
+        const int rr1 = min(nbt, STAGE);
+#pragma unroll
+        for (int u = 0; u < RAW_PER_THREAD; ++u) {
+            const int i = u * LEARN_THREADS + tid;
+            v[u] = make_uint4(0, 0, 0, 0);
+            if (i < rr1) {
+                int q = 0, hi = 26; // seg[q] <= i < seg[hi]
+                while (hi - q > 1) {
+                    const int mid = (q + hi) >> 1;
+                    if (S.seg[mid] <= i) q = mid; else hi = mid;
+                }
+                v[u] = recb[(size_t)S.segcell[q] * cap + (uint32_t)(i - S.seg[q])];
+            }
+        }
 
         // the item's sites: rank among the cell's sites (block prefix over wave ballots)
         int base = 0;
         for (int b0 = 0; b0 < nown; b0 += LEARN_THREADS) {
             const int i = b0 + tid;
-            uint4 v = make_uint4(0, 0, 0, 0);
+            uint4 o = make_uint4(0, 0, 0, 0);
             bool site = false;
             if (i < nown) {
-                v = recb[(size_t)cell * cap + i];
-                const uint32_t k = v.w & 7u;
+                o = b0 == 0 ? own : recb[(size_t)cell * cap + i];
+                const uint32_t k = o.w & 7u;
                 site = k == KIND_ACID || k == KIND_BASE;
             }
             const uint64_t mask = __ballot(site);
@@ -259,7 +314,7 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
                 tot += S.wcount[q];
             }
             const int rank = before + __popcll(mask & lanes_below());
-            if (site && rank >= lo && rank < lo + SITES_PER_WG) S.site[rank - lo] = v;
+            if (site && rank >= lo && rank < lo + SITES_PER_WG) S.site[rank - lo] = o;
             base += tot;
             __syncthreads();
         }
@@ -267,11 +322,6 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
         if (nsite == 0) continue; // uniform: base is the same in every thread
 
         const uint4 s0 = S.site[0];
-        if (tid == 0) {
-            int acc = 0;
-            S.seg[0] = 0;
-            for (int q = 1; q <= 26; ++q) { acc += S.seg[q]; S.seg[q] = acc; }
-        }
         int so[3] = {0, 0, 0}; // this lane's site as offsets from site 0
         int sq = 0;            // 16 when the site's ionized charge is positive
         if (lane < nsite) {
@@ -280,10 +330,14 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
             so[1] = (int32_t)(me.y - s0.y);
             so[2] = (int32_t)(me.z - s0.z);
             sq = (me.w & 7u) == KIND_ACID ? 0 : 16;
-            if (wave == 0) {
-                for (int d = 0; d < 3; ++d) {
-                    atomicMin(&S.box[d], so[d]);
-                    atomicMax(&S.box[3 + d], so[d]);
+        }
+        if (wave == 0) {
+            // the sites' bounding box (offsets from site 0; absent lanes repeat site 0)
+            for (int d = 0; d < 3; ++d) {
+                const int mn = wave_min(so[d]), mx = wave_max(so[d]);
+                if (lane == 0) {
+                    S.box[d] = mn;
+                    S.box[3 + d] = mx;
                 }
             }
         }
@@ -303,54 +357,60 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
         const int64_t bhi[3] = {S.box[3] + rcl, S.box[4] + rcl, S.box[5] + rcl};
         const float sfx = (float)so[0], sfy = (float)so[1], sfz = (float)so[2];
         const int hrow = lane * (LIN + 1) + 16; // - (code ^ sq) + k: channel 16 for equal signs, else 0
-        const int nbt = S.seg[26];
 
         for (int r0 = 0; r0 < nbt; r0 += STAGE) {
-            if (tid == 0) S.nstaged = 0;
-            __syncthreads();
             const int r1 = min(nbt, r0 + STAGE);
-            // two records per thread in flight, then the kept ones compacted
-            for (int b0 = r0; b0 < r1; b0 += 2 * LEARN_THREADS) {
-                uint4 v[2];
-                bool in[2];
+            if (r0 > 0) {
+                // a further round (more than STAGE neighbour records)
+                __syncthreads();
 #pragma unroll
-                for (int uu = 0; uu < 2; ++uu) {
-                    const int i = b0 + uu * LEARN_THREADS + tid;
-                    in[uu] = i < r1;
-                    v[uu] = make_uint4(0, 0, 0, 0);
-                    if (in[uu]) {
-                        int q = 0, hi = 26; // seg[q] <= i < seg[hi]
+                for (int u = 0; u < RAW_PER_THREAD; ++u) {
+                    const int i = r0 + u * LEARN_THREADS + tid;
+                    v[u] = make_uint4(0, 0, 0, 0);
+                    if (i < r1) {
+                        int q = 0, hi = 26;
                         while (hi - q > 1) {
                             const int mid = (q + hi) >> 1;
                             if (S.seg[mid] <= i) q = mid; else hi = mid;
                         }
-                        v[uu] = recb[(size_t)S.segcell[q] * cap + (uint32_t)(i - S.seg[q])];
+                        v[u] = recb[(size_t)S.segcell[q] * cap + (uint32_t)(i - S.seg[q])];
                     }
                 }
+                __syncthreads();
+            }
+            // keep the charged records near the sites, compacted in (slot, wavefront) order
+            uint64_t km[RAW_PER_THREAD];
+            int kx[RAW_PER_THREAD], ky[RAW_PER_THREAD], kz[RAW_PER_THREAD], kq[RAW_PER_THREAD];
 #pragma unroll
-                for (int uu = 0; uu < 2; ++uu) {
-                    const int qq = in[uu] ? q_of(v[uu].w) : 0;
-                    const int ox = (int32_t)(v[uu].x - s0.x), oy = (int32_t)(v[uu].y - s0.y),
-                              oz = (int32_t)(v[uu].z - s0.z);
-                    const bool keep = qq != 0 && ox >= blo[0] && ox <= bhi[0] && oy >= blo[1] && oy <= bhi[1] &&
-                                      oz >= blo[2] && oz <= bhi[2];
-                    // one LDS atomic per wavefront for the records it keeps
-                    const uint64_t mask = __ballot(keep);
-                    int slot = 0;
-                    if (lane == 0 && mask) slot = atomicAdd(&S.nstaged, __popcll(mask));
-                    slot = __shfl(slot, 0, 64) + __popcll(mask & lanes_below());
-                    if (keep) {
-                        S.nbf[slot] = make_float4((float)ox, (float)oy, (float)oz, __int_as_float(qq > 0 ? 16 : 0));
-                        S.nbi[slot] = make_int4(ox, oy, oz, 0);
-                    }
-                }
+            for (int u = 0; u < RAW_PER_THREAD; ++u) {
+                const int i = r0 + u * LEARN_THREADS + tid;
+                const int qq = i < r1 ? q_of(v[u].w) : 0;
+                kx[u] = (int32_t)(v[u].x - s0.x);
+                ky[u] = (int32_t)(v[u].y - s0.y);
+                kz[u] = (int32_t)(v[u].z - s0.z);
+                kq[u] = qq > 0 ? 16 : 0;
+                const bool keep = qq != 0 && kx[u] >= blo[0] && kx[u] <= bhi[0] && ky[u] >= blo[1] &&
+                                  ky[u] <= bhi[1] && kz[u] >= blo[2] && kz[u] <= bhi[2];
+                km[u] = __ballot(keep);
+                if (lane == 0) S.kcount[u][wave] = __popcll(km[u]);
             }
             __syncthreads();
-            const int ns = S.nstaged;
+            int ns = 0;
+#pragma unroll
+            for (int u = 0; u < RAW_PER_THREAD; ++u) {
+                int before = ns;
+                for (int q = 0; q < LEARN_WAVES; ++q) {
+                    before += q < wave ? S.kcount[u][q] : 0;
+                    ns += S.kcount[u][q];
+                }
+                if ((km[u] >> lane) & 1ull)
+                    nb[before + __popcll(km[u] & lanes_below())] = make_int4(kx[u], ky[u], kz[u], kq[u]);
+            }
+            __syncthreads();
             if (lane < nsite) {
                 for (int j = wave; j < ns; j += LEARN_WAVES) {
-                    const float4 o = S.nbf[j];
-                    const float dx = o.x - sfx, dy = o.y - sfy, dz = o.z - sfz;
+                    const int4 o = nb[j];
+                    const float dx = (float)o.x - sfx, dy = (float)o.y - sfy, dz = (float)o.z - sfz;
                     const float d2f = dx * dx + dy * dy + dz * dz;
                     const float t = __builtin_amdgcn_sqrtf(d2f) * inv_c;
                     const float tr = __builtin_rintf(t);
@@ -358,17 +418,16 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
                     int k = (int)t;
                     if (fabsf(t - tr) < 1e-4f && tr < 16.5f) {
                         // near a shell boundary or the cutoff: the exact integer thresholds
-                        const int4 oi = S.nbi[j];
-                        const uint32_t ax = (uint32_t)abs((int32_t)((uint32_t)oi.x - (uint32_t)so[0]));
-                        const uint32_t ay = (uint32_t)abs((int32_t)((uint32_t)oi.y - (uint32_t)so[1]));
-                        const uint32_t az = (uint32_t)abs((int32_t)((uint32_t)oi.z - (uint32_t)so[2]));
+                        const uint32_t ax = (uint32_t)abs((int32_t)((uint32_t)o.x - (uint32_t)so[0]));
+                        const uint32_t ay = (uint32_t)abs((int32_t)((uint32_t)o.y - (uint32_t)so[1]));
+                        const uint32_t az = (uint32_t)abs((int32_t)((uint32_t)o.z - (uint32_t)so[2]));
                         const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
                         inr = d2 < R2;
                         k = k > 15 ? 15 : k;
                         while (k > 0 && d2 < R2sh[k]) --k;
                         while (k < 15 && d2 >= R2sh[k + 1]) ++k;
                     }
-                    if (inr) atomicAdd(&(&S.hist[0][0])[hrow - (__float_as_int(o.w) ^ sq) + k], 1);
+                    if (inr) atomicAdd(&(&S.hist[0][0])[hrow - (o.w ^ sq) + k], 1);
                 }
             }
             __syncthreads();
@@ -392,15 +451,14 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
-                    const float z = mlp_rows16<XS, HS, W1S, W2S>(W1b, W2b, g.p32 + MLP_B1, g.p32 + MLP_B2,
-                                                                 g.p32 + MLP_W3, g.p32[MLP_B3], Xw, Hw, nullptr);
+                    const float z = mlp_rows16<XS, HS, W1S, W2S>(W1b, W2b, b1, b2, w3, w3[LH], Xw, Hw, nullptr);
                     const int rr = row0 + (lane & 15);
-                    if (lane < 16 && rr < nsite) R.phat[S.site[rr].w >> 8] = site_prob((double)z);
+                    if (lane < 16 && rr < nsite) phat[S.site[rr].w >> 8] = site_prob((double)z);
                 }
             } else if (tid < nsite) {
                 double x[LIN];
                 for (int i = 0; i < LIN; ++i) x[i] = (double)S.hist[tid][i];
-                R.phat[S.site[tid].w >> 8] = site_prob(mlp_row_f64(g.p64, x));
+                phat[S.site[tid].w >> 8] = site_prob(mlp_row_f64(g.p64, x));
             }
         }
         __syncthreads();
@@ -616,6 +674,9 @@ hipError_t set_learn_lds_limit()
     hipError_t e = hipFuncSetAttribute((const void*)k_learn<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)learn_infer_lds_bytes());
     if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_learn<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)learn_stage_bytes());
+    if (e == hipSuccess)
         e = hipFuncSetAttribute((const void*)k_mlp_fwd, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)learn_lds_bytes());
     if (e == hipSuccess)
@@ -627,7 +688,7 @@ hipError_t set_learn_lds_limit()
 hipError_t launch_learn(const SweepArgs& a, const LearnArgs& g, hipStream_t s)
 {
     if (a.precision == 64 || !g.infer)
-        hipLaunchKernelGGL(k_learn<double>, dim3(g.grid), dim3(LEARN_THREADS), 0, s, a, g);
+        hipLaunchKernelGGL(k_learn<double>, dim3(g.grid), dim3(LEARN_THREADS), learn_stage_bytes(), s, a, g);
     else
         hipLaunchKernelGGL(k_learn<float>, dim3(g.grid), dim3(LEARN_THREADS), learn_infer_lds_bytes(), s, a, g);
     return hipGetLastError();
