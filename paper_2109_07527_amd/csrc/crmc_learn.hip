@@ -27,9 +27,9 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int LIN = MLP_IN, LH = MLP_H;
 constexpr int SITES_PER_WG = 64;    // sites of one cell handled by one workgroup
-constexpr int LEARN_THREADS = 1024; // sixteen wavefronts: each takes every 16th staged record
+constexpr int LEARN_THREADS = 512;  // eight wavefronts: each takes every 8th kept record
 constexpr int LEARN_WAVES = LEARN_THREADS / 64;
-constexpr int RAW_PER_THREAD = 4;
+constexpr int RAW_PER_THREAD = 6;
 constexpr int STAGE = LEARN_THREADS * RAW_PER_THREAD; // neighbour records examined per round
 
 __device__ __forceinline__ uint64_t lanes_below()
@@ -350,11 +350,10 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
         // unless it lies within 1e-4 of an integer up to 16, where the integer
         // thresholds do.
         const float inv_c = 16.0f / sqrtf((float)R2);
-        // records farther than rc from the sites' bounding box along any axis
-        // cannot count
-        const int64_t rcl = (int64_t)ceil(sqrt((double)R2)) + 1;
-        const int64_t blo[3] = {S.box[0] - rcl, S.box[1] - rcl, S.box[2] - rcl};
-        const int64_t bhi[3] = {S.box[3] + rcl, S.box[4] + rcl, S.box[5] + rcl};
+        // a record at a squared distance of R2 or more from the sites' bounding
+        // box is at least that far from every site and cannot count
+        const int blo[3] = {S.box[0], S.box[1], S.box[2]};
+        const int bhi[3] = {S.box[3], S.box[4], S.box[5]};
         const float sfx = (float)so[0], sfy = (float)so[1], sfz = (float)so[2];
         const int hrow = lane * (LIN + 1) + 16; // - (code ^ sq) + k: channel 16 for equal signs, else 0
 
@@ -389,8 +388,13 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
                 ky[u] = (int32_t)(v[u].y - s0.y);
                 kz[u] = (int32_t)(v[u].z - s0.z);
                 kq[u] = qq > 0 ? 16 : 0;
-                const bool keep = qq != 0 && kx[u] >= blo[0] && kx[u] <= bhi[0] && ky[u] >= blo[1] &&
-                                  ky[u] <= bhi[1] && kz[u] >= blo[2] && kz[u] <= bhi[2];
+                const int64_t x = kx[u], y = ky[u], z = kz[u];
+                // gaps clamped at 2^31 (R2 < 2^60 since rc <= L / 4), so the sum cannot wrap
+                const int64_t cl = (int64_t)1 << 31;
+                const uint64_t ex = (uint64_t)min(max(max((int64_t)blo[0] - x, x - (int64_t)bhi[0]), (int64_t)0), cl);
+                const uint64_t ey = (uint64_t)min(max(max((int64_t)blo[1] - y, y - (int64_t)bhi[1]), (int64_t)0), cl);
+                const uint64_t ez = (uint64_t)min(max(max((int64_t)blo[2] - z, z - (int64_t)bhi[2]), (int64_t)0), cl);
+                const bool keep = qq != 0 && ex * ex + ey * ey + ez * ez < R2;
                 km[u] = __ballot(keep);
                 if (lane == 0) S.kcount[u][wave] = __popcll(km[u]);
             }
