@@ -75,6 +75,38 @@ def read_traffic(args):
     return float(kv["bytes_per_launch"])
 
 
+def calibrate_offsets(S, systems, first, count):
+    """Per replica and site kind, the logit offset d with mean over the
+    replica's acid (base) sites of logistic(z_i + d) equal to their ionized
+    fraction over the given sweeps; z_i are the logits the kernels used in
+    the latest sweep.  Any fixed offsets keep the chain exact."""
+    import numpy as np
+    out = []
+    for r, sy in enumerate(systems):
+        p = S.site_probabilities(r)
+        ser = S.series(r, first, count).astype(np.float64)
+        kind = np.asarray(sy["kind"])
+        pair = []
+        for col, k in ((0, 1), (1, 2)):
+            m = kind[:p.size] == k
+            if not m.any():
+                pair.append(0.0)
+                continue
+            z = np.log(p[m] / (1.0 - p[m]))
+            target = min(max(ser[:, col].mean() / m.sum(), 1e-4), 1.0 - 1e-4)
+            lo, hi = -30.0, 30.0
+            for _ in range(60):
+                mid = 0.5 * (lo + hi)
+                if np.mean(1.0 / (1.0 + np.exp(-(z + mid)))) < target:
+                    lo = mid
+                else:
+                    hi = mid
+            pair.append(round(0.5 * (lo + hi), 4))
+        S.set_proposal_offsets(r, pair[0], pair[1])
+        out.append(pair)
+    return out
+
+
 def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4):
     """The oracle as it stands (plain FP64 C, one core) on the same system at
     one pH, started from the same neutral state; rate over the sweeps of the
@@ -152,6 +184,9 @@ def main():
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--learned-eps", type=float, default=0.1)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="with --learned: per-replica logit offsets that match the mean network output of the "
+                         "acid and of the base sites to their ionized fractions")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -202,8 +237,10 @@ def main():
         # rows from plain sweeps, BF16 matrix-core training, then the learned proposal
         per_sweep = sum(int(((sy["kind"] == 1) | (sy["kind"] == 2)).sum()) for sy in systems)
         S.collect_training(args.train_rows)
-        S.sweep_ex(conds, max(1, -(-args.train_rows // max(per_sweep, 1))))
+        n_collect = max(1, -(-args.train_rows // max(per_sweep, 1)))
+        S.sweep_ex(conds, n_collect)
         rows = S.training_rows()
+        S.init_proposal_weights(7)
         torch.cuda.synchronize()
         tt = time.perf_counter()
         loss = S.train(args.epochs, batch=1024, lr=args.lr, seed=7)
@@ -211,10 +248,15 @@ def main():
         train_s = time.perf_counter() - tt
         S.collect_training(0)
         S.set_proposal(True, args.learned_eps)
+        offsets = None
+        if args.calibrate:
+            S.sweep_ex(conds, 1)
+            offsets = calibrate_offsets(S, systems, args.warmup, n_collect)
         S.sweep_ex(conds, 100)
         torch.cuda.synchronize()
         learned = {"train_rows": int(rows), "epochs": args.epochs, "batch": 1024, "lr": args.lr,
-                   "final_loss": round(loss, 5), "train_seconds": round(train_s, 3), "eps": args.learned_eps}
+                   "final_loss": round(loss, 5), "train_seconds": round(train_s, 3), "eps": args.learned_eps,
+                   "logit_offsets": offsets}
     before = [S.observe(r) for r in range(R)]
 
     # timed region: exactly --steps sweeps, replayed as captured graphs

@@ -238,7 +238,20 @@ int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out);
  * crmc_set_proposal_weights / crmc_get_proposal_weights: the network's
  *   CRMC_MLP_PARAMS FP32 parameters, W1[128][32], b1[128], W2[128][128],
  *   b2[128], w3[128], b3 (rows are output units); setting them restarts Adam.
- *   Before any are set, all are zero (every site weight 1/2).
+ *   Before any are set they hold crmc_init_proposal_weights(h, seed ^
+ *   0x5DEECE66D) of the handle's seed.
+ * crmc_init_proposal_weights: He-uniform weights from a splitmix64 stream of
+ *   seed: W1 and W2 uniform in +-sqrt(6 / fan_in), w3 in +-sqrt(3 / 128),
+ *   biases zero; restarts Adam.  (With all weights zero the hidden units and
+ *   their gradients vanish and training can move the output bias only.)
+ * crmc_set_proposal_offsets: offsets added to the network's logit for the
+ *   acid and the base sites of one replica (a calibration to the replica's
+ *   conditions; any fixed offsets keep the chain exact).  Zero after
+ *   crmc_build_cells; they take effect from the next sweep.
+ * crmc_get_site_probabilities: p_i of every site of a replica as last
+ *   evaluated (in its colour's phase of the latest sweep with the proposal
+ *   on; 0 before any), indexed by particle input order; n >= the replica's
+ *   particle count.
  * crmc_collect_training: while capacity > 0, every sweep appends one row per
  *   site and phase (32 features, then 1 if the site is ionized at the start
  *   of the phase) to a device buffer of that many rows (further rows are
@@ -258,6 +271,9 @@ int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out);
 int crmc_set_proposal(crmc_t h, int32_t learned, double eps);
 int crmc_set_proposal_weights(crmc_t h, const float* w, int64_t n);
 int crmc_get_proposal_weights(crmc_t h, float* w, int64_t n);
+int crmc_init_proposal_weights(crmc_t h, uint64_t seed);
+int crmc_set_proposal_offsets(crmc_t h, int32_t replica, double acid, double base);
+int crmc_get_site_probabilities(crmc_t h, int32_t replica, double* out, int64_t n);
 int crmc_collect_training(crmc_t h, int64_t capacity);
 int crmc_training_rows(crmc_t h, int64_t* n);
 int crmc_read_training(crmc_t h, int64_t first, int64_t count, float* out);

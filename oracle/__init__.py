@@ -94,6 +94,8 @@ def lib():
         L.orc_adam_step.argtypes = [P(d), P(d), P(d), P(d), i64, d, d, d, d]
         L.orc_set_learned.restype = C.c_int
         L.orc_set_learned.argtypes = [vp, P(d), d, C.c_int]
+        L.orc_set_learned_offsets.restype = None
+        L.orc_set_learned_offsets.argtypes = [vp, d, d]
         L.orc_features_of_cell_sites.restype = C.c_int
         L.orc_features_of_cell_sites.argtypes = [vp, C.c_int, C.c_int, P(i32), P(d)]
         _lib = L
@@ -226,6 +228,10 @@ class Oracle:
         rc = self._L.orc_set_learned(self.h, _ptr(par, C.c_double), float(eps), int(bool(on)))
         if rc:
             raise ValueError("eps must lie in (0, 1]")
+
+    def set_learned_offsets(self, acid=0.0, base=0.0):
+        """Offsets added to the network's logit of acid and base sites."""
+        self._L.orc_set_learned_offsets(self.h, float(acid), float(base))
 
     def cell_site_features(self, cell, cap=4096):
         """(site ids, features) of the sites in one cell of the last sweep's grid."""

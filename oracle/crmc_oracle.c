@@ -160,6 +160,7 @@ typedef struct {
     /* learned proposal */
     int learned;
     double lp_eps;
+    double lp_off[2];    /* logit offsets of acid and base sites */
     double* lp_par;      /* ORC_MLP_PARAMS values */
     double* lp_phat;     /* per site id: network output for the current phase */
     int lp_nsites;
@@ -510,6 +511,14 @@ int orc_features_of_cell_sites(const orc_sys* S, int c, int cap, int32_t* sid, d
 
 /* Enable the learned proposal with the given network parameters and uniform
    mixing eps (0 < eps <= 1; eps = 1 is the plain uniform proposal). */
+/* Offsets added to the network's logit of acid and base sites (a fixed
+   per-condition calibration; any fixed weights keep the chain exact). */
+void orc_set_learned_offsets(orc_sys* S, double acid, double base)
+{
+    S->lp_off[0] = acid;
+    S->lp_off[1] = base;
+}
+
 int orc_set_learned(orc_sys* S, const double* par, double eps, int on)
 {
     if (on && (!(eps > 0.0) || eps > 1.0)) return -1;
@@ -1143,7 +1152,8 @@ static void one_sweep(orc_sys* S, int32_t* series)
                         if (sp->kind != ORC_ACID && sp->kind != ORC_BASE) continue;
                         double x[ORC_MLP_IN];
                         site_features(S, sp, D.cell[j], x);
-                        S->lp_phat[sp->sid] = site_prob(orc_mlp_logit(S->lp_par, x));
+                        S->lp_phat[sp->sid] =
+                            site_prob(orc_mlp_logit(S->lp_par, x) + S->lp_off[sp->kind == ORC_ACID ? 0 : 1]);
                     }
             }
             int ntr = S->trials * D.ncell + (nsites * S->site_trials + 15) / 16;

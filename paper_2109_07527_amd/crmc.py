@@ -93,6 +93,9 @@ def load():
         "crmc_set_proposal": (C.c_int, [vp, i32, d]),
         "crmc_set_proposal_weights": (C.c_int, [vp, P(C.c_float), i64]),
         "crmc_get_proposal_weights": (C.c_int, [vp, P(C.c_float), i64]),
+        "crmc_init_proposal_weights": (C.c_int, [vp, u64]),
+        "crmc_set_proposal_offsets": (C.c_int, [vp, i32, d, d]),
+        "crmc_get_site_probabilities": (C.c_int, [vp, i32, P(d), i64]),
         "crmc_collect_training": (C.c_int, [vp, i64]),
         "crmc_training_rows": (C.c_int, [vp, P(i64)]),
         "crmc_read_training": (C.c_int, [vp, i64, i64, P(C.c_float)]),
@@ -289,6 +292,22 @@ def crmc_get_proposal_weights(h):
     return w
 
 
+def crmc_init_proposal_weights(h, seed):
+    return _check(h, load().crmc_init_proposal_weights(h, int(seed) & (2**64 - 1)))
+
+
+def crmc_set_proposal_offsets(h, replica, acid, base):
+    return _check(h, load().crmc_set_proposal_offsets(h, int(replica), float(acid), float(base)))
+
+
+def crmc_get_site_probabilities(h, replica):
+    n = C.c_int64(0)
+    _check(h, load().crmc_get_occupancy(h, int(replica), 0, None, C.byref(n)))  # particle count
+    out = np.zeros(max(n.value, 1), dtype=np.float64)
+    _check(h, load().crmc_get_site_probabilities(h, int(replica), _p(out, C.c_double), out.size))
+    return out[:n.value]
+
+
 def crmc_collect_training(h, capacity):
     return _check(h, load().crmc_collect_training(h, int(capacity)))
 
@@ -442,6 +461,15 @@ class System:
 
     def proposal_weights(self):
         return crmc_get_proposal_weights(self.h)
+
+    def init_proposal_weights(self, seed):
+        return crmc_init_proposal_weights(self.h, seed)
+
+    def set_proposal_offsets(self, replica, acid, base):
+        return crmc_set_proposal_offsets(self.h, replica, acid, base)
+
+    def site_probabilities(self, replica):
+        return crmc_get_site_probabilities(self.h, replica)
 
     def collect_training(self, capacity):
         return crmc_collect_training(self.h, capacity)

@@ -279,6 +279,27 @@ int upload_descriptors(crmc_t h)
     return CRMC_OK;
 }
 
+// He-uniform initial network: W1 and W2 from U(-sqrt(6 / fan_in), +sqrt(6 / fan_in)),
+// w3 from U(-sqrt(3 / 128), +sqrt(3 / 128)), biases zero; splitmix64 stream of seed
+std::vector<float> initial_weights(uint64_t seed)
+{
+    std::vector<float> w(MLP_PARAMS, 0.0f);
+    uint64_t x = seed;
+    auto uniform = [&x]() {
+        x += 0x9E3779B97F4A7C15ull;
+        uint64_t z = x;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0; // [-1, 1)
+    };
+    const double a1 = std::sqrt(6.0 / MLP_IN), a2 = std::sqrt(6.0 / MLP_H), a3 = std::sqrt(3.0 / MLP_H);
+    for (int i = 0; i < MLP_B1; ++i) w[(size_t)i] = (float)(a1 * uniform());
+    for (int i = MLP_W2; i < MLP_B2; ++i) w[(size_t)i] = (float)(a2 * uniform());
+    for (int i = MLP_W3; i < MLP_B3; ++i) w[(size_t)i] = (float)(a3 * uniform());
+    return w;
+}
+
 int ensure_params(crmc_t h)
 {
     if (h->d_p32) return CRMC_OK;
@@ -290,7 +311,10 @@ int ensure_params(crmc_t h)
     HIP_TRY(h, dalloc(&h->d_adam_v, MLP_PARAMS));
     HIP_TRY(h, dalloc(&h->d_grad, MLP_PARAMS));
     HIP_TRY(h, dalloc(&h->d_loss, 1));
-    HIP_TRY(h, hipMemset(h->d_p32, 0, MLP_PARAMS * sizeof(float)));
+    {
+        const std::vector<float> w0 = initial_weights(h->p.seed ^ 0x5DEECE66Dull);
+        HIP_TRY(h, hipMemcpy(h->d_p32, w0.data(), MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
+    }
     HIP_TRY(h, hipMemset(h->d_adam_m, 0, MLP_PARAMS * sizeof(float)));
     HIP_TRY(h, hipMemset(h->d_adam_v, 0, MLP_PARAMS * sizeof(float)));
     HIP_TRY(h, hipMemset(h->d_grad, 0, MLP_PARAMS * sizeof(float)));
@@ -303,7 +327,7 @@ int ensure_params(crmc_t h)
     g.p64 = h->d_p64;
     g.w1b = h->d_w1b;
     g.w2b = h->d_w2b;
-    HIP_TRY(h, launch_params_convert(g, h->stream)); // all-zero network: every site weight 1/2
+    HIP_TRY(h, launch_params_convert(g, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return CRMC_OK;
 }
@@ -691,6 +715,7 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     HIP_TRY(h, dalloc(&d.moves, 12));
     HIP_TRY(h, dalloc(&d.series, (size_t)series_cap * 4));
     HIP_TRY(h, dalloc(&d.phat, (size_t)std::max(n, 1)));
+    HIP_TRY(h, hipMemset(d.phat, 0, (size_t)std::max(n, 1) * sizeof(double)));
     HIP_TRY(h, dalloc(&d.nsc, ncells));
     HIP_TRY(h, hipMemset(d.nsc, 0, ncells * sizeof(uint32_t)));
     HIP_TRY(h, hipMemcpy(d.rec[0], cells.data(), nrec * sizeof(uint4), hipMemcpyHostToDevice));
@@ -955,6 +980,34 @@ int crmc_set_proposal_weights(crmc_t h, const float* w, int64_t n)
     h->adam_t = 0;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     return CRMC_OK;
+}
+
+int crmc_set_proposal_offsets(crmc_t h, int32_t replica, double acid, double base)
+{
+    if (!h || replica < 0 || replica >= (int32_t)h->reps.size() || !std::isfinite(acid) || !std::isfinite(base))
+        return fail(h, CRMC_E_ARG, "invalid replica or offset");
+    h->reps[(size_t)replica].d.lp_off[0] = acid;
+    h->reps[(size_t)replica].d.lp_off[1] = base;
+    return CRMC_OK;
+}
+
+int crmc_get_site_probabilities(crmc_t h, int32_t replica, double* out, int64_t n)
+{
+    if (!h || !out || replica < 0 || replica >= (int32_t)h->reps.size())
+        return fail(h, CRMC_E_ARG, "invalid replica or buffer");
+    const HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    if (n < (int64_t)r.nsites) return fail(h, CRMC_E_ARG, "buffer smaller than the replica's particle count");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(out, r.d.phat, (size_t)r.nsites * sizeof(double), hipMemcpyDeviceToHost));
+    return CRMC_OK;
+}
+
+int crmc_init_proposal_weights(crmc_t h, uint64_t seed)
+{
+    if (!h) return CRMC_E_ARG;
+    const std::vector<float> w = initial_weights(seed);
+    return crmc_set_proposal_weights(h, w.data(), MLP_PARAMS);
 }
 
 int crmc_get_proposal_weights(crmc_t h, float* w, int64_t n)

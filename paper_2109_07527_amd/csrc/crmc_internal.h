@@ -73,6 +73,7 @@ struct Replica {
     uint32_t dom_begin;      // prefix of domains per phase over replicas
     uint32_t* nsc;           // per cell: acid and base sites as binned at the start of the sweep
     double* phat;            // per site: network output of the current phase (learned proposal)
+    double lp_off[2];        // logit offsets of acid and base sites (learned proposal)
     double L, scale, lnZ0;   // scale = L / 2^32; lnZ0 = ln(rho0 NA) + 3 ln(scale)
     uint64_t R2;             // Coulomb cutoff on the integer squared distance
     double lnKA, lnKB, lnKion, kappa;
@@ -134,6 +135,7 @@ struct LearnItem {
     const uint4* rec;      // the sweep's record buffer of the replica
     const uint32_t* cnt;   // its cell counts
     double* phat;          // per site network outputs
+    double off[2];         // logit offsets of acid and base sites
     uint32_t cell, part, r, n, cap, pad;
 };
 

@@ -246,6 +246,7 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
         const uint4* recb = I.rec;
         const uint32_t* cntb = I.cnt;
         double* phat = I.phat;
+        const double off_acid = I.off[0], off_base = I.off[1];
         const int lo = (int)part * SITES_PER_WG;
         // the cell's records are read before its count arrives (the slots up
         // to the capacity are all inside the cell's storage)
@@ -457,12 +458,16 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
                     __builtin_amdgcn_wave_barrier();
                     const float z = mlp_rows16<XS, HS, W1S, W2S>(W1b, W2b, b1, b2, w3, w3[LH], Xw, Hw, nullptr);
                     const int rr = row0 + (lane & 15);
-                    if (lane < 16 && rr < nsite) phat[S.site[rr].w >> 8] = site_prob((double)z);
+                    if (lane < 16 && rr < nsite) {
+                        const uint32_t m = S.site[rr].w;
+                        phat[m >> 8] = site_prob((double)z + ((m & 7u) == KIND_ACID ? off_acid : off_base));
+                    }
                 }
             } else if (tid < nsite) {
                 double x[LIN];
                 for (int i = 0; i < LIN; ++i) x[i] = (double)S.hist[tid][i];
-                phat[S.site[tid].w >> 8] = site_prob(mlp_row_f64(g.p64, x));
+                const uint32_t m = S.site[tid].w;
+                phat[m >> 8] = site_prob(mlp_row_f64(g.p64, x) + ((m & 7u) == KIND_ACID ? off_acid : off_base));
             }
         }
         __syncthreads();

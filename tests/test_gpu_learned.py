@@ -3,7 +3,8 @@
 The network's BF16 matrix-core forward and backward passes against the FP64
 oracle at the same (BF16-rounded) parameters; the FP64 chain with the learned
 proposal bit for bit against the oracle's; eps = 1 against the plain chain;
-training rows and a short training run.
+training rows, a short training run, and training from the library's
+initial weights.
 """
 import numpy as np
 import pytest
@@ -13,6 +14,7 @@ from workloads import random_sites, nanoparticle_pair, config1
 
 pytestmark = pytest.mark.gpu
 NP_ = 20865
+MLP_B1, MLP_W2, MLP_B2 = 4096, 4224, 4224 + 16384  # W1 [0, 4096), b1, W2 [4224, 20608)
 
 
 def _gpu():
@@ -94,7 +96,8 @@ def _case(name):
     return s, dict(lB=2.0, rc=6.0), dict(pH=4.5, pKa=4.5, pKb=5.0, pIX_pos=s["pIX"], pIX_neg=s["pIX"], kappa=0.5)
 
 
-def _run_pair(crmc, name, eps, learned_gpu=True, learned_oracle=True, nsw=12, trials=2, seed=71, scale=2.0):
+def _run_pair(crmc, name, eps, learned_gpu=True, learned_oracle=True, nsw=12, trials=2, seed=71, scale=2.0,
+              offsets=(0.0, 0.0)):
     s, m, c = _case(name)
     p = _params(9, scale)
     S = crmc.System(n_replicas=1, lB=m["lB"], rc=m["rc"], precision=64, trials_per_cell=trials, seed=seed)
@@ -103,6 +106,7 @@ def _run_pair(crmc, name, eps, learned_gpu=True, learned_oracle=True, nsw=12, tr
         kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
     S.build_cells(0, **kw)
     S.set_proposal_weights(p)
+    S.set_proposal_offsets(0, *offsets)
     if learned_gpu:
         S.set_proposal(True, eps)
     S.sweep_ex([c], nsw)
@@ -116,14 +120,16 @@ def _run_pair(crmc, name, eps, learned_gpu=True, learned_oracle=True, nsw=12, tr
     o.set_schedule(trials)
     if learned_oracle:
         o.set_learned(p.astype(np.float64), eps)
+        o.set_learned_offsets(*offsets)
     ser = o.sweeps(nsw)
     return S, obs, o, ser, nsw
 
 
-@pytest.mark.parametrize("name", ["mixed", "np_pair_small", "chain40"])
-def test_fp64_learned_chain_bit_exact(name):
+@pytest.mark.parametrize("name,offsets", [("mixed", (0.0, 0.0)), ("np_pair_small", (0.0, 0.0)),
+                                          ("chain40", (0.0, 0.0)), ("np_pair_small", (-2.5, 1.5))])
+def test_fp64_learned_chain_bit_exact(name, offsets):
     crmc = _gpu()
-    S, obs, o, ser, nsw = _run_pair(crmc, name, 0.1)
+    S, obs, o, ser, nsw = _run_pair(crmc, name, 0.1, offsets=offsets)
     for a, b in zip(S.particles(0), o.particles()):
         assert np.array_equal(np.asarray(a).astype(np.int64), np.asarray(b).astype(np.int64))
     assert np.array_equal(S.series(0, 0, nsw), ser)
@@ -187,3 +193,56 @@ def test_training_rows_and_a_short_training_run():
     assert np.isfinite(l1) and l5 < l1
     w = S.proposal_weights()
     assert np.isfinite(w).all() and not np.array_equal(w, _params(11, 0.5))
+
+
+def test_training_from_the_initial_weights_learns_the_features():
+    """From the library's initial (He-uniform) weights, training moves the
+    hidden layers and fits better than the best constant predictor, whose
+    loss is the label entropy; all-zero weights could only move the output
+    bias."""
+    crmc = _gpu()
+    s, m, c = _case("np_pair_small")
+    S = crmc.System(n_replicas=1, lB=2.0, rc=6.0, precision=32, trials_per_cell=4, seed=3)
+    S.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"])
+    S.sweep_ex([c], 50)
+    S.collect_training(100000)
+    S.sweep_ex([c], 200)
+    rows = S.read_training()
+    y = rows[:, 32]
+    ybar = float(y.mean())
+    h_const = -(ybar * np.log(ybar) + (1.0 - ybar) * np.log(1.0 - ybar))
+    w0 = S.proposal_weights()
+    assert np.abs(w0[:MLP_B1]).max() > 0.1 and np.abs(w0[MLP_W2:MLP_B2]).max() > 0.1
+    loss = S.train(20, batch=256, lr=2e-3, seed=4)
+    w1 = S.proposal_weights()
+    assert np.abs(w1[:MLP_B1] - w0[:MLP_B1]).max() > 1e-3
+    assert np.abs(w1[MLP_W2:MLP_B2] - w0[MLP_W2:MLP_B2]).max() > 1e-3
+    assert loss < 0.97 * h_const, (loss, h_const)
+    z = S.mlp_forward(rows[:2000, :32].astype(np.float32))
+    assert np.std(z) > 0.1
+    # re-drawing from a seed is deterministic and restarts from those weights
+    S.init_proposal_weights(99)
+    a = S.proposal_weights()
+    S.init_proposal_weights(99)
+    assert np.array_equal(a, S.proposal_weights()) and not np.array_equal(a, w1)
+
+
+def test_site_probabilities_follow_the_network_and_offsets():
+    """The p_i the kernels used, read back, against the network evaluated on
+    the host (FP64 path): with offsets (a, b) every acid's logit moves by a
+    and every base's by b, and the chain with the offsets is still the
+    oracle's (bit-exact test above)."""
+    crmc = _gpu()
+    S0, obs0, _, _, _ = _run_pair(crmc, "np_pair_small", 0.1, learned_oracle=False)
+    S1, obs1, _, _, _ = _run_pair(crmc, "np_pair_small", 0.1, learned_oracle=False, nsw=12, offsets=(-2.5, 1.5))
+    p0, p1 = S0.site_probabilities(0), S1.site_probabilities(0)
+    kind = np.asarray(_case("np_pair_small")[0]["kind"])
+    site = (kind == 1) | (kind == 2)
+    assert np.all((p0[site] > 0) & (p0[site] < 1)) and np.all((p1[site] > 0) & (p1[site] < 1))
+    # the two chains differ, so compare the spread of logits, not site by site
+    z0 = np.log(p0[site] / (1 - p0[site]))
+    assert np.std(z0) > 0.05
+    z1 = np.log(p1[site] / (1 - p1[site]))
+    ks = kind[site]
+    assert np.median(z1[ks == 1]) < np.median(z0[ks == 1]) - 1.0
+    assert np.median(z1[ks == 2]) > np.median(z0[ks == 2]) + 0.5

@@ -178,7 +178,8 @@ def _near_charge_params(a, b):
     return par
 
 
-def test_learned_proposal_keeps_per_site_occupancies():
+@pytest.mark.parametrize("offsets", [(0.0, 0.0), (-3.0, 1.0)])
+def test_learned_proposal_keeps_per_site_occupancies(offsets):
     """T-13 with power: four acid sites in one cell, a base (always charged)
     two to four sigma away; the network strongly prefers the two acids
     nearest to the base.  Every per-site occupancy, and the near-minus-far
@@ -198,6 +199,7 @@ def test_learned_proposal_keeps_per_site_occupancies():
     o.set_particles(xyz, np.array(kinds))
     o.set_schedule(8)
     o.set_learned(_near_charge_params(4.0, -2.0), 0.02)
+    o.set_learned_offsets(*offsets)
     nsw = 4000
     occ = np.zeros((nsw, 5))
     for t in range(nsw):
