@@ -7,7 +7,7 @@
 //                cells that overlap it (at most 27, usually 8): no atomics, no scan.
 //   k_plan       per sweep: sorts the domains of every colour into light ones
 //                (one wavefront each) and heavy ones (a whole workgroup).
-//   k_phase<R>   per colour: every domain (one cell, or two reflection-paired
+//   k_phase<R, L> per colour: every domain (one cell, or two reflection-paired
 //                cells of the colour) runs its trials back to back: Philox
 //                words twelve trials at a time, move and participants, pair
 //                sum of the energy change over the domain's own lists (LDS)
@@ -686,7 +686,7 @@ constexpr uint32_t CLS_MASK_SITE = 0xFu, CLS_MASK_ION = 0x7u;
 // The domain's trials.  wpd wavefronts share the pair sums (wpd = 1: light
 // domain, no workgroup barriers; wpd = 4: heavy domain, the whole workgroup;
 // uniform over the workgroup).
-template <typename Real>
+template <typename Real, bool LEARNED>
 __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint4* __restrict__ pool,
                                            int pool_records, int wid, const int wpd, double (*red)[4], int (*ovf)[4])
 {
@@ -712,7 +712,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     int n0 = (int)R.cnt0[G.cell0];
     int n1 = ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
     const int ntr_max = a.trials * ncell + ((n0 + n1) * a.site_trials + 15) / 16;
-    const Pool pl = pool_layout(n0, n1, ncell, ntr_max, cap, ncores, a.learned);
+    const Pool pl = pool_layout(n0, n1, ncell, ntr_max, cap, ncores, LEARNED ? 1 : 0);
     if (pl.st_off > pool_records) { // the plan and the host size pools so that this never happens
         if (tid == 0) atomicOr(a.err, ERR_POOL);
         return;
@@ -795,7 +795,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     // ---- learned proposal: site probabilities of the lists, class weights ------
     double* aux = reinterpret_cast<double*>(pool + pl.aux_off);
     ClassW cw{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    const bool learned = a.learned != 0;
+    constexpr bool learned = LEARNED;
     if (learned) {
         const double* phat = R.phat;
         for (int i = tid; i < n0 + n1; i += nt) {
@@ -1264,8 +1264,10 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
 extern __shared__ uint4 smem[];
 
 // heavy domains first (one workgroup each), then light ones (four per
-// workgroup, one per wavefront); the grid is an upper bound
-template <typename Real>
+// workgroup, one per wavefront); the grid is an upper bound.  The learned
+// proposal's code is compiled only into the LEARNED instances, so that the
+// plain kernel keeps its register budget (three wavefronts per SIMD).
+template <typename Real, bool LEARNED>
 __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
 {
     __shared__ double red[2][4];
@@ -1280,7 +1282,8 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
     const int q = heavy ? a.pool : a.pool / 4;
     const uint32_t gd = heavy ? a.plan_heavy[(size_t)colour * a.ndom_total + j]
                               : a.plan_light[(size_t)colour * a.ndom_total + j];
-    run_domain<Real>(a, gd, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0, heavy ? 4 : 1, red, ovf);
+    run_domain<Real, LEARNED>(a, gd, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0, heavy ? 4 : 1, red,
+                              ovf);
 }
 
 // ------------------------------------------------------------------------
@@ -1403,10 +1406,14 @@ hipError_t launch_plan(const SweepArgs& a, hipStream_t s)
 
 hipError_t launch_phase(const SweepArgs& a, size_t lds, hipStream_t s)
 {
-    if (a.precision == 64)
-        hipLaunchKernelGGL(k_phase<double>, dim3(a.ndom_total), dim3(PHASE_THREADS), lds, s, a);
-    else
-        hipLaunchKernelGGL(k_phase<float>, dim3(a.ndom_total), dim3(PHASE_THREADS), lds, s, a);
+    const dim3 grid(a.ndom_total), block(PHASE_THREADS);
+    if (a.precision == 64) {
+        if (a.learned) hipLaunchKernelGGL((k_phase<double, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_phase<double, false>), grid, block, lds, s, a);
+    } else {
+        if (a.learned) hipLaunchKernelGGL((k_phase<float, true>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_phase<float, false>), grid, block, lds, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -1434,7 +1441,8 @@ hipError_t launch_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k
 
 hipError_t set_phase_lds_limit(size_t bytes)
 {
-    const void* fns[] = {(const void*)k_phase<float>, (const void*)k_phase<double>};
+    const void* fns[] = {(const void*)k_phase<float, false>, (const void*)k_phase<double, false>,
+                         (const void*)k_phase<float, true>, (const void*)k_phase<double, true>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
