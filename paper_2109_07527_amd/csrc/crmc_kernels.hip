@@ -6,16 +6,17 @@
 //                pairing table.  One wavefront per new cell gathers from the old
 //                cells that overlap it (at most 27, usually 8): no atomics, no scan.
 //   k_plan       per sweep: sorts the domains of every colour into light ones
-//                (one wavefront each) and heavy ones (a whole workgroup).
+//                (one wavefront each) and heavy ones (a whole workgroup); with
+//                the learned proposal on, lists the feature kernel's work items.
 //   k_phase<R, L> per colour: every domain (one cell, or two reflection-paired
 //                cells of the colour) runs its trials back to back: Philox
-//                words twelve trials at a time, move and participants, pair
+//                words ten trials at a time, move and participants, pair
 //                sum of the energy change over the domain's own lists (LDS)
 //                and its 26-cell neighbourhoods (staged in LDS once, the excess
 //                read from memory), R = float or double terms with FP64
 //                accumulation,
 //                acceptance of Sec. II C, commit in LDS; writes the cells back
-//                at the end.
+//                at the end.  L: the learned site proposal compiled in.
 //   k_sweep_end  per sweep: series row, group histograms, sweep counter.
 //   k_energy     total energy of a replica from scratch (FP64), per cell.
 #include "crmc_internal.h"
