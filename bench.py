@@ -144,14 +144,16 @@ WORKLOADS = {
             "(pI_X=0.668), lB=2, kappa=0.5, rc=8; 9 replicas pH 3..11",
     "chains": "256 weak-acid chains of seeded uneven length 50..2000 (pKa 4.5, pI_S 2), 16x16 grid of "
               "pH 2..12 x kappa 0.1..1.0, lB=2, rc=6, L_r = 12 ceil(40 (N_r/40)^(1/3) / 12); one launch per phase",
+    "suspension": "64 nanoparticles (R=8, 800 sites each, 32 acid- and 32 base-coated, pKa=pKb=5) in L=300, "
+                  "~2e5 ions (pI_X=0.862), lB=2, kappa=0.5, rc=8; 8 replicas pH 3..10",
 }
 
 
 def load_workload(name):
     """(systems, per-replica conditions, model constants) of a workload."""
-    from workloads import config2, config3
-    if name == "pair":
-        c = config2()
+    from workloads import config2, config3, config5
+    if name in ("pair", "suspension"):
+        c = config2() if name == "pair" else config5()
         conds = [dict(pH=pH, pKa=c["pKa"], pKb=c["pKb"], pIX_pos=c["pIX"], pIX_neg=c["pIX"], kappa=c["kappa"])
                  for pH in c["pH_list"]]
         return [c] * len(conds), conds, dict(lB=c["lB"], rc=c["rc"])
@@ -193,7 +195,7 @@ def main():
                     help="only run a plain device copy of MIB MiB ten times (counter calibration) and exit")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = 10000 if args.workload == "pair" else 1000
+        args.steps = {"pair": 10000, "chains": 1000, "suspension": 500}[args.workload]
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -320,7 +322,7 @@ def main():
         config["autotuned"] = {"light_neighbours": tuned["light_neighbours"], "lds_records": tuned["lds_records"],
                                "candidates": len(tuned["candidates"]),
                                "best_ms_per_sweep": round(tuned["best_ms_per_sweep"], 4)}
-    if args.workload == "pair":
+    if args.workload != "chains":
         config.update(cells_per_edge=after[0]["n_cells"], cell_capacity=after[0]["cell_capacity"])
     line = {
         "metric": METRIC, "value": round(rate, 1), "unit": "trial moves/s", "n_gpus": 1,
@@ -335,19 +337,21 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
-    if args.workload == "pair":
+    if args.workload != "chains":
         line.update(tau_int_sweeps=taus, alpha_acid=alphaA, alpha_base=alphaB)
     else:
         line.update(tau_int_sweeps_median=float(np.median(taus)), tau_int_sweeps_max=float(np.max(taus)),
                     alpha_acid_range=[float(np.min(alphaA)), float(np.max(alphaA))])
     if not args.no_cpu_baseline:
-        rb = 4 if args.workload == "pair" else int(np.argsort([len(sy["kind"]) for sy in systems])[R // 2])
+        rb = {"pair": 4, "suspension": 4}.get(args.workload)
+        if rb is None:
+            rb = int(np.argsort([len(sy["kind"]) for sy in systems])[R // 2])
         sysd = dict(systems[rb])
         sysd["n_cells"] = after[rb]["n_cells"]
         sysd["lB"], sysd["rc"] = model["lB"], model["rc"]
         line["cpu_baseline"] = cpu_baseline(sysd, conds[rb], args.trials, args.site_trials, args.cpu_seconds,
                                             replica=rb)
-        if args.workload != "pair":
+        if args.workload == "chains":
             line["cpu_baseline"]["sample"] += " (median-length chain, replica %d)" % rb
     print(json.dumps(line), flush=True)
 
