@@ -107,7 +107,7 @@ def calibrate_offsets(S, systems, first, count):
     return out
 
 
-def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4):
+def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4, pairing=True):
     """The oracle as it stands (plain FP64 C, one core) on the same system at
     one pH, started from the same neutral state; rate over the sweeps of the
     last half of the sample."""
@@ -118,7 +118,7 @@ def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4):
     o.set_particles(system["xyz"], system["kind"])
     if len(system.get("core_R", [])):
         o.set_cores(system["core_xyz"], system["core_R"])
-    o.set_schedule(trials, pairing=True, site_trials=site_trials)
+    o.set_schedule(trials, pairing=pairing, site_trials=site_trials)
     t_start = time.perf_counter()
     marks = []
     while True:
@@ -174,6 +174,8 @@ def main():
     ap.add_argument("--site-trials", type=int, default=0, help="extra trials per 16 sites of a domain")
     ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per phase workgroup in records (0 = default)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one in the timed region")
+    ap.add_argument("--no-pairing", action="store_true",
+                    help="single-cell domains instead of reflection-paired cell pairs")
     ap.add_argument("--kernel-steps", type=int, default=400, help="sweeps of the per-kernel event timing pass")
     ap.add_argument("--light-neighbours", type=int, default=0,
                     help="neighbour records up to which a domain runs on one wavefront (0 = library default)")
@@ -224,7 +226,7 @@ def main():
     systems, conds, model = load_workload(args.workload)
     R = len(conds)
     S = crmc.System(n_replicas=R, lB=model["lB"], rc=model["rc"], eps=1.0, precision=args.precision,
-                    trials_per_cell=args.trials, pairing=True, seed=2024, site_trials=args.site_trials,
+                    trials_per_cell=args.trials, pairing=not args.no_pairing, seed=2024, site_trials=args.site_trials,
                     lds_records=args.lds_records, use_graph=not args.no_graph,
                     light_neighbours=args.light_neighbours)
     for r in range(R):
@@ -314,7 +316,7 @@ def main():
     config = {"workload": WORKLOADS[args.workload], "replicas": R, "trials_per_cell": args.trials,
               "site_trials_per_16": args.site_trials, "graph": not args.no_graph,
               "light_neighbours": args.light_neighbours, "lds_records": args.lds_records,
-              "schedule": "shifted cells, paired domains",
+              "schedule": "shifted cells, " + ("single-cell domains" if args.no_pairing else "paired domains"),
               "cells_total": int(sum(cells)), "records_mean": round(float(sum(n_rec)), 1)}
     if learned is not None:
         config["learned_proposal"] = learned
@@ -350,7 +352,7 @@ def main():
         sysd["n_cells"] = after[rb]["n_cells"]
         sysd["lB"], sysd["rc"] = model["lB"], model["rc"]
         line["cpu_baseline"] = cpu_baseline(sysd, conds[rb], args.trials, args.site_trials, args.cpu_seconds,
-                                            replica=rb)
+                                            replica=rb, pairing=not args.no_pairing)
         if args.workload == "chains":
             line["cpu_baseline"]["sample"] += " (median-length chain, replica %d)" % rb
     print(json.dumps(line), flush=True)
