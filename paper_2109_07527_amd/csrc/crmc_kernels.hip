@@ -542,6 +542,18 @@ __device__ __forceinline__ void uniform_chg(Chg& c)
     c.pres_old = rfl(c.pres_old); c.pres_new = rfl(c.pres_new);
 }
 
+// u < exp(min(0, lnp)) in FP64, decided from the single-precision exponential
+// unless u lies within 1e-4 (relative) of it: that estimate is off by a few
+// 1e-6 at most, so only near-ties pay for the double-precision exp
+__device__ __forceinline__ bool metropolis(double u, double lnp)
+{
+    if (!(lnp < 0.0)) return u < 1.0;
+    const double e = (double)__expf((float)lnp);
+    if (u < e * (1.0 - 1e-4)) return true;
+    if (u > e * (1.0 + 1e-4)) return false;
+    return u < exp(lnp);
+}
+
 // LDS written by one lane becomes visible to the other lanes of its wavefront
 // in program order; this keeps the compiler from moving memory accesses across
 __device__ __forceinline__ void wave_sync()
@@ -1143,7 +1155,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         dU = rfld(dU);
         if (rfl(any_ov)) dU = __longlong_as_double(0x7FF0000000000000ll);
         const double lnp = lnp_counts + lnvol - dU;
-        const bool accept = rfl(!cap_fail && u < exp(lnp < 0.0 ? lnp : 0.0)) != 0;
+        const bool accept = rfl(!cap_fail && metropolis(u, lnp)) != 0;
         if (tid == 0) {
             if (cap_fail) atomicOr(a.err, ERR_INSERT_CAPACITY);
             if (a.log) {
