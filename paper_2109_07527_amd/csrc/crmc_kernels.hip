@@ -400,11 +400,12 @@ __device__ __forceinline__ int code_ion(uint32_t code) { return (int)((code >> 2
 // records inside the Coulomb cutoff (times lB dq at the end), aw = excluded
 // volume change; ov set on an overlap created by an insertion.  valid = 0
 // masks the lane out.  Branch-free on the common path (the 64 lanes diverge
-// anyway); the rare cases (a distance within 1e-5 of rc, or within the WCA
-// range) are handled behind wavefront-uniform tests.
+// anyway).  A record within 1e-5 of rc (rare) is left out and flagged in
+// `band`; pair_band adds it afterwards if its exact integer distance is inside
+// the cutoff.  The excluded-volume term sits behind a wavefront-uniform test.
 template <typename Real>
 __device__ __forceinline__ void pair_acc(const uint4& rec, uint32_t code, bool valid, const Chg& c,
-                                         const PairParams& P, double& aq, double& aw, int& ov)
+                                         const PairParams& P, double& aq, double& aw, int& ov, int& band)
 {
     const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
     const Real sc = scale_of<Real>(P);
@@ -412,13 +413,8 @@ __device__ __forceinline__ void pair_acc(const uint4& rec, uint32_t code, bool v
     const Real r2 = fx * fx + fy * fy + fz * fz;
     const bool coupled = valid && (P.ion_coupling || !code_ion(code));
     if (c.dq != 0) {
-        bool in = r2 < (Real)P.rc2_lo;
-        const bool band = !in && r2 <= (Real)P.rc2_hi;
-        if (__ballot(band)) {
-            const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
-            const bool exact = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az < P.R2;
-            in = in || (band && exact);
-        }
+        const bool in = r2 < (Real)P.rc2_lo;
+        band |= (coupled && !in && r2 <= (Real)P.rc2_hi) ? 1 : 0;
         const Real rinv = Math<Real>::rsqrt(r2);
         const Real phi = Math<Real>::ex(-(Real)P.kappa * (r2 * rinv)) * rinv;
         const Real qphi = (Real)code_q(code) * phi;
@@ -433,6 +429,28 @@ __device__ __forceinline__ void pair_acc(const uint4& rec, uint32_t code, bool v
             const Real w = (Real)4.0 * (Real)P.eps * (ir6 * ir6 - ir6) + (Real)P.eps;
             aw += (double)((near && !over) ? (Real)c.dw * w : (Real)0);
             if (over && c.dw > 0) ov = 1;
+        }
+    }
+}
+
+// the Coulomb term of a record in the band around rc, if its exact squared
+// lattice distance is inside the cutoff
+template <typename Real>
+__device__ __forceinline__ void pair_band(const uint4& rec, uint32_t code, bool valid, const Chg& c,
+                                          const PairParams& P, double& aq)
+{
+    if (c.dq == 0) return;
+    const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
+    const Real sc = scale_of<Real>(P);
+    const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
+    const Real r2 = fx * fx + fy * fy + fz * fz;
+    const bool coupled = valid && (P.ion_coupling || !code_ion(code));
+    if (coupled && !(r2 < (Real)P.rc2_lo) && r2 <= (Real)P.rc2_hi) {
+        const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
+        if ((uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az < P.R2) {
+            const Real rinv = Math<Real>::rsqrt(r2);
+            const Real phi = Math<Real>::ex(-(Real)P.kappa * (r2 * rinv)) * rinv;
+            aq += (double)((Real)code_q(code) * phi);
         }
     }
 }
@@ -1087,7 +1105,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         // member j's own list (changing: read from the pool), its staged
         // neighbour slots, and any neighbours left in memory
         double aqA = 0.0, aqB = 0.0, aw = 0.0;
-        int ov = 0;
+        int ov = 0, band = 0;
 #pragma unroll 1
         for (int j = 0; j < ncell; ++j) {
             const bool inA = A.member == j, inB = B.member == j;
@@ -1099,8 +1117,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const bool v = g < nn && g != skA && g != skB;
                 const uint4 rc = pool[bs + min(g, nn - 1)];
                 const uint32_t code = charge_code(rc.w);
-                if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov);
-                if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov);
+                if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, band);
+                if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, band);
             }
             const int lo = j ? nbc0 : 0, hi = j ? nb_total : nbc0;
             const int s1 = min(hi, st_end);
@@ -1109,8 +1127,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const int g = g0 + tid;
                 const bool v = g < s1;
                 const uint4 rc = pool[pl.st_off + min(g, s1 - 1)];
-                if (inA) pair_acc<Real>(rc, rc.w, v, A, P, aqA, aw, ov);
-                if (inB) pair_acc<Real>(rc, rc.w, v, B, P, aqB, aw, ov);
+                if (inA) pair_acc<Real>(rc, rc.w, v, A, P, aqA, aw, ov, band);
+                if (inB) pair_acc<Real>(rc, rc.w, v, B, P, aqB, aw, ov, band);
             }
             if (hi > st_end) {
                 int q = 0;
@@ -1122,8 +1140,49 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                     const bool v = g0 + lane < hi;
                     const uint4 rc = v ? recb[(size_t)c * cap + off] : make_uint4(0u, 0u, 0u, 0u);
                     const uint32_t code = charge_code(rc.w);
-                    if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov);
-                    if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov);
+                    if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, band);
+                    if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, band);
+                }
+            }
+        }
+        if (__ballot(band)) {
+            // records within 1e-5 of the cutoff (rare): the exact integer test
+#pragma unroll 1
+            for (int j = 0; j < ncell; ++j) {
+                const bool inA = A.member == j, inB = B.member == j;
+                if (!inA && !inB) continue;
+                const int bs = pl.base(j), nn = j ? n1 : n0;
+                const int skA = inA ? A.own : -1, skB = inB ? B.own : -1;
+                for (int g0 = 0; g0 < nn; g0 += nt) {
+                    const int g = g0 + tid;
+                    const bool v = g < nn && g != skA && g != skB;
+                    const uint4 rc = pool[bs + min(g, nn - 1)];
+                    const uint32_t code = charge_code(rc.w);
+                    if (inA) pair_band<Real>(rc, code, v, A, P, aqA);
+                    if (inB) pair_band<Real>(rc, code, v, B, P, aqB);
+                }
+                const int lo = j ? nbc0 : 0, hi = j ? nb_total : nbc0;
+                const int s1 = min(hi, st_end);
+                for (int g0 = lo; g0 < s1; g0 += nt) {
+                    const int g = g0 + tid;
+                    const bool v = g < s1;
+                    const uint4 rc = pool[pl.st_off + min(g, s1 - 1)];
+                    if (inA) pair_band<Real>(rc, rc.w, v, A, P, aqA);
+                    if (inB) pair_band<Real>(rc, rc.w, v, B, P, aqB);
+                }
+                if (hi > st_end) {
+                    int q = 0;
+                    const int m0 = max(lo, st_end);
+                    for (int g0 = m0 + 64 * wid; g0 < hi; g0 += nt) {
+                        uint32_t c;
+                        int off;
+                        chunk_src(g0, lane, q, pre_v, seg_cell, c, off);
+                        const bool v = g0 + lane < hi;
+                        const uint4 rc = v ? recb[(size_t)c * cap + off] : make_uint4(0u, 0u, 0u, 0u);
+                        const uint32_t code = charge_code(rc.w);
+                        if (inA) pair_band<Real>(rc, code, v, A, P, aqA);
+                        if (inB) pair_band<Real>(rc, code, v, B, P, aqB);
+                    }
                 }
             }
         }
