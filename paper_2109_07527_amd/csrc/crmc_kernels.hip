@@ -204,12 +204,14 @@ template <> struct Math<float> {
     // the hardware approximations (about 1 ulp; r^2 >= 1/4 wherever they matter)
     __device__ static __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
     __device__ static __forceinline__ float ex(float x) { return __expf(x); }
+    __device__ static __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
     __device__ static __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     __device__ static __forceinline__ float sqrt_(float x) { return sqrtf(x); }
 };
 template <> struct Math<double> {
     __device__ static __forceinline__ double rsqrt(double x) { return 1.0 / sqrt(x); }
     __device__ static __forceinline__ double ex(double x) { return exp(x); }
+    __device__ static __forceinline__ double ex2(double x) { return exp2(x); }
     __device__ static __forceinline__ double rcp(double x) { return 1.0 / x; }
     __device__ static __forceinline__ double sqrt_(double x) { return sqrt(x); }
 };
@@ -373,8 +375,8 @@ struct Chg {
 };
 
 struct PairParams {
-    float scale_f;
-    double scale_d;
+    float scale_f, sc2_f, kl_f; // lattice unit, its square, -kappa log2(e)
+    double scale_d, sc2_d, kl_d;
     uint64_t R2;
     double rc2_lo, rc2_hi; // rc^2 (1 -+ 1e-5): outside this band the float distance decides
     double lB, kappa, eps;
@@ -385,6 +387,31 @@ template <typename Real>
 __device__ __forceinline__ Real scale_of(const PairParams& P)
 {
     return sizeof(Real) == 4 ? (Real)P.scale_f : (Real)P.scale_d;
+}
+template <typename Real>
+__device__ __forceinline__ Real sc2_of(const PairParams& P)
+{
+    return sizeof(Real) == 4 ? (Real)P.sc2_f : (Real)P.sc2_d;
+}
+template <typename Real>
+__device__ __forceinline__ Real kl_of(const PairParams& P)
+{
+    return sizeof(Real) == 4 ? (Real)P.kl_f : (Real)P.kl_d;
+}
+
+// squared distance (sigma^2) of a lattice offset, and the screened Coulomb
+// kernel exp(-kappa r) / r from it
+template <typename Real>
+__device__ __forceinline__ Real r2_of(int32_t dx, int32_t dy, int32_t dz, const PairParams& P)
+{
+    const Real fx = (Real)dx, fy = (Real)dy, fz = (Real)dz;
+    return (fx * fx + fy * fy + fz * fz) * sc2_of<Real>(P);
+}
+template <typename Real>
+__device__ __forceinline__ Real yukawa(Real r2, const PairParams& P)
+{
+    const Real rinv = Math<Real>::rsqrt(r2);
+    return Math<Real>::ex2(kl_of<Real>(P) * (r2 * rinv)) * rinv;
 }
 
 // Charge code of a staged neighbour record (replaces its meta word in the
@@ -408,16 +435,12 @@ __device__ __forceinline__ void pair_acc(const uint4& rec, uint32_t code, bool v
                                          const PairParams& P, double& aq, double& aw, int& ov, int& band)
 {
     const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
-    const Real sc = scale_of<Real>(P);
-    const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
-    const Real r2 = fx * fx + fy * fy + fz * fz;
+    const Real r2 = r2_of<Real>(dx, dy, dz, P);
     const bool coupled = valid && (P.ion_coupling || !code_ion(code));
     if (c.dq != 0) {
         const bool in = r2 < (Real)P.rc2_lo;
         band |= (coupled && !in && r2 <= (Real)P.rc2_hi) ? 1 : 0;
-        const Real rinv = Math<Real>::rsqrt(r2);
-        const Real phi = Math<Real>::ex(-(Real)P.kappa * (r2 * rinv)) * rinv;
-        const Real qphi = (Real)code_q(code) * phi;
+        const Real qphi = (Real)code_q(code) * yukawa<Real>(r2, P);
         aq += (double)((in && coupled) ? qphi : (Real)0);
     }
     if (c.dw != 0) {
@@ -441,17 +464,12 @@ __device__ __forceinline__ void pair_band(const uint4& rec, uint32_t code, bool 
 {
     if (c.dq == 0) return;
     const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
-    const Real sc = scale_of<Real>(P);
-    const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
-    const Real r2 = fx * fx + fy * fy + fz * fz;
+    const Real r2 = r2_of<Real>(dx, dy, dz, P);
     const bool coupled = valid && (P.ion_coupling || !code_ion(code));
     if (coupled && !(r2 < (Real)P.rc2_lo) && r2 <= (Real)P.rc2_hi) {
         const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
-        if ((uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az < P.R2) {
-            const Real rinv = Math<Real>::rsqrt(r2);
-            const Real phi = Math<Real>::ex(-(Real)P.kappa * (r2 * rinv)) * rinv;
-            aq += (double)((Real)code_q(code) * phi);
-        }
+        if ((uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az < P.R2)
+            aq += (double)((Real)code_q(code) * yukawa<Real>(r2, P));
     }
 }
 
@@ -872,6 +890,10 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     PairParams P;
     P.scale_f = (float)R.scale;
     P.scale_d = R.scale;
+    P.sc2_d = R.scale * R.scale;
+    P.sc2_f = (float)P.sc2_d;
+    P.kl_d = -R.kappa * 1.4426950408889634074; // log2(e)
+    P.kl_f = (float)P.kl_d;
     P.R2 = R.R2;
     P.rc2_lo = (double)R.R2 * R.scale * R.scale * (1.0 - 1e-5);
     P.rc2_hi = (double)R.R2 * R.scale * R.scale * (1.0 + 1e-5);
