@@ -414,19 +414,20 @@ __device__ __forceinline__ Real yukawa(Real r2, const PairParams& P)
     return Math<Real>::ex2(kl_of<Real>(P) * (r2 * rinv)) * rinv;
 }
 
-// Charge code of a staged neighbour record (replaces its meta word in the
-// on-chip copy): bits 0-1 the charge (two's complement), bit 2 free ion.
-__device__ __forceinline__ uint32_t charge_code(uint32_t meta)
+// The charge a record shows the Coulomb sum, as FP32 bits (it replaces the
+// meta word in the on-chip copy of a neighbour record): zero for a free ion
+// when ions do not couple.  Without coupling no excluded-volume term is
+// evaluated either, so nothing else of the meta word is needed.
+__device__ __forceinline__ uint32_t charge_bits(uint32_t meta, int ion_coupling)
 {
-    return ((uint32_t)rec_q(meta) & 3u) | ((uint32_t)rec_is_ion(meta) << 2);
+    const int q = (ion_coupling || !rec_is_ion(meta)) ? rec_q(meta) : 0;
+    return __float_as_uint((float)q);
 }
-__device__ __forceinline__ int code_q(uint32_t code) { return ((int)(code << 30)) >> 30; }
-__device__ __forceinline__ int code_ion(uint32_t code) { return (int)((code >> 2) & 1u); }
 
 // Per-lane sums for one changed particle c: aq = sum of q_j phi(r) over the
 // records inside the Coulomb cutoff (times lB dq at the end), aw = excluded
-// volume change; ov set on an overlap created by an insertion.  valid = 0
-// masks the lane out.  Branch-free on the common path (the 64 lanes diverge
+// volume change; ov set on an overlap created by an insertion.  code is the
+// record's charge_bits; valid = 0 masks the lane out.  Branch-free on the common path (the 64 lanes diverge
 // anyway).  A record within 1e-5 of rc (rare) is left out and flagged in
 // `band`; pair_band adds it afterwards if its exact integer distance is inside
 // the cutoff.  The excluded-volume term sits behind a wavefront-uniform test.
@@ -436,11 +437,11 @@ __device__ __forceinline__ void pair_acc(const uint4& rec, uint32_t code, bool v
 {
     const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
     const Real r2 = r2_of<Real>(dx, dy, dz, P);
-    const bool coupled = valid && (P.ion_coupling || !code_ion(code));
+    const bool coupled = valid;
     if (c.dq != 0) {
         const bool in = r2 < (Real)P.rc2_lo;
         band |= (coupled && !in && r2 <= (Real)P.rc2_hi) ? 1 : 0;
-        const Real qphi = (Real)code_q(code) * yukawa<Real>(r2, P);
+        const Real qphi = (Real)__uint_as_float(code) * yukawa<Real>(r2, P);
         aq += (double)((in && coupled) ? qphi : (Real)0);
     }
     if (c.dw != 0) {
@@ -465,11 +466,10 @@ __device__ __forceinline__ void pair_band(const uint4& rec, uint32_t code, bool 
     if (c.dq == 0) return;
     const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
     const Real r2 = r2_of<Real>(dx, dy, dz, P);
-    const bool coupled = valid && (P.ion_coupling || !code_ion(code));
-    if (coupled && !(r2 < (Real)P.rc2_lo) && r2 <= (Real)P.rc2_hi) {
+    if (valid && !(r2 < (Real)P.rc2_lo) && r2 <= (Real)P.rc2_hi) {
         const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
         if ((uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az < P.R2)
-            aq += (double)((Real)code_q(code) * yukawa<Real>(r2, P));
+            aq += (double)((Real)__uint_as_float(code) * yukawa<Real>(r2, P));
     }
 }
 
@@ -810,7 +810,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const int gl = g0 + u * nt + lane;
                 if (gl < st_end) {
                     uint4 w = v[u];
-                    w.w = charge_code(w.w);
+                    w.w = charge_bits(w.w, a.ion_coupling);
                     pool[pl.st_off + gl] = w;
                 }
             }
@@ -1138,7 +1138,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const int g = g0 + tid;
                 const bool v = g < nn && g != skA && g != skB;
                 const uint4 rc = pool[bs + min(g, nn - 1)];
-                const uint32_t code = charge_code(rc.w);
+                const uint32_t code = charge_bits(rc.w, P.ion_coupling);
                 if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, band);
                 if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, band);
             }
@@ -1161,7 +1161,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                     chunk_src(g0, lane, q, pre_v, seg_cell, c, off);
                     const bool v = g0 + lane < hi;
                     const uint4 rc = v ? recb[(size_t)c * cap + off] : make_uint4(0u, 0u, 0u, 0u);
-                    const uint32_t code = charge_code(rc.w);
+                    const uint32_t code = charge_bits(rc.w, P.ion_coupling);
                     if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, band);
                     if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, band);
                 }
@@ -1179,7 +1179,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                     const int g = g0 + tid;
                     const bool v = g < nn && g != skA && g != skB;
                     const uint4 rc = pool[bs + min(g, nn - 1)];
-                    const uint32_t code = charge_code(rc.w);
+                    const uint32_t code = charge_bits(rc.w, P.ion_coupling);
                     if (inA) pair_band<Real>(rc, code, v, A, P, aqA);
                     if (inB) pair_band<Real>(rc, code, v, B, P, aqB);
                 }
@@ -1201,7 +1201,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                         chunk_src(g0, lane, q, pre_v, seg_cell, c, off);
                         const bool v = g0 + lane < hi;
                         const uint4 rc = v ? recb[(size_t)c * cap + off] : make_uint4(0u, 0u, 0u, 0u);
-                        const uint32_t code = charge_code(rc.w);
+                        const uint32_t code = charge_bits(rc.w, P.ion_coupling);
                         if (inA) pair_band<Real>(rc, code, v, A, P, aqA);
                         if (inB) pair_band<Real>(rc, code, v, B, P, aqB);
                     }
