@@ -376,6 +376,7 @@ struct Chg {
 
 struct PairParams {
     float scale_f, sc2_f, kl_f; // lattice unit, its square, -kappa log2(e)
+    float rc2_f, band_f;        // rc^2; half-width of the exact-test band (with room for rounding)
     double scale_d, sc2_d, kl_d;
     uint64_t R2;
     double rc2_lo, rc2_hi; // rc^2 (1 -+ 1e-5): outside this band the float distance decides
@@ -427,20 +428,22 @@ __device__ __forceinline__ uint32_t charge_bits(uint32_t meta, int ion_coupling)
 // Per-lane sums for one changed particle c: aq = sum of q_j phi(r) over the
 // records inside the Coulomb cutoff (times lB dq at the end), aw = excluded
 // volume change; ov set on an overlap created by an insertion.  code is the
-// record's charge_bits; valid = 0 masks the lane out.  Branch-free on the common path (the 64 lanes diverge
-// anyway).  A record within 1e-5 of rc (rare) is left out and flagged in
-// `band`; pair_band adds it afterwards if its exact integer distance is inside
-// the cutoff.  The excluded-volume term sits behind a wavefront-uniform test.
+// record's charge_bits; valid = 0 masks the lane out.  Branch-free on the
+// common path (the 64 lanes diverge anyway).  A record within 1e-5 of rc
+// (rare) is left out; gap keeps the least |r^2 - rc^2| seen, and when that is
+// inside the band pair_band adds such records afterwards if their exact
+// integer distance is inside the cutoff.  The excluded-volume term sits
+// behind a wavefront-uniform test.
 template <typename Real>
 __device__ __forceinline__ void pair_acc(const uint4& rec, uint32_t code, bool valid, const Chg& c,
-                                         const PairParams& P, double& aq, double& aw, int& ov, int& band)
+                                         const PairParams& P, double& aq, double& aw, int& ov, float& gap)
 {
     const int32_t dx = (int32_t)(rec.x - c.x), dy = (int32_t)(rec.y - c.y), dz = (int32_t)(rec.z - c.z);
     const Real r2 = r2_of<Real>(dx, dy, dz, P);
     const bool coupled = valid;
     if (c.dq != 0) {
         const bool in = r2 < (Real)P.rc2_lo;
-        band |= (coupled && !in && r2 <= (Real)P.rc2_hi) ? 1 : 0;
+        gap = fminf(gap, coupled ? fabsf((float)r2 - P.rc2_f) : 3.0e38f);
         const Real qphi = (Real)__uint_as_float(code) * yukawa<Real>(r2, P);
         aq += (double)((in && coupled) ? qphi : (Real)0);
     }
@@ -895,6 +898,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     P.kl_d = -R.kappa * 1.4426950408889634074; // log2(e)
     P.kl_f = (float)P.kl_d;
     P.R2 = R.R2;
+    P.rc2_f = (float)((double)R.R2 * R.scale * R.scale);
+    P.band_f = P.rc2_f * 1.2e-5f;
     P.rc2_lo = (double)R.R2 * R.scale * R.scale * (1.0 - 1e-5);
     P.rc2_hi = (double)R.R2 * R.scale * R.scale * (1.0 + 1e-5);
     P.lB = a.lB;
@@ -1127,7 +1132,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         // member j's own list (changing: read from the pool), its staged
         // neighbour slots, and any neighbours left in memory
         double aqA = 0.0, aqB = 0.0, aw = 0.0;
-        int ov = 0, band = 0;
+        int ov = 0;
+        float gap = 3.0e38f;
 #pragma unroll 1
         for (int j = 0; j < ncell; ++j) {
             const bool inA = A.member == j, inB = B.member == j;
@@ -1139,8 +1145,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const bool v = g < nn && g != skA && g != skB;
                 const uint4 rc = pool[bs + min(g, nn - 1)];
                 const uint32_t code = charge_bits(rc.w, P.ion_coupling);
-                if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, band);
-                if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, band);
+                if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, gap);
+                if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, gap);
             }
             const int lo = j ? nbc0 : 0, hi = j ? nb_total : nbc0;
             const int s1 = min(hi, st_end);
@@ -1149,8 +1155,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const int g = g0 + tid;
                 const bool v = g < s1;
                 const uint4 rc = pool[pl.st_off + min(g, s1 - 1)];
-                if (inA) pair_acc<Real>(rc, rc.w, v, A, P, aqA, aw, ov, band);
-                if (inB) pair_acc<Real>(rc, rc.w, v, B, P, aqB, aw, ov, band);
+                if (inA) pair_acc<Real>(rc, rc.w, v, A, P, aqA, aw, ov, gap);
+                if (inB) pair_acc<Real>(rc, rc.w, v, B, P, aqB, aw, ov, gap);
             }
             if (hi > st_end) {
                 int q = 0;
@@ -1162,12 +1168,12 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                     const bool v = g0 + lane < hi;
                     const uint4 rc = v ? recb[(size_t)c * cap + off] : make_uint4(0u, 0u, 0u, 0u);
                     const uint32_t code = charge_bits(rc.w, P.ion_coupling);
-                    if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, band);
-                    if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, band);
+                    if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, gap);
+                    if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, gap);
                 }
             }
         }
-        if (__ballot(band)) {
+        if (__ballot(gap <= P.band_f)) {
             // records within 1e-5 of the cutoff (rare): the exact integer test
 #pragma unroll 1
             for (int j = 0; j < ncell; ++j) {
