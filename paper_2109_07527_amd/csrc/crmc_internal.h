@@ -43,6 +43,10 @@ __host__ __device__ inline uint32_t make_meta(uint32_t kind, uint32_t charged, u
 struct SweepTab {
     uint32_t o[4];     // grid shift of the current sweep
     uint32_t pairc[8]; // reflection centre of the active-cell pairing, per colour
+    // written at the end of a sweep for the next one: its shift and the one
+    // it follows, valid for sweep number valid - 1 (0: none)
+    uint32_t next[4], prev[4];
+    uint64_t valid;
 };
 
 // One replica as the kernels see it.

@@ -115,9 +115,14 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     const uint32_t hw = *R.hiwater;
 
     uint32_t on[3], oo[3];
-    grid_shift(R.key0, R.key1, s, a.fixed_grid, on);
-    if (s == 0) { oo[0] = oo[1] = oo[2] = 0u; }
-    else grid_shift(R.key0, R.key1, s - 1, a.fixed_grid, oo);
+    if (R.tab->valid == s + 1u) {
+        // left by the end of the previous sweep
+        for (int d = 0; d < 3; ++d) { on[d] = R.tab->next[d]; oo[d] = R.tab->prev[d]; }
+    } else {
+        grid_shift(R.key0, R.key1, s, a.fixed_grid, on);
+        if (s == 0) { oo[0] = oo[1] = oo[2] = 0u; }
+        else grid_shift(R.key0, R.key1, s - 1, a.fixed_grid, oo);
+    }
 
     if (gcell == 0 && lane < PLAN_N) a.plan_n[lane] = 0u; // plan and learned-proposal counters of the sweep
     if (k == 0 && lane < 12) {
@@ -1405,6 +1410,15 @@ __global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a)
             R.group_hist[R.group_hist_off[g] + gc[g]] += 1;
             gc[g] = 0;
         }
+    }
+    // the next sweep's shift and this one's, so that its re-binning need not
+    // draw them in every wavefront
+    for (uint32_t r = threadIdx.x; r < a.nrep; r += blockDim.x) {
+        SweepTab* T = a.reps[r].tab;
+        uint32_t nx[3];
+        grid_shift(a.reps[r].key0, a.reps[r].key1, s + 1u, a.fixed_grid, nx);
+        for (int d = 0; d < 3; ++d) { T->prev[d] = T->o[d]; T->next[d] = nx[d]; }
+        T->valid = s + 2u;
     }
     __syncthreads();
     if (threadIdx.x == 0) *a.sweep = s + 1u;
