@@ -1397,16 +1397,18 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
 __global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a)
 {
     const uint64_t s = *a.sweep;
-    for (uint32_t r = 0; r < a.nrep; ++r) {
+    // one wavefront per replica, the four wavefronts taking turns
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    for (uint32_t r = wave; r < a.nrep; r += blockDim.x / 64u) {
         const Replica& R = a.reps[r];
-        if (threadIdx.x < 4 && R.series_cap > 0) {
+        if (lane < 4 && R.series_cap > 0) {
             const int64_t row = (int64_t)(s % (uint64_t)R.series_cap);
-            R.series[row * 4 + threadIdx.x] = (int32_t)R.totals[threadIdx.x];
+            R.series[row * 4 + lane] = (int32_t)R.totals[lane];
         }
         // ionized sites per group at the start of this sweep (counted by the
         // re-binning); the slot is cleared for the sweep after next
         int32_t* gc = R.group_count + (s & 1u) * R.ngroups;
-        for (uint32_t g = threadIdx.x; g < R.ngroups; g += blockDim.x) {
+        for (uint32_t g = lane; g < R.ngroups; g += 64u) {
             R.group_hist[R.group_hist_off[g] + gc[g]] += 1;
             gc[g] = 0;
         }
