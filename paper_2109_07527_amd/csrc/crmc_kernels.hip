@@ -936,15 +936,21 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                           key0, key1, w);
             ph0 = w[0]; ph1 = w[1]; ph2 = w[2]; ph3 = w[3];
         }
+        // words 0-3 and 16-19 serve every trial; the insertion coordinates
+        // (words 4-15) are read where an insertion needs them
         uint32_t W[20];
 #pragma unroll
-        for (int b = 0; b < 5; ++b) {
+        for (int b = 0; b < 5; b += 4) {
             const int src = 6 * tl + b;
             W[4 * b + 0] = rdl(ph0, src);
             W[4 * b + 1] = rdl(ph1, src);
             W[4 * b + 2] = rdl(ph2, src);
             W[4 * b + 3] = rdl(ph3, src);
         }
+        const auto word = [&](int w) -> uint32_t {
+            const int c = w & 3;
+            return rdl(c == 0 ? ph0 : (c == 1 ? ph1 : (c == 2 ? ph2 : ph3)), 6 * tl + (w >> 2));
+        };
 
         const uint32_t kk = pick32(W[0], (uint32_t)(2 * nreact));
         const int rsel = (int)(kk >> 1);
@@ -1089,9 +1095,9 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const int j = ncell == 1 ? 0 : (int)pick32(wc, (uint32_t)ncell);
                 B.member = j;
                 B.own = -1;
-                B.x = (j ? ib1[0] : ib0[0]) + pick64(W[wo + 0], W[wo + 1], j ? iw1[0] : iw0[0]);
-                B.y = (j ? ib1[1] : ib0[1]) + pick64(W[wo + 2], W[wo + 3], j ? iw1[1] : iw0[1]);
-                B.z = (j ? ib1[2] : ib0[2]) + pick64(W[wo + 4], W[wo + 5], j ? iw1[2] : iw0[2]);
+                B.x = (j ? ib1[0] : ib0[0]) + pick64(word(wo + 0), word(wo + 1), j ? iw1[0] : iw0[0]);
+                B.y = (j ? ib1[1] : ib0[1]) + pick64(word(wo + 2), word(wo + 3), j ? iw1[1] : iw0[1]);
+                B.z = (j ? ib1[2] : ib0[2]) + pick64(word(wo + 4), word(wo + 5), j ? iw1[2] : iw0[2]);
                 lnvol += j ? lnZm1 : lnZm0;
             } else {
                 const uint4 rc = pool[pl.base(b_mem) + b_own];
@@ -1112,9 +1118,9 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const int j = ncell == 1 ? 0 : (int)pick32(W[18], (uint32_t)ncell);
                 A.member = j;
                 A.own = -1;
-                A.x = (j ? ib1[0] : ib0[0]) + pick64(W[4], W[5], j ? iw1[0] : iw0[0]);
-                A.y = (j ? ib1[1] : ib0[1]) + pick64(W[6], W[7], j ? iw1[1] : iw0[1]);
-                A.z = (j ? ib1[2] : ib0[2]) + pick64(W[8], W[9], j ? iw1[2] : iw0[2]);
+                A.x = (j ? ib1[0] : ib0[0]) + pick64(word(4), word(5), j ? iw1[0] : iw0[0]);
+                A.y = (j ? ib1[1] : ib0[1]) + pick64(word(6), word(7), j ? iw1[1] : iw0[1]);
+                A.z = (j ? ib1[2] : ib0[2]) + pick64(word(8), word(9), j ? iw1[2] : iw0[2]);
                 lnvol += j ? lnZm1 : lnZm0;
             } else {
                 const uint4 rc = pool[pl.base(a_mem) + a_own];
