@@ -41,8 +41,27 @@ def _mixed(seed=3, L=24.0, with_core=True, charged=False):
     return s
 
 
+def _cutoff_line(L=80.0, rc=6.0, n=12):
+    """Acid sites on a line whose neighbours sit at lattice distances just
+    inside and just outside the cutoff (alternately floor and ceil of rc in
+    lattice units, both within 1e-5 of rc): every flip sums pairs that only the
+    exact integer test separates."""
+    t = rc / L * 2.0 ** 32
+    d_in, d_out = math.floor(t), math.ceil(t)
+    assert d_in * d_in < math.ceil(t * t) <= d_out * d_out
+    xs = [2 ** 28]
+    for k in range(1, n):
+        xs.append(xs[-1] + (d_in if k % 2 else d_out))
+    pts = np.array([[x, 2 ** 31, 2 ** 31 + 12345] for x in xs], dtype=np.float64)
+    xyz = pts * (L / 2.0 ** 32)  # exact: the library maps them back to these lattice points
+    return dict(L=L, xyz=xyz, kind=np.ones(n, np.int32), group=np.zeros(n, np.int32),
+                core_xyz=np.zeros((0, 3)), core_R=np.zeros(0))
+
+
 CASES = {
     # name: (system factory, model, condition)
+    "cutoff_band": (lambda: _cutoff_line(), dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=0),
+                    _cond(4.5, 4.5, 5.0, 1.0, 1.0, 0.5)),
     "mixed": (lambda: _mixed(), dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=1),
               _cond(6.0, 5.0, 5.0, 0.5, 0.7, 0.5)),
     "mixed_charged_start": (lambda: _mixed(charged=True), dict(lB=2.0, rc=6.0, eps=1.0, ion_coupling=1),
@@ -139,7 +158,7 @@ def _compare_logs(glog, olog, ftol=1e-5):
     return n_checked, False
 
 
-@pytest.mark.parametrize("case", ["mixed", "chain40", "np_pair_small"])
+@pytest.mark.parametrize("case", ["mixed", "chain40", "np_pair_small", "cutoff_band"])
 def test_fp32_decisions_and_dU(case):
     crmc = _gpu()
     make, model, cond = CASES[case]
