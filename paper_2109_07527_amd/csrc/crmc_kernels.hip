@@ -775,6 +775,16 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         return;
     }
 
+    // ---- the first round of the own lists and tables: in flight while the
+    //      neighbour counts and records are gathered
+    const int tab_len = max(max(n0, n1), max(pl.nln, pl.ncl));
+    uint4 f0 = make_uint4(0u, 0u, 0u, 0u), f1 = f0, fc = f0;
+    double fl = 0.0, fd = 0.0;
+    if (tid < n0) f0 = recb[(size_t)G.cell0 * cap + tid];
+    if (tid < n1) f1 = recb[(size_t)G.cell1 * cap + tid];
+    if (tid < pl.nln) fl = a.lntab[tid];
+    if (tid < pl.ncl) { fc = core_g[tid]; fd = cdel_g[tid]; }
+
     // ---- neighbour segments: counts, then a wavefront prefix scan -----------
     int cnt = 0;
     uint32_t seg_cell = 0;
@@ -832,9 +842,12 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     uint4* lcore = pool + pl.core_off;
     double* lcdel = reinterpret_cast<double*>(pool + pl.cdel_off);
     {
-        // one round loads a share of every table, all in flight together
-        const int len = max(max(n0, n1), max(pl.nln, pl.ncl));
-        for (int i = tid; i < len; i += nt) {
+        if (tid < n0) pool[tid] = f0;
+        if (tid < n1) pool[pl.room0 + tid] = f1;
+        if (tid < pl.nln) lnt[tid] = fl;
+        if (tid < pl.ncl) { lcore[tid] = fc; lcdel[tid] = fd; }
+        // further rounds (long lists): a share of every table, all in flight together
+        for (int i = tid + nt; i < tab_len; i += nt) {
             uint4 r0 = make_uint4(0u, 0u, 0u, 0u), r1 = r0, cx = r0;
             double l = 0.0, dl = 0.0;
             if (i < n0) r0 = recb[(size_t)G.cell0 * cap + i];
