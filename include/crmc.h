@@ -310,7 +310,7 @@ int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_can
  * enqueues is bracketed by HIP events on the library's stream.
  * crmc_get_timing (synchronizes) returns the accumulated device milliseconds
  * and launch counts per kernel kind: [0] re-binning, planning and the learned
- * proposal's feature and network kernels, [1] trial phases,
+ * proposal's feature-and-network kernel, [1] trial phases,
  * [2] end-of-sweep bookkeeping; crmc_set_timing(h, 1) also resets them.
  */
 int crmc_set_timing(crmc_t h, int32_t on);
