@@ -63,6 +63,7 @@ def lib():
         L.orc_log_count.restype = i64
         L.orc_log_count.argtypes = [vp]
         L.orc_set_check.argtypes = [vp, C.c_int]
+        L.orc_set_trial_limit.argtypes = [vp, i64]
         L.orc_max_dU_err.restype = d
         L.orc_max_dU_err.argtypes = [vp]
         L.orc_set_particles.argtypes = [vp, C.c_int, P(u32), P(i32), P(i32), P(i32)]
@@ -256,6 +257,12 @@ class Oracle:
 
     def set_check(self, on=True):
         self._L.orc_set_check(self.h, int(on))
+
+    def set_trial_limit(self, n):
+        """Run only the next n trials in processing order (n < 0: no limit);
+        later trials of the sweeps are skipped, so the state is the one after
+        those n trials.  For comparing a prefix of a long run."""
+        self._L.orc_set_trial_limit(self.h, int(n))
 
     def max_dU_err(self):
         return self._L.orc_max_dU_err(self.h)

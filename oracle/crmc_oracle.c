@@ -157,6 +157,10 @@ typedef struct {
        energy difference and the largest deviation is kept */
     int check_dU;
     double max_dU_err;
+    /* test aid: when trial_limit >= 0, trials beyond the first trial_limit
+       (counted from the last orc_set_trial_limit, in processing order) are
+       skipped; they are not logged and change nothing */
+    int64_t trial_limit, trials_run;
     /* learned proposal */
     int learned;
     double lp_eps;
@@ -342,6 +346,7 @@ orc_sys* orc_create(double L, int n_cells, double lB, double kappa, double rc, d
     S->key[0] = (uint32_t)seed;
     S->key[1] = (uint32_t)(seed >> 32) ^ replica;
     S->trials = 1;
+    S->trial_limit = -1;
     S->ncells = n_cells * n_cells * n_cells;
     S->cells = (orc_list*)calloc((size_t)S->ncells, sizeof(orc_list));
     return S;
@@ -560,6 +565,7 @@ void orc_set_log(orc_sys* S, orc_trial* log, int64_t cap)
 int64_t orc_log_count(const orc_sys* S) { return S->log_n; }
 
 void orc_set_check(orc_sys* S, int on) { S->check_dU = on; S->max_dU_err = 0.0; }
+void orc_set_trial_limit(orc_sys* S, int64_t n) { S->trial_limit = n; S->trials_run = 0; }
 double orc_max_dU_err(const orc_sys* S) { return S->max_dU_err; }
 
 static void ensure_cap(orc_sys* S, int need)
@@ -1158,6 +1164,8 @@ static void one_sweep(orc_sys* S, int32_t* series)
             }
             int ntr = S->trials * D.ncell + (nsites * S->site_trials + 15) / 16;
             for (int t = 0; t < ntr; ++t) {
+                if (S->trial_limit >= 0 && S->trials_run >= S->trial_limit) break;
+                S->trials_run++;
                 uint32_t w[24];
                 trial_words(S, TAG_TRIAL, (uint32_t)S->sweep, (uint32_t)D.cell[0], (uint32_t)t * 8u, w);
                 do_trial(S, &D, w, D.cell[0], t);

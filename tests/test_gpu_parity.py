@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 from oracle import closed_forms as cf
-from workloads import config1, config2, nanoparticle_pair, random_sites, ring
+from workloads import config1, config2, config3, config5, nanoparticle_pair, random_sites, ring
 
 pytestmark = pytest.mark.gpu
 
@@ -285,6 +285,66 @@ def test_config2_full_size_sampled_replicas():
         o.sweeps(nsw)
         n, _ = _compare_logs(glog[glog["replica"] == r], o.log())
         assert n > 1000
+
+
+def test_config3_full_size_sampled_replicas():
+    """The 256 uneven chains (50..2000 sites, L up to 156) in one batch, FP32,
+    for two sweeps; the shortest, a median and the longest chain against the
+    oracle trial by trial."""
+    crmc = _gpu()
+    reps = config3()
+    model = dict(lB=reps[0]["lB"], rc=reps[0]["rc"], eps=1.0, ion_coupling=1)
+    conds = [_cond(r["pH"], r["pKa"], r["pKb"], r["pIX"], r["pIX"], r["kappa"]) for r in reps]
+    S = crmc.System(n_replicas=len(reps), lB=model["lB"], rc=model["rc"], eps=1.0, precision=32,
+                    trials_per_cell=1, seed=2024)
+    for i, r in enumerate(reps):
+        S.build_cells(i, r)
+    cap = 6_000_000
+    S.enable_log(cap)
+    nsw = 2
+    S.sweep_ex(conds, nsw)
+    glog = S.read_log()
+    assert len(glog) < cap
+    sizes = np.array([len(r["kind"]) for r in reps])
+    order = np.argsort(sizes)
+    for i in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        obs = S.observe(i)
+        assert obs["status"] == 0
+        o = _oracle_for(reps[i], model, conds[i], obs["n_cells"], 1, True, seed=2024, replica=i)
+        o.enable_log(2_000_000)
+        o.sweeps(nsw)
+        n, _ = _compare_logs(glog[glog["replica"] == i], o.log())
+        assert n > 100
+
+
+@pytest.mark.timeout(400)
+def test_config5_full_size_sampled_replica():
+    """The 64-nanoparticle suspension (51 200 sites, L = 300, eight pH replicas,
+    FP32) for one sweep; the first trials of one replica in the oracle's
+    processing order against the oracle trial by trial.  The oracle's initial
+    energy is a brute-force sum over all pairs (about a minute here) and its dU
+    runs over the whole system, so a full sweep would take minutes."""
+    crmc = _gpu()
+    c = config5()
+    model = dict(lB=c["lB"], rc=c["rc"], eps=1.0, ion_coupling=1)
+    conds = [_cond(pH, c["pKa"], c["pKb"], c["pIX"], c["pIX"], c["kappa"]) for pH in c["pH_list"]]
+    S = crmc.System(n_replicas=len(conds), lB=c["lB"], rc=c["rc"], eps=1.0, precision=32, trials_per_cell=1,
+                    seed=2024)
+    for r in range(len(conds)):
+        S.build_cells(r, c)
+    S.enable_log(4_000_000)
+    S.sweep_ex(conds, 1)
+    glog = S.read_log()
+    r = 4
+    obs = S.observe(r)
+    assert obs["status"] == 0
+    o = _oracle_for(c, model, conds[r], obs["n_cells"], 1, True, seed=2024, replica=r)
+    o.enable_log(20_000)
+    o.set_trial_limit(3000)
+    o.sweeps(1)
+    assert len(o.log()) == 3000
+    n, _ = _compare_logs(glog[glog["replica"] == r], o.log())
+    assert n > 1000
 
 
 @pytest.mark.parametrize("case", ["mixed", "np_pair_small", "chain40"])

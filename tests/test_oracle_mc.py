@@ -134,6 +134,25 @@ def test_deterministic_and_seed_dependent():
     assert not all(np.array_equal(u, v) for u, v in zip(pa, c2.particles()))
 
 
+def test_trial_limit_runs_a_prefix():
+    """A trial limit of k gives exactly the first k trials of the unlimited
+    run, in the same order, and the limit 0 runs none."""
+    full, part, none = _mixed_system(seed=3), _mixed_system(seed=3), _mixed_system(seed=3)
+    for o in (full, part, none):
+        o.set_schedule(2)
+        o.enable_log(100_000)
+    full.sweeps(3)
+    ref = full.log()
+    k = len(ref) // 2 + 7
+    part.set_trial_limit(k)
+    part.sweeps(3)
+    assert part.log().tobytes() == ref[:k].tobytes()
+    none.set_trial_limit(0)
+    none.sweeps(2)
+    assert len(none.log()) == 0
+    assert none.energy() == pytest.approx(_mixed_system(seed=3).energy(), abs=1e-12)
+
+
 # ------------------------------------------------ statistical pins -----
 def _ideal_40(seed=7, n_cells=6):
     rng = np.random.default_rng(1)
