@@ -212,6 +212,33 @@ int crmc_get_occupancy(crmc_t h, int32_t replica, int64_t cap, uint64_t* out, in
 int crmc_get_group_hist(crmc_t h, int32_t replica, int64_t cap, int64_t* out, int32_t off_cap,
                         int32_t* off, int32_t* n_groups);
 
+/*
+ * Checkpoint and resume.  The state of a Markov chain is its particle
+ * configuration (Sec. II: site charges, free-ion positions) plus what this
+ * library accumulates along the chain; the random numbers are counter based,
+ * so the sweep counter is all that is needed to continue the same chain.
+ *
+ * crmc_export_state writes, for every replica: the records of every cell in
+ * their list order (ion picks depend on it), the running-energy terms, the
+ * move counters, the per-site occupancy sums, the group histograms and the
+ * retained series window; and the sweep counter, the proposal switch and, if
+ * the network was ever used, its FP32 parameters with the Adam moments.  The
+ * format is a versioned little-endian byte string of this library.  With
+ * buf = NULL only *bytes = the size is written; a buffer smaller than *bytes
+ * gives CRMC_E_ARG with *bytes set to the size needed.  Synchronizes.
+ *
+ * crmc_import_state restores such a state into a handle created with the same
+ * n_replicas, precision and seed whose replicas were built from the same
+ * inputs (same box, cell grid, capacity, sites, groups and cores; before its
+ * first sweep or later).  A state that does not match, or is truncated or
+ * malformed, gives CRMC_E_ARG and leaves the handle unchanged.  Sweeping on
+ * from the imported state with the same conditions continues the exported
+ * chain bit for bit.  Conditions, logs, traces, timing and collected training
+ * rows are not part of the state.  Synchronizes.
+ */
+int crmc_export_state(crmc_t h, void* buf, int64_t* bytes);
+int crmc_import_state(crmc_t h, const void* buf, int64_t bytes);
+
 /* Trial logging (testing): keep up to `capacity` records on the device. */
 int crmc_enable_log(crmc_t h, int64_t capacity);
 int crmc_read_log(crmc_t h, int64_t cap, crmc_trial_rec* out, int64_t* n_out);

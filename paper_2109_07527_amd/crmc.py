@@ -106,6 +106,8 @@ def load():
         "crmc_get_series": (C.c_int, [vp, i32, i64, i64, P(i32)]),
         "crmc_get_particles": (C.c_int, [vp, i32, i32, P(u32), P(i32), P(i32), P(i32), P(i32)]),
         "crmc_energy": (C.c_int, [vp, i32, P(d)]),
+        "crmc_export_state": (C.c_int, [vp, vp, P(i64)]),
+        "crmc_import_state": (C.c_int, [vp, vp, i64]),
         "crmc_get_occupancy": (C.c_int, [vp, i32, i64, P(u64), P(i64)]),
         "crmc_get_group_hist": (C.c_int, [vp, i32, i64, P(i64), i32, P(i32), P(i32)]),
         "crmc_enable_log": (C.c_int, [vp, i64]),
@@ -215,6 +217,20 @@ def crmc_get_particles(h, replica, cap=None):
                                         _p(c, C.c_int32), _p(s, C.c_int32), C.byref(n)))
     m = min(n.value, cap)
     return X[:m], k[:m], c[:m], s[:m]
+
+
+def crmc_export_state(h):
+    """The chain's state as bytes (see crmc_import_state)."""
+    n = C.c_int64(0)
+    _check(h, load().crmc_export_state(h, None, C.byref(n)))
+    buf = C.create_string_buffer(max(n.value, 1))
+    _check(h, load().crmc_export_state(h, buf, C.byref(n)))
+    return buf.raw[:n.value]
+
+
+def crmc_import_state(h, state):
+    buf = C.create_string_buffer(bytes(state), len(state))
+    _check(h, load().crmc_import_state(h, buf, len(state)))
 
 
 def crmc_energy(h, replica):
@@ -503,6 +519,12 @@ class System:
 
     def energy(self, replica=0):
         return crmc_energy(self.h, replica)
+
+    def export_state(self):
+        return crmc_export_state(self.h)
+
+    def import_state(self, state):
+        return crmc_import_state(self.h, state)
 
     def occupancy(self, replica=0):
         return crmc_get_occupancy(self.h, replica)

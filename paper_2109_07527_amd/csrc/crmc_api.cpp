@@ -513,6 +513,126 @@ int check_device_errors(crmc_t h)
 
 } // namespace
 
+// ------------------------------------------------------------------------
+// checkpoint and resume
+// ------------------------------------------------------------------------
+namespace {
+
+constexpr char STATE_MAGIC[8] = {'C', 'R', 'M', 'C', 'S', 'T', 'A', 'T'};
+constexpr uint32_t STATE_VERSION = 1;
+
+struct Blob {
+    std::vector<uint8_t> b;
+    template <class T> void put(const T& v) { put_n(&v, 1); }
+    template <class T> void put_n(const T* v, size_t n)
+    {
+        const uint8_t* p = reinterpret_cast<const uint8_t*>(v);
+        b.insert(b.end(), p, p + n * sizeof(T));
+    }
+};
+
+struct Cursor {
+    const uint8_t* p;
+    size_t n, at = 0;
+    template <class T> bool get(T& v) { return get_n(&v, 1); }
+    template <class T> bool get_n(T* v, size_t k)
+    {
+        const size_t bytes = k * sizeof(T);
+        if (bytes > n - at) return false;
+        std::memcpy(v, p + at, bytes);
+        at += bytes;
+        return true;
+    }
+};
+
+// shape of a built replica that a state must match
+struct RepShape {
+    uint32_t n, cap, ncells, nsites, ngroups, ncores;
+    double L;
+};
+
+RepShape shape_of(const HostReplica& r) { return RepShape{r.n, r.cap, r.ncells, r.nsites, r.ngroups, r.ncores, r.L}; }
+
+bool same_shape(const RepShape& a, const RepShape& b)
+{
+    return a.n == b.n && a.cap == b.cap && a.ncells == b.ncells && a.nsites == b.nsites && a.ngroups == b.ngroups &&
+           a.ncores == b.ncores && a.L == b.L;
+}
+
+int serialize_state(crmc_t h, Blob& out)
+{
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    int rc = check_device_errors(h);
+    if (rc) return rc;
+    out.put_n(STATE_MAGIC, 8);
+    out.put(STATE_VERSION);
+    out.put((uint32_t)h->reps.size());
+    out.put((int32_t)h->p.precision);
+    out.put((uint32_t)0);
+    out.put(h->p.seed);
+    out.put((int64_t)h->sweeps);
+    const int buf = (int)(h->sweeps & 1);
+    for (const HostReplica& r : h->reps) {
+        out.put(shape_of(r));
+        out.put(r.E0);
+        out.put(r.e0_kappa);
+        uint32_t hiw = 0;
+        HIP_TRY(h, hipMemcpy(&hiw, r.d.hiwater, sizeof hiw, hipMemcpyDeviceToHost));
+        out.put(hiw);
+        out.put((uint32_t)0);
+        // records of every cell in list order (the order later picks depend on)
+        std::vector<uint32_t> cnt(r.ncells);
+        std::vector<uint4> rec((size_t)r.ncells * r.cap);
+        HIP_TRY(h, hipMemcpy(cnt.data(), r.d.cnt[buf], r.ncells * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HIP_TRY(h, hipMemcpy(rec.data(), r.d.rec[buf], rec.size() * sizeof(uint4), hipMemcpyDeviceToHost));
+        out.put_n(cnt.data(), cnt.size());
+        for (uint32_t c = 0; c < r.ncells; ++c) out.put_n(&rec[(size_t)c * r.cap], cnt[c]);
+        std::vector<double> e(r.ncells);
+        HIP_TRY(h, hipMemcpy(e.data(), r.d.e_acc, e.size() * sizeof(double), hipMemcpyDeviceToHost));
+        out.put_n(e.data(), e.size());
+        std::vector<uint64_t> occ(r.nsites);
+        if (r.nsites) HIP_TRY(h, hipMemcpy(occ.data(), r.d.occupancy, occ.size() * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        out.put_n(occ.data(), occ.size());
+        std::vector<int32_t> gc(2 * std::max<uint32_t>(r.ngroups, 1));
+        HIP_TRY(h, hipMemcpy(gc.data(), r.d.group_count, gc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        out.put_n(gc.data(), gc.size());
+        std::vector<int64_t> gh((size_t)r.hist_off[r.ngroups]);
+        if (!gh.empty()) HIP_TRY(h, hipMemcpy(gh.data(), r.d.group_hist, gh.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+        out.put_n(gh.data(), gh.size());
+        int64_t tot[4];
+        uint64_t mv[12];
+        HIP_TRY(h, hipMemcpy(tot, r.d.totals, sizeof tot, hipMemcpyDeviceToHost));
+        HIP_TRY(h, hipMemcpy(mv, r.d.moves, sizeof mv, hipMemcpyDeviceToHost));
+        out.put_n(tot, 4);
+        out.put_n(mv, 12);
+        // the retained window of the series, oldest first
+        const int64_t capn = r.d.series_cap;
+        const int64_t first = std::max<int64_t>(0, h->sweeps - capn);
+        std::vector<int32_t> all((size_t)capn * 4);
+        HIP_TRY(h, hipMemcpy(all.data(), r.d.series, all.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        out.put(capn);
+        for (int64_t s = first; s < h->sweeps; ++s) out.put_n(&all[(size_t)(s % capn) * 4], 4);
+        out.put_n(r.d.lp_off, 2);
+    }
+    // proposal: switch, eps, and the network with its optimizer state when present
+    out.put((uint32_t)h->learned);
+    out.put(h->learn_eps);
+    out.put((uint32_t)(h->d_p32 != nullptr));
+    if (h->d_p32) {
+        std::vector<float> w(MLP_PARAMS), m(MLP_PARAMS), v(MLP_PARAMS);
+        HIP_TRY(h, hipMemcpy(w.data(), h->d_p32, MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(h, hipMemcpy(m.data(), h->d_adam_m, MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
+        HIP_TRY(h, hipMemcpy(v.data(), h->d_adam_v, MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost));
+        out.put_n(w.data(), w.size());
+        out.put_n(m.data(), m.size());
+        out.put_n(v.data(), v.size());
+        out.put(h->adam_t);
+    }
+    return CRMC_OK;
+}
+
+} // namespace
+
 extern "C" {
 
 double crmc_pIX_from_salt(double pIS, double pH, double pKw)
@@ -1250,6 +1370,156 @@ int crmc_get_particles(crmc_t h, int32_t replica, int32_t cap, uint32_t* xyz, in
         }
     *n_out = k;
     return check_device_errors(h);
+}
+
+int crmc_export_state(crmc_t h, void* buf, int64_t* bytes)
+{
+    if (!h || !bytes || (buf && *bytes < 0)) return fail(h, CRMC_E_ARG, "bad arguments");
+    for (const HostReplica& r : h->reps)
+        if (!r.built) return fail(h, CRMC_E_STATE, "every replica must be built before exporting the state");
+    Blob b;
+    int rc = serialize_state(h, b);
+    if (rc) return rc;
+    const int64_t need = (int64_t)b.b.size();
+    if (!buf) {
+        *bytes = need;
+        return CRMC_OK;
+    }
+    if (*bytes < need) {
+        *bytes = need;
+        return fail(h, CRMC_E_ARG, "state buffer too small (" + std::to_string(need) + " bytes needed)");
+    }
+    std::memcpy(buf, b.b.data(), (size_t)need);
+    *bytes = need;
+    return CRMC_OK;
+}
+
+int crmc_import_state(crmc_t h, const void* buf, int64_t bytes)
+{
+    if (!h || !buf || bytes <= 0) return fail(h, CRMC_E_ARG, "bad arguments");
+    for (const HostReplica& r : h->reps)
+        if (!r.built) return fail(h, CRMC_E_STATE, "build every replica from the same inputs before importing");
+    Cursor in{(const uint8_t*)buf, (size_t)bytes};
+    const auto bad = [&](const char* what) { return fail(h, CRMC_E_ARG, std::string("state does not fit: ") + what); };
+    char magic[8];
+    uint32_t version = 0, nrep = 0, pad = 0;
+    int32_t precision = 0;
+    uint64_t seed = 0;
+    int64_t sweeps = 0;
+    if (!in.get_n(magic, 8) || std::memcmp(magic, STATE_MAGIC, 8) != 0) return bad("not a state");
+    if (!in.get(version) || version != STATE_VERSION) return bad("unknown version");
+    if (!in.get(nrep) || nrep != h->reps.size()) return bad("replica count");
+    if (!in.get(precision) || precision != h->p.precision) return bad("precision");
+    if (!in.get(pad) || !in.get(seed) || seed != h->p.seed) return bad("seed");
+    if (!in.get(sweeps) || sweeps < 0 || (uint64_t)sweeps >= (1ull << 32)) return bad("sweep counter");
+
+    // parse everything on the host first; the handle changes only if all of it fits
+    struct RepState {
+        double E0, e0_kappa;
+        uint32_t hiw;
+        std::vector<uint32_t> cnt;
+        std::vector<uint4> rec;
+        std::vector<double> e;
+        std::vector<uint64_t> occ;
+        std::vector<int32_t> gc, series;
+        std::vector<int64_t> gh;
+        int64_t tot[4];
+        uint64_t mv[12];
+        double lp_off[2];
+    };
+    std::vector<RepState> st(nrep);
+    for (uint32_t i = 0; i < nrep; ++i) {
+        const HostReplica& r = h->reps[i];
+        RepState& q = st[i];
+        RepShape sh{};
+        uint32_t pad2 = 0;
+        if (!in.get(sh) || !same_shape(sh, shape_of(r))) return bad("replica geometry");
+        if (!in.get(q.E0) || !in.get(q.e0_kappa) || !in.get(q.hiw) || !in.get(pad2)) return bad("truncated");
+        q.cnt.resize(r.ncells);
+        if (!in.get_n(q.cnt.data(), q.cnt.size())) return bad("truncated");
+        q.rec.assign((size_t)r.ncells * r.cap, make_uint4(0, 0, 0, 0));
+        for (uint32_t c = 0; c < r.ncells; ++c) {
+            if (q.cnt[c] > r.cap) return bad("cell count above capacity");
+            if (!in.get_n(&q.rec[(size_t)c * r.cap], q.cnt[c])) return bad("truncated");
+        }
+        q.e.resize(r.ncells);
+        q.occ.resize(r.nsites);
+        q.gc.resize(2 * std::max<uint32_t>(r.ngroups, 1));
+        q.gh.resize((size_t)r.hist_off[r.ngroups]);
+        if (!in.get_n(q.e.data(), q.e.size()) || !in.get_n(q.occ.data(), q.occ.size()) ||
+            !in.get_n(q.gc.data(), q.gc.size()) || !in.get_n(q.gh.data(), q.gh.size()) || !in.get_n(q.tot, 4) ||
+            !in.get_n(q.mv, 12))
+            return bad("truncated");
+        int64_t capn = 0;
+        if (!in.get(capn) || capn != r.d.series_cap) return bad("series window");
+        const int64_t rows = std::min<int64_t>(sweeps, capn);
+        q.series.resize((size_t)rows * 4);
+        if (!in.get_n(q.series.data(), q.series.size()) || !in.get_n(q.lp_off, 2)) return bad("truncated");
+    }
+    uint32_t learned = 0, has_par = 0;
+    double eps = 0.0;
+    std::vector<float> w, m, v;
+    int64_t adam_t = 0;
+    if (!in.get(learned) || !in.get(eps) || !in.get(has_par) || learned > 1 || has_par > 1) return bad("proposal");
+    if (learned && (!(eps > 0.0) || eps > 1.0)) return bad("proposal eps");
+    if (has_par) {
+        w.resize(MLP_PARAMS);
+        m.resize(MLP_PARAMS);
+        v.resize(MLP_PARAMS);
+        if (!in.get_n(w.data(), w.size()) || !in.get_n(m.data(), m.size()) || !in.get_n(v.data(), v.size()) ||
+            !in.get(adam_t))
+            return bad("truncated network");
+    }
+    if (in.at != in.n) return bad("trailing bytes");
+
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const int buf_now = (int)(sweeps & 1);
+    for (uint32_t i = 0; i < nrep; ++i) {
+        HostReplica& r = h->reps[i];
+        const RepState& q = st[i];
+        Replica& d = r.d;
+        HIP_TRY(h, hipMemcpy(d.rec[buf_now], q.rec.data(), q.rec.size() * sizeof(uint4), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.cnt[buf_now], q.cnt.data(), q.cnt.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemset(d.cnt[buf_now ^ 1], 0, r.ncells * sizeof(uint32_t)));
+        HIP_TRY(h, hipMemcpy(d.e_acc, q.e.data(), q.e.size() * sizeof(double), hipMemcpyHostToDevice));
+        if (r.nsites)
+            HIP_TRY(h, hipMemcpy(d.occupancy, q.occ.data(), q.occ.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.group_count, q.gc.data(), q.gc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        if (!q.gh.empty())
+            HIP_TRY(h, hipMemcpy(d.group_hist, q.gh.data(), q.gh.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.totals, q.tot, sizeof q.tot, hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.moves, q.mv, sizeof q.mv, hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.hiwater, &q.hiw, sizeof q.hiw, hipMemcpyHostToDevice));
+        std::vector<int32_t> all((size_t)d.series_cap * 4, 0);
+        const int64_t first = std::max<int64_t>(0, sweeps - d.series_cap);
+        for (int64_t s = first; s < sweeps; ++s)
+            std::memcpy(&all[(size_t)(s % d.series_cap) * 4], &q.series[(size_t)(s - first) * 4], 4 * sizeof(int32_t));
+        HIP_TRY(h, hipMemcpy(d.series, all.data(), all.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        // the cached grid shifts are recomputed from the sweep counter
+        HIP_TRY(h, hipMemset(d.tab, 0, sizeof(SweepTab)));
+        d.lp_off[0] = q.lp_off[0];
+        d.lp_off[1] = q.lp_off[1];
+        r.E0 = q.E0;
+        r.e0_kappa = q.e0_kappa;
+    }
+    const uint64_t s64 = (uint64_t)sweeps;
+    HIP_TRY(h, hipMemcpy(h->d_sweep, &s64, sizeof s64, hipMemcpyHostToDevice));
+    h->sweeps = sweeps;
+    h->learned = learned != 0;
+    h->learn_eps = eps;
+    if (has_par) {
+        int rc = ensure_params(h);
+        if (rc) return rc;
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        HIP_TRY(h, hipMemcpy(h->d_p32, w.data(), MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(h->d_adam_m, m.data(), MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(h->d_adam_v, v.data(), MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
+        h->adam_t = adam_t;
+        LearnArgs g = learn_args(h);
+        HIP_TRY(h, launch_params_convert(g, h->stream));
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    return CRMC_OK;
 }
 
 int crmc_energy(crmc_t h, int32_t replica, double* out)

@@ -1,0 +1,126 @@
+"""Checkpoint and resume through the C ABI (needs an MI355X).
+
+A chain exported after some sweeps and imported into a handle rebuilt from
+the same inputs must continue bit for bit: the state exported after the same
+further sweeps is byte-identical to that of the uninterrupted run, and so are
+the observables.  States that do not fit the handle are rejected and leave it
+unchanged.
+"""
+import numpy as np
+import pytest
+
+from workloads import nanoparticle_pair, random_sites
+
+pytestmark = pytest.mark.gpu
+CRMC_E_ARG = -1
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_07527_amd import crmc
+    return crmc
+
+
+def _mixed():
+    s = random_sites(12, 10, 24.0, 3, min_dist=1.0)
+    s.update(core_xyz=np.array([[12.0, 12.0, 12.0]]), core_R=np.array([3.0]))
+    return s
+
+
+def _pair():
+    return nanoparticle_pair(seed=2, L=48.0, R=6.0, sites=300, separation=16.0)
+
+
+def _cond(pH, kappa=0.5):
+    return dict(pH=pH, pKa=5.0, pKb=5.0, pIX_pos=0.7, pIX_neg=0.9, kappa=kappa)
+
+
+def _system(crmc, s, n_rep, precision, seed=11, learned=False):
+    S = crmc.System(n_replicas=n_rep, lB=2.0, rc=6.0, eps=1.0, ion_coupling=1, precision=precision,
+                    trials_per_cell=2, seed=seed)
+    for r in range(n_rep):
+        kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"], group=s.get("group"))
+        if len(s.get("core_R", [])):
+            kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
+        S.build_cells(r, **kw)
+    if learned:
+        S.init_proposal_weights(5)
+        S.set_proposal(1, 0.2)
+    return S
+
+
+def _observables(S, n_rep, sweeps):
+    out = []
+    for r in range(n_rep):
+        obs = S.observe(r)
+        X, k, c, sid = S.particles(r)
+        out.append((sorted(obs.items()), X.tobytes(), k.tobytes(), c.tobytes(), sid.tobytes(),
+                    S.series(r, 0, sweeps).tobytes(), S.occupancy(r).tobytes()))
+    return out
+
+
+@pytest.mark.parametrize("case", ["mixed_fp32", "mixed_fp64_learned", "pair_fp32", "pair_fp64_learned"])
+def test_resume_continues_the_chain_bit_for_bit(case):
+    crmc = _gpu()
+    make, precision, learned = {"mixed_fp32": (_mixed, 32, False), "mixed_fp64_learned": (_mixed, 64, True),
+                                "pair_fp32": (_pair, 32, False), "pair_fp64_learned": (_pair, 64, True)}[case]
+    s = make()
+    conds = [_cond(4.0), _cond(7.5, kappa=0.3)]
+    n1, n2 = 3, 7  # odd: the import lands on the second record buffer
+    A = _system(crmc, s, 2, precision, learned=learned)
+    A.sweep_ex(conds, n1)
+    state = A.export_state()
+    A.sweep_ex(conds, n2)
+    final = A.export_state()
+    ref = _observables(A, 2, n1 + n2)
+
+    # a fresh handle built from the same inputs, never swept
+    B = _system(crmc, s, 2, precision)
+    B.import_state(state)
+    assert B.export_state() == state
+    B.sweep_ex(conds, n2)
+    assert B.export_state() == final
+    assert _observables(B, 2, n1 + n2) == ref
+    for r in range(2):
+        assert B.energy(r) == A.energy(r)
+
+    # a handle that has already run its own sweeps, with the other proposal,
+    # is overwritten as well (a network it holds stays allocated, so only the
+    # observables are compared)
+    C = _system(crmc, s, 2, precision, learned=not learned)
+    C.sweep_ex([_cond(9.0), _cond(3.0)], 2)
+    C.import_state(state)
+    C.sweep_ex(conds, n2)
+    assert _observables(C, 2, n1 + n2) == ref
+
+
+def test_states_that_do_not_fit_are_rejected():
+    crmc = _gpu()
+    s = _mixed()
+    A = _system(crmc, s, 2, 32)
+    A.sweep_ex([_cond(4.0), _cond(6.0)], 2)
+    state = A.export_state()
+
+    B = _system(crmc, s, 2, 32)
+    B.sweep_ex([_cond(5.0), _cond(5.0)], 1)
+    before = B.export_state()
+    bad = [state[:len(state) // 2],                  # truncated
+           state + b"\0",                           # trailing bytes
+           b"X" + state[1:],                        # not a state
+           ]
+    for blob in bad:
+        with pytest.raises(crmc.CrmcError) as e:
+            B.import_state(blob)
+        assert e.value.code == CRMC_E_ARG
+        assert B.export_state() == before
+    for other in (_system(crmc, s, 2, 32, seed=12),   # another seed
+                  _system(crmc, s, 2, 64),            # another precision
+                  _system(crmc, s, 1, 32),            # another replica count
+                  _system(crmc, _pair(), 2, 32)):     # another geometry
+        snap = other.export_state()
+        with pytest.raises(crmc.CrmcError) as e:
+            other.import_state(state)
+        assert e.value.code == CRMC_E_ARG
+        assert other.export_state() == snap
