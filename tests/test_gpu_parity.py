@@ -198,6 +198,38 @@ def test_unstaged_neighbours_bit_exact(light):
     _same_state(S.particles(0), o.particles())
 
 
+@pytest.mark.parametrize("case", ["mixed", "np_pair_small"])
+def test_conditions_changing_between_calls_bit_exact(case):
+    """A titration-like protocol: pH, pI_X and kappa change between calls
+    (a time-dependent reservoir pH, App. B).  The FP64 chain follows the
+    oracle given the same changes, and after the kappa change the retained
+    energy restarts from the state's energy at the new screening length."""
+    crmc = _gpu()
+    make, model, c0 = CASES[case]
+    s = make()
+    steps = [(c0, 4),
+             (dict(c0, pH=c0["pH"] + 2.0, pIX_pos=c0["pIX_pos"] + 0.4, pIX_neg=c0["pIX_neg"] - 0.2), 3),
+             (dict(c0, pH=c0["pH"] - 1.5, kappa=c0["kappa"] * 0.6), 5),
+             (dict(c0, pKa=c0["pKa"] + 1.0, pKb=c0["pKb"] - 0.5), 2)]
+    S = _gpu_system(crmc, s, model, 1, 64, 2, True, seed=31)
+    for c, n in steps:
+        S.sweep_ex([c], n)
+    obs = S.observe(0)
+    assert obs["status"] == 0
+    o = _oracle_for(s, model, c0, obs["n_cells"], 2, True, seed=31)
+    ser = []
+    for c, n in steps:
+        o.set_conditions(c["pH"], c["pKa"], c["pKb"], c["pIX_pos"], c["pIX_neg"], kappa=c["kappa"])
+        ser.append(o.sweeps(n))
+    nsw = sum(n for _, n in steps)
+    _same_state(S.particles(0), o.particles())
+    assert np.array_equal(S.series(0, 0, nsw), np.concatenate(ser))
+    att, acc = o.move_stats()
+    assert list(att) == obs["attempts"] and list(acc) == obs["accepts"]
+    assert obs["energy"] == pytest.approx(o.energy(), rel=1e-9, abs=1e-9)
+    assert sum(obs["accepts"]) > 0
+
+
 def test_replica_batch_with_different_conditions():
     """Several replicas of different size and conditions in one launch; each
     matches its own oracle."""
