@@ -19,7 +19,8 @@ from workloads import random_sites, ring
 
 pytestmark = pytest.mark.gpu
 RHO = 0.0269424
-K = 4.5  # allowed deviation in standard errors
+K = 3.0       # allowed deviation of a mean in standard errors
+K_BIN = 4.0   # of one histogram bin (many bins are compared at once)
 
 
 def _gpu():
@@ -73,7 +74,7 @@ def test_ring_enumeration_fp32():
         f = (ser[:, :, 0] == v).astype(float)
         m = f.mean(axis=1)
         se = max(m.std(ddof=1) / np.sqrt(len(m)), 1e-4)
-        assert abs(m.mean() - P[v]) < K * se, (v, m.mean(), P[v], se)
+        assert abs(m.mean() - P[v]) < K_BIN * se, (v, m.mean(), P[v], se)
 
 
 def test_acids_and_bases_ideal_fp32():
@@ -104,9 +105,10 @@ def test_salt_only_box_fp32():
 
 def test_interacting_chain_matches_the_paper_mode_chain_fp32():
     """Interacting ions (Coulomb and excluded volume with every particle), no
-    closed form: the 40-site chain's <alpha> at three pH values against the
-    stored mean of the oracle's paper-mode chain (global moves, tests/golden/
-    chain40_alpha.json), within K combined standard errors."""
+    closed form: the 40-site chain's <alpha> and distribution of the number of
+    ionized sites at three pH values against the stored values of the oracle's
+    paper-mode chain (global moves, tests/golden/chain40_alpha.json), within K
+    (means) and K_BIN (bins holding at least 0.2 %) combined standard errors."""
     import json
     import os
     from workloads import config1
@@ -130,3 +132,11 @@ def test_interacting_chain_matches_the_paper_mode_chain_fp32():
         mean, se = m.mean(), m.std(ddof=1) / np.sqrt(per)
         tol = K * np.hypot(se, p["se"])
         assert abs(mean - p["alpha"]) < tol, (p["pH"], mean, p["alpha"], se, p["se"])
+        n = np.rint(x * 40.0).astype(np.int64)
+        h = np.stack([np.bincount(row, minlength=41) / len(row) for row in n])
+        hm, hse = h.mean(axis=0), h.std(axis=0, ddof=1) / np.sqrt(per)
+        for v in range(41):
+            if p["P_nA"][v] < 2e-3:
+                continue
+            tol = K_BIN * np.hypot(hse[v], p["P_nA_se"][v])
+            assert abs(hm[v] - p["P_nA"][v]) < tol, (p["pH"], v, hm[v], p["P_nA"][v], hse[v], p["P_nA_se"][v])
