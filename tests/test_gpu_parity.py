@@ -198,6 +198,50 @@ def test_unstaged_neighbours_bit_exact(light):
     _same_state(S.particles(0), o.particles())
 
 
+@pytest.mark.parametrize("case", ["np_pair_small", "mixed_groups"])
+def test_observables_equal_those_of_the_oracle_states(case):
+    """Per-site occupancy sums and per-group histograms of the number of
+    ionized sites (the paper's alpha and particle-charge distributions), both
+    sampled at the start of every sweep, equal what the test accumulates from
+    the oracle's state before each of its sweeps (FP64 chain).  Groups are the
+    caller's ids mapped to dense indices in ascending order."""
+    crmc = _gpu()
+    if case == "mixed_groups":
+        make, model, cond = CASES["mixed"]
+        s = make()
+        s = dict(s, group=np.array([(7, -2, 30)[i % 3] for i in range(len(s["kind"]))], dtype=np.int32))
+    else:
+        make, model, cond = CASES[case]
+        s = make()
+    nsw = 9
+    S = _gpu_system(crmc, s, model, 1, 64, 2, True, seed=41)
+    S.sweep_ex([cond], nsw)
+    obs = S.observe(0)
+    assert obs["status"] == 0
+    o = _oracle_for(s, model, cond, obs["n_cells"], 2, True, seed=41)
+    kind = np.asarray(s["kind"])
+    group = np.asarray(s["group"])
+    ids = sorted(set(group.tolist()))
+    dense = np.array([ids.index(g) for g in group.tolist()])
+    sizes = np.bincount(dense, minlength=len(ids))
+    occ = np.zeros(len(kind), dtype=np.uint64)
+    hist = [np.zeros(n + 1, dtype=np.int64) for n in sizes]
+    for _ in range(nsw):
+        _, k, c, sid = o.particles()
+        on = sid[(sid >= 0) & (c == 1) & ((k == 1) | (k == 2))]
+        occ[on] += 1
+        cnt = np.bincount(dense[on], minlength=len(ids))
+        for g in range(len(ids)):
+            hist[g][cnt[g]] += 1
+        o.sweeps(1)
+    assert occ.sum() > 0
+    assert np.array_equal(S.occupancy(0), occ)
+    gh = S.group_hist(0)
+    assert len(gh) == len(hist)
+    for a, b in zip(gh, hist):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("case", ["mixed", "np_pair_small"])
 def test_conditions_changing_between_calls_bit_exact(case):
     """A titration-like protocol: pH, pI_X and kappa change between calls
