@@ -58,7 +58,7 @@
 extern "C" {
 #endif
 
-#define CRMC_ABI_VERSION 1
+#define CRMC_ABI_VERSION 2
 
 typedef struct crmc_s* crmc_t;
 
@@ -83,7 +83,8 @@ enum crmc_kind {
 /* move ids used by statistics and trial logs */
 enum crmc_move {
     CRMC_ACID_FWD = 0, CRMC_ACID_BACK = 1, CRMC_BASE_FWD = 2,
-    CRMC_BASE_BACK = 3, CRMC_SALT_IN = 4, CRMC_SALT_OUT = 5
+    CRMC_BASE_BACK = 3, CRMC_SALT_IN = 4, CRMC_SALT_OUT = 5,
+    CRMC_ION_RELOCATE = 6 /* not one of the paper's moves: see crmc_params.ion_trials */
 };
 
 typedef struct {
@@ -105,7 +106,16 @@ typedef struct {
     int32_t use_graph;       /* 1: replay captured HIP graphs of whole sweeps; 0: launch each kernel */
     int32_t learned_proposal; /* 1: acid/base sites picked by the learned proposal (see
                                  crmc_set_proposal); 0: uniform picks */
-    int32_t reserved1;       /* must be 0 */
+    int32_t ion_trials;      /* ion relocation trials per cell of a domain per phase, after the
+                                reaction trials (0 = none, the paper's six moves only; <= 4096).
+                                A relocation (move id 6) removes a free ion of the domain picked
+                                uniformly (cations first in the ordering) and re-inserts it at a
+                                point drawn like an insertion of its sign, accepted with
+                                min(1, (V_new / V_old) exp(-dU)), V the insertion volume of the
+                                cell drawn.  It stands in for the ion motion the paper gets from
+                                molecular dynamics: the six moves alone move an ion only by
+                                deleting and re-inserting it with a reaction, which mixes ion
+                                positions very slowly when salt is dilute */
     double lB;               /* Bjerrum length (sigma) */
     double rc;               /* Coulomb cutoff (sigma) */
     double eps_wca;          /* excluded-volume strength (kT); 0 disables it */
@@ -140,6 +150,8 @@ typedef struct {
     int32_t n_cells;          /* cells per box edge */
     int32_t cell_capacity;
     int32_t max_cell_count;   /* most records any cell has held after re-binning */
+    int64_t relocation_attempts; /* ion relocation trials (auto-rejected ones included) */
+    int64_t relocation_accepts;
 } crmc_obs;
 
 /* Trial log record (56 bytes), written when logging is enabled. */

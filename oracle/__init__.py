@@ -64,6 +64,8 @@ def lib():
         L.orc_log_count.argtypes = [vp]
         L.orc_set_check.argtypes = [vp, C.c_int]
         L.orc_set_trial_limit.argtypes = [vp, i64]
+        L.orc_set_ion_trials.argtypes = [vp, C.c_int]
+        L.orc_relocation_stats.argtypes = [vp, P(i64)]
         L.orc_max_dU_err.restype = d
         L.orc_max_dU_err.argtypes = [vp]
         L.orc_set_particles.argtypes = [vp, C.c_int, P(u32), P(i32), P(i32), P(i32)]
@@ -191,13 +193,21 @@ class Oracle:
         if kappa is not None:
             self._L.orc_set_kappa(self.h, float(kappa))
 
-    def set_schedule(self, trials_per_cell=1, fixed_grid=False, pairing=True, site_trials=0):
+    def set_schedule(self, trials_per_cell=1, fixed_grid=False, pairing=True, site_trials=0, ion_trials=0):
         """Cell schedule: trials per active cell per phase, plus site_trials/16
-        extra trials per ionizable site of a domain (rounded up); fixed_grid
+        extra trials per ionizable site of a domain (rounded up), then
+        ion_trials ion relocation trials per cell of the domain; fixed_grid
         turns the per-sweep random shift off (a planted mistake for the negative
         control); pairing lets a trial act on two reflection-paired cells."""
         self._L.orc_set_schedule(self.h, int(trials_per_cell), int(bool(fixed_grid)), int(bool(pairing)),
                                  int(site_trials))
+        self._L.orc_set_ion_trials(self.h, int(ion_trials))
+
+    def relocation_stats(self):
+        """(attempts, accepts) of the ion relocation trials."""
+        out = np.zeros(2, dtype=np.int64)
+        self._L.orc_relocation_stats(self.h, _ptr(out, C.c_int64))
+        return int(out[0]), int(out[1])
 
     def partner(self, sweep, colour, a, M):
         return int(self._L.orc_partner(self.h, int(sweep), int(colour), int(a), int(M)))

@@ -135,6 +135,7 @@ typedef struct {
     int fixed_grid;  /* 1 = never shift the grid (test-only negative control) */
     int pairing;     /* 1 = trials act on reflection-paired cells, 0 = single cells */
     int site_trials; /* extra trials per 16 ionizable sites of a domain */
+    int ion_trials;  /* ion relocation trials per cell of a domain, after the reaction trials */
     /* state, in global order */
     int np, npcap;
     orc_particle* P;
@@ -145,6 +146,7 @@ typedef struct {
     int64_t paper_trial;
     double E; /* running energy: brute force at build, then += accepted dU */
     int64_t attempts[6], accepts[6];
+    int64_t reloc_att, reloc_acc; /* ion relocation trials */
     /* cell lists during a sweep */
     orc_list* cells;
     int ncells;
@@ -564,6 +566,8 @@ void orc_set_log(orc_sys* S, orc_trial* log, int64_t cap)
 }
 int64_t orc_log_count(const orc_sys* S) { return S->log_n; }
 
+void orc_set_ion_trials(orc_sys* S, int ion_trials) { S->ion_trials = ion_trials; }
+void orc_relocation_stats(const orc_sys* S, int64_t out[2]) { out[0] = S->reloc_att; out[1] = S->reloc_acc; }
 void orc_set_check(orc_sys* S, int on) { S->check_dU = on; S->max_dU_err = 0.0; }
 void orc_set_trial_limit(orc_sys* S, int64_t n) { S->trial_limit = n; S->trials_run = 0; }
 double orc_max_dU_err(const orc_sys* S) { return S->max_dU_err; }
@@ -879,12 +883,18 @@ static void swap_remove(orc_list* l, int i)
     l->n--;
 }
 
-static void do_trial(orc_sys* S, orc_dom* D, const uint32_t* w, int64_t cell, int64_t trial)
+/* One trial of a domain.  reloc = 0: one of the six moves of Sec. II C.
+   reloc = 1: an ion relocation (move id 6, not one of the paper's moves; it
+   stands in for the motion the paper's ions get from molecular dynamics): a
+   free ion of the domain picked uniformly is removed and re-inserted at a
+   point drawn like an insertion of its sign.  The proposal is symmetric up to
+   the insertion densities, so ln p = ln V_new - ln V_old - dU (eq. accrat). */
+static void do_trial(orc_sys* S, orc_dom* D, const uint32_t* w, int64_t cell, int64_t trial, int reloc)
 {
     uint32_t k = pick32(w[0], (uint32_t)(2 * D->nreact));
     int reaction = D->react[k >> 1];
     int dir = (int)(k & 1u);
-    int move = 2 * reaction + dir;
+    int move = reloc ? 6 : 2 * reaction + dir;
 
     int m0a = count_of(D, ORC_ACID, 0), mca = count_of(D, ORC_ACID, 1);
     int m0b = count_of(D, ORC_BASE, 0), mcb = count_of(D, ORC_BASE, 1);
@@ -928,6 +938,13 @@ static void do_trial(orc_sys* S, orc_dom* D, const uint32_t* w, int64_t cell, in
         del_neg = kth(D, ORC_XNEG, 1, (int)pick32(w[3], (uint32_t)nneg));
         lnp_counts = log((double)npos) + log((double)nneg) - S->lnKion;
         break;
+    case 6: { /* ion relocation: the k-th ion, cations first */
+        if (npos + nneg == 0) { auto_reject = 1; break; }
+        const int kk = (int)pick32(w[1], (uint32_t)(npos + nneg));
+        if (kk < npos) { del_pos = kth(D, ORC_XPOS, 1, kk); ins_pos = 1; }
+        else { del_neg = kth(D, ORC_XNEG, 1, kk - npos); ins_neg = 1; }
+        break;
+    }
     }
     if (D->sys && move <= 3 && !auto_reject) {
         /* learned site pick: the count ratio of the uniform picks becomes
@@ -947,7 +964,7 @@ static void do_trial(orc_sys* S, orc_dom* D, const uint32_t* w, int64_t cell, in
         default: lnp_counts = lnq + log((double)nneg) - S->lnKB; break;
         }
     }
-    S->attempts[move]++;
+    if (move == 6) S->reloc_att++; else S->attempts[move]++;
     double u = unit53(w[16], w[17]);
     if (auto_reject) {
         if (S->log && S->log_n < S->log_cap) {
@@ -1048,7 +1065,7 @@ static void do_trial(orc_sys* S, orc_dom* D, const uint32_t* w, int64_t cell, in
        cell into the hole (when both deleted ions sit in one cell, the one at
        the higher index goes first); insertions appended to their cells, X+
        before X- */
-    S->accepts[move]++;
+    if (move == 6) S->reloc_acc++; else S->accepts[move]++;
     S->E += dU;
     if (site >= 0) D->list[sj]->p[si].charged = !D->list[sj]->p[si].charged;
     if (del_pos >= 0 && del_neg >= 0 && pj == nj && ni > pi) {
@@ -1162,13 +1179,15 @@ static void one_sweep(orc_sys* S, int32_t* series)
                             site_prob(orc_mlp_logit(S->lp_par, x) + S->lp_off[sp->kind == ORC_ACID ? 0 : 1]);
                     }
             }
-            int ntr = S->trials * D.ncell + (nsites * S->site_trials + 15) / 16;
+            /* the reaction trials, then the ion relocation trials */
+            int ntr_react = S->trials * D.ncell + (nsites * S->site_trials + 15) / 16;
+            int ntr = ntr_react + S->ion_trials * D.ncell;
             for (int t = 0; t < ntr; ++t) {
                 if (S->trial_limit >= 0 && S->trials_run >= S->trial_limit) break;
                 S->trials_run++;
                 uint32_t w[24];
                 trial_words(S, TAG_TRIAL, (uint32_t)S->sweep, (uint32_t)D.cell[0], (uint32_t)t * 8u, w);
-                do_trial(S, &D, w, D.cell[0], t);
+                do_trial(S, &D, w, D.cell[0], t, t >= ntr_react);
             }
         }
     }
@@ -1211,7 +1230,7 @@ int orc_paper_trials(orc_sys* S, int64_t ntrials, int64_t sample_every, int32_t*
         trial_words(S, TAG_PAPER, (uint32_t)g, (uint32_t)(g >> 32), 0u, w);
         whole.n = S->np; whole.cap = S->npcap; whole.p = S->P;
         D.list[0] = &whole;
-        do_trial(S, &D, w, -1, g);
+        do_trial(S, &D, w, -1, g, 0);
         S->np = whole.n; S->npcap = whole.cap; S->P = whole.p;
         if (series && sample_every > 0 && (t + 1) % sample_every == 0) {
             orc_counts(S, cnt);

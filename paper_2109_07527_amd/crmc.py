@@ -33,7 +33,7 @@ class crmc_params(C.Structure):
                 ("pairing", C.c_int32), ("ion_coupling", C.c_int32), ("lds_records", C.c_int32),
                 ("fixed_grid", C.c_int32), ("site_trials", C.c_int32),
                 ("light_neighbours", C.c_int32), ("use_graph", C.c_int32),
-                ("learned_proposal", C.c_int32), ("reserved1", C.c_int32),
+                ("learned_proposal", C.c_int32), ("ion_trials", C.c_int32),
                 ("lB", C.c_double), ("rc", C.c_double), ("eps_wca", C.c_double), ("rho0NA", C.c_double),
                 ("pKw", C.c_double), ("kappa", C.c_double), ("pKb", C.c_double), ("learned_eps", C.c_double),
                 ("seed", C.c_uint64), ("stream", C.c_void_p)]
@@ -49,7 +49,8 @@ class crmc_obs(C.Structure):
                 ("n_base", C.c_int64), ("n_base_charged", C.c_int64), ("n_xpos", C.c_int64),
                 ("n_xneg", C.c_int64), ("energy", C.c_double), ("attempts", C.c_int64 * 6),
                 ("accepts", C.c_int64 * 6), ("error_flags", C.c_uint32), ("n_cells", C.c_int32),
-                ("cell_capacity", C.c_int32), ("max_cell_count", C.c_int32)]
+                ("cell_capacity", C.c_int32), ("max_cell_count", C.c_int32),
+                ("relocation_attempts", C.c_int64), ("relocation_accepts", C.c_int64)]
 
 
 class crmc_trial_rec(C.Structure):
@@ -417,7 +418,7 @@ class System:
 
     def __init__(self, n_replicas=1, lB=2.0, rc=6.0, eps=1.0, rho0NA=0.0269424, pKw=14.0, kappa=0.5,
                  pKb=5.0, seed=1234, precision=32, trials_per_cell=1, pairing=True, ion_coupling=True,
-                 lds_records=0, fixed_grid=False, site_trials=0, light_neighbours=0, use_graph=True,
+                 lds_records=0, fixed_grid=False, site_trials=0, ion_trials=0, light_neighbours=0, use_graph=True,
                  learned=False, learned_eps=0.1, stream="torch"):
         p = crmc_params()
         p.n_replicas = int(n_replicas)
@@ -428,6 +429,7 @@ class System:
         p.lds_records = int(lds_records)
         p.fixed_grid = int(bool(fixed_grid))
         p.site_trials = int(site_trials)
+        p.ion_trials = int(ion_trials)
         p.light_neighbours = int(light_neighbours)
         p.use_graph = int(bool(use_graph))
         p.learned_proposal = int(bool(learned))

@@ -195,6 +195,7 @@ SweepArgs base_args(crmc_t h)
     a.pairing = h->p.pairing;
     a.fixed_grid = h->p.fixed_grid;
     a.site_trials = h->p.site_trials;
+    a.ion_trials = h->p.ion_trials;
     a.pool = h->pool;
     a.precision = h->p.precision;
     a.light_nb = h->p.light_neighbours > 0 ? h->p.light_neighbours : DEFAULT_LIGHT_NB;
@@ -600,11 +601,11 @@ int serialize_state(crmc_t h, Blob& out)
         if (!gh.empty()) HIP_TRY(h, hipMemcpy(gh.data(), r.d.group_hist, gh.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
         out.put_n(gh.data(), gh.size());
         int64_t tot[4];
-        uint64_t mv[12];
+        uint64_t mv[14];
         HIP_TRY(h, hipMemcpy(tot, r.d.totals, sizeof tot, hipMemcpyDeviceToHost));
         HIP_TRY(h, hipMemcpy(mv, r.d.moves, sizeof mv, hipMemcpyDeviceToHost));
         out.put_n(tot, 4);
-        out.put_n(mv, 12);
+        out.put_n(mv, 14);
         // the retained window of the series, oldest first
         const int64_t capn = r.d.series_cap;
         const int64_t first = std::max<int64_t>(0, h->sweeps - capn);
@@ -654,7 +655,8 @@ int crmc_create(const crmc_params* p, crmc_t* out)
     if (!(p->rc > 1.2) || !(p->lB >= 0.0) || !(p->eps_wca >= 0.0) || !(p->rho0NA > 0.0)) return CRMC_E_ARG;
     if (p->lds_records < 0 || p->site_trials < 0 || p->site_trials > 4096) return CRMC_E_ARG;
     if (p->light_neighbours < 0 || p->light_neighbours > 65536) return CRMC_E_ARG;
-    if (p->reserved1 != 0 || (p->learned_proposal != 0 && p->learned_proposal != 1)) return CRMC_E_ARG;
+    if (p->ion_trials < 0 || p->ion_trials > 4096 || (p->learned_proposal != 0 && p->learned_proposal != 1))
+        return CRMC_E_ARG;
     if (p->learned_proposal && (!(p->learned_eps > 0.0) || p->learned_eps > 1.0)) return CRMC_E_ARG;
     crmc_t h = new (std::nothrow) crmc_s;
     if (!h) return CRMC_E_NOMEM;
@@ -832,7 +834,7 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     HIP_TRY(h, dalloc(&d.core_x, cores.size()));
     HIP_TRY(h, dalloc(&d.core_delta, deltas.size()));
     HIP_TRY(h, dalloc(&d.totals, 4));
-    HIP_TRY(h, dalloc(&d.moves, 12));
+    HIP_TRY(h, dalloc(&d.moves, 14));
     HIP_TRY(h, dalloc(&d.series, (size_t)series_cap * 4));
     HIP_TRY(h, dalloc(&d.phat, (size_t)std::max(n, 1)));
     HIP_TRY(h, hipMemset(d.phat, 0, (size_t)std::max(n, 1) * sizeof(double)));
@@ -850,7 +852,7 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     HIP_TRY(h, hipMemcpy(d.core_x, cores.data(), cores.size() * sizeof(uint4), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d.core_delta, deltas.data(), deltas.size() * sizeof(double), hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d.totals, tot, sizeof tot, hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemset(d.moves, 0, 12 * sizeof(uint64_t)));
+    HIP_TRY(h, hipMemset(d.moves, 0, 14 * sizeof(uint64_t)));
     HIP_TRY(h, hipMemset(d.series, 0, (size_t)series_cap * 4 * sizeof(int32_t)));
     {
         // cell boundaries b_k = ceil(k 2^32 / n) (b_n wraps to 0) and ln of the widths
@@ -1293,7 +1295,7 @@ int crmc_observe(crmc_t h, int32_t replica, crmc_obs* out)
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     std::memset(out, 0, sizeof *out);
     int64_t tot[4];
-    uint64_t mv[12];
+    uint64_t mv[14];
     std::vector<double> e(r.ncells);
     uint32_t err = 0;
     HIP_TRY(h, hipMemcpy(tot, r.d.totals, sizeof tot, hipMemcpyDeviceToHost));
@@ -1316,6 +1318,8 @@ int crmc_observe(crmc_t h, int32_t replica, crmc_obs* out)
         out->attempts[i] = (int64_t)mv[i];
         out->accepts[i] = (int64_t)mv[6 + i];
     }
+    out->relocation_attempts = (int64_t)mv[12];
+    out->relocation_accepts = (int64_t)mv[13];
     out->error_flags = err;
     out->n_cells = (int32_t)r.n;
     out->cell_capacity = (int32_t)r.cap;
@@ -1424,7 +1428,7 @@ int crmc_import_state(crmc_t h, const void* buf, int64_t bytes)
         std::vector<int32_t> gc, series;
         std::vector<int64_t> gh;
         int64_t tot[4];
-        uint64_t mv[12];
+        uint64_t mv[14];
         double lp_off[2];
     };
     std::vector<RepState> st(nrep);
@@ -1448,7 +1452,7 @@ int crmc_import_state(crmc_t h, const void* buf, int64_t bytes)
         q.gh.resize((size_t)r.hist_off[r.ngroups]);
         if (!in.get_n(q.e.data(), q.e.size()) || !in.get_n(q.occ.data(), q.occ.size()) ||
             !in.get_n(q.gc.data(), q.gc.size()) || !in.get_n(q.gh.data(), q.gh.size()) || !in.get_n(q.tot, 4) ||
-            !in.get_n(q.mv, 12))
+            !in.get_n(q.mv, 14))
             return bad("truncated");
         int64_t capn = 0;
         if (!in.get(capn) || capn != r.d.series_cap) return bad("series window");

@@ -116,6 +116,7 @@ struct SweepArgs {
     uint64_t log_cap;
     double lB, eps, ln2;
     int32_t ion_coupling, trials, pairing, fixed_grid, site_trials;
+    int32_t ion_trials; // ion relocation trials per cell of a domain, after the reaction trials
     int32_t pool;      // LDS pool of a phase workgroup, in records (a light domain gets a quarter)
     int32_t precision; // 32 or 64
     int32_t light_nb;  // neighbour records up to which a domain may run on one wavefront

@@ -8,7 +8,7 @@
 //   k_plan       per sweep: sorts the domains of every colour into light ones
 //                (one wavefront each) and heavy ones (a whole workgroup); with
 //                the learned proposal on, lists the feature kernel's work items.
-//   k_phase<R, L> per colour: every domain (one cell, or two reflection-paired
+//   k_phase<R, L, M> per colour: every domain (one cell, or two reflection-paired
 //                cells of the colour) runs its trials back to back: Philox
 //                words ten trials at a time, move and participants, pair
 //                sum of the energy change over the domain's own lists (LDS)
@@ -16,7 +16,8 @@
 //                read from memory), R = float or double terms with FP64
 //                accumulation,
 //                acceptance of Sec. II C, commit in LDS; writes the cells back
-//                at the end.  L: the learned site proposal compiled in.
+//                at the end.  L: the learned site proposal compiled in; M: the
+//                ion relocation trials compiled in.
 //   k_sweep_end  per sweep: series row, group histograms, sweep counter.
 //   k_energy     total energy of a replica from scratch (FP64), per cell.
 #include "crmc_internal.h"
@@ -350,7 +351,7 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
         }
         const int n0 = (int)R.cnt0[G.cell0];
         const int n1 = G.ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
-        const int ntr_max = a.trials * G.ncell + ((n0 + n1) * a.site_trials + 15) / 16;
+        const int ntr_max = (a.trials + a.ion_trials) * G.ncell + ((n0 + n1) * a.site_trials + 15) / 16;
         const Pool p = pool_layout(n0, n1, G.ncell, ntr_max, R.cap, R.ncores, a.learned);
         light = nb <= a.light_nb && p.st_off <= a.pool / 4;
     }
@@ -743,7 +744,7 @@ constexpr uint32_t CLS_MASK_SITE = 0xFu, CLS_MASK_ION = 0x7u;
 // The domain's trials.  wpd wavefronts share the pair sums (wpd = 1: light
 // domain, no workgroup barriers; wpd = 4: heavy domain, the whole workgroup;
 // uniform over the workgroup).
-template <typename Real, bool LEARNED>
+template <typename Real, bool LEARNED, bool RELOC>
 __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint4* __restrict__ pool,
                                            int pool_records, int wid, const int wpd, double (*red)[4], int (*ovf)[4])
 {
@@ -768,7 +769,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
 
     int n0 = (int)R.cnt0[G.cell0];
     int n1 = ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
-    const int ntr_max = a.trials * ncell + ((n0 + n1) * a.site_trials + 15) / 16;
+    const int ntr_max = (a.trials + a.ion_trials) * ncell + ((n0 + n1) * a.site_trials + 15) / 16;
     const Pool pl = pool_layout(n0, n1, ncell, ntr_max, cap, ncores, LEARNED ? 1 : 0);
     if (pl.st_off > pool_records) { // the plan and the host size pools so that this never happens
         if (tid == 0) atomicOr(a.err, ERR_POOL);
@@ -883,8 +884,10 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     MemberCounts c0 = count_member(pool, 0, n0, lane);
     MemberCounts c1 = count_member(pool, pl.room0, n1, lane);
     const int nsites = c0.a0 + c0.ac + c0.b0 + c0.bc + c1.a0 + c1.ac + c1.b0 + c1.bc;
-    // trials of this domain: the state-independent schedule
-    const int ntr = rfl(a.trials * ncell + (nsites * a.site_trials + 15) / 16);
+    // trials of this domain: the state-independent schedule, reaction trials
+    // first, then the ion relocation trials
+    const int ntr_react = rfl(a.trials * ncell + (nsites * a.site_trials + 15) / 16);
+    const int ntr = ntr_react + (RELOC ? a.ion_trials * ncell : 0);
     int react0 = 2, react1 = 2, nreact = 1;
     {
         const bool ha = c0.a0 + c0.ac + c1.a0 + c1.ac > 0, hb = c0.b0 + c0.bc + c1.b0 + c1.bc > 0;
@@ -929,6 +932,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
 
     // attempts and accepts per move, three 21-bit fields per word (moves 0-2, 3-5)
     uint64_t attL = 0, attH = 0, acpL = 0, acpH = 0;
+    int rel_att = 0, rel_acc = 0; // ion relocations
     int dA = 0, dB = 0, dXp = 0, dXm = 0; // changes of nA-, nB+, nX+, nX-
     double dE = 0.0;
     uint32_t ph0 = 0, ph1 = 0, ph2 = 0, ph3 = 0;
@@ -968,7 +972,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         const uint32_t kk = pick32(W[0], (uint32_t)(2 * nreact));
         const int rsel = (int)(kk >> 1);
         const int reaction = rsel == 0 ? react0 : (rsel == 1 ? react1 : 2);
-        const int move = rfl(2 * reaction + (int)(kk & 1u));
+        const int move = rfl(RELOC && t >= ntr_react ? 6 : 2 * reaction + (int)(kk & 1u));
         const double u = rfld(unit53(W[16], W[17]));
         const int m0a = c0.a0 + c1.a0, mca = c0.ac + c1.ac, m0b = c0.b0 + c1.b0, mcb = c0.bc + c1.bc;
         const int npos = c0.xp + c1.xp, nneg = c0.xn + c1.xn;
@@ -1006,11 +1010,21 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         case 4:
             lnp_counts = -lnt[npos + 1] - lnt[nneg + 1] + lnKion;
             break;
-        default:
+        case 5:
             auto_reject = npos == 0 || nneg == 0;
             am = CLS_MASK_ION; av = KIND_XPOS; ak = (int)pick32(W[2], (uint32_t)npos); ac0 = c0.xp;
             bm = CLS_MASK_ION; bv = KIND_XNEG; bk = (int)pick32(W[3], (uint32_t)nneg); bc0 = c0.xn;
             if (!auto_reject) lnp_counts = lnt[npos] + lnt[nneg] - lnKion;
+            break;
+        default:
+            if (RELOC) {
+                // ion relocation: the k-th free ion of the domain, cations first
+                auto_reject = npos + nneg == 0;
+                const int k = (int)pick32(W[1], (uint32_t)(npos + nneg));
+                am = CLS_MASK_ION;
+                if (k < npos) { av = KIND_XPOS; ak = k; ac0 = c0.xp; }
+                else { av = KIND_XNEG; ak = k - npos; ac0 = c0.xn; }
+            }
             break;
         }
         // learned site pick (moves 0-3): uniform with probability eps (word
@@ -1063,7 +1077,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
             }
         }
         const uint64_t mv_one = 1ull << (21 * (move % 3));
-        if (move < 3) attL += mv_one; else attH += mv_one;
+        if (move < 3) attL += mv_one; else if (!RELOC || move < 6) attH += mv_one; else ++rel_att;
         if (auto_reject) {
             if (tid == 0 && a.log) {
                 const unsigned long long li = atomicAdd(a.log_n, 1ull);
@@ -1081,6 +1095,29 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         Chg A, B;
         double lnvol = 0.0;
         const bool insertion = move == 0 || move == 2 || move == 4;
+        if (RELOC && move == 6) {
+            // ion relocation: A is the ion leaving its place, B the same ion at
+            // a point drawn like an insertion of its sign
+            const int q = av == KIND_XPOS ? 1 : -1;
+            const uint4 rc = pool[pl.base(a_mem) + a_own];
+            A.member = a_mem; A.own = a_own;
+            A.x = rflu(rc.x); A.y = rflu(rc.y); A.z = rflu(rc.z);
+            A.ion = 1; A.q_old = q; A.q_new = 0; A.pres_old = 1; A.pres_new = 0;
+            A.dq = a.ion_coupling ? -q : 0;
+            A.dw = ev_on ? -1 : 0;
+            lnvol -= a_mem ? lnZm1 : lnZm0;
+            const uint32_t wc = q > 0 ? W[18] : W[19];
+            const int wo = q > 0 ? 4 : 10;
+            const int j = ncell == 1 ? 0 : (int)pick32(wc, (uint32_t)ncell);
+            B.member = j; B.own = -1;
+            B.x = (j ? ib1[0] : ib0[0]) + pick64(word(wo + 0), word(wo + 1), j ? iw1[0] : iw0[0]);
+            B.y = (j ? ib1[1] : ib0[1]) + pick64(word(wo + 2), word(wo + 3), j ? iw1[1] : iw0[1]);
+            B.z = (j ? ib1[2] : ib0[2]) + pick64(word(wo + 4), word(wo + 5), j ? iw1[2] : iw0[2]);
+            B.ion = 1; B.q_old = 0; B.q_new = q; B.pres_old = 0; B.pres_new = 1;
+            B.dq = a.ion_coupling ? q : 0;
+            B.dw = ev_on ? 1 : 0;
+            lnvol += j ? lnZm1 : lnZm0;
+        }
         if (move <= 3) {
             // A: the site flips
             const uint4 rc = pool[pl.base(a_mem) + a_own];
@@ -1092,7 +1129,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
             A.q_old = sgn * chg; A.q_new = sgn * (1 - chg);
             A.dq = A.q_new - A.q_old; A.dw = 0; A.ion = 0; A.pres_old = 1; A.pres_new = 1;
         }
-        {
+        if (!RELOC || move < 6) {
             // B (and A for salt moves): ions in or out
             const int qB = (move <= 1) ? 1 : -1; // cation for acid moves, anion otherwise
             B.ion = 1;
@@ -1119,7 +1156,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 lnvol -= b_mem ? lnZm1 : lnZm0;
             }
         }
-        if (move >= 4) {
+        if (move == 4 || move == 5) {
             A.ion = 1;
             A.q_old = insertion ? 0 : 1;
             A.q_new = insertion ? 1 : 0;
@@ -1283,12 +1320,24 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
 
         // ---- commit: flip; deletions (higher index first within one cell);
         //      insertions appended, cation before anion -----------------------
-        if (move < 3) acpL += mv_one; else acpH += mv_one;
+        if (move < 3) acpL += mv_one; else if (!RELOC || move < 6) acpH += mv_one; else ++rel_acc;
         dE += dU;
         if (tid == 0) {
             if (move <= 3) pool[pl.base(A.member) + A.own].w ^= 8u;
             int l0 = n0, l1 = n1;
-            if (!insertion) {
+            if (RELOC && move == 6) {
+                // the ion leaves its slot like a deletion, then is appended
+                int& cn = A.member ? l1 : l0;
+                const int bs = pl.base(A.member);
+                pool[bs + A.own] = pool[bs + cn - 1];
+                if (learned) aux[bs + A.own] = aux[bs + cn - 1];
+                --cn;
+                int& cm = B.member ? l1 : l0;
+                pool[pl.base(B.member) + cm] =
+                    make_uint4(B.x, B.y, B.z, make_meta(B.q_new > 0 ? KIND_XPOS : KIND_XNEG, 1u, NO_SITE));
+                if (learned) aux[pl.base(B.member) + cm] = 0.0;
+                ++cm;
+            } else if (!insertion) {
                 // deleted: B always; A too for the salt move
                 int dm0 = B.member, di0 = B.own, dm1 = -1, di1 = -1;
                 if (move == 5) {
@@ -1338,9 +1387,14 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
             }
         }
         // counts
-        apply_counts(c0, move, A.member == 0, B.member == 0);
-        apply_counts(c1, move, A.member == 1, B.member == 1);
-        {
+        if (RELOC && move == 6) {
+            const int pos = B.q_new > 0;
+            MemberCounts& ca = A.member ? c1 : c0;
+            MemberCounts& cb = B.member ? c1 : c0;
+            if (pos) { --ca.xp; ++cb.xp; } else { --ca.xn; ++cb.xn; }
+        } else {
+            apply_counts(c0, move, A.member == 0, B.member == 0);
+            apply_counts(c1, move, A.member == 1, B.member == 1);
             const int sg = (move & 1) ? -1 : 1;
             dA += move <= 1 ? sg : 0;
             dB += (move == 2 || move == 3) ? sg : 0;
@@ -1367,6 +1421,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
             if (na) atomicAdd((unsigned long long*)&R.moves[i], na);
             if (nc) atomicAdd((unsigned long long*)&R.moves[6 + i], nc);
         }
+        if (rel_att) atomicAdd((unsigned long long*)&R.moves[12], (unsigned long long)rel_att);
+        if (rel_acc) atomicAdd((unsigned long long*)&R.moves[13], (unsigned long long)rel_acc);
         if (dA) atomicAdd((unsigned long long*)&R.totals[0], (unsigned long long)(long long)dA);
         if (dB) atomicAdd((unsigned long long*)&R.totals[1], (unsigned long long)(long long)dB);
         if (dXp) atomicAdd((unsigned long long*)&R.totals[2], (unsigned long long)(long long)dXp);
@@ -1389,9 +1445,10 @@ extern __shared__ uint4 smem[];
 
 // heavy domains first (one workgroup each), then light ones (four per
 // workgroup, one per wavefront); the grid is an upper bound.  The learned
-// proposal's code is compiled only into the LEARNED instances, so that the
-// plain kernel keeps its register budget (three wavefronts per SIMD).
-template <typename Real, bool LEARNED>
+// proposal's code is compiled only into the LEARNED instances, and the ion
+// relocation trials only into the RELOC ones, so that the plain kernel keeps
+// its register budget (three wavefronts per SIMD).
+template <typename Real, bool LEARNED, bool RELOC>
 __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
 {
     __shared__ double red[2][4];
@@ -1406,8 +1463,8 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
     const int q = heavy ? a.pool : a.pool / 4;
     const uint32_t gd = heavy ? a.plan_heavy[(size_t)colour * a.ndom_total + j]
                               : a.plan_light[(size_t)colour * a.ndom_total + j];
-    run_domain<Real, LEARNED>(a, gd, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0, heavy ? 4 : 1, red,
-                              ovf);
+    run_domain<Real, LEARNED, RELOC>(a, gd, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0,
+                                     heavy ? 4 : 1, red, ovf);
 }
 
 // ------------------------------------------------------------------------
@@ -1539,15 +1596,22 @@ hipError_t launch_plan(const SweepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename Real, bool LEARNED>
+static void launch_phase_r(const SweepArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    if (a.ion_trials > 0) hipLaunchKernelGGL((k_phase<Real, LEARNED, true>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_phase<Real, LEARNED, false>), grid, block, lds, s, a);
+}
+
 hipError_t launch_phase(const SweepArgs& a, size_t lds, hipStream_t s)
 {
     const dim3 grid(a.ndom_total), block(PHASE_THREADS);
     if (a.precision == 64) {
-        if (a.learned) hipLaunchKernelGGL((k_phase<double, true>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_phase<double, false>), grid, block, lds, s, a);
+        if (a.learned) launch_phase_r<double, true>(a, grid, block, lds, s);
+        else launch_phase_r<double, false>(a, grid, block, lds, s);
     } else {
-        if (a.learned) hipLaunchKernelGGL((k_phase<float, true>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_phase<float, false>), grid, block, lds, s, a);
+        if (a.learned) launch_phase_r<float, true>(a, grid, block, lds, s);
+        else launch_phase_r<float, false>(a, grid, block, lds, s);
     }
     return hipGetLastError();
 }
@@ -1576,8 +1640,10 @@ hipError_t launch_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k
 
 hipError_t set_phase_lds_limit(size_t bytes)
 {
-    const void* fns[] = {(const void*)k_phase<float, false>, (const void*)k_phase<double, false>,
-                         (const void*)k_phase<float, true>, (const void*)k_phase<double, true>};
+    const void* fns[] = {(const void*)k_phase<float, false, false>, (const void*)k_phase<double, false, false>,
+                         (const void*)k_phase<float, true, false>,  (const void*)k_phase<double, true, false>,
+                         (const void*)k_phase<float, false, true>,  (const void*)k_phase<double, false, true>,
+                         (const void*)k_phase<float, true, true>,   (const void*)k_phase<double, true, true>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;

@@ -97,10 +97,11 @@ def _case(name):
 
 
 def _run_pair(crmc, name, eps, learned_gpu=True, learned_oracle=True, nsw=12, trials=2, seed=71, scale=2.0,
-              offsets=(0.0, 0.0)):
+              offsets=(0.0, 0.0), ion_trials=0):
     s, m, c = _case(name)
     p = _params(9, scale)
-    S = crmc.System(n_replicas=1, lB=m["lB"], rc=m["rc"], precision=64, trials_per_cell=trials, seed=seed)
+    S = crmc.System(n_replicas=1, lB=m["lB"], rc=m["rc"], precision=64, trials_per_cell=trials, seed=seed,
+                    ion_trials=ion_trials)
     kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"])
     if len(s.get("core_R", [])):
         kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
@@ -117,7 +118,7 @@ def _run_pair(crmc, name, eps, learned_gpu=True, learned_oracle=True, nsw=12, tr
     o.set_particles(s["xyz"], s["kind"])
     if len(s.get("core_R", [])):
         o.set_cores(s["core_xyz"], s["core_R"])
-    o.set_schedule(trials)
+    o.set_schedule(trials, ion_trials=ion_trials)
     if learned_oracle:
         o.set_learned(p.astype(np.float64), eps)
         o.set_learned_offsets(*offsets)
@@ -125,11 +126,12 @@ def _run_pair(crmc, name, eps, learned_gpu=True, learned_oracle=True, nsw=12, tr
     return S, obs, o, ser, nsw
 
 
-@pytest.mark.parametrize("name,offsets", [("mixed", (0.0, 0.0)), ("np_pair_small", (0.0, 0.0)),
-                                          ("chain40", (0.0, 0.0)), ("np_pair_small", (-2.5, 1.5))])
-def test_fp64_learned_chain_bit_exact(name, offsets):
+@pytest.mark.parametrize("name,offsets,ion_trials", [("mixed", (0.0, 0.0), 0), ("np_pair_small", (0.0, 0.0), 0),
+                                                     ("chain40", (0.0, 0.0), 0), ("np_pair_small", (-2.5, 1.5), 0),
+                                                     ("np_pair_small", (0.0, 0.0), 2)])
+def test_fp64_learned_chain_bit_exact(name, offsets, ion_trials):
     crmc = _gpu()
-    S, obs, o, ser, nsw = _run_pair(crmc, name, 0.1, offsets=offsets)
+    S, obs, o, ser, nsw = _run_pair(crmc, name, 0.1, offsets=offsets, ion_trials=ion_trials)
     for a, b in zip(S.particles(0), o.particles()):
         assert np.array_equal(np.asarray(a).astype(np.int64), np.asarray(b).astype(np.int64))
     assert np.array_equal(S.series(0, 0, nsw), ser)

@@ -78,23 +78,24 @@ CASES = {
 }
 
 
-def _oracle_for(s, model, cond, n_cells, trials, pairing, seed, replica=0, fixed_grid=False, site_trials=0):
+def _oracle_for(s, model, cond, n_cells, trials, pairing, seed, replica=0, fixed_grid=False, site_trials=0,
+                ion_trials=0):
     o = oracle.Oracle(s["L"], n_cells, model["lB"], cond["kappa"], model["rc"], eps=model["eps"],
                       ion_coupling=model["ion_coupling"], seed=seed, replica=replica)
     o.set_conditions(cond["pH"], cond["pKa"], cond["pKb"], cond["pIX_pos"], cond["pIX_neg"])
     o.set_particles(s["xyz"], s["kind"], charged=s.get("charged"))
     if len(s.get("core_R", [])):
         o.set_cores(s["core_xyz"], s["core_R"])
-    o.set_schedule(trials, fixed_grid=fixed_grid, pairing=pairing, site_trials=site_trials)
+    o.set_schedule(trials, fixed_grid=fixed_grid, pairing=pairing, site_trials=site_trials, ion_trials=ion_trials)
     return o
 
 
 def _gpu_system(crmc, s, model, n_rep, precision, trials, pairing, seed, lds_records=0, fixed_grid=False,
-                site_trials=0):
+                site_trials=0, ion_trials=0):
     S = crmc.System(n_replicas=n_rep, lB=model["lB"], rc=model["rc"], eps=model["eps"],
                     ion_coupling=model["ion_coupling"], precision=precision, trials_per_cell=trials,
                     pairing=pairing, seed=seed, lds_records=lds_records, fixed_grid=fixed_grid,
-                    site_trials=site_trials)
+                    site_trials=site_trials, ion_trials=ion_trials)
     for r in range(n_rep):
         kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"], charged=s.get("charged"), group=s.get("group"))
         if len(s.get("core_R", [])):
@@ -112,22 +113,28 @@ def _same_state(gpu_particles, orc_particles):
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
-@pytest.mark.parametrize("trials,pairing,site_trials", [(1, True, 0), (2, True, 0), (1, False, 0), (1, True, 12)])
-def test_fp64_bit_exact(case, trials, pairing, site_trials):
+@pytest.mark.parametrize("trials,pairing,site_trials,ion_trials",
+                         [(1, True, 0, 0), (2, True, 0, 0), (1, False, 0, 0), (1, True, 12, 0), (1, True, 0, 2),
+                          (2, False, 0, 1)])
+def test_fp64_bit_exact(case, trials, pairing, site_trials, ion_trials):
     crmc = _gpu()
     make, model, cond = CASES[case]
     s = make()
     nsw = 12
-    S = _gpu_system(crmc, s, model, 1, 64, trials, pairing, seed=77, site_trials=site_trials)
+    S = _gpu_system(crmc, s, model, 1, 64, trials, pairing, seed=77, site_trials=site_trials, ion_trials=ion_trials)
     S.sweep_ex([cond], nsw)
     obs = S.observe(0)
     assert obs["status"] == 0 and obs["error_flags"] & 11 == 0
-    o = _oracle_for(s, model, cond, obs["n_cells"], trials, pairing, seed=77, site_trials=site_trials)
+    o = _oracle_for(s, model, cond, obs["n_cells"], trials, pairing, seed=77, site_trials=site_trials,
+                    ion_trials=ion_trials)
     ser = o.sweeps(nsw)
     _same_state(S.particles(0), o.particles())
     assert np.array_equal(S.series(0, 0, nsw), ser)
     att, acc = o.move_stats()
     assert list(att) == obs["attempts"] and list(acc) == obs["accepts"]
+    assert o.relocation_stats() == (obs["relocation_attempts"], obs["relocation_accepts"])
+    if ion_trials and case != "salt_only":
+        assert obs["relocation_accepts"] > 0
     assert obs["energy"] == pytest.approx(o.running_energy(), rel=1e-9, abs=1e-9)
     assert S.energy(0) == pytest.approx(o.energy(), rel=1e-9, abs=1e-9)
     assert sum(obs["accepts"]) > 0
@@ -158,17 +165,18 @@ def _compare_logs(glog, olog, ftol=1e-5):
     return n_checked, False
 
 
-@pytest.mark.parametrize("case", ["mixed", "chain40", "np_pair_small", "cutoff_band"])
-def test_fp32_decisions_and_dU(case):
+@pytest.mark.parametrize("case,ion_trials", [("mixed", 0), ("chain40", 0), ("np_pair_small", 0), ("cutoff_band", 0),
+                                             ("np_pair_small", 2), ("chain40", 1)])
+def test_fp32_decisions_and_dU(case, ion_trials):
     crmc = _gpu()
     make, model, cond = CASES[case]
     s = make()
     nsw = 10
-    S = _gpu_system(crmc, s, model, 1, 32, 2, True, seed=5)
+    S = _gpu_system(crmc, s, model, 1, 32, 2, True, seed=5, ion_trials=ion_trials)
     S.enable_log(2_000_000)
     S.sweep_ex([cond], nsw)
     obs = S.observe(0)
-    o = _oracle_for(s, model, cond, obs["n_cells"], 2, True, seed=5)
+    o = _oracle_for(s, model, cond, obs["n_cells"], 2, True, seed=5, ion_trials=ion_trials)
     o.enable_log(2_000_000)
     o.sweeps(nsw)
     n, diverged = _compare_logs(S.read_log(), o.log())
@@ -425,7 +433,8 @@ def test_config5_full_size_sampled_replica():
 
 @pytest.mark.parametrize("case", ["mixed", "np_pair_small", "chain40"])
 @pytest.mark.parametrize("light", [1, 65536])
-def test_light_and_heavy_domains_bit_exact(case, light):
+@pytest.mark.parametrize("ion_trials", [0, 1])
+def test_light_and_heavy_domains_bit_exact(case, light, ion_trials):
     """Every domain on a whole workgroup (light_neighbours = 1) or every domain
     that fits on one wavefront: the chain is the oracle's either way."""
     crmc = _gpu()
@@ -433,7 +442,7 @@ def test_light_and_heavy_domains_bit_exact(case, light):
     s = make()
     S = crmc.System(n_replicas=1, lB=model["lB"], rc=model["rc"], eps=model["eps"],
                     ion_coupling=model["ion_coupling"], precision=64, trials_per_cell=3, seed=41,
-                    light_neighbours=light)
+                    light_neighbours=light, ion_trials=ion_trials)
     kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"])
     if len(s.get("core_R", [])):
         kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
@@ -441,7 +450,7 @@ def test_light_and_heavy_domains_bit_exact(case, light):
     S.sweep_ex([cond], 12)
     obs = S.observe(0)
     assert obs["status"] == 0
-    o = _oracle_for(s, model, cond, obs["n_cells"], 3, True, seed=41)
+    o = _oracle_for(s, model, cond, obs["n_cells"], 3, True, seed=41, ion_trials=ion_trials)
     ser = o.sweeps(12)
     _same_state(S.particles(0), o.particles())
     assert np.array_equal(S.series(0, 0, 12), ser)

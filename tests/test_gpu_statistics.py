@@ -103,6 +103,27 @@ def test_salt_only_box_fp32():
     assert np.array_equal(ser[:, :, 2], ser[:, :, 3])
 
 
+def test_one_site_counterion_with_relocation_fp32():
+    """T-6: one acid site with Coulomb and excluded-volume interactions with
+    the ions, dilute salt (pI_S = 6), on the cell schedule with ion relocation
+    trials; P(ionized) against the quadrature.  Without relocation a lone
+    counter-ion's position mixes only through salt exchange (far too slowly
+    here)."""
+    pIX = cf.pIX_from_salt(6.0, 7.5)
+    ex = cf.one_site_ion_probability(24.0, 8.0, 0.5, 6.0, 7.5, 4.5, pIX, RHO)
+    s = dict(L=24.0, xyz=np.array([[12.0, 12.0, 12.0]]), kind=np.array([1]))
+    crmc = _gpu()
+    n_rep, nsw = 256, 4000
+    S = crmc.System(n_replicas=n_rep, lB=8.0, rc=6.0, eps=1.0, ion_coupling=1, precision=32, trials_per_cell=8,
+                    ion_trials=2, seed=99)
+    for r in range(n_rep):
+        S.build_cells(r, L=s["L"], xyz=s["xyz"], kind=s["kind"])
+    S.sweep_ex([_cond(7.5, 4.5, 5.0, pIX, pIX)] * n_rep, nsw)
+    x = np.stack([S.series(r, 0, nsw)[nsw // 10:, 0] for r in range(n_rep)]).astype(float)
+    _mean_within(x, ex)
+    assert S.observe(0)["relocation_accepts"] > 0
+
+
 def test_interacting_chain_matches_the_paper_mode_chain_fp32():
     """Interacting ions (Coulomb and excluded volume with every particle), no
     closed form: the 40-site chain's <alpha> and distribution of the number of

@@ -85,6 +85,38 @@ def test_local_dU_equals_bruteforce_difference(with_core):
     assert b.sum() > 50  # moves were accepted, so the check saw real changes
 
 
+@pytest.mark.parametrize("with_core", [False, True])
+def test_relocation_dU_equals_bruteforce_difference(with_core):
+    """T-7 for the ion relocation trials: dU of removing an ion and placing it
+    elsewhere equals E_total(new) - E_total(old), its own old-new pair left
+    out; the running energy stays equal to the brute-force energy."""
+    o = _mixed_system(with_core=with_core)
+    o.set_check(True)
+    o.set_schedule(1, ion_trials=3)
+    o.sweeps(8)
+    assert o.max_dU_err() < 1e-10
+    att, acc = o.relocation_stats()
+    assert acc > 20 and att > acc
+    assert o.running_energy() == pytest.approx(o.energy(), rel=1e-9, abs=1e-9)
+
+
+def test_relocation_trials_follow_the_reaction_trials():
+    """With ion_trials = 0 the chain is the paper's six moves only; with
+    relocation trials the reaction trials of every domain are unchanged up to
+    the first relocation of the sweep (the trial log agrees until then)."""
+    a, b = _mixed_system(seed=3), _mixed_system(seed=3)
+    a.set_schedule(2)
+    b.set_schedule(2, ion_trials=1)
+    for o in (a, b):
+        o.enable_log(100_000)
+    a.sweeps(1)
+    b.sweeps(1)
+    la, lb = a.log(), b.log()
+    first = int(np.argmax(lb["move"] == 6))
+    assert lb["move"][first] == 6 and (la["move"] < 6).all()
+    assert la[:first].tobytes() == lb[:first].tobytes()
+
+
 def test_running_energy_and_invariants():
     """T-11: retained energy equals the brute-force energy; electroneutrality;
     no free ion overlaps anything or a core."""
@@ -271,6 +303,26 @@ def test_ring_enumeration():
             ser = o.sweeps(4000)
         _within(ser[:, 0] / 12.0, ex)
         _hist_within(ser[len(ser) // 10:, 0], P)
+
+
+def test_one_site_counterion_cell_schedule_with_relocation():
+    """T-6 on the cell schedule.  Cell-local insertion alone mixes the position
+    of a lone counter-ion only through salt exchange, far too slowly at this
+    dilution; with ion relocation trials the schedule reaches the quadrature.
+    Independent seeds give the standard error."""
+    pIX = cf.pIX_from_salt(6.0, 7.5)
+    ex = cf.one_site_ion_probability(24.0, 8.0, 0.5, 6.0, 7.5, 4.5, pIX, RHO)
+    vals = []
+    for seed in range(12):
+        o = oracle.Oracle(24.0, 4, 8.0, 0.5, 6.0, eps=1.0, seed=600 + seed)
+        o.set_conditions(7.5, 4.5, 5.0, pIX, pIX)
+        o.set_particles(np.array([[12.0, 12.0, 12.0]]), np.array([1]))
+        o.set_schedule(8, ion_trials=2)
+        s = o.sweeps(5000)
+        vals.append(s[500:, 0].mean())
+    v = np.array(vals)
+    m, se = v.mean(), v.std(ddof=1) / np.sqrt(len(v))
+    assert abs(m - ex) < 3.5 * se, (m, ex, se)
 
 
 def test_one_site_interacting_counterion():
