@@ -70,6 +70,8 @@ def read_traffic(args):
     want = {"source_hash": phase_source_hash(), "trials_per_cell": str(args.trials),
             "precision": str(args.precision), "lds_records": str(args.lds_records),
             "site_trials": str(args.site_trials), "light_neighbours": str(args.light_neighbours)}
+    if args.ion_trials:
+        return None  # the counters were taken on the paper's six moves only
     if any(kv.get(k) != v for k, v in want.items()) or "bytes_per_launch" not in kv:
         return None
     return float(kv["bytes_per_launch"])
@@ -107,7 +109,7 @@ def calibrate_offsets(S, systems, first, count):
     return out
 
 
-def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4, pairing=True):
+def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4, pairing=True, ion_trials=0):
     """The oracle as it stands (plain FP64 C, one core) on the same system at
     one pH, started from the same neutral state; rate over the sweeps of the
     last half of the sample."""
@@ -118,15 +120,18 @@ def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4, pairing=
     o.set_particles(system["xyz"], system["kind"])
     if len(system.get("core_R", [])):
         o.set_cores(system["core_xyz"], system["core_R"])
-    o.set_schedule(trials, pairing=pairing, site_trials=site_trials)
+    o.set_schedule(trials, pairing=pairing, site_trials=site_trials, ion_trials=ion_trials)
     t_start = time.perf_counter()
     marks = []
+
+    def attempted():
+        return int(sum(o.move_stats()[0])) + o.relocation_stats()[0]
     while True:
-        a0 = int(sum(o.move_stats()[0]))
+        a0 = attempted()
         t0 = time.perf_counter()
         o.sweeps(1, series=False)
         t1 = time.perf_counter()
-        marks.append((t1 - t0, int(sum(o.move_stats()[0])) - a0))
+        marks.append((t1 - t0, attempted() - a0))
         if t1 - t_start > seconds:
             break
     tail = marks[len(marks) // 2:]
@@ -172,6 +177,9 @@ def main():
     ap.add_argument("--trials", type=int, default=8, help="trials per cell per sweep")
     ap.add_argument("--precision", type=int, default=32, choices=(32, 64))
     ap.add_argument("--site-trials", type=int, default=0, help="extra trials per 16 sites of a domain")
+    ap.add_argument("--ion-trials", type=int, default=0,
+                    help="ion relocation trials per cell of a domain per phase (not one of the paper's moves; "
+                         "default 0)")
     ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per phase workgroup in records (0 = default)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one in the timed region")
     ap.add_argument("--no-pairing", action="store_true",
@@ -227,6 +235,7 @@ def main():
     R = len(conds)
     S = crmc.System(n_replicas=R, lB=model["lB"], rc=model["rc"], eps=1.0, precision=args.precision,
                     trials_per_cell=args.trials, pairing=not args.no_pairing, seed=2024, site_trials=args.site_trials,
+                    ion_trials=args.ion_trials,
                     lds_records=args.lds_records, use_graph=not args.no_graph,
                     light_neighbours=args.light_neighbours)
     for r in range(R):
@@ -283,7 +292,8 @@ def main():
     torch.cuda.synchronize()
     ms, launches = crmc.crmc_get_timing(S.h)
     crmc.crmc_set_timing(S.h, False)
-    trials = sum(sum(a["attempts"]) - sum(b["attempts"]) for a, b in zip(after, before))
+    trials = sum(sum(a["attempts"]) + a["relocation_attempts"] - sum(b["attempts"]) - b["relocation_attempts"]
+                 for a, b in zip(after, before))
     accepts = sum(sum(a["accepts"]) - sum(b["accepts"]) for a, b in zip(after, before))
     rate = trials / elapsed
 
@@ -314,7 +324,8 @@ def main():
                 "avg_launch_ms": round(phase_avg_ms, 5), "timed_launches": int(launches[1])}
 
     config = {"workload": WORKLOADS[args.workload], "replicas": R, "trials_per_cell": args.trials,
-              "site_trials_per_16": args.site_trials, "graph": not args.no_graph,
+              "site_trials_per_16": args.site_trials, "ion_trials_per_cell": args.ion_trials,
+              "graph": not args.no_graph,
               "light_neighbours": args.light_neighbours, "lds_records": args.lds_records,
               "schedule": "shifted cells, " + ("single-cell domains" if args.no_pairing else "paired domains"),
               "cells_total": int(sum(cells)), "records_mean": round(float(sum(n_rec)), 1)}
@@ -352,7 +363,7 @@ def main():
         sysd["n_cells"] = after[rb]["n_cells"]
         sysd["lB"], sysd["rc"] = model["lB"], model["rc"]
         line["cpu_baseline"] = cpu_baseline(sysd, conds[rb], args.trials, args.site_trials, args.cpu_seconds,
-                                            replica=rb, pairing=not args.no_pairing)
+                                            replica=rb, pairing=not args.no_pairing, ion_trials=args.ion_trials)
         if args.workload == "chains":
             line["cpu_baseline"]["sample"] += " (median-length chain, replica %d)" % rb
     print(json.dumps(line), flush=True)
