@@ -144,6 +144,49 @@ def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4, pairing=
                       % (cond["pH"], len(marks), time.perf_counter() - t_start, len(tail), c["nXp"] + c["nXm"])}
 
 
+def cpu_worker(spec):
+    """One oracle baseline run in a process of its own (no GPU use): one
+    replica of the chain batch, printed as a JSON line."""
+    from workloads import config3
+    r = spec["replica"]
+    sysd = dict(config3()[r])
+    sysd["n_cells"] = spec["n_cells"]
+    cond = dict(pH=sysd["pH"], pKa=sysd["pKa"], pKb=sysd["pKb"], pIX_pos=sysd["pIX"], pIX_neg=sysd["pIX"],
+                kappa=sysd["kappa"])
+    res = cpu_baseline(sysd, cond, spec["trials"], spec["site_trials"], spec["seconds"], replica=r,
+                       pairing=spec["pairing"], ion_trials=spec["ion_trials"])
+    res["replica"], res["sites"] = r, len(sysd["kind"])
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline_cores(systems, after, args, cores):
+    """The chain batch on the host: one replica per core (chains spread over
+    the length range), each timed like cpu_baseline in a child process; the
+    host's rate is the sum of the per-core rates."""
+    import subprocess
+    import numpy as np
+    order = np.argsort([len(sy["kind"]) for sy in systems])
+    picks = [int(order[round(i * (len(order) - 1) / max(cores - 1, 1))]) for i in range(cores)]
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    procs = []
+    for r in picks:
+        spec = dict(replica=r, n_cells=after[r]["n_cells"], trials=args.trials, site_trials=args.site_trials,
+                    ion_trials=args.ion_trials, seconds=args.cpu_seconds, pairing=not args.no_pairing)
+        procs.append(subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", json.dumps(spec)],
+                                      stdout=subprocess.PIPE, env=env, cwd=ROOT))
+    outs = []
+    for p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError("oracle baseline worker failed")
+        outs.append(json.loads(out.decode().strip().splitlines()[-1]))
+    sizes = sorted(o["sites"] for o in outs)
+    return {"value": sum(o["value"] for o in outs), "unit": "trial moves/s", "cores": len(outs), "kind": "oracle",
+            "sample": "one chain per core (%d chains of %d..%d sites spread over the length range), each from the "
+                      "neutral start for about %.0f s; per-core rate over the last half of its sweeps, summed"
+                      % (len(outs), sizes[0], sizes[-1], args.cpu_seconds)}
+
+
 WORKLOADS = {
     "pair": "nanoparticle pair: 2000 acid + 2000 base sites, R=10, separation 25, L=120, ~2e4 ions "
             "(pI_X=0.668), lB=2, kappa=0.5, rc=8; 9 replicas pH 3..11",
@@ -200,10 +243,17 @@ def main():
                     help="with --learned: per-replica logit offsets that match the mean network output of the "
                          "acid and of the base sites to their ionized fractions")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-cores", type=int, default=0,
+                    help="host cores of the oracle baseline for the chain batch (0 = the process's CPU share, "
+                         "at most 16); the single-system workloads use one core")
+    ap.add_argument("--cpu-worker", default=None, help=argparse.SUPPRESS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB ten times (counter calibration) and exit")
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        cpu_worker(json.loads(args.cpu_worker))
+        return
     if args.steps is None:
         args.steps = {"pair": 10000, "chains": 1000, "suspension": 500}[args.workload]
 
@@ -362,10 +412,12 @@ def main():
         sysd = dict(systems[rb])
         sysd["n_cells"] = after[rb]["n_cells"]
         sysd["lB"], sysd["rc"] = model["lB"], model["rc"]
-        line["cpu_baseline"] = cpu_baseline(sysd, conds[rb], args.trials, args.site_trials, args.cpu_seconds,
-                                            replica=rb, pairing=not args.no_pairing, ion_trials=args.ion_trials)
         if args.workload == "chains":
-            line["cpu_baseline"]["sample"] += " (median-length chain, replica %d)" % rb
+            cores = args.cpu_cores or min(16, len(os.sched_getaffinity(0)))
+            line["cpu_baseline"] = cpu_baseline_cores(systems, after, args, cores)
+        else:
+            line["cpu_baseline"] = cpu_baseline(sysd, conds[rb], args.trials, args.site_trials, args.cpu_seconds,
+                                                replica=rb, pairing=not args.no_pairing, ion_trials=args.ion_trials)
     print(json.dumps(line), flush=True)
 
 
