@@ -163,36 +163,69 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
 
     const uint64_t lt = lanemask_lt();
     uint32_t base = 0, nsite = 0;
-    for (int iz = 0; iz < ncand[2]; ++iz)
-        for (int iy = 0; iy < ncand[1]; ++iy)
-            for (int ix = 0; ix < ncand[0]; ++ix) {
-                const uint32_t oc = cand[0][ix] + n * (cand[1][iy] + n * cand[2][iz]);
-                const uint32_t cc = scnt[oc];
-                for (uint32_t b = 0; b < cc; b += 64u) {
-                    const uint32_t i = b + lane;
-                    bool match = false;
-                    uint4 rec = make_uint4(0, 0, 0, 0);
-                    if (i < cc) {
-                        rec = src[(size_t)oc * cap + i];
-                        match = cell_of(rec.x - on[0], n) == kc[0] && cell_of(rec.y - on[1], n) == kc[1] &&
-                                cell_of(rec.z - on[2], n) == kc[2];
-                    }
-                    const uint64_t mask = __ballot(match);
-                    const uint32_t kd = rec.w & 7u;
-                    nsite += (uint32_t)__popcll(__ballot(match && (kd == KIND_ACID || kd == KIND_BASE)));
-                    if (match) {
-                        const uint32_t pos = base + (uint32_t)__popcll(mask & lt);
-                        if (pos < cap) dst[(size_t)k * cap + pos] = rec;
-                        const uint32_t sid = rec.w >> 8;
-                        // each site lands in exactly one new cell: non-returning adds
-                        if (sid != NO_SITE && rec_charged(rec.w)) {
-                            atomicAdd((unsigned long long*)&R.occupancy[sid], 1ull);
-                            atomicAdd(&R.group_count[(s & 1u) * R.ngroups + (uint32_t)R.site_group[sid]], 1);
-                        }
-                    }
-                    base += (uint32_t)__popcll(mask);
-                }
+    // one record: does it fall into new cell k?  Matches are appended in
+    // order (stable), counted, and a charged site is sampled
+    const auto take = [&](bool valid, const uint4& rec) {
+        const bool match = valid && cell_of(rec.x - on[0], n) == kc[0] && cell_of(rec.y - on[1], n) == kc[1] &&
+                           cell_of(rec.z - on[2], n) == kc[2];
+        const uint64_t mask = __ballot(match);
+        const uint32_t kd = rec.w & 7u;
+        nsite += (uint32_t)__popcll(__ballot(match && (kd == KIND_ACID || kd == KIND_BASE)));
+        if (match) {
+            const uint32_t pos = base + (uint32_t)__popcll(mask & lt);
+            if (pos < cap) dst[(size_t)k * cap + pos] = rec;
+            const uint32_t sid = rec.w >> 8;
+            // each site lands in exactly one new cell: non-returning adds
+            if (sid != NO_SITE && rec_charged(rec.w)) {
+                atomicAdd((unsigned long long*)&R.occupancy[sid], 1ull);
+                atomicAdd(&R.group_count[(s & 1u) * R.ngroups + (uint32_t)R.site_group[sid]], 1);
             }
+        }
+        base += (uint32_t)__popcll(mask);
+    };
+    // the overlapping old cells in ascending (z, y, x) order, one per lane,
+    // with their counts loaded at once and scanned
+    const int nc0 = ncand[0], nc01 = ncand[0] * ncand[1], ncand_all = nc01 * ncand[2];
+    uint32_t my_oc = 0, my_cc = 0;
+    if ((int)lane < ncand_all) {
+        const int ix = (int)lane % nc0, iy = ((int)lane / nc0) % ncand[1], iz = (int)lane / nc01;
+        const uint32_t cx = ix == 0 ? cand[0][0] : (ix == 1 ? cand[0][1] : cand[0][2]);
+        const uint32_t cy = iy == 0 ? cand[1][0] : (iy == 1 ? cand[1][1] : cand[1][2]);
+        const uint32_t cz = iz == 0 ? cand[2][0] : (iz == 1 ? cand[2][1] : cand[2][2]);
+        my_oc = cx + n * (cy + n * cz);
+        my_cc = scnt[my_oc];
+    }
+    uint32_t incl = my_cc;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, off, 64);
+        if ((int)lane >= off) incl += v;
+    }
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, ncand_all - 1);
+    if (total <= 64u) {
+        // sparse: lane j takes record j of the concatenated lists
+        uint32_t oc = 0, idx = 0;
+        for (int c = 0; c < ncand_all; ++c) {
+            const uint32_t end = (uint32_t)__builtin_amdgcn_readlane((int)incl, c);
+            const uint32_t cc = (uint32_t)__builtin_amdgcn_readlane((int)my_cc, c);
+            const uint32_t occ = (uint32_t)__builtin_amdgcn_readlane((int)my_oc, c);
+            if (lane >= end - cc && lane < end) { oc = occ; idx = lane - (end - cc); }
+        }
+        uint4 rec = make_uint4(0, 0, 0, 0);
+        if (lane < total) rec = src[(size_t)oc * cap + idx];
+        take(lane < total, rec);
+    } else {
+        for (int c = 0; c < ncand_all; ++c) {
+            const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)my_oc, c);
+            const uint32_t cc = (uint32_t)__builtin_amdgcn_readlane((int)my_cc, c);
+            for (uint32_t b = 0; b < cc; b += 64u) {
+                const uint32_t i = b + lane;
+                uint4 rec = make_uint4(0, 0, 0, 0);
+                if (i < cc) rec = src[(size_t)oc * cap + i];
+                take(i < cc, rec);
+            }
+        }
+    }
     if (lane == 0) {
         R.cnt[nxt][k] = base < cap ? base : cap;
         R.cnt0[k] = base < cap ? base : cap;
