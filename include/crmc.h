@@ -243,7 +243,10 @@ int crmc_get_group_hist(crmc_t h, int32_t replica, int64_t cap, int64_t* out, in
  * n_replicas, precision and seed whose replicas were built from the same
  * inputs (same box, cell grid, capacity, sites, groups and cores; before its
  * first sweep or later).  A state that does not match, or is truncated or
- * malformed, gives CRMC_E_ARG and leaves the handle unchanged.  Sweeping on
+ * malformed, gives CRMC_E_ARG and leaves the handle unchanged (the whole
+ * state is checked on the host before any device memory is written); a
+ * device or allocation error during the copy (CRMC_E_DEVICE, CRMC_E_NOMEM)
+ * leaves the replicas in an undefined state.  Sweeping on
  * from the imported state with the same conditions continues the exported
  * chain bit for bit.  Conditions, logs, traces, timing and collected training
  * rows are not part of the state.  Synchronizes.
