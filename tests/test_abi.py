@@ -36,7 +36,7 @@ def _params(**kw):
 
 @pytest.mark.parametrize("bad", [dict(precision=16), dict(trials_per_cell=0), dict(rc=0.0),
                                  dict(n_replicas=0), dict(rho0NA=-1.0), dict(lds_records=-5),
-                                 dict(lB=-1.0)])
+                                 dict(lB=-1.0), dict(ion_trials=-1), dict(ion_trials=5000)])
 def test_create_rejects_invalid_parameters(bad):
     L = crmc.load()
     h = C.c_void_p()
@@ -49,4 +49,7 @@ def test_null_arguments():
     L = crmc.load()
     assert L.crmc_create(None, None) == crmc.CRMC_E_ARG
     assert L.crmc_sweep(None, 7.0, 4.5, 1.0, 1) == crmc.CRMC_E_ARG
+    n = C.c_int64(0)
+    assert L.crmc_export_state(None, None, C.byref(n)) == crmc.CRMC_E_ARG
+    assert L.crmc_import_state(None, None, 0) == crmc.CRMC_E_ARG
     L.crmc_destroy(None)
