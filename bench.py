@@ -32,6 +32,7 @@ import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
+SERIES_WINDOW = 16384  # sweeps of the per-sweep series the library retains
 sys.path.insert(0, ROOT)
 
 METRIC = "CR-MC trial moves/s and indep. samples/s at matched <alpha>; % HBM roofline"
@@ -350,8 +351,12 @@ def main():
     # independent samples: per replica, tau_int (in sweeps) of the ionized-site count
     taus, alphaA, alphaB, samples = [], [], [], 0.0
     sweeps_per_s = args.steps / elapsed
+    # the timed sweeps, as far as the library still retains them (the last
+    # SERIES_WINDOW sweeps, the kernel timing pass included)
+    first = before[0]["sweeps"]
+    start = max(first, first + args.steps + n_kern - SERIES_WINDOW)
     for r in range(R):
-        ser = S.series(r, args.warmup, args.steps).astype(np.float64)
+        ser = S.series(r, start, first + args.steps - start).astype(np.float64)
         q = ser[:, 0] + ser[:, 1]
         t = tau_int(q)
         taus.append(round(t, 2))
@@ -394,6 +399,7 @@ def main():
         "dtype": "f32" if args.precision == 32 else "f64", "data": "synthetic",
         "config": config,
         "independent_samples_per_s": round(samples, 1),
+        "tau_window_sweeps": int(first + args.steps - start),
         "acceptance": round(accepts / max(trials, 1), 4),
         "kernel_ms": {"bin_plan": round(ms[0] / max(launches[0], 1), 5), "phase": round(phase_avg_ms, 5),
                       "sweep_end": round(ms[2] / max(launches[2], 1), 5)},

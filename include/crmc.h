@@ -200,7 +200,8 @@ int crmc_observe(crmc_t h, int32_t replica, crmc_obs* out);
 /*
  * Per-sweep series [nA-, nB+, nX+, nX-] of a replica for sweeps
  * first .. first+count-1 (counted from build), written to out (count*4).
- * Sweeps beyond the retained window return CRMC_E_ARG.
+ * The library retains the last 16384 sweeps; sweeps outside that window (or
+ * not yet run) return CRMC_E_ARG.
  */
 int crmc_get_series(crmc_t h, int32_t replica, int64_t first, int64_t count, int32_t* out);
 
