@@ -382,6 +382,20 @@ int crmc_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32
 /* Combined-ion chemical potential from a symmetric salt (eq. pIXgen). */
 double crmc_pIX_from_salt(double pIS, double pH, double pKw);
 
+/*
+ * Ungrouping (Sec. II D): the probability that a combined ion is one of its
+ * subspecies is the ratio of their activities, 10^(pI_X - pI_i).  out[4] =
+ * {S+ of X+, H+ of X+, S- of X-, OH- of X-} for salt potentials pIS_pos,
+ * pIS_neg, the pH and pOH = pKw - pH, and the combined potentials pIX_pos,
+ * pIX_neg the chain was run with; multiply by <n_X+> or <n_X-> for the
+ * subspecies' means.  With pI_X from eq. pIXgen the salt ion and H+ (pH <=
+ * pKw/2) or OH- (pH >= pKw/2) shares of one sign sum to 1; the rest of the
+ * other sign is made of the ions that keep a non-neutral reservoir neutral.
+ * Host only; CRMC_E_ARG for a NULL out or non-finite input.
+ */
+int crmc_ungroup_fractions(double pH, double pKw, double pIS_pos, double pIS_neg, double pIX_pos, double pIX_neg,
+                           double* out);
+
 const char* crmc_last_error(crmc_t h);
 void crmc_destroy(crmc_t h);
 

@@ -119,6 +119,7 @@ def load():
         "crmc_read_trace": (C.c_int, [vp, i64, vp, P(i64)]),
         "crmc_get_timing": (C.c_int, [vp, P(d), P(i64)]),
         "crmc_pIX_from_salt": (d, [d, d, d]),
+        "crmc_ungroup_fractions": (C.c_int, [d, d, d, d, d, d, P(d)]),
         "crmc_last_error": (C.c_char_p, [vp]),
         "crmc_destroy": (None, [vp]),
     }
@@ -393,6 +394,16 @@ def crmc_read_trace(h, cap):
 
 def crmc_pIX_from_salt(pIS, pH, pKw=14.0):
     return load().crmc_pIX_from_salt(float(pIS), float(pH), float(pKw))
+
+
+def crmc_ungroup_fractions(pH, pIS_pos, pIS_neg, pIX_pos, pIX_neg, pKw=14.0):
+    """{S+, H+} shares of X+ and {S-, OH-} shares of X- (a dict)."""
+    out = np.zeros(4)
+    rc = load().crmc_ungroup_fractions(float(pH), float(pKw), float(pIS_pos), float(pIS_neg), float(pIX_pos),
+                                       float(pIX_neg), _p(out, C.c_double))
+    if rc:
+        raise CrmcError(rc, "invalid arguments")
+    return dict(S_pos=out[0], H=out[1], S_neg=out[2], OH=out[3])
 
 
 def crmc_destroy(h):

@@ -642,6 +642,20 @@ double crmc_pIX_from_salt(double pIS, double pH, double pKw)
     return -std::log10(std::pow(10.0, -pIS) + std::pow(10.0, -std::min(pH, pOH)));
 }
 
+int crmc_ungroup_fractions(double pH, double pKw, double pIS_pos, double pIS_neg, double pIX_pos, double pIX_neg,
+                           double* out)
+{
+    if (!out || !std::isfinite(pH) || !std::isfinite(pKw) || !std::isfinite(pIS_pos) || !std::isfinite(pIS_neg) ||
+        !std::isfinite(pIX_pos) || !std::isfinite(pIX_neg))
+        return CRMC_E_ARG;
+    // a subspecies' share of its combined ion is the ratio of their activities
+    out[0] = std::pow(10.0, pIX_pos - pIS_pos);
+    out[1] = std::pow(10.0, pIX_pos - pH);
+    out[2] = std::pow(10.0, pIX_neg - pIS_neg);
+    out[3] = std::pow(10.0, pIX_neg - (pKw - pH));
+    return CRMC_OK;
+}
+
 const char* crmc_last_error(crmc_t h) { return h ? h->err.c_str() : "null handle"; }
 
 int crmc_create(const crmc_params* p, crmc_t* out)

@@ -25,6 +25,25 @@ def test_pIX_from_salt_matches_closed_form():
         assert crmc.crmc_pIX_from_salt(pIS, pH) == pytest.approx(cf.pIX_from_salt(pIS, pH), abs=1e-13)
 
 
+def test_ungrouping_shares_complete_the_combined_ions():
+    """With pI_X from eq. pIXgen, the salt ion and H+ make up the whole X+ at
+    pH <= 7 and the salt ion and OH- the whole X- at pH >= 7; the salt share
+    is 10^(pI_X - pI_S) whatever the pH, and a NULL output is an error."""
+    from oracle import closed_forms as cf
+    for pIS, pH in [(2.0, 4.5), (1.0, 6.9), (3.0, 2.0), (2.0, 7.0), (2.5, 9.5), (0.5, 12.0)]:
+        pIX = cf.pIX_from_salt(pIS, pH)
+        f = crmc.crmc_ungroup_fractions(pH, pIS, pIS, pIX, pIX)
+        if pH <= 7.0:
+            assert f["S_pos"] + f["H"] == pytest.approx(1.0, abs=1e-12)
+            assert f["S_neg"] + f["OH"] < 1.0 or pH == 7.0
+        if pH >= 7.0:
+            assert f["S_neg"] + f["OH"] == pytest.approx(1.0, abs=1e-12)
+        assert f["S_pos"] == pytest.approx(10.0 ** (pIX - pIS), rel=1e-12)
+        assert f["S_pos"] == pytest.approx(f["S_neg"], rel=1e-12)
+    L = crmc.load()
+    assert L.crmc_ungroup_fractions(7.0, 14.0, 2.0, 2.0, 1.9, 1.9, None) == crmc.CRMC_E_ARG
+
+
 def _params(**kw):
     p = crmc.crmc_params()
     p.n_replicas, p.precision, p.trials_per_cell, p.pairing, p.ion_coupling = 1, 32, 1, 1, 1
