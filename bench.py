@@ -145,6 +145,21 @@ def cpu_baseline(system, cond, trials, site_trials, seconds, replica=4, pairing=
                       % (cond["pH"], len(marks), time.perf_counter() - t_start, len(tail), c["nXp"] + c["nXm"])}
 
 
+def host_cpu():
+    """The host's CPU model and logical CPU count, for the baseline's record."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return "%s; %d logical CPUs, %d in this process's share" % (model or "unknown CPU", os.cpu_count() or 0,
+                                                                 len(os.sched_getaffinity(0)))
+
+
 def cpu_worker(spec):
     """One oracle baseline run in a process of its own (no GPU use): one
     replica of the chain batch, printed as a JSON line."""
@@ -424,6 +439,7 @@ def main():
         else:
             line["cpu_baseline"] = cpu_baseline(sysd, conds[rb], args.trials, args.site_trials, args.cpu_seconds,
                                                 replica=rb, pairing=not args.no_pairing, ion_trials=args.ion_trials)
+        line["cpu_baseline"]["host"] = host_cpu()
     print(json.dumps(line), flush=True)
 
 
