@@ -196,6 +196,8 @@ SweepArgs base_args(crmc_t h)
     a.fixed_grid = h->p.fixed_grid;
     a.site_trials = h->p.site_trials;
     a.ion_trials = h->p.ion_trials;
+    a.bin_sparse_any = 0;
+    for (const auto& r : h->reps) a.bin_sparse_any |= (int32_t)r.d.bin_sparse;
     a.pool = h->pool;
     a.precision = h->p.precision;
     a.light_nb = h->p.light_neighbours > 0 ? h->p.light_neighbours : DEFAULT_LIGHT_NB;
@@ -884,6 +886,9 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
         HIP_TRY(h, hipMemset(d.tab, 0, sizeof(SweepTab)));
     }
     d.series_cap = series_cap;
+    // at least four cells per particle given: a cell's re-binning gathers a
+    // few records at most, so one lane per cell keeps more cells in flight
+    d.bin_sparse = (uint64_t)ncells >= 4ull * (uint64_t)std::max(n, 1) ? 1u : 0u;
     d.n = nc;
     d.h = nc / 2u;
     d.ncells = ncells;

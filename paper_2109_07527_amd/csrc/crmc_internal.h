@@ -76,6 +76,7 @@ struct Replica {
     uint32_t cell_begin;     // prefix of cells over replicas (binning grid)
     uint32_t dom_begin;      // prefix of domains per phase over replicas
     uint32_t* nsc;           // per cell: acid and base sites as binned at the start of the sweep
+    uint32_t bin_sparse;     // 1: re-binned one lane per cell (far fewer particles than cells)
     double* phat;            // per site: network output of the current phase (learned proposal)
     double lp_off[2];        // logit offsets of acid and base sites (learned proposal)
     double L, scale, lnZ0;   // scale = L / 2^32; lnZ0 = ln(rho0 NA) + 3 ln(scale)
@@ -117,6 +118,7 @@ struct SweepArgs {
     double lB, eps, ln2;
     int32_t ion_coupling, trials, pairing, fixed_grid, site_trials;
     int32_t ion_trials; // ion relocation trials per cell of a domain, after the reaction trials
+    int32_t bin_sparse_any; // some replica is re-binned one lane per cell
     int32_t pool;      // LDS pool of a phase workgroup, in records (a light domain gets a quarter)
     int32_t precision; // 32 or 64
     int32_t light_nb;  // neighbour records up to which a domain may run on one wavefront

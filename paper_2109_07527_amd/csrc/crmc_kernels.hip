@@ -98,51 +98,24 @@ __device__ __forceinline__ uint64_t lanemask_lt()
 // ------------------------------------------------------------------------
 // k_bin: stable re-binning into the shifted grid of this sweep
 // ------------------------------------------------------------------------
-__global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
+// grid shifts of this sweep (on) and of the previous one (oo)
+__device__ __forceinline__ void bin_shifts(const Replica& R, uint64_t s, int fixed_grid, uint32_t on[3], uint32_t oo[3])
 {
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    const uint32_t gcell = blockIdx.x * (BIN_THREADS / 64) + wave;
-    if (gcell >= a.ncell_total) return;
-    const uint32_t r = a.cell2rep[gcell];
-    const Replica& R = a.reps[r];
-    const uint32_t n = R.n, cap = R.cap;
-    const uint32_t k = gcell - R.cell_begin;
-    const uint64_t s = *a.sweep;
-    const int cur = (int)(s & 1u), nxt = cur ^ 1;
-    const uint4* __restrict__ src = R.rec[cur];
-    const uint32_t* __restrict__ scnt = R.cnt[cur];
-    uint4* __restrict__ dst = R.rec[nxt];
-    const uint32_t* __restrict__ bnd = R.bnd;
-    const uint32_t hw = *R.hiwater;
-
-    uint32_t on[3], oo[3];
     if (R.tab->valid == s + 1u) {
         // left by the end of the previous sweep
         for (int d = 0; d < 3; ++d) { on[d] = R.tab->next[d]; oo[d] = R.tab->prev[d]; }
     } else {
-        grid_shift(R.key0, R.key1, s, a.fixed_grid, on);
+        grid_shift(R.key0, R.key1, s, fixed_grid, on);
         if (s == 0) { oo[0] = oo[1] = oo[2] = 0u; }
-        else grid_shift(R.key0, R.key1, s - 1, a.fixed_grid, oo);
+        else grid_shift(R.key0, R.key1, s - 1, fixed_grid, oo);
     }
+}
 
-    if (gcell == 0 && lane < PLAN_N) a.plan_n[lane] = 0u; // plan and learned-proposal counters of the sweep
-    if (k == 0 && lane < 12) {
-        // the sweep's table: shift, and the pairing centre of every colour
-        const uint32_t M = R.h * R.h * R.h;
-        uint32_t v = 0;
-        if (lane < 4) v = lane < 3 ? on[lane] : 0u;
-        else {
-            uint32_t w[4];
-            philox4x32_10((uint32_t)s, lane - 4u, 0u, TAG_PAIR, R.key0, R.key1, w);
-            const uint32_t rr = pick32(w[0], M);
-            v = (uint32_t)(((uint64_t)M - 1u + 2ull * M - 2ull * rr) % M);
-        }
-        if (lane < 4) R.tab->o[lane] = v; else R.tab->pairc[lane - 4] = v;
-    }
-
-    const uint32_t kc[3] = {k % n, (k / n) % n, k / (n * n)};
-    uint32_t cand[3][3];
-    int ncand[3];
+// the old cells that overlap new cell kc, per dimension in ascending order
+__device__ __forceinline__ void bin_candidates(const uint32_t* __restrict__ bnd, uint32_t n, const uint32_t kc[3],
+                                               const uint32_t on[3], const uint32_t oo[3], uint32_t cand[3][3],
+                                               int ncand[3])
+{
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const uint32_t lo_abs = on[d] + bnd[kc[d]];
@@ -160,6 +133,52 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
         cand[d][0] = v0; cand[d][1] = v1; cand[d][2] = v2;
         ncand[d] = m;
     }
+}
+
+// One wavefront per new cell of the dense replicas; the cells of sparse
+// replicas (far fewer records than cells) are left to k_bin_sparse.  The
+// wavefront of a replica's cell 0 writes the sweep's table either way.
+__global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
+{
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t gcell = blockIdx.x * (BIN_THREADS / 64) + wave;
+    if (gcell >= a.ncell_total) return;
+    const uint32_t r = a.cell2rep[gcell];
+    const Replica& R = a.reps[r];
+    const uint32_t n = R.n, cap = R.cap;
+    const uint32_t k = gcell - R.cell_begin;
+    if (R.bin_sparse && k != 0 && gcell != 0) return;
+    const uint64_t s = *a.sweep;
+    const int cur = (int)(s & 1u), nxt = cur ^ 1;
+    const uint4* __restrict__ src = R.rec[cur];
+    const uint32_t* __restrict__ scnt = R.cnt[cur];
+    uint4* __restrict__ dst = R.rec[nxt];
+    const uint32_t* __restrict__ bnd = R.bnd;
+    const uint32_t hw = *R.hiwater;
+
+    uint32_t on[3], oo[3];
+    bin_shifts(R, s, a.fixed_grid, on, oo);
+
+    if (gcell == 0 && lane < PLAN_N) a.plan_n[lane] = 0u; // plan and learned-proposal counters of the sweep
+    if (k == 0 && lane < 12) {
+        // the sweep's table: shift, and the pairing centre of every colour
+        const uint32_t M = R.h * R.h * R.h;
+        uint32_t v = 0;
+        if (lane < 4) v = lane < 3 ? on[lane] : 0u;
+        else {
+            uint32_t w[4];
+            philox4x32_10((uint32_t)s, lane - 4u, 0u, TAG_PAIR, R.key0, R.key1, w);
+            const uint32_t rr = pick32(w[0], M);
+            v = (uint32_t)(((uint64_t)M - 1u + 2ull * M - 2ull * rr) % M);
+        }
+        if (lane < 4) R.tab->o[lane] = v; else R.tab->pairc[lane - 4] = v;
+    }
+    if (R.bin_sparse) return;
+
+    const uint32_t kc[3] = {k % n, (k / n) % n, k / (n * n)};
+    uint32_t cand[3][3];
+    int ncand[3];
+    bin_candidates(bnd, n, kc, on, oo, cand, ncand);
 
     const uint64_t lt = lanemask_lt();
     uint32_t base = 0, nsite = 0;
@@ -233,6 +252,60 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
         if (base > cap) atomicOr(a.err, ERR_BIN_CAPACITY);
         if (base > hw) atomicMax(R.hiwater, base); // rarely taken once the mark has settled
     }
+}
+
+// One lane per new cell of the sparse replicas: the lane walks the
+// overlapping old cells in the same order as k_bin and appends its matches
+// one by one, so the result is the same stable order; 64 cells are in flight
+// per wavefront instead of one.
+__global__ __launch_bounds__(BIN_THREADS) void k_bin_sparse(SweepArgs a)
+{
+    const uint32_t gcell = blockIdx.x * BIN_THREADS + threadIdx.x;
+    if (gcell >= a.ncell_total) return;
+    const uint32_t r = a.cell2rep[gcell];
+    const Replica& R = a.reps[r];
+    if (!R.bin_sparse) return;
+    const uint32_t n = R.n, cap = R.cap;
+    const uint32_t k = gcell - R.cell_begin;
+    const uint64_t s = *a.sweep;
+    const int cur = (int)(s & 1u), nxt = cur ^ 1;
+    const uint4* __restrict__ src = R.rec[cur];
+    const uint32_t* __restrict__ scnt = R.cnt[cur];
+    uint4* __restrict__ dst = R.rec[nxt];
+    uint32_t on[3], oo[3];
+    bin_shifts(R, s, a.fixed_grid, on, oo);
+    const uint32_t kc[3] = {k % n, (k / n) % n, k / (n * n)};
+    uint32_t cand[3][3];
+    int ncand[3];
+    bin_candidates(R.bnd, n, kc, on, oo, cand, ncand);
+
+    uint32_t base = 0, nsite = 0;
+    for (int iz = 0; iz < ncand[2]; ++iz)
+        for (int iy = 0; iy < ncand[1]; ++iy)
+            for (int ix = 0; ix < ncand[0]; ++ix) {
+                const uint32_t oc = cand[0][ix] + n * (cand[1][iy] + n * cand[2][iz]);
+                const uint32_t cc = scnt[oc];
+                for (uint32_t i = 0; i < cc; ++i) {
+                    const uint4 rec = src[(size_t)oc * cap + i];
+                    if (cell_of(rec.x - on[0], n) != kc[0] || cell_of(rec.y - on[1], n) != kc[1] ||
+                        cell_of(rec.z - on[2], n) != kc[2])
+                        continue;
+                    if (base < cap) dst[(size_t)k * cap + base] = rec;
+                    const uint32_t kd = rec.w & 7u;
+                    nsite += (kd == KIND_ACID || kd == KIND_BASE) ? 1u : 0u;
+                    const uint32_t sid = rec.w >> 8;
+                    if (sid != NO_SITE && rec_charged(rec.w)) {
+                        atomicAdd((unsigned long long*)&R.occupancy[sid], 1ull);
+                        atomicAdd(&R.group_count[(s & 1u) * R.ngroups + (uint32_t)R.site_group[sid]], 1);
+                    }
+                    ++base;
+                }
+            }
+    R.cnt[nxt][k] = base < cap ? base : cap;
+    R.cnt0[k] = base < cap ? base : cap;
+    R.nsc[k] = nsite;
+    if (base > cap) atomicOr(a.err, ERR_BIN_CAPACITY);
+    if (base > *R.hiwater) atomicMax(R.hiwater, base);
 }
 
 // ------------------------------------------------------------------------
@@ -1620,6 +1693,9 @@ hipError_t launch_bin(const SweepArgs& a, hipStream_t s)
 {
     const uint32_t per = BIN_THREADS / 64;
     hipLaunchKernelGGL(k_bin, dim3((a.ncell_total + per - 1) / per), dim3(BIN_THREADS), 0, s, a);
+    if (a.bin_sparse_any)
+        hipLaunchKernelGGL(k_bin_sparse, dim3((a.ncell_total + BIN_THREADS - 1) / BIN_THREADS), dim3(BIN_THREADS), 0,
+                           s, a);
     return hipGetLastError();
 }
 
