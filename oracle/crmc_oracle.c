@@ -54,6 +54,20 @@
  * uniform-pick count ratio of Sec. II C) makes every trial satisfy detailed
  * balance for the frozen environment.
  *
+ * Ion relocation trials (cell mode, optional, off by default; not in the
+ * paper, whose ions move by molecular dynamics between MC blocks): after the
+ * reaction trials of a domain, a free ion picked uniformly is removed and
+ * re-inserted at a point drawn like an insertion of its sign, accepted with
+ * min(1, (V_new / V_old) exp(-dU)) (eq. accrat for that proposal).
+ *
+ * A trial limit (a test aid) stops a run after its first n trials in
+ * processing order; it changes no arithmetic.
+ *
+ * Pinned by the tests: closed forms (ideal ions, salt-only box, high-salt
+ * limit), the exact enumeration of a 12-site ring, the one-site quadrature,
+ * brute-force energy differences on every trial, the two schedules against
+ * each other, and a fixed-grid negative control.
+ *
  * Everything is FP64.  Random numbers are Philox4x32-10 (Salmon, Moraes, Dror,
  * Shaw, SC'11), written here from its published definition.
  */
