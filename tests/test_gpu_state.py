@@ -37,9 +37,9 @@ def _cond(pH, kappa=0.5):
     return dict(pH=pH, pKa=5.0, pKb=5.0, pIX_pos=0.7, pIX_neg=0.9, kappa=kappa)
 
 
-def _system(crmc, s, n_rep, precision, seed=11, learned=False):
+def _system(crmc, s, n_rep, precision, seed=11, learned=False, ion_trials=0):
     S = crmc.System(n_replicas=n_rep, lB=2.0, rc=6.0, eps=1.0, ion_coupling=1, precision=precision,
-                    trials_per_cell=2, seed=seed)
+                    trials_per_cell=2, seed=seed, ion_trials=ion_trials)
     for r in range(n_rep):
         kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"], group=s.get("group"))
         if len(s.get("core_R", [])):
@@ -61,15 +61,17 @@ def _observables(S, n_rep, sweeps):
     return out
 
 
-@pytest.mark.parametrize("case", ["mixed_fp32", "mixed_fp64_learned", "pair_fp32", "pair_fp64_learned"])
+@pytest.mark.parametrize("case", ["mixed_fp32", "mixed_fp64_learned", "pair_fp32", "pair_fp64_learned",
+                                  "pair_fp32_relocation"])
 def test_resume_continues_the_chain_bit_for_bit(case):
     crmc = _gpu()
-    make, precision, learned = {"mixed_fp32": (_mixed, 32, False), "mixed_fp64_learned": (_mixed, 64, True),
-                                "pair_fp32": (_pair, 32, False), "pair_fp64_learned": (_pair, 64, True)}[case]
+    make, precision, learned, it = {"mixed_fp32": (_mixed, 32, False, 0), "mixed_fp64_learned": (_mixed, 64, True, 0),
+                                    "pair_fp32": (_pair, 32, False, 0), "pair_fp64_learned": (_pair, 64, True, 0),
+                                    "pair_fp32_relocation": (_pair, 32, False, 2)}[case]
     s = make()
     conds = [_cond(4.0), _cond(7.5, kappa=0.3)]
     n1, n2 = 3, 7  # odd: the import lands on the second record buffer
-    A = _system(crmc, s, 2, precision, learned=learned)
+    A = _system(crmc, s, 2, precision, learned=learned, ion_trials=it)
     A.sweep_ex(conds, n1)
     state = A.export_state()
     A.sweep_ex(conds, n2)
@@ -77,7 +79,7 @@ def test_resume_continues_the_chain_bit_for_bit(case):
     ref = _observables(A, 2, n1 + n2)
 
     # a fresh handle built from the same inputs, never swept
-    B = _system(crmc, s, 2, precision)
+    B = _system(crmc, s, 2, precision, ion_trials=it)
     B.import_state(state)
     assert B.export_state() == state
     B.sweep_ex(conds, n2)
@@ -85,11 +87,13 @@ def test_resume_continues_the_chain_bit_for_bit(case):
     assert _observables(B, 2, n1 + n2) == ref
     for r in range(2):
         assert B.energy(r) == A.energy(r)
+    if it:
+        assert A.observe(0)["relocation_accepts"] > 0
 
     # a handle that has already run its own sweeps, with the other proposal,
     # is overwritten as well (a network it holds stays allocated, so only the
     # observables are compared)
-    C = _system(crmc, s, 2, precision, learned=not learned)
+    C = _system(crmc, s, 2, precision, learned=not learned, ion_trials=it)
     C.sweep_ex([_cond(9.0), _cond(3.0)], 2)
     C.import_state(state)
     C.sweep_ex(conds, n2)
