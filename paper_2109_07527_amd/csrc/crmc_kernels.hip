@@ -17,7 +17,9 @@
 //                accumulation,
 //                acceptance of Sec. II C, commit in LDS; writes the cells back
 //                at the end.  L: the learned site proposal compiled in; M: the
-//                ion relocation trials compiled in.
+//                ion relocation trials compiled in.  k_phase_fast<R, M>: the
+//                same, with the trials of empty domains evaluated side by
+//                side (batches with sparse replicas).
 //   k_sweep_end  per sweep: series row, group histograms, sweep counter.
 //   k_energy     total energy of a replica from scratch (FP64), per cell.
 #include "crmc_internal.h"
@@ -850,7 +852,7 @@ constexpr uint32_t CLS_MASK_SITE = 0xFu, CLS_MASK_ION = 0x7u;
 // The domain's trials.  wpd wavefronts share the pair sums (wpd = 1: light
 // domain, no workgroup barriers; wpd = 4: heavy domain, the whole workgroup;
 // uniform over the workgroup).
-template <typename Real, bool LEARNED, bool RELOC>
+template <typename Real, bool LEARNED, bool RELOC, bool FAST>
 __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint4* __restrict__ pool,
                                            int pool_records, int wid, const int wpd, double (*red)[4], int (*ovf)[4])
 {
@@ -1043,7 +1045,152 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     double dE = 0.0;
     uint32_t ph0 = 0, ph1 = 0, ph2 = 0, ph3 = 0;
     int nred = 0;
-    for (int t = 0; t < ntr; ++t) {
+
+    // ---- an empty light domain: until its first accepted insertion no trial
+    //      changes anything, so ten consecutive trials are evaluated side by
+    //      side against the same state (six lanes each, lane 6i + b holding
+    //      Philox block b of trial i as in the loop below) and taken in order
+    //      up to and including the first accepted one
+    int t_first = 0;
+    if (FAST && wpd == 1 && n0 + n1 == 0 && nreact == 1 && !spill) {
+        const int grp = lane / 6, sub = lane % 6; // lanes 60-63 idle
+        const bool lead = sub == 0 && grp < 10;
+        const double lnp_counts = -lnt[1] - lnt[1] + lnKion;
+        bool done = false;
+        for (int t0 = 0; t0 < ntr && !done; t0 += 10) {
+            const int t = t0 + grp;
+            const bool live = grp < 10 && t < ntr;
+            uint32_t w4[4];
+            philox4x32_10((uint32_t)s, G.cell0, (uint32_t)(t0 + lane / 6) * 8u + (uint32_t)(lane % 6), TAG_TRIAL,
+                          key0, key1, w4);
+            const auto wd = [&](int wi) -> uint32_t {
+                const int c = wi & 3;
+                const uint32_t v = c == 0 ? w4[0] : (c == 1 ? w4[1] : (c == 2 ? w4[2] : w4[3]));
+                return (uint32_t)__shfl((int)v, 6 * grp + (wi >> 2), 64);
+            };
+            // the salt reaction alone: forward (move 4) or reverse (5, nothing to delete)
+            const int move = RELOC && t >= ntr_react ? 6 : 4 + (int)(pick32(wd(0), 2u) & 1u);
+            const double u = unit53(wd(16), wd(17));
+            const bool ins = live && move == 4;
+            Chg A, B;
+            const int jA = ncell == 1 ? 0 : (int)pick32(wd(18), (uint32_t)ncell);
+            const int jB = ncell == 1 ? 0 : (int)pick32(wd(19), (uint32_t)ncell);
+            A.member = jA; A.own = -1; A.ion = 1; A.q_old = 0; A.q_new = 1; A.pres_old = 0; A.pres_new = 1;
+            A.dq = a.ion_coupling ? 1 : 0; A.dw = ev_on ? 1 : 0;
+            A.x = (jA ? ib1[0] : ib0[0]) + pick64(wd(4), wd(5), jA ? iw1[0] : iw0[0]);
+            A.y = (jA ? ib1[1] : ib0[1]) + pick64(wd(6), wd(7), jA ? iw1[1] : iw0[1]);
+            A.z = (jA ? ib1[2] : ib0[2]) + pick64(wd(8), wd(9), jA ? iw1[2] : iw0[2]);
+            B.member = jB; B.own = -1; B.ion = 1; B.q_old = 0; B.q_new = -1; B.pres_old = 0; B.pres_new = 1;
+            B.dq = a.ion_coupling ? -1 : 0; B.dw = ev_on ? 1 : 0;
+            B.x = (jB ? ib1[0] : ib0[0]) + pick64(wd(10), wd(11), jB ? iw1[0] : iw0[0]);
+            B.y = (jB ? ib1[1] : ib0[1]) + pick64(wd(12), wd(13), jB ? iw1[1] : iw0[1]);
+            B.z = (jB ? ib1[2] : ib0[2]) + pick64(wd(14), wd(15), jB ? iw1[2] : iw0[2]);
+            const double lnvol = (jB ? lnZm1 : lnZm0) + (jA ? lnZm1 : lnZm0);
+
+            // energy change: the group's six lanes share the member's staged
+            // neighbours (the domain's own lists are empty)
+            double aqA = 0.0, aqB = 0.0, aw = 0.0;
+            int ov = 0;
+            float gap = 3.0e38f;
+            for (int j = 0; j < ncell; ++j) {
+                const int lo = j ? nbc0 : 0, hi = j ? nb_total : nbc0;
+                for (int g = lo + sub; g < hi; g += 6) {
+                    const uint4 rc = pool[pl.st_off + g];
+                    if (ins && jA == j) pair_acc<Real>(rc, rc.w, true, A, P, aqA, aw, ov, gap);
+                    if (ins && jB == j) pair_acc<Real>(rc, rc.w, true, B, P, aqB, aw, ov, gap);
+                }
+            }
+            if (__ballot(gap <= P.band_f)) {
+                for (int j = 0; j < ncell; ++j) {
+                    const int lo = j ? nbc0 : 0, hi = j ? nb_total : nbc0;
+                    for (int g = lo + sub; g < hi; g += 6) {
+                        const uint4 rc = pool[pl.st_off + g];
+                        if (ins && jA == j) pair_band<Real>(rc, rc.w, true, A, P, aqA);
+                        if (ins && jB == j) pair_band<Real>(rc, rc.w, true, B, P, aqB);
+                    }
+                }
+            }
+            double acc = P.lB * ((double)A.dq * aqA + (double)B.dq * aqB) + aw;
+            if (ins && ev_on && ncores) {
+                for (int k = sub; k < (int)ncores; k += 6) {
+                    const uint4 cx = pl.ncl ? lcore[k] : core_g[k];
+                    const double dl = pl.ncl ? lcdel[k] : cdel_g[k];
+                    acc += wca_core<Real>(A, cx, dl, P, ov);
+                    acc += wca_core<Real>(B, cx, dl, P, ov);
+                }
+            }
+            if (ins && sub == 0) acc += changed_pair<Real>(A, B, P, ev_on, ov);
+            // the group's sums, its six lanes added in order
+            double dU = 0.0;
+            int gov = 0;
+            for (int q = 0; q < 6; ++q) {
+                dU += __shfl(acc, 6 * grp + q, 64);
+                gov |= __shfl(ov, 6 * grp + q, 64);
+            }
+            if (gov) dU = __longlong_as_double(0x7FF0000000000000ll);
+            const double lnp = lnp_counts + lnvol - dU;
+            const bool cap_fail = ins && ((jA == 0) + (jB == 0) > (int)cap || (jA == 1) + (jB == 1) > (int)cap);
+            const bool accepted = ins && !cap_fail && metropolis(u, lnp);
+            // the first accepted trial of the ten; the trials up to it are final
+            const uint64_t accm = __ballot(lead && live && accepted);
+            const int first = accm ? (int)(__builtin_ctzll(accm) / 6) : 10;
+            const bool taken = lead && live && grp <= first;
+            attH += (uint64_t)__popcll(__ballot(taken && move == 4)) << 21;
+            attH += (uint64_t)__popcll(__ballot(taken && move == 5)) << 42;
+            rel_att += __popcll(__ballot(taken && move == 6));
+            if (taken && cap_fail) atomicOr(a.err, ERR_INSERT_CAPACITY);
+            if (taken && a.log) {
+                const unsigned long long li = atomicAdd(a.log_n, 1ull);
+                if (li < a.log_cap) {
+                    TrialRec& L = a.log[li];
+                    L.sweep = (int64_t)s; L.cell = G.cell0; L.trial = t; L.replica = (int32_t)r;
+                    L.move = move; L.status = move == 4 ? (accepted ? 1 : 0) : 2;
+                    L.dU = move == 4 ? dU : __longlong_as_double(0x7FF8000000000000ll);
+                    L.lnp = move == 4 ? lnp : L.dU;
+                    L.u = u;
+                }
+            }
+            if (accm) {
+                // commit the accepted insertion: cation, then anion, appended
+                const int src = 6 * first;
+                const int ja = (int)rdl((uint32_t)jA, src), jb = (int)rdl((uint32_t)jB, src);
+                const uint32_t ax = rdl(A.x, src), ay = rdl(A.y, src), az = rdl(A.z, src);
+                const uint32_t bx = rdl(B.x, src), by = rdl(B.y, src), bz = rdl(B.z, src);
+                const long long ub = __double_as_longlong(dU);
+                const double dUf =
+                    __longlong_as_double((long long)(((uint64_t)rdl((uint32_t)((uint64_t)ub >> 32), src) << 32) |
+                                                     (uint64_t)rdl((uint32_t)ub, src)));
+                if (tid == 0) {
+                    int l0 = 0, l1 = 0;
+                    int& ca = ja ? l1 : l0;
+                    pool[pl.base(ja) + ca] = make_uint4(ax, ay, az, make_meta(KIND_XPOS, 1u, NO_SITE));
+                    if (learned) aux[pl.base(ja) + ca] = 0.0;
+                    ++ca;
+                    int& cb = jb ? l1 : l0;
+                    pool[pl.base(jb) + cb] = make_uint4(bx, by, bz, make_meta(KIND_XNEG, 1u, NO_SITE));
+                    if (learned) aux[pl.base(jb) + cb] = 0.0;
+                    ++cb;
+                }
+                acpH += 1ull << 21;
+                dE += dUf;
+                MemberCounts& cma = ja ? c1 : c0;
+                MemberCounts& cmb = jb ? c1 : c0;
+                ++cma.xp;
+                ++cmb.xn;
+                dXp += 1;
+                dXm += 1;
+                n0 += (ja == 0) + (jb == 0);
+                n1 += (ja == 1) + (jb == 1);
+                t_first = t0 + first + 1;
+                done = true;
+            } else {
+                t_first = min(t0 + 10, ntr);
+            }
+            wave_sync();
+        }
+    }
+
+    for (int t = t_first; t < ntr; ++t) {
         // the loop-carried state is uniform: keep it in scalar registers
         n0 = rfl(n0);
         n1 = rfl(n1);
@@ -1053,10 +1200,10 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         // Philox words, ten trials at a time: lane 6i + b holds block b of
         // trial i of the batch (blocks 0-4 every trial, 5 the learned pick)
         const int tl = t % 10;
-        if (tl == 0) {
+        if (tl == 0 || t == t_first) {
             uint32_t w[4];
-            philox4x32_10((uint32_t)s, G.cell0, (uint32_t)(t + lane / 6) * 8u + (uint32_t)(lane % 6), TAG_TRIAL,
-                          key0, key1, w);
+            philox4x32_10((uint32_t)s, G.cell0, (uint32_t)(t - tl + lane / 6) * 8u + (uint32_t)(lane % 6),
+                          TAG_TRIAL, key0, key1, w);
             ph0 = w[0]; ph1 = w[1]; ph2 = w[2]; ph3 = w[3];
         }
         // words 0-3 and 16-19 serve every trial; the insertion coordinates
@@ -1551,11 +1698,13 @@ extern __shared__ uint4 smem[];
 
 // heavy domains first (one workgroup each), then light ones (four per
 // workgroup, one per wavefront); the grid is an upper bound.  The learned
-// proposal's code is compiled only into the LEARNED instances, and the ion
-// relocation trials only into the RELOC ones, so that the plain kernel keeps
-// its register budget (three wavefronts per SIMD).
-template <typename Real, bool LEARNED, bool RELOC>
-__global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
+// proposal's code is compiled only into the LEARNED instances, the ion
+// relocation trials only into the RELOC ones and the side-by-side trials of
+// empty domains only into k_phase_fast (batches with sparse replicas, plain
+// proposal), so that the plain kernel keeps its register budget (three
+// wavefronts per SIMD).
+template <typename Real, bool LEARNED, bool RELOC, bool FAST>
+__device__ __forceinline__ void phase_body(const SweepArgs& a)
 {
     __shared__ double red[2][4];
     __shared__ int ovf[2][4];
@@ -1569,8 +1718,22 @@ __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
     const int q = heavy ? a.pool : a.pool / 4;
     const uint32_t gd = heavy ? a.plan_heavy[(size_t)colour * a.ndom_total + j]
                               : a.plan_light[(size_t)colour * a.ndom_total + j];
-    run_domain<Real, LEARNED, RELOC>(a, gd, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0,
-                                     heavy ? 4 : 1, red, ovf);
+    run_domain<Real, LEARNED, RELOC, FAST>(a, gd, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0,
+                                           heavy ? 4 : 1, red, ovf);
+}
+
+template <typename Real, bool LEARNED, bool RELOC>
+__global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
+{
+    phase_body<Real, LEARNED, RELOC, false>(a);
+}
+
+// the FAST instances hold their register use to three wavefronts per SIMD:
+// the batches they serve are bound by how many domains are in flight
+template <typename Real, bool RELOC>
+__global__ __launch_bounds__(PHASE_THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_phase_fast(SweepArgs a)
+{
+    phase_body<Real, false, RELOC, true>(a);
 }
 
 // ------------------------------------------------------------------------
@@ -1705,11 +1868,18 @@ hipError_t launch_plan(const SweepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename Real, bool LEARNED, bool RELOC>
+static void launch_phase_f(const SweepArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    if (!LEARNED && a.bin_sparse_any) hipLaunchKernelGGL((k_phase_fast<Real, RELOC>), grid, block, lds, s, a);
+    else hipLaunchKernelGGL((k_phase<Real, LEARNED, RELOC>), grid, block, lds, s, a);
+}
+
 template <typename Real, bool LEARNED>
 static void launch_phase_r(const SweepArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
 {
-    if (a.ion_trials > 0) hipLaunchKernelGGL((k_phase<Real, LEARNED, true>), grid, block, lds, s, a);
-    else hipLaunchKernelGGL((k_phase<Real, LEARNED, false>), grid, block, lds, s, a);
+    if (a.ion_trials > 0) launch_phase_f<Real, LEARNED, true>(a, grid, block, lds, s);
+    else launch_phase_f<Real, LEARNED, false>(a, grid, block, lds, s);
 }
 
 hipError_t launch_phase(const SweepArgs& a, size_t lds, hipStream_t s)
@@ -1752,7 +1922,9 @@ hipError_t set_phase_lds_limit(size_t bytes)
     const void* fns[] = {(const void*)k_phase<float, false, false>, (const void*)k_phase<double, false, false>,
                          (const void*)k_phase<float, true, false>,  (const void*)k_phase<double, true, false>,
                          (const void*)k_phase<float, false, true>,  (const void*)k_phase<double, false, true>,
-                         (const void*)k_phase<float, true, true>,   (const void*)k_phase<double, true, true>};
+                         (const void*)k_phase<float, true, true>,   (const void*)k_phase<double, true, true>,
+                         (const void*)k_phase_fast<float, false>,   (const void*)k_phase_fast<double, false>,
+                         (const void*)k_phase_fast<float, true>,    (const void*)k_phase_fast<double, true>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
