@@ -54,6 +54,8 @@ struct crmc_s {
     uint32_t* d_plan_n = nullptr;     // per colour: heavy and light domain counts
     uint32_t* d_plan_heavy = nullptr; // per colour: ndom_total domain slots
     uint32_t* d_plan_light = nullptr;
+    uint4* d_plan_geo_heavy = nullptr;  // beside each slot: replica, cells, counts
+    uint4* d_plan_geo_light = nullptr;
     // learned proposal
     bool learned = false;
     double learn_eps = 0.1;
@@ -204,6 +206,8 @@ SweepArgs base_args(crmc_t h)
     a.plan_n = h->d_plan_n;
     a.plan_heavy = h->d_plan_heavy;
     a.plan_light = h->d_plan_light;
+    a.plan_geo_heavy = h->d_plan_geo_heavy;
+    a.plan_geo_light = h->d_plan_geo_light;
     a.learned = h->learned ? 1 : 0;
     a.learn_eps = h->learn_eps;
     a.trace = h->d_trace;
@@ -245,6 +249,9 @@ int upload_descriptors(crmc_t h)
         if (h->d_plan_n) (void)hipFree(h->d_plan_n);
         if (h->d_plan_heavy) (void)hipFree(h->d_plan_heavy);
         if (h->d_plan_light) (void)hipFree(h->d_plan_light);
+        if (h->d_plan_geo_heavy) (void)hipFree(h->d_plan_geo_heavy);
+        if (h->d_plan_geo_light) (void)hipFree(h->d_plan_geo_light);
+        h->d_plan_geo_heavy = h->d_plan_geo_light = nullptr;
         h->d_cell2rep = h->d_dom2rep = nullptr;
         h->d_lntab = nullptr;
         h->d_plan_n = h->d_plan_heavy = h->d_plan_light = nullptr;
@@ -258,6 +265,8 @@ int upload_descriptors(crmc_t h)
         HIP_TRY(h, dalloc(&h->d_plan_n, PLAN_N));
         HIP_TRY(h, dalloc(&h->d_plan_heavy, (size_t)8 * doms));
         HIP_TRY(h, dalloc(&h->d_plan_light, (size_t)8 * doms));
+        HIP_TRY(h, dalloc(&h->d_plan_geo_heavy, (size_t)8 * doms));
+        HIP_TRY(h, dalloc(&h->d_plan_geo_light, (size_t)8 * doms));
         HIP_TRY(h, hipMemset(h->d_plan_n, 0, PLAN_N * sizeof(uint32_t)));
         HIP_TRY(h, hipMemcpy(h->d_cell2rep, c2r.data(), c2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(h->d_dom2rep, d2r.data(), d2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -451,6 +460,7 @@ int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n, bool u
                          (uint64_t)lds * 31ull ^ (uint64_t)(uintptr_t)a0.lntab ^
                          (uint64_t)(uintptr_t)a0.trace * 65537ull ^ (uint64_t)a0.trace_cap * 131ull ^
                          (uint64_t)(uintptr_t)a0.plan_heavy * 17ull ^ (uint64_t)(uintptr_t)a0.plan_light * 257ull ^
+                         (uint64_t)(uintptr_t)a0.plan_geo_heavy * 37ull ^ (uint64_t)(uintptr_t)a0.plan_geo_light * 41ull ^
                          (uint64_t)(uintptr_t)a0.plan_n * 4099ull ^ (uint64_t)a0.light_nb * 1000033ull ^
                          (uint64_t)a0.pool * 7777ull ^ (uint64_t)a0.learned * 99991ull ^
                          (uint64_t)(a0.learn_eps * 1e12) * 13ull ^ (uint64_t)use_learn * 424243ull ^
@@ -1697,6 +1707,8 @@ void crmc_destroy(crmc_t h)
     if (h->d_plan_n) (void)hipFree(h->d_plan_n);
     if (h->d_plan_heavy) (void)hipFree(h->d_plan_heavy);
     if (h->d_plan_light) (void)hipFree(h->d_plan_light);
+    if (h->d_plan_geo_heavy) (void)hipFree(h->d_plan_geo_heavy);
+    if (h->d_plan_geo_light) (void)hipFree(h->d_plan_geo_light);
     void* lp[] = {h->d_R2sh, h->d_p32, h->d_p64, h->d_w1b, h->d_w2b, h->d_adam_m, h->d_adam_v,
                   h->d_grad, h->d_loss, h->d_data, h->d_data_n, h->d_lwork};
     for (void* q : lp)

@@ -126,6 +126,8 @@ struct SweepArgs {
                            // items of the learned proposal's feature kernel
     uint32_t* plan_heavy;  // per colour: ndom_total slots of domain indices
     uint32_t* plan_light;
+    uint4* plan_geo_heavy; // beside each slot: replica, first and second cell, and
+    uint4* plan_geo_light; // the two cells' binned counts (16 bits each)
     struct LearnItem* lwork; // per colour: lwork_cap work items of the feature kernel, or null
                              // when no learned-proposal kernel runs
     uint32_t lwork_cap;

@@ -421,6 +421,7 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
     const int colour = (int)blockIdx.y;
     const uint32_t gd = blockIdx.x * 64u + threadIdx.x;
     bool valid = gd < a.ndom_total, light = false;
+    uint4 geo = make_uint4(0u, 0u, 0u, 0u);
     if (valid) {
         const uint32_t r = a.dom2rep[gd];
         const Replica& R = a.reps[r];
@@ -462,6 +463,7 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
         const int ntr_max = (a.trials + a.ion_trials) * G.ncell + ((n0 + n1) * a.site_trials + 15) / 16;
         const Pool p = pool_layout(n0, n1, G.ncell, ntr_max, R.cap, R.ncores, a.learned);
         light = nb <= a.light_nb && p.st_off <= a.pool / 4;
+        geo = make_uint4(r, G.cell0, G.ncell == 2 ? G.cell1 : G.cell0, (uint32_t)n0 | ((uint32_t)n1 << 16));
     }
     const uint64_t ml = __ballot(valid && light), mh = __ballot(valid && !light);
     const uint32_t lane = threadIdx.x;
@@ -474,8 +476,15 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
     bh = rdl0(bh);
     if (!valid) return;
     const uint64_t lt = lanemask_lt();
-    if (light) a.plan_light[(size_t)colour * a.ndom_total + bl + (uint32_t)__popcll(ml & lt)] = gd;
-    else a.plan_heavy[(size_t)colour * a.ndom_total + bh + (uint32_t)__popcll(mh & lt)] = gd;
+    if (light) {
+        const size_t slot = (size_t)colour * a.ndom_total + bl + (uint32_t)__popcll(ml & lt);
+        a.plan_light[slot] = gd;
+        a.plan_geo_light[slot] = geo;
+    } else {
+        const size_t slot = (size_t)colour * a.ndom_total + bh + (uint32_t)__popcll(mh & lt);
+        a.plan_heavy[slot] = gd;
+        a.plan_geo_heavy[slot] = geo;
+    }
 }
 
 // a particle whose state the trial changes
@@ -853,14 +862,14 @@ constexpr uint32_t CLS_MASK_SITE = 0xFu, CLS_MASK_ION = 0x7u;
 // domain, no workgroup barriers; wpd = 4: heavy domain, the whole workgroup;
 // uniform over the workgroup).
 template <typename Real, bool LEARNED, bool RELOC, bool FAST>
-__device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint4* __restrict__ pool,
+__device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint4 geo, uint4* __restrict__ pool,
                                            int pool_records, int wid, const int wpd, double (*red)[4], int (*ovf)[4])
 {
     const int nt = 64 * wpd;
     const int lane = threadIdx.x & 63;
     const int tid = wid * 64 + lane;
     const uint64_t t_start = a.trace ? wall_clock64() : 0;
-    const uint32_t r = rflu(a.dom2rep[gd]);
+    const uint32_t r = rflu(geo.x);
     const Replica& R = a.reps[r];
     const uint32_t n = R.n, cap = R.cap;
     const uint64_t s = *a.sweep;
@@ -872,11 +881,18 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     const uint4* __restrict__ core_g = R.core_x;
     const double* __restrict__ cdel_g = R.core_delta;
     const int colour = a.colour;
-    const DomGeo G = domain_geometry(R, gd - R.dom_begin, colour, a.pairing);
+    // the domain's cells and their binned counts, left by the plan kernel
+    DomGeo G;
+    G.cell0 = rflu(geo.y);
+    G.cell1 = rflu(geo.z);
+    G.ncell = G.cell1 != G.cell0 ? 2 : 1;
+    G.cc0[0] = G.cell0 % n; G.cc0[1] = (G.cell0 / n) % n; G.cc0[2] = G.cell0 / (n * n);
+    G.cc1[0] = G.cell1 % n; G.cc1[1] = (G.cell1 / n) % n; G.cc1[2] = G.cell1 / (n * n);
     const int ncell = G.ncell;
+    (void)colour;
 
-    int n0 = (int)R.cnt0[G.cell0];
-    int n1 = ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
+    int n0 = (int)(rflu(geo.w) & 0xFFFFu);
+    int n1 = (int)(rflu(geo.w) >> 16);
     const int ntr_max = (a.trials + a.ion_trials) * ncell + ((n0 + n1) * a.site_trials + 15) / 16;
     const Pool pl = pool_layout(n0, n1, ncell, ntr_max, cap, ncores, LEARNED ? 1 : 0);
     if (pl.st_off > pool_records) { // the plan and the host size pools so that this never happens
@@ -1716,9 +1732,10 @@ __device__ __forceinline__ void phase_body(const SweepArgs& a)
     const uint32_t j = heavy ? b : (b - nh) * 4u + (uint32_t)wave;
     if (!heavy && j >= nl) return;
     const int q = heavy ? a.pool : a.pool / 4;
-    const uint32_t gd = heavy ? a.plan_heavy[(size_t)colour * a.ndom_total + j]
-                              : a.plan_light[(size_t)colour * a.ndom_total + j];
-    run_domain<Real, LEARNED, RELOC, FAST>(a, gd, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0,
+    const size_t slot = (size_t)colour * a.ndom_total + j;
+    const uint32_t gd = heavy ? a.plan_heavy[slot] : a.plan_light[slot];
+    const uint4 geo = heavy ? a.plan_geo_heavy[slot] : a.plan_geo_light[slot];
+    run_domain<Real, LEARNED, RELOC, FAST>(a, gd, geo, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0,
                                            heavy ? 4 : 1, red, ovf);
 }
 
