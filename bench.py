@@ -246,8 +246,9 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=400, help="sweeps of the per-kernel event timing pass")
     ap.add_argument("--light-neighbours", type=int, default=0,
                     help="neighbour records up to which a domain runs on one wavefront (0 = library default)")
-    ap.add_argument("--autotune", type=int, default=0, metavar="SWEEPS",
-                    help="before the warm-up, time SWEEPS sweeps per launch shape and keep the fastest")
+    ap.add_argument("--autotune", type=int, default=None, metavar="SWEEPS",
+                    help="before the warm-up, time SWEEPS sweeps per launch shape and keep the fastest "
+                         "(default: 5 for the chain batch and the suspension, 0 for the pair)")
     ap.add_argument("--learned", action="store_true",
                     help="learned site proposal: collect rows from plain sweeps after the warm-up, train the "
                          "network on the GPU, then time sweeps with the learned proposal")
@@ -272,6 +273,8 @@ def main():
         return
     if args.steps is None:
         args.steps = {"pair": 10000, "chains": 1000, "suspension": 500}[args.workload]
+    if args.autotune is None:
+        args.autotune = 0 if args.workload == "pair" else 5
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
