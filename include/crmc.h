@@ -40,8 +40,8 @@
  *     by crmc_destroy.
  *   - Calls that launch work are asynchronous and ordered on the stream given
  *     in crmc_params (NULL = the default stream).  crmc_observe,
- *     crmc_get_series, crmc_get_particles, crmc_energy, crmc_read_log and
- *     crmc_destroy synchronize.
+ *     crmc_get_series, crmc_get_particles, crmc_energy, crmc_read_log,
+ *     crmc_export_state, crmc_import_state and crmc_destroy synchronize.
  *   - Errors: a negative status; crmc_last_error() describes the last one.
  *     Device-side conditions (a cell running out of capacity) are reported as
  *     CRMC_E_CAPACITY by the next synchronizing call; the state is then not
