@@ -20,7 +20,8 @@
 //                ion relocation trials compiled in.  k_phase_fast<R, M>: the
 //                same, with the trials of empty domains evaluated side by
 //                side (batches with sparse replicas).
-//   k_sweep_end  per sweep: series row, group histograms, sweep counter.
+//   k_sweep_end  per sweep: series row, group histograms, next grid shift;
+//                k_sweep_advance then advances the sweep counter.
 //   k_energy     total energy of a replica from scratch (FP64), per cell.
 #include "crmc_internal.h"
 
@@ -1760,33 +1761,37 @@ __global__ __launch_bounds__(PHASE_THREADS) __attribute__((amdgpu_waves_per_eu(4
 __global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a)
 {
     const uint64_t s = *a.sweep;
-    // one wavefront per replica, the four wavefronts taking turns
-    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    for (uint32_t r = wave; r < a.nrep; r += blockDim.x / 64u) {
-        const Replica& R = a.reps[r];
-        if (lane < 4 && R.series_cap > 0) {
-            const int64_t row = (int64_t)(s % (uint64_t)R.series_cap);
-            R.series[row * 4 + lane] = (int32_t)R.totals[lane];
-        }
-        // ionized sites per group at the start of this sweep (counted by the
-        // re-binning); the slot is cleared for the sweep after next
-        int32_t* gc = R.group_count + (s & 1u) * R.ngroups;
-        for (uint32_t g = lane; g < R.ngroups; g += 64u) {
-            R.group_hist[R.group_hist_off[g] + gc[g]] += 1;
-            gc[g] = 0;
-        }
+    // one wavefront per replica
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t r = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6);
+    if (r >= a.nrep) return;
+    const Replica& R = a.reps[r];
+    if (lane < 4 && R.series_cap > 0) {
+        const int64_t row = (int64_t)(s % (uint64_t)R.series_cap);
+        R.series[row * 4 + lane] = (int32_t)R.totals[lane];
+    }
+    // ionized sites per group at the start of this sweep (counted by the
+    // re-binning); the slot is cleared for the sweep after next
+    int32_t* gc = R.group_count + (s & 1u) * R.ngroups;
+    for (uint32_t g = lane; g < R.ngroups; g += 64u) {
+        R.group_hist[R.group_hist_off[g] + gc[g]] += 1;
+        gc[g] = 0;
     }
     // the next sweep's shift and this one's, so that its re-binning need not
     // draw them in every wavefront
-    for (uint32_t r = threadIdx.x; r < a.nrep; r += blockDim.x) {
-        SweepTab* T = a.reps[r].tab;
+    if (lane == 0) {
+        SweepTab* T = R.tab;
         uint32_t nx[3];
-        grid_shift(a.reps[r].key0, a.reps[r].key1, s + 1u, a.fixed_grid, nx);
+        grid_shift(R.key0, R.key1, s + 1u, a.fixed_grid, nx);
         for (int d = 0; d < 3; ++d) { T->prev[d] = T->o[d]; T->next[d] = nx[d]; }
         T->valid = s + 2u;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) *a.sweep = s + 1u;
+}
+
+// the sweep counter, advanced once every replica's end-of-sweep work has read it
+__global__ __launch_bounds__(64) void k_sweep_advance(SweepArgs a)
+{
+    if (threadIdx.x == 0) *a.sweep = *a.sweep + 1u;
 }
 
 // ------------------------------------------------------------------------
@@ -1915,7 +1920,8 @@ hipError_t launch_phase(const SweepArgs& a, size_t lds, hipStream_t s)
 
 hipError_t launch_sweep_end(const SweepArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sweep_end, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sweep_end, dim3((a.nrep + 3u) / 4u), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_sweep_advance, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
