@@ -199,7 +199,11 @@ SweepArgs base_args(crmc_t h)
     a.site_trials = h->p.site_trials;
     a.ion_trials = h->p.ion_trials;
     a.bin_sparse_any = 0;
-    for (const auto& r : h->reps) a.bin_sparse_any |= (int32_t)r.d.bin_sparse;
+    a.bin_dense_any = 0;
+    for (const auto& r : h->reps) {
+        a.bin_sparse_any |= (int32_t)r.d.bin_sparse;
+        a.bin_dense_any |= (int32_t)!r.d.bin_sparse;
+    }
     a.pool = h->pool;
     a.precision = h->p.precision;
     a.light_nb = h->p.light_neighbours > 0 ? h->p.light_neighbours : DEFAULT_LIGHT_NB;

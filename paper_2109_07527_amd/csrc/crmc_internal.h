@@ -119,6 +119,7 @@ struct SweepArgs {
     int32_t ion_coupling, trials, pairing, fixed_grid, site_trials;
     int32_t ion_trials; // ion relocation trials per cell of a domain, after the reaction trials
     int32_t bin_sparse_any; // some replica is re-binned one lane per cell
+    int32_t bin_dense_any;  // some replica is re-binned one wavefront per cell
     int32_t pool;      // LDS pool of a phase workgroup, in records (a light domain gets a quarter)
     int32_t precision; // 32 or 64
     int32_t light_nb;  // neighbour records up to which a domain may run on one wavefront

@@ -140,7 +140,7 @@ __device__ __forceinline__ void bin_candidates(const uint32_t* __restrict__ bnd,
 
 // One wavefront per new cell of the dense replicas; the cells of sparse
 // replicas (far fewer records than cells) are left to k_bin_sparse.  The
-// wavefront of a replica's cell 0 writes the sweep's table either way.
+// wavefront of a dense replica's cell 0 writes the sweep's table.
 __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
 {
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
@@ -150,7 +150,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     const Replica& R = a.reps[r];
     const uint32_t n = R.n, cap = R.cap;
     const uint32_t k = gcell - R.cell_begin;
-    if (R.bin_sparse && k != 0 && gcell != 0) return;
+    if (R.bin_sparse) return; // k_bin_sparse, table and counters included
     const uint64_t s = *a.sweep;
     const int cur = (int)(s & 1u), nxt = cur ^ 1;
     const uint4* __restrict__ src = R.rec[cur];
@@ -176,7 +176,6 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
         }
         if (lane < 4) R.tab->o[lane] = v; else R.tab->pairc[lane - 4] = v;
     }
-    if (R.bin_sparse) return;
 
     const uint32_t kc[3] = {k % n, (k / n) % n, k / (n * n)};
     uint32_t cand[3][3];
@@ -277,6 +276,21 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_sparse(SweepArgs a)
     uint4* __restrict__ dst = R.rec[nxt];
     uint32_t on[3], oo[3];
     bin_shifts(R, s, a.fixed_grid, on, oo);
+    // the duties of k_bin for the cells it leaves to this kernel: the sweep's
+    // plan counters (with global cell 0) and the replica's table (with its cell 0)
+    if (gcell == 0)
+        for (int i = 0; i < PLAN_N; ++i) a.plan_n[i] = 0u;
+    if (k == 0) {
+        const uint32_t M = R.h * R.h * R.h;
+        for (int d = 0; d < 3; ++d) R.tab->o[d] = on[d];
+        R.tab->o[3] = 0u;
+        for (uint32_t c = 0; c < 8u; ++c) {
+            uint32_t w[4];
+            philox4x32_10((uint32_t)s, c, 0u, TAG_PAIR, R.key0, R.key1, w);
+            const uint32_t rr = pick32(w[0], M);
+            R.tab->pairc[c] = (uint32_t)(((uint64_t)M - 1u + 2ull * M - 2ull * rr) % M);
+        }
+    }
     const uint32_t kc[3] = {k % n, (k / n) % n, k / (n * n)};
     uint32_t cand[3][3];
     int ncand[3];
@@ -1878,7 +1892,8 @@ __global__ void k_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k
 hipError_t launch_bin(const SweepArgs& a, hipStream_t s)
 {
     const uint32_t per = BIN_THREADS / 64;
-    hipLaunchKernelGGL(k_bin, dim3((a.ncell_total + per - 1) / per), dim3(BIN_THREADS), 0, s, a);
+    if (a.bin_dense_any)
+        hipLaunchKernelGGL(k_bin, dim3((a.ncell_total + per - 1) / per), dim3(BIN_THREADS), 0, s, a);
     if (a.bin_sparse_any)
         hipLaunchKernelGGL(k_bin_sparse, dim3((a.ncell_total + BIN_THREADS - 1) / BIN_THREADS), dim3(BIN_THREADS), 0,
                            s, a);
