@@ -12,6 +12,10 @@ import pytest
 from paper_2109_07527_amd import crmc
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# numpy names of the trace record's fields and their C names
+TRACE_FIELDS = [("t0", "t0"), ("t1", "t1"), ("sweep", "sweep"), ("domain", "domain"), ("colour", "colour"),
+                ("trials", "trials"), ("neighbours", "neighbours"), ("own", "own"), ("staged", "staged"),
+                ("hw_id", "hw_id")]
 STRUCTS = [("crmc_params", crmc.crmc_params), ("crmc_cond", crmc.crmc_cond), ("crmc_obs", crmc.crmc_obs),
            ("crmc_trial_rec", crmc.crmc_trial_rec), ("crmc_tune", crmc.crmc_tune)]
 
@@ -19,6 +23,9 @@ STRUCTS = [("crmc_params", crmc.crmc_params), ("crmc_cond", crmc.crmc_cond), ("c
 @pytest.mark.skipif(shutil.which("gcc") is None, reason="no host C compiler")
 def test_binding_structures_match_the_header():
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "crmc.h"', 'int main(void) {']
+    lines.append('printf("crmc_phase_trace size %zu\\n", sizeof(crmc_phase_trace));')
+    for field, c_field in TRACE_FIELDS:
+        lines.append('printf("crmc_phase_trace.%s %%zu\\n", offsetof(crmc_phase_trace, %s));' % (field, c_field))
     for name, cls in STRUCTS:
         lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (name, name))
         for field, _ in cls._fields_:
@@ -35,6 +42,9 @@ def test_binding_structures_match_the_header():
         if ln.strip():
             k, v = ln.rsplit(" ", 1)
             want[k] = int(v)
+    assert crmc.TRACE_DTYPE.itemsize == want["crmc_phase_trace size"]
+    for field, _ in TRACE_FIELDS:
+        assert crmc.TRACE_DTYPE.fields[field][1] == want["crmc_phase_trace.%s" % field], field
     for name, cls in STRUCTS:
         assert C.sizeof(cls) == want["%s size" % name], name
         for field, _ in cls._fields_:
