@@ -282,6 +282,34 @@ def test_conditions_changing_between_calls_bit_exact(case):
     assert sum(obs["accepts"]) > 0
 
 
+@pytest.mark.parametrize("case", ["chain40", "mixed"])
+def test_four_argument_sweep_bit_exact(case):
+    """crmc_sweep(pH, pKa, mu_ion, n): one condition for every replica, with
+    pI_X+ = pI_X- = mu_ion and the base pK and kappa taken from the creation
+    parameters; FP64 chain against the oracle given the same conditions."""
+    crmc = _gpu()
+    make, model, _ = CASES[case]
+    s = make()
+    pH, pKa, mu, pKb, kappa = 5.2, 4.8, cf.pIX_from_salt(1.5, 5.2), 6.3, 0.4
+    S = crmc.System(n_replicas=2, lB=model["lB"], rc=model["rc"], eps=model["eps"],
+                    ion_coupling=model["ion_coupling"], precision=64, trials_per_cell=2, seed=19, pKb=pKb,
+                    kappa=kappa)
+    for r in range(2):
+        kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"])
+        if len(s.get("core_R", [])):
+            kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
+        S.build_cells(r, **kw)
+    S.sweep(pH, pKa, mu, 10)
+    cond = _cond(pH, pKa, pKb, mu, mu, kappa)
+    for r in range(2):
+        obs = S.observe(r)
+        assert obs["status"] == 0
+        o = _oracle_for(s, model, cond, obs["n_cells"], 2, True, seed=19, replica=r)
+        ser = o.sweeps(10)
+        _same_state(S.particles(r), o.particles())
+        assert np.array_equal(S.series(r, 0, 10), ser)
+
+
 def test_replica_batch_with_different_conditions():
     """Several replicas of different size and conditions in one launch; each
     matches its own oracle."""
