@@ -168,3 +168,40 @@ def test_graph_replays_equal_eager_launches(case):
         states.append(seq)
     for a, b in zip(*states):
         assert a == b
+
+
+def test_handles_interleaved_on_one_device_are_independent():
+    """Two handles with different parameters (precision, schedule, proposal,
+    relocation, pool) sweeping in turn end in the states each reaches alone."""
+    crmc = _gpu()
+    specs = [dict(s=_pair(), precision=32, learned=False, it=2, pool=0, trials=2),
+             dict(s=_mixed(), precision=64, learned=True, it=0, pool=6000, trials=3)]
+    conds = [_cond(5.0), _cond(8.0, kappa=0.4)]
+
+    def make(sp):
+        S = crmc.System(n_replicas=2, lB=2.0, rc=6.0, eps=1.0, ion_coupling=1, precision=sp["precision"],
+                        trials_per_cell=sp["trials"], seed=23, ion_trials=sp["it"], lds_records=sp["pool"])
+        s = sp["s"]
+        for r in range(2):
+            kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"], group=s.get("group"))
+            if len(s.get("core_R", [])):
+                kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
+            S.build_cells(r, **kw)
+        if sp["learned"]:
+            S.init_proposal_weights(3)
+            S.set_proposal(1, 0.3)
+        return S
+
+    alone = []
+    for sp in specs:
+        S = make(sp)
+        for n in (5, 20, 5):
+            S.sweep_ex(conds, n)
+        alone.append(S.export_state())
+        S.close()
+    A, B = make(specs[0]), make(specs[1])
+    for n in (5, 20, 5):
+        A.sweep_ex(conds, n)
+        B.sweep_ex(conds, n)
+    assert A.export_state() == alone[0]
+    assert B.export_state() == alone[1]
