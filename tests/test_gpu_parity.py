@@ -310,6 +310,32 @@ def test_four_argument_sweep_bit_exact(case):
         assert np.array_equal(S.series(r, 0, 10), ser)
 
 
+def test_thousand_replicas_sampled_bit_exact():
+    """1000 replicas of a small system in one handle (every table indexed by
+    replica, the end-of-sweep grid over replicas): the first, a middle and the
+    last replica against the oracle, FP64."""
+    crmc = _gpu()
+    make, model, cond = CASES["mixed"]
+    s = make()
+    n_rep = 1000
+    S = crmc.System(n_replicas=n_rep, lB=model["lB"], rc=model["rc"], eps=model["eps"],
+                    ion_coupling=model["ion_coupling"], precision=64, trials_per_cell=2, seed=29)
+    kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"])
+    if len(s.get("core_R", [])):
+        kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
+    for r in range(n_rep):
+        S.build_cells(r, **kw)
+    conds = [dict(cond, pH=cond["pH"] + 0.002 * r) for r in range(n_rep)]
+    S.sweep_ex(conds, 6)
+    for r in (0, 517, n_rep - 1):
+        obs = S.observe(r)
+        assert obs["status"] == 0 and obs["sweeps"] == 6
+        o = _oracle_for(s, model, conds[r], obs["n_cells"], 2, True, seed=29, replica=r)
+        ser = o.sweeps(6)
+        _same_state(S.particles(r), o.particles())
+        assert np.array_equal(S.series(r, 0, 6), ser)
+
+
 def test_replica_batch_with_different_conditions():
     """Several replicas of different size and conditions in one launch; each
     matches its own oracle."""
