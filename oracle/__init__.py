@@ -99,6 +99,10 @@ def lib():
         L.orc_set_learned.argtypes = [vp, P(d), d, C.c_int]
         L.orc_set_learned_offsets.restype = None
         L.orc_set_learned_offsets.argtypes = [vp, d, d]
+        L.orc_load_state.restype = C.c_int
+        L.orc_load_state.argtypes = [vp, C.c_int, P(u32), P(i32), P(i32), P(i32), u64]
+        L.orc_prepare_sweep.argtypes = [vp]
+        L.orc_set_domain_filter.argtypes = [vp, C.c_int, P(i32)]
         L.orc_features_of_cell_sites.restype = C.c_int
         L.orc_features_of_cell_sites.argtypes = [vp, C.c_int, C.c_int, P(i32), P(d)]
         _lib = L
@@ -225,6 +229,37 @@ class Oracle:
         self._L.orc_set_particles(self.h, n, _ptr(X, C.c_uint32), _ptr(kind, C.c_int32),
                                   None if ch is None else _ptr(ch, C.c_int32),
                                   None if sd is None else _ptr(sd, C.c_int32))
+
+    def load_state(self, xyz, kind, charged, sid, sweep):
+        """Test aid: continue a chain another program ran.  Fixed-point
+        positions, kinds, charged flags and site ids in that program's
+        particle order (which the next sweep's stable binning starts from), at
+        the start of sweep `sweep`.  The running energy restarts from a
+        brute-force sum and the move counters from zero; no arithmetic
+        changes.  Call set_cores first when the system has cores."""
+        kind = np.ascontiguousarray(kind, dtype=np.int32)
+        n = kind.size
+        X = np.ascontiguousarray(np.asarray(xyz, dtype=np.uint32).reshape(-1))
+        ch = np.ascontiguousarray(charged, dtype=np.int32)
+        sd = np.ascontiguousarray(sid, dtype=np.int32)
+        self._L.orc_load_state(self.h, n, _ptr(X, C.c_uint32), _ptr(kind, C.c_int32), _ptr(ch, C.c_int32),
+                               _ptr(sd, C.c_int32), int(sweep))
+
+    def prepare_sweep(self):
+        """Test aid: bin into the current sweep's shifted grid without
+        running trials (cell_site_features then reads that grid)."""
+        self._L.orc_prepare_sweep(self.h)
+
+    def set_domain_filter(self, first_cells):
+        """Test aid: later sweeps run only the listed domains (first cell of
+        each) of their first colour phase and skip the other phases; None
+        turns it off.  Domains of one colour do not interact, so the listed
+        domains' trials are exactly those of the full sweep."""
+        if first_cells is None:
+            self._L.orc_set_domain_filter(self.h, -1, None)
+            return
+        a = np.ascontiguousarray(first_cells, dtype=np.int32)
+        self._L.orc_set_domain_filter(self.h, a.size, _ptr(a, C.c_int32))
 
     def set_cores(self, xyz, radius):
         radius = np.ascontiguousarray(radius, dtype=np.float64)

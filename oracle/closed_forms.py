@@ -19,6 +19,8 @@ rho0*NA the reference number density (rho0 = 1 M), V the box volume.
   for fixed site positions with site-site screened Coulomb and ideal ions.
 * ``one_site_ion_probability`` - a single acid site with an interacting
   counterion in the dilute limit (quadrature of the site-ion Boltzmann factor).
+* ``salt_pair_ratio``    - a box with no ionizable groups and interacting free
+  ions: the exact ratio of the weights of the one-pair and the empty state.
 """
 from __future__ import annotations
 
@@ -163,6 +165,46 @@ def enumerate_sites(X, kinds, L, lB, kappa, rc, pH, pKa, pKb, pIXp, pIXm, rho0NA
     nA = int((np.array(kinds) == 1).sum())
     P = np.bincount(nAm, weights=w, minlength=nA + 1)
     return P, float((nAm * w).sum() / max(nA, 1)), (states * w[:, None]).sum(0)
+
+
+def _attractive_pair_J(L, lB, kappa, rc, eps):
+    """J = V + 4 pi int_0^rc r^2 (exp(-u(r)) - 1) dr for a pair of opposite
+    unit charges: u = -lB exp(-kappa r)/r below rc (truncated) plus the
+    shifted WCA below 2^(1/6) when eps > 0, infinite below 1/2 (the hard core
+    of the excluded volume)."""
+    V = L ** 3
+
+    def u(r):
+        e = -lB * math.exp(-kappa * r) / r if lB else 0.0
+        if eps > 0.0 and r < 2.0 ** (1.0 / 6.0):
+            e += 4.0 * eps * (r ** -12 - r ** -6) + eps
+        return e
+
+    def integrand(r):
+        if eps > 0.0 and r < 0.5:
+            return -r * r
+        return r * r * (math.exp(-u(r)) - 1.0)
+
+    val = 0.0
+    edges = [0.0, 0.5, 2.0 ** (1.0 / 6.0), rc]
+    for a, b in zip(edges[:-1], edges[1:]):
+        val += integrate.quad(integrand, a, b, epsabs=1e-13, epsrel=1e-12, limit=200)[0]
+    return V + 4.0 * math.pi * val
+
+
+def salt_pair_ratio(L, lB, kappa, rc, pIXp, pIXm, rho0NA, eps=1.0):
+    """P(one X+ X- pair) / P(no free ion) in a periodic box without ionizable
+    groups, with interacting free ions.
+
+    Summing eq. (QQ) over the positions of one cation and one anion gives the
+    weight (a b / V^2) int int exp(-u(|r1 - r2|)) dr1 dr2 = a b J / V with
+    a = rho0 NA V 10^-pIX+, b likewise with pIX-, and J the pair integral of
+    ``_attractive_pair_J`` (minimum image, rc < L/2); the empty box has weight
+    1.  The ratio is exact: states with more pairs do not enter it."""
+    V = L ** 3
+    a = rho0NA * V * 10.0 ** (-pIXp)
+    b = rho0NA * V * 10.0 ** (-pIXm)
+    return a * b * _attractive_pair_J(L, lB, kappa, rc, eps) / V
 
 
 def one_site_ion_probability(L, lB, kappa, rc, pH, pKa, pIX, rho0NA, eps=1.0):

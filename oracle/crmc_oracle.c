@@ -60,8 +60,12 @@
  * re-inserted at a point drawn like an insertion of its sign, accepted with
  * min(1, (V_new / V_old) exp(-dU)) (eq. accrat for that proposal).
  *
- * A trial limit (a test aid) stops a run after its first n trials in
- * processing order; it changes no arithmetic.
+ * Test aids that change no arithmetic: a trial limit stops a run after its
+ * first n trials in processing order; a state can be loaded in a given
+ * particle order at a given sweep index (to continue a chain that another
+ * program ran); the grid of the current sweep can be binned without running
+ * trials (to read site features); a domain filter runs only chosen domains of
+ * the first colour phase of a sweep.
  *
  * Pinned by the tests: closed forms (ideal ions, salt-only box, high-salt
  * limit), the exact enumeration of a 12-site ring, the one-site quadrature,
@@ -177,6 +181,12 @@ typedef struct {
        (counted from the last orc_set_trial_limit, in processing order) are
        skipped; they are not logged and change nothing */
     int64_t trial_limit, trials_run;
+    /* test aid: when dom_filter_n >= 0, a sweep runs only the domains of its
+       first colour phase whose first cell is listed (every domain of one
+       colour is independent of the others, so their trials are exactly those
+       of the full sweep) and skips the other seven phases */
+    int dom_filter_n;
+    int32_t* dom_filter;
     /* learned proposal */
     int learned;
     double lp_eps;
@@ -363,6 +373,7 @@ orc_sys* orc_create(double L, int n_cells, double lB, double kappa, double rc, d
     S->key[1] = (uint32_t)(seed >> 32) ^ replica;
     S->trials = 1;
     S->trial_limit = -1;
+    S->dom_filter_n = -1;
     S->ncells = n_cells * n_cells * n_cells;
     S->cells = (orc_list*)calloc((size_t)S->ncells, sizeof(orc_list));
     return S;
@@ -373,6 +384,7 @@ void orc_destroy(orc_sys* S)
     if (!S) return;
     for (int c = 0; c < S->ncells; ++c) free(S->cells[c].p);
     free(S->cells); free(S->flat); free(S->P); free(S->core_x); free(S->core_delta);
+    free(S->dom_filter);
     free(S->lp_par); free(S->lp_phat);
     free(S);
 }
@@ -653,6 +665,41 @@ int orc_set_particles(orc_sys* S, int np, const uint32_t* xyz, const int32_t* ki
     S->E = orc_energy(S);
     S->sweep = 0;
     S->paper_trial = 0;
+    memset(S->attempts, 0, sizeof S->attempts);
+    memset(S->accepts, 0, sizeof S->accepts);
+    return 0;
+}
+
+/* Test aid: the state of a chain that another program ran, at the start of
+   sweep `sweep`: particles in the given order, which becomes the global order
+   the next sweep's stable binning starts from (the order a sweep leaves is
+   cell order of its grid, then list order inside each cell).  The running
+   energy restarts from a brute-force sum and the move counters from zero.
+   Nothing else changes: the random numbers are counter based, so the next
+   sweep draws exactly the words the other program's sweep drew. */
+int orc_load_state(orc_sys* S, int np, const uint32_t* xyz, const int32_t* kind, const int32_t* charged,
+                   const int32_t* sid, uint64_t sweep)
+{
+    ensure_cap(S, np > 0 ? np : 1);
+    S->np = np;
+    int maxsid = -1;
+    for (int i = 0; i < np; ++i) {
+        orc_particle* p = &S->P[i];
+        p->x[0] = xyz[3 * i]; p->x[1] = xyz[3 * i + 1]; p->x[2] = xyz[3 * i + 2];
+        p->kind = kind[i];
+        p->charged = is_ion(kind[i]) ? 1 : charged[i];
+        p->sid = is_ion(kind[i]) ? -1 : sid[i];
+        if (p->sid > maxsid) maxsid = p->sid;
+    }
+    if (maxsid + 1 > S->lp_nsites || !S->lp_phat) {
+        free(S->lp_phat);
+        S->lp_nsites = maxsid + 1;
+        S->lp_phat = (double*)calloc((size_t)(maxsid + 2), sizeof(double));
+    }
+    S->E = orc_energy(S);
+    S->sweep = sweep;
+    S->paper_trial = 0;
+    S->reloc_att = S->reloc_acc = 0;
     memset(S->attempts, 0, sizeof S->attempts);
     memset(S->accepts, 0, sizeof S->accepts);
     return 0;
@@ -1143,6 +1190,38 @@ static void set_cell_region(const orc_sys* S, orc_dom* D, int j, int c, const ui
     D->cell[j] = c;
 }
 
+/* Test aid: bin the particles into the shifted grid of the current sweep
+   (the first step of a sweep) without running trials or advancing, so that
+   orc_features_of_cell_sites reads the cells the sweep's first phase sees. */
+void orc_prepare_sweep(orc_sys* S)
+{
+    uint32_t o[3];
+    orc_shift(S, S->sweep, o);
+    bin_into_cells(S, o);
+}
+
+/* Test aid: n >= 0 restricts the next sweeps to the listed domains (by their
+   first cell) of the first colour phase; n < 0 turns the filter off. */
+void orc_set_domain_filter(orc_sys* S, int n, const int32_t* first_cells)
+{
+    free(S->dom_filter);
+    S->dom_filter = NULL;
+    S->dom_filter_n = n;
+    if (n > 0) {
+        S->dom_filter = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+        memcpy(S->dom_filter, first_cells, sizeof(int32_t) * (size_t)n);
+    }
+}
+
+static int domain_selected(const orc_sys* S, int colour, int first_cell)
+{
+    if (S->dom_filter_n < 0) return 1;
+    if (colour != 0) return 0;
+    for (int i = 0; i < S->dom_filter_n; ++i)
+        if (S->dom_filter[i] == first_cell) return 1;
+    return 0;
+}
+
 static void one_sweep(orc_sys* S, int32_t* series)
 {
     int n = S->n, h = n / 2;
@@ -1167,6 +1246,7 @@ static void one_sweep(orc_sys* S, int32_t* series)
                 int c = (2 * i + px) + n * ((2 * jj + py) + n * (2 * kk + pz));
                 set_cell_region(S, &D, j, c, o, lnZ0 + lnk);
             }
+            if (!domain_selected(S, colour, D.cell[0])) continue;
             /* static move set and trial count: the domain's site content does
                not depend on the state */
             int has_acid = 0, has_base = 0, nsites = 0;

@@ -422,3 +422,141 @@ def test_site_weighted_schedule_ring_enumeration():
     ser = o.sweeps(3000)
     _within(ser[:, 0] / 12.0, ex)
     _hist_within(ser[len(ser) // 10:, 0], P)
+
+
+def _pair_ratio(n):
+    """P(n = 1) / P(n = 0) of a series of ion counts, with its standard error
+    (delta method on i1 - r i0, which carries the covariance of the two
+    indicator means and their autocorrelation)."""
+    i1 = (n == 1).astype(float)
+    i0 = (n == 0).astype(float)
+    r = i1.mean() / i0.mean()
+    _, se, _ = mean_se(i1 - r * i0)
+    return r, se / i0.mean()
+
+
+@pytest.mark.parametrize("mode", ["paper", "cell"])
+def test_salt_pair_with_interacting_ions(mode):
+    """Ion-ion pin: a box with no ionizable groups, strongly coupled free ions
+    (lB = 8).  The ratio of the weights of the one-pair state and the empty
+    box is exactly a b J / V (J the X+ X- pair integral by quadrature), at any
+    salt level; with ideal ions it would be a b.  Both schedules (the cell
+    schedule with relocation trials, which mix the ions inside a domain)."""
+    L, rc, lB, kappa, pIX = 12.0, 3.0, 8.0, 0.5, 1.668
+    ex = cf.salt_pair_ratio(L, lB, kappa, rc, pIX, pIX, RHO)
+    ideal = cf.salt_pair_ratio(L, 0.0, kappa, rc, pIX, pIX, RHO, eps=0.0)
+    o = oracle.Oracle(L, 4, lB, kappa, rc, eps=1.0, seed=71)
+    o.set_conditions(7.0, 4.5, 5.0, pIX, pIX)
+    o.set_particles(np.zeros((0, 3)), np.zeros(0, dtype=np.int32))
+    if mode == "paper":
+        s = o.paper_trials(12_000_000, 20)
+    else:
+        o.set_schedule(4, ion_trials=4)
+        s = o.sweeps(80_000)
+    r, se = _pair_ratio(s[len(s) // 10:, 2])
+    assert abs(r - ex) < 3.0 * se, (r, ex, se)
+    assert abs(r - ideal) > 5.0 * se, (r, ideal, se)  # the pair interaction is resolved
+
+
+def test_salt_pair_integral_against_sampling():
+    """The pair integral of the closed form against a plain Monte Carlo
+    estimate of int exp(-u) over the box (uniform points, minimum image)."""
+    L, rc, lB, kappa = 12.0, 3.0, 8.0, 0.5
+    J = cf._attractive_pair_J(L, lB, kappa, rc, 1.0)
+    rng = np.random.default_rng(4)
+    # importance split: the sphere r < rc sampled densely, the rest contributes V - 4/3 pi rc^3 exactly
+    n = 2_000_000
+    r = rc * rng.random(n) ** (1.0 / 3.0)
+    u = np.where(r < 0.5, np.inf, -lB * np.exp(-kappa * r) / r)
+    wca = r < 2.0 ** (1.0 / 6.0)
+    with np.errstate(over="ignore", divide="ignore", invalid="ignore"):
+        u = np.where(wca & (r >= 0.5), u + 4.0 * (r ** -12 - r ** -6) + 1.0, u)
+        f = np.exp(-u)
+    vs = 4.0 / 3.0 * np.pi * rc ** 3
+    est = L ** 3 - vs + vs * f.mean()
+    se = vs * f.std() / np.sqrt(n)
+    assert abs(est - J) < 4.0 * se, (est, J, se)
+
+
+# ------------------------------------------------------- test aids ----
+def _colour_of(cell, n):
+    cx, cy, cz = cell % n, (cell // n) % n, cell // (n * n)
+    return (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2)
+
+
+@pytest.mark.parametrize("learned,ion_trials", [(False, 0), (True, 1)])
+def test_loaded_state_continues_the_chain(learned, ion_trials):
+    """A chain stopped after 5 sweeps, loaded in its particle order into a new
+    oracle at sweep 5, continues exactly as the uninterrupted chain: same log
+    of trials, same particles in the same order, same series."""
+    rng = np.random.default_rng(2)
+    par = rng.normal(0.0, 0.2, oracle.mlp_params())
+
+    def make():
+        o = _mixed_system(seed=3)
+        o.set_schedule(2, ion_trials=ion_trials)
+        if learned:
+            o.set_learned(par, eps=0.3)
+        return o
+
+    full = make()
+    full.sweeps(5)
+    X, k, c, sid = full.particles()
+    e5 = full.energy()
+    full.enable_log(200_000)
+    ref_series = full.sweeps(4)
+    ref_log = full.log()
+    cont = make()
+    cont.load_state(X, k, c, sid, 5)
+    assert cont.sweep_index() == 5
+    assert cont.running_energy() == pytest.approx(e5, abs=1e-9)
+    cont.enable_log(200_000)
+    ser = cont.sweeps(4)
+    assert np.array_equal(ser, ref_series)
+    assert cont.log().tobytes() == ref_log.tobytes()
+    for a, b in zip(cont.particles(), full.particles()):
+        assert np.array_equal(a, b)
+    assert cont.running_energy() == pytest.approx(full.running_energy(), abs=1e-9)
+
+
+def test_domain_filter_runs_chosen_first_phase_domains():
+    """The filter runs exactly the chosen domains of the first colour phase:
+    their trials are those of the full sweep, and nothing else runs."""
+    full = _mixed_system(seed=5)
+    part = _mixed_system(seed=5)
+    for o in (full, part):
+        o.set_schedule(3)
+        o.sweeps(2)
+        o.enable_log(100_000)
+    full.sweeps(1)
+    log = full.log()
+    n = 4
+    first0 = sorted({int(c) for c in log["cell"] if _colour_of(int(c), n) == 0})
+    assert len(first0) >= 2
+    pick = first0[::2]
+    part.set_domain_filter(pick)
+    part.sweeps(1)
+    got = part.log()
+    want = log[np.isin(log["cell"], pick)]
+    assert len(got) == len(want) > 0
+    assert got.tobytes() == want.tobytes()
+    part.set_domain_filter(None)
+
+
+def test_prepare_sweep_bins_the_current_grid():
+    """After prepare_sweep the cell lists are the stable binning of the
+    current sweep's shifted grid: every site listed in a cell lies in it."""
+    o = _mixed_system(seed=7)
+    o.set_schedule(2)
+    o.set_learned(np.zeros(oracle.mlp_params()), eps=1.0)
+    o.sweeps(3)
+    X, k, c, sid = o.particles()
+    o.prepare_sweep()
+    sh = o.shift(3)
+    n = 4
+    cell = (((X.astype(np.uint64) - sh.astype(np.uint64)) % 2 ** 32) * n) >> 32
+    lin = cell[:, 0] + n * (cell[:, 1] + n * cell[:, 2])
+    site = (k == 1) | (k == 2)
+    for cc in range(n ** 3):
+        ids, _ = o.cell_site_features(cc)
+        assert sorted(ids.tolist()) == sorted(sid[site & (lin == cc)].tolist())
