@@ -322,6 +322,21 @@ int crmc_training_rows(crmc_t h, int64_t* n);
 int crmc_read_training(crmc_t h, int64_t first, int64_t count, float* out);
 int crmc_train(crmc_t h, int32_t epochs, int32_t batch, double lr, uint64_t seed, double* last_loss);
 int crmc_mlp_forward(crmc_t h, const float* X, int32_t n, float* logits);
+/*
+ * crmc_load_training: replaces the training rows with n host rows (n x 33,
+ *   32 features then the 0/1 label) and stops collection; crmc_train then
+ *   trains on them.  Synchronizes.  CRMC_E_ARG for n < 0 or NULL rows.
+ * crmc_record_features: on = 1 keeps, per site, the 32 features the learned
+ *   proposal's kernel evaluated in the site's colour phase of the latest
+ *   sweep in which that kernel ran (proposal on, or rows being collected);
+ *   crmc_get_site_features copies them (n >= 32 x the replica's particle
+ *   count, row i for input particle i, zero for ions and before any
+ *   evaluation).  A check of the features; it costs a store of 128 bytes per
+ *   site and phase while on.  CRMC_E_STATE when recording is off.
+ */
+int crmc_load_training(crmc_t h, const float* rows, int64_t n);
+int crmc_record_features(crmc_t h, int32_t on);
+int crmc_get_site_features(crmc_t h, int32_t replica, float* out, int64_t n);
 int crmc_mlp_gradient(crmc_t h, const float* rows, int32_t n, float* grad, double* loss);
 
 /*

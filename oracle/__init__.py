@@ -100,7 +100,7 @@ def lib():
         L.orc_set_learned_offsets.restype = None
         L.orc_set_learned_offsets.argtypes = [vp, d, d]
         L.orc_load_state.restype = C.c_int
-        L.orc_load_state.argtypes = [vp, C.c_int, P(u32), P(i32), P(i32), P(i32), u64]
+        L.orc_load_state.argtypes = [vp, C.c_int, P(u32), P(i32), P(i32), P(i32), u64, C.c_int]
         L.orc_prepare_sweep.argtypes = [vp]
         L.orc_set_domain_filter.argtypes = [vp, C.c_int, P(i32)]
         L.orc_features_of_cell_sites.restype = C.c_int
@@ -230,12 +230,13 @@ class Oracle:
                                   None if ch is None else _ptr(ch, C.c_int32),
                                   None if sd is None else _ptr(sd, C.c_int32))
 
-    def load_state(self, xyz, kind, charged, sid, sweep):
+    def load_state(self, xyz, kind, charged, sid, sweep, energy=True):
         """Test aid: continue a chain another program ran.  Fixed-point
         positions, kinds, charged flags and site ids in that program's
         particle order (which the next sweep's stable binning starts from), at
         the start of sweep `sweep`.  The running energy restarts from a
-        brute-force sum and the move counters from zero; no arithmetic
+        brute-force sum (NaN with energy=False: the sum is quadratic in the
+        particle count) and the move counters from zero; no arithmetic
         changes.  Call set_cores first when the system has cores."""
         kind = np.ascontiguousarray(kind, dtype=np.int32)
         n = kind.size
@@ -243,7 +244,7 @@ class Oracle:
         ch = np.ascontiguousarray(charged, dtype=np.int32)
         sd = np.ascontiguousarray(sid, dtype=np.int32)
         self._L.orc_load_state(self.h, n, _ptr(X, C.c_uint32), _ptr(kind, C.c_int32), _ptr(ch, C.c_int32),
-                               _ptr(sd, C.c_int32), int(sweep))
+                               _ptr(sd, C.c_int32), int(sweep), int(bool(energy)))
 
     def prepare_sweep(self):
         """Test aid: bin into the current sweep's shifted grid without

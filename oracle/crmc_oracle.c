@@ -674,11 +674,12 @@ int orc_set_particles(orc_sys* S, int np, const uint32_t* xyz, const int32_t* ki
    sweep `sweep`: particles in the given order, which becomes the global order
    the next sweep's stable binning starts from (the order a sweep leaves is
    cell order of its grid, then list order inside each cell).  The running
-   energy restarts from a brute-force sum and the move counters from zero.
-   Nothing else changes: the random numbers are counter based, so the next
+   energy restarts from a brute-force sum (or from NaN when with_energy is 0:
+   that sum is quadratic in the particle count, and the local energy changes
+   do not need it) and the move counters from zero.  Nothing else changes: the random numbers are counter based, so the next
    sweep draws exactly the words the other program's sweep drew. */
 int orc_load_state(orc_sys* S, int np, const uint32_t* xyz, const int32_t* kind, const int32_t* charged,
-                   const int32_t* sid, uint64_t sweep)
+                   const int32_t* sid, uint64_t sweep, int with_energy)
 {
     ensure_cap(S, np > 0 ? np : 1);
     S->np = np;
@@ -696,7 +697,7 @@ int orc_load_state(orc_sys* S, int np, const uint32_t* xyz, const int32_t* kind,
         S->lp_nsites = maxsid + 1;
         S->lp_phat = (double*)calloc((size_t)(maxsid + 2), sizeof(double));
     }
-    S->E = orc_energy(S);
+    S->E = with_energy ? orc_energy(S) : NAN;
     S->sweep = sweep;
     S->paper_trial = 0;
     S->reloc_att = S->reloc_acc = 0;

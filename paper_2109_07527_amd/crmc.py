@@ -102,6 +102,9 @@ def load():
         "crmc_read_training": (C.c_int, [vp, i64, i64, P(C.c_float)]),
         "crmc_train": (C.c_int, [vp, i32, i32, d, u64, P(d)]),
         "crmc_mlp_forward": (C.c_int, [vp, P(C.c_float), i32, P(C.c_float)]),
+        "crmc_load_training": (C.c_int, [vp, P(C.c_float), i64]),
+        "crmc_record_features": (C.c_int, [vp, i32]),
+        "crmc_get_site_features": (C.c_int, [vp, i32, P(C.c_float), i64]),
         "crmc_mlp_gradient": (C.c_int, [vp, P(C.c_float), i32, P(C.c_float), P(d)]),
         "crmc_observe": (C.c_int, [vp, i32, P(crmc_obs)]),
         "crmc_get_series": (C.c_int, [vp, i32, i64, i64, P(i32)]),
@@ -344,6 +347,23 @@ def crmc_read_training(h, first=0, count=None):
     return out
 
 
+def crmc_load_training(h, rows):
+    rows = np.ascontiguousarray(rows, dtype=np.float32).reshape(-1, 33)
+    return _check(h, load().crmc_load_training(h, _p(rows, C.c_float), rows.shape[0]))
+
+
+def crmc_record_features(h, on):
+    return _check(h, load().crmc_record_features(h, int(bool(on))))
+
+
+def crmc_get_site_features(h, replica):
+    n = C.c_int64(0)
+    _check(h, load().crmc_get_occupancy(h, int(replica), 0, None, C.byref(n)))  # particle count
+    out = np.zeros((max(n.value, 1), 32), dtype=np.float32)
+    _check(h, load().crmc_get_site_features(h, int(replica), _p(out, C.c_float), out.size))
+    return out[:n.value]
+
+
 def crmc_train(h, epochs, batch=256, lr=1e-3, seed=1):
     loss = C.c_double()
     _check(h, load().crmc_train(h, int(epochs), int(batch), float(lr), int(seed), C.byref(loss)))
@@ -508,6 +528,15 @@ class System:
 
     def read_training(self, first=0, count=None):
         return crmc_read_training(self.h, first, count)
+
+    def load_training(self, rows):
+        return crmc_load_training(self.h, rows)
+
+    def record_features(self, on=True):
+        return crmc_record_features(self.h, on)
+
+    def site_features(self, replica):
+        return crmc_get_site_features(self.h, replica)
 
     def train(self, epochs, batch=256, lr=1e-3, seed=1):
         return crmc_train(self.h, epochs, batch, lr, seed)

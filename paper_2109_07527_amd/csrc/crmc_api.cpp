@@ -99,7 +99,9 @@ struct crmc_s {
     hipStream_t gstream = nullptr;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    uint64_t gkey = 0;
+    std::vector<uint8_t> gargs; // launch arguments the captured graphs were recorded with
+    // recorded per-site features (checks of the learned proposal)
+    bool record_feat = false;
 };
 
 namespace {
@@ -156,7 +158,7 @@ void free_replica(HostReplica& r)
     Replica& d = r.d;
     void* ptrs[] = {d.rec[0], d.rec[1], d.cnt[0], d.cnt[1], d.cnt0, d.e_acc, d.occupancy, d.site_group,
                     d.group_count, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
-                    d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab, d.phat, d.nsc};
+                    d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab, d.phat, d.nsc, d.feat};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     d = Replica{};
@@ -175,7 +177,8 @@ void set_conditions(crmc_t h, HostReplica& r, const crmc_cond& c)
 
 SweepArgs base_args(crmc_t h)
 {
-    SweepArgs a{};
+    SweepArgs a;
+    std::memset(&a, 0, sizeof a);
     a.reps = h->d_reps;
     a.cell2rep = h->d_cell2rep;
     a.dom2rep = h->d_dom2rep;
@@ -350,7 +353,8 @@ int ensure_params(crmc_t h)
 
 LearnArgs learn_args(crmc_t h)
 {
-    LearnArgs g{};
+    LearnArgs g;
+    std::memset(&g, 0, sizeof g);
     // one workgroup per compute unit (the kernel holds the network in LDS)
     g.grid = (uint32_t)std::max(h->ncu, 1);
     g.R2sh = h->d_R2sh;
@@ -460,20 +464,19 @@ void drop_graphs(crmc_t h)
 // recaptured when anything baked into its launch arguments changes.
 int sweeps_by_graph(crmc_t h, const SweepArgs& a0, size_t lds, int64_t n, bool use_learn, const LearnArgs& lg)
 {
-    const uint64_t key = (uint64_t)(uintptr_t)a0.log * 1000003ull ^ (uint64_t)a0.log_cap * 7919ull ^
-                         (uint64_t)lds * 31ull ^ (uint64_t)(uintptr_t)a0.lntab ^
-                         (uint64_t)(uintptr_t)a0.trace * 65537ull ^ (uint64_t)a0.trace_cap * 131ull ^
-                         (uint64_t)(uintptr_t)a0.plan_heavy * 17ull ^ (uint64_t)(uintptr_t)a0.plan_light * 257ull ^
-                         (uint64_t)(uintptr_t)a0.plan_geo_heavy * 37ull ^ (uint64_t)(uintptr_t)a0.plan_geo_light * 41ull ^
-                         (uint64_t)(uintptr_t)a0.plan_n * 4099ull ^ (uint64_t)a0.light_nb * 1000033ull ^
-                         (uint64_t)a0.pool * 7777ull ^ (uint64_t)a0.learned * 99991ull ^
-                         (uint64_t)(a0.learn_eps * 1e12) * 13ull ^ (uint64_t)use_learn * 424243ull ^
-                         (uint64_t)(uintptr_t)lg.data * 3ull ^ (uint64_t)lg.grid * 5ull ^
-                         (uint64_t)(uintptr_t)a0.lwork * 11ull ^ (uint64_t)a0.lwork_cap * 29ull ^
-                         (uint64_t)(uintptr_t)a0.reps * 101ull;
-    if (key != h->gkey) {
+    // A captured graph holds its kernels' arguments by value.  It is replayed
+    // only while every argument (pointers, capacities, switches, launch
+    // shape) is byte for byte the one it was captured with; anything else
+    // (a buffer reallocated, even at the same address with another capacity)
+    // recaptures.
+    std::vector<uint8_t> key(sizeof(SweepArgs) + sizeof(LearnArgs) + sizeof(size_t) + 1, 0);
+    std::memcpy(key.data(), &a0, sizeof(SweepArgs));
+    if (use_learn) std::memcpy(key.data() + sizeof(SweepArgs), &lg, sizeof(LearnArgs));
+    std::memcpy(key.data() + sizeof(SweepArgs) + sizeof(LearnArgs), &lds, sizeof(size_t));
+    key.back() = use_learn ? 1 : 0;
+    if (key != h->gargs) {
         drop_graphs(h);
-        h->gkey = key;
+        h->gargs.swap(key);
     }
     if (!h->gstream) HIP_TRY(h, hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
     if (!h->ev_in) HIP_TRY(h, hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming));
@@ -868,6 +871,10 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     HIP_TRY(h, dalloc(&d.series, (size_t)series_cap * 4));
     HIP_TRY(h, dalloc(&d.phat, (size_t)std::max(n, 1)));
     HIP_TRY(h, hipMemset(d.phat, 0, (size_t)std::max(n, 1) * sizeof(double)));
+    if (h->record_feat) {
+        HIP_TRY(h, dalloc(&d.feat, (size_t)std::max(n, 1) * MLP_IN));
+        HIP_TRY(h, hipMemset(d.feat, 0, (size_t)std::max(n, 1) * MLP_IN * sizeof(float)));
+    }
     HIP_TRY(h, dalloc(&d.nsc, ncells));
     HIP_TRY(h, hipMemset(d.nsc, 0, ncells * sizeof(uint32_t)));
     HIP_TRY(h, hipMemcpy(d.rec[0], cells.data(), nrec * sizeof(uint4), hipMemcpyHostToDevice));
@@ -982,8 +989,10 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
         r.e0_kappa = r.d.kappa;
     }
     // the pool of a heavy domain must hold both cells' lists (2 cap), the ln k
-    // table (2 cap + 2 doubles) and up to 64 cores with their Deltas (96 records)
-    if (h->pool < (int)(3 * maxcap + 128)) h->pool = (int)(3 * maxcap + 128);
+    // table (2 cap + 2 doubles), up to 64 cores with their Deltas (96 records)
+    // and, with the learned proposal, a double per list slot (cap records)
+    const int pool_floor = (int)((h->learned ? 4 : 3) * maxcap + 128);
+    if (h->pool < pool_floor) h->pool = pool_floor;
     h->pool = (h->pool + 3) & ~3; // four equal quarters for light domains
     const size_t lds = (size_t)h->pool * sizeof(uint4);
     int dev = 0, maxlds = 0;
@@ -1050,7 +1059,7 @@ int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_can
     int dev = 0, maxlds = 0;
     HIP_TRY(h, hipGetDevice(&dev));
     HIP_TRY(h, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const int pool_min = (int)(3 * maxcap + 128);
+    const int pool_min = (int)((h->learned ? 4 : 3) * maxcap + 128);
     const int pool_max = (maxlds - 1024) / (int)sizeof(uint4);
     const int light_c[] = {256, 512, 768, 1024, 1536};
     const int pool_c[] = {pool_min, 3072, 4096, 6144, 8192};
@@ -1212,6 +1221,49 @@ int crmc_read_training(crmc_t h, int64_t first, int64_t count, float* out)
     if (!out || first < 0 || count < 0 || first + count > n) return fail(h, CRMC_E_ARG, "rows out of range");
     HIP_TRY(h, hipMemcpy(out, h->d_data + (size_t)first * (MLP_IN + 1), (size_t)count * (MLP_IN + 1) * sizeof(float),
                          hipMemcpyDeviceToHost));
+    return CRMC_OK;
+}
+
+int crmc_load_training(crmc_t h, const float* rows, int64_t n)
+{
+    if (!h || n < 0 || n > (int64_t)1 << 28 || (n > 0 && !rows)) return fail(h, CRMC_E_ARG, "invalid rows");
+    int rc = crmc_collect_training(h, 0);
+    if (rc) return rc;
+    if (n == 0) return CRMC_OK;
+    HIP_TRY(h, dalloc(&h->d_data, (size_t)n * (MLP_IN + 1)));
+    h->data_cap = n;
+    HIP_TRY(h, hipMemcpy(h->d_data, rows, (size_t)n * (MLP_IN + 1) * sizeof(float), hipMemcpyHostToDevice));
+    const unsigned long long nn = (unsigned long long)n;
+    HIP_TRY(h, hipMemcpy(h->d_data_n, &nn, sizeof nn, hipMemcpyHostToDevice));
+    return CRMC_OK;
+}
+
+int crmc_record_features(crmc_t h, int32_t on)
+{
+    if (!h || (on != 0 && on != 1)) return fail(h, CRMC_E_ARG, "invalid switch");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    for (auto& r : h->reps) {
+        if (r.d.feat) (void)hipFree(r.d.feat);
+        r.d.feat = nullptr;
+        if (!on || !r.built) continue;
+        const size_t m = (size_t)std::max<uint32_t>(r.nsites, 1) * MLP_IN;
+        HIP_TRY(h, dalloc(&r.d.feat, m));
+        HIP_TRY(h, hipMemset(r.d.feat, 0, m * sizeof(float)));
+    }
+    h->record_feat = on != 0;
+    return CRMC_OK;
+}
+
+int crmc_get_site_features(crmc_t h, int32_t replica, float* out, int64_t n)
+{
+    if (!h || !out || replica < 0 || replica >= (int32_t)h->reps.size())
+        return fail(h, CRMC_E_ARG, "invalid replica or buffer");
+    const HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    if (!r.d.feat) return fail(h, CRMC_E_STATE, "feature recording is off");
+    if (n < (int64_t)r.nsites * MLP_IN) return fail(h, CRMC_E_ARG, "buffer smaller than 32 values per particle");
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpy(out, r.d.feat, (size_t)r.nsites * MLP_IN * sizeof(float), hipMemcpyDeviceToHost));
     return CRMC_OK;
 }
 

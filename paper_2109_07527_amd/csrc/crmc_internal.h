@@ -78,6 +78,7 @@ struct Replica {
     uint32_t* nsc;           // per cell: acid and base sites as binned at the start of the sweep
     uint32_t bin_sparse;     // 1: re-binned one lane per cell (far fewer particles than cells)
     double* phat;            // per site: network output of the current phase (learned proposal)
+    float* feat;             // per site: its 32 features as last evaluated (only while recording; else null)
     double lp_off[2];        // logit offsets of acid and base sites (learned proposal)
     double L, scale, lnZ0;   // scale = L / 2^32; lnZ0 = ln(rho0 NA) + 3 ln(scale)
     uint64_t R2;             // Coulomb cutoff on the integer squared distance
@@ -145,6 +146,7 @@ struct LearnItem {
     const uint4* rec;      // the sweep's record buffer of the replica
     const uint32_t* cnt;   // its cell counts
     double* phat;          // per site network outputs
+    float* feat;           // per site features (recording only; else null)
     double off[2];         // logit offsets of acid and base sites
     uint32_t cell, part, r, n, cap, pad;
 };

@@ -454,6 +454,7 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
                     L.rec = R.rec[buf];
                     L.cnt = R.cnt[buf];
                     L.phat = R.phat;
+                    L.feat = R.feat;
                     L.off[0] = R.lp_off[0];
                     L.off[1] = R.lp_off[1];
                     L.cell = cell;

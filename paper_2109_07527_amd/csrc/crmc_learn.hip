@@ -438,6 +438,11 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
             __syncthreads();
         }
 
+        // recorded features (checks): per site, as evaluated in this phase
+        if (I.feat && tid < nsite) {
+            float* f = I.feat + (size_t)(S.site[tid].w >> 8) * LIN;
+            for (int i = 0; i < LIN; ++i) f[i] = (float)S.hist[tid][i];
+        }
         // training rows: the features and the site's ionization at the start of the phase
         if (g.data && tid < nsite) {
             const unsigned long long row = atomicAdd(g.data_n, 1ull);

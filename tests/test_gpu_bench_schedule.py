@@ -1,0 +1,183 @@
+"""The benchmarked schedule against the oracle (needs an MI355X).
+
+The benchmark runs 8 trials per cell in the equilibrated state of its
+workloads, where nanoparticle-surface domains gather about a thousand
+neighbour records and the tuned launch shape keeps only part of them on
+chip.  These tests bring one replica of each workload to that state on the
+GPU (several hundred FP32 sweeps), hand the state to the oracle in the GPU's
+particle order at the GPU's sweep index, and compare the next sweep's trials
+of the heaviest first-phase domains (and some others) trial by trial:
+decisions equal outside 1e-4 of the threshold, every energy change within
+1e-5 * max(|dU|, 1 kT).  A last test compares the benchmarked FP32 chain's
+<alpha> per replica with the FP64 chain (which is the oracle's, bit for bit).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import config2, config5
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2109_07527_amd import crmc
+    return crmc
+
+
+def _compare(glog, olog, ftol=1e-5):
+    """Every oracle trial against the GPU's; a domain's comparison stops at
+    its first decision within 1e-4 of the threshold that came out
+    differently (the chains legitimately part there)."""
+    key = {(int(r["cell"]), int(r["trial"])): r for r in glog}
+    stopped = set()
+    n = 0
+    for r in olog:
+        cell = int(r["cell"])
+        if cell in stopped:
+            continue
+        g = key[(cell, int(r["trial"]))]
+        assert g["move"] == r["move"], (r, g)
+        if r["status"] == 2:
+            assert g["status"] == 2
+            n += 1
+            continue
+        ro, rg = r["dU"], g["dU"]
+        if np.isfinite(ro) and ro < 1e3:
+            assert abs(rg - ro) <= ftol * max(abs(ro), 1.0), (r, g)
+        else:
+            assert not np.isfinite(rg) or rg > 1e3
+        if g["status"] != r["status"]:
+            assert abs(r["u"] - math.exp(min(0.0, r["lnp"]))) < 1e-4, (r, g)
+            stopped.add(cell)
+            continue
+        n += 1
+    return n
+
+
+def _first_phase_domains(X, n, shift, o, sweep):
+    """(first cell, neighbour records) of every domain of the first colour
+    phase of the sweep, from the particles' cells in its shifted grid."""
+    cell = (((X.astype(np.uint64) - shift.astype(np.uint64)) % (1 << 32)) * n) >> 32
+    lin = (cell[:, 0] + n * (cell[:, 1] + n * cell[:, 2])).astype(np.int64)
+    cnt = np.bincount(lin, minlength=n ** 3).reshape(n, n, n)  # [z][y][x]
+    nb = np.zeros_like(cnt)
+    for dz in (-1, 0, 1):
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if dx or dy or dz:
+                    nb += np.roll(cnt, (-dz, -dy, -dx), axis=(0, 1, 2))
+    h = n // 2
+    M = h ** 3
+    out = []
+    for a in range(M):
+        b = o.partner(sweep, 0, a, M)
+        if b < a:
+            continue
+        w = 0
+        for m in (a, b) if b != a else (a,):
+            i, j, k = m % h, (m // h) % h, m // (h * h)
+            w += int(nb[2 * k, 2 * j, 2 * i])
+        i, j, k = a % h, (a // h) % h, a // (h * h)
+        out.append((2 * i + n * (2 * j + n * 2 * k), w))
+    return out
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("workload,lds,light", [("pair", 0, 0), ("suspension", 3072, 512)])
+def test_equilibrated_bench_schedule_heavy_domains(workload, lds, light):
+    crmc = _gpu()
+    c = config2() if workload == "pair" else config5()
+    pH = 7.0
+    cond = dict(pH=pH, pKa=c["pKa"], pKb=c["pKb"], pIX_pos=c["pIX"], pIX_neg=c["pIX"], kappa=c["kappa"])
+    S = crmc.System(n_replicas=1, lB=c["lB"], rc=c["rc"], precision=32, trials_per_cell=8, seed=2024,
+                    lds_records=lds, light_neighbours=light)
+    S.build_cells(0, c)
+    S.sweep_ex([cond], 300)
+    obs = S.observe(0)
+    assert obs["status"] == 0, obs
+    X, k, ch, sid = S.particles(0)
+    s0 = obs["sweeps"]
+    ions = obs["n_xpos"] + obs["n_xneg"]
+    print("%s: %d ions after %d sweeps" % (workload, ions, s0), flush=True)
+    S.enable_log(8_000_000)
+    S.sweep_ex([cond], 1)
+    glog = S.read_log()
+    obs1 = S.observe(0)
+    assert obs1["status"] == 0
+    n = obs["n_cells"]
+    o = oracle.Oracle(c["L"], n, c["lB"], c["kappa"], c["rc"], seed=2024)
+    o.set_conditions(cond["pH"], cond["pKa"], cond["pKb"], cond["pIX_pos"], cond["pIX_neg"])
+    o.set_cores(c["core_xyz"], c["core_R"])
+    o.set_schedule(8)
+    o.load_state(X, k, ch, sid, s0, energy=False)
+    doms = _first_phase_domains(X, n, o.shift(s0), o, s0)
+    doms.sort(key=lambda d: -d[1])
+    rng = np.random.default_rng(3)
+    rest = [d[0] for d in doms[12:]]
+    pick = [d[0] for d in doms[:12]] + [int(v) for v in rng.choice(rest, 12, replace=False)]
+    heavy_nb = doms[0][1]
+    print("%s: heaviest domain %d neighbour records, 12th %d" % (workload, heavy_nb, doms[11][1]), flush=True)
+    assert heavy_nb > 500
+    o.set_domain_filter(pick)
+    o.enable_log(100_000)
+    o.sweeps(1)
+    olog = o.log()
+    assert set(int(v) for v in olog["cell"]) == set(pick)
+    glog = glog[glog["sweep"] == s0]
+    n_ok = _compare(glog, olog)
+    assert n_ok > 0.9 * len(olog), (n_ok, len(olog))
+    assert len(olog) >= 24 * 16
+
+
+@pytest.mark.timeout(900)
+def test_matched_alpha_suspension_learned_fp32_vs_fp64():
+    """The benchmarked configuration (64-nanoparticle suspension, eight pH
+    replicas, FP32 with the trained learned proposal) against the plain FP64
+    chain: <alpha> of the acid and of the base sites of every replica within
+    3.5 combined standard errors (Sokal windows; 16 comparisons)."""
+    crmc = _gpu()
+    from paper_2109_07527_amd.stats import mean_se
+    c = config5()
+    conds = [dict(pH=pH, pKa=c["pKa"], pKb=c["pKb"], pIX_pos=c["pIX"], pIX_neg=c["pIX"], kappa=c["kappa"])
+             for pH in c["pH_list"]]
+    R = len(conds)
+    nA = int((np.asarray(c["kind"]) == 1).sum())
+    nB = int((np.asarray(c["kind"]) == 2).sum())
+    eq, meas = 500, 1500
+    res = {}
+    for prec in (32, 64):
+        S = crmc.System(n_replicas=R, lB=c["lB"], rc=c["rc"], precision=prec, trials_per_cell=8, seed=4242 + prec,
+                        lds_records=3072, light_neighbours=512)
+        for r in range(R):
+            S.build_cells(r, c)
+        S.sweep_ex(conds, eq)
+        if prec == 32:
+            S.collect_training(1_000_000)
+            S.sweep_ex(conds, 3)
+            S.init_proposal_weights(7)
+            S.train(1, batch=1024, lr=1e-3, seed=7)
+            S.collect_training(0)
+            S.set_proposal(True, 0.1)
+            S.sweep_ex(conds, 50)
+        first = S.observe(0)["sweeps"]
+        S.sweep_ex(conds, meas)
+        for r in range(R):
+            assert S.observe(r)["status"] == 0
+        res[prec] = [S.series(r, first, meas).astype(np.float64) for r in range(R)]
+        print("precision %d done" % prec, flush=True)
+        S.close()
+    worst = 0.0
+    for r in range(R):
+        for col, nsite in ((0, nA), (1, nB)):
+            m1, s1, _ = mean_se(res[32][r][:, col] / nsite)
+            m2, s2, _ = mean_se(res[64][r][:, col] / nsite)
+            z = abs(m1 - m2) / math.hypot(s1, s2)
+            worst = max(worst, z)
+            assert z < 3.5, (r, col, m1, s1, m2, s2)
+    print("largest deviation %.2f combined SE" % worst, flush=True)

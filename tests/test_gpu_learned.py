@@ -248,3 +248,166 @@ def test_site_probabilities_follow_the_network_and_offsets():
     ks = kind[site]
     assert np.median(z1[ks == 1]) < np.median(z0[ks == 1]) - 1.0
     assert np.median(z1[ks == 2]) > np.median(z0[ks == 2]) + 0.5
+
+
+def _colour0_cells(n):
+    """Linear indices of the first colour's cells (all coordinates even)."""
+    e = np.arange(0, n, 2)
+    cx, cy, cz = np.meshgrid(e, e, e, indexing="ij")
+    return (cx + n * (cy + n * cz)).ravel()
+
+
+def test_fp32_features_and_probabilities_full_size():
+    """The FP32 path of the learned proposal (float shell tests with the exact
+    integer fallback, BF16 matrix-core network) on the full-size nanoparticle
+    pair (4000 sites, L = 120) with ions at the start of three different
+    sweeps: every first-phase site's 32 features equal, as integers, the
+    oracle's count on the same state, and its p_i equals the logistic of the
+    FP64 network at the BF16-rounded weights plus the replica's offset within
+    the BF16 tolerance.  Only the first phase of a sweep starts from a state
+    the oracle can rebuild exactly (later phases follow FP32 decisions)."""
+    crmc = _gpu()
+    from workloads import config2
+    c = config2()
+    cond = dict(pH=7.0, pKa=c["pKa"], pKb=c["pKb"], pIX_pos=c["pIX"], pIX_neg=c["pIX"], kappa=c["kappa"])
+    p = _params(13, 1.0)
+    off = (-0.7, 0.4)
+    S = crmc.System(n_replicas=1, lB=c["lB"], rc=c["rc"], precision=32, trials_per_cell=8, seed=2024,
+                    learned=True, learned_eps=0.1)
+    S.build_cells(0, c)
+    S.set_proposal_weights(p)
+    S.set_proposal_offsets(0, *off)
+    S.sweep_ex([cond], 40)
+    S.record_features(True)
+    pr = _bf16_params(p)
+    kind = np.asarray(c["kind"])
+    checked, z_err, total = 0, [], 0.0
+    for rnd in range(3):
+        X, k, ch, sid = S.particles(0)
+        obs = S.observe(0)
+        s0 = obs["sweeps"]
+        assert obs["n_xpos"] + obs["n_xneg"] > 100
+        S.sweep_ex([cond], 1)
+        F = S.site_features(0)
+        P = S.site_probabilities(0)
+        o = oracle.Oracle(c["L"], obs["n_cells"], c["lB"], c["kappa"], c["rc"], seed=2024)
+        o.set_conditions(cond["pH"], cond["pKa"], cond["pKb"], cond["pIX_pos"], cond["pIX_neg"])
+        o.set_cores(c["core_xyz"], c["core_R"])
+        o.set_learned(pr, 0.1)
+        o.load_state(X, k, ch, sid, s0, energy=False)
+        o.prepare_sweep()
+        for cell in _colour0_cells(obs["n_cells"]):
+            ids, Xf = o.cell_site_features(int(cell))
+            if len(ids) == 0:
+                continue
+            assert np.array_equal(F[ids].astype(np.float64), Xf), (rnd, cell)
+            for i, x in zip(ids, Xf):
+                zo = oracle.mlp_logit(pr, x) + (off[0] if kind[i] == 1 else off[1])
+                pg = P[i]
+                if 1e-6 < pg < 1 - 1e-6 and abs(zo) < 13.0:
+                    zg = np.log(pg / (1.0 - pg))
+                    z_err.append(abs(zg - zo) / max(1.0, abs(zo)))
+                else:
+                    po = 1.0 / (1.0 + np.exp(-zo))
+                    assert abs(pg - min(max(po, 1e-6), 1 - 1e-6)) < 1e-4, (i, pg, po)
+                checked += 1
+            total += Xf.sum()
+    z_err = np.array(z_err)
+    assert checked > 1000 and total > 10 * checked, (checked, total)
+    assert z_err.mean() < 5e-3 and z_err.max() < 3e-2, (z_err.mean(), z_err.max())
+
+
+def _lcg_shuffle_orders(n, epochs, seed):
+    """The minibatch order of crmc_train: per epoch one Fisher-Yates pass
+    over the row indices driven by the 64-bit LCG x -> 6364136223846793005 x
+    + 1442695040888963407 (Knuth's MMIX constants), seeded with one step from
+    the seed; index j = (x >> 33) mod (i + 1)."""
+    A, Cc, M = 6364136223846793005, 1442695040888963407, (1 << 64) - 1
+    st = (seed * A + Cc) & M
+    perm = list(range(n))
+    out = []
+    for _ in range(epochs):
+        for i in range(n - 1, 0, -1):
+            st = (st * A + Cc) & M
+            j = (st >> 33) % (i + 1)
+            perm[i], perm[j] = perm[j], perm[i]
+        out.append(list(perm))
+    return out
+
+
+def test_training_steps_match_the_oracle_adam():
+    """crmc_train against the oracle step for step: the same minibatches (the
+    library's seeded shuffle), the FP64 mean cross-entropy gradient at the
+    BF16-rounded weights, and the FP64 Adam step (lr 1e-3, betas 0.9 and
+    0.999, bias-corrected moments).  After 16 steps the parameter changes
+    agree component by component within a small fraction of the step size
+    (a BF16 gradient can differ in sign where the exact gradient is close to
+    zero, so a few components may differ by up to 2 lr per step), and the
+    last epoch's mean loss agrees."""
+    crmc = _gpu()
+    rng = np.random.default_rng(17)
+    n, batch, epochs, lr, seed = 2048, 256, 2, 1e-3, 5
+    X = rng.integers(0, 12, (n, 32)).astype(np.float32)
+    wt = rng.normal(0, 0.3, 32)
+    y = (rng.random(n) < 1.0 / (1.0 + np.exp(-(X - 5.5) @ wt / 4.0))).astype(np.float32)
+    rows = np.concatenate([X, y[:, None]], 1)
+    p0 = _params(21, 1.0)
+    S = crmc.System(n_replicas=1)
+    S.set_proposal_weights(p0)
+    S.load_training(rows)
+    assert S.training_rows() == n
+    loss_gpu = S.train(epochs, batch=batch, lr=lr, seed=seed)
+    p_gpu = S.proposal_weights().astype(np.float64)
+    # the oracle: FP64 master parameters, BF16 weights for each gradient
+    par = p0.astype(np.float64)
+    m = np.zeros_like(par)
+    v = np.zeros_like(par)
+    t = 0
+    losses = []
+    for order in _lcg_shuffle_orders(n, epochs, seed):
+        losses = []
+        for b in range(n // batch):
+            idx = np.array(order[b * batch:(b + 1) * batch])
+            pb = par.copy()
+            pb[:4096] = _bf16(par[:4096].astype(np.float32))
+            pb[4224:4224 + 16384] = _bf16(par[4224:4224 + 16384].astype(np.float32))
+            l, g = oracle.mlp_loss_grad(pb, X[idx].astype(np.float64), y[idx].astype(np.float64))
+            losses.append(l)
+            t += 1
+            oracle.adam_step(par, g, m, v, t, lr)
+    assert loss_gpu == pytest.approx(np.mean(losses), rel=1e-2)
+    step = lr * t
+    d_gpu, d_orc = p_gpu - p0.astype(np.float64), par - p0.astype(np.float64)
+    err = np.abs(d_gpu - d_orc)
+    assert np.percentile(err, 99) < 0.1 * step, np.percentile(err, 99) / step
+    assert err.max() < 2.0 * step
+    assert np.abs(d_orc).mean() > 0.3 * step  # the steps are not vanishing
+    # the BF16 copies the kernels use follow the trained masters
+    Xq = X[:256]
+    z1 = S.mlp_forward(Xq)
+    S2 = crmc.System(n_replicas=1)
+    S2.set_proposal_weights(p_gpu.astype(np.float32))
+    assert np.array_equal(z1, S2.mlp_forward(Xq))
+
+
+def test_training_buffer_reallocated_under_graph_replay():
+    """Collecting rows into a buffer of N rows and then of N/2 rows, with the
+    sweeps replayed from captured graphs: the second buffer never receives
+    more than N/2 rows (the graphs follow every change of a launch argument)."""
+    crmc = _gpu()
+    s, m, c = _case("np_pair_small")
+    S = crmc.System(n_replicas=1, lB=2.0, rc=6.0, precision=32, trials_per_cell=2, seed=3, use_graph=True)
+    S.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"])
+    S.sweep_ex([c], 20)
+    N = 240 * 30
+    S.collect_training(N)
+    S.sweep_ex([c], 40)
+    assert S.training_rows() == N
+    S.collect_training(N // 2)
+    S.sweep_ex([c], 40)
+    assert S.training_rows() == N // 2
+    S.collect_training(N)
+    S.sweep_ex([c], 16)
+    assert S.training_rows() == 16 * 240
+    rows = S.read_training()
+    assert np.all(rows[:, :32] >= 0) and set(np.unique(rows[:, 32])) <= {0.0, 1.0}
