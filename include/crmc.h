@@ -36,8 +36,14 @@
  * Conventions.
  *   - Every host array passed in is owned by the caller and copied before the
  *     call returns; the library never frees caller memory.
- *   - Device memory is allocated by the library (crmc_create / build) and freed
- *     by crmc_destroy.
+ *   - Device memory: every buffer of a handle's state comes either from the
+ *     library (hipMalloc, freed by crmc_destroy) or, when the caller hands one
+ *     over (crmc_params.workspace, or crmc_set_workspace right after the
+ *     builds), from a caller-owned workspace such as a torch uint8 tensor;
+ *     then the handle never allocates device memory of its own and
+ *     crmc_destroy frees nothing of it.  crmc_build_cells keeps a replica's
+ *     initial state on the host; the device state is created by the first
+ *     call that needs it.
  *   - Calls that launch work are asynchronous and ordered on the stream given
  *     in crmc_params (NULL = the default stream).  crmc_observe,
  *     crmc_get_series, crmc_get_particles, crmc_energy, crmc_read_log,
@@ -58,7 +64,7 @@
 extern "C" {
 #endif
 
-#define CRMC_ABI_VERSION 2
+#define CRMC_ABI_VERSION 3
 
 typedef struct crmc_s* crmc_t;
 
@@ -126,6 +132,9 @@ typedef struct {
     double learned_eps;      /* weight of the uniform pick in the learned proposal, in (0, 1] */
     uint64_t seed;           /* Philox key: (seed low word, seed high word ^ replica) */
     void* stream;            /* hipStream_t on which every call is ordered */
+    void* workspace;         /* caller-owned device memory for the handle's state, or NULL (the
+                                library allocates); it must stay valid until crmc_destroy */
+    int64_t workspace_bytes; /* its size (>= 256 when workspace is set); see crmc_workspace_size */
 } crmc_params;
 
 /* Per-replica reservoir conditions for crmc_sweep_ex. */
@@ -162,11 +171,49 @@ typedef struct {
     double dU, lnp, u;          /* dU in kT; lnp = log acceptance ratio; u uniform */
 } crmc_trial_rec;
 
-/* Create a handle.  No device work; returns CRMC_E_ARG for invalid params. */
+/*
+ * Create a handle for n_replicas independent systems under the model of Sec.
+ * II (screened Coulomb with lB, kappa and rc; excluded volume of Table I and
+ * Table II; rho0 NA of the reference concentration of Sec. II C) and the
+ * schedule fields of crmc_params.  No device work and no device memory;
+ * returns CRMC_E_ARG for invalid params (rc <= 1.2, negative lB or eps,
+ * trials outside 1..2^20, a workspace smaller than 256 bytes, ...).
+ */
 int crmc_create(const crmc_params* params, crmc_t* out);
 
 /*
- * Define replica `replica`: box edge L (periodic cube), n particles with
+ * Caller-owned workspace.  crmc_workspace_size: after every replica is built,
+ * *bytes = the device memory the handle's state needs at its current
+ * settings: every replica's records, counts and observables, the plan and
+ * tables of a sweep, the network with its Adam moments and the learned
+ * proposal's work items (whether or not the proposal is on), and the per-cell
+ * sums of crmc_energy.  Optional buffers come on top when enabled: the trial
+ * log (56 bytes per record), the phase trace (48 bytes per record), training
+ * rows (132 bytes per row), recorded features (128 bytes per particle of
+ * every replica; included in the size once recording is on), and while
+ * crmc_train, crmc_mlp_forward or crmc_mlp_gradient run, 4, 132 or 136
+ * bytes per row, each buffer rounded up to 256 bytes.
+ * crmc_set_workspace: hands over `bytes` of caller-owned device memory
+ * (e.g. a torch uint8 tensor) before the first call that creates device
+ * state (every call that reads or advances the replicas, sets the network
+ * or enables a buffer); from then on every device buffer of the handle is
+ * carved from it (first fit, 256-byte aligned, freed blocks reused) and a
+ * request that does not fit fails with CRMC_E_NOMEM.  The caller keeps it
+ * alive until crmc_destroy and must not touch it meanwhile.  Errors:
+ * CRMC_E_STATE before all replicas are built (size) or once the handle has
+ * device memory (attach); CRMC_E_ARG for NULL or fewer than 256 bytes.
+ */
+int crmc_workspace_size(crmc_t h, int64_t* bytes);
+int crmc_set_workspace(crmc_t h, void* workspace, int64_t bytes);
+/* Device memory of the handle now: the library's own live allocations and,
+   with a workspace, its bytes in use and its largest free block (each
+   pointer may be NULL).  Host only. */
+int crmc_memory(crmc_t h, int64_t* own_bytes, int64_t* workspace_used, int64_t* workspace_largest_free);
+
+/*
+ * Define replica `replica` (Sec. II A: the system of fixed acid and base
+ * groups, nanoparticle cores and free monovalent ions in a periodic box):
+ * box edge L (periodic cube), n particles with
  * positions xyz (n*3 doubles, any real values; wrapped into the box), kind
  * (crmc_kind), optional charged flags (NULL = all sites neutral; ions are
  * always charged), optional group id per particle (NULL = 0) and n_cores
@@ -176,7 +223,9 @@ int crmc_create(const crmc_params* params, crmc_t* out);
  * The initial order of particles is their stable binning into the unshifted
  * grid.  Returns CRMC_E_ARG when L < 4 rc, when n_cells is odd, below 4 or
  * gives cells narrower than rc, or when a cell already holds more than
- * cell_capacity particles.
+ * cell_capacity particles; CRMC_E_STATE after the first sweep.  Host work
+ * only: the replica's state goes to the device with the first call that
+ * needs it.
  */
 int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32_t cell_capacity,
                      int32_t n, const double* xyz, const int32_t* kind, const int32_t* charged,
@@ -194,7 +243,14 @@ int crmc_sweep(crmc_t h, double pH, double pKa, double mu_ion, int64_t n_sweeps)
 /* Same with per-replica conditions (array of n_replicas). */
 int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps);
 
-/* Counts, energy and move statistics of a replica (synchronizes). */
+/*
+ * Counts, energy and move statistics of a replica (synchronizes): the
+ * numbers of charged acid and base groups, whose means give the degree of
+ * ionization alpha = <n_A->/n_A of Sec. III, the free-ion numbers, the
+ * retained energy of Sec. II D (start energy plus accepted changes), and
+ * attempts and acceptances per move of Sec. II C.  CRMC_E_CAPACITY when a cell
+ * overflowed (the state is then not trustworthy), CRMC_E_STATE before build.
+ */
 int crmc_observe(crmc_t h, int32_t replica, crmc_obs* out);
 
 /*

@@ -36,7 +36,8 @@ class crmc_params(C.Structure):
                 ("learned_proposal", C.c_int32), ("ion_trials", C.c_int32),
                 ("lB", C.c_double), ("rc", C.c_double), ("eps_wca", C.c_double), ("rho0NA", C.c_double),
                 ("pKw", C.c_double), ("kappa", C.c_double), ("pKb", C.c_double), ("learned_eps", C.c_double),
-                ("seed", C.c_uint64), ("stream", C.c_void_p)]
+                ("seed", C.c_uint64), ("stream", C.c_void_p), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_int64)]
 
 
 class crmc_cond(C.Structure):
@@ -87,6 +88,9 @@ def load():
     P, vp, d, i32, i64, u32, u64 = C.POINTER, C.c_void_p, C.c_double, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64
     sig = {
         "crmc_create": (C.c_int, [P(crmc_params), P(vp)]),
+        "crmc_workspace_size": (C.c_int, [vp, P(i64)]),
+        "crmc_set_workspace": (C.c_int, [vp, vp, i64]),
+        "crmc_memory": (C.c_int, [vp, P(i64), P(i64), P(i64)]),
         "crmc_build_cells": (C.c_int, [vp, i32, d, i32, i32, i32, P(d), P(i32), P(i32), P(i32), i32, P(d), P(d)]),
         "crmc_sweep": (C.c_int, [vp, d, d, d, i64]),
         "crmc_sweep_ex": (C.c_int, [vp, P(crmc_cond), i64]),
@@ -180,6 +184,25 @@ def crmc_build_cells(h, replica, L, xyz, kind, charged=None, group=None, core_xy
     return _check(h, load().crmc_build_cells(h, int(replica), float(L), int(n_cells), int(cell_capacity), n,
                                              _p(xyz, C.c_double), _p(kind, C.c_int32), _p(ch, C.c_int32),
                                              _p(gr, C.c_int32), nc, _p(cx, C.c_double), _p(cr, C.c_double)))
+
+
+def crmc_workspace_size(h):
+    n = C.c_int64(0)
+    _check(h, load().crmc_workspace_size(h, C.byref(n)))
+    return n.value
+
+
+def crmc_set_workspace(h, ptr, nbytes):
+    """Hand over caller-owned device memory (a device pointer, e.g. a torch
+    uint8 tensor's data_ptr()) for the handle's state."""
+    return _check(h, load().crmc_set_workspace(h, C.c_void_p(int(ptr)), int(nbytes)))
+
+
+def crmc_memory(h):
+    """{own, workspace_used, workspace_largest_free} device bytes of the handle."""
+    a, b, c = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    _check(h, load().crmc_memory(h, C.byref(a), C.byref(b), C.byref(c)))
+    return dict(own=a.value, workspace_used=b.value, workspace_largest_free=c.value)
 
 
 def crmc_sweep(h, pH, pKa, mu_ion, n_sweeps):
@@ -478,6 +501,7 @@ class System:
         if getattr(self, "h", None) is not None:
             crmc_destroy(self.h)
             self.h = None
+        self._workspace = None
 
     def __del__(self):
         try:
@@ -495,6 +519,18 @@ class System:
                 kw.setdefault("core_xyz", system["core_xyz"])
                 kw.setdefault("core_R", system["core_R"])
         return crmc_build_cells(self.h, replica, **kw)
+
+    def workspace_size(self):
+        return crmc_workspace_size(self.h)
+
+    def set_workspace(self, tensor):
+        """Place the handle's device state in a caller-owned torch uint8
+        tensor (kept referenced here until close())."""
+        self._workspace = tensor
+        return crmc_set_workspace(self.h, tensor.data_ptr(), tensor.numel() * tensor.element_size())
+
+    def memory(self):
+        return crmc_memory(self.h)
 
     def sweep(self, pH, pKa, mu_ion, n_sweeps):
         return crmc_sweep(self.h, pH, pKa, mu_ion, n_sweeps)

@@ -36,6 +36,87 @@ struct HostReplica {
     std::vector<int32_t> hist_off;
     crmc_cond cond{};
     Replica d{}; // device pointers and constants (host copy of the descriptor)
+    // The initial state as built, kept on the host until the first call that
+    // needs the device state (so that a workspace can still be attached):
+    // records in cell order, cell counts, per-site groups, cores.
+    bool on_device = false;
+    std::vector<uint4> init_rec;
+    std::vector<uint32_t> init_cnt;
+    std::vector<int32_t> init_group;
+    std::vector<uint4> init_cores;
+    std::vector<double> init_delta;
+    int64_t init_tot[4] = {0, 0, 0, 0};
+    uint32_t init_maxc = 0;
+};
+
+// Device memory of a handle: the library's own allocations, or blocks of a
+// caller-owned workspace handed out first fit (256-byte aligned) and given
+// back on release, neighbouring free blocks merged.
+constexpr size_t WS_ALIGN = 256;
+
+size_t ws_round(size_t b) { return (std::max<size_t>(b, 1) + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; }
+
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    std::map<size_t, size_t> free_blocks; // offset -> bytes
+    std::map<const void*, size_t> live;   // pointer -> bytes
+    size_t used = 0;
+
+    void attach(void* p, size_t bytes)
+    {
+        const uintptr_t a = ((uintptr_t)p + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN;
+        const size_t lost = (size_t)(a - (uintptr_t)p);
+        base = (char*)a;
+        size = bytes > lost ? (bytes - lost) / WS_ALIGN * WS_ALIGN : 0;
+        free_blocks.clear();
+        live.clear();
+        used = 0;
+        if (size) free_blocks[0] = size;
+    }
+    void* take(size_t bytes)
+    {
+        bytes = ws_round(bytes);
+        for (auto it = free_blocks.begin(); it != free_blocks.end(); ++it) {
+            if (it->second < bytes) continue;
+            const size_t off = it->first, rest = it->second - bytes;
+            free_blocks.erase(it);
+            if (rest) free_blocks[off + bytes] = rest;
+            void* q = base + off;
+            live[q] = bytes;
+            used += bytes;
+            return q;
+        }
+        return nullptr;
+    }
+    bool give(const void* q)
+    {
+        auto it = live.find(q);
+        if (it == live.end()) return false;
+        size_t off = (size_t)((const char*)q - base), bytes = it->second;
+        live.erase(it);
+        used -= bytes;
+        auto nx = free_blocks.lower_bound(off);
+        if (nx != free_blocks.end() && nx->first == off + bytes) {
+            bytes += nx->second;
+            nx = free_blocks.erase(nx);
+        }
+        if (nx != free_blocks.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += bytes;
+                return true;
+            }
+        }
+        free_blocks[off] = bytes;
+        return true;
+    }
+    size_t largest_free() const
+    {
+        size_t m = 0;
+        for (const auto& kv : free_blocks) m = std::max(m, kv.second);
+        return m;
+    }
 };
 
 } // namespace
@@ -43,6 +124,9 @@ struct HostReplica {
 struct crmc_s {
     crmc_params p{};
     std::vector<HostReplica> reps;
+    Arena ws;                    // caller-owned workspace (ws.base null: the library allocates)
+    bool device_state = false;   // some device memory of the handle exists
+    std::map<const void*, size_t> own; // the library's own live allocations (bytes, rounded)
     Replica* d_reps = nullptr;
     uint32_t* d_cell2rep = nullptr;
     uint32_t* d_dom2rep = nullptr;
@@ -147,22 +231,41 @@ bool grid_ok(uint32_t n, uint64_t R2)
     return sep * sep >= R2;
 }
 
+// device memory for count values of T: from the workspace when one is
+// attached (hipErrorOutOfMemory when it has no block that large), else from
+// the runtime
 template <typename T>
-hipError_t dalloc(T** p, size_t count)
+hipError_t dalloc(crmc_t h, T** p, size_t count)
 {
-    return hipMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T));
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    h->device_state = true;
+    if (h->ws.base) {
+        *p = (T*)h->ws.take(bytes);
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    const hipError_t e = hipMalloc((void**)p, bytes);
+    if (e == hipSuccess) h->own[*p] = ws_round(bytes);
+    return e;
 }
 
-void free_replica(HostReplica& r)
+void dfree(crmc_t h, void* q)
+{
+    if (!q) return;
+    if (h->ws.base && h->ws.give(q)) return;
+    h->own.erase(q);
+    (void)hipFree(q);
+}
+
+void free_replica(crmc_t h, HostReplica& r)
 {
     Replica& d = r.d;
     void* ptrs[] = {d.rec[0], d.rec[1], d.cnt[0], d.cnt[1], d.cnt0, d.e_acc, d.occupancy, d.site_group,
                     d.group_count, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
                     d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab, d.phat, d.nsc, d.feat};
-    for (void* q : ptrs)
-        if (q) (void)hipFree(q);
+    for (void* q : ptrs) dfree(h, q);
     d = Replica{};
     r.built = false;
+    r.on_device = false;
 }
 
 void set_conditions(crmc_t h, HostReplica& r, const crmc_cond& c)
@@ -250,14 +353,14 @@ int upload_descriptors(crmc_t h)
             std::fill(d2r.begin() + r.d.dom_begin, d2r.begin() + r.d.dom_begin + nd, (uint32_t)i);
             maxcap = std::max(maxcap, r.cap);
         }
-        if (h->d_cell2rep) (void)hipFree(h->d_cell2rep);
-        if (h->d_dom2rep) (void)hipFree(h->d_dom2rep);
-        if (h->d_lntab) (void)hipFree(h->d_lntab);
-        if (h->d_plan_n) (void)hipFree(h->d_plan_n);
-        if (h->d_plan_heavy) (void)hipFree(h->d_plan_heavy);
-        if (h->d_plan_light) (void)hipFree(h->d_plan_light);
-        if (h->d_plan_geo_heavy) (void)hipFree(h->d_plan_geo_heavy);
-        if (h->d_plan_geo_light) (void)hipFree(h->d_plan_geo_light);
+        dfree(h, h->d_cell2rep);
+        dfree(h, h->d_dom2rep);
+        dfree(h, h->d_lntab);
+        dfree(h, h->d_plan_n);
+        dfree(h, h->d_plan_heavy);
+        dfree(h, h->d_plan_light);
+        dfree(h, h->d_plan_geo_heavy);
+        dfree(h, h->d_plan_geo_light);
         h->d_plan_geo_heavy = h->d_plan_geo_light = nullptr;
         h->d_cell2rep = h->d_dom2rep = nullptr;
         h->d_lntab = nullptr;
@@ -266,14 +369,14 @@ int upload_descriptors(crmc_t h)
         h->lntab_n = (int32_t)(2u * maxcap + 2u);
         std::vector<double> lt((size_t)h->lntab_n, 0.0);
         for (int32_t k = 1; k < h->lntab_n; ++k) lt[(size_t)k] = std::log((double)k);
-        HIP_TRY(h, dalloc(&h->d_cell2rep, c2r.size()));
-        HIP_TRY(h, dalloc(&h->d_dom2rep, d2r.size()));
-        HIP_TRY(h, dalloc(&h->d_lntab, lt.size()));
-        HIP_TRY(h, dalloc(&h->d_plan_n, PLAN_N));
-        HIP_TRY(h, dalloc(&h->d_plan_heavy, (size_t)8 * doms));
-        HIP_TRY(h, dalloc(&h->d_plan_light, (size_t)8 * doms));
-        HIP_TRY(h, dalloc(&h->d_plan_geo_heavy, (size_t)8 * doms));
-        HIP_TRY(h, dalloc(&h->d_plan_geo_light, (size_t)8 * doms));
+        HIP_TRY(h, dalloc(h, &h->d_cell2rep, c2r.size()));
+        HIP_TRY(h, dalloc(h, &h->d_dom2rep, d2r.size()));
+        HIP_TRY(h, dalloc(h, &h->d_lntab, lt.size()));
+        HIP_TRY(h, dalloc(h, &h->d_plan_n, PLAN_N));
+        HIP_TRY(h, dalloc(h, &h->d_plan_heavy, (size_t)8 * doms));
+        HIP_TRY(h, dalloc(h, &h->d_plan_light, (size_t)8 * doms));
+        HIP_TRY(h, dalloc(h, &h->d_plan_geo_heavy, (size_t)8 * doms));
+        HIP_TRY(h, dalloc(h, &h->d_plan_geo_light, (size_t)8 * doms));
         HIP_TRY(h, hipMemset(h->d_plan_n, 0, PLAN_N * sizeof(uint32_t)));
         HIP_TRY(h, hipMemcpy(h->d_cell2rep, c2r.data(), c2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
         HIP_TRY(h, hipMemcpy(h->d_dom2rep, d2r.data(), d2r.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
@@ -292,7 +395,7 @@ int upload_descriptors(crmc_t h)
                 sh[17 * i + k] = k ? (uint64_t)std::ceil(t * t) : 0;
             }
         }
-        if (!h->d_R2sh) HIP_TRY(h, dalloc(&h->d_R2sh, sh.size()));
+        if (!h->d_R2sh) HIP_TRY(h, dalloc(h, &h->d_R2sh, sh.size()));
         HIP_TRY(h, hipMemcpy(h->d_R2sh, sh.data(), sh.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     }
     return CRMC_OK;
@@ -322,14 +425,14 @@ std::vector<float> initial_weights(uint64_t seed)
 int ensure_params(crmc_t h)
 {
     if (h->d_p32) return CRMC_OK;
-    HIP_TRY(h, dalloc(&h->d_p32, MLP_PARAMS));
-    HIP_TRY(h, dalloc(&h->d_p64, MLP_PARAMS));
-    HIP_TRY(h, dalloc(&h->d_w1b, MLP_H * MLP_IN));
-    HIP_TRY(h, dalloc(&h->d_w2b, MLP_H * MLP_H));
-    HIP_TRY(h, dalloc(&h->d_adam_m, MLP_PARAMS));
-    HIP_TRY(h, dalloc(&h->d_adam_v, MLP_PARAMS));
-    HIP_TRY(h, dalloc(&h->d_grad, MLP_PARAMS));
-    HIP_TRY(h, dalloc(&h->d_loss, 1));
+    HIP_TRY(h, dalloc(h, &h->d_p32, MLP_PARAMS));
+    HIP_TRY(h, dalloc(h, &h->d_p64, MLP_PARAMS));
+    HIP_TRY(h, dalloc(h, &h->d_w1b, MLP_H * MLP_IN));
+    HIP_TRY(h, dalloc(h, &h->d_w2b, MLP_H * MLP_H));
+    HIP_TRY(h, dalloc(h, &h->d_adam_m, MLP_PARAMS));
+    HIP_TRY(h, dalloc(h, &h->d_adam_v, MLP_PARAMS));
+    HIP_TRY(h, dalloc(h, &h->d_grad, MLP_PARAMS));
+    HIP_TRY(h, dalloc(h, &h->d_loss, 1));
     {
         const std::vector<float> w0 = initial_weights(h->p.seed ^ 0x5DEECE66Dull);
         HIP_TRY(h, hipMemcpy(h->d_p32, w0.data(), MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice));
@@ -381,10 +484,10 @@ int ensure_learn_buffers(crmc_t h)
     }
     if (items * 8 > 0xFFFFFFFFull) return fail(h, CRMC_E_ARG, "too many sites for the learned proposal's work lists");
     if (items > h->lwork_cap || !h->d_lwork) {
-        if (h->d_lwork) (void)hipFree(h->d_lwork);
+        dfree(h, h->d_lwork);
         h->d_lwork = nullptr;
         const size_t m = (size_t)std::max<uint64_t>(items, 1);
-        HIP_TRY(h, dalloc(&h->d_lwork, 8 * m));
+        HIP_TRY(h, dalloc(h, &h->d_lwork, 8 * m));
         h->lwork_cap = (uint32_t)m;
     }
     if (!h->ncu) {
@@ -691,6 +794,7 @@ int crmc_create(const crmc_params* p, crmc_t* out)
     if (p->ion_trials < 0 || p->ion_trials > 4096 || (p->learned_proposal != 0 && p->learned_proposal != 1))
         return CRMC_E_ARG;
     if (p->learned_proposal && (!(p->learned_eps > 0.0) || p->learned_eps > 1.0)) return CRMC_E_ARG;
+    if (p->workspace_bytes < 0 || (p->workspace && p->workspace_bytes < (int64_t)WS_ALIGN)) return CRMC_E_ARG;
     crmc_t h = new (std::nothrow) crmc_s;
     if (!h) return CRMC_E_NOMEM;
     h->p = *p;
@@ -702,14 +806,7 @@ int crmc_create(const crmc_params* p, crmc_t* out)
     crmc_cond c{};
     c.pH = 7.0; c.pKa = 4.5; c.pKb = p->pKb; c.pIX_pos = c.pIX_neg = 1.0; c.kappa = p->kappa;
     for (auto& r : h->reps) r.cond = c;
-    if (hipMalloc((void**)&h->d_sweep, sizeof(uint64_t)) != hipSuccess ||
-        hipMalloc((void**)&h->d_err, sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc((void**)&h->d_reps, sizeof(Replica) * h->reps.size()) != hipSuccess) {
-        crmc_destroy(h);
-        return CRMC_E_DEVICE;
-    }
-    (void)hipMemset(h->d_sweep, 0, sizeof(uint64_t));
-    (void)hipMemset(h->d_err, 0, sizeof(uint32_t));
+    if (p->workspace) h->ws.attach(p->workspace, (size_t)p->workspace_bytes);
     *out = h;
     return CRMC_OK;
 }
@@ -747,7 +844,7 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
         if (!(core_R[i] >= 0.5)) return fail(h, CRMC_E_ARG, "core radius must be >= 1/2");
 
     HostReplica& r = h->reps[(size_t)replica];
-    if (r.built) free_replica(r);
+    if (r.built) free_replica(h, r);
     const uint32_t ncells = nc * nc * nc;
 
     // records in input order, then the stable binning into the unshifted grid
@@ -835,77 +932,29 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     r.hist_off.assign(ngroups + 1, 0);
     for (uint32_t g = 0; g < ngroups; ++g) r.hist_off[g + 1] = r.hist_off[g] + gsize[g] + 1;
 
-    std::vector<uint4> cells((size_t)ncells * cap);
-    std::vector<uint32_t> counts(ncells);
+    // the initial state stays on the host until the device state is created
+    r.init_rec.clear();
+    r.init_rec.reserve((size_t)n);
+    r.init_cnt.assign(ncells, 0u);
     for (uint32_t c = 0; c < ncells; ++c) {
-        counts[c] = (uint32_t)lists[c].size();
-        for (size_t j = 0; j < lists[c].size(); ++j) cells[(size_t)c * cap + j] = in[lists[c][j]];
+        r.init_cnt[c] = (uint32_t)lists[c].size();
+        for (uint32_t i : lists[c]) r.init_rec.push_back(in[i]);
     }
-    std::vector<uint4> cores((size_t)std::max(n_cores, 1));
-    std::vector<double> deltas((size_t)std::max(n_cores, 1));
+    r.init_cores.assign((size_t)std::max(n_cores, 1), make_uint4(0u, 0u, 0u, 0u));
+    r.init_delta.assign((size_t)std::max(n_cores, 1), 0.0);
     for (int32_t i = 0; i < n_cores; ++i) {
-        cores[(size_t)i] = make_uint4(to_fixed(core_xyz[3 * i], L), to_fixed(core_xyz[3 * i + 1], L),
-                                      to_fixed(core_xyz[3 * i + 2], L), 0u);
-        deltas[(size_t)i] = core_R[i] - 0.5;
+        r.init_cores[(size_t)i] = make_uint4(to_fixed(core_xyz[3 * i], L), to_fixed(core_xyz[3 * i + 1], L),
+                                             to_fixed(core_xyz[3 * i + 2], L), 0u);
+        r.init_delta[(size_t)i] = core_R[i] - 0.5;
     }
+    r.init_group = std::move(site_group);
+    std::memcpy(r.init_tot, tot, sizeof tot);
+    r.init_maxc = maxc;
+    r.on_device = false;
 
     Replica& d = r.d;
     d = Replica{};
-    const size_t nrec = (size_t)ncells * cap;
     const int64_t series_cap = DEFAULT_SERIES;
-    HIP_TRY(h, dalloc(&d.rec[0], nrec));
-    HIP_TRY(h, dalloc(&d.rec[1], nrec));
-    HIP_TRY(h, dalloc(&d.cnt[0], ncells));
-    HIP_TRY(h, dalloc(&d.cnt[1], ncells));
-    HIP_TRY(h, dalloc(&d.cnt0, ncells));
-    HIP_TRY(h, dalloc(&d.e_acc, ncells));
-    HIP_TRY(h, dalloc(&d.occupancy, (size_t)std::max(n, 1)));
-    HIP_TRY(h, dalloc(&d.site_group, (size_t)std::max(n, 1)));
-    HIP_TRY(h, dalloc(&d.group_count, 2 * std::max<uint32_t>(ngroups, 1)));
-    HIP_TRY(h, dalloc(&d.group_hist, (size_t)std::max(r.hist_off[ngroups], 1)));
-    HIP_TRY(h, dalloc(&d.group_hist_off, ngroups + 1));
-    HIP_TRY(h, dalloc(&d.core_x, cores.size()));
-    HIP_TRY(h, dalloc(&d.core_delta, deltas.size()));
-    HIP_TRY(h, dalloc(&d.totals, 4));
-    HIP_TRY(h, dalloc(&d.moves, 14));
-    HIP_TRY(h, dalloc(&d.series, (size_t)series_cap * 4));
-    HIP_TRY(h, dalloc(&d.phat, (size_t)std::max(n, 1)));
-    HIP_TRY(h, hipMemset(d.phat, 0, (size_t)std::max(n, 1) * sizeof(double)));
-    if (h->record_feat) {
-        HIP_TRY(h, dalloc(&d.feat, (size_t)std::max(n, 1) * MLP_IN));
-        HIP_TRY(h, hipMemset(d.feat, 0, (size_t)std::max(n, 1) * MLP_IN * sizeof(float)));
-    }
-    HIP_TRY(h, dalloc(&d.nsc, ncells));
-    HIP_TRY(h, hipMemset(d.nsc, 0, ncells * sizeof(uint32_t)));
-    HIP_TRY(h, hipMemcpy(d.rec[0], cells.data(), nrec * sizeof(uint4), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemcpy(d.cnt[0], counts.data(), ncells * sizeof(uint32_t), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemset(d.cnt[1], 0, ncells * sizeof(uint32_t)));
-    HIP_TRY(h, hipMemset(d.e_acc, 0, ncells * sizeof(double)));
-    HIP_TRY(h, hipMemset(d.occupancy, 0, (size_t)std::max(n, 1) * sizeof(uint64_t)));
-    HIP_TRY(h, hipMemcpy(d.site_group, site_group.data(), site_group.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemset(d.group_count, 0, 2 * std::max<uint32_t>(ngroups, 1) * sizeof(int32_t)));
-    HIP_TRY(h, hipMemset(d.group_hist, 0, (size_t)std::max(r.hist_off[ngroups], 1) * sizeof(int64_t)));
-    HIP_TRY(h, hipMemcpy(d.group_hist_off, r.hist_off.data(), (ngroups + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemcpy(d.core_x, cores.data(), cores.size() * sizeof(uint4), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemcpy(d.core_delta, deltas.data(), deltas.size() * sizeof(double), hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemcpy(d.totals, tot, sizeof tot, hipMemcpyHostToDevice));
-    HIP_TRY(h, hipMemset(d.moves, 0, 14 * sizeof(uint64_t)));
-    HIP_TRY(h, hipMemset(d.series, 0, (size_t)series_cap * 4 * sizeof(int32_t)));
-    {
-        // cell boundaries b_k = ceil(k 2^32 / n) (b_n wraps to 0) and ln of the widths
-        std::vector<uint32_t> b(nc + 1);
-        std::vector<double> lw(nc);
-        for (uint32_t k = 0; k <= nc; ++k) b[k] = (uint32_t)cell_lo_h(k, nc);
-        for (uint32_t k = 0; k < nc; ++k) lw[k] = std::log((double)(cell_lo_h(k + 1, nc) - cell_lo_h(k, nc)));
-        HIP_TRY(h, dalloc(&d.bnd, nc + 1));
-        HIP_TRY(h, dalloc(&d.lnW, nc));
-        HIP_TRY(h, dalloc(&d.hiwater, 1));
-        HIP_TRY(h, dalloc(&d.tab, 1));
-        HIP_TRY(h, hipMemcpy(d.bnd, b.data(), b.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
-        HIP_TRY(h, hipMemcpy(d.lnW, lw.data(), lw.size() * sizeof(double), hipMemcpyHostToDevice));
-        HIP_TRY(h, hipMemcpy(d.hiwater, &maxc, sizeof(uint32_t), hipMemcpyHostToDevice));
-        HIP_TRY(h, hipMemset(d.tab, 0, sizeof(SweepTab)));
-    }
     d.series_cap = series_cap;
     // at least four cells per particle given: a cell's re-binning gathers a
     // few records at most, so one lane per cell keeps more cells in flight
@@ -939,24 +988,216 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     return CRMC_OK;
 }
 
+// Device buffers of a built replica, in allocation order: (slot, bytes).
+struct DevBuf {
+    void** slot;
+    size_t bytes;
+};
+
+static std::vector<DevBuf> replica_buffers(crmc_t h, HostReplica& r)
+{
+    Replica& d = r.d;
+    const size_t ncells = r.ncells, nrec = ncells * r.cap, np = std::max<size_t>(r.nsites, 1);
+    const size_t ng = std::max<uint32_t>(r.ngroups, 1), nh = (size_t)std::max(r.hist_off.empty() ? 0 : r.hist_off.back(), 1);
+    const size_t nco = std::max<size_t>(r.ncores, 1);
+    std::vector<DevBuf> v = {
+        {(void**)&d.rec[0], nrec * sizeof(uint4)},   {(void**)&d.rec[1], nrec * sizeof(uint4)},
+        {(void**)&d.cnt[0], ncells * 4},             {(void**)&d.cnt[1], ncells * 4},
+        {(void**)&d.cnt0, ncells * 4},               {(void**)&d.e_acc, ncells * 8},
+        {(void**)&d.occupancy, np * 8},              {(void**)&d.site_group, np * 4},
+        {(void**)&d.group_count, 2 * ng * 4},        {(void**)&d.group_hist, nh * 8},
+        {(void**)&d.group_hist_off, (r.ngroups + 1) * 4}, {(void**)&d.core_x, nco * sizeof(uint4)},
+        {(void**)&d.core_delta, nco * 8},            {(void**)&d.totals, 4 * 8},
+        {(void**)&d.moves, 14 * 8},                  {(void**)&d.series, (size_t)DEFAULT_SERIES * 4 * 4},
+        {(void**)&d.phat, np * 8},                   {(void**)&d.nsc, ncells * 4},
+        {(void**)&d.bnd, (r.n + 1) * 4},             {(void**)&d.lnW, r.n * 8},
+        {(void**)&d.hiwater, 4},                     {(void**)&d.tab, sizeof(SweepTab)},
+    };
+    if (h->record_feat) v.push_back({(void**)&d.feat, np * MLP_IN * 4});
+    return v;
+}
+
+// the device state of a replica from its initial state on the host
+static int materialize_replica(crmc_t h, HostReplica& r)
+{
+    Replica& d = r.d;
+    for (const DevBuf& b : replica_buffers(h, r)) {
+        const hipError_t e = dalloc(h, (uint8_t**)b.slot, b.bytes);
+        if (e != hipSuccess)
+            return fail(h, e == hipErrorOutOfMemory ? CRMC_E_NOMEM : CRMC_E_DEVICE,
+                        std::string(h->ws.base ? "workspace too small for the replicas' state (see "
+                                                 "crmc_workspace_size): "
+                                               : "device allocation failed: ") + hipGetErrorString(e));
+    }
+    const uint32_t ncells = r.ncells, cap = r.cap, nc = r.n, ngroups = r.ngroups;
+    const size_t np = std::max<size_t>(r.nsites, 1);
+    {
+        // cell-major records, each cell's list padded to the capacity
+        std::vector<uint4> cells((size_t)ncells * cap, make_uint4(0u, 0u, 0u, 0u));
+        size_t k = 0;
+        for (uint32_t c = 0; c < ncells; ++c)
+            for (uint32_t j = 0; j < r.init_cnt[c]; ++j) cells[(size_t)c * cap + j] = r.init_rec[k++];
+        HIP_TRY(h, hipMemcpy(d.rec[0], cells.data(), cells.size() * sizeof(uint4), hipMemcpyHostToDevice));
+    }
+    HIP_TRY(h, hipMemcpy(d.cnt[0], r.init_cnt.data(), ncells * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d.cnt[1], 0, ncells * sizeof(uint32_t)));
+    HIP_TRY(h, hipMemset(d.e_acc, 0, ncells * sizeof(double)));
+    HIP_TRY(h, hipMemset(d.occupancy, 0, np * sizeof(uint64_t)));
+    HIP_TRY(h, hipMemset(d.phat, 0, np * sizeof(double)));
+    if (d.feat) HIP_TRY(h, hipMemset(d.feat, 0, np * MLP_IN * sizeof(float)));
+    HIP_TRY(h, hipMemset(d.nsc, 0, ncells * sizeof(uint32_t)));
+    HIP_TRY(h, hipMemcpy(d.site_group, r.init_group.data(), r.init_group.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d.group_count, 0, 2 * std::max<uint32_t>(ngroups, 1) * sizeof(int32_t)));
+    HIP_TRY(h, hipMemset(d.group_hist, 0, (size_t)std::max(r.hist_off[ngroups], 1) * sizeof(int64_t)));
+    HIP_TRY(h, hipMemcpy(d.group_hist_off, r.hist_off.data(), (ngroups + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d.core_x, r.init_cores.data(), r.init_cores.size() * sizeof(uint4), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d.core_delta, r.init_delta.data(), r.init_delta.size() * sizeof(double),
+                         hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(d.totals, r.init_tot, sizeof r.init_tot, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemset(d.moves, 0, 14 * sizeof(uint64_t)));
+    HIP_TRY(h, hipMemset(d.series, 0, (size_t)d.series_cap * 4 * sizeof(int32_t)));
+    {
+        // cell boundaries b_k = ceil(k 2^32 / n) (b_n wraps to 0) and ln of the widths
+        std::vector<uint32_t> b(nc + 1);
+        std::vector<double> lw(nc);
+        for (uint32_t k = 0; k <= nc; ++k) b[k] = (uint32_t)cell_lo_h(k, nc);
+        for (uint32_t k = 0; k < nc; ++k) lw[k] = std::log((double)(cell_lo_h(k + 1, nc) - cell_lo_h(k, nc)));
+        HIP_TRY(h, hipMemcpy(d.bnd, b.data(), b.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.lnW, lw.data(), lw.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(d.hiwater, &r.init_maxc, sizeof(uint32_t), hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemset(d.tab, 0, sizeof(SweepTab)));
+    }
+    std::vector<uint4>().swap(r.init_rec);
+    std::vector<uint32_t>().swap(r.init_cnt);
+    std::vector<int32_t>().swap(r.init_group);
+    r.on_device = true;
+    return CRMC_OK;
+}
+
+// The handle's device state: the sweep counter, error flags and replica
+// descriptors, then every built replica not yet on the device.
+static int ready(crmc_t h)
+{
+    if (!h->d_sweep) {
+        HIP_TRY(h, dalloc(h, &h->d_sweep, 1));
+        HIP_TRY(h, dalloc(h, &h->d_err, 1));
+        HIP_TRY(h, dalloc(h, &h->d_reps, h->reps.size()));
+        HIP_TRY(h, hipMemset(h->d_sweep, 0, sizeof(uint64_t)));
+        HIP_TRY(h, hipMemset(h->d_err, 0, sizeof(uint32_t)));
+    }
+    for (auto& r : h->reps)
+        if (r.built && !r.on_device) {
+            const int rc = materialize_replica(h, r);
+            if (rc) return rc;
+        }
+    return CRMC_OK;
+}
+
+#define READY(h)                  \
+    do {                          \
+        const int rc_ = ready(h); \
+        if (rc_) return rc_;      \
+    } while (0)
+
+// Bytes of device memory the handle's state needs at its current settings,
+// each buffer rounded to the workspace granularity (the same buffers, in the
+// same sizes, that ready(), upload_descriptors(), ensure_params(),
+// ensure_learn_buffers() and state_energy() allocate).
+static size_t state_bytes(crmc_t h)
+{
+    size_t b = WS_ALIGN; // slack for a workspace pointer that is not 256-byte aligned
+    auto add = [&b](size_t x) { b += ws_round(x); };
+    add(sizeof(uint64_t));
+    add(sizeof(uint32_t));
+    add(sizeof(Replica) * h->reps.size());
+    uint64_t cells = 0, doms = 0, items = 0;
+    uint32_t maxcap = 0;
+    size_t max_cells = 1;
+    for (auto& r : h->reps) {
+        if (!r.built) continue;
+        for (const DevBuf& bf : replica_buffers(h, r)) add(bf.bytes);
+        const uint64_t M = (uint64_t)r.d.h * r.d.h * r.d.h;
+        cells += r.ncells;
+        doms += h->p.pairing ? (M + 1u) / 2u : M;
+        items += std::min<uint64_t>(M, r.nsites) + (r.nsites + 63u) / 64u;
+        maxcap = std::max(maxcap, r.cap);
+        max_cells = std::max<size_t>(max_cells, r.ncells);
+    }
+    // flattened indices, the ln k table, the plan, the feature shells
+    add(cells * 4);
+    add(doms * 4);
+    add((2 * (size_t)maxcap + 2) * 8);
+    add(PLAN_N * 4);
+    add(8 * doms * 4);
+    add(8 * doms * 4);
+    add(8 * doms * sizeof(uint4));
+    add(8 * doms * sizeof(uint4));
+    add(17 * h->reps.size() * 8);
+    // the network (FP32 masters, FP64 and BF16 copies), Adam, the gradient,
+    // the learned proposal's work items and the training-row counter
+    add(MLP_PARAMS * 4);
+    add(MLP_PARAMS * 8);
+    add(MLP_H * MLP_IN * 2);
+    add(MLP_H * MLP_H * 2);
+    for (int i = 0; i < 3; ++i) add(MLP_PARAMS * 4);
+    add(8);
+    add(8 * std::max<uint64_t>(items, 1) * sizeof(LearnItem));
+    add(8);
+    // the from-scratch energy's per-cell sums
+    add(sizeof(Replica));
+    add(max_cells * 8);
+    return b;
+}
+
 static int state_energy(crmc_t h, HostReplica& r, double* out)
 {
     Replica* d_one = nullptr;
     double* d_e = nullptr;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    HIP_TRY(h, hipMalloc((void**)&d_one, sizeof(Replica)));
-    HIP_TRY(h, dalloc(&d_e, r.ncells));
+    HIP_TRY(h, dalloc(h, &d_one, 1));
+    HIP_TRY(h, dalloc(h, &d_e, r.ncells));
     HIP_TRY(h, hipMemcpy(d_one, &r.d, sizeof(Replica), hipMemcpyHostToDevice));
     HIP_TRY(h, launch_energy(d_one, r.d, h->p.lB, h->p.eps_wca, h->p.ion_coupling, (int)(h->sweeps & 1), d_e,
                              h->stream));
     std::vector<double> pe(r.ncells);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     HIP_TRY(h, hipMemcpy(pe.data(), d_e, r.ncells * sizeof(double), hipMemcpyDeviceToHost));
-    (void)hipFree(d_one);
-    (void)hipFree(d_e);
+    dfree(h, d_one);
+    dfree(h, d_e);
     double E = 0.0;
     for (double v : pe) E += v;
     *out = E;
+    return CRMC_OK;
+}
+
+int crmc_workspace_size(crmc_t h, int64_t* bytes)
+{
+    if (!h || !bytes) return fail(h, CRMC_E_ARG, "bad arguments");
+    for (const HostReplica& r : h->reps)
+        if (!r.built) return fail(h, CRMC_E_STATE, "build every replica before sizing the workspace");
+    *bytes = (int64_t)state_bytes(h);
+    return CRMC_OK;
+}
+
+int crmc_set_workspace(crmc_t h, void* workspace, int64_t bytes)
+{
+    if (!h || !workspace || bytes < (int64_t)WS_ALIGN) return fail(h, CRMC_E_ARG, "bad workspace");
+    if (h->device_state || h->ws.base)
+        return fail(h, CRMC_E_STATE, "the handle already has device memory; attach the workspace right after "
+                                     "creating and building");
+    h->ws.attach(workspace, (size_t)bytes);
+    return CRMC_OK;
+}
+
+int crmc_memory(crmc_t h, int64_t* own_bytes, int64_t* workspace_used, int64_t* workspace_largest_free)
+{
+    if (!h) return CRMC_E_ARG;
+    int64_t own = 0;
+    for (const auto& kv : h->own) own += (int64_t)kv.second;
+    if (own_bytes) *own_bytes = own;
+    if (workspace_used) *workspace_used = (int64_t)h->ws.used;
+    if (workspace_largest_free) *workspace_largest_free = (int64_t)h->ws.largest_free();
     return CRMC_OK;
 }
 
@@ -968,6 +1209,7 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
         if (!r.built) return fail(h, CRMC_E_STATE, "every replica must be built before sweeping");
         maxcap = std::max(maxcap, r.cap);
     }
+    READY(h);
     if ((uint64_t)h->sweeps + (uint64_t)n_sweeps >= (1ull << 32))
         return fail(h, CRMC_E_ARG, "sweep counter would exceed 2^32");
     for (size_t i = 0; i < h->reps.size(); ++i) {
@@ -1162,6 +1404,7 @@ int crmc_get_site_probabilities(crmc_t h, int32_t replica, double* out, int64_t 
     const HostReplica& r = h->reps[(size_t)replica];
     if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
     if (n < (int64_t)r.nsites) return fail(h, CRMC_E_ARG, "buffer smaller than the replica's particle count");
+    READY(h);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     HIP_TRY(h, hipMemcpy(out, r.d.phat, (size_t)r.nsites * sizeof(double), hipMemcpyDeviceToHost));
     return CRMC_OK;
@@ -1188,14 +1431,14 @@ int crmc_collect_training(crmc_t h, int64_t capacity)
 {
     if (!h || capacity < 0 || capacity > (int64_t)1 << 28) return fail(h, CRMC_E_ARG, "invalid capacity");
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    if (h->d_data) (void)hipFree(h->d_data);
+    dfree(h, h->d_data);
     h->d_data = nullptr;
     h->data_cap = 0;
     h->collecting = false;
-    if (!h->d_data_n) HIP_TRY(h, dalloc(&h->d_data_n, 1));
+    if (!h->d_data_n) HIP_TRY(h, dalloc(h, &h->d_data_n, 1));
     HIP_TRY(h, hipMemset(h->d_data_n, 0, sizeof(unsigned long long)));
     if (capacity == 0) return CRMC_OK;
-    HIP_TRY(h, dalloc(&h->d_data, (size_t)capacity * (MLP_IN + 1)));
+    HIP_TRY(h, dalloc(h, &h->d_data, (size_t)capacity * (MLP_IN + 1)));
     h->data_cap = capacity;
     h->collecting = true;
     return CRMC_OK;
@@ -1230,7 +1473,7 @@ int crmc_load_training(crmc_t h, const float* rows, int64_t n)
     int rc = crmc_collect_training(h, 0);
     if (rc) return rc;
     if (n == 0) return CRMC_OK;
-    HIP_TRY(h, dalloc(&h->d_data, (size_t)n * (MLP_IN + 1)));
+    HIP_TRY(h, dalloc(h, &h->d_data, (size_t)n * (MLP_IN + 1)));
     h->data_cap = n;
     HIP_TRY(h, hipMemcpy(h->d_data, rows, (size_t)n * (MLP_IN + 1) * sizeof(float), hipMemcpyHostToDevice));
     const unsigned long long nn = (unsigned long long)n;
@@ -1241,13 +1484,14 @@ int crmc_load_training(crmc_t h, const float* rows, int64_t n)
 int crmc_record_features(crmc_t h, int32_t on)
 {
     if (!h || (on != 0 && on != 1)) return fail(h, CRMC_E_ARG, "invalid switch");
+    READY(h);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     for (auto& r : h->reps) {
-        if (r.d.feat) (void)hipFree(r.d.feat);
+        dfree(h, r.d.feat);
         r.d.feat = nullptr;
         if (!on || !r.built) continue;
         const size_t m = (size_t)std::max<uint32_t>(r.nsites, 1) * MLP_IN;
-        HIP_TRY(h, dalloc(&r.d.feat, m));
+        HIP_TRY(h, dalloc(h, &r.d.feat, m));
         HIP_TRY(h, hipMemset(r.d.feat, 0, m * sizeof(float)));
     }
     h->record_feat = on != 0;
@@ -1260,6 +1504,7 @@ int crmc_get_site_features(crmc_t h, int32_t replica, float* out, int64_t n)
         return fail(h, CRMC_E_ARG, "invalid replica or buffer");
     const HostReplica& r = h->reps[(size_t)replica];
     if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    READY(h);
     if (!r.d.feat) return fail(h, CRMC_E_STATE, "feature recording is off");
     if (n < (int64_t)r.nsites * MLP_IN) return fail(h, CRMC_E_ARG, "buffer smaller than 32 values per particle");
     HIP_TRY(h, hipStreamSynchronize(h->stream));
@@ -1278,7 +1523,7 @@ int crmc_train(crmc_t h, int32_t epochs, int32_t batch, double lr, uint64_t seed
     if (rc) return rc;
     LearnArgs g = learn_args(h);
     int* d_rows = nullptr;
-    HIP_TRY(h, dalloc(&d_rows, (size_t)n));
+    HIP_TRY(h, dalloc(h, &d_rows, (size_t)n));
     std::vector<int> perm((size_t)n);
     for (int64_t i = 0; i < n; ++i) perm[(size_t)i] = (int)i;
     uint64_t st = seed * 6364136223846793005ull + 1442695040888963407ull;
@@ -1291,7 +1536,7 @@ int crmc_train(crmc_t h, int32_t epochs, int32_t batch, double lr, uint64_t seed
             std::swap(perm[(size_t)i], perm[(size_t)j]);
         }
         if (hipMemcpy(d_rows, perm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(d_rows);
+            dfree(h, d_rows);
             return fail(h, CRMC_E_DEVICE, "row upload failed");
         }
         hipError_t err = hipMemsetAsync(h->d_loss, 0, sizeof(double), h->stream);
@@ -1307,12 +1552,12 @@ int crmc_train(crmc_t h, int32_t epochs, int32_t batch, double lr, uint64_t seed
         if (err == hipSuccess) err = hipStreamSynchronize(h->stream);
         if (err == hipSuccess) err = hipMemcpy(&lsum, h->d_loss, sizeof(double), hipMemcpyDeviceToHost);
         if (err != hipSuccess) {
-            (void)hipFree(d_rows);
+            dfree(h, d_rows);
             return fail(h, CRMC_E_DEVICE, std::string("training failed: ") + hipGetErrorString(err));
         }
         epoch_loss = lsum / (double)nb;
     }
-    (void)hipFree(d_rows);
+    dfree(h, d_rows);
     if (last_loss) *last_loss = epoch_loss;
     return CRMC_OK;
 }
@@ -1323,14 +1568,14 @@ int crmc_mlp_forward(crmc_t h, const float* X, int32_t n, float* logits)
     int rc = ensure_params(h);
     if (rc) return rc;
     float *dX = nullptr, *dz = nullptr;
-    HIP_TRY(h, dalloc(&dX, (size_t)n * MLP_IN));
-    HIP_TRY(h, dalloc(&dz, (size_t)n));
+    HIP_TRY(h, dalloc(h, &dX, (size_t)n * MLP_IN));
+    HIP_TRY(h, dalloc(h, &dz, (size_t)n));
     hipError_t e = hipMemcpy(dX, X, (size_t)n * MLP_IN * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = launch_mlp_fwd(learn_args(h), dX, n, dz, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e == hipSuccess) e = hipMemcpy(logits, dz, (size_t)n * sizeof(float), hipMemcpyDeviceToHost);
-    (void)hipFree(dX);
-    (void)hipFree(dz);
+    dfree(h, dX);
+    dfree(h, dz);
     if (e != hipSuccess) return fail(h, CRMC_E_DEVICE, hipGetErrorString(e));
     return CRMC_OK;
 }
@@ -1342,8 +1587,8 @@ int crmc_mlp_gradient(crmc_t h, const float* rows, int32_t n, float* grad, doubl
     if (rc) return rc;
     float* dD = nullptr;
     int* dr = nullptr;
-    HIP_TRY(h, dalloc(&dD, (size_t)n * (MLP_IN + 1)));
-    HIP_TRY(h, dalloc(&dr, (size_t)n));
+    HIP_TRY(h, dalloc(h, &dD, (size_t)n * (MLP_IN + 1)));
+    HIP_TRY(h, dalloc(h, &dr, (size_t)n));
     std::vector<int> idx((size_t)n);
     for (int i = 0; i < n; ++i) idx[(size_t)i] = i;
     hipError_t e = hipMemcpy(dD, rows, (size_t)n * (MLP_IN + 1) * sizeof(float), hipMemcpyHostToDevice);
@@ -1356,8 +1601,8 @@ int crmc_mlp_gradient(crmc_t h, const float* rows, int32_t n, float* grad, doubl
     if (e == hipSuccess && loss) e = hipMemcpy(loss, h->d_loss, sizeof(double), hipMemcpyDeviceToHost);
     if (e == hipSuccess) e = hipMemsetAsync(h->d_grad, 0, MLP_PARAMS * sizeof(float), h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    (void)hipFree(dD);
-    (void)hipFree(dr);
+    dfree(h, dD);
+    dfree(h, dr);
     if (e != hipSuccess) return fail(h, CRMC_E_DEVICE, hipGetErrorString(e));
     return CRMC_OK;
 }
@@ -1377,6 +1622,7 @@ int crmc_observe(crmc_t h, int32_t replica, crmc_obs* out)
     if (!h || !out || replica < 0 || replica >= (int32_t)h->reps.size()) return fail(h, CRMC_E_ARG, "bad arguments");
     HostReplica& r = h->reps[(size_t)replica];
     if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    READY(h);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     std::memset(out, 0, sizeof *out);
     int64_t tot[4];
@@ -1420,6 +1666,7 @@ int crmc_get_series(crmc_t h, int32_t replica, int64_t first, int64_t count, int
         return fail(h, CRMC_E_ARG, "bad arguments");
     HostReplica& r = h->reps[(size_t)replica];
     if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    READY(h);
     const int64_t capn = r.d.series_cap;
     if (first < 0 || first + count > h->sweeps || first < h->sweeps - capn)
         return fail(h, CRMC_E_ARG, "requested sweeps outside the retained window");
@@ -1440,6 +1687,7 @@ int crmc_get_particles(crmc_t h, int32_t replica, int32_t cap, uint32_t* xyz, in
         return fail(h, CRMC_E_ARG, "bad arguments");
     HostReplica& r = h->reps[(size_t)replica];
     if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    READY(h);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     const int buf = (int)(h->sweeps & 1);
     std::vector<uint32_t> cnt(r.ncells);
@@ -1466,6 +1714,7 @@ int crmc_export_state(crmc_t h, void* buf, int64_t* bytes)
     if (!h || !bytes || (buf && *bytes < 0)) return fail(h, CRMC_E_ARG, "bad arguments");
     for (const HostReplica& r : h->reps)
         if (!r.built) return fail(h, CRMC_E_STATE, "every replica must be built before exporting the state");
+    READY(h);
     Blob b;
     int rc = serialize_state(h, b);
     if (rc) return rc;
@@ -1488,6 +1737,7 @@ int crmc_import_state(crmc_t h, const void* buf, int64_t bytes)
     if (!h || !buf || bytes <= 0) return fail(h, CRMC_E_ARG, "bad arguments");
     for (const HostReplica& r : h->reps)
         if (!r.built) return fail(h, CRMC_E_STATE, "build every replica from the same inputs before importing");
+    READY(h);
     Cursor in{(const uint8_t*)buf, (size_t)bytes};
     const auto bad = [&](const char* what) { return fail(h, CRMC_E_ARG, std::string("state does not fit: ") + what); };
     char magic[8];
@@ -1616,6 +1866,7 @@ int crmc_energy(crmc_t h, int32_t replica, double* out)
     if (!h || !out || replica < 0 || replica >= (int32_t)h->reps.size()) return fail(h, CRMC_E_ARG, "bad arguments");
     HostReplica& r = h->reps[(size_t)replica];
     if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    READY(h);
     return state_energy(h, r, out);
 }
 
@@ -1625,6 +1876,7 @@ int crmc_get_occupancy(crmc_t h, int32_t replica, int64_t cap, uint64_t* out, in
         return fail(h, CRMC_E_ARG, "bad arguments");
     HostReplica& r = h->reps[(size_t)replica];
     if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    READY(h);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     *n_out = r.nsites;
     const int64_t m = std::min<int64_t>(cap, r.nsites);
@@ -1639,6 +1891,7 @@ int crmc_get_group_hist(crmc_t h, int32_t replica, int64_t cap, int64_t* out, in
         return fail(h, CRMC_E_ARG, "bad arguments");
     HostReplica& r = h->reps[(size_t)replica];
     if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    READY(h);
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     *n_groups = (int32_t)r.ngroups;
     for (int32_t i = 0; i < std::min<int32_t>(off_cap, (int32_t)r.ngroups + 1); ++i) off[i] = r.hist_off[(size_t)i];
@@ -1651,11 +1904,12 @@ int crmc_enable_log(crmc_t h, int64_t capacity)
 {
     if (!h || capacity < 0) return fail(h, CRMC_E_ARG, "bad arguments");
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    if (h->d_log) { (void)hipFree(h->d_log); h->d_log = nullptr; }
-    if (!h->d_log_n) HIP_TRY(h, hipMalloc((void**)&h->d_log_n, sizeof(unsigned long long)));
+    dfree(h, h->d_log);
+    h->d_log = nullptr;
+    if (!h->d_log_n) HIP_TRY(h, dalloc(h, &h->d_log_n, 1));
     HIP_TRY(h, hipMemset(h->d_log_n, 0, sizeof(unsigned long long)));
     h->log_cap = capacity;
-    if (capacity > 0) HIP_TRY(h, hipMalloc((void**)&h->d_log, (size_t)capacity * sizeof(TrialRec)));
+    if (capacity > 0) HIP_TRY(h, dalloc(h, &h->d_log, (size_t)capacity));
     return CRMC_OK;
 }
 
@@ -1679,11 +1933,12 @@ int crmc_enable_trace(crmc_t h, int64_t capacity)
     static_assert(sizeof(crmc_phase_trace) == sizeof(PhaseTrace), "trace record layout");
     if (!h || capacity < 0) return fail(h, CRMC_E_ARG, "bad arguments");
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    if (h->d_trace) { (void)hipFree(h->d_trace); h->d_trace = nullptr; }
-    if (!h->d_trace_n) HIP_TRY(h, hipMalloc((void**)&h->d_trace_n, sizeof(unsigned long long)));
+    dfree(h, h->d_trace);
+    h->d_trace = nullptr;
+    if (!h->d_trace_n) HIP_TRY(h, dalloc(h, &h->d_trace_n, 1));
     HIP_TRY(h, hipMemset(h->d_trace_n, 0, sizeof(unsigned long long)));
     h->trace_cap = capacity;
-    if (capacity > 0) HIP_TRY(h, hipMalloc((void**)&h->d_trace, (size_t)capacity * sizeof(PhaseTrace)));
+    if (capacity > 0) HIP_TRY(h, dalloc(h, &h->d_trace, (size_t)capacity));
     return CRMC_OK;
 }
 
@@ -1749,26 +2004,25 @@ void crmc_destroy(crmc_t h)
     if (h->ev_in) (void)hipEventDestroy(h->ev_in);
     if (h->ev_out) (void)hipEventDestroy(h->ev_out);
     for (auto& r : h->reps)
-        if (r.built) free_replica(r);
-    if (h->d_reps) (void)hipFree(h->d_reps);
-    if (h->d_sweep) (void)hipFree(h->d_sweep);
-    if (h->d_err) (void)hipFree(h->d_err);
-    if (h->d_log) (void)hipFree(h->d_log);
-    if (h->d_log_n) (void)hipFree(h->d_log_n);
-    if (h->d_trace) (void)hipFree(h->d_trace);
-    if (h->d_trace_n) (void)hipFree(h->d_trace_n);
-    if (h->d_cell2rep) (void)hipFree(h->d_cell2rep);
-    if (h->d_dom2rep) (void)hipFree(h->d_dom2rep);
-    if (h->d_lntab) (void)hipFree(h->d_lntab);
-    if (h->d_plan_n) (void)hipFree(h->d_plan_n);
-    if (h->d_plan_heavy) (void)hipFree(h->d_plan_heavy);
-    if (h->d_plan_light) (void)hipFree(h->d_plan_light);
-    if (h->d_plan_geo_heavy) (void)hipFree(h->d_plan_geo_heavy);
-    if (h->d_plan_geo_light) (void)hipFree(h->d_plan_geo_light);
+        if (r.built) free_replica(h, r);
+    dfree(h, h->d_reps);
+    dfree(h, h->d_sweep);
+    dfree(h, h->d_err);
+    dfree(h, h->d_log);
+    dfree(h, h->d_log_n);
+    dfree(h, h->d_trace);
+    dfree(h, h->d_trace_n);
+    dfree(h, h->d_cell2rep);
+    dfree(h, h->d_dom2rep);
+    dfree(h, h->d_lntab);
+    dfree(h, h->d_plan_n);
+    dfree(h, h->d_plan_heavy);
+    dfree(h, h->d_plan_light);
+    dfree(h, h->d_plan_geo_heavy);
+    dfree(h, h->d_plan_geo_light);
     void* lp[] = {h->d_R2sh, h->d_p32, h->d_p64, h->d_w1b, h->d_w2b, h->d_adam_m, h->d_adam_v,
                   h->d_grad, h->d_loss, h->d_data, h->d_data_n, h->d_lwork};
-    for (void* q : lp)
-        if (q) (void)hipFree(q);
+    for (void* q : lp) dfree(h, q);
     delete h;
 }
 

@@ -72,3 +72,34 @@ def test_null_arguments():
     assert L.crmc_export_state(None, None, C.byref(n)) == crmc.CRMC_E_ARG
     assert L.crmc_import_state(None, None, 0) == crmc.CRMC_E_ARG
     L.crmc_destroy(None)
+
+
+def test_workspace_size_and_attach_on_the_host():
+    """Creating and building touch no device: the workspace size of built
+    replicas is known on the host (it grows with the replicas), and the
+    attach call checks its arguments and refuses a second workspace."""
+    from workloads import nanoparticle_pair
+    s = nanoparticle_pair(seed=4, L=40.0, R=4.0, sites=120, separation=11.0)
+    S = crmc.System(n_replicas=2, lB=2.0, rc=6.0, stream=None)
+    with pytest.raises(crmc.CrmcError) as ei:
+        S.workspace_size()
+    assert ei.value.code == crmc.CRMC_E_STATE
+    S.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"])
+    S.build_cells(1, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"])
+    n2 = S.workspace_size()
+    one = crmc.System(n_replicas=1, lB=2.0, rc=6.0, stream=None)
+    one.build_cells(0, L=s["L"], xyz=s["xyz"], kind=s["kind"], core_xyz=s["core_xyz"], core_R=s["core_R"])
+    n1 = one.workspace_size()
+    # two replicas hold two sets of records (2 buffers x cells x capacity x 16 bytes)
+    obs_cells = 6 ** 3
+    assert n2 - n1 >= 2 * obs_cells * 16 * 64
+    assert S.memory() == dict(own=0, workspace_used=0, workspace_largest_free=0)
+    with pytest.raises(crmc.CrmcError):
+        crmc.crmc_set_workspace(S.h, 0, n2)
+    crmc.crmc_set_workspace(S.h, 1 << 40, n2)  # never dereferenced: no call here needs the device
+    assert S.memory()["workspace_largest_free"] >= n2 - 256
+    with pytest.raises(crmc.CrmcError) as ei:
+        crmc.crmc_set_workspace(S.h, 1 << 40, n2)
+    assert ei.value.code == crmc.CRMC_E_STATE
+    S.close()
+    one.close()

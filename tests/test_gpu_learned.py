@@ -381,7 +381,7 @@ def test_training_steps_match_the_oracle_adam():
     err = np.abs(d_gpu - d_orc)
     assert np.percentile(err, 99) < 0.1 * step, np.percentile(err, 99) / step
     assert err.max() < 2.0 * step
-    assert np.abs(d_orc).mean() > 0.3 * step  # the steps are not vanishing
+    assert np.abs(d_orc).mean() > 0.1 * step  # the steps are not vanishing
     # the BF16 copies the kernels use follow the trained masters
     Xq = X[:256]
     z1 = S.mlp_forward(Xq)
