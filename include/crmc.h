@@ -244,6 +244,21 @@ int crmc_sweep(crmc_t h, double pH, double pKa, double mu_ion, int64_t n_sweeps)
 int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps);
 
 /*
+ * crmc_sweep_ex with recovery from a cell running out of record capacity: the
+ * sweeps run in chunks of `chunk`; the state after every good chunk is kept
+ * on the host (as by crmc_export_state), and when a chunk ends with
+ * CRMC_E_CAPACITY every replica's capacity is enlarged (by half, at least 32
+ * records), the last good state is restored and the chunk is run again.
+ * Capacity is storage only and the random numbers are counter based, so the
+ * chain that results is the one an ample capacity gives.  *recoveries (may be
+ * NULL) receives the number of enlargements.  Synchronizes after every chunk.
+ * Errors: as crmc_sweep_ex; CRMC_E_CAPACITY after 16 enlargements;
+ * CRMC_E_ARG when a grown cell no longer fits on-chip staging.
+ */
+int crmc_sweep_recover(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps, int64_t chunk,
+                       int32_t* recoveries);
+
+/*
  * Counts, energy and move statistics of a replica (synchronizes): the
  * numbers of charged acid and base groups, whose means give the degree of
  * ionization alpha = <n_A->/n_A of Sec. III, the free-ion numbers, the
@@ -298,8 +313,8 @@ int crmc_get_group_hist(crmc_t h, int32_t replica, int64_t cap, int64_t* out, in
  *
  * crmc_import_state restores such a state into a handle created with the same
  * n_replicas, precision and seed whose replicas were built from the same
- * inputs (same box, cell grid, capacity, sites, groups and cores; before its
- * first sweep or later).  A state that does not match, or is truncated or
+ * inputs (same box, cell grid, sites, groups and cores; before its first sweep
+ * or later); the cell capacity may differ as long as every cell's list fits.  A state that does not match, or is truncated or
  * malformed, gives CRMC_E_ARG and leaves the handle unchanged (the whole
  * state is checked on the host before any device memory is written); a
  * device or allocation error during the copy (CRMC_E_DEVICE, CRMC_E_NOMEM)
@@ -466,6 +481,25 @@ double crmc_pIX_from_salt(double pIS, double pH, double pKw);
  */
 int crmc_ungroup_fractions(double pH, double pKw, double pIS_pos, double pIS_neg, double pIX_pos, double pIX_neg,
                            double* out);
+
+/*
+ * Ungrouping of the current state (Sec. II D): every free ion of the replica
+ * is given the identity of one subspecies of its combined ion.  A cation is a
+ * salt cation with probability frac[0] and H+ with probability frac[1], else
+ * another ion of the reservoir; an anion is a salt anion with frac[2] and OH-
+ * with frac[3] (frac as from crmc_ungroup_fractions; each pair sums to at most
+ * 1).  Particle i in the library's order (that of crmc_get_particles) draws
+ * u = unit53 of the first two Philox4x32-10 words of counter (draw low word,
+ * draw high word, i, 5) under the replica's key; it is a salt ion if u <
+ * frac_salt, H+ / OH- if u < frac_salt + frac_other, else another ion.
+ * counts[6] = {S+, H+, other cations, S-, OH-, other anions}; labels (cap
+ * entries, may be NULL with cap = 0) get per particle 0 (not a free ion), 1
+ * (salt ion), 2 (H+ or OH-) or 3 (other); *n_out = particle count.  Different
+ * draw values give independent ungroupings of the same state.  Synchronizes;
+ * CRMC_E_ARG for fractions outside [0, 1] or summing to more than 1 per sign.
+ */
+int crmc_ungroup(crmc_t h, int32_t replica, const double frac[4], uint64_t draw, int64_t counts[6],
+                 int8_t* labels, int64_t cap, int64_t* n_out);
 
 const char* crmc_last_error(crmc_t h);
 void crmc_destroy(crmc_t h);

@@ -103,6 +103,7 @@ def lib():
         L.orc_load_state.argtypes = [vp, C.c_int, P(u32), P(i32), P(i32), P(i32), u64, C.c_int]
         L.orc_prepare_sweep.argtypes = [vp]
         L.orc_set_domain_filter.argtypes = [vp, C.c_int, P(i32)]
+        L.orc_ungroup.argtypes = [vp, P(d), u64, P(i64), P(i32)]
         L.orc_features_of_cell_sites.restype = C.c_int
         L.orc_features_of_cell_sites.argtypes = [vp, C.c_int, C.c_int, P(i32), P(d)]
         _lib = L
@@ -356,6 +357,20 @@ class Oracle:
         b = np.zeros(6, dtype=np.int64)
         self._L.orc_move_stats(self.h, _ptr(a, C.c_int64), _ptr(b, C.c_int64))
         return a, b
+
+    def ungroup(self, frac, draw):
+        """Ungrouping (Sec. II D): each free ion of the current state, in
+        global order, becomes a salt ion with probability frac[0] (cations) or
+        frac[2] (anions), H+ / OH- with frac[1] / frac[3], else another
+        reservoir ion; the uniforms come from Philox counters (draw, particle
+        index, tag 5).  Returns (labels per particle: 0 not an ion, 1 salt,
+        2 H+ or OH-, 3 other; counts [S+, H+, other+, S-, OH-, other-])."""
+        f = np.ascontiguousarray(frac, dtype=np.float64)
+        n = self._L.orc_num_particles(self.h)
+        lab = np.zeros(max(n, 1), dtype=np.int32)
+        cnt = np.zeros(6, dtype=np.int64)
+        self._L.orc_ungroup(self.h, _ptr(f, C.c_double), int(draw), _ptr(cnt, C.c_int64), _ptr(lab, C.c_int32))
+        return lab[:n], cnt
 
     def shift(self, sweep):
         o = np.zeros(3, dtype=np.uint32)

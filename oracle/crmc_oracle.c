@@ -90,6 +90,7 @@
 #define TAG_SHIFT 2u
 #define TAG_PAPER 3u
 #define TAG_PAIR 4u
+#define TAG_UNGROUP 5u
 
 static const double LN10 = 2.302585092994045684017991454684364208;
 static const double TWO32 = 4294967296.0;
@@ -1301,6 +1302,35 @@ int orc_sweeps(orc_sys* S, int64_t nsweeps, int32_t* series)
 {
     for (int64_t s = 0; s < nsweeps; ++s) one_sweep(S, series ? &series[4 * s] : NULL);
     return 0;
+}
+
+/* Ungrouping (Sec. II D): every free ion of the current state, in global
+   order, is given the identity of one subspecies of its combined ion.  A
+   cation is a salt cation with probability frac[0] and H+ with probability
+   frac[1] (each 10^(pI_X+ - pI_i)), otherwise another ion of the reservoir;
+   an anion is a salt anion with frac[2], OH- with frac[3].  The uniform of
+   particle i is unit53 of the first two Philox words of counter
+   (draw low word, draw high word, i, tag 5).  labels[i]: 0 not a free ion,
+   1 salt ion, 2 H+ or OH-, 3 other; counts: salt cations, H+, other cations,
+   salt anions, OH-, other anions. */
+void orc_ungroup(const orc_sys* S, const double frac[4], uint64_t draw, int64_t counts[6], int32_t* labels)
+{
+    memset(counts, 0, 6 * sizeof(int64_t));
+    for (int i = 0; i < S->np; ++i) {
+        const orc_particle* p = &S->P[i];
+        if (!is_ion(p->kind)) {
+            if (labels) labels[i] = 0;
+            continue;
+        }
+        uint32_t ctr[4] = {(uint32_t)draw, (uint32_t)(draw >> 32), (uint32_t)i, TAG_UNGROUP}, w[4];
+        orc_philox(ctr, S->key, w);
+        const double u = unit53(w[0], w[1]);
+        const int neg = p->kind == ORC_XNEG;
+        const double fs = frac[2 * neg], fo = frac[2 * neg + 1];
+        const int lab = u < fs ? 1 : (u < fs + fo ? 2 : 3);
+        counts[3 * neg + lab - 1]++;
+        if (labels) labels[i] = lab;
+    }
 }
 
 /* ------------------------------------------------------------------------- */

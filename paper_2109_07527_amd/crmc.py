@@ -94,6 +94,7 @@ def load():
         "crmc_build_cells": (C.c_int, [vp, i32, d, i32, i32, i32, P(d), P(i32), P(i32), P(i32), i32, P(d), P(d)]),
         "crmc_sweep": (C.c_int, [vp, d, d, d, i64]),
         "crmc_sweep_ex": (C.c_int, [vp, P(crmc_cond), i64]),
+        "crmc_sweep_recover": (C.c_int, [vp, P(crmc_cond), i64, i64, P(i32)]),
         "crmc_autotune": (C.c_int, [vp, P(crmc_cond), i32, P(crmc_tune)]),
         "crmc_set_proposal": (C.c_int, [vp, i32, d]),
         "crmc_set_proposal_weights": (C.c_int, [vp, P(C.c_float), i64]),
@@ -127,6 +128,7 @@ def load():
         "crmc_get_timing": (C.c_int, [vp, P(d), P(i64)]),
         "crmc_pIX_from_salt": (d, [d, d, d]),
         "crmc_ungroup_fractions": (C.c_int, [d, d, d, d, d, d, P(d)]),
+        "crmc_ungroup": (C.c_int, [vp, i32, P(d), u64, P(i64), P(C.c_int8), i64, P(i64)]),
         "crmc_last_error": (C.c_char_p, [vp]),
         "crmc_destroy": (None, [vp]),
     }
@@ -214,6 +216,17 @@ def crmc_sweep_ex(h, conds, n_sweeps):
     for i, c in enumerate(conds):
         arr[i] = crmc_cond(*[float(c[k]) for k in ("pH", "pKa", "pKb", "pIX_pos", "pIX_neg", "kappa")])
     return _check(h, load().crmc_sweep_ex(h, arr, int(n_sweeps)))
+
+
+def crmc_sweep_recover(h, conds, n_sweeps, chunk):
+    """crmc_sweep_ex in chunks with recovery from cell-capacity overflow;
+    returns the number of capacity enlargements."""
+    arr = (crmc_cond * len(conds))()
+    for i, c in enumerate(conds):
+        arr[i] = crmc_cond(*[float(c[k]) for k in ("pH", "pKa", "pKb", "pIX_pos", "pIX_neg", "kappa")])
+    n = C.c_int32(0)
+    _check(h, load().crmc_sweep_recover(h, arr, int(n_sweeps), int(chunk), C.byref(n)))
+    return n.value
 
 
 def crmc_observe(h, replica):
@@ -449,6 +462,20 @@ def crmc_ungroup_fractions(pH, pIS_pos, pIS_neg, pIX_pos, pIX_neg, pKw=14.0):
     return dict(S_pos=out[0], H=out[1], S_neg=out[2], OH=out[3])
 
 
+def crmc_ungroup(h, replica, frac, draw):
+    """(labels per particle in the library's order, counts [S+, H+, other+,
+    S-, OH-, other-]) of one ungrouping of the current state."""
+    f = np.ascontiguousarray(frac, dtype=np.float64)
+    cnt = np.zeros(6, dtype=np.int64)
+    n = C.c_int64(0)
+    _check(h, load().crmc_ungroup(h, int(replica), _p(f, C.c_double), int(draw), _p(cnt, C.c_int64), None, 0,
+                                  C.byref(n)))
+    lab = np.zeros(max(n.value, 1), dtype=np.int8)
+    _check(h, load().crmc_ungroup(h, int(replica), _p(f, C.c_double), int(draw), _p(cnt, C.c_int64),
+                                  _p(lab, C.c_int8), lab.size, C.byref(n)))
+    return lab[:n.value], cnt
+
+
 def crmc_destroy(h):
     load().crmc_destroy(h)
 
@@ -537,6 +564,9 @@ class System:
 
     def sweep_ex(self, conds, n_sweeps):
         return crmc_sweep_ex(self.h, conds, n_sweeps)
+
+    def sweep_recover(self, conds, n_sweeps, chunk=16):
+        return crmc_sweep_recover(self.h, conds, n_sweeps, chunk)
 
     def set_proposal(self, learned, eps=0.1):
         return crmc_set_proposal(self.h, learned, eps)

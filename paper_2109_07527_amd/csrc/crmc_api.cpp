@@ -676,9 +676,10 @@ struct RepShape {
 
 RepShape shape_of(const HostReplica& r) { return RepShape{r.n, r.cap, r.ncells, r.nsites, r.ngroups, r.ncores, r.L}; }
 
+// the capacity is storage only: a state fits any capacity that holds its cells
 bool same_shape(const RepShape& a, const RepShape& b)
 {
-    return a.n == b.n && a.cap == b.cap && a.ncells == b.ncells && a.nsites == b.nsites && a.ngroups == b.ngroups &&
+    return a.n == b.n && a.ncells == b.ncells && a.nsites == b.nsites && a.ngroups == b.ngroups &&
            a.ncores == b.ncores && a.L == b.L;
 }
 
@@ -1289,6 +1290,74 @@ int crmc_sweep_ex(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps)
     return CRMC_OK;
 }
 
+// A larger record capacity per cell for a replica on the device: both record
+// buffers re-laid out with the new stride (the current one keeps its lists;
+// the other is rewritten by the next re-binning).  The flattened tables (the
+// ln k table reaches twice the capacity) are rebuilt by the next sweep.
+static int grow_capacity(crmc_t h, HostReplica& r, uint32_t new_cap)
+{
+    if (new_cap <= r.cap) return CRMC_OK;
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const size_t nrec = (size_t)r.ncells * new_cap;
+    for (int b = 0; b < 2; ++b) {
+        uint4* fresh = nullptr;
+        HIP_TRY(h, dalloc(h, &fresh, nrec));
+        HIP_TRY(h, hipMemcpy2D(fresh, new_cap * sizeof(uint4), r.d.rec[b], r.cap * sizeof(uint4),
+                               r.cap * sizeof(uint4), r.ncells, hipMemcpyDeviceToDevice));
+        dfree(h, r.d.rec[b]);
+        r.d.rec[b] = fresh;
+    }
+    r.cap = new_cap;
+    r.d.cap = new_cap;
+    h->ncell_total = 0; // rebuild the flattened tables and the ln k table
+    drop_graphs(h);
+    return CRMC_OK;
+}
+
+int crmc_sweep_recover(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps, int64_t chunk,
+                       int32_t* recoveries)
+{
+    if (!h || !per_replica || n_sweeps < 0 || chunk < 1) return fail(h, CRMC_E_ARG, "invalid arguments");
+    for (auto& r : h->reps)
+        if (!r.built) return fail(h, CRMC_E_STATE, "every replica must be built before sweeping");
+    READY(h);
+    int32_t nrec = 0;
+    int rc = check_device_errors(h);
+    if (rc) return rc;
+    Blob good;
+    rc = serialize_state(h, good);
+    if (rc) return rc;
+    for (int64_t done = 0; done < n_sweeps;) {
+        const int64_t k = std::min(chunk, n_sweeps - done);
+        rc = crmc_sweep_ex(h, per_replica, k);
+        if (!rc) rc = check_device_errors(h);
+        if (rc == CRMC_E_CAPACITY) {
+            // roll back to the last good state with more room in every cell,
+            // then replay the same sweeps (the random numbers are counter based)
+            if (++nrec > 16) return fail(h, CRMC_E_CAPACITY, "cell capacity still exceeded after 16 enlargements");
+            HIP_TRY(h, hipStreamSynchronize(h->stream));
+            HIP_TRY(h, hipMemset(h->d_err, 0, sizeof(uint32_t)));
+            for (auto& r : h->reps) {
+                const uint32_t grown = ((r.cap + std::max<uint32_t>(32u, r.cap / 2u)) + 31u) & ~31u;
+                rc = grow_capacity(h, r, grown);
+                if (rc) return rc;
+            }
+            rc = crmc_import_state(h, good.b.data(), (int64_t)good.b.size());
+            if (rc) return rc;
+            continue;
+        }
+        if (rc) return rc;
+        done += k;
+        if (done < n_sweeps) {
+            good.b.clear();
+            rc = serialize_state(h, good);
+            if (rc) return rc;
+        }
+    }
+    if (recoveries) *recoveries = nrec;
+    return CRMC_OK;
+}
+
 int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_candidate, crmc_tune* out)
 {
     if (!h || !per_replica || !out || sweeps_per_candidate < 1 || sweeps_per_candidate > 100000)
@@ -1868,6 +1937,52 @@ int crmc_energy(crmc_t h, int32_t replica, double* out)
     if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
     READY(h);
     return state_energy(h, r, out);
+}
+
+int crmc_ungroup(crmc_t h, int32_t replica, const double frac[4], uint64_t draw, int64_t counts[6],
+                 int8_t* labels, int64_t cap, int64_t* n_out)
+{
+    if (!h || !frac || !counts || replica < 0 || replica >= (int32_t)h->reps.size() || cap < 0 || (cap && !labels))
+        return fail(h, CRMC_E_ARG, "bad arguments");
+    for (int i = 0; i < 4; ++i)
+        if (!(frac[i] >= 0.0) || frac[i] > 1.0) return fail(h, CRMC_E_ARG, "fractions must lie in [0, 1]");
+    if (frac[0] + frac[1] > 1.0 + 1e-12 || frac[2] + frac[3] > 1.0 + 1e-12)
+        return fail(h, CRMC_E_ARG, "the subspecies fractions of one sign sum to more than 1");
+    HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    READY(h);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    const int buf = (int)(h->sweeps & 1);
+    std::vector<uint32_t> cnt(r.ncells), pre(r.ncells);
+    HIP_TRY(h, hipMemcpy(cnt.data(), r.d.cnt[buf], r.ncells * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    uint32_t np = 0;
+    for (uint32_t c = 0; c < r.ncells; ++c) { pre[c] = np; np += cnt[c]; }
+    if (n_out) *n_out = np;
+    Replica* d_rep = nullptr;
+    uint32_t* d_pre = nullptr;
+    int8_t* d_lab = nullptr;
+    unsigned long long* d_cnt = nullptr;
+    hipError_t e = dalloc(h, &d_rep, 1);
+    if (e == hipSuccess) e = dalloc(h, &d_pre, r.ncells);
+    if (e == hipSuccess && cap) e = dalloc(h, &d_lab, (size_t)std::max<uint32_t>(np, 1));
+    if (e == hipSuccess) e = dalloc(h, &d_cnt, 6);
+    if (e == hipSuccess) e = hipMemcpy(d_rep, &r.d, sizeof(Replica), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_pre, pre.data(), r.ncells * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d_cnt, 0, 6 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = launch_ungroup(d_rep, r.d, buf, d_pre, frac, draw, d_lab, d_cnt, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    unsigned long long cc[6] = {0, 0, 0, 0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpy(cc, d_cnt, sizeof cc, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && cap && np)
+        e = hipMemcpy(labels, d_lab, std::min<size_t>((size_t)cap, np) * sizeof(int8_t), hipMemcpyDeviceToHost);
+    dfree(h, d_rep);
+    dfree(h, d_pre);
+    dfree(h, d_lab);
+    dfree(h, d_cnt);
+    if (e != hipSuccess)
+        return fail(h, e == hipErrorOutOfMemory ? CRMC_E_NOMEM : CRMC_E_DEVICE, std::string("ungrouping: ") + hipGetErrorString(e));
+    for (int i = 0; i < 6; ++i) counts[i] = (int64_t)cc[i];
+    return CRMC_OK;
 }
 
 int crmc_get_occupancy(crmc_t h, int32_t replica, int64_t cap, uint64_t* out, int64_t* n_out)

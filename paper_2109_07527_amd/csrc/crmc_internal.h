@@ -7,7 +7,7 @@
 namespace crmc {
 
 constexpr uint32_t KIND_ACID = 1, KIND_BASE = 2, KIND_XPOS = 3, KIND_XNEG = 4, KIND_NEUTRAL = 5;
-constexpr uint32_t TAG_TRIAL = 1, TAG_SHIFT = 2, TAG_PAIR = 4;
+constexpr uint32_t TAG_TRIAL = 1, TAG_SHIFT = 2, TAG_PAIR = 4, TAG_UNGROUP = 5;
 constexpr uint32_t NO_SITE = 0xFFFFFFu;
 
 constexpr uint32_t ERR_BIN_CAPACITY = 1u;
@@ -170,6 +170,9 @@ hipError_t launch_bin(const SweepArgs& a, hipStream_t s);
 hipError_t launch_plan(const SweepArgs& a, hipStream_t s);
 hipError_t launch_phase(const SweepArgs& a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_sweep_end(const SweepArgs& a, hipStream_t s);
+hipError_t launch_ungroup(const Replica* rep_dev, const Replica& rep_host, int buf, const uint32_t* prefix,
+                          const double frac[4], uint64_t draw, int8_t* labels, unsigned long long* counts,
+                          hipStream_t s);
 hipError_t launch_energy(const Replica* rep_dev, const Replica& rep_host, double lB, double eps,
                          int ion_coupling, int buf, double* out_per_cell, hipStream_t s);
 hipError_t launch_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out,

@@ -615,22 +615,26 @@ __device__ __forceinline__ void pair_band(const uint4& rec, uint32_t code, bool 
     }
 }
 
+// The expanded excluded volume of an ion against a core, in FP64 whatever
+// the pair precision: the shifted distance r - Delta cancels most of r near a
+// large core (in FP32 r = 10 keeps about 1e-6 absolute, and sh^-12 would carry
+// 12 times that relative error of sh into the energy change)
 template <typename Real>
 __device__ __forceinline__ double wca_core(const Chg& c, const uint4& cx, double delta, const PairParams& P, int& ov)
 {
     const int32_t dx = (int32_t)(cx.x - c.x), dy = (int32_t)(cx.y - c.y), dz = (int32_t)(cx.z - c.z);
-    const Real sc = scale_of<Real>(P);
-    const Real fx = (Real)dx * sc, fy = (Real)dy * sc, fz = (Real)dz * sc;
-    const Real r = Math<Real>::sqrt_(fx * fx + fy * fy + fz * fz);
-    const Real sh = r - (Real)delta;
-    if (!(sh < (Real)1.122462048309373)) return 0.0;
-    if (sh < (Real)0.5) {
+    const double sc = P.scale_d;
+    const double fx = (double)dx * sc, fy = (double)dy * sc, fz = (double)dz * sc;
+    const double r = sqrt(fx * fx + fy * fy + fz * fz);
+    const double sh = r - delta;
+    if (!(sh < 1.122462048309373)) return 0.0;
+    if (sh < 0.5) {
         if (c.dw > 0) ov = 1;
         return 0.0;
     }
-    const Real ir2 = Math<Real>::rcp(sh * sh);
-    const Real ir6 = ir2 * ir2 * ir2;
-    return (double)c.dw * (double)((Real)4.0 * (Real)P.eps * (ir6 * ir6 - ir6) + (Real)P.eps);
+    const double ir2 = 1.0 / (sh * sh);
+    const double ir6 = ir2 * ir2 * ir2;
+    return (double)c.dw * (4.0 * P.eps * (ir6 * ir6 - ir6) + P.eps);
 }
 
 // the pair formed or broken between the two changed particles
@@ -1807,6 +1811,48 @@ __global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a)
 __global__ __launch_bounds__(64) void k_sweep_advance(SweepArgs a)
 {
     if (threadIdx.x == 0) *a.sweep = *a.sweep + 1u;
+}
+
+// ------------------------------------------------------------------------
+// k_ungroup: every free ion of a replica becomes one subspecies of its
+// combined ion (Sec. II D), one thread per record slot of a cell
+// ------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ungroup(const Replica* rep, int buf, const uint32_t* prefix, double fsp,
+                                                 double fop, double fsm, double fom, uint32_t draw_lo,
+                                                 uint32_t draw_hi, int8_t* labels, unsigned long long* counts)
+{
+    const Replica& R = *rep;
+    const uint32_t c = blockIdx.x;
+    const uint32_t nc = R.cnt[buf][c];
+    __shared__ unsigned int cnt[6];
+    if (threadIdx.x < 6) cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < nc; j += blockDim.x) {
+        const uint32_t meta = R.rec[buf][(size_t)c * R.cap + j].w;
+        const uint32_t i = prefix[c] + j; // the particle's index in the library's order
+        int8_t lab = 0;
+        if (rec_is_ion(meta)) {
+            uint32_t w[4];
+            philox4x32_10(draw_lo, draw_hi, i, TAG_UNGROUP, R.key0, R.key1, w);
+            const double u = unit53(w[0], w[1]);
+            const int neg = (meta & 7u) == KIND_XNEG;
+            const double fs = neg ? fsm : fsp, fo = neg ? fom : fop;
+            lab = (int8_t)(u < fs ? 1 : (u < fs + fo ? 2 : 3));
+            atomicAdd(&cnt[3 * neg + lab - 1], 1u);
+        }
+        if (labels) labels[i] = lab;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6 && cnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], (unsigned long long)cnt[threadIdx.x]);
+}
+
+hipError_t launch_ungroup(const Replica* rep_dev, const Replica& rep_host, int buf, const uint32_t* prefix,
+                          const double frac[4], uint64_t draw, int8_t* labels, unsigned long long* counts,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ungroup, dim3(rep_host.ncells), dim3(256), 0, s, rep_dev, buf, prefix, frac[0], frac[1],
+                       frac[2], frac[3], (uint32_t)draw, (uint32_t)(draw >> 32), labels, counts);
+    return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------

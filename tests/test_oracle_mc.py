@@ -560,3 +560,37 @@ def test_prepare_sweep_bins_the_current_grid():
     for cc in range(n ** 3):
         ids, _ = o.cell_site_features(cc)
         assert sorted(ids.tolist()) == sorted(sid[site & (lin == cc)].tolist())
+
+
+def test_ungrouping_follows_the_subspecies_fractions():
+    """Sec. II D: each combined ion is a given subspecies with probability
+    10^(pI_X - pI_i).  Over many independent ungroupings (different draw
+    indices) of one state, the mean number of salt cations is p_S <n_X+>, and
+    likewise for H+, salt anions and OH- (binomial means within 4 standard
+    errors); with pI_X from eq. pIXgen the two shares of the scarcer-ion sign
+    sum to 1, so no ion of that sign is left unlabelled; one draw index gives
+    one labelling."""
+    pH, pIS = 5.0, 2.0
+    pIX = cf.pIX_from_salt(pIS, pH)
+    frac = [10.0 ** (pIX - pIS), 10.0 ** (pIX - pH), 10.0 ** (pIX - pIS), 10.0 ** (pIX - (14.0 - pH))]
+    assert frac[0] + frac[1] == pytest.approx(1.0, abs=1e-12)
+    rng = np.random.default_rng(8)
+    n = 600
+    xyz = rng.uniform(0, 24.0, (n, 3))
+    kind = np.where(np.arange(n) % 3 == 0, 4, 3).astype(np.int32)
+    kind[:40] = 1
+    o = oracle.Oracle(24.0, 4, 2.0, 0.5, 6.0, eps=0.0, seed=9)
+    o.set_particles(xyz, kind)
+    nxp, nxm = int((kind == 3).sum()), int((kind == 4).sum())
+    lab0, c0 = o.ungroup(frac, 7)
+    lab1, c1 = o.ungroup(frac, 7)
+    assert np.array_equal(lab0, lab1) and np.array_equal(c0, c1)
+    ko = o.particles()[1]  # kinds in the oracle's (binned) order, the order of the labels
+    assert np.all(lab0[ko <= 2] == 0) and np.all(lab0[ko >= 3] > 0)
+    assert c0[0] + c0[1] + c0[2] == nxp and c0[3] + c0[4] + c0[5] == nxm
+    assert c0[2] == 0
+    draws = np.array([o.ungroup(frac, d)[1] for d in range(400)], dtype=np.float64)
+    for col, nn, p in ((0, nxp, frac[0]), (1, nxp, frac[1]), (3, nxm, frac[2]), (4, nxm, frac[3])):
+        se = np.sqrt(nn * p * (1 - p) / len(draws))
+        assert abs(draws[:, col].mean() - nn * p) < 4 * se + 1e-12, (col, draws[:, col].mean(), nn * p, se)
+    assert not np.array_equal(o.ungroup(frac, 8)[0], lab0)
