@@ -288,6 +288,21 @@ int crmc_get_particles(crmc_t h, int32_t replica, int32_t cap, uint32_t* xyz, in
 /* Total energy of the current state recomputed from scratch (kT). */
 int crmc_energy(crmc_t h, int32_t replica, double* out);
 
+/*
+ * crmc_energy without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same kernel and the same summation
+ * order as crmc_energy, so the result is bit-identical; its per-cell partial
+ * sums and the replica descriptor go to a fixed device array of the library
+ * (8 MiB + 1 KiB per GPU, held until the process ends), so replicas of at
+ * most 2^20 cells are accepted (CRMC_E_ARG otherwise).  The replica's device
+ * state must already exist (CRMC_E_STATE before the first call that creates
+ * it, e.g. a sweep).  Calls on one GPU share that array: calls that overlap
+ * in time on one GPU (other host threads, other handles) race and must be
+ * serialized by the caller.  Synchronizes.
+ */
+int crmc_energy_noalloc(crmc_t h, int32_t replica, double* out);
+
 /* Per-site count of sweeps at whose start the site was charged (n_sites values). */
 int crmc_get_occupancy(crmc_t h, int32_t replica, int64_t cap, uint64_t* out, int64_t* n_out);
 

@@ -115,6 +115,7 @@ def load():
         "crmc_get_series": (C.c_int, [vp, i32, i64, i64, P(i32)]),
         "crmc_get_particles": (C.c_int, [vp, i32, i32, P(u32), P(i32), P(i32), P(i32), P(i32)]),
         "crmc_energy": (C.c_int, [vp, i32, P(d)]),
+        "crmc_energy_noalloc": (C.c_int, [vp, i32, P(d)]),
         "crmc_export_state": (C.c_int, [vp, vp, P(i64)]),
         "crmc_import_state": (C.c_int, [vp, vp, i64]),
         "crmc_get_occupancy": (C.c_int, [vp, i32, i64, P(u64), P(i64)]),
@@ -277,6 +278,12 @@ def crmc_import_state(h, state):
 def crmc_energy(h, replica):
     e = C.c_double(0.0)
     _check(h, load().crmc_energy(h, int(replica), C.byref(e)))
+    return e.value
+
+
+def crmc_energy_noalloc(h, replica):
+    e = C.c_double(0.0)
+    _check(h, load().crmc_energy_noalloc(h, int(replica), C.byref(e)))
     return e.value
 
 

@@ -1939,6 +1939,36 @@ int crmc_energy(crmc_t h, int32_t replica, double* out)
     return state_energy(h, r, out);
 }
 
+int crmc_energy_noalloc(crmc_t h, int32_t replica, double* out)
+{
+    if (!h || !out || replica < 0 || replica >= (int32_t)h->reps.size()) return fail(h, CRMC_E_ARG, "bad arguments");
+    HostReplica& r = h->reps[(size_t)replica];
+    if (!r.built) return fail(h, CRMC_E_STATE, "replica not built");
+    if (!r.on_device)
+        return fail(h, CRMC_E_STATE, "the replica's device state does not exist yet (it would have to be allocated)");
+    if ((size_t)r.ncells > NOALLOC_CELLS)
+        return fail(h, CRMC_E_ARG, "more cells than the fixed scratch holds (" + std::to_string(NOALLOC_CELLS) + ")");
+    void* base = nullptr;
+    HIP_TRY(h, noalloc_scratch(&base));
+    Replica* d_rep = (Replica*)base;
+    double* d_e = (double*)((char*)base + NOALLOC_DESC_BYTES);
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    HIP_TRY(h, hipMemcpyAsync(d_rep, &r.d, sizeof(Replica), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(h, launch_energy(d_rep, r.d, h->p.lB, h->p.eps_wca, h->p.ion_coupling, (int)(h->sweeps & 1), d_e,
+                             h->stream));
+    // the per-cell sums, added on the host in cell order (as crmc_energy does)
+    double chunk[2048];
+    double E = 0.0;
+    for (size_t c0 = 0; c0 < r.ncells; c0 += 2048) {
+        const size_t m = std::min<size_t>(2048, r.ncells - c0);
+        HIP_TRY(h, hipMemcpyAsync(chunk, d_e + c0, m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        for (size_t i = 0; i < m; ++i) E += chunk[i];
+    }
+    *out = E;
+    return CRMC_OK;
+}
+
 int crmc_ungroup(crmc_t h, int32_t replica, const double frac[4], uint64_t draw, int64_t counts[6],
                  int8_t* labels, int64_t cap, int64_t* n_out)
 {

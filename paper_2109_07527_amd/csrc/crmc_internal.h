@@ -170,6 +170,11 @@ hipError_t launch_bin(const SweepArgs& a, hipStream_t s);
 hipError_t launch_plan(const SweepArgs& a, hipStream_t s);
 hipError_t launch_phase(const SweepArgs& a, size_t lds_bytes, hipStream_t s);
 hipError_t launch_sweep_end(const SweepArgs& a, hipStream_t s);
+// fixed scratch of crmc_energy_noalloc (see noalloc_scratch)
+constexpr size_t NOALLOC_DESC_BYTES = 1024;
+constexpr size_t NOALLOC_CELLS = (size_t)1 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch(void** out);
 hipError_t launch_ungroup(const Replica* rep_dev, const Replica& rep_host, int buf, const uint32_t* prefix,
                           const double frac[4], uint64_t draw, int8_t* labels, unsigned long long* counts,
                           hipStream_t s);

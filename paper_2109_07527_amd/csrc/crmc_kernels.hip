@@ -27,6 +27,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 namespace crmc {
 
 // ------------------------------------------------------------------------
@@ -1985,6 +1987,35 @@ hipError_t launch_sweep_end(const SweepArgs& a, hipStream_t s)
     hipLaunchKernelGGL(k_sweep_end, dim3((a.nrep + 3u) / 4u), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_sweep_advance, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
+}
+
+// Fixed device scratch of the energy entry point that allocates nothing: the
+// replica's descriptor in its first NOALLOC_DESC_BYTES, then one FP64 sum per
+// cell for at most NOALLOC_CELLS cells (8 MiB + 1 KiB per device, held until
+// the process ends).  Host code never passes the symbol itself to a kernel or
+// a copy: noalloc_scratch() resolves its address on the current device once
+// and hands out that pointer.
+static __device__ __align__(256) unsigned char scratch[NOALLOC_DESC_BYTES + NOALLOC_CELLS * sizeof(double)];
+
+static_assert(sizeof(Replica) <= NOALLOC_DESC_BYTES, "the descriptor slot holds a replica descriptor");
+
+hipError_t noalloc_scratch(void** out)
+{
+    static std::mutex mu;
+    static void* ptr[NOALLOC_MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_energy(const Replica* rep_dev, const Replica& rep_host, double lB, double eps, int ion_coupling,
