@@ -104,6 +104,9 @@ def lib():
         L.orc_prepare_sweep.argtypes = [vp]
         L.orc_set_domain_filter.argtypes = [vp, C.c_int, P(i32)]
         L.orc_ungroup.argtypes = [vp, P(d), u64, P(i64), P(i32)]
+        L.orc_md.restype = d
+        L.orc_md.argtypes = [vp, i64, d, d]
+        L.orc_forces.argtypes = [vp, P(d)]
         L.orc_features_of_cell_sites.restype = C.c_int
         L.orc_features_of_cell_sites.argtypes = [vp, C.c_int, C.c_int, P(i32), P(d)]
         _lib = L
@@ -357,6 +360,19 @@ class Oracle:
         b = np.zeros(6, dtype=np.int64)
         self._L.orc_move_stats(self.h, _ptr(a, C.c_int64), _ptr(b, C.c_int64))
         return a, b
+
+    def md(self, nsteps, dt=0.005, gamma=1.0):
+        """A block of Langevin molecular dynamics of the free ions (velocity
+        Verlet, Maxwell-Boltzmann start, friction gamma; units sigma, kT, ion
+        mass).  Returns the mean v^2 per component over ions and steps."""
+        return float(self._L.orc_md(self.h, int(nsteps), float(dt), float(gamma)))
+
+    def forces(self):
+        """Forces on the free ions (zero rows for other particles), global order."""
+        n = self._L.orc_num_particles(self.h)
+        F = np.zeros((max(n, 1), 3))
+        self._L.orc_forces(self.h, _ptr(F, C.c_double))
+        return F[:n]
 
     def ungroup(self, frac, draw):
         """Ungrouping (Sec. II D): each free ion of the current state, in

@@ -91,6 +91,8 @@
 #define TAG_PAPER 3u
 #define TAG_PAIR 4u
 #define TAG_UNGROUP 5u
+#define TAG_MDVEL 6u
+#define TAG_MDNOISE 7u
 
 static const double LN10 = 2.302585092994045684017991454684364208;
 static const double TWO32 = 4294967296.0;
@@ -124,6 +126,7 @@ typedef struct {
     int32_t kind;
     int32_t charged; /* sites: 0/1; free ions: always 1 */
     int32_t sid;     /* site index in input order; -1 for free ions */
+    double v[3];     /* velocity during a molecular-dynamics block (free ions) */
 } orc_particle;
 
 typedef struct {
@@ -163,6 +166,7 @@ typedef struct {
     double* core_delta;
     uint64_t sweep;
     int64_t paper_trial;
+    uint64_t md_step; /* molecular-dynamics steps run so far (counter of their random numbers) */
     double E; /* running energy: brute force at build, then += accepted dU */
     int64_t attempts[6], accepts[6];
     int64_t reloc_att, reloc_acc; /* ion relocation trials */
@@ -1331,6 +1335,154 @@ void orc_ungroup(const orc_sys* S, const double frac[4], uint64_t draw, int64_t 
         counts[3 * neg + lab - 1]++;
         if (labels) labels[i] = lab;
     }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Hybrid MD / CR-MC: Langevin dynamics of the free ions between sweeps       */
+/* ------------------------------------------------------------------------- */
+/* Force on free ion a from the rest of the system: -grad of the energy E of
+   the energy model (screened Coulomb inside the exact integer cutoff, the
+   excluded volume of every pair with a free ion, the expanded excluded volume
+   of the cores).  Brute force over every other particle. */
+static void ion_force(const orc_sys* S, const orc_particle* P, int np, int a, double f[3])
+{
+    const double s = S->L / TWO32;
+    f[0] = f[1] = f[2] = 0.0;
+    const orc_particle* pa = &P[a];
+    const int qa = charge_of(pa->kind, pa->charged);
+    for (int j = 0; j < np; ++j) {
+        if (j == a) continue;
+        const orc_particle* pb = &P[j];
+        if (!S->ion_coupling) continue; /* ideal ions feel nothing */
+        int32_t d[3];
+        lattice_delta(pb->x, pa->x, d); /* from b to a */
+        const uint64_t r2i = (uint64_t)((int64_t)d[0] * d[0]) + (uint64_t)((int64_t)d[1] * d[1]) +
+                             (uint64_t)((int64_t)d[2] * d[2]);
+        const double dx = d[0] * s, dy = d[1] * s, dz = d[2] * s;
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        double g = 0.0; /* -dU/dr / r */
+        const int qb = charge_of(pb->kind, pb->charged);
+        if (r2i < S->R2 && qa != 0 && qb != 0) {
+            const double r = sqrt(r2);
+            g += S->lB * (double)(qa * qb) * exp(-S->kappa * r) * (1.0 + S->kappa * r) / (r2 * r);
+        }
+        if (S->eps > 0.0 && r2 < 1.2599210498948731647672106) {
+            const double ir2 = 1.0 / r2, ir6 = ir2 * ir2 * ir2;
+            g += 4.0 * S->eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir2;
+        }
+        f[0] += g * dx; f[1] += g * dy; f[2] += g * dz;
+    }
+    if (S->ion_coupling && S->eps > 0.0) {
+        for (int c = 0; c < S->nc; ++c) {
+            int32_t d[3];
+            lattice_delta(&S->core_x[3 * c], pa->x, d);
+            const double dx = d[0] * s, dy = d[1] * s, dz = d[2] * s;
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double sh = r - S->core_delta[c];
+            if (sh < 1.122462048309373) {
+                const double ir = 1.0 / sh, ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
+                const double g = 4.0 * S->eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir / r;
+                f[0] += g * dx; f[1] += g * dy; f[2] += g * dz;
+            }
+        }
+    }
+}
+
+/* three standard normal deviates (Box-Muller) from one Philox block */
+static void normals3(const orc_sys* S, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag, double z[3])
+{
+    uint32_t ctr[4] = {c0, c1, c2, tag}, w[4];
+    orc_philox(ctr, S->key, w);
+    const double TWO_PI = 6.283185307179586476925286766559;
+    const double u1 = ((double)w[0] + 1.0) / TWO32, u2 = (double)w[1] / TWO32;
+    const double u3 = ((double)w[2] + 1.0) / TWO32, u4 = (double)w[3] / TWO32;
+    const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+    z[0] = r1 * cos(TWO_PI * u2);
+    z[1] = r1 * sin(TWO_PI * u2);
+    z[2] = r2 * cos(TWO_PI * u4);
+}
+
+/* Forces of all free ions (zero for other particles) in global order (tests). */
+void orc_forces(const orc_sys* S, double* F)
+{
+    for (int i = 0; i < S->np; ++i) {
+        if (is_ion(S->P[i].kind)) ion_force(S, S->P, S->np, i, &F[3 * i]);
+        else F[3 * i] = F[3 * i + 1] = F[3 * i + 2] = 0.0;
+    }
+}
+
+/* A molecular-dynamics block: nsteps velocity-Verlet steps of length dt for
+   the free ions with a Langevin thermostat of friction gamma (the hybrid
+   MD/MC protocol of Sec. III, units sigma, kT and the ion mass, so tau = 1).
+   Sites and cores stay where they are.  At the start every ion gets a
+   Maxwell-Boltzmann velocity; one step is
+     v += dt/2 F;  x += dt v (rounded to the lattice);  F = F_c(x) - gamma v
+     + sqrt(2 gamma / dt) xi;  v += dt/2 F,
+   with F = F_c at the start.  The ions stay binned in the grid of the last
+   sweep: after every drift they are re-binned into it stably, and the
+   random numbers of an ion are addressed by its cell and slot there:
+   Philox counter (step, cell, slot, 6) for the initial velocity and
+   (step, cell, slot, 7) for the noise of a step, step the running count of
+   MD steps.  The retained energy restarts from a brute-force sum.  Returns
+   the mean of v^2 per component over the ions and the steps (the
+   thermostat's temperature check). */
+double orc_md(orc_sys* S, int64_t nsteps, double dt, double gamma)
+{
+    uint32_t o[3] = {0u, 0u, 0u};
+    if (S->sweep > 0) orc_shift(S, S->sweep - 1, o);
+    bin_into_cells(S, o);
+    const double to_lat = TWO32 / S->L;
+    const double noise = sqrt(2.0 * gamma / dt);
+    double v2sum = 0.0;
+    int64_t v2n = 0;
+    /* initial velocities and forces, in the current binning */
+    gather_from_cells(S);
+    double* F = (double*)calloc((size_t)3 * (size_t)(S->np > 0 ? S->np : 1), sizeof(double));
+    {
+        int k = 0;
+        for (int c = 0; c < S->ncells; ++c)
+            for (int j = 0; j < S->cells[c].n; ++j, ++k) {
+                orc_particle* p = &S->P[k];
+                if (!is_ion(p->kind)) { p->v[0] = p->v[1] = p->v[2] = 0.0; continue; }
+                normals3(S, (uint32_t)S->md_step, (uint32_t)c, (uint32_t)j, TAG_MDVEL, p->v);
+            }
+        for (int i = 0; i < S->np; ++i)
+            if (is_ion(S->P[i].kind)) ion_force(S, S->P, S->np, i, &F[3 * i]);
+    }
+    for (int64_t st = 0; st < nsteps; ++st) {
+        const uint64_t g = S->md_step + (uint64_t)st;
+        for (int i = 0; i < S->np; ++i) {
+            orc_particle* p = &S->P[i];
+            if (!is_ion(p->kind)) continue;
+            for (int k = 0; k < 3; ++k) {
+                p->v[k] += 0.5 * dt * F[3 * i + k];
+                p->x[k] = (uint32_t)((int64_t)p->x[k] + llround(dt * p->v[k] * to_lat));
+            }
+        }
+        /* re-bin (stable) into the same grid; forces travel with nothing: they are recomputed */
+        bin_into_cells(S, o);
+        gather_from_cells(S);
+        int k = 0;
+        for (int c = 0; c < S->ncells; ++c)
+            for (int j = 0; j < S->cells[c].n; ++j, ++k) {
+                orc_particle* p = &S->P[k];
+                if (!is_ion(p->kind)) continue;
+                double fc[3], z[3];
+                ion_force(S, S->P, S->np, k, fc);
+                normals3(S, (uint32_t)g, (uint32_t)c, (uint32_t)j, TAG_MDNOISE, z);
+                for (int q = 0; q < 3; ++q) {
+                    F[3 * k + q] = fc[q] - gamma * p->v[q] + noise * z[q];
+                    p->v[q] += 0.5 * dt * F[3 * k + q];
+                    v2sum += p->v[q] * p->v[q];
+                }
+                v2n += 3;
+            }
+    }
+    free(F);
+    S->md_step += (uint64_t)nsteps;
+    /* the cells of the next sweep start from this global order */
+    S->E = orc_energy(S);
+    return v2n ? v2sum / (double)v2n : 0.0;
 }
 
 /* ------------------------------------------------------------------------- */

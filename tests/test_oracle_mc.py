@@ -594,3 +594,109 @@ def test_ungrouping_follows_the_subspecies_fractions():
         se = np.sqrt(nn * p * (1 - p) / len(draws))
         assert abs(draws[:, col].mean() - nn * p) < 4 * se + 1e-12, (col, draws[:, col].mean(), nn * p, se)
     assert not np.array_equal(o.ungroup(frac, 8)[0], lab0)
+
+
+# ------------------------------------------------- molecular dynamics ----
+def _md_system(seed=3):
+    """Sites, a core and free ions, some of them placed inside the reach of
+    the excluded volume of a site, of another ion and of the core."""
+    L = 24.0
+    rng = np.random.default_rng(seed)
+    s = random_sites(12, 10, L, 3, min_dist=1.0)
+    core = np.array([[L / 2, L / 2, L / 2]])
+    R = np.array([3.0])
+    pts = [p for p in s["xyz"]]
+    ions = []
+    # close contacts: 1.0 from a site, an ion pair 0.95 apart, 0.9 outside the core's Delta
+    ions.append(s["xyz"][0] + np.array([1.0, 0.0, 0.0]))
+    ions.append(np.array([3.0, 20.0, 3.0]))
+    ions.append(np.array([3.95, 20.0, 3.0]))
+    ions.append(core[0] + np.array([0.0, 0.0, R[0] - 0.5 + 0.9]))
+    while len(ions) < 30:
+        p = rng.uniform(0, L, 3)
+        d = np.array(pts + ions) - p
+        d -= L * np.round(d / L)
+        dc = p - core[0]
+        if (d ** 2).sum(1).min() > 0.9 ** 2 and np.linalg.norm(dc) > R[0] + 0.4:
+            ions.append(p)
+    xyz = np.concatenate([s["xyz"], np.array(ions)])
+    kind = np.concatenate([s["kind"], np.where(np.arange(30) % 2 == 0, 3, 4)]).astype(np.int32)
+    charged = np.concatenate([(np.arange(22) % 3 == 0).astype(np.int32), np.ones(30, np.int32)])
+    return L, xyz, kind, charged, core, R
+
+
+def test_md_forces_are_minus_the_energy_gradient():
+    """Every free ion's force against central differences of the brute-force
+    total energy (displacements of 1e-6 sigma on the lattice): Coulomb,
+    excluded volume against sites and ions, and the core's expanded excluded
+    volume, all with the right sign and factor."""
+    L, xyz, kind, charged, core, R = _md_system()
+    o = oracle.Oracle(L, 4, 2.0, 0.5, 6.0, eps=1.0, seed=1)
+    o.set_particles(xyz, kind, charged=charged)
+    o.set_cores(core, R)
+    X, k, c, sid = o.particles()
+    F = o.forces()
+    h = int(1e-6 * 2 ** 32 / L)
+
+    def energy_with(i, dim, dl):
+        X2 = X.astype(np.int64)
+        X2[i, dim] = (X2[i, dim] + dl) % 2 ** 32
+        t = oracle.Oracle(L, 4, 2.0, 0.5, 6.0, eps=1.0, seed=1)
+        t.set_cores(core, R)
+        t.load_state(X2.astype(np.uint32), k, c, sid, 0)
+        return t.energy()
+    ions = np.where((k == 3) | (k == 4))[0]
+    assert np.abs(F).max() > 20.0  # the close contacts are exercised
+    for i in ions:
+        for dim in range(3):
+            fd = -(energy_with(i, dim, h) - energy_with(i, dim, -h)) / (2 * h * L / 2 ** 32)
+            assert abs(fd - F[i, dim]) < 1e-6 * max(1.0, abs(F[i, dim])), (i, dim, fd, F[i, dim])
+    assert np.all(F[(k != 3) & (k != 4)] == 0.0)
+
+
+def test_md_thermostat_gives_the_temperature():
+    """Langevin velocity Verlet keeps <v^2> per component at kT / m = 1 for
+    ideal ions (friction 1, step 0.005: the discretisation shifts it by
+    O(gamma dt), a few 1e-3) and with interactions; the retained energy is
+    the brute-force energy after the block."""
+    rng = np.random.default_rng(2)
+    o = oracle.Oracle(24.0, 4, 0.0, 0.5, 6.0, eps=0.0, ion_coupling=0, seed=2)
+    o.set_particles(rng.uniform(0, 24.0, (40, 3)), np.where(np.arange(40) % 2 == 0, 3, 4).astype(np.int32))
+    v2 = o.md(20000, 0.005, 1.0)
+    assert abs(v2 - 1.0) < 0.015, v2
+    L, xyz, kind, charged, core, R = _md_system()
+    o = oracle.Oracle(L, 4, 2.0, 0.5, 6.0, eps=1.0, seed=3)
+    o.set_particles(xyz, kind, charged=charged)
+    o.set_cores(core, R)
+    v2 = o.md(20000, 0.005, 1.0)
+    # 90 degrees of freedom decorrelating over ~1/(2 gamma) = 100 steps: SE about 0.01
+    assert abs(v2 - 1.0) < 0.045, v2
+    assert o.running_energy() == pytest.approx(o.energy(), abs=1e-12)
+    X, k, _, _ = o.particles()
+    assert np.array_equal(np.sort(k), np.sort(kind))  # the block moves ions, it creates and deletes none
+
+
+def test_hybrid_md_and_cell_schedule_reach_the_one_site_quadrature():
+    """The paper's hybrid protocol (Sec. III: blocks of 400 Langevin MD steps
+    of length 0.005 between blocks of MC): on the cell schedule without
+    relocation trials, MD moves the lone counter-ion, and P(ionized) of one
+    acid site at dilute salt matches the quadrature (T-6), which the six
+    cell-local moves alone do not reach in finite runs (R-4).  Independent
+    seeds give the standard error."""
+    pIX = cf.pIX_from_salt(6.0, 7.5)
+    ex = cf.one_site_ion_probability(24.0, 8.0, 0.5, 6.0, 7.5, 4.5, pIX, RHO)
+    vals = []
+    for seed in range(10):
+        o = oracle.Oracle(24.0, 4, 8.0, 0.5, 6.0, eps=1.0, seed=700 + seed)
+        o.set_conditions(7.5, 4.5, 5.0, pIX, pIX)
+        o.set_particles(np.array([[12.0, 12.0, 12.0]]), np.array([1]))
+        o.set_schedule(8)
+        ser = []
+        for _ in range(3500):
+            ser.append(o.sweeps(1)[0, 0])
+            o.md(400, 0.005, 1.0)
+        vals.append(np.mean(ser[300:]))
+    v = np.array(vals)
+    m, se = v.mean(), v.std(ddof=1) / np.sqrt(len(v))
+    assert abs(m - ex) < 3.5 * se, (m, ex, se)
+    assert se < 0.03
