@@ -259,6 +259,27 @@ int crmc_sweep_recover(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps,
                        int32_t* recoveries);
 
 /*
+ * Hybrid MD / CR-MC (Sec. III: blocks of MD steps between blocks of MC
+ * steps): n_steps of Langevin molecular dynamics of the free ions of every
+ * replica, velocity Verlet with time step dt and friction gamma (units sigma,
+ * kT and the ion mass, tau = 1; the paper runs dt = 0.005 and n_MD = 400).
+ * Sites and cores stay fixed.  Every ion starts the block with a
+ * Maxwell-Boltzmann velocity; a step is v += dt/2 F; x += dt v (rounded to
+ * the position lattice); F = F_c(x) - gamma v + sqrt(2 gamma / dt) xi;
+ * v += dt/2 F, F_c = -grad E of the energy model in FP64 (cells are at least
+ * rc wide, so the 27 cells around an ion hold every partner).  After every
+ * drift the ions are re-binned stably into the grid of the last sweep; the
+ * random numbers of an ion come from Philox counters (step, cell, slot, 6)
+ * (start velocity) and (step, cell, slot, 7) (noise), step the handle's
+ * running count of MD steps (part of the exported state).  The retained energy
+ * restarts from a from-scratch sum after the block.  Uses 72 bytes per record
+ * slot of device memory (made at the first block, not in crmc_workspace_size).
+ * Synchronizes.  Errors: CRMC_E_ARG for dt <= 0 or gamma < 0; CRMC_E_CAPACITY
+ * when a cell overflowed.
+ */
+int crmc_md(crmc_t h, int64_t n_steps, double dt, double gamma);
+
+/*
  * Counts, energy and move statistics of a replica (synchronizes): the
  * numbers of charged acid and base groups, whose means give the degree of
  * ionization alpha = <n_A->/n_A of Sec. III, the free-ion numbers, the

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcrmc.so")
-SOURCES = ["crmc_kernels.hip", "crmc_learn.hip", "crmc_api.cpp"]
+SOURCES = ["crmc_kernels.hip", "crmc_learn.hip", "crmc_md.hip", "crmc_api.cpp"]
 ARCH = os.environ.get("CRMC_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for every device compile.

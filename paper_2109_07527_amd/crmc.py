@@ -95,6 +95,7 @@ def load():
         "crmc_sweep": (C.c_int, [vp, d, d, d, i64]),
         "crmc_sweep_ex": (C.c_int, [vp, P(crmc_cond), i64]),
         "crmc_sweep_recover": (C.c_int, [vp, P(crmc_cond), i64, i64, P(i32)]),
+        "crmc_md": (C.c_int, [vp, i64, d, d]),
         "crmc_autotune": (C.c_int, [vp, P(crmc_cond), i32, P(crmc_tune)]),
         "crmc_set_proposal": (C.c_int, [vp, i32, d]),
         "crmc_set_proposal_weights": (C.c_int, [vp, P(C.c_float), i64]),
@@ -228,6 +229,10 @@ def crmc_sweep_recover(h, conds, n_sweeps, chunk):
     n = C.c_int32(0)
     _check(h, load().crmc_sweep_recover(h, arr, int(n_sweeps), int(chunk), C.byref(n)))
     return n.value
+
+
+def crmc_md(h, n_steps, dt=0.005, gamma=1.0):
+    return _check(h, load().crmc_md(h, int(n_steps), float(dt), float(gamma)))
 
 
 def crmc_observe(h, replica):
@@ -571,6 +576,10 @@ class System:
 
     def sweep_ex(self, conds, n_sweeps):
         return crmc_sweep_ex(self.h, conds, n_sweeps)
+
+    def md(self, n_steps, dt=0.005, gamma=1.0):
+        """A block of Langevin molecular dynamics of the free ions."""
+        return crmc_md(self.h, n_steps, dt, gamma)
 
     def sweep_recover(self, conds, n_sweeps, chunk=16):
         return crmc_sweep_recover(self.h, conds, n_sweeps, chunk)

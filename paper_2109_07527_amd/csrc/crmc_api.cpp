@@ -40,6 +40,8 @@ struct HostReplica {
     // needs the device state (so that a workspace can still be attached):
     // records in cell order, cell counts, per-site groups, cores.
     bool on_device = false;
+    double* md_vel[2] = {nullptr, nullptr}; // molecular dynamics: 3 doubles per record slot per buffer
+    double* md_force = nullptr;
     std::vector<uint4> init_rec;
     std::vector<uint32_t> init_cnt;
     std::vector<int32_t> init_group;
@@ -184,6 +186,10 @@ struct crmc_s {
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     std::vector<uint8_t> gargs; // launch arguments the captured graphs were recorded with
+    // molecular dynamics: steps run so far (counter of their random numbers), pointer tables
+    uint64_t md_steps = 0;
+    double** d_md_vel = nullptr;   // 2 per replica
+    double** d_md_force = nullptr; // 1 per replica
     // recorded per-site features (checks of the learned proposal)
     bool record_feat = false;
 };
@@ -263,6 +269,9 @@ void free_replica(crmc_t h, HostReplica& r)
                     d.group_count, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
                     d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab, d.phat, d.nsc, d.feat};
     for (void* q : ptrs) dfree(h, q);
+    for (double*& q : r.md_vel) { dfree(h, q); q = nullptr; }
+    dfree(h, r.md_force);
+    r.md_force = nullptr;
     d = Replica{};
     r.built = false;
     r.on_device = false;
@@ -642,7 +651,7 @@ int check_device_errors(crmc_t h)
 namespace {
 
 constexpr char STATE_MAGIC[8] = {'C', 'R', 'M', 'C', 'S', 'T', 'A', 'T'};
-constexpr uint32_t STATE_VERSION = 1;
+constexpr uint32_t STATE_VERSION = 2;
 
 struct Blob {
     std::vector<uint8_t> b;
@@ -695,6 +704,7 @@ int serialize_state(crmc_t h, Blob& out)
     out.put((uint32_t)0);
     out.put(h->p.seed);
     out.put((int64_t)h->sweeps);
+    out.put((uint64_t)h->md_steps);
     const int buf = (int)(h->sweeps & 1);
     for (const HostReplica& r : h->reps) {
         out.put(shape_of(r));
@@ -1309,6 +1319,9 @@ static int grow_capacity(crmc_t h, HostReplica& r, uint32_t new_cap)
     }
     r.cap = new_cap;
     r.d.cap = new_cap;
+    for (double*& q : r.md_vel) { dfree(h, q); q = nullptr; }
+    dfree(h, r.md_force);
+    r.md_force = nullptr;
     h->ncell_total = 0; // rebuild the flattened tables and the ln k table
     drop_graphs(h);
     return CRMC_OK;
@@ -1355,6 +1368,76 @@ int crmc_sweep_recover(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps,
         }
     }
     if (recoveries) *recoveries = nrec;
+    return CRMC_OK;
+}
+
+int crmc_md(crmc_t h, int64_t n_steps, double dt, double gamma)
+{
+    if (!h || n_steps < 0 || !(dt > 0.0) || !(gamma >= 0.0) || !std::isfinite(dt) || !std::isfinite(gamma))
+        return fail(h, CRMC_E_ARG, "invalid molecular-dynamics arguments");
+    uint32_t maxcap = 0;
+    for (auto& r : h->reps) {
+        if (!r.built) return fail(h, CRMC_E_STATE, "every replica must be built before molecular dynamics");
+        maxcap = std::max(maxcap, r.cap);
+    }
+    READY(h);
+    int rc = upload_descriptors(h);
+    if (rc) return rc;
+    if (n_steps == 0) return CRMC_OK;
+    // per-slot velocities (both record buffers) and forces, made at the first block
+    std::vector<double*> vel(2 * h->reps.size()), frc(h->reps.size());
+    for (size_t i = 0; i < h->reps.size(); ++i) {
+        HostReplica& r = h->reps[i];
+        const size_t m = (size_t)r.ncells * r.cap * 3;
+        for (int b = 0; b < 2; ++b)
+            if (!r.md_vel[b]) HIP_TRY(h, dalloc(h, &r.md_vel[b], m));
+        if (!r.md_force) HIP_TRY(h, dalloc(h, &r.md_force, m));
+        vel[2 * i] = r.md_vel[0];
+        vel[2 * i + 1] = r.md_vel[1];
+        frc[i] = r.md_force;
+    }
+    if (!h->d_md_vel) HIP_TRY(h, dalloc(h, &h->d_md_vel, vel.size()));
+    if (!h->d_md_force) HIP_TRY(h, dalloc(h, &h->d_md_force, frc.size()));
+    HIP_TRY(h, hipMemcpy(h->d_md_vel, vel.data(), vel.size() * sizeof(double*), hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(h->d_md_force, frc.data(), frc.size() * sizeof(double*), hipMemcpyHostToDevice));
+    MdArgs m;
+    std::memset(&m, 0, sizeof m);
+    m.reps = h->d_reps;
+    m.cell2rep = h->d_cell2rep;
+    m.ncell_total = h->ncell_total;
+    m.vel = h->d_md_vel;
+    m.force = h->d_md_force;
+    m.err = h->d_err;
+    m.lB = h->p.lB;
+    m.eps = h->p.eps_wca;
+    m.dt = dt;
+    m.gamma = gamma;
+    m.noise = std::sqrt(2.0 * gamma / dt);
+    m.ion_coupling = h->p.ion_coupling;
+    const int buf0 = (int)(h->sweeps & 1);
+    int buf = buf0;
+    HIP_TRY(h, launch_md_block(m, buf0, h->md_steps, n_steps, maxcap, h->stream, &buf));
+    if (buf != buf0) {
+        // the sweeps read the records of buffer (sweeps & 1)
+        for (auto& r : h->reps) {
+            HIP_TRY(h, hipMemcpyAsync(r.d.rec[buf0], r.d.rec[buf], (size_t)r.ncells * r.cap * sizeof(uint4),
+                                      hipMemcpyDeviceToDevice, h->stream));
+            HIP_TRY(h, hipMemcpyAsync(r.d.cnt[buf0], r.d.cnt[buf], (size_t)r.ncells * sizeof(uint32_t),
+                                      hipMemcpyDeviceToDevice, h->stream));
+        }
+    }
+    h->md_steps += (uint64_t)n_steps;
+    rc = check_device_errors(h);
+    if (rc) return rc;
+    // positions moved: the retained energy restarts from a from-scratch sum
+    for (auto& r : h->reps) {
+        double E = 0.0;
+        rc = state_energy(h, r, &E);
+        if (rc) return rc;
+        HIP_TRY(h, hipMemset(r.d.e_acc, 0, r.ncells * sizeof(double)));
+        r.E0 = E;
+        r.e0_kappa = r.d.kappa;
+    }
     return CRMC_OK;
 }
 
@@ -1820,6 +1903,8 @@ int crmc_import_state(crmc_t h, const void* buf, int64_t bytes)
     if (!in.get(precision) || precision != h->p.precision) return bad("precision");
     if (!in.get(pad) || !in.get(seed) || seed != h->p.seed) return bad("seed");
     if (!in.get(sweeps) || sweeps < 0 || (uint64_t)sweeps >= (1ull << 32)) return bad("sweep counter");
+    uint64_t md_steps = 0;
+    if (!in.get(md_steps)) return bad("truncated");
 
     // parse everything on the host first; the handle changes only if all of it fits
     struct RepState {
@@ -1913,6 +1998,7 @@ int crmc_import_state(crmc_t h, const void* buf, int64_t bytes)
     const uint64_t s64 = (uint64_t)sweeps;
     HIP_TRY(h, hipMemcpy(h->d_sweep, &s64, sizeof s64, hipMemcpyHostToDevice));
     h->sweeps = sweeps;
+    h->md_steps = md_steps;
     h->learned = learned != 0;
     h->learn_eps = eps;
     if (has_par) {
@@ -2166,7 +2252,7 @@ void crmc_destroy(crmc_t h)
     dfree(h, h->d_plan_geo_heavy);
     dfree(h, h->d_plan_geo_light);
     void* lp[] = {h->d_R2sh, h->d_p32, h->d_p64, h->d_w1b, h->d_w2b, h->d_adam_m, h->d_adam_v,
-                  h->d_grad, h->d_loss, h->d_data, h->d_data_n, h->d_lwork};
+                  h->d_grad, h->d_loss, h->d_data, h->d_data_n, h->d_lwork, h->d_md_vel, h->d_md_force};
     for (void* q : lp) dfree(h, q);
     delete h;
 }

@@ -165,6 +165,18 @@ struct LearnArgs {
     int32_t infer;            // compute site probabilities (else features / rows only)
 };
 
+// arguments of the molecular-dynamics kernels (hybrid MD / CR-MC)
+struct MdArgs {
+    Replica* reps;            // device replica descriptors
+    const uint32_t* cell2rep; // global cell index -> replica
+    uint32_t ncell_total;
+    double* const* vel;       // per replica and record buffer (2 r + buf): 3 doubles per record slot
+    double* const* force;     // per replica: 3 doubles per record slot of the current buffer
+    uint32_t* err;            // device error flags
+    double lB, eps, dt, gamma, noise; // noise = sqrt(2 gamma kT / (m dt)), kT = m = 1
+    int32_t ion_coupling;
+};
+
 // launchers (device translation units)
 hipError_t launch_bin(const SweepArgs& a, hipStream_t s);
 hipError_t launch_plan(const SweepArgs& a, hipStream_t s);
@@ -191,5 +203,7 @@ hipError_t launch_adam(const LearnArgs& g, float* grad, float* m, float* v, floa
                        hipStream_t s);
 hipError_t launch_params_convert(const LearnArgs& g, hipStream_t s);
 hipError_t set_learn_lds_limit();
+hipError_t launch_md_block(const MdArgs& m, int buf0, uint64_t step0, int64_t nsteps, uint32_t maxcap, hipStream_t s,
+                           int* buf_out);
 
 } // namespace crmc

@@ -1,0 +1,300 @@
+// CDNA4 (gfx950) kernels of the hybrid MD / CR-MC protocol: blocks of
+// Langevin molecular dynamics of the free ions between sweeps (Sec. III:
+// velocity Verlet with a Langevin thermostat, n_MD steps between blocks of MC
+// steps; units sigma, kT and the ion mass, so tau = 1).  Sites and
+// nanoparticle cores stay where they are.
+//
+//   k_md_vinit    Maxwell-Boltzmann velocities of the free ions at the start
+//                 of a block (Box-Muller on Philox counter (step, cell, slot, 6)).
+//   k_md_force    FP64 force on every free ion from the 27 cells around its
+//                 cell (cells are at least rc wide): screened Coulomb inside
+//                 the exact integer cutoff, excluded volume with every other
+//                 particle, expanded excluded volume of the cores; with the
+//                 Langevin drag and noise (counter (step, cell, slot, 7)) and
+//                 the second half kick when asked.
+//   k_md_drift    first half kick and drift, rounded to the position lattice.
+//   k_md_rebin    the moved ions back into cells of the same grid (the grid of
+//                 the last sweep), stably: a new cell gathers its records from
+//                 the 27 cells around it in ascending cell index, each in slot
+//                 order, with their velocities.  One wavefront per cell.
+#include "crmc_internal.h"
+
+#include <math.h>
+
+namespace crmc {
+
+constexpr uint32_t TAG_MDVEL = 6, TAG_MDNOISE = 7;
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the two
+// multiply-xor bijections with the Weyl key schedule
+__device__ __forceinline__ void md_philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                          uint32_t k1, uint32_t out[4])
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// three standard normal deviates from one Philox block (Box-Muller on the
+// uniforms (w0 + 1) / 2^32, w1 / 2^32 and (w2 + 1) / 2^32, w3 / 2^32)
+__device__ __forceinline__ void md_normals3(const Replica& R, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t tag,
+                                            double z[3])
+{
+    uint32_t w[4];
+    md_philox(c0, c1, c2, tag, R.key0, R.key1, w);
+    const double TWO32 = 4294967296.0, TWO_PI = 6.283185307179586476925286766559;
+    const double u1 = ((double)w[0] + 1.0) / TWO32, u2 = (double)w[1] / TWO32;
+    const double u3 = ((double)w[2] + 1.0) / TWO32, u4 = (double)w[3] / TWO32;
+    const double r1 = sqrt(-2.0 * log(u1)), r2 = sqrt(-2.0 * log(u3));
+    z[0] = r1 * cos(TWO_PI * u2);
+    z[1] = r1 * sin(TWO_PI * u2);
+    z[2] = r2 * cos(TWO_PI * u4);
+}
+
+__device__ __forceinline__ int md_is_ion(uint32_t meta)
+{
+    const uint32_t k = meta & 7u;
+    return k == KIND_XPOS || k == KIND_XNEG;
+}
+
+__device__ __forceinline__ int md_q(uint32_t meta)
+{
+    const uint32_t k = meta & 7u, c = (meta >> 3) & 1u;
+    if (k == KIND_ACID) return -(int)c;
+    if (k == KIND_BASE) return (int)c;
+    if (k == KIND_XPOS) return 1;
+    if (k == KIND_XNEG) return -1;
+    return 0;
+}
+
+// -grad of the energy on free ion a (record ra at cell c, slot j of buf)
+__device__ void md_ion_force(const Replica& R, int buf, uint32_t c, uint32_t j, const uint4& ra, const MdArgs& m,
+                             double f[3])
+{
+    f[0] = f[1] = f[2] = 0.0;
+    if (!m.ion_coupling) return; // ideal ions feel nothing
+    const uint32_t n = R.n, cap = R.cap;
+    const uint32_t cx = c % n, cy = (c / n) % n, cz = c / (n * n);
+    const uint4* recb = R.rec[buf];
+    const uint32_t* cntb = R.cnt[buf];
+    const double s = R.scale;
+    const int qa = md_q(ra.w);
+    for (int o = 0; o < 27; ++o) {
+        const uint32_t x = (cx + n + (uint32_t)(o % 3) - 1u) % n, y = (cy + n + (uint32_t)((o / 3) % 3) - 1u) % n,
+                       z = (cz + n + (uint32_t)(o / 9) - 1u) % n;
+        const uint32_t oc = x + n * (y + n * z);
+        const uint32_t cnt = cntb[oc];
+        for (uint32_t k = 0; k < cnt; ++k) {
+            if (oc == c && k == j) continue;
+            const uint4 rb = recb[(size_t)oc * cap + k];
+            const int32_t dx = (int32_t)(ra.x - rb.x), dy = (int32_t)(ra.y - rb.y), dz = (int32_t)(ra.z - rb.z);
+            const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
+            const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+            const double fx = dx * s, fy = dy * s, fz = dz * s;
+            const double r2 = fx * fx + fy * fy + fz * fz;
+            double g = 0.0;
+            const int qb = md_q(rb.w);
+            if (r2i < R.R2 && qa != 0 && qb != 0) {
+                const double r = sqrt(r2);
+                g += m.lB * (double)(qa * qb) * exp(-R.kappa * r) * (1.0 + R.kappa * r) / (r2 * r);
+            }
+            if (m.eps > 0.0 && r2 < 1.2599210498948731647672106) {
+                const double ir2 = 1.0 / r2, ir6 = ir2 * ir2 * ir2;
+                g += 4.0 * m.eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir2;
+            }
+            f[0] += g * fx; f[1] += g * fy; f[2] += g * fz;
+        }
+    }
+    if (m.eps > 0.0) {
+        for (uint32_t k = 0; k < R.ncores; ++k) {
+            const uint4 cc = R.core_x[k];
+            const int32_t dx = (int32_t)(ra.x - cc.x), dy = (int32_t)(ra.y - cc.y), dz = (int32_t)(ra.z - cc.z);
+            const double fx = dx * s, fy = dy * s, fz = dz * s;
+            const double r = sqrt(fx * fx + fy * fy + fz * fz);
+            const double sh = r - R.core_delta[k];
+            if (sh < 1.122462048309373) {
+                const double ir = 1.0 / sh, ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
+                const double g = 4.0 * m.eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir / r;
+                f[0] += g * fx; f[1] += g * fy; f[2] += g * fz;
+            }
+        }
+    }
+}
+
+// one wavefront per cell of the replicas (global cell index from the
+// flattened cell table), its lanes striding over the cell's slots
+struct CellOf {
+    uint32_t r, c, cnt;
+    bool live;
+};
+
+__device__ __forceinline__ CellOf md_cell(const MdArgs& m, int buf)
+{
+    CellOf t{0u, 0u, 0u, false};
+    const uint32_t gc = blockIdx.x;
+    if (gc >= m.ncell_total) return t;
+    t.r = m.cell2rep[gc];
+    const Replica& R = m.reps[t.r];
+    t.c = gc - R.cell_begin;
+    t.cnt = R.cnt[buf][t.c];
+    t.live = true;
+    return t;
+}
+
+__global__ __launch_bounds__(64) void k_md_vinit(MdArgs m, int buf, uint64_t step)
+{
+    const CellOf t = md_cell(m, buf);
+    if (!t.live) return;
+    const Replica& R = m.reps[t.r];
+    for (uint32_t j = threadIdx.x; j < t.cnt; j += blockDim.x) {
+        const size_t slot = (size_t)t.c * R.cap + j;
+        double v[3] = {0.0, 0.0, 0.0};
+        if (md_is_ion(R.rec[buf][slot].w)) md_normals3(R, (uint32_t)step, t.c, j, TAG_MDVEL, v);
+        double* vb = m.vel[t.r * 2 + buf] + 3 * slot;
+        vb[0] = v[0]; vb[1] = v[1]; vb[2] = v[2];
+    }
+}
+
+// forces in the binning of buf; with langevin set, the drag and the noise of
+// MD step `step` are added and the second half kick is applied
+__global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t step, int langevin)
+{
+    const CellOf t = md_cell(m, buf);
+    if (!t.live) return;
+    const Replica& R = m.reps[t.r];
+    for (uint32_t j = threadIdx.x; j < t.cnt; j += blockDim.x) {
+        const size_t slot = (size_t)t.c * R.cap + j;
+        const uint4 ra = R.rec[buf][slot];
+        double* fb = m.force[t.r] + 3 * slot;
+        if (!md_is_ion(ra.w)) {
+            fb[0] = fb[1] = fb[2] = 0.0;
+            continue;
+        }
+        double f[3];
+        md_ion_force(R, buf, t.c, j, ra, m, f);
+        if (langevin) {
+            double z[3];
+            md_normals3(R, (uint32_t)step, t.c, j, TAG_MDNOISE, z);
+            double* vb = m.vel[t.r * 2 + buf] + 3 * slot;
+            for (int q = 0; q < 3; ++q) {
+                f[q] = f[q] - m.gamma * vb[q] + m.noise * z[q];
+                vb[q] += 0.5 * m.dt * f[q];
+            }
+        }
+        fb[0] = f[0]; fb[1] = f[1]; fb[2] = f[2];
+    }
+}
+
+__global__ __launch_bounds__(64) void k_md_drift(MdArgs m, int buf)
+{
+    const CellOf t = md_cell(m, buf);
+    if (!t.live) return;
+    const Replica& R = m.reps[t.r];
+    const double to_lat = 4294967296.0 / R.L;
+    for (uint32_t j = threadIdx.x; j < t.cnt; j += blockDim.x) {
+        const size_t slot = (size_t)t.c * R.cap + j;
+        uint4& ra = R.rec[buf][slot];
+        if (!md_is_ion(ra.w)) continue;
+        double* vb = m.vel[t.r * 2 + buf] + 3 * slot;
+        const double* fb = m.force[t.r] + 3 * slot;
+        uint32_t x[3] = {ra.x, ra.y, ra.z};
+        for (int q = 0; q < 3; ++q) {
+            vb[q] += 0.5 * m.dt * fb[q];
+            x[q] = (uint32_t)((long long)x[q] + llround(m.dt * vb[q] * to_lat));
+        }
+        ra.x = x[0]; ra.y = x[1]; ra.z = x[2];
+    }
+}
+
+// the records (and velocities) of buf re-binned into buf ^ 1 in the same grid
+__global__ __launch_bounds__(64) void k_md_rebin(MdArgs m, int buf)
+{
+    const uint32_t gc = blockIdx.x;
+    if (gc >= m.ncell_total) return;
+    const uint32_t r = m.cell2rep[gc];
+    const Replica& R = m.reps[r];
+    const uint32_t c = gc - R.cell_begin, n = R.n, cap = R.cap;
+    const uint32_t cx = c % n, cy = (c / n) % n, cz = c / (n * n);
+    const uint32_t lane = threadIdx.x;
+    const uint32_t o0 = R.tab->o[0], o1 = R.tab->o[1], o2 = R.tab->o[2];
+    // the 27 cells around c in ascending index
+    uint32_t nb = 0xFFFFFFFFu;
+    if (lane < 27) {
+        const uint32_t x = (cx + n + (lane % 3) - 1u) % n, y = (cy + n + ((lane / 3) % 3) - 1u) % n,
+                       z = (cz + n + (lane / 9) - 1u) % n;
+        nb = x + n * (y + n * z);
+    }
+    // rank of this lane's cell among the 27 (distinct when n >= 3)
+    uint32_t rank = 0;
+    for (int q = 0; q < 27; ++q) {
+        const uint32_t v = (uint32_t)__shfl((int)nb, q, 64);
+        rank += (v < nb) ? 1u : 0u;
+    }
+    const uint4* src = R.rec[buf];
+    const double* vsrc = m.vel[r * 2 + buf];
+    uint4* dst = R.rec[buf ^ 1];
+    double* vdst = m.vel[r * 2 + (buf ^ 1)];
+    uint32_t out = 0;
+    for (uint32_t q = 0; q < 27; ++q) {
+        // the source cell of rank q
+        const uint64_t who = __ballot(lane < 27 && rank == q);
+        const uint32_t sc = (uint32_t)__shfl((int)nb, (int)__builtin_ctzll(who), 64);
+        const uint32_t cnt = R.cnt[buf][sc];
+        for (uint32_t b0 = 0; b0 < cnt; b0 += 64) {
+            const uint32_t k = b0 + lane;
+            bool mine = false;
+            uint4 rec = make_uint4(0u, 0u, 0u, 0u);
+            if (k < cnt) {
+                rec = src[(size_t)sc * cap + k];
+                const uint32_t nx = __umulhi(rec.x - o0, n), ny = __umulhi(rec.y - o1, n), nz = __umulhi(rec.z - o2, n);
+                mine = nx + n * (ny + n * nz) == c;
+            }
+            const uint64_t mask = __ballot(mine);
+            const uint32_t before = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            if (mine) {
+                const uint32_t at = out + before;
+                if (at < cap) {
+                    dst[(size_t)c * cap + at] = rec;
+                    const double* vs = vsrc + 3 * ((size_t)sc * cap + k);
+                    double* vd = vdst + 3 * ((size_t)c * cap + at);
+                    vd[0] = vs[0]; vd[1] = vs[1]; vd[2] = vs[2];
+                }
+            }
+            out += (uint32_t)__popcll(mask);
+        }
+    }
+    if (lane == 0) {
+        R.cnt[buf ^ 1][c] = out < cap ? out : cap;
+        if (out > cap) atomicOr(m.err, ERR_BIN_CAPACITY);
+        atomicMax(R.hiwater, out);
+    }
+}
+
+hipError_t launch_md_block(const MdArgs& m, int buf0, uint64_t step0, int64_t nsteps, uint32_t maxcap, hipStream_t s,
+                           int* buf_out)
+{
+    (void)maxcap;
+    const dim3 grid(m.ncell_total), block(64);
+    int buf = buf0;
+    hipLaunchKernelGGL(k_md_vinit, grid, block, 0, s, m, buf, step0);
+    hipLaunchKernelGGL(k_md_force, grid, block, 0, s, m, buf, step0, 0);
+    for (int64_t st = 0; st < nsteps; ++st) {
+        hipLaunchKernelGGL(k_md_drift, grid, block, 0, s, m, buf);
+        hipLaunchKernelGGL(k_md_rebin, dim3(m.ncell_total), dim3(64), 0, s, m, buf);
+        buf ^= 1;
+        hipLaunchKernelGGL(k_md_force, grid, block, 0, s, m, buf, step0 + (uint64_t)st, 1);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    *buf_out = buf;
+    return hipGetLastError();
+}
+
+} // namespace crmc
