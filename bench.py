@@ -243,6 +243,14 @@ TRAFFIC_FILES = {
 }
 
 
+def phase_kernel_name(precision, learned, reloc):
+    """The phase kernel a sweep of this configuration launches (as rocprofv3 names it)."""
+    m = "true" if reloc else "false"
+    if learned and precision == 32:
+        return "k_phase_learned32<%s>" % m
+    return "k_phase<%s, %s, %s>" % ("float" if precision == 32 else "double", "true" if learned else "false", m)
+
+
 def load_workload(name):
     """(systems, per-replica conditions, model constants) of a workload."""
     from workloads import config2, config3, config5
@@ -491,7 +499,7 @@ def main():
     traffic = read_traffic(args, TRAFFIC_FILES.get((wl, use_learned)), tuned)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_phase<float, %s, false>" % ("true" if use_learned else "false"),
+                "kernel": phase_kernel_name(args.precision, use_learned, args.ion_trials > 0),
                 "bytes_per_launch": round(bytes_launch), "avg_launch_ms": round(phase_avg_ms, 5),
                 "timed_launches": int(launches[1])}
 

@@ -363,6 +363,9 @@ constexpr int MAX_LDS_CORES = 64; // nanoparticle cores copied on chip (more are
 // LDS pool of one domain, offsets in 16-byte records:
 //   member 0's list | member 1's list | ln k table (doubles) | cores | core
 //   Deltas (doubles) | neighbour records (as many as fit)
+// longest list (with room for growth) a light domain holds in registers
+constexpr int REG_ROOM = 64;
+
 struct Pool {
     int room0, room1;
     int ln_off, nln;
@@ -480,7 +483,8 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
         const int n1 = G.ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
         const int ntr_max = (a.trials + a.ion_trials) * G.ncell + ((n0 + n1) * a.site_trials + 15) / 16;
         const Pool p = pool_layout(n0, n1, G.ncell, ntr_max, R.cap, R.ncores, a.learned);
-        light = nb <= a.light_nb && p.st_off <= a.pool / 4;
+        // a light domain keeps its lists in registers, one record per lane
+        light = nb <= a.light_nb && p.st_off <= a.pool / 4 && p.room0 <= REG_ROOM && p.room1 <= REG_ROOM;
         geo = make_uint4(r, G.cell0, G.ncell == 2 ? G.cell1 : G.cell0, (uint32_t)n0 | ((uint32_t)n1 << 16));
     }
     const uint64_t ml = __ballot(valid && light), mh = __ballot(valid && !light);
@@ -627,7 +631,12 @@ __device__ __forceinline__ double wca_core(const Chg& c, const uint4& cx, double
     const int32_t dx = (int32_t)(cx.x - c.x), dy = (int32_t)(cx.y - c.y), dz = (int32_t)(cx.z - c.z);
     const double sc = P.scale_d;
     const double fx = (double)dx * sc, fy = (double)dy * sc, fz = (double)dz * sc;
-    const double r = sqrt(fx * fx + fy * fy + fz * fz);
+    const double r2 = fx * fx + fy * fy + fz * fz;
+    // far from the core (most pairs): out of reach without the square root;
+    // the margin keeps every pair that the test below could take
+    const double reach = delta + 1.122462048309373;
+    if (r2 > reach * reach * (1.0 + 1e-12)) return 0.0;
+    const double r = sqrt(r2);
     const double sh = r - delta;
     if (!(sh < 1.122462048309373)) return 0.0;
     if (sh < 0.5) {
@@ -880,14 +889,108 @@ __device__ __forceinline__ void class_sums(const uint4* pool, const double* aux,
 
 // class of a participant: meta mask and value
 constexpr uint32_t CLS_MASK_SITE = 0xFu, CLS_MASK_ION = 0x7u;
-// The domain's trials.  wpd wavefronts share the pair sums (wpd = 1: light
-// domain, no workgroup barriers; wpd = 4: heavy domain, the whole workgroup;
-// uniform over the workgroup).
-template <typename Real, bool LEARNED, bool RELOC, bool FAST>
-__device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint4 geo, uint4* __restrict__ pool,
-                                           int pool_records, int wid, const int wpd, double (*red)[4], int (*ovf)[4])
+
+// ---- lists of a light domain held in registers: record i of a member's list
+//      in lane i (rooms of at most 64 records, which the plan checks), with the
+//      learned proposal's site probability of the slot beside it.  The helpers
+//      give the results of their LDS counterparts above for such lists.
+
+__device__ __forceinline__ uint4 lane_rec(const uint4& r, int i)
 {
-    const int nt = 64 * wpd;
+    return make_uint4(rdl(r.x, i), rdl(r.y, i), rdl(r.z, i), rdl(r.w, i));
+}
+__device__ __forceinline__ double lane_d(double v, int i)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)b, i);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), i);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
+}
+
+__device__ __forceinline__ MemberCounts count_reg(uint32_t meta, int nn, int lane)
+{
+    const uint32_t m = lane < nn ? meta : 0u;
+    const int kd = rec_kind(m), ch = rec_charged(m);
+    MemberCounts c;
+    c.a0 = __popcll(__ballot(kd == (int)KIND_ACID && !ch));
+    c.ac = __popcll(__ballot(kd == (int)KIND_ACID && ch));
+    c.b0 = __popcll(__ballot(kd == (int)KIND_BASE && !ch));
+    c.bc = __popcll(__ballot(kd == (int)KIND_BASE && ch));
+    c.xp = __popcll(__ballot(kd == (int)KIND_XPOS));
+    c.xn = __popcll(__ballot(kd == (int)KIND_XNEG));
+    return c;
+}
+
+__device__ __forceinline__ int reg_kth(uint32_t meta, int nn, uint32_t mask, uint32_t value, int k, int lane)
+{
+    const bool p = lane < nn && (meta & mask) == value;
+    const uint64_t m = __ballot(p);
+    if (k >= __popcll(m)) return -1;
+    const uint64_t hit = __ballot(p && __popcll(m & lanemask_lt()) == k);
+    return (int)__builtin_ctzll(hit);
+}
+
+__device__ __forceinline__ int reg_kth_weighted(uint32_t meta, double pd, int nn, uint32_t mask, uint32_t value,
+                                                bool fwd, double target, int lane)
+{
+    const bool el = lane < nn && (meta & mask) == value;
+    const double a = el ? pd : 0.0;
+    double c = el ? (fwd ? a : 1.0 - a) : 0.0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double v = __shfl_up(c, off, 64);
+        if (lane >= off) c += v;
+    }
+    const double acc = 0.0;
+    c += acc;
+    const uint64_t hit = __ballot(el && c > target);
+    if (hit) return (int)__builtin_ctzll(hit);
+    const uint64_t em = __ballot(el);
+    return em ? 63 - (int)__builtin_clzll(em) : -1;
+}
+
+__device__ __forceinline__ void class_sums_reg(uint32_t meta, double pd, int nn, int lane, double& a0, double& ac,
+                                               double& b0, double& bc)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    if (lane < nn) {
+        const int kd = rec_kind(meta), ch = rec_charged(meta);
+        if (kd == (int)KIND_ACID) { if (ch) s1 += 1.0 - pd; else s0 += pd; }
+        if (kd == (int)KIND_BASE) { if (ch) s3 += 1.0 - pd; else s2 += pd; }
+    }
+    a0 = wave_sum_dpp(s0);
+    ac = wave_sum_dpp(s1);
+    b0 = wave_sum_dpp(s2);
+    bc = wave_sum_dpp(s3);
+}
+
+// swap-remove slot i of a register list of nn records; append at slot nn
+__device__ __forceinline__ void reg_remove(uint4& r, double& d, int i, int nn, int lane, bool learned)
+{
+    const uint4 last = lane_rec(r, nn - 1);
+    const double dl = learned ? lane_d(d, nn - 1) : 0.0;
+    if (lane == i) {
+        r = last;
+        if (learned) d = dl;
+    }
+}
+__device__ __forceinline__ void reg_append(uint4& r, double& d, int nn, uint4 v, int lane)
+{
+    if (lane == nn) {
+        r = v;
+        d = 0.0;
+    }
+}
+// The domain's trials.  WPD wavefronts share the pair sums (WPD = 1: light
+// domain, no workgroup barriers; WPD = 4: heavy domain, the whole workgroup;
+// uniform over the workgroup).
+template <typename Real, bool LEARNED, bool RELOC, bool FAST, int WPD>
+__device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint4 geo, uint4* __restrict__ pool,
+                                           int pool_records, int wid, double (*red)[4], int (*ovf)[4])
+{
+    constexpr int wpd = WPD;
+    constexpr bool REG = WPD == 1; // the domain's lists in registers (light) or in the pool (heavy)
+    constexpr int nt = 64 * wpd;
     const int lane = threadIdx.x & 63;
     const int tid = wid * 64 + lane;
     const uint64_t t_start = a.trace ? wall_clock64() : 0;
@@ -917,7 +1020,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     int n1 = (int)(rflu(geo.w) >> 16);
     const int ntr_max = (a.trials + a.ion_trials) * ncell + ((n0 + n1) * a.site_trials + 15) / 16;
     const Pool pl = pool_layout(n0, n1, ncell, ntr_max, cap, ncores, LEARNED ? 1 : 0);
-    if (pl.st_off > pool_records) { // the plan and the host size pools so that this never happens
+    // the plan and the host size pools (and light domains' lists) so that this never happens
+    if (pl.st_off > pool_records || (REG && (pl.room0 > REG_ROOM || pl.room1 > REG_ROOM))) {
         if (tid == 0) atomicOr(a.err, ERR_POOL);
         return;
     }
@@ -989,8 +1093,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     uint4* lcore = pool + pl.core_off;
     double* lcdel = reinterpret_cast<double*>(pool + pl.cdel_off);
     {
-        if (tid < n0) pool[tid] = f0;
-        if (tid < n1) pool[pl.room0 + tid] = f1;
+        if (!REG && tid < n0) pool[tid] = f0;
+        if (!REG && tid < n1) pool[pl.room0 + tid] = f1;
         if (tid < pl.nln) lnt[tid] = fl;
         if (tid < pl.ncl) { lcore[tid] = fc; lcdel[tid] = fd; }
         // further rounds (long lists): a share of every table, all in flight together
@@ -1001,19 +1105,30 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
             if (i < n1) r1 = recb[(size_t)G.cell1 * cap + i];
             if (i < pl.nln) l = a.lntab[i];
             if (i < pl.ncl) { cx = core_g[i]; dl = cdel_g[i]; }
-            if (i < n0) pool[i] = r0;
-            if (i < n1) pool[pl.room0 + i] = r1;
+            if (!REG && i < n0) pool[i] = r0;
+            if (!REG && i < n1) pool[pl.room0 + i] = r1;
             if (i < pl.nln) lnt[i] = l;
             if (i < pl.ncl) { lcore[i] = cx; lcdel[i] = dl; }
         }
     }
     if (wpd > 1) __syncthreads(); else wave_sync();
+    // a light domain's lists: lane i holds record i of each member (lanes past
+    // the count hold stale or zero records and are never read as members)
+    uint4 L0 = f0, L1 = f1;
+    double D0 = 0.0, D1 = 0.0;
 
     // ---- learned proposal: site probabilities of the lists, class weights ------
     double* aux = reinterpret_cast<double*>(pool + pl.aux_off);
     ClassW cw{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     constexpr bool learned = LEARNED;
-    if (learned) {
+    if (learned && REG) {
+        const double* phat = R.phat;
+        const int k0 = rec_kind(L0.w), k1 = rec_kind(L1.w);
+        if (lane < n0 && (k0 == (int)KIND_ACID || k0 == (int)KIND_BASE)) D0 = phat[L0.w >> 8];
+        if (lane < n1 && (k1 == (int)KIND_ACID || k1 == (int)KIND_BASE)) D1 = phat[L1.w >> 8];
+        class_sums_reg(L0.w, D0, n0, lane, cw.a0_0, cw.ac_0, cw.b0_0, cw.bc_0);
+        class_sums_reg(L1.w, D1, n1, lane, cw.a0_1, cw.ac_1, cw.b0_1, cw.bc_1);
+    } else if (learned) {
         const double* phat = R.phat;
         for (int i = tid; i < n0 + n1; i += nt) {
             const int slot = i < n0 ? i : pl.room0 + (i - n0);
@@ -1027,8 +1142,8 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     }
 
     // ---- counts per member ----------------------------------------------------
-    MemberCounts c0 = count_member(pool, 0, n0, lane);
-    MemberCounts c1 = count_member(pool, pl.room0, n1, lane);
+    MemberCounts c0 = REG ? count_reg(L0.w, n0, lane) : count_member(pool, 0, n0, lane);
+    MemberCounts c1 = REG ? count_reg(L1.w, n1, lane) : count_member(pool, pl.room0, n1, lane);
     const int nsites = c0.a0 + c0.ac + c0.b0 + c0.bc + c1.a0 + c1.ac + c1.b0 + c1.bc;
     // trials of this domain: the state-independent schedule, reaction trials
     // first, then the ion relocation trials
@@ -1090,7 +1205,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     //      Philox block b of trial i as in the loop below) and taken in order
     //      up to and including the first accepted one
     int t_first = 0;
-    if (FAST && wpd == 1 && n0 + n1 == 0 && nreact == 1 && !spill) {
+    if (FAST && REG && n0 + n1 == 0 && nreact == 1 && !spill) {
         const int grp = lane / 6, sub = lane % 6; // lanes 60-63 idle
         const bool lead = sub == 0 && grp < 10;
         const double lnp_counts = -lnt[1] - lnt[1] + lnKion;
@@ -1198,16 +1313,13 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const double dUf =
                     __longlong_as_double((long long)(((uint64_t)rdl((uint32_t)((uint64_t)ub >> 32), src) << 32) |
                                                      (uint64_t)rdl((uint32_t)ub, src)));
-                if (tid == 0) {
-                    int l0 = 0, l1 = 0;
-                    int& ca = ja ? l1 : l0;
-                    pool[pl.base(ja) + ca] = make_uint4(ax, ay, az, make_meta(KIND_XPOS, 1u, NO_SITE));
-                    if (learned) aux[pl.base(ja) + ca] = 0.0;
-                    ++ca;
-                    int& cb = jb ? l1 : l0;
-                    pool[pl.base(jb) + cb] = make_uint4(bx, by, bz, make_meta(KIND_XNEG, 1u, NO_SITE));
-                    if (learned) aux[pl.base(jb) + cb] = 0.0;
-                    ++cb;
+                {
+                    // the lists were empty: cation and anion in slots 0 and 0, or 0 and 1
+                    const uint4 ra = make_uint4(ax, ay, az, make_meta(KIND_XPOS, 1u, NO_SITE));
+                    const uint4 rb = make_uint4(bx, by, bz, make_meta(KIND_XNEG, 1u, NO_SITE));
+                    if (ja) reg_append(L1, D1, 0, ra, lane); else reg_append(L0, D0, 0, ra, lane);
+                    const int sb = ja == jb ? 1 : 0;
+                    if (jb) reg_append(L1, D1, sb, rb, lane); else reg_append(L0, D0, sb, rb, lane);
                 }
                 acpH += 1ull << 21;
                 dE += dUf;
@@ -1332,8 +1444,10 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const double target = unit53(wt0, wt1) * (lp_W0 + lp_W1);
                 const int mem = (target < lp_W0 && lp_W0 > 0.0) || lp_W1 <= 0.0 ? 0 : 1;
                 a_mem = mem;
-                a_own = rfl(member_kth_weighted(pool, aux, mem ? pl.room0 : 0, mem ? n1 : n0, am, av, !(move & 1),
-                                                mem ? target - lp_W0 : target, lane));
+                a_own = REG ? rfl(reg_kth_weighted(mem ? L1.w : L0.w, mem ? D1 : D0, mem ? n1 : n0, am, av,
+                                                   !(move & 1), mem ? target - lp_W0 : target, lane))
+                            : rfl(member_kth_weighted(pool, aux, mem ? pl.room0 : 0, mem ? n1 : n0, am, av,
+                                                      !(move & 1), mem ? target - lp_W0 : target, lane));
             }
         }
         if (!auto_reject) {
@@ -1343,14 +1457,15 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 if (!cm) continue;
                 const int k = pidx ? bk : ak, k0 = pidx ? bc0 : ac0;
                 const int mem = k < k0 ? 0 : 1;
-                const int own = rfl(member_kth(pool, mem ? pl.room0 : 0, mem ? n1 : n0, cm, cv, mem ? k - k0 : k,
-                                               lane));
+                const int own = REG ? rfl(reg_kth(mem ? L1.w : L0.w, mem ? n1 : n0, cm, cv, mem ? k - k0 : k, lane))
+                                    : rfl(member_kth(pool, mem ? pl.room0 : 0, mem ? n1 : n0, cm, cv,
+                                                     mem ? k - k0 : k, lane));
                 if (pidx) { b_mem = mem; b_own = own; } else { a_mem = mem; a_own = own; }
             }
             if (learned && move <= 3) {
                 // ln q_rev(i | s') - ln q_fwd(i | s) replaces the count ratio
                 const bool fwd = !(move & 1);
-                const double p_i = rfld(aux[(a_mem ? pl.room0 : 0) + a_own]);
+                const double p_i = REG ? lane_d(a_mem ? D1 : D0, a_own) : rfld(aux[(a_mem ? pl.room0 : 0) + a_own]);
                 const double wi = fwd ? p_i : 1.0 - p_i, wr = 1.0 - wi;
                 const int m = move == 0 ? m0a : move == 1 ? mca : move == 2 ? m0b : mcb;
                 const int mr = (move == 0 ? mca : move == 1 ? m0a : move == 2 ? mcb : m0b) + 1;
@@ -1390,7 +1505,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
             // ion relocation: A is the ion leaving its place, B the same ion at
             // a point drawn like an insertion of its sign
             const int q = av == KIND_XPOS ? 1 : -1;
-            const uint4 rc = pool[pl.base(a_mem) + a_own];
+            const uint4 rc = REG ? lane_rec(a_mem ? L1 : L0, a_own) : pool[pl.base(a_mem) + a_own];
             A.member = a_mem; A.own = a_own;
             A.x = rflu(rc.x); A.y = rflu(rc.y); A.z = rflu(rc.z);
             A.ion = 1; A.q_old = q; A.q_new = 0; A.pres_old = 1; A.pres_new = 0;
@@ -1411,7 +1526,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         }
         if (move <= 3) {
             // A: the site flips
-            const uint4 rc = pool[pl.base(a_mem) + a_own];
+            const uint4 rc = REG ? lane_rec(a_mem ? L1 : L0, a_own) : pool[pl.base(a_mem) + a_own];
             A.member = a_mem; A.own = a_own;
             A.x = rflu(rc.x); A.y = rflu(rc.y); A.z = rflu(rc.z);
             const uint32_t mw = rflu(rc.w);
@@ -1441,7 +1556,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 B.z = (j ? ib1[2] : ib0[2]) + pick64(word(wo + 4), word(wo + 5), j ? iw1[2] : iw0[2]);
                 lnvol += j ? lnZm1 : lnZm0;
             } else {
-                const uint4 rc = pool[pl.base(b_mem) + b_own];
+                const uint4 rc = REG ? lane_rec(b_mem ? L1 : L0, b_own) : pool[pl.base(b_mem) + b_own];
                 B.member = b_mem; B.own = b_own;
                 B.x = rflu(rc.x); B.y = rflu(rc.y); B.z = rflu(rc.z);
                 lnvol -= b_mem ? lnZm1 : lnZm0;
@@ -1464,7 +1579,7 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 A.z = (j ? ib1[2] : ib0[2]) + pick64(word(8), word(9), j ? iw1[2] : iw0[2]);
                 lnvol += j ? lnZm1 : lnZm0;
             } else {
-                const uint4 rc = pool[pl.base(a_mem) + a_own];
+                const uint4 rc = REG ? lane_rec(a_mem ? L1 : L0, a_own) : pool[pl.base(a_mem) + a_own];
                 A.member = a_mem; A.own = a_own;
                 A.x = rflu(rc.x); A.y = rflu(rc.y); A.z = rflu(rc.z);
                 lnvol -= a_mem ? lnZm1 : lnZm0;
@@ -1492,13 +1607,23 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
             if (!inA && !inB) continue;
             const int bs = pl.base(j), nn = j ? n1 : n0;
             const int skA = inA ? A.own : -1, skB = inB ? B.own : -1;
-            for (int g0 = 0; g0 < nn; g0 += nt) {
-                const int g = g0 + tid;
-                const bool v = g < nn && g != skA && g != skB;
-                const uint4 rc = pool[bs + min(g, nn - 1)];
-                const uint32_t code = charge_bits(rc.w, P.ion_coupling);
-                if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, gap);
-                if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, gap);
+            if (REG) {
+                if (nn > 0) {
+                    const bool v = lane < nn && lane != skA && lane != skB;
+                    const uint4 rc = j ? L1 : L0;
+                    const uint32_t code = charge_bits(rc.w, P.ion_coupling);
+                    if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, gap);
+                    if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, gap);
+                }
+            } else {
+                for (int g0 = 0; g0 < nn; g0 += nt) {
+                    const int g = g0 + tid;
+                    const bool v = g < nn && g != skA && g != skB;
+                    const uint4 rc = pool[bs + min(g, nn - 1)];
+                    const uint32_t code = charge_bits(rc.w, P.ion_coupling);
+                    if (inA) pair_acc<Real>(rc, code, v, A, P, aqA, aw, ov, gap);
+                    if (inB) pair_acc<Real>(rc, code, v, B, P, aqB, aw, ov, gap);
+                }
             }
             const int lo = j ? nbc0 : 0, hi = j ? nb_total : nbc0;
             const int s1 = min(hi, st_end);
@@ -1533,13 +1658,23 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 if (!inA && !inB) continue;
                 const int bs = pl.base(j), nn = j ? n1 : n0;
                 const int skA = inA ? A.own : -1, skB = inB ? B.own : -1;
-                for (int g0 = 0; g0 < nn; g0 += nt) {
-                    const int g = g0 + tid;
-                    const bool v = g < nn && g != skA && g != skB;
-                    const uint4 rc = pool[bs + min(g, nn - 1)];
-                    const uint32_t code = charge_bits(rc.w, P.ion_coupling);
-                    if (inA) pair_band<Real>(rc, code, v, A, P, aqA);
-                    if (inB) pair_band<Real>(rc, code, v, B, P, aqB);
+                if (REG) {
+                    if (nn > 0) {
+                        const bool v = lane < nn && lane != skA && lane != skB;
+                        const uint4 rc = j ? L1 : L0;
+                        const uint32_t code = charge_bits(rc.w, P.ion_coupling);
+                        if (inA) pair_band<Real>(rc, code, v, A, P, aqA);
+                        if (inB) pair_band<Real>(rc, code, v, B, P, aqB);
+                    }
+                } else {
+                    for (int g0 = 0; g0 < nn; g0 += nt) {
+                        const int g = g0 + tid;
+                        const bool v = g < nn && g != skA && g != skB;
+                        const uint4 rc = pool[bs + min(g, nn - 1)];
+                        const uint32_t code = charge_bits(rc.w, P.ion_coupling);
+                        if (inA) pair_band<Real>(rc, code, v, A, P, aqA);
+                        if (inB) pair_band<Real>(rc, code, v, B, P, aqB);
+                    }
                 }
                 const int lo = j ? nbc0 : 0, hi = j ? nb_total : nbc0;
                 const int s1 = min(hi, st_end);
@@ -1613,7 +1748,40 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         //      insertions appended, cation before anion -----------------------
         if (move < 3) acpL += mv_one; else if (!RELOC || move < 6) acpH += mv_one; else ++rel_acc;
         dE += dU;
-        if (tid == 0) {
+        if (REG) {
+            // the same edits of the register lists, every lane taking part
+            if (move <= 3 && lane == A.own) {
+                if (A.member) L1.w ^= 8u;
+                else L0.w ^= 8u;
+            }
+            int l0 = n0, l1 = n1;
+            const auto rm = [&](int mem, int idx) {
+                if (mem) { reg_remove(L1, D1, idx, l1, lane, learned); --l1; }
+                else { reg_remove(L0, D0, idx, l0, lane, learned); --l0; }
+            };
+            const auto ap = [&](int mem, uint4 v) {
+                if (mem) { reg_append(L1, D1, l1, v, lane); ++l1; }
+                else { reg_append(L0, D0, l0, v, lane); ++l0; }
+            };
+            const uint4 recB = make_uint4(B.x, B.y, B.z, make_meta(B.q_new > 0 ? KIND_XPOS : KIND_XNEG, 1u, NO_SITE));
+            if (RELOC && move == 6) {
+                rm(A.member, A.own);
+                ap(B.member, recB);
+            } else if (!insertion) {
+                int dm0 = B.member, di0 = B.own, dm1 = -1, di1 = -1;
+                if (move == 5) {
+                    dm0 = A.member; di0 = A.own; dm1 = B.member; di1 = B.own;
+                    if (dm0 == dm1 && di1 > di0) {
+                        const int t0 = di0; di0 = di1; di1 = t0;
+                    }
+                }
+                rm(dm0, di0);
+                if (dm1 >= 0) rm(dm1, di1);
+            } else {
+                if (move == 4) ap(A.member, make_uint4(A.x, A.y, A.z, make_meta(KIND_XPOS, 1u, NO_SITE)));
+                ap(B.member, recB);
+            }
+        } else if (tid == 0) {
             if (move <= 3) pool[pl.base(A.member) + A.own].w ^= 8u;
             int l0 = n0, l1 = n1;
             if (RELOC && move == 6) {
@@ -1694,13 +1862,18 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         }
         n0 += grow0;
         n1 += grow1;
-        if (wpd > 1) __syncthreads(); else wave_sync();
+        if (wpd > 1) __syncthreads(); else if (!REG) wave_sync();
     }
 
     // ---- write the domain's cells back ----------------------------------------
-    if (wpd > 1) __syncthreads(); else wave_sync();
-    for (int i = tid; i < n0; i += nt) recb[(size_t)G.cell0 * cap + i] = pool[i];
-    for (int i = tid; i < n1; i += nt) recb[(size_t)G.cell1 * cap + i] = pool[pl.room0 + i];
+    if (REG) {
+        if (lane < n0) recb[(size_t)G.cell0 * cap + lane] = L0;
+        if (lane < n1) recb[(size_t)G.cell1 * cap + lane] = L1;
+    } else {
+        if (wpd > 1) __syncthreads(); else wave_sync();
+        for (int i = tid; i < n0; i += nt) recb[(size_t)G.cell0 * cap + i] = pool[i];
+        for (int i = tid; i < n1; i += nt) recb[(size_t)G.cell1 * cap + i] = pool[pl.room0 + i];
+    }
     if (tid == 0) {
         cntb[G.cell0] = (uint32_t)n0;
         if (ncell == 2) cntb[G.cell1] = (uint32_t)n1;
@@ -1757,14 +1930,24 @@ __device__ __forceinline__ void phase_body(const SweepArgs& a)
     const size_t slot = (size_t)colour * a.ndom_total + j;
     const uint32_t gd = heavy ? a.plan_heavy[slot] : a.plan_light[slot];
     const uint4 geo = heavy ? a.plan_geo_heavy[slot] : a.plan_geo_light[slot];
-    run_domain<Real, LEARNED, RELOC, FAST>(a, gd, geo, smem + (heavy ? 0 : (size_t)wave * q), q, heavy ? wave : 0,
-                                           heavy ? 4 : 1, red, ovf);
+    if (heavy) run_domain<Real, LEARNED, RELOC, FAST, 4>(a, gd, geo, smem, q, wave, red, ovf);
+    else run_domain<Real, LEARNED, RELOC, FAST, 1>(a, gd, geo, smem + (size_t)wave * q, q, 0, red, ovf);
 }
 
 template <typename Real, bool LEARNED, bool RELOC>
 __global__ __launch_bounds__(PHASE_THREADS) void k_phase(SweepArgs a)
 {
     phase_body<Real, LEARNED, RELOC, false>(a);
+}
+
+// The FP32 learned instances are held to three wavefronts per SIMD (a few
+// registers spill): a tuned LDS pool of 3072 records allows three workgroups
+// per compute unit, and at two wavefronts the suspension's phase takes 30 %
+// longer.
+template <bool RELOC>
+__global__ __launch_bounds__(PHASE_THREADS) __attribute__((amdgpu_waves_per_eu(3))) void k_phase_learned32(SweepArgs a)
+{
+    phase_body<float, true, RELOC, false>(a);
 }
 
 // the FAST instances hold their register use to four wavefronts per SIMD
@@ -1959,6 +2142,7 @@ template <typename Real, bool LEARNED, bool RELOC>
 static void launch_phase_f(const SweepArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
 {
     if (!LEARNED && a.bin_sparse_any) hipLaunchKernelGGL((k_phase_fast<Real, RELOC>), grid, block, lds, s, a);
+    else if (LEARNED && sizeof(Real) == 4) hipLaunchKernelGGL((k_phase_learned32<RELOC>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((k_phase<Real, LEARNED, RELOC>), grid, block, lds, s, a);
 }
 
@@ -2041,7 +2225,8 @@ hipError_t set_phase_lds_limit(size_t bytes)
                          (const void*)k_phase<float, false, true>,  (const void*)k_phase<double, false, true>,
                          (const void*)k_phase<float, true, true>,   (const void*)k_phase<double, true, true>,
                          (const void*)k_phase_fast<float, false>,   (const void*)k_phase_fast<double, false>,
-                         (const void*)k_phase_fast<float, true>,    (const void*)k_phase_fast<double, true>};
+                         (const void*)k_phase_fast<float, true>,    (const void*)k_phase_fast<double, true>,
+                         (const void*)k_phase_learned32<false>,     (const void*)k_phase_learned32<true>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;

@@ -139,10 +139,18 @@ def test_equilibrated_bench_schedule_heavy_domains(workload, lds, light):
 def test_matched_alpha_suspension_learned_fp32_vs_fp64():
     """The benchmarked configuration (64-nanoparticle suspension, eight pH
     replicas, FP32 with the trained learned proposal) against the plain FP64
-    chain: <alpha> of the acid and of the base sites of every replica within
-    3.5 combined standard errors (Sokal windows; 16 comparisons)."""
+    chain: <alpha> of the acid and of the base sites of every replica, 16
+    comparisons, each within 4 combined standard errors and their mean
+    squared deviation below 2.5 (the 0.999 quantile of chi^2_16 / 16), so a
+    bias common to several replicas fails long before any single one does.
+    Each standard error is the larger of the Sokal-window and the blocking
+    estimate: the window is set by the fast decay of the site counts and can
+    miss a slow mode that blocking still sees.  (Interleaved plain and learned
+    blocks of one FP32 chain scatter by up to 3.3 such errors per replica in
+    single runs, in FP64 as in FP32 and with eps = 1, so 3.5 per comparison
+    failed now and then with no bias behind it.)"""
     crmc = _gpu()
-    from paper_2109_07527_amd.stats import mean_se
+    from paper_2109_07527_amd.stats import blocking_se, mean_se
     c = config5()
     conds = [dict(pH=pH, pKa=c["pKa"], pKb=c["pKb"], pIX_pos=c["pIX"], pIX_neg=c["pIX"], kappa=c["kappa"])
              for pH in c["pH_list"]]
@@ -172,12 +180,16 @@ def test_matched_alpha_suspension_learned_fp32_vs_fp64():
         res[prec] = [S.series(r, first, meas).astype(np.float64) for r in range(R)]
         print("precision %d done" % prec, flush=True)
         S.close()
-    worst = 0.0
+    worst, z2 = 0.0, []
     for r in range(R):
         for col, nsite in ((0, nA), (1, nB)):
-            m1, s1, _ = mean_se(res[32][r][:, col] / nsite)
-            m2, s2, _ = mean_se(res[64][r][:, col] / nsite)
+            x1, x2 = res[32][r][:, col] / nsite, res[64][r][:, col] / nsite
+            m1, s1, _ = mean_se(x1)
+            m2, s2, _ = mean_se(x2)
+            s1, s2 = max(s1, blocking_se(x1)), max(s2, blocking_se(x2))
             z = abs(m1 - m2) / math.hypot(s1, s2)
             worst = max(worst, z)
-            assert z < 3.5, (r, col, m1, s1, m2, s2)
-    print("largest deviation %.2f combined SE" % worst, flush=True)
+            z2.append(z * z)
+            assert z < 4.0, (r, col, m1, s1, m2, s2)
+    assert float(np.mean(z2)) < 2.5, z2
+    print("largest deviation %.2f combined SE, mean squared %.2f" % (worst, float(np.mean(z2))), flush=True)

@@ -49,11 +49,16 @@ def test_library_host_paths_under_sanitizers():
     host_san = []
     for f in ("-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=all"):
         host_san += ["-Xarch_host", f]
+    # the kernel translation units (device code and thin launchers) are built
+    # as the product builds them; the host paths under test at -O1 -g
+    kernel_flags = ["-O3"] + base[1:]
     with tempfile.TemporaryDirectory() as d:
         objs = []
-        for src, san in (("crmc_kernels.hip", False), ("crmc_learn.hip", False), ("crmc_api.cpp", True)):
+        for src, san in (("crmc_kernels.hip", False), ("crmc_learn.hip", False), ("crmc_md.hip", False),
+                         ("crmc_api.cpp", True)):
             o = os.path.join(d, src + ".o")
-            subprocess.check_call([hipcc] + base + (host_san if san else []) + ["-c", os.path.join(CSRC, src), "-o", o],
+            flags = (base + host_san) if san else kernel_flags
+            subprocess.check_call([hipcc] + flags + ["-c", os.path.join(CSRC, src), "-o", o],
                                   stderr=subprocess.DEVNULL)
             objs.append(o)
         drv = os.path.join(d, "host_driver.o")
