@@ -82,14 +82,15 @@ __device__ __forceinline__ int rec_is_ion(uint32_t meta)
     const uint32_t k = meta & 7u;
     return k == KIND_XPOS || k == KIND_XNEG;
 }
+// Charge of a record from its kind and charged flag (meta & 15 = kind + 8
+// charged), looked up branch-free: two bits per value hold q + 1.  An acid is
+// -1 when charged, a base +1, a cation +1 and an anion -1 whatever the flag,
+// everything else 0.  The second table gives free ions charge 0 (ions that do
+// not couple).
+constexpr uint32_t Q_TABLE = 0x54a15495u, Q_TABLE_NO_ION = 0x55615555u;
 __device__ __forceinline__ int rec_q(uint32_t meta)
 {
-    const uint32_t k = meta & 7u, c = (meta >> 3) & 1u;
-    if (k == KIND_ACID) return -(int)c;
-    if (k == KIND_BASE) return (int)c;
-    if (k == KIND_XPOS) return 1;
-    if (k == KIND_XNEG) return -1;
-    return 0;
+    return (int)((Q_TABLE >> (2u * (meta & 15u))) & 3u) - 1;
 }
 
 __device__ __forceinline__ uint32_t rdl0(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 0); }
@@ -566,7 +567,8 @@ __device__ __forceinline__ Real yukawa(Real r2, const PairParams& P)
 // evaluated either, so nothing else of the meta word is needed.
 __device__ __forceinline__ uint32_t charge_bits(uint32_t meta, int ion_coupling)
 {
-    const int q = (ion_coupling || !rec_is_ion(meta)) ? rec_q(meta) : 0;
+    const uint32_t tab = ion_coupling ? Q_TABLE : Q_TABLE_NO_ION;
+    const int q = (int)((tab >> (2u * (meta & 15u))) & 3u) - 1;
     return __float_as_uint((float)q);
 }
 
