@@ -333,6 +333,9 @@ def main():
                          "default 0)")
     ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per phase workgroup in records (0 = default)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one in the timed region")
+    ap.add_argument("--tune-schedule", type=int, default=0, metavar="SWEEPS",
+                    help="first choose trials per cell (4, 8, 16) and pairing by independent samples/s, each "
+                         "candidate a chain of its own timed over SWEEPS sweeps (plain proposal)")
     ap.add_argument("--no-pairing", action="store_true",
                     help="single-cell domains instead of reflection-paired cell pairs")
     ap.add_argument("--kernel-steps", type=int, default=200, help="sweeps of the per-kernel event timing pass")
@@ -406,6 +409,16 @@ def main():
 
     systems, conds, model = load_workload(wl)
     R = len(conds)
+    schedule = None
+    if args.tune_schedule:
+        from paper_2109_07527_amd.tune import search_schedule
+        schedule = search_schedule(systems, conds, model, trials=(4, 8, 16), pairing=(True, False),
+                                   window=args.tune_schedule, equilibrate=args.equilibrate,
+                                   precision=args.precision, shape_sweeps=args.autotune)
+        args.trials = schedule["best"]["trials_per_cell"]
+        args.no_pairing = not schedule["best"]["pairing"]
+        progress("schedule: %d trials per cell, %s domains" % (args.trials, "paired" if not args.no_pairing
+                                                                 else "single-cell"))
     S = crmc.System(n_replicas=R, lB=model["lB"], rc=model["rc"], eps=1.0, precision=args.precision,
                     trials_per_cell=args.trials, pairing=not args.no_pairing, seed=2024, site_trials=args.site_trials,
                     ion_trials=args.ion_trials,
@@ -520,6 +533,10 @@ def main():
                                "best_ms_per_sweep": round(tuned["best_ms_per_sweep"], 4)}
     if wl != "chains":
         config.update(cells_per_edge=after[0]["n_cells"], cell_capacity=after[0]["cell_capacity"])
+    if schedule is not None:
+        config["schedule_search"] = [{k: c[k] for k in ("trials_per_cell", "pairing", "ms_per_sweep",
+                                                        "independent_samples_per_s", "window_over_50_tau")}
+                                     for c in schedule["candidates"]]
     head = lstats if use_learned else plain
     samples = None
     if head is not None and head["independent_samples_per_s"] is not None:

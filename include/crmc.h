@@ -454,15 +454,20 @@ int crmc_mlp_gradient(crmc_t h, const float* rows, int32_t n, float* grad, doubl
  * result: the chain depends only on the seed, the schedule and the
  * conditions, so the tuning sweeps are ordinary sweeps of the chain (they
  * advance it by out->sweeps_used sweeps under per_replica conditions).
- * Every replica must be built.  Synchronizes.  Errors: CRMC_E_ARG for
- * sweeps_per_candidate outside 1..100000, CRMC_E_STATE before build; on a
- * device error the previous launch shape is kept.
+ * Every replica must be built.  Synchronizes.  A configuration tuned before
+ * in the same process (same device, precision, schedule, proposal, seed,
+ * and replicas of the same grids, capacities, cores, sites and built particle
+ * counts) takes the cached shape without timing: out->reserved = 1,
+ * n_candidates = 0 and sweeps_used = 0 (the chain does not advance).
+ * Errors: CRMC_E_ARG for sweeps_per_candidate outside 1..100000,
+ * CRMC_E_STATE before build; on a device error the previous launch shape is
+ * kept.
  */
 #define CRMC_TUNE_MAX 32
 typedef struct {
     int32_t light_neighbours, lds_records; /* chosen launch shape */
     int32_t n_candidates;
-    int32_t reserved;
+    int32_t reserved;                      /* 1: the shape came from this process's cache */
     int64_t sweeps_used;                   /* sweeps the tuning advanced the chain by */
     double best_ms_per_sweep;
     double ms_per_sweep[CRMC_TUNE_MAX];    /* per candidate */

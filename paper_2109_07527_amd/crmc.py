@@ -339,7 +339,7 @@ def crmc_autotune(h, conds, sweeps_per_candidate):
     _check(h, load().crmc_autotune(h, arr, int(sweeps_per_candidate), C.byref(t)))
     n = t.n_candidates
     return {"light_neighbours": t.light_neighbours, "lds_records": t.lds_records, "sweeps_used": t.sweeps_used,
-            "best_ms_per_sweep": t.best_ms_per_sweep,
+            "best_ms_per_sweep": t.best_ms_per_sweep, "cached": bool(t.reserved),
             "candidates": [(t.cand_light[i], t.cand_lds[i], t.ms_per_sweep[i]) for i in range(n)]}
 
 

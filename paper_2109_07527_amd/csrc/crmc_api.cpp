@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -49,6 +50,7 @@ struct HostReplica {
     std::vector<double> init_delta;
     int64_t init_tot[4] = {0, 0, 0, 0};
     uint32_t init_maxc = 0;
+    int64_t n_built = 0;   // particles the replica was built with
 };
 
 // Device memory of a handle: the library's own allocations, or blocks of a
@@ -946,6 +948,7 @@ int crmc_build_cells(crmc_t h, int32_t replica, double L, int32_t n_cells, int32
     // the initial state stays on the host until the device state is created
     r.init_rec.clear();
     r.init_rec.reserve((size_t)n);
+    r.n_built = (int64_t)n;
     r.init_cnt.assign(ncells, 0u);
     for (uint32_t c = 0; c < ncells; ++c) {
         r.init_cnt[c] = (uint32_t)lists[c].size();
@@ -1441,6 +1444,27 @@ int crmc_md(crmc_t h, int64_t n_steps, double dt, double gamma)
     return CRMC_OK;
 }
 
+// Launch shapes chosen by crmc_autotune in this process, keyed by the device,
+// precision, schedule, proposal, seed and the replicas' grids, capacities,
+// cores and sizes: a handle rebuilt on the same inputs tunes once.
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<int, int>> g_tune_cache;
+
+static std::string tune_key(crmc_t h, int dev)
+{
+    std::string k;
+    char b[160];
+    std::snprintf(b, sizeof b, "d%d p%d t%d s%d i%d q%d f%d l%d k%llu;", dev, h->p.precision, h->p.trials_per_cell,
+                  h->p.site_trials, h->p.ion_trials, h->p.pairing, h->p.fixed_grid, (int)h->learned,
+                  (unsigned long long)h->p.seed);
+    k += b;
+    for (auto& r : h->reps) {
+        std::snprintf(b, sizeof b, "%u,%u,%u,%u,%lld;", r.n, r.cap, r.ncores, r.nsites, (long long)r.n_built);
+        k += b;
+    }
+    return k;
+}
+
 int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_candidate, crmc_tune* out)
 {
     if (!h || !per_replica || !out || sweeps_per_candidate < 1 || sweeps_per_candidate > 100000)
@@ -1453,6 +1477,21 @@ int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_can
     int dev = 0, maxlds = 0;
     HIP_TRY(h, hipGetDevice(&dev));
     HIP_TRY(h, hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const std::string key = tune_key(h, dev);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        const auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            // the same configuration was tuned before in this process
+            std::memset(out, 0, sizeof *out);
+            h->p.light_neighbours = it->second.first;
+            h->pool = it->second.second;
+            out->light_neighbours = it->second.first;
+            out->lds_records = it->second.second;
+            out->reserved = 1;
+            return CRMC_OK;
+        }
+    }
     const int pool_min = (int)((h->learned ? 4 : 3) * maxcap + 128);
     const int pool_max = (maxlds - 1024) / (int)sizeof(uint4);
     const int light_c[] = {256, 512, 768, 1024, 1536};
@@ -1512,6 +1551,10 @@ int crmc_autotune(crmc_t h, const crmc_cond* per_replica, int32_t sweeps_per_can
     out->lds_records = best_p;
     out->best_ms_per_sweep = best;
     out->sweeps_used = (int64_t)out->n_candidates * (sweeps_per_candidate + 1);
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune_cache[key] = std::make_pair(best_l, best_p);
+    }
     return CRMC_OK;
 }
 

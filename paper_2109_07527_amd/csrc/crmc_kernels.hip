@@ -364,8 +364,10 @@ constexpr int MAX_LDS_CORES = 64; // nanoparticle cores copied on chip (more are
 // LDS pool of one domain, offsets in 16-byte records:
 //   member 0's list | member 1's list | ln k table (doubles) | cores | core
 //   Deltas (doubles) | neighbour records (as many as fit)
-// longest list (with room for growth) a light domain holds in registers
+// longest list (with room for growth) a light domain holds in registers, and
+// the plan's flag for such a domain (a bit of the replica word of its slot)
 constexpr int REG_ROOM = 64;
+constexpr uint32_t GEO_REG = 0x80000000u;
 
 struct Pool {
     int room0, room1;
@@ -484,9 +486,11 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
         const int n1 = G.ncell == 2 ? (int)R.cnt0[G.cell1] : 0;
         const int ntr_max = (a.trials + a.ion_trials) * G.ncell + ((n0 + n1) * a.site_trials + 15) / 16;
         const Pool p = pool_layout(n0, n1, G.ncell, ntr_max, R.cap, R.ncores, a.learned);
-        // a light domain keeps its lists in registers, one record per lane
-        light = nb <= a.light_nb && p.st_off <= a.pool / 4 && p.room0 <= REG_ROOM && p.room1 <= REG_ROOM;
-        geo = make_uint4(r, G.cell0, G.ncell == 2 ? G.cell1 : G.cell0, (uint32_t)n0 | ((uint32_t)n1 << 16));
+        light = nb <= a.light_nb && p.st_off <= a.pool / 4;
+        // a light domain whose lists (with their room) fit 64 records each
+        // keeps them in registers, one record per lane (flag: bit 31)
+        const uint32_t reg = light && p.room0 <= REG_ROOM && p.room1 <= REG_ROOM ? GEO_REG : 0u;
+        geo = make_uint4(r | reg, G.cell0, G.ncell == 2 ? G.cell1 : G.cell0, (uint32_t)n0 | ((uint32_t)n1 << 16));
     }
     const uint64_t ml = __ballot(valid && light), mh = __ballot(valid && !light);
     const uint32_t lane = threadIdx.x;
@@ -985,18 +989,20 @@ __device__ __forceinline__ void reg_append(uint4& r, double& d, int nn, uint4 v,
 }
 // The domain's trials.  WPD wavefronts share the pair sums (WPD = 1: light
 // domain, no workgroup barriers; WPD = 4: heavy domain, the whole workgroup;
-// uniform over the workgroup).
-template <typename Real, bool LEARNED, bool RELOC, bool FAST, int WPD>
+// uniform over the workgroup).  REGL: the domain's lists in registers (light
+// domains whose lists fit), else in the pool.
+template <typename Real, bool LEARNED, bool RELOC, bool FAST, int WPD, bool REGL>
 __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint4 geo, uint4* __restrict__ pool,
                                            int pool_records, int wid, double (*red)[4], int (*ovf)[4])
 {
+    static_assert(!REGL || WPD == 1, "register lists are held by one wavefront");
     constexpr int wpd = WPD;
-    constexpr bool REG = WPD == 1; // the domain's lists in registers (light) or in the pool (heavy)
+    constexpr bool REG = REGL;
     constexpr int nt = 64 * wpd;
     const int lane = threadIdx.x & 63;
     const int tid = wid * 64 + lane;
     const uint64_t t_start = a.trace ? wall_clock64() : 0;
-    const uint32_t r = rflu(geo.x);
+    const uint32_t r = rflu(geo.x) & ~GEO_REG;
     const Replica& R = a.reps[r];
     const uint32_t n = R.n, cap = R.cap;
     const uint64_t s = *a.sweep;
@@ -1932,8 +1938,10 @@ __device__ __forceinline__ void phase_body(const SweepArgs& a)
     const size_t slot = (size_t)colour * a.ndom_total + j;
     const uint32_t gd = heavy ? a.plan_heavy[slot] : a.plan_light[slot];
     const uint4 geo = heavy ? a.plan_geo_heavy[slot] : a.plan_geo_light[slot];
-    if (heavy) run_domain<Real, LEARNED, RELOC, FAST, 4>(a, gd, geo, smem, q, wave, red, ovf);
-    else run_domain<Real, LEARNED, RELOC, FAST, 1>(a, gd, geo, smem + (size_t)wave * q, q, 0, red, ovf);
+    if (heavy) run_domain<Real, LEARNED, RELOC, FAST, 4, false>(a, gd, geo, smem, q, wave, red, ovf);
+    else if (geo.x & GEO_REG)
+        run_domain<Real, LEARNED, RELOC, FAST, 1, true>(a, gd, geo, smem + (size_t)wave * q, q, 0, red, ovf);
+    else run_domain<Real, LEARNED, RELOC, FAST, 1, false>(a, gd, geo, smem + (size_t)wave * q, q, 0, red, ovf);
 }
 
 template <typename Real, bool LEARNED, bool RELOC>

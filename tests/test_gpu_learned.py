@@ -126,12 +126,17 @@ def _run_pair(crmc, name, eps, learned_gpu=True, learned_oracle=True, nsw=12, tr
     return S, obs, o, ser, nsw
 
 
-@pytest.mark.parametrize("name,offsets,ion_trials", [("mixed", (0.0, 0.0), 0), ("np_pair_small", (0.0, 0.0), 0),
-                                                     ("chain40", (0.0, 0.0), 0), ("np_pair_small", (-2.5, 1.5), 0),
-                                                     ("np_pair_small", (0.0, 0.0), 2)])
-def test_fp64_learned_chain_bit_exact(name, offsets, ion_trials):
+@pytest.mark.parametrize("name,offsets,ion_trials,trials", [("mixed", (0.0, 0.0), 0, 2), ("np_pair_small", (0.0, 0.0), 0, 2),
+                                                            ("chain40", (0.0, 0.0), 0, 2),
+                                                            ("np_pair_small", (-2.5, 1.5), 0, 2),
+                                                            ("np_pair_small", (0.0, 0.0), 2, 2),
+                                                            ("np_pair_small", (0.0, 0.0), 0, 20)])
+def test_fp64_learned_chain_bit_exact(name, offsets, ion_trials, trials):
+    """The FP64 learned chain is the oracle's bit for bit; with 20 trials per
+    cell the light domains' lists exceed 64 records with their room and stay
+    in the LDS pool instead of registers."""
     crmc = _gpu()
-    S, obs, o, ser, nsw = _run_pair(crmc, name, 0.1, offsets=offsets, ion_trials=ion_trials)
+    S, obs, o, ser, nsw = _run_pair(crmc, name, 0.1, offsets=offsets, ion_trials=ion_trials, trials=trials)
     for a, b in zip(S.particles(0), o.particles()):
         assert np.array_equal(np.asarray(a).astype(np.int64), np.asarray(b).astype(np.int64))
     assert np.array_equal(S.series(0, 0, nsw), ser)

@@ -488,14 +488,18 @@ def test_config5_full_size_sampled_replica():
 @pytest.mark.parametrize("case", ["mixed", "np_pair_small", "chain40"])
 @pytest.mark.parametrize("light", [1, 65536])
 @pytest.mark.parametrize("ion_trials", [0, 1])
-def test_light_and_heavy_domains_bit_exact(case, light, ion_trials):
+@pytest.mark.parametrize("trials", [3, 20])
+def test_light_and_heavy_domains_bit_exact(case, light, ion_trials, trials):
     """Every domain on a whole workgroup (light_neighbours = 1) or every domain
-    that fits on one wavefront: the chain is the oracle's either way."""
+    that fits on one wavefront: the chain is the oracle's either way.  With 3
+    trials per cell the light domains' lists (with room for two insertions per
+    trial) fit 64 records and sit in registers; with 20 they do not, and the
+    light domains keep them in the LDS pool."""
     crmc = _gpu()
     make, model, cond = CASES[case]
     s = make()
     S = crmc.System(n_replicas=1, lB=model["lB"], rc=model["rc"], eps=model["eps"],
-                    ion_coupling=model["ion_coupling"], precision=64, trials_per_cell=3, seed=41,
+                    ion_coupling=model["ion_coupling"], precision=64, trials_per_cell=trials, seed=41,
                     light_neighbours=light, ion_trials=ion_trials)
     kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"])
     if len(s.get("core_R", [])):
@@ -504,7 +508,7 @@ def test_light_and_heavy_domains_bit_exact(case, light, ion_trials):
     S.sweep_ex([cond], 12)
     obs = S.observe(0)
     assert obs["status"] == 0
-    o = _oracle_for(s, model, cond, obs["n_cells"], 3, True, seed=41, ion_trials=ion_trials)
+    o = _oracle_for(s, model, cond, obs["n_cells"], trials, True, seed=41, ion_trials=ion_trials)
     ser = o.sweeps(12)
     _same_state(S.particles(0), o.particles())
     assert np.array_equal(S.series(0, 0, 12), ser)
