@@ -333,6 +333,9 @@ def main():
                          "default 0)")
     ap.add_argument("--lds-records", type=int, default=0, help="LDS pool per phase workgroup in records (0 = default)")
     ap.add_argument("--no-graph", action="store_true", help="launch kernels one by one in the timed region")
+    ap.add_argument("--md-steps", type=int, default=0, metavar="N",
+                    help="after the timed sweeps, time one hybrid-MD block of N Langevin steps (dt 0.005, "
+                         "gamma 1) of the free ions and report it under 'md'")
     ap.add_argument("--tune-schedule", type=int, default=0, metavar="SWEEPS",
                     help="first choose trials per cell (4, 8, 16) and pairing by independent samples/s, each "
                          "candidate a chain of its own timed over SWEEPS sweeps (plain proposal)")
@@ -555,6 +558,19 @@ def main():
         "roofline": roofline,
         "cpu_baseline": None,
     }
+    if args.md_steps:
+        # one block of the hybrid protocol: start velocities, N velocity-Verlet steps with the
+        # Langevin thermostat, re-binning after every drift, and the energy restart at the end
+        S.md(10, 0.005, 1.0)
+        torch.cuda.synchronize()
+        ions = sum(S.observe(r)["n_xpos"] + S.observe(r)["n_xneg"] for r in range(R))
+        t0 = time.perf_counter()
+        S.md(args.md_steps, 0.005, 1.0)
+        torch.cuda.synchronize()
+        md_s = time.perf_counter() - t0
+        line["md"] = {"steps": args.md_steps, "dt": 0.005, "gamma": 1.0, "ions": int(ions),
+                      "ms_per_block": round(1e3 * md_s, 3), "ms_per_step": round(1e3 * md_s / args.md_steps, 4),
+                      "ion_steps_per_s": round(ions * args.md_steps / md_s, 1)}
     if head is not None:
         line["stats"] = head
     if use_learned and plain is not None and lstats is not None:

@@ -11,7 +11,8 @@
 //                 the exact integer cutoff, excluded volume with every other
 //                 particle, expanded excluded volume of the cores; with the
 //                 Langevin drag and noise (counter (step, cell, slot, 7)) and
-//                 the second half kick when asked.
+//                 the second half kick when asked.  The cell's neighbourhood
+//                 is staged in LDS and eight lanes share each ion.
 //   k_md_drift    first half kick and drift, rounded to the position lattice.
 //   k_md_rebin    the moved ions back into cells of the same grid (the grid of
 //                 the last sweep), stably: a new cell gathers its records from
@@ -74,57 +75,43 @@ __device__ __forceinline__ int md_q(uint32_t meta)
     return 0;
 }
 
-// -grad of the energy on free ion a (record ra at cell c, slot j of buf)
-__device__ void md_ion_force(const Replica& R, int buf, uint32_t c, uint32_t j, const uint4& ra, const MdArgs& m,
-                             double f[3])
+// Force on ion a (charge qa) from record rb, added to f: screened Coulomb
+// inside the exact integer cutoff, excluded volume below 2^(1/6), both as
+// minus the gradient of the truncated pair energy, in FP64.
+__device__ __forceinline__ void md_pair(const uint4& ra, int qa, const uint4& rb, const Replica& R, const MdArgs& m,
+                                        double s, double f[3])
 {
-    f[0] = f[1] = f[2] = 0.0;
-    if (!m.ion_coupling) return; // ideal ions feel nothing
-    const uint32_t n = R.n, cap = R.cap;
-    const uint32_t cx = c % n, cy = (c / n) % n, cz = c / (n * n);
-    const uint4* recb = R.rec[buf];
-    const uint32_t* cntb = R.cnt[buf];
-    const double s = R.scale;
-    const int qa = md_q(ra.w);
-    for (int o = 0; o < 27; ++o) {
-        const uint32_t x = (cx + n + (uint32_t)(o % 3) - 1u) % n, y = (cy + n + (uint32_t)((o / 3) % 3) - 1u) % n,
-                       z = (cz + n + (uint32_t)(o / 9) - 1u) % n;
-        const uint32_t oc = x + n * (y + n * z);
-        const uint32_t cnt = cntb[oc];
-        for (uint32_t k = 0; k < cnt; ++k) {
-            if (oc == c && k == j) continue;
-            const uint4 rb = recb[(size_t)oc * cap + k];
-            const int32_t dx = (int32_t)(ra.x - rb.x), dy = (int32_t)(ra.y - rb.y), dz = (int32_t)(ra.z - rb.z);
-            const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
-            const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
-            const double fx = dx * s, fy = dy * s, fz = dz * s;
-            const double r2 = fx * fx + fy * fy + fz * fz;
-            double g = 0.0;
-            const int qb = md_q(rb.w);
-            if (r2i < R.R2 && qa != 0 && qb != 0) {
-                const double r = sqrt(r2);
-                g += m.lB * (double)(qa * qb) * exp(-R.kappa * r) * (1.0 + R.kappa * r) / (r2 * r);
-            }
-            if (m.eps > 0.0 && r2 < 1.2599210498948731647672106) {
-                const double ir2 = 1.0 / r2, ir6 = ir2 * ir2 * ir2;
-                g += 4.0 * m.eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir2;
-            }
-            f[0] += g * fx; f[1] += g * fy; f[2] += g * fz;
-        }
+    const int32_t dx = (int32_t)(ra.x - rb.x), dy = (int32_t)(ra.y - rb.y), dz = (int32_t)(ra.z - rb.z);
+    const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
+    const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+    const double fx = dx * s, fy = dy * s, fz = dz * s;
+    const double r2 = fx * fx + fy * fy + fz * fz;
+    double g = 0.0;
+    const int qb = md_q(rb.w);
+    if (r2i < R.R2 && qa != 0 && qb != 0) {
+        const double r = sqrt(r2);
+        g += m.lB * (double)(qa * qb) * exp(-R.kappa * r) * (1.0 + R.kappa * r) / (r2 * r);
     }
-    if (m.eps > 0.0) {
-        for (uint32_t k = 0; k < R.ncores; ++k) {
-            const uint4 cc = R.core_x[k];
-            const int32_t dx = (int32_t)(ra.x - cc.x), dy = (int32_t)(ra.y - cc.y), dz = (int32_t)(ra.z - cc.z);
-            const double fx = dx * s, fy = dy * s, fz = dz * s;
-            const double r = sqrt(fx * fx + fy * fy + fz * fz);
-            const double sh = r - R.core_delta[k];
-            if (sh < 1.122462048309373) {
-                const double ir = 1.0 / sh, ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
-                const double g = 4.0 * m.eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir / r;
-                f[0] += g * fx; f[1] += g * fy; f[2] += g * fz;
-            }
-        }
+    if (m.eps > 0.0 && r2 < 1.2599210498948731647672106) {
+        const double ir2 = 1.0 / r2, ir6 = ir2 * ir2 * ir2;
+        g += 4.0 * m.eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir2;
+    }
+    f[0] += g * fx; f[1] += g * fy; f[2] += g * fz;
+}
+
+// the expanded excluded volume of core k on ion ra, added to f
+__device__ __forceinline__ void md_core(const uint4& ra, const Replica& R, uint32_t k, const MdArgs& m, double s,
+                                        double f[3])
+{
+    const uint4 cc = R.core_x[k];
+    const int32_t dx = (int32_t)(ra.x - cc.x), dy = (int32_t)(ra.y - cc.y), dz = (int32_t)(ra.z - cc.z);
+    const double fx = dx * s, fy = dy * s, fz = dz * s;
+    const double r = sqrt(fx * fx + fy * fy + fz * fz);
+    const double sh = r - R.core_delta[k];
+    if (sh < 1.122462048309373) {
+        const double ir = 1.0 / sh, ir2 = ir * ir, ir6 = ir2 * ir2 * ir2;
+        const double g = 4.0 * m.eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir / r;
+        f[0] += g * fx; f[1] += g * fy; f[2] += g * fz;
     }
 }
 
@@ -162,33 +149,94 @@ __global__ __launch_bounds__(64) void k_md_vinit(MdArgs m, int buf, uint64_t ste
     }
 }
 
-// forces in the binning of buf; with langevin set, the drag and the noise of
-// MD step `step` are added and the second half kick is applied
+// Forces in the binning of buf; with langevin set, the drag and the noise of
+// MD step `step` are added and the second half kick is applied.  One
+// wavefront per cell: the records of the 27 cells around it (cells are at
+// least rc wide) are staged in LDS once, segment by segment (the first
+// MD_STAGE of them; the rest are read from memory), then the cell's slots are
+// taken MD_PER at a time, MD_GROUP lanes per slot splitting its partners, and
+// each force is summed over its group.
+constexpr int MD_STAGE = 512, MD_GROUP = 8, MD_PER = 64 / MD_GROUP;
+
 __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t step, int langevin)
 {
+    __shared__ uint4 nbr[MD_STAGE];
     const CellOf t = md_cell(m, buf);
     if (!t.live) return;
     const Replica& R = m.reps[t.r];
-    for (uint32_t j = threadIdx.x; j < t.cnt; j += blockDim.x) {
-        const size_t slot = (size_t)t.c * R.cap + j;
-        const uint4 ra = R.rec[buf][slot];
-        double* fb = m.force[t.r] + 3 * slot;
-        if (!md_is_ion(ra.w)) {
-            fb[0] = fb[1] = fb[2] = 0.0;
-            continue;
-        }
-        double f[3];
-        md_ion_force(R, buf, t.c, j, ra, m, f);
-        if (langevin) {
-            double z[3];
-            md_normals3(R, (uint32_t)step, t.c, j, TAG_MDNOISE, z);
-            double* vb = m.vel[t.r * 2 + buf] + 3 * slot;
-            for (int q = 0; q < 3; ++q) {
-                f[q] = f[q] - m.gamma * vb[q] + m.noise * z[q];
-                vb[q] += 0.5 * m.dt * f[q];
+    const uint32_t lane = threadIdx.x, n = R.n, cap = R.cap, c = t.c;
+    const uint32_t cx = c % n, cy = (c / n) % n, cz = c / (n * n);
+    const uint4* recb = R.rec[buf];
+    const uint32_t* cntb = R.cnt[buf];
+    const double s = R.scale;
+    // lane o < 27: neighbour cell o (x fastest, offsets -1, 0, +1), its count
+    // and where its records start in the concatenated list
+    uint32_t ocell = 0u;
+    int ocnt = 0;
+    if (lane < 27) {
+        const uint32_t x = (cx + n + (lane % 3) - 1u) % n, y = (cy + n + ((lane / 3) % 3) - 1u) % n,
+                       z = (cz + n + (lane / 9) - 1u) % n;
+        ocell = x + n * (y + n * z);
+        ocnt = (int)cntb[ocell];
+    }
+    int pre = ocnt;
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) {
+        const int v = __shfl_up(pre, off, 64);
+        if ((int)lane >= off) pre += v;
+    }
+    const int ostart = pre - ocnt;
+    for (int o = 0; o < 27; ++o) {
+        const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, o);
+        const int cn = __builtin_amdgcn_readlane(ocnt, o), st = __builtin_amdgcn_readlane(ostart, o);
+        for (int k = (int)lane; k < cn && st + k < MD_STAGE; k += 64) nbr[st + k] = recb[(size_t)oc * cap + k];
+    }
+    __syncthreads();
+    const int grp = (int)lane / MD_GROUP, sub = (int)lane % MD_GROUP;
+    for (int j0 = 0; j0 < (int)t.cnt; j0 += MD_PER) {
+        const int j = j0 + grp;
+        const bool have = j < (int)t.cnt;
+        const size_t slot = (size_t)c * cap + (size_t)(have ? j : 0);
+        const uint4 ra = recb[slot];
+        const bool ion = have && md_is_ion(ra.w);
+        double f[3] = {0.0, 0.0, 0.0};
+        if (ion && m.ion_coupling) { // ideal ions feel nothing
+            const int qa = md_q(ra.w);
+            for (int o = 0; o < 27; ++o) {
+                const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, o);
+                const int cn = __builtin_amdgcn_readlane(ocnt, o), st = __builtin_amdgcn_readlane(ostart, o);
+                for (int k = sub; k < cn; k += MD_GROUP) {
+                    if (oc == c && k == j) continue;
+                    const uint4 rb = st + k < MD_STAGE ? nbr[st + k] : recb[(size_t)oc * cap + k];
+                    md_pair(ra, qa, rb, R, m, s, f);
+                }
             }
+            if (m.eps > 0.0)
+                for (uint32_t k = (uint32_t)sub; k < R.ncores; k += MD_GROUP) md_core(ra, R, k, m, s, f);
         }
-        fb[0] = f[0]; fb[1] = f[1]; fb[2] = f[2];
+#pragma unroll
+        for (int off = 1; off < MD_GROUP; off <<= 1) {
+            f[0] += __shfl_xor(f[0], off, 64);
+            f[1] += __shfl_xor(f[1], off, 64);
+            f[2] += __shfl_xor(f[2], off, 64);
+        }
+        if (have && sub == 0) {
+            double* fb = m.force[t.r] + 3 * slot;
+            if (!ion) {
+                fb[0] = fb[1] = fb[2] = 0.0;
+                continue;
+            }
+            if (langevin) {
+                double z[3];
+                md_normals3(R, (uint32_t)step, c, (uint32_t)j, TAG_MDNOISE, z);
+                double* vb = m.vel[t.r * 2 + buf] + 3 * slot;
+                for (int q = 0; q < 3; ++q) {
+                    f[q] = f[q] - m.gamma * vb[q] + m.noise * z[q];
+                    vb[q] += 0.5 * m.dt * f[q];
+                }
+            }
+            fb[0] = f[0]; fb[1] = f[1]; fb[2] = f[2];
+        }
     }
 }
 
