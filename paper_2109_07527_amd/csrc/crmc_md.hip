@@ -65,22 +65,25 @@ __device__ __forceinline__ int md_is_ion(uint32_t meta)
     return k == KIND_XPOS || k == KIND_XNEG;
 }
 
+// charge of a record, looked up branch-free from meta & 15 (kind + 8 charged):
+// two bits per value hold q + 1 (an acid -1 when charged, a base +1, a cation
+// +1 and an anion -1 whatever the flag, everything else 0)
 __device__ __forceinline__ int md_q(uint32_t meta)
 {
-    const uint32_t k = meta & 7u, c = (meta >> 3) & 1u;
-    if (k == KIND_ACID) return -(int)c;
-    if (k == KIND_BASE) return (int)c;
-    if (k == KIND_XPOS) return 1;
-    if (k == KIND_XNEG) return -1;
-    return 0;
+    return (int)((0x54a15495u >> (2u * (meta & 15u))) & 3u) - 1;
 }
 
 // Force on ion a (charge qa) from record rb, added to f: screened Coulomb
 // inside the exact integer cutoff, excluded volume below 2^(1/6), both as
 // minus the gradient of the truncated pair energy, in FP64.
-__device__ __forceinline__ void md_pair(const uint4& ra, int qa, const uint4& rb, const Replica& R, const MdArgs& m,
-                                        double s, double f[3])
+struct MdPair {
+    double s, lB, kappa, eps; // lattice unit, Bjerrum length, screening, WCA depth
+    uint64_t R2;              // Coulomb cutoff on the integer squared distance
+};
+
+__device__ __forceinline__ void md_pair(const uint4& ra, int qa, const uint4& rb, const MdPair& P, double f[3])
 {
+    const double s = P.s;
     const int32_t dx = (int32_t)(ra.x - rb.x), dy = (int32_t)(ra.y - rb.y), dz = (int32_t)(ra.z - rb.z);
     const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
     const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
@@ -88,13 +91,13 @@ __device__ __forceinline__ void md_pair(const uint4& ra, int qa, const uint4& rb
     const double r2 = fx * fx + fy * fy + fz * fz;
     double g = 0.0;
     const int qb = md_q(rb.w);
-    if (r2i < R.R2 && qa != 0 && qb != 0) {
+    if (r2i < P.R2 && qa != 0 && qb != 0) {
         const double r = sqrt(r2);
-        g += m.lB * (double)(qa * qb) * exp(-R.kappa * r) * (1.0 + R.kappa * r) / (r2 * r);
+        g += P.lB * (double)(qa * qb) * exp(-P.kappa * r) * (1.0 + P.kappa * r) / (r2 * r);
     }
-    if (m.eps > 0.0 && r2 < 1.2599210498948731647672106) {
+    if (P.eps > 0.0 && r2 < 1.2599210498948731647672106) {
         const double ir2 = 1.0 / r2, ir6 = ir2 * ir2 * ir2;
-        g += 4.0 * m.eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir2;
+        g += 4.0 * P.eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir2;
     }
     f[0] += g * fx; f[1] += g * fy; f[2] += g * fz;
 }
@@ -155,7 +158,9 @@ __global__ __launch_bounds__(64) void k_md_vinit(MdArgs m, int buf, uint64_t ste
 // least rc wide) are staged in LDS once, segment by segment (the first
 // MD_STAGE of them; the rest are read from memory), then the cell's slots are
 // taken MD_PER at a time, MD_GROUP lanes per slot splitting its partners, and
-// each force is summed over its group.
+// each force is summed over its group.  (Screening the partners first and
+// packing the interacting ones into a dense list was slower: the distance
+// tests cost about as much as the pair terms they would skip.)
 constexpr int MD_STAGE = 512, MD_GROUP = 8, MD_PER = 64 / MD_GROUP;
 
 __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t step, int langevin)
@@ -169,6 +174,7 @@ __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t ste
     const uint4* recb = R.rec[buf];
     const uint32_t* cntb = R.cnt[buf];
     const double s = R.scale;
+    const MdPair P{s, m.lB, R.kappa, m.eps, R.R2};
     // lane o < 27: neighbour cell o (x fastest, offsets -1, 0, +1), its count
     // and where its records start in the concatenated list
     uint32_t ocell = 0u;
@@ -205,10 +211,14 @@ __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t ste
             for (int o = 0; o < 27; ++o) {
                 const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, o);
                 const int cn = __builtin_amdgcn_readlane(ocnt, o), st = __builtin_amdgcn_readlane(ostart, o);
-                for (int k = sub; k < cn; k += MD_GROUP) {
+                const int staged = min(cn, max(MD_STAGE - st, 0));
+                for (int k = sub; k < staged; k += MD_GROUP) {
                     if (oc == c && k == j) continue;
-                    const uint4 rb = st + k < MD_STAGE ? nbr[st + k] : recb[(size_t)oc * cap + k];
-                    md_pair(ra, qa, rb, R, m, s, f);
+                    md_pair(ra, qa, nbr[st + k], P, f);
+                }
+                for (int k = staged + sub; k < cn; k += MD_GROUP) {
+                    if (oc == c && k == j) continue;
+                    md_pair(ra, qa, recb[(size_t)oc * cap + k], P, f);
                 }
             }
             if (m.eps > 0.0)
@@ -272,12 +282,13 @@ __global__ __launch_bounds__(64) void k_md_rebin(MdArgs m, int buf)
     const uint32_t cx = c % n, cy = (c / n) % n, cz = c / (n * n);
     const uint32_t lane = threadIdx.x;
     const uint32_t o0 = R.tab->o[0], o1 = R.tab->o[1], o2 = R.tab->o[2];
-    // the 27 cells around c in ascending index
-    uint32_t nb = 0xFFFFFFFFu;
+    // the 27 cells around c, their counts loaded at once
+    uint32_t nb = 0xFFFFFFFFu, ncnt = 0u;
     if (lane < 27) {
         const uint32_t x = (cx + n + (lane % 3) - 1u) % n, y = (cy + n + ((lane / 3) % 3) - 1u) % n,
                        z = (cz + n + (lane / 9) - 1u) % n;
         nb = x + n * (y + n * z);
+        ncnt = R.cnt[buf][nb];
     }
     // rank of this lane's cell among the 27 (distinct when n >= 3)
     uint32_t rank = 0;
@@ -291,10 +302,11 @@ __global__ __launch_bounds__(64) void k_md_rebin(MdArgs m, int buf)
     double* vdst = m.vel[r * 2 + (buf ^ 1)];
     uint32_t out = 0;
     for (uint32_t q = 0; q < 27; ++q) {
-        // the source cell of rank q
+        // the source cell of rank q (cells in ascending index)
         const uint64_t who = __ballot(lane < 27 && rank == q);
-        const uint32_t sc = (uint32_t)__shfl((int)nb, (int)__builtin_ctzll(who), 64);
-        const uint32_t cnt = R.cnt[buf][sc];
+        const int src_lane = (int)__builtin_ctzll(who);
+        const uint32_t sc = (uint32_t)__shfl((int)nb, src_lane, 64);
+        const uint32_t cnt = (uint32_t)__shfl((int)ncnt, src_lane, 64);
         for (uint32_t b0 = 0; b0 < cnt; b0 += 64) {
             const uint32_t k = b0 + lane;
             bool mine = false;
