@@ -1417,6 +1417,7 @@ int crmc_md(crmc_t h, int64_t n_steps, double dt, double gamma)
     m.gamma = gamma;
     m.noise = std::sqrt(2.0 * gamma / dt);
     m.ion_coupling = h->p.ion_coupling;
+    m.precision = h->p.precision;
     const int buf0 = (int)(h->sweeps & 1);
     int buf = buf0;
     HIP_TRY(h, launch_md_block(m, buf0, h->md_steps, n_steps, maxcap, h->stream, &buf));

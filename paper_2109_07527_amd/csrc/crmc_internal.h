@@ -175,6 +175,7 @@ struct MdArgs {
     uint32_t* err;            // device error flags
     double lB, eps, dt, gamma, noise; // noise = sqrt(2 gamma kT / (m dt)), kT = m = 1
     int32_t ion_coupling;
+    int32_t precision;        // 32: pair forces in FP32 (summed in FP64), 64: all FP64
 };
 
 // launchers (device translation units)

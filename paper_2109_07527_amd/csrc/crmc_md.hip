@@ -12,7 +12,8 @@
 //                 particle, expanded excluded volume of the cores; with the
 //                 Langevin drag and noise (counter (step, cell, slot, 7)) and
 //                 the second half kick when asked.  The cell's neighbourhood
-//                 is staged in LDS and eight lanes share each ion.
+//                 is staged in LDS and eight lanes share each ion.  Pair
+//                 terms in FP64, or in FP32 (summed in FP64) for FP32 handles.
 //   k_md_drift    first half kick and drift, rounded to the position lattice.
 //   k_md_rebin    the moved ions back into cells of the same grid (the grid of
 //                 the last sweep), stably: a new cell gathers its records from
@@ -79,6 +80,7 @@ __device__ __forceinline__ int md_q(uint32_t meta)
 struct MdPair {
     double s, lB, kappa, eps; // lattice unit, Bjerrum length, screening, WCA depth
     uint64_t R2;              // Coulomb cutoff on the integer squared distance
+    float sf, lBf, kappaf, klf, epsf; // FP32 copies; klf = -kappa log2(e)
 };
 
 __device__ __forceinline__ void md_pair(const uint4& ra, int qa, const uint4& rb, const MdPair& P, double f[3])
@@ -100,6 +102,31 @@ __device__ __forceinline__ void md_pair(const uint4& ra, int qa, const uint4& rb
         g += 4.0 * P.eps * (12.0 * ir6 * ir6 - 6.0 * ir6) * ir2;
     }
     f[0] += g * fx; f[1] += g * fy; f[2] += g * fz;
+}
+
+// The same force with FP32 pair arithmetic (hardware reciprocal square root,
+// base-2 exponential and reciprocal, each within a few ulp), summed in FP64:
+// the molecular dynamics of FP32 handles.  The cutoff is the same exact
+// integer test.
+__device__ __forceinline__ void md_pair32(const uint4& ra, int qa, const uint4& rb, const MdPair& P, double f[3])
+{
+    const int32_t dx = (int32_t)(ra.x - rb.x), dy = (int32_t)(ra.y - rb.y), dz = (int32_t)(ra.z - rb.z);
+    const uint32_t ax = (uint32_t)abs(dx), ay = (uint32_t)abs(dy), az = (uint32_t)abs(dz);
+    const uint64_t r2i = (uint64_t)ax * ax + (uint64_t)ay * ay + (uint64_t)az * az;
+    const float fx = (float)dx * P.sf, fy = (float)dy * P.sf, fz = (float)dz * P.sf;
+    const float r2 = fx * fx + fy * fy + fz * fz;
+    float g = 0.0f;
+    const int qb = md_q(rb.w);
+    if (r2i < P.R2 && qa != 0 && qb != 0) {
+        const float rinv = __builtin_amdgcn_rsqf(r2), r = r2 * rinv;
+        const float e = __builtin_amdgcn_exp2f(P.klf * r);
+        g += P.lBf * (float)(qa * qb) * e * (1.0f + P.kappaf * r) * (rinv * rinv * rinv);
+    }
+    if (P.eps > 0.0 && r2 < 1.2599210498948731647672106f) {
+        const float ir2 = __builtin_amdgcn_rcpf(r2), ir6 = ir2 * ir2 * ir2;
+        g += 4.0f * P.epsf * (12.0f * ir6 * ir6 - 6.0f * ir6) * ir2;
+    }
+    f[0] += (double)(g * fx); f[1] += (double)(g * fy); f[2] += (double)(g * fz);
 }
 
 // the expanded excluded volume of core k on ion ra, added to f
@@ -163,6 +190,7 @@ __global__ __launch_bounds__(64) void k_md_vinit(MdArgs m, int buf, uint64_t ste
 // tests cost about as much as the pair terms they would skip.)
 constexpr int MD_STAGE = 512, MD_GROUP = 8, MD_PER = 64 / MD_GROUP;
 
+template <bool F32>
 __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t step, int langevin)
 {
     __shared__ uint4 nbr[MD_STAGE];
@@ -174,7 +202,8 @@ __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t ste
     const uint4* recb = R.rec[buf];
     const uint32_t* cntb = R.cnt[buf];
     const double s = R.scale;
-    const MdPair P{s, m.lB, R.kappa, m.eps, R.R2};
+    const MdPair P{s, m.lB, R.kappa, m.eps, R.R2, (float)s, (float)m.lB, (float)R.kappa,
+                   (float)(-R.kappa * 1.4426950408889634074), (float)m.eps};
     // lane o < 27: neighbour cell o (x fastest, offsets -1, 0, +1), its count
     // and where its records start in the concatenated list
     uint32_t ocell = 0u;
@@ -214,11 +243,13 @@ __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t ste
                 const int staged = min(cn, max(MD_STAGE - st, 0));
                 for (int k = sub; k < staged; k += MD_GROUP) {
                     if (oc == c && k == j) continue;
-                    md_pair(ra, qa, nbr[st + k], P, f);
+                    if (F32) md_pair32(ra, qa, nbr[st + k], P, f);
+                    else md_pair(ra, qa, nbr[st + k], P, f);
                 }
                 for (int k = staged + sub; k < cn; k += MD_GROUP) {
                     if (oc == c && k == j) continue;
-                    md_pair(ra, qa, recb[(size_t)oc * cap + k], P, f);
+                    if (F32) md_pair32(ra, qa, recb[(size_t)oc * cap + k], P, f);
+                    else md_pair(ra, qa, recb[(size_t)oc * cap + k], P, f);
                 }
             }
             if (m.eps > 0.0)
@@ -344,12 +375,13 @@ hipError_t launch_md_block(const MdArgs& m, int buf0, uint64_t step0, int64_t ns
     const dim3 grid(m.ncell_total), block(64);
     int buf = buf0;
     hipLaunchKernelGGL(k_md_vinit, grid, block, 0, s, m, buf, step0);
-    hipLaunchKernelGGL(k_md_force, grid, block, 0, s, m, buf, step0, 0);
+    const auto force = m.precision == 32 ? k_md_force<true> : k_md_force<false>;
+    hipLaunchKernelGGL(force, grid, block, 0, s, m, buf, step0, 0);
     for (int64_t st = 0; st < nsteps; ++st) {
         hipLaunchKernelGGL(k_md_drift, grid, block, 0, s, m, buf);
         hipLaunchKernelGGL(k_md_rebin, dim3(m.ncell_total), dim3(64), 0, s, m, buf);
         buf ^= 1;
-        hipLaunchKernelGGL(k_md_force, grid, block, 0, s, m, buf, step0 + (uint64_t)st, 1);
+        hipLaunchKernelGGL(force, grid, block, 0, s, m, buf, step0 + (uint64_t)st, 1);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
