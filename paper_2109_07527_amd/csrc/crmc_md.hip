@@ -183,12 +183,21 @@ __global__ __launch_bounds__(64) void k_md_vinit(MdArgs m, int buf, uint64_t ste
 // MD step `step` are added and the second half kick is applied.  One
 // wavefront per cell: the records of the 27 cells around it (cells are at
 // least rc wide) are staged in LDS once, segment by segment (the first
-// MD_STAGE of them; the rest are read from memory), then the cell's slots are
-// taken MD_PER at a time, MD_GROUP lanes per slot splitting its partners, and
-// each force is summed over its group.  (Screening the partners first and
-// packing the interacting ones into a dense list was slower: the distance
-// tests cost about as much as the pair terms they would skip.)
-constexpr int MD_STAGE = 512, MD_GROUP = 8, MD_PER = 64 / MD_GROUP;
+// MD_STAGE of them; the rest are read from memory).  The cell's ions, listed
+// 64 slots at a time, each get a group of lanes (as many as fit all of them in
+// one pass, a power of two) that split its partners, and each force is summed
+// over its group.  (Screening the partners first and packing the interacting
+// ones into a dense list was slower: the distance tests cost about as much as
+// the pair terms they would skip.)
+constexpr int MD_STAGE = 512;
+
+// LDS written by one lane is read by others of the same wavefront in program
+// order; this keeps the compiler from moving accesses across
+__device__ __forceinline__ void md_wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 template <bool F32>
 __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t step, int langevin)
@@ -221,63 +230,103 @@ __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t ste
         if ((int)lane >= off) pre += v;
     }
     const int ostart = pre - ocnt;
+    const int total = __builtin_amdgcn_readlane(pre, 26);
+    // the first 64 records of every segment, nine segments' loads in flight
+    // at a time (each lane reads an in-range slot, the stores are masked),
+    // then the rest of longer segments
+    for (int b = 0; b < 27; b += 9) {
+        uint4 v[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+            const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, b + u);
+            const int cn = __builtin_amdgcn_readlane(ocnt, b + u);
+            v[u] = recb[(size_t)oc * cap + (uint32_t)min((int)lane, max(cn - 1, 0))];
+        }
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+            const int cn = __builtin_amdgcn_readlane(ocnt, b + u), st = __builtin_amdgcn_readlane(ostart, b + u);
+            if ((int)lane < cn && st + (int)lane < MD_STAGE) nbr[st + lane] = v[u];
+        }
+    }
     for (int o = 0; o < 27; ++o) {
         const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, o);
         const int cn = __builtin_amdgcn_readlane(ocnt, o), st = __builtin_amdgcn_readlane(ostart, o);
-        for (int k = (int)lane; k < cn && st + k < MD_STAGE; k += 64) nbr[st + k] = recb[(size_t)oc * cap + k];
+        for (int k = 64 + (int)lane; k < cn && st + k < MD_STAGE; k += 64) nbr[st + k] = recb[(size_t)oc * cap + k];
     }
     __syncthreads();
-    const int grp = (int)lane / MD_GROUP, sub = (int)lane % MD_GROUP;
-    for (int j0 = 0; j0 < (int)t.cnt; j0 += MD_PER) {
-        const int j = j0 + grp;
-        const bool have = j < (int)t.cnt;
-        const size_t slot = (size_t)c * cap + (size_t)(have ? j : 0);
-        const uint4 ra = recb[slot];
-        const bool ion = have && md_is_ion(ra.w);
-        double f[3] = {0.0, 0.0, 0.0};
-        if (ion && m.ion_coupling) { // ideal ions feel nothing
-            const int qa = md_q(ra.w);
-            for (int o = 0; o < 27; ++o) {
-                const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, o);
-                const int cn = __builtin_amdgcn_readlane(ocnt, o), st = __builtin_amdgcn_readlane(ostart, o);
-                const int staged = min(cn, max(MD_STAGE - st, 0));
-                for (int k = sub; k < staged; k += MD_GROUP) {
-                    if (oc == c && k == j) continue;
-                    if (F32) md_pair32(ra, qa, nbr[st + k], P, f);
-                    else md_pair(ra, qa, nbr[st + k], P, f);
-                }
-                for (int k = staged + sub; k < cn; k += MD_GROUP) {
-                    if (oc == c && k == j) continue;
-                    if (F32) md_pair32(ra, qa, recb[(size_t)oc * cap + k], P, f);
-                    else md_pair(ra, qa, recb[(size_t)oc * cap + k], P, f);
-                }
-            }
-            if (m.eps > 0.0)
-                for (uint32_t k = (uint32_t)sub; k < R.ncores; k += MD_GROUP) md_core(ra, R, k, m, s, f);
+    __shared__ uint16_t ionj[64];
+    const int self0 = __builtin_amdgcn_readlane(ostart, 13); // the centre cell's records in the list
+    for (int b0 = 0; b0 < (int)t.cnt; b0 += 64) {
+        // 64 slots at a time: their ions listed in slot order, the other
+        // records (sites) get zero force
+        const int jl = b0 + (int)lane;
+        const bool have = jl < (int)t.cnt;
+        const uint4 rj = have ? recb[(size_t)c * cap + jl] : make_uint4(0u, 0u, 0u, 0u);
+        const bool is_ion = have && md_is_ion(rj.w);
+        if (have && !is_ion) {
+            double* fb = m.force[t.r] + 3 * ((size_t)c * cap + jl);
+            fb[0] = fb[1] = fb[2] = 0.0;
         }
-#pragma unroll
-        for (int off = 1; off < MD_GROUP; off <<= 1) {
-            f[0] += __shfl_xor(f[0], off, 64);
-            f[1] += __shfl_xor(f[1], off, 64);
-            f[2] += __shfl_xor(f[2], off, 64);
-        }
-        if (have && sub == 0) {
-            double* fb = m.force[t.r] + 3 * slot;
-            if (!ion) {
-                fb[0] = fb[1] = fb[2] = 0.0;
-                continue;
-            }
-            if (langevin) {
-                double z[3];
-                md_normals3(R, (uint32_t)step, c, (uint32_t)j, TAG_MDNOISE, z);
-                double* vb = m.vel[t.r * 2 + buf] + 3 * slot;
-                for (int q = 0; q < 3; ++q) {
-                    f[q] = f[q] - m.gamma * vb[q] + m.noise * z[q];
-                    vb[q] += 0.5 * m.dt * f[q];
+        const uint64_t im = __ballot(is_ion);
+        const int nion = __popcll(im);
+        if (is_ion) ionj[__popcll(im & ((1ull << lane) - 1ull))] = (uint16_t)(jl - b0);
+        md_wave_sync();
+        // lanes per ion: the largest power of two that fits them all in one pass
+        int lg = 6;
+        while (lg > 0 && (nion << lg) > 64) --lg;
+        const int G = 1 << lg;
+        const int gi = (int)lane >> lg, sub = (int)lane & (G - 1);
+        for (int i0 = 0; i0 < nion; i0 += 64 >> lg) {
+            const int i = i0 + gi;
+            const bool act = i < nion;
+            const int j = b0 + (int)ionj[act ? i : 0];
+            const size_t slot = (size_t)c * cap + (size_t)j;
+            const uint4 ra = recb[slot];
+            double f[3] = {0.0, 0.0, 0.0};
+            if (act && m.ion_coupling) { // ideal ions feel nothing
+                const int qa = md_q(ra.w);
+                // the staged part of the concatenated list in one stride
+                const int self = self0 + j;
+                for (int g = sub; g < min(total, MD_STAGE); g += G) {
+                    if (g == self) continue;
+                    if (F32) md_pair32(ra, qa, nbr[g], P, f);
+                    else md_pair(ra, qa, nbr[g], P, f);
                 }
+                // the rest, segment by segment from memory
+                if (total > MD_STAGE) {
+                    for (int o = 0; o < 27; ++o) {
+                        const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, o);
+                        const int cn = __builtin_amdgcn_readlane(ocnt, o), st = __builtin_amdgcn_readlane(ostart, o);
+                        for (int k = max(MD_STAGE - st, 0) + sub; k < cn; k += G) {
+                            if (oc == c && k == j) continue;
+                            if (F32) md_pair32(ra, qa, recb[(size_t)oc * cap + k], P, f);
+                            else md_pair(ra, qa, recb[(size_t)oc * cap + k], P, f);
+                        }
+                    }
+                }
+                if (m.eps > 0.0)
+                    for (uint32_t k = (uint32_t)sub; k < R.ncores; k += (uint32_t)G) md_core(ra, R, k, m, s, f);
             }
-            fb[0] = f[0]; fb[1] = f[1]; fb[2] = f[2];
+            for (int off = 1; off < G; off <<= 1) {
+                f[0] += __shfl_xor(f[0], off, 64);
+                f[1] += __shfl_xor(f[1], off, 64);
+                f[2] += __shfl_xor(f[2], off, 64);
+            }
+            if (act && sub == 0) {
+                if (langevin) {
+                    double z[3];
+                    md_normals3(R, (uint32_t)step, c, (uint32_t)j, TAG_MDNOISE, z);
+                    double* vb = m.vel[t.r * 2 + buf] + 3 * slot;
+                    for (int q = 0; q < 3; ++q) {
+                        f[q] = f[q] - m.gamma * vb[q] + m.noise * z[q];
+                        vb[q] += 0.5 * m.dt * f[q];
+                    }
+                }
+                double* fb = m.force[t.r] + 3 * slot;
+                fb[0] = f[0]; fb[1] = f[1]; fb[2] = f[2];
+            }
         }
+        md_wave_sync(); // the ion list is rewritten for the next slots
     }
 }
 
@@ -331,34 +380,50 @@ __global__ __launch_bounds__(64) void k_md_rebin(MdArgs m, int buf)
     const double* vsrc = m.vel[r * 2 + buf];
     uint4* dst = R.rec[buf ^ 1];
     double* vdst = m.vel[r * 2 + (buf ^ 1)];
+    // lane q < 27: the source cell of rank q and its count (ascending index)
+    const uint32_t to = lane < 27 ? rank : lane;
+    const uint32_t qcell = (uint32_t)__builtin_amdgcn_ds_permute((int)(to << 2), (int)nb);
+    const uint32_t qcnt = (uint32_t)__builtin_amdgcn_ds_permute((int)(to << 2), (int)ncnt);
     uint32_t out = 0;
-    for (uint32_t q = 0; q < 27; ++q) {
-        // the source cell of rank q (cells in ascending index)
-        const uint64_t who = __ballot(lane < 27 && rank == q);
-        const int src_lane = (int)__builtin_ctzll(who);
-        const uint32_t sc = (uint32_t)__shfl((int)nb, src_lane, 64);
-        const uint32_t cnt = (uint32_t)__shfl((int)ncnt, src_lane, 64);
-        for (uint32_t b0 = 0; b0 < cnt; b0 += 64) {
-            const uint32_t k = b0 + lane;
-            bool mine = false;
-            uint4 rec = make_uint4(0u, 0u, 0u, 0u);
-            if (k < cnt) {
-                rec = src[(size_t)sc * cap + k];
-                const uint32_t nx = __umulhi(rec.x - o0, n), ny = __umulhi(rec.y - o1, n), nz = __umulhi(rec.z - o2, n);
-                mine = nx + n * (ny + n * nz) == c;
+    // a slot's record goes to this cell if it falls into it: appended in order
+    const auto take = [&](uint32_t sc, uint32_t k, bool valid, const uint4& rec) {
+        bool mine = false;
+        if (valid) {
+            const uint32_t nx = __umulhi(rec.x - o0, n), ny = __umulhi(rec.y - o1, n), nz = __umulhi(rec.z - o2, n);
+            mine = nx + n * (ny + n * nz) == c;
+        }
+        const uint64_t mask = __ballot(mine);
+        const uint32_t before = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if (mine) {
+            const uint32_t at = out + before;
+            if (at < cap) {
+                dst[(size_t)c * cap + at] = rec;
+                const double* vs = vsrc + 3 * ((size_t)sc * cap + k);
+                double* vd = vdst + 3 * ((size_t)c * cap + at);
+                vd[0] = vs[0]; vd[1] = vs[1]; vd[2] = vs[2];
             }
-            const uint64_t mask = __ballot(mine);
-            const uint32_t before = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            if (mine) {
-                const uint32_t at = out + before;
-                if (at < cap) {
-                    dst[(size_t)c * cap + at] = rec;
-                    const double* vs = vsrc + 3 * ((size_t)sc * cap + k);
-                    double* vd = vdst + 3 * ((size_t)c * cap + at);
-                    vd[0] = vs[0]; vd[1] = vs[1]; vd[2] = vs[2];
-                }
+        }
+        out += (uint32_t)__popcll(mask);
+    };
+    // the first 64 records of nine source cells in flight at a time (each lane
+    // reads an in-range slot), taken in rank order, longer cells finished
+    // before the next rank
+    for (int b = 0; b < 27; b += 9) {
+        uint4 v[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) {
+            const uint32_t sc = (uint32_t)__builtin_amdgcn_readlane((int)qcell, b + u);
+            const uint32_t cn = (uint32_t)__builtin_amdgcn_readlane((int)qcnt, b + u);
+            v[u] = src[(size_t)sc * cap + (cn ? min(lane, cn - 1u) : 0u)];
+        }
+        for (int u = 0; u < 9; ++u) {
+            const uint32_t sc = (uint32_t)__builtin_amdgcn_readlane((int)qcell, b + u);
+            const uint32_t cn = (uint32_t)__builtin_amdgcn_readlane((int)qcnt, b + u);
+            take(sc, lane, lane < cn, v[u]);
+            for (uint32_t b0 = 64; b0 < cn; b0 += 64) {
+                const uint32_t k = b0 + lane;
+                take(sc, k, k < cn, k < cn ? src[(size_t)sc * cap + k] : make_uint4(0u, 0u, 0u, 0u));
             }
-            out += (uint32_t)__popcll(mask);
         }
     }
     if (lane == 0) {
