@@ -266,7 +266,8 @@ int crmc_sweep_recover(crmc_t h, const crmc_cond* per_replica, int64_t n_sweeps,
  * Sites and cores stay fixed.  Every ion starts the block with a
  * Maxwell-Boltzmann velocity; a step is v += dt/2 F; x += dt v (rounded to
  * the position lattice); F = F_c(x) - gamma v + sqrt(2 gamma / dt) xi;
- * v += dt/2 F, F_c = -grad E of the energy model in FP64 (cells are at least
+ * v += dt/2 F, F_c = -grad E of the energy model (pair terms in the handle's
+ * precision, summed in FP64; the cores' term in FP64; cells are at least
  * rc wide, so the 27 cells around an ion hold every partner).  After every
  * drift the ions are re-binned stably into the grid of the last sweep; the
  * random numbers of an ion come from Philox counters (step, cell, slot, 6)
