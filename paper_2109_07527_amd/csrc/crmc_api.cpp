@@ -269,7 +269,7 @@ void free_replica(crmc_t h, HostReplica& r)
     Replica& d = r.d;
     void* ptrs[] = {d.rec[0], d.rec[1], d.cnt[0], d.cnt[1], d.cnt0, d.e_acc, d.occupancy, d.site_group,
                     d.group_count, d.group_hist, d.group_hist_off, d.core_x, d.core_delta, d.totals,
-                    d.moves, d.series, d.bnd, d.lnW, d.hiwater, d.tab, d.phat, d.nsc, d.feat};
+                    d.moves, d.ctr, d.series, d.bnd, d.lnW, d.hiwater, d.tab, d.phat, d.nsc, d.feat};
     for (void* q : ptrs) dfree(h, q);
     for (double*& q : r.md_vel) { dfree(h, q); q = nullptr; }
     dfree(h, r.md_force);
@@ -321,6 +321,7 @@ SweepArgs base_args(crmc_t h)
         a.bin_sparse_any |= (int32_t)r.d.bin_sparse;
         a.bin_dense_any |= (int32_t)!r.d.bin_sparse;
     }
+    a.bin_cpw = a.ncell_total >= BIN_BATCH_MIN_CELLS ? (int32_t)BIN_CPW : 1;
     a.pool = h->pool;
     a.precision = h->p.precision;
     a.light_nb = h->p.light_neighbours > 0 ? h->p.light_neighbours : DEFAULT_LIGHT_NB;
@@ -343,6 +344,8 @@ int upload_descriptors(crmc_t h)
     uint32_t cells = 0, doms = 0;
     for (size_t i = 0; i < h->reps.size(); ++i) {
         HostReplica& r = h->reps[i];
+        // the re-binning takes BIN_CPW cells of one replica per wavefront
+        if (r.ncells % BIN_CPW != 0) return fail(h, CRMC_E_DEVICE, "internal error: cell count not a multiple of eight");
         r.d.cell_begin = cells;
         r.d.dom_begin = doms;
         cells += r.ncells;
@@ -1023,6 +1026,7 @@ static std::vector<DevBuf> replica_buffers(crmc_t h, HostReplica& r)
         {(void**)&d.group_hist_off, (r.ngroups + 1) * 4}, {(void**)&d.core_x, nco * sizeof(uint4)},
         {(void**)&d.core_delta, nco * 8},            {(void**)&d.totals, 4 * 8},
         {(void**)&d.moves, 14 * 8},                  {(void**)&d.series, (size_t)DEFAULT_SERIES * 4 * 4},
+        {(void**)&d.ctr, (size_t)CTR_STRIPES * CTR_STRIDE * 4},
         {(void**)&d.phat, np * 8},                   {(void**)&d.nsc, ncells * 4},
         {(void**)&d.bnd, (r.n + 1) * 4},             {(void**)&d.lnW, r.n * 8},
         {(void**)&d.hiwater, 4},                     {(void**)&d.tab, sizeof(SweepTab)},
@@ -1070,6 +1074,7 @@ static int materialize_replica(crmc_t h, HostReplica& r)
                          hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(d.totals, r.init_tot, sizeof r.init_tot, hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemset(d.moves, 0, 14 * sizeof(uint64_t)));
+    HIP_TRY(h, hipMemset(d.ctr, 0, (size_t)CTR_STRIPES * CTR_STRIDE * sizeof(uint32_t)));
     HIP_TRY(h, hipMemset(d.series, 0, (size_t)d.series_cap * 4 * sizeof(int32_t)));
     {
         // cell boundaries b_k = ceil(k 2^32 / n) (b_n wraps to 0) and ln of the widths

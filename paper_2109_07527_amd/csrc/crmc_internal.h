@@ -15,7 +15,15 @@ constexpr uint32_t ERR_INSERT_CAPACITY = 2u;
 constexpr uint32_t INFO_UNSTAGED = 4u;   // some neighbours were read from memory during trials
 constexpr uint32_t ERR_POOL = 8u;        // a domain did not fit its LDS pool (not processed)
 
-constexpr int BIN_THREADS = 256;    // four wavefronts, one new cell each
+// A phase's thousands of domains add their counts to 256 copies of a
+// replica's counters (one per 128-byte line) rather than to one line; a
+// sweep's counts fit in 32 bits
+constexpr int CTR_STRIPES = 256, CTR_STRIDE = 32;
+
+constexpr int BIN_THREADS = 256;    // four wavefronts
+// new cells per wavefront of the re-binning: BIN_CPW once a launch has
+// enough cells to fill the chip that way, else one
+constexpr uint32_t BIN_CPW = 8, BIN_BATCH_MIN_CELLS = 65536;
 constexpr int PHASE_THREADS = 256;  // one heavy domain, or four light domains (one per wavefront)
 constexpr int DEFAULT_LIGHT_NB = 768;
 
@@ -63,7 +71,10 @@ struct Replica {
     uint4* core_x;           // core centres (x, y, z, unused)
     double* core_delta;      // Delta = R - 1/2
     int64_t* totals;         // nA-, nB+, nX+, nX-
-    uint64_t* moves;         // attempts[6], accepts[6]
+    uint64_t* moves;         // attempts[6], accepts[6], relocation attempts and accepts
+    uint32_t* ctr;           // CTR_STRIPES stripes of CTR_STRIDE: one sweep's adds of the domains
+                             // to moves (0-13) and totals (14-17, two's complement), folded into
+                             // them and cleared at the end of every sweep
     int32_t* series;         // series_cap rows of 4
     uint32_t* bnd;           // n+1 cell boundaries b_k = ceil(k 2^32 / n), b_n stored as 0
     double* lnW;             // n: ln of the cell widths in lattice units
@@ -120,7 +131,8 @@ struct SweepArgs {
     int32_t ion_coupling, trials, pairing, fixed_grid, site_trials;
     int32_t ion_trials; // ion relocation trials per cell of a domain, after the reaction trials
     int32_t bin_sparse_any; // some replica is re-binned one lane per cell
-    int32_t bin_dense_any;  // some replica is re-binned one wavefront per cell
+    int32_t bin_dense_any;  // some replica is re-binned by wavefronts (k_bin)
+    int32_t bin_cpw;        // new cells per wavefront of k_bin
     int32_t pool;      // LDS pool of a phase workgroup, in records (a light domain gets a quarter)
     int32_t precision; // 32 or 64
     int32_t light_nb;  // neighbour records up to which a domain may run on one wavefront

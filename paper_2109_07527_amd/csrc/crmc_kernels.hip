@@ -3,8 +3,9 @@
 //   k_bin        per sweep: draw the grid shift, re-bin every record into the
 //                shifted cells (stable: old cell order, then order in the old
 //                cell), sample per-site occupancy, publish the sweep's shift and
-//                pairing table.  One wavefront per new cell gathers from the old
-//                cells that overlap it (at most 27, usually 8): no atomics, no scan.
+//                pairing table.  Each new cell gathers from the old cells that
+//                overlap it (at most 27, usually 8), eight cells per wavefront:
+//                places records without atomics or a global scan.
 //   k_plan       per sweep: sorts the domains of every colour into light ones
 //                (one wavefront each) and heavy ones (a whole workgroup); with
 //                the learned proposal on, lists the feature kernel's work items.
@@ -20,7 +21,8 @@
 //                ion relocation trials compiled in.  k_phase_fast<R, M>: the
 //                same, with the trials of empty domains evaluated side by
 //                side (batches with sparse replicas).
-//   k_sweep_end  per sweep: series row, group histograms, next grid shift;
+//   k_sweep_end  per sweep: folds the domains' counter stripes, series row,
+//                group histograms, next grid shift;
 //                k_sweep_advance then advances the sweep counter.
 //   k_energy     total energy of a replica from scratch (FP64), per cell.
 #include "crmc_internal.h"
@@ -141,74 +143,107 @@ __device__ __forceinline__ void bin_candidates(const uint32_t* __restrict__ bnd,
     }
 }
 
-// One wavefront per new cell of the dense replicas; the cells of sparse
-// replicas (far fewer records than cells) are left to k_bin_sparse.  The
-// wavefront of a dense replica's cell 0 writes the sweep's table.
-__global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
-{
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    const uint32_t gcell = blockIdx.x * (BIN_THREADS / 64) + wave;
-    if (gcell >= a.ncell_total) return;
-    const uint32_t r = a.cell2rep[gcell];
-    const Replica& R = a.reps[r];
-    const uint32_t n = R.n, cap = R.cap;
-    const uint32_t k = gcell - R.cell_begin;
-    if (R.bin_sparse) return; // k_bin_sparse, table and counters included
-    const uint64_t s = *a.sweep;
-    const int cur = (int)(s & 1u), nxt = cur ^ 1;
-    const uint4* __restrict__ src = R.rec[cur];
-    const uint32_t* __restrict__ scnt = R.cnt[cur];
-    uint4* __restrict__ dst = R.rec[nxt];
-    const uint32_t* __restrict__ bnd = R.bnd;
-    const uint32_t hw = *R.hiwater;
-
+// What the re-binning of one replica in one sweep needs (wavefront-uniform)
+struct BinRep {
+    uint64_t s;
+    const uint4* src;
+    const uint32_t* scnt;
+    uint4* dst;
+    uint32_t n, cap, hw, nxt;
     uint32_t on[3], oo[3];
-    bin_shifts(R, s, a.fixed_grid, on, oo);
+};
 
-    if (gcell == 0 && lane < PLAN_N) a.plan_n[lane] = 0u; // plan and learned-proposal counters of the sweep
-    if (k == 0 && lane < 12) {
-        // the sweep's table: shift, and the pairing centre of every colour
+__device__ __forceinline__ void bin_rep(const SweepArgs& a, const Replica& R, BinRep& b)
+{
+    b.s = *a.sweep;
+    const int cur = (int)(b.s & 1u);
+    b.nxt = (uint32_t)(cur ^ 1);
+    b.src = R.rec[cur];
+    b.scnt = R.cnt[cur];
+    b.dst = R.rec[b.nxt];
+    b.n = R.n;
+    b.cap = R.cap;
+    b.hw = *R.hiwater;
+    bin_shifts(R, b.s, a.fixed_grid, b.on, b.oo);
+}
+
+// the sweep's table of a replica (its cell 0's duty): shift, and the
+// pairing centre of every colour
+__device__ __forceinline__ void bin_table(const Replica& R, const BinRep& b, uint32_t lane)
+{
+    if (lane < 12) {
         const uint32_t M = R.h * R.h * R.h;
         uint32_t v = 0;
-        if (lane < 4) v = lane < 3 ? on[lane] : 0u;
+        if (lane < 4) v = lane == 0 ? b.on[0] : (lane == 1 ? b.on[1] : (lane == 2 ? b.on[2] : 0u));
         else {
             uint32_t w[4];
-            philox4x32_10((uint32_t)s, lane - 4u, 0u, TAG_PAIR, R.key0, R.key1, w);
+            philox4x32_10((uint32_t)b.s, lane - 4u, 0u, TAG_PAIR, R.key0, R.key1, w);
             const uint32_t rr = pick32(w[0], M);
             v = (uint32_t)(((uint64_t)M - 1u + 2ull * M - 2ull * rr) % M);
         }
         if (lane < 4) R.tab->o[lane] = v; else R.tab->pairc[lane - 4] = v;
     }
+}
 
+// One chunk of candidate records (one per lane) for new cell k: the matches
+// are appended in order after `base` (stable), sites counted, and every
+// charged site sampled into its occupancy and its group's counter
+__device__ __forceinline__ void bin_take(const Replica& R, const BinRep& b, uint32_t k, const uint32_t kc[3], bool valid,
+                                         const uint4& rec, uint32_t lane, uint32_t& base, uint32_t& nsite)
+{
+    const uint32_t n = b.n;
+    const bool match = valid && cell_of(rec.x - b.on[0], n) == kc[0] && cell_of(rec.y - b.on[1], n) == kc[1] &&
+                       cell_of(rec.z - b.on[2], n) == kc[2];
+    const uint64_t mask = __ballot(match);
+    const uint32_t kd = rec.w & 7u;
+    nsite += (uint32_t)__popcll(__ballot(match && (kd == KIND_ACID || kd == KIND_BASE)));
+    const uint32_t sid = rec.w >> 8;
+    const bool charged_site = match && sid != NO_SITE && rec_charged(rec.w);
+    int grp = -1;
+    if (match) {
+        const uint32_t pos = base + (uint32_t)__popcll(mask & lanemask_lt());
+        if (pos < b.cap) b.dst[(size_t)k * b.cap + pos] = rec;
+        // each site lands in exactly one new cell: non-returning adds
+        if (charged_site) {
+            atomicAdd((unsigned long long*)&R.occupancy[sid], 1ull);
+            grp = R.site_group[sid];
+        }
+    }
+    // the group counters take one add per group present (a cell's sites
+    // mostly share one group, and thousands of cells share each counter)
+    uint64_t pend = __ballot(charged_site);
+    while (pend) {
+        const int lead = (int)__builtin_ctzll(pend);
+        const int g = __builtin_amdgcn_readlane(grp, lead);
+        const uint64_t same = __ballot(grp == g) & pend;
+        if ((int)lane == lead) atomicAdd(&R.group_count[(b.s & 1u) * R.ngroups + (uint32_t)g], (int)__popcll(same));
+        pend &= ~same;
+    }
+    base += (uint32_t)__popcll(mask);
+}
+
+__device__ __forceinline__ void bin_finish(const SweepArgs& a, const Replica& R, const BinRep& b, uint32_t k,
+                                           uint32_t base, uint32_t nsite, uint32_t lane)
+{
+    if (lane == 0) {
+        R.cnt[b.nxt][k] = base < b.cap ? base : b.cap;
+        R.cnt0[k] = base < b.cap ? base : b.cap;
+        R.nsc[k] = nsite;
+        if (base > b.cap) atomicOr(a.err, ERR_BIN_CAPACITY);
+        if (base > b.hw) atomicMax(R.hiwater, base); // rarely taken once the mark has settled
+    }
+}
+
+// New cell k by the whole wavefront, for any number of candidate cells and
+// any list length: the overlapping old cells in ascending (z, y, x) order,
+// one per lane, with their counts loaded at once and scanned
+__device__ void bin_cell(const SweepArgs& a, const Replica& R, const BinRep& b, uint32_t k, uint32_t lane)
+{
+    const uint32_t n = b.n, cap = b.cap;
     const uint32_t kc[3] = {k % n, (k / n) % n, k / (n * n)};
     uint32_t cand[3][3];
     int ncand[3];
-    bin_candidates(bnd, n, kc, on, oo, cand, ncand);
-
-    const uint64_t lt = lanemask_lt();
-    uint32_t base = 0, nsite = 0;
-    // one record: does it fall into new cell k?  Matches are appended in
-    // order (stable), counted, and a charged site is sampled
-    const auto take = [&](bool valid, const uint4& rec) {
-        const bool match = valid && cell_of(rec.x - on[0], n) == kc[0] && cell_of(rec.y - on[1], n) == kc[1] &&
-                           cell_of(rec.z - on[2], n) == kc[2];
-        const uint64_t mask = __ballot(match);
-        const uint32_t kd = rec.w & 7u;
-        nsite += (uint32_t)__popcll(__ballot(match && (kd == KIND_ACID || kd == KIND_BASE)));
-        if (match) {
-            const uint32_t pos = base + (uint32_t)__popcll(mask & lt);
-            if (pos < cap) dst[(size_t)k * cap + pos] = rec;
-            const uint32_t sid = rec.w >> 8;
-            // each site lands in exactly one new cell: non-returning adds
-            if (sid != NO_SITE && rec_charged(rec.w)) {
-                atomicAdd((unsigned long long*)&R.occupancy[sid], 1ull);
-                atomicAdd(&R.group_count[(s & 1u) * R.ngroups + (uint32_t)R.site_group[sid]], 1);
-            }
-        }
-        base += (uint32_t)__popcll(mask);
-    };
-    // the overlapping old cells in ascending (z, y, x) order, one per lane,
-    // with their counts loaded at once and scanned
+    bin_candidates(R.bnd, n, kc, b.on, b.oo, cand, ncand);
     const int nc0 = ncand[0], nc01 = ncand[0] * ncand[1], ncand_all = nc01 * ncand[2];
     uint32_t my_oc = 0, my_cc = 0;
     if ((int)lane < ncand_all) {
@@ -217,7 +252,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
         const uint32_t cy = iy == 0 ? cand[1][0] : (iy == 1 ? cand[1][1] : cand[1][2]);
         const uint32_t cz = iz == 0 ? cand[2][0] : (iz == 1 ? cand[2][1] : cand[2][2]);
         my_oc = cx + n * (cy + n * cz);
-        my_cc = scnt[my_oc];
+        my_cc = b.scnt[my_oc];
     }
     uint32_t incl = my_cc;
 #pragma unroll
@@ -226,8 +261,9 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
         if ((int)lane >= off) incl += v;
     }
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, ncand_all - 1);
+    uint32_t base = 0, nsite = 0;
     if (total <= 64u) {
-        // sparse: lane j takes record j of the concatenated lists
+        // lane j takes record j of the concatenated lists
         uint32_t oc = 0, idx = 0;
         for (int c = 0; c < ncand_all; ++c) {
             const uint32_t end = (uint32_t)__builtin_amdgcn_readlane((int)incl, c);
@@ -236,27 +272,118 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
             if (lane >= end - cc && lane < end) { oc = occ; idx = lane - (end - cc); }
         }
         uint4 rec = make_uint4(0, 0, 0, 0);
-        if (lane < total) rec = src[(size_t)oc * cap + idx];
-        take(lane < total, rec);
+        if (lane < total) rec = b.src[(size_t)oc * cap + idx];
+        bin_take(R, b, k, kc, lane < total, rec, lane, base, nsite);
     } else {
         for (int c = 0; c < ncand_all; ++c) {
             const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)my_oc, c);
             const uint32_t cc = (uint32_t)__builtin_amdgcn_readlane((int)my_cc, c);
-            for (uint32_t b = 0; b < cc; b += 64u) {
-                const uint32_t i = b + lane;
+            for (uint32_t b0 = 0; b0 < cc; b0 += 64u) {
+                const uint32_t i = b0 + lane;
                 uint4 rec = make_uint4(0, 0, 0, 0);
-                if (i < cc) rec = src[(size_t)oc * cap + i];
-                take(i < cc, rec);
+                if (i < cc) rec = b.src[(size_t)oc * cap + i];
+                bin_take(R, b, k, kc, i < cc, rec, lane, base, nsite);
             }
         }
     }
-    if (lane == 0) {
-        R.cnt[nxt][k] = base < cap ? base : cap;
-        R.cnt0[k] = base < cap ? base : cap;
-        R.nsc[k] = nsite;
-        if (base > cap) atomicOr(a.err, ERR_BIN_CAPACITY);
-        if (base > hw) atomicMax(R.hiwater, base); // rarely taken once the mark has settled
+    bin_finish(a, R, b, k, base, nsite, lane);
+}
+
+// One wavefront per bin_cpw (1 or BIN_CPW) consecutive new cells of the
+// dense replicas; the cells of sparse replicas (far fewer records than
+// cells) are left to k_bin_sparse.  The cell index is uniform over the wavefront, so the
+// replica, its tables and the grid shifts come through scalar loads.  The
+// cells of one replica whose candidates are at most eight old cells holding
+// at most 64 records in all (the common case) are re-binned together: lane
+// 8i + c holds candidate c of cell i, so the counts of all of them arrive in
+// one load, and the records of all of them (one per lane and cell) in one
+// round; the others go one by one through bin_cell.  Every cell gets the
+// same stable order either way.
+__global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
+{
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63u;
+    const uint32_t cpw = (uint32_t)a.bin_cpw;
+    const uint32_t g0 = (blockIdx.x * (BIN_THREADS / 64) + wave) * cpw;
+    if (g0 >= a.ncell_total) return;
+    // a replica's cell count (an even edge count, cubed) is a multiple of
+    // BIN_CPW, so the cells of a wavefront belong to one replica
+    const uint32_t gend = min(g0 + cpw, a.ncell_total);
+    const uint32_t r = a.cell2rep[g0];
+    const Replica& R = a.reps[r];
+    if (g0 == 0 && lane < PLAN_N && !R.bin_sparse)
+        a.plan_n[lane] = 0u; // plan and learned-proposal counters of the sweep
+    if (R.bin_sparse) return;
+    BinRep b;
+    bin_rep(a, R, b);
+    const uint32_t n = b.n, cap = b.cap;
+    const uint32_t k0 = g0 - R.cell_begin, m = gend - g0;
+    if (k0 == 0) bin_table(R, b, lane);
+    if (cpw == 1) {
+        bin_cell(a, R, b, k0, lane);
+        return;
     }
+
+    // lane 8i + c: candidate c of cell k0 + i
+    const uint32_t ci = lane >> 3, cs = lane & 7u;
+    const bool live = ci < m;
+    const uint32_t k = k0 + (live ? ci : 0u);
+    const uint32_t kc[3] = {k % n, (k / n) % n, k / (n * n)};
+    uint32_t cand[3][3];
+    int ncand[3];
+    bin_candidates(R.bnd, n, kc, b.on, b.oo, cand, ncand);
+    const int nc0 = ncand[0], nc01 = ncand[0] * ncand[1], ncand_all = nc01 * ncand[2];
+    const bool few = ncand_all <= 8;
+    uint32_t my_oc = 0, my_cc = 0;
+    if (live && few && (int)cs < ncand_all) {
+        const int ix = (int)cs % nc0, iy = ((int)cs / nc0) % ncand[1], iz = (int)cs / nc01;
+        const uint32_t cx = ix == 0 ? cand[0][0] : (ix == 1 ? cand[0][1] : cand[0][2]);
+        const uint32_t cy = iy == 0 ? cand[1][0] : (iy == 1 ? cand[1][1] : cand[1][2]);
+        const uint32_t cz = iz == 0 ? cand[2][0] : (iz == 1 ? cand[2][1] : cand[2][2]);
+        my_oc = cx + n * (cy + n * cz);
+        my_cc = b.scnt[my_oc];
+    }
+    // inclusive scan of the counts within each group of eight lanes
+    uint32_t incl = my_cc;
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, off, 8);
+        if ((int)cs >= off) incl += v;
+    }
+    const uint32_t tot = (uint32_t)__shfl((int)incl, (int)(lane | 7u), 64);
+    // cells left to bin_cell: more than eight candidates or 64 records
+    const uint64_t slow = __ballot(live && cs == 0 && (!few || tot > 64u));
+
+    uint4 v[BIN_CPW];
+#pragma unroll
+    for (uint32_t i = 0; i < BIN_CPW; ++i) {
+        v[i] = make_uint4(0u, 0u, 0u, 0u);
+        if (i < m && !((slow >> (8 * i)) & 1ull)) {
+            const uint32_t ti = (uint32_t)__builtin_amdgcn_readlane((int)tot, (int)(8 * i));
+            uint32_t oc = 0, idx = 0;
+#pragma unroll
+            for (uint32_t c = 0; c < 8; ++c) {
+                const uint32_t end = (uint32_t)__builtin_amdgcn_readlane((int)incl, (int)(8 * i + c));
+                const uint32_t cc = (uint32_t)__builtin_amdgcn_readlane((int)my_cc, (int)(8 * i + c));
+                const uint32_t occ = (uint32_t)__builtin_amdgcn_readlane((int)my_oc, (int)(8 * i + c));
+                if (lane >= end - cc && lane < end) { oc = occ; idx = lane - (end - cc); }
+            }
+            if (lane < ti) v[i] = b.src[(size_t)oc * cap + idx];
+        }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < BIN_CPW; ++i) {
+        if (i < m && !((slow >> (8 * i)) & 1ull)) {
+            const uint32_t ti = (uint32_t)__builtin_amdgcn_readlane((int)tot, (int)(8 * i));
+            const uint32_t kci[3] = {(uint32_t)__builtin_amdgcn_readlane((int)kc[0], (int)(8 * i)),
+                                     (uint32_t)__builtin_amdgcn_readlane((int)kc[1], (int)(8 * i)),
+                                     (uint32_t)__builtin_amdgcn_readlane((int)kc[2], (int)(8 * i))};
+            uint32_t base = 0, nsite = 0;
+            bin_take(R, b, k0 + i, kci, lane < ti, v[i], lane, base, nsite);
+            bin_finish(a, R, b, k0 + i, base, nsite, lane);
+        }
+    }
+    for (uint32_t i = 0; i < m; ++i)
+        if ((slow >> (8 * i)) & 1ull) bin_cell(a, R, b, k0 + i, lane);
 }
 
 // One lane per new cell of the sparse replicas: the lane walks the
@@ -300,6 +427,10 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_sparse(SweepArgs a)
     bin_candidates(R.bnd, n, kc, on, oo, cand, ncand);
 
     uint32_t base = 0, nsite = 0;
+    // the lane's adds to one group counter are gathered while the group stays
+    // the same (a chain's sites share one) and flushed when it changes
+    int run_g = -1, run_n = 0;
+    int32_t* gcnt = R.group_count + (s & 1u) * R.ngroups;
     for (int iz = 0; iz < ncand[2]; ++iz)
         for (int iy = 0; iy < ncand[1]; ++iy)
             for (int ix = 0; ix < ncand[0]; ++ix) {
@@ -316,11 +447,18 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_sparse(SweepArgs a)
                     const uint32_t sid = rec.w >> 8;
                     if (sid != NO_SITE && rec_charged(rec.w)) {
                         atomicAdd((unsigned long long*)&R.occupancy[sid], 1ull);
-                        atomicAdd(&R.group_count[(s & 1u) * R.ngroups + (uint32_t)R.site_group[sid]], 1);
+                        const int g = R.site_group[sid];
+                        if (g != run_g) {
+                            if (run_n) atomicAdd(&gcnt[run_g], run_n);
+                            run_g = g;
+                            run_n = 0;
+                        }
+                        ++run_n;
                     }
                     ++base;
                 }
             }
+    if (run_n) atomicAdd(&gcnt[run_g], run_n);
     R.cnt[nxt][k] = base < cap ? base : cap;
     R.cnt0[k] = base < cap ? base : cap;
     R.nsc[k] = nsite;
@@ -722,6 +860,16 @@ __device__ __forceinline__ double wave_sum_dpp(double v)
         r[k] = __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
     }
     return (r[0] + r[1]) + (r[2] + r[3]);
+}
+// the same for 32-bit integers (sums modulo 2^32), returned uniform
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+    return ((uint32_t)__builtin_amdgcn_readlane((int)v, 0) + (uint32_t)__builtin_amdgcn_readlane((int)v, 16)) +
+           ((uint32_t)__builtin_amdgcn_readlane((int)v, 32) + (uint32_t)__builtin_amdgcn_readlane((int)v, 48));
 }
 __device__ __forceinline__ uint32_t rflu(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 __device__ __forceinline__ uint32_t rdl(uint32_t v, int lane) { return (uint32_t)__builtin_amdgcn_readlane((int)v, lane); }
@@ -1886,19 +2034,21 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         cntb[G.cell0] = (uint32_t)n0;
         if (ncell == 2) cntb[G.cell1] = (uint32_t)n1;
         if (dE != 0.0) R.e_acc[G.cell0] += dE;
+        // the domain's stripe of the replica's counters (k_sweep_end folds them)
+        uint32_t* ct = R.ctr + (size_t)(gd % (uint32_t)CTR_STRIPES) * CTR_STRIDE;
         for (int i = 0; i < 6; ++i) {
             const int sh = 21 * (i % 3);
-            const unsigned long long na = ((i < 3 ? attL : attH) >> sh) & 0x1FFFFFull;
-            const unsigned long long nc = ((i < 3 ? acpL : acpH) >> sh) & 0x1FFFFFull;
-            if (na) atomicAdd((unsigned long long*)&R.moves[i], na);
-            if (nc) atomicAdd((unsigned long long*)&R.moves[6 + i], nc);
+            const uint32_t na = (uint32_t)(((i < 3 ? attL : attH) >> sh) & 0x1FFFFFull);
+            const uint32_t nc = (uint32_t)(((i < 3 ? acpL : acpH) >> sh) & 0x1FFFFFull);
+            if (na) atomicAdd(&ct[i], na);
+            if (nc) atomicAdd(&ct[6 + i], nc);
         }
-        if (rel_att) atomicAdd((unsigned long long*)&R.moves[12], (unsigned long long)rel_att);
-        if (rel_acc) atomicAdd((unsigned long long*)&R.moves[13], (unsigned long long)rel_acc);
-        if (dA) atomicAdd((unsigned long long*)&R.totals[0], (unsigned long long)(long long)dA);
-        if (dB) atomicAdd((unsigned long long*)&R.totals[1], (unsigned long long)(long long)dB);
-        if (dXp) atomicAdd((unsigned long long*)&R.totals[2], (unsigned long long)(long long)dXp);
-        if (dXm) atomicAdd((unsigned long long*)&R.totals[3], (unsigned long long)(long long)dXm);
+        if (rel_att) atomicAdd(&ct[12], (uint32_t)rel_att);
+        if (rel_acc) atomicAdd(&ct[13], (uint32_t)rel_acc);
+        if (dA) atomicAdd(&ct[14], (uint32_t)dA);
+        if (dB) atomicAdd(&ct[15], (uint32_t)dB);
+        if (dXp) atomicAdd(&ct[16], (uint32_t)dXp);
+        if (dXm) atomicAdd(&ct[17], (uint32_t)dXm);
         if (a.trace) {
             const unsigned long long ti = atomicAdd(a.trace_n, 1ull);
             if (ti < a.trace_cap) {
@@ -1970,7 +2120,7 @@ __global__ __launch_bounds__(PHASE_THREADS) __attribute__((amdgpu_waves_per_eu(4
 }
 
 // ------------------------------------------------------------------------
-// k_sweep_end: series row, group histograms, advance the sweep counter
+// k_sweep_end: counters, series row, group histograms, the next shift
 // ------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a)
 {
@@ -1980,9 +2130,53 @@ __global__ __launch_bounds__(256) void k_sweep_end(SweepArgs a)
     const uint32_t r = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6);
     if (r >= a.nrep) return;
     const Replica& R = a.reps[r];
-    if (lane < 4 && R.series_cap > 0) {
-        const int64_t row = (int64_t)(s % (uint64_t)R.series_cap);
-        R.series[row * 4 + lane] = (int32_t)R.totals[lane];
+    // fold the sweep's counter stripes (lane i holds stripes i, i + 64, ...)
+    // into the replica's counters and clear them
+    static_assert(CTR_STRIPES % 64 == 0 && CTR_STRIDE >= 20 && CTR_STRIDE % 4 == 0, "whole stripes per lane, in 16-byte pieces");
+    {
+        constexpr int SPL = CTR_STRIPES / 64;
+        // the counters as they stand, read before any stripe is cleared
+        uint64_t mv[14];
+        int64_t tot[4];
+#pragma unroll
+        for (int i = 0; i < 14; ++i) mv[i] = R.moves[i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) tot[j] = R.totals[j];
+        uint32_t v[20]; // counters 0-17 and two unused words, in 16-byte pieces
+#pragma unroll
+        for (int i = 0; i < 20; ++i) v[i] = 0u;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            const uint4* st = reinterpret_cast<const uint4*>(R.ctr + (size_t)(lane + 64u * q) * CTR_STRIDE);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) {
+                const uint4 w = st[i];
+                v[4 * i] += w.x; v[4 * i + 1] += w.y; v[4 * i + 2] += w.z; v[4 * i + 3] += w.w;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            uint4* st = reinterpret_cast<uint4*>(R.ctr + (size_t)(lane + 64u * q) * CTR_STRIDE);
+#pragma unroll
+            for (int i = 0; i < 5; ++i) st[i] = make_uint4(0u, 0u, 0u, 0u);
+        }
+        uint32_t x[18];
+#pragma unroll
+        for (int i = 0; i < 18; ++i) x[i] = wave_sum_u32(v[i]);
+        // the new totals are kept in registers: the series row takes them
+        // from there, not from the memory lane 0 writes
+#pragma unroll
+        for (int j = 0; j < 4; ++j) tot[j] += (int64_t)(int32_t)x[14 + j];
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < 14; ++i) R.moves[i] = mv[i] + (uint64_t)x[i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) R.totals[j] = tot[j];
+        }
+        if (lane < 4 && R.series_cap > 0) {
+            const int64_t row = (int64_t)(s % (uint64_t)R.series_cap);
+            R.series[row * 4 + lane] = (int32_t)(lane == 0 ? tot[0] : (lane == 1 ? tot[1] : (lane == 2 ? tot[2] : tot[3])));
+        }
     }
     // ionized sites per group at the start of this sweep (counted by the
     // re-binning); the slot is cleared for the sweep after next
@@ -2133,7 +2327,7 @@ __global__ void k_philox(int64_t n, const uint32_t* ctr, uint32_t k0, uint32_t k
 // ------------------------------------------------------------------------
 hipError_t launch_bin(const SweepArgs& a, hipStream_t s)
 {
-    const uint32_t per = BIN_THREADS / 64;
+    const uint32_t per = BIN_THREADS / 64 * (uint32_t)a.bin_cpw;
     if (a.bin_dense_any)
         hipLaunchKernelGGL(k_bin, dim3((a.ncell_total + per - 1) / per), dim3(BIN_THREADS), 0, s, a);
     if (a.bin_sparse_any)

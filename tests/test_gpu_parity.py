@@ -336,6 +336,43 @@ def test_thousand_replicas_sampled_bit_exact():
         assert np.array_equal(S.series(r, 0, 6), ser)
 
 
+def test_batched_rebinning_bit_exact():
+    """A handle with over 65 536 cells re-bins eight new cells per wavefront:
+    1030 small boxes of 64 cells and two nanoparticle pairs whose surface
+    cells gather more than 64 records (the one-cell path inside a batch).
+    Sampled replicas of both kinds against the oracle, FP64, with their move
+    counts."""
+    crmc = _gpu()
+    small, model, cond = CASES["mixed"]
+    _, pair_model, pair_cond = CASES["np_pair_small"]
+    assert pair_model == model
+    s_small = small()
+    s_pair = CASES["np_pair_small"][0]()
+    n_small = 1030
+    systems = [s_small] * n_small + [s_pair] * 2
+    conds = [dict(cond, pH=cond["pH"] + 0.001 * r) for r in range(n_small)] + [pair_cond, dict(pair_cond, pH=8.0)]
+    S = crmc.System(n_replicas=len(systems), lB=model["lB"], rc=model["rc"], eps=model["eps"],
+                    ion_coupling=model["ion_coupling"], precision=64, trials_per_cell=2, seed=37)
+    for r, s in enumerate(systems):
+        kw = dict(L=s["L"], xyz=s["xyz"], kind=s["kind"], charged=s.get("charged"), group=s.get("group"))
+        if len(s.get("core_R", [])):
+            kw.update(core_xyz=s["core_xyz"], core_R=s["core_R"])
+        S.build_cells(r, **kw)
+    n_cells = [S.observe(r)["n_cells"] for r in (0, n_small)]
+    assert n_small * n_cells[0] ** 3 + 2 * n_cells[1] ** 3 >= 65536, n_cells
+    nsw = 4
+    S.sweep_ex(conds, nsw)
+    for r in (0, 1, 515, n_small - 1, n_small, n_small + 1):
+        obs = S.observe(r)
+        assert obs["status"] == 0 and obs["sweeps"] == nsw
+        o = _oracle_for(systems[r], model, conds[r], obs["n_cells"], 2, True, seed=37, replica=r)
+        ser = o.sweeps(nsw)
+        _same_state(S.particles(r), o.particles())
+        assert np.array_equal(S.series(r, 0, nsw), ser), r
+        att, acc = o.move_stats()
+        assert list(att) == obs["attempts"] and list(acc) == obs["accepts"], r
+
+
 def test_replica_batch_with_different_conditions():
     """Several replicas of different size and conditions in one launch; each
     matches its own oracle."""
