@@ -7,10 +7,12 @@
 //                while rows are being collected; with the proposal on, the
 //                network output p = logistic of a 32 -> 128 -> 128 -> 1 ReLU
 //                perceptron.  R = float: BF16 matrix cores
-//                (v_mfma_f32_16x16x16bf16_1k) with FP32 accumulation;
+//                (v_mfma_f32_16x16x32_bf16) with FP32 accumulation;
 //                R = double: FP64, vector unit.
 //   k_mlp_grad   mean binary cross-entropy gradient of a minibatch on the
-//                matrix cores (BF16 operands, FP32 accumulation).
+//                matrix cores (BF16 operands, FP32 accumulation; 16x16x32
+//                products, and 16x16x16 for the weight gradients, whose K is
+//                the wavefront's 16 rows).
 //   k_adam       Adam step on the FP32 master parameters, refreshing the
 //                BF16 copies the inference uses.
 //   k_mlp_fwd    logits of given feature rows (the same network code as k_learn<float>).
@@ -23,9 +25,22 @@
 namespace crmc {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// gfx950's 16x16x32 BF16 matrix product (FP32 accumulate): lane (col, grp)
+// supplies A[col][8 grp + e] and B[8 grp + e][col], e = 0..7, and receives
+// D[4 grp + e][col], e = 0..3.  Any pairing of the K indices that A and B
+// share gives the same product, so only that they share it matters.
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                   0, 0, 0);
+}
+
 constexpr int LIN = MLP_IN, LH = MLP_H;
+static_assert(LIN % 32 == 0 && LH % 32 == 0, "the products step K by 32");
 constexpr int SITES_PER_WG = 64;    // sites of one cell handled by one workgroup
 constexpr int LEARN_THREADS = 512;  // eight wavefronts: each takes every 8th kept record
 constexpr int LEARN_WAVES = LEARN_THREADS / 64;
@@ -75,16 +90,16 @@ __device__ __forceinline__ float mlp_rows16(const short* W1b, const short* W2b, 
 #pragma unroll
     for (int t = 0; t < 8; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < LIN / 16; ++ks) {
-        bf16x4 a;
+    for (int ks = 0; ks < LIN / 32; ++ks) {
+        bf16x8 a;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[e] = X[col * XS + ks * 16 + 4 * grp + e];
+        for (int e = 0; e < 8; ++e) a[e] = X[col * XS + ks * 32 + 8 * grp + e];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            bf16x4 b;
+            bf16x8 b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) b[e] = W1b[(t * 16 + col) * W1S + ks * 16 + 4 * grp + e];
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            for (int e = 0; e < 8; ++e) b[e] = W1b[(t * 16 + col) * W1S + ks * 32 + 8 * grp + e];
+            acc[t] = mfma32(a, b, acc[t]);
         }
     }
     // bias, ReLU, to LDS as bf16 (row-major [m][n])
@@ -102,16 +117,16 @@ __device__ __forceinline__ float mlp_rows16(const short* W1b, const short* W2b, 
 #pragma unroll
     for (int t = 0; t < 8; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-    for (int ks = 0; ks < LH / 16; ++ks) {
-        bf16x4 a;
+    for (int ks = 0; ks < LH / 32; ++ks) {
+        bf16x8 a;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[e] = H[col * HS + ks * 16 + 4 * grp + e];
+        for (int e = 0; e < 8; ++e) a[e] = H[col * HS + ks * 32 + 8 * grp + e];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            bf16x4 b;
+            bf16x8 b;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) b[e] = W2b[(t * 16 + col) * W2S + ks * 16 + 4 * grp + e];
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+            for (int e = 0; e < 8; ++e) b[e] = W2b[(t * 16 + col) * W2S + ks * 32 + 8 * grp + e];
+            acc[t] = mfma32(a, b, acc[t]);
         }
     }
     // bias, ReLU, dot with w3: lane (col, grp) sums its 8 columns for rows 4 grp + e
@@ -594,16 +609,16 @@ __global__ __launch_bounds__(256) void k_mlp_grad(LearnArgs g, const float* data
     f32x4 dh[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) dh[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ks = 0; ks < LH / 16; ++ks) {
-        bf16x4 av;
+    for (int ks = 0; ks < LH / 32; ++ks) {
+        bf16x8 av;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) av[e] = D2b[col * LH + ks * 16 + 4 * grp + e];
+        for (int e = 0; e < 8; ++e) av[e] = D2b[col * LH + ks * 32 + 8 * grp + e];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            bf16x4 bv;
+            bf16x8 bv;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) bv[e] = W2b[(ks * 16 + 4 * grp + e) * LH + t * 16 + col];
-            dh[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, dh[t], 0, 0, 0);
+            for (int e = 0; e < 8; ++e) bv[e] = W2b[(ks * 32 + 8 * grp + e) * LH + t * 16 + col];
+            dh[t] = mfma32(av, bv, dh[t]);
         }
     }
     // dA1 = dH1 [H1 > 0] (H1 > 0 read from its bf16 copy), into D2 / D2b
