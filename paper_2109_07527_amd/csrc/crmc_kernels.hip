@@ -4,8 +4,9 @@
 //                shifted cells (stable: old cell order, then order in the old
 //                cell), sample per-site occupancy, publish the sweep's shift and
 //                pairing table.  Each new cell gathers from the old cells that
-//                overlap it (at most 27, usually 8), eight cells per wavefront:
-//                places records without atomics or a global scan.
+//                overlap it (at most 27, usually 8), one or (on large launches)
+//                eight cells per wavefront: places records without atomics or
+//                a global scan.
 //   k_plan       per sweep: sorts the domains of every colour into light ones
 //                (one wavefront each) and heavy ones (a whole workgroup); with
 //                the learned proposal on, lists the feature kernel's work items.
@@ -529,7 +530,9 @@ __device__ __forceinline__ Pool pool_layout(int n0, int n1, int ncell, int ntr_m
     p.ncl = ncores <= (uint32_t)MAX_LDS_CORES ? (int)ncores : 0;
     p.cdel_off = p.core_off + p.ncl;
     p.aux_off = p.cdel_off + (p.ncl + 1) / 2;
-    p.st_off = p.aux_off + (learned ? (p.room0 + p.room1 + 1) / 2 : 0);
+    // the learned proposal's per-slot p_i (doubles), or with register lists its
+    // eight class weights (at least four records either way)
+    p.st_off = p.aux_off + (learned ? max((p.room0 + p.room1 + 1) / 2, 4) : 0);
     return p;
 }
 
@@ -1276,14 +1279,24 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
     // ---- learned proposal: site probabilities of the lists, class weights ------
     double* aux = reinterpret_cast<double*>(pool + pl.aux_off);
     ClassW cw{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // with register lists the p_i sit beside the records and the aux slots hold
+    // the eight class weights instead, in the order of ClassW: index 2 c + m
+    // for class c (0 neutral acids, 1 ionized acids, 2 neutral bases, 3
+    // ionized bases; the sites move c eligible for) and member m
+    double* const cwl = aux;
     constexpr bool learned = LEARNED;
     if (learned && REG) {
         const double* phat = R.phat;
         const int k0 = rec_kind(L0.w), k1 = rec_kind(L1.w);
         if (lane < n0 && (k0 == (int)KIND_ACID || k0 == (int)KIND_BASE)) D0 = phat[L0.w >> 8];
         if (lane < n1 && (k1 == (int)KIND_ACID || k1 == (int)KIND_BASE)) D1 = phat[L1.w >> 8];
-        class_sums_reg(L0.w, D0, n0, lane, cw.a0_0, cw.ac_0, cw.b0_0, cw.bc_0);
-        class_sums_reg(L1.w, D1, n1, lane, cw.a0_1, cw.ac_1, cw.b0_1, cw.bc_1);
+        double w0, w1, w2, w3, w4, w5, w6, w7;
+        class_sums_reg(L0.w, D0, n0, lane, w0, w2, w4, w6);
+        class_sums_reg(L1.w, D1, n1, lane, w1, w3, w5, w7);
+        if (lane < 8)
+            cwl[lane] = lane == 0 ? w0 : lane == 1 ? w1 : lane == 2 ? w2 : lane == 3 ? w3
+                      : lane == 4 ? w4 : lane == 5 ? w5 : lane == 6 ? w6 : w7;
+        wave_sync();
     } else if (learned) {
         const double* phat = R.phat;
         for (int i = tid; i < n0 + n1; i += nt) {
@@ -1594,8 +1607,13 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
             const int src = 6 * tl + 5;
             const uint32_t we = rdl(ph0, src), wt0 = rdl(ph1, src), wt1 = rdl(ph2, src);
             weighted = !((double)we * (1.0 / 4294967296.0) < a.learn_eps);
-            lp_W0 = move == 0 ? cw.a0_0 : move == 1 ? cw.ac_0 : move == 2 ? cw.b0_0 : cw.bc_0;
-            lp_W1 = move == 0 ? cw.a0_1 : move == 1 ? cw.ac_1 : move == 2 ? cw.b0_1 : cw.bc_1;
+            if (REG) {
+                lp_W0 = cwl[2 * move];
+                lp_W1 = cwl[2 * move + 1];
+            } else {
+                lp_W0 = move == 0 ? cw.a0_0 : move == 1 ? cw.ac_0 : move == 2 ? cw.b0_0 : cw.bc_0;
+                lp_W1 = move == 0 ? cw.a0_1 : move == 1 ? cw.ac_1 : move == 2 ? cw.b0_1 : cw.bc_1;
+            }
             if (weighted) {
                 const double target = unit53(wt0, wt1) * (lp_W0 + lp_W1);
                 const int mem = (target < lp_W0 && lp_W0 > 0.0) || lp_W1 <= 0.0 ? 0 : 1;
@@ -1625,8 +1643,9 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
                 const double wi = fwd ? p_i : 1.0 - p_i, wr = 1.0 - wi;
                 const int m = move == 0 ? m0a : move == 1 ? mca : move == 2 ? m0b : mcb;
                 const int mr = (move == 0 ? mca : move == 1 ? m0a : move == 2 ? mcb : m0b) + 1;
-                const double Wr = (move == 0 ? cw.ac_0 + cw.ac_1 : move == 1 ? cw.a0_0 + cw.a0_1
-                                   : move == 2 ? cw.bc_0 + cw.bc_1 : cw.b0_0 + cw.b0_1) + wr;
+                const double Wr = (REG ? cwl[2 * (move ^ 1)] + cwl[2 * (move ^ 1) + 1]
+                                       : move == 0 ? cw.ac_0 + cw.ac_1 : move == 1 ? cw.a0_0 + cw.a0_1
+                                       : move == 2 ? cw.bc_0 + cw.bc_1 : cw.b0_0 + cw.b0_1) + wr;
                 const double eps = a.learn_eps;
                 const double lnq = log(eps / mr + (1.0 - eps) * wr / Wr) - log(eps / m + (1.0 - eps) * wi / (lp_W0 + lp_W1));
                 lp_w = p_i;
@@ -1994,7 +2013,12 @@ __device__ __forceinline__ void run_domain(const SweepArgs& a, uint32_t gd, uint
         if (learned && move <= 3) {
             const double p = lp_w, q = 1.0 - lp_w;
             const bool m1 = A.member != 0;
-            switch (move) {
+            if (REG) {
+                // every lane makes the same two updates of the same slots
+                const int c = 2 * move + (m1 ? 1 : 0), cr = 2 * (move ^ 1) + (m1 ? 1 : 0);
+                cwl[c] -= (move & 1) ? q : p;
+                cwl[cr] += (move & 1) ? p : q;
+            } else switch (move) {
             case 0: if (m1) { cw.a0_1 -= p; cw.ac_1 += q; } else { cw.a0_0 -= p; cw.ac_0 += q; } break;
             case 1: if (m1) { cw.ac_1 -= q; cw.a0_1 += p; } else { cw.ac_0 -= q; cw.a0_0 += p; } break;
             case 2: if (m1) { cw.b0_1 -= p; cw.bc_1 += q; } else { cw.b0_0 -= p; cw.bc_0 += q; } break;
