@@ -27,9 +27,11 @@ constexpr uint32_t BIN_CPW = 8, BIN_BATCH_MIN_CELLS = 65536;
 constexpr int PHASE_THREADS = 256;  // one heavy domain, or four light domains (one per wavefront)
 constexpr int DEFAULT_LIGHT_NB = 768;
 
-// sweep plan counters (cleared by the re-binning kernel)
-constexpr int PLAN_LWORK = 24;  // + colour: work items of the feature kernel
-constexpr int PLAN_N = 32;
+// sweep plan counters (cleared by the re-binning kernel), one 128-byte line
+// per colour: heavy domains, light domains, work items of the feature kernel
+constexpr int PLAN_STRIDE = 32, PLAN_HEAVY = 0, PLAN_LIGHT = 1, PLAN_LWORK = 2;
+constexpr int PLAN_N = 8 * PLAN_STRIDE;
+__host__ __device__ constexpr int plan_idx(int colour, int k) { return colour * PLAN_STRIDE + k; }
 
 // learned proposal network: W1[128][32], b1[128], W2[128][128], b2[128], w3[128], b3
 constexpr int MLP_IN = 32, MLP_H = 128;
@@ -136,8 +138,8 @@ struct SweepArgs {
     int32_t pool;      // LDS pool of a phase workgroup, in records (a light domain gets a quarter)
     int32_t precision; // 32 or 64
     int32_t light_nb;  // neighbour records up to which a domain may run on one wavefront
-    uint32_t* plan_n;      // [2c], [2c+1]: heavy and light domains of colour c; [24+c]: work
-                           // items of the learned proposal's feature kernel
+    uint32_t* plan_n;      // plan_idx(c, PLAN_HEAVY / PLAN_LIGHT / PLAN_LWORK): heavy and light
+                           // domains of colour c, work items of the learned proposal's feature kernel
     uint32_t* plan_heavy;  // per colour: ndom_total slots of domain indices
     uint32_t* plan_light;
     uint4* plan_geo_heavy; // beside each slot: replica, first and second cell, and

@@ -311,8 +311,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(SweepArgs a)
     const uint32_t gend = min(g0 + cpw, a.ncell_total);
     const uint32_t r = a.cell2rep[g0];
     const Replica& R = a.reps[r];
-    if (g0 == 0 && lane < PLAN_N && !R.bin_sparse)
-        a.plan_n[lane] = 0u; // plan and learned-proposal counters of the sweep
+    if (g0 == 0 && lane < 24 && !R.bin_sparse)
+        a.plan_n[plan_idx(lane / 3, lane % 3)] = 0u; // plan and learned-proposal counters of the sweep
     if (R.bin_sparse) return;
     BinRep b;
     bin_rep(a, R, b);
@@ -410,7 +410,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin_sparse(SweepArgs a)
     // the duties of k_bin for the cells it leaves to this kernel: the sweep's
     // plan counters (with global cell 0) and the replica's table (with its cell 0)
     if (gcell == 0)
-        for (int i = 0; i < PLAN_N; ++i) a.plan_n[i] = 0u;
+        for (int c = 0; c < 8; ++c)
+            for (int j = 0; j < 3; ++j) a.plan_n[plan_idx(c, j)] = 0u;
     if (k == 0) {
         const uint32_t M = R.h * R.h * R.h;
         for (int d = 0; d < 3; ++d) R.tab->o[d] = on[d];
@@ -576,7 +577,8 @@ __device__ __forceinline__ uint32_t neighbour_cell(uint32_t x, uint32_t y, uint3
 }
 
 // one thread per domain, one colour per workgroup (blockIdx.y); the list
-// slots are claimed with one atomic per wavefront and class.  With the
+// slots are claimed with one atomic per wavefront and class, on a line of
+// counters per colour (the colours' workgroups run side by side).  With the
 // learned proposal on, each cell of the domain also gets its work items for
 // the feature kernel: one per 64 sites (sites never change cells within a
 // sweep, so the counts of the re-binning hold for all phases).
@@ -586,9 +588,7 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
     const uint32_t gd = blockIdx.x * 64u + threadIdx.x;
     bool valid = gd < a.ndom_total, light = false;
     uint4 geo = make_uint4(0u, 0u, 0u, 0u);
-    if (valid) {
-        const uint32_t r = a.dom2rep[gd];
-        const Replica& R = a.reps[r];
+    const auto plan_domain = [&](const Replica& R, uint32_t r) {
         const DomGeo G = domain_geometry(R, gd - R.dom_begin, colour, a.pairing);
         if (a.lwork) {
             for (int c = 0; c < G.ncell; ++c) {
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
                 const uint32_t m = (R.nsc[cell] + 63u) / 64u;
                 if (m == 0u) continue;
                 // the capacity bounds every sweep's items (sites / 64 + cells with sites)
-                const uint32_t b = atomicAdd(&a.plan_n[PLAN_LWORK + colour], m);
+                const uint32_t b = atomicAdd(&a.plan_n[plan_idx(colour, PLAN_LWORK)], m);
                 const int buf = (int)((*a.sweep + 1u) & 1u);
                 for (uint32_t i = 0; i < m && b + i < a.lwork_cap; ++i) {
                     LearnItem& L = a.lwork[(size_t)colour * a.lwork_cap + b + i];
@@ -632,13 +632,23 @@ __global__ __launch_bounds__(64) void k_plan(SweepArgs a)
         // keeps them in registers, one record per lane (flag: bit 31)
         const uint32_t reg = light && p.room0 <= REG_ROOM && p.room1 <= REG_ROOM ? GEO_REG : 0u;
         geo = make_uint4(r | reg, G.cell0, G.ncell == 2 ? G.cell1 : G.cell0, (uint32_t)n0 | ((uint32_t)n1 << 16));
+    };
+    // lane 0's domain is valid whenever any lane's is; when all the
+    // wavefront's domains belong to one replica (the common case), its
+    // descriptor and tables come through scalar loads
+    const uint32_t r = a.dom2rep[valid ? gd : blockIdx.x * 64u];
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)r);
+    if (__ballot(r != r0) == 0ull) {
+        if (valid) plan_domain(a.reps[r0], r0);
+    } else if (valid) {
+        plan_domain(a.reps[r], r);
     }
     const uint64_t ml = __ballot(valid && light), mh = __ballot(valid && !light);
     const uint32_t lane = threadIdx.x;
     uint32_t bl = 0, bh = 0;
     if (lane == 0) {
-        if (ml) bl = atomicAdd(&a.plan_n[2 * colour + 1], (uint32_t)__popcll(ml));
-        if (mh) bh = atomicAdd(&a.plan_n[2 * colour], (uint32_t)__popcll(mh));
+        if (ml) bl = atomicAdd(&a.plan_n[plan_idx(colour, PLAN_LIGHT)], (uint32_t)__popcll(ml));
+        if (mh) bh = atomicAdd(&a.plan_n[plan_idx(colour, PLAN_HEAVY)], (uint32_t)__popcll(mh));
     }
     bl = rdl0(bl);
     bh = rdl0(bh);
@@ -2102,7 +2112,7 @@ __device__ __forceinline__ void phase_body(const SweepArgs& a)
     __shared__ double red[2][4];
     __shared__ int ovf[2][4];
     const int colour = a.colour;
-    const uint32_t nh = a.plan_n[2 * colour], nl = a.plan_n[2 * colour + 1];
+    const uint32_t nh = a.plan_n[plan_idx(colour, PLAN_HEAVY)], nl = a.plan_n[plan_idx(colour, PLAN_LIGHT)];
     const uint32_t b = blockIdx.x;
     const int wave = (int)(threadIdx.x >> 6);
     const bool heavy = b < nh;

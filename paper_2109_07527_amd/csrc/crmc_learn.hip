@@ -231,7 +231,7 @@ __global__ __launch_bounds__(LEARN_THREADS) void k_learn(SweepArgs a, LearnArgs 
     extern __shared__ uint4 lsh4[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int colour = a.colour;
-    const uint32_t nwork = min(a.plan_n[PLAN_LWORK + colour], a.lwork_cap);
+    const uint32_t nwork = min(a.plan_n[plan_idx(colour, PLAN_LWORK)], a.lwork_cap);
     if (blockIdx.x >= nwork) return;
     const uint64_t s = *a.sweep;
     const int buf = (int)((s + 1u) & 1u);
