@@ -234,19 +234,23 @@ __global__ __launch_bounds__(64) void k_md_force(MdArgs m, int buf, uint64_t ste
     // the first 64 records of every segment, nine segments' loads in flight
     // at a time (each lane reads an in-range slot, the stores are masked),
     // then the rest of longer segments
+    const auto seg_load = [&](int o) -> uint4 {
+        const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, o);
+        const int cn = __builtin_amdgcn_readlane(ocnt, o);
+        return recb[(size_t)oc * cap + (uint32_t)min((int)lane, max(cn - 1, 0))];
+    };
+    const auto seg_store = [&](int o, const uint4& v) {
+        const int cn = __builtin_amdgcn_readlane(ocnt, o), st = __builtin_amdgcn_readlane(ostart, o);
+        if ((int)lane < cn && st + (int)lane < MD_STAGE) nbr[st + lane] = v;
+    };
     for (int b = 0; b < 27; b += 9) {
-        uint4 v[9];
-#pragma unroll
-        for (int u = 0; u < 9; ++u) {
-            const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, b + u);
-            const int cn = __builtin_amdgcn_readlane(ocnt, b + u);
-            v[u] = recb[(size_t)oc * cap + (uint32_t)min((int)lane, max(cn - 1, 0))];
-        }
-#pragma unroll
-        for (int u = 0; u < 9; ++u) {
-            const int cn = __builtin_amdgcn_readlane(ocnt, b + u), st = __builtin_amdgcn_readlane(ostart, b + u);
-            if ((int)lane < cn && st + (int)lane < MD_STAGE) nbr[st + lane] = v[u];
-        }
+        // nine loads, then nine stores (named registers, not an array the
+        // compiler would place in scratch)
+        const uint4 v0 = seg_load(b), v1 = seg_load(b + 1), v2 = seg_load(b + 2), v3 = seg_load(b + 3),
+                    v4 = seg_load(b + 4), v5 = seg_load(b + 5), v6 = seg_load(b + 6), v7 = seg_load(b + 7),
+                    v8 = seg_load(b + 8);
+        seg_store(b, v0); seg_store(b + 1, v1); seg_store(b + 2, v2); seg_store(b + 3, v3); seg_store(b + 4, v4);
+        seg_store(b + 5, v5); seg_store(b + 6, v6); seg_store(b + 7, v7); seg_store(b + 8, v8);
     }
     for (int o = 0; o < 27; ++o) {
         const uint32_t oc = (uint32_t)__builtin_amdgcn_readlane((int)ocell, o);
